@@ -1,0 +1,80 @@
+"""Pins of the oracle's Philox4x32-10 streams and the uniform mapping.
+
+Random numbers are an input of the method, not a formula of the paper (section
+2.2.2 replaces the CPU generator by a GPU library generator); the generator
+here is Philox4x32-10 (Salmon et al., SC'11).  Known-answer vectors of the
+published generator are not available in this environment, so the generator
+is pinned by the properties a uniform generator must have: the values lie on
+the stated 2^-24 grid inside (0,1), are uniform (chi-square), show no serial
+correlation, streams of different histories and paths are independent, and
+one counter bit changes about half of the output bits (avalanche)."""
+import numpy as np
+import pytest
+from scipy import stats as sst
+
+import oracle
+
+
+def test_uniform_grid_and_range():
+    u = oracle.uniforms(1, 0, 0, 0, 0, 200_000)
+    assert u.min() > 0.0 and u.max() < 1.0
+    k = u * 2 ** 24
+    assert np.all(k == np.round(k))
+    assert np.all(np.round(k).astype(np.int64) % 2 == 1)
+
+
+def test_uniformity_chi2():
+    u = oracle.uniforms(7, 3, 12345, 0, 0, 1_000_000)
+    h, _ = np.histogram(u, bins=200, range=(0, 1))
+    p = sst.chisquare(h).pvalue
+    assert p > 1e-4
+
+
+def test_serial_pairs_uniform_and_uncorrelated():
+    u = oracle.uniforms(9, 0, 77, 5, 0, 400_000)
+    a, b = u[0::2], u[1::2]
+    assert abs(np.corrcoef(u[:-1], u[1:])[0, 1]) < 5.0 / np.sqrt(len(u))
+    h, _, _ = np.histogram2d(a, b, bins=20, range=((0, 1), (0, 1)))
+    assert sst.chisquare(h.ravel()).pvalue > 1e-4
+
+
+def test_streams_independent_across_histories_and_paths():
+    n = 2000
+    firsts = np.array([oracle.uniforms(1, 0, h, 0, 0, 1)[0] for h in range(n)])
+    assert sst.kstest(firsts, "uniform").pvalue > 1e-4
+    paths = np.array([oracle.uniforms(1, 0, 5, p, 0, 1)[0] for p in range(n)])
+    assert sst.kstest(paths, "uniform").pvalue > 1e-4
+    assert abs(np.corrcoef(firsts, paths)[0, 1]) < 5.0 / np.sqrt(n)
+
+
+def test_job_changes_stream():
+    a = oracle.uniforms(1, 0, 3, 0, 0, 64)
+    b = oracle.uniforms(1, 1, 3, 0, 0, 64)
+    assert not np.array_equal(a, b)
+
+
+def test_counter_blocks_are_consecutive_draws():
+    u = oracle.uniforms(11, 2, 99, 4, 0, 16)
+    v = oracle.uniforms(11, 2, 99, 4, 8, 8)
+    assert np.array_equal(u[8:], v)
+
+
+def test_avalanche():
+    rng = np.random.default_rng(0)
+    flips = []
+    for _ in range(300):
+        key = [int(x) for x in rng.integers(0, 2 ** 32, size=2)]
+        ctr = [int(x) for x in rng.integers(0, 2 ** 32, size=4)]
+        w, bit = int(rng.integers(0, 4)), int(rng.integers(0, 32))
+        a = oracle.philox(key, ctr)
+        ctr2 = list(ctr)
+        ctr2[w] ^= 1 << bit
+        b = oracle.philox(key, ctr2)
+        flips.append(sum(bin(x ^ y).count("1") for x, y in zip(a, b)))
+    m = np.mean(flips)
+    assert abs(m - 64.0) < 2.0
+
+
+def test_spawn_paths_distinct():
+    ps = {oracle.spawn_path(1, 0, 10, 0, c, w) for c in range(50) for w in range(4)}
+    assert len(ps) == 200

@@ -1,0 +1,158 @@
+"""Pins of the oracle's sampling algorithms against their target densities
+(chi-square on histograms of many draws): Klein-Nishina (Butcher-Messel
+composition/rejection), Moller, bremsstrahlung, the modified-Wentzel deflection
+and its multiple-scattering first moment (Lewis: <cos> = exp(-sum t)),
+annihilation photon pairs (positrons: section 2.1), and the source: the
+piecewise-linear spectrum and the beamlet choice P(I) <= r < P(I+1)
+(section 2.3.1)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats as sst
+from scipy.integrate import quad
+
+import oracle
+from paper_1107_3355_amd import inputs as I
+
+MC2 = 0.51099895
+
+
+def _chi2_p(counts, weights):
+    """chi-square p-value of histogram counts against bin weights (any scale)"""
+    counts = np.asarray(counts, dtype=float)
+    e = np.asarray(weights, dtype=float) * counts.sum() / np.sum(weights)
+    keep = e > 5
+    c, e = counts[keep], e[keep]
+    e = e * c.sum() / e.sum()
+    return sst.chisquare(c, e).pvalue
+
+
+@pytest.mark.parametrize("e", [0.1, 1.0, 10.0])
+def test_compton_energy_distribution(e):
+    n = 400_000
+    eps, cos = oracle.sample(0, e, n=n, seed=3)
+    k = e / MC2
+    e0 = 1 / (1 + 2 * k)
+    assert eps.min() >= e0 and eps.max() <= 1.0
+    assert np.allclose(cos, 1 - (1 - eps) / (k * eps), atol=1e-12)
+    edges = np.linspace(e0, 1, 61)
+    f = lambda x: oracle.phys(oracle.DSIGMA_KN, I.WATER, e, x)
+    exp = np.array([quad(f, a, b, epsrel=1e-10)[0] for a, b in zip(edges[:-1], edges[1:])])
+    h, _ = np.histogram(eps, edges)
+    assert _chi2_p(h, exp) > 1e-4
+
+
+@pytest.mark.parametrize("t", [0.5, 2.0, 20.0])
+def test_moller_distribution(t):
+    wcc = 0.2
+    eps, cpr = oracle.sample(1, t, wcc, n=200_000, seed=5)
+    e0 = wcc / t
+    assert eps.min() >= e0 * (1 - 1e-12) and eps.max() <= 0.5 + 1e-12
+    edges = np.exp(np.linspace(math.log(e0), math.log(0.5), 41))
+    f = lambda x: oracle.phys(oracle.DSIGMA_MOLLER, I.WATER, t, x)
+    exp = np.array([quad(f, a, b, epsrel=1e-10)[0] for a, b in zip(edges[:-1], edges[1:])])
+    h, _ = np.histogram(eps, edges)
+    assert _chi2_p(h, exp) > 1e-4
+    # primary after the collision: binary-collision kinematics
+    w = eps * t
+    tp = t - w
+    c_expect = np.sqrt(tp * (t + 2 * MC2) / (t * (tp + 2 * MC2)))
+    assert np.allclose(cpr, c_expect, atol=1e-9)
+
+
+@pytest.mark.parametrize("t", [0.3, 5.0, 20.0])
+def test_bremsstrahlung_distribution(t):
+    wcb = 0.05
+    k, _ = oracle.sample(2, t, wcb, n=200_000, seed=7)
+    assert k.min() >= wcb and k.max() <= t
+    edges = np.exp(np.linspace(math.log(wcb), math.log(t), 41))
+    f = lambda x: oracle.phys(oracle.DMU_BREMS, I.WATER, t, x)
+    exp = np.array([quad(f, a, b, epsrel=1e-10)[0] for a, b in zip(edges[:-1], edges[1:])])
+    h, _ = np.histogram(k, edges)
+    assert _chi2_p(h, exp) > 1e-4
+
+
+@pytest.mark.parametrize("t", [1e-3, 0.3, 3.0, 25.0])
+def test_mw_deflection_distribution(t):
+    mu, _ = oracle.sample(3, t, n=200_000, seed=11)
+    assert mu.min() >= 0 and mu.max() <= 1
+    if t >= 20.0:
+        cdf = lambda x: x
+    else:
+        a = oracle.mw_A(t)
+        cdf = lambda x: (1 + a) * x / (x + a)
+    assert sst.kstest(mu, cdf).pvalue > 1e-4
+    target = -0.5 * math.expm1(-t)
+    assert abs(mu.mean() - target) < 5 * mu.std() / math.sqrt(len(mu))
+
+
+@pytest.mark.parametrize("t,nh", [(0.05, 10), (0.2, 5), (1.0, 3)])
+def test_multiple_scattering_first_moment(t, nh):
+    c, norm = oracle.sample(4, t, 0.0, nh, n=100_000, seed=13)
+    assert np.allclose(norm, 1.0, atol=1e-12)
+    assert abs(c.mean() - math.exp(-nh * t)) < 5 * c.std() / math.sqrt(len(c))
+
+
+def test_annihilation_pairs():
+    c, dot = oracle.sample(5, 0.0, n=100_000, seed=17)
+    assert np.allclose(dot, -1.0, atol=1e-12)
+    assert sst.kstest(c, "uniform", args=(-1, 2)).pvalue > 1e-4
+
+
+def test_triangular_spectrum():
+    w = I.water_cube_2mev()
+    src = I.Source(I.PHOTON, I.triangular_spectrum(), [I.parallel_beam_z(w.phantom, 5.0)])
+    out = oracle.sample_source(src, w.phantom, n=200_000)
+    e = out[:, 0]
+    lo, pk, hi = 0.25, 1.2, 6.0
+    cdf = lambda x: np.where(x < pk, (x - lo) ** 2 / ((hi - lo) * (pk - lo)),
+                             1 - (hi - x) ** 2 / ((hi - lo) * (hi - pk)))
+    assert sst.kstest(e, cdf).pvalue > 1e-4
+    assert abs(e.mean() - (lo + pk + hi) / 3) < 5 * e.std() / math.sqrt(len(e))
+
+
+def test_beamlet_choice_follows_fluence():
+    ph = I.homogeneous((40, 40, 20), (0.5, 0.5, 0.5), I.ID_WATER, 1.0)
+    rng = np.random.default_rng(4)
+    f = rng.uniform(0, 1, size=(8, 8)).astype(np.float32)
+    f[2, 3] = 0.0
+    beams = [I.gantry_beam(ph, g, nb=8, bsize=1.0, intensity=f) for g in (0.0, 90.0)]
+    src = I.Source(I.PHOTON, I.mono(1.0), beams)
+    n = 200_000
+    out = oracle.sample_source(src, ph, n=n)
+    bl = out[:, 1]
+    assert np.all(bl >= 0)
+    counts = np.bincount(bl.astype(int), minlength=128)
+    ff = np.concatenate([f.ravel(), f.ravel()]).astype(np.float64)
+    assert counts[2 * 8 + 3] == 0 and counts[64 + 2 * 8 + 3] == 0
+    assert _chi2_p(counts.astype(float), ff / ff.sum() * n) > 1e-4
+
+
+def test_point_source_geometry():
+    ph = I.homogeneous((20, 20, 20), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
+    b = I.point_beam_z(ph, field=10.0, ssd=90.0, sad=100.0)
+    src = I.Source(I.PHOTON, I.mono(1.0), [b])
+    out = oracle.sample_source(src, ph, n=20_000)
+    x, d = out[:, 2:5], out[:, 5:8]
+    assert np.allclose(x[:, 2], 0.0)                         # enters through z = 0
+    assert np.allclose(np.linalg.norm(d, axis=1), 1.0)
+    s = np.array([10.0, 10.0, -90.0])                        # source position
+    # the ray from the source passes through the entry point
+    v = x - s
+    cr = np.cross(v, d)
+    assert np.abs(cr).max() < 1e-9
+    # the field is 10x10 at SAD = 100, i.e. 9x9 at the surface (SSD 90)
+    assert np.abs(x[:, 0] - 10.0).max() <= 4.5 + 1e-9 and np.abs(x[:, 1] - 10.0).max() <= 4.5 + 1e-9
+    assert np.abs(x[:, 0] - 10.0).max() > 4.4
+
+
+def test_beam_missing_phantom_escapes():
+    ph = I.homogeneous((4, 4, 4), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
+    b = I.Beam(iso=(2.0, 2.0, 2.0), dir=(0.0, 0.0, 1.0), e1=(1.0, 0.0, 0.0), sad=0.0, nbx=1,
+               nby=1, bw=1.0, bh=1.0)
+    b.iso = (50.0, 50.0, 2.0)  # the field lies beside the phantom
+    src = I.Source(I.PHOTON, I.mono(1.0), [b])
+    r = oracle.run(I.MATERIALS, ph, src, n_hist=100, n_batches=2, want_hist=True, n_threads=1)
+    assert r["e_in"] == pytest.approx(100.0) and r["e_esc"] == pytest.approx(100.0)
+    assert r["e_dep"] == 0.0
