@@ -1,0 +1,242 @@
+/*
+ * gdpm.h -- C ABI of libgdpm: coupled photon/electron Monte Carlo dose on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem statement follows the paper (Jia et al., "GPU-based fast Monte
+ * Carlo simulation for radiotherapy dose calculation", gDPM v2.0):
+ *   - a voxelised geometry with a material and a density per voxel, material
+ *     properties and cross-section data (section 2.2.1);
+ *   - a source with an energy spectrum (section 2.3.2), fluence maps grouped
+ *     over all beam angles into beamlets of intensity f_I (section 2.3.1) and
+ *     the linac gantry geometry (section 2.3);
+ *   - a number of histories split evenly into N_b batches (section 2.2.1),
+ *     or an uncertainty target on the mean of sigma/D_max over voxels above
+ *     half the maximum dose (section 3.1);
+ *   - out: per-voxel mean dose and its standard error over the batches
+ *     (section 2.2.1).
+ * Transport: photon Woodcock tracking; class-II condensed-history electrons;
+ * positrons as electrons with two photons at the end (section 2.1); absorption
+ * energies (section 3.1); single precision transport (section 2.2.2) with
+ * double-precision dose tallies.
+ *
+ * Conventions
+ *   Units: cm, MeV, g/cm^3.  Dose is MeV/g per source history (multiply by
+ *   1.602176634e-10 for Gy).  Voxel index v = ix + nx*(iy + ny*iz); the
+ *   phantom occupies [0, nx*dx) x [0, ny*dy) x [0, nz*dz).
+ *   Every function returns a gdpm_status; no exception crosses the ABI.  On
+ *   failure gdpm_last_error() describes the cause (thread-local, valid until
+ *   the next call on the same thread).
+ *   Host input arrays are copied before a call returns; the caller keeps
+ *   ownership of everything it passes.  Handles are destroyed explicitly;
+ *   destroying a context invalidates its phantoms, sources and jobs.
+ *   A context is bound to one HIP device and is not thread-safe: calls on one
+ *   context must not overlap.
+ */
+#ifndef GDPM_H
+#define GDPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GDPM_OK = 0,
+    GDPM_E_INVALID = 1,        /* an argument is out of range or inconsistent */
+    GDPM_E_NOMEM = 2,          /* a device or host allocation failed */
+    GDPM_E_DEVICE = 3,         /* a HIP call failed */
+    GDPM_E_OVERFLOW = 4,       /* a particle queue filled up; outputs are not valid */
+    GDPM_E_BUSY = 5,           /* the context has a job in flight */
+    GDPM_E_NOT_CONVERGED = 6   /* target uncertainty not reached within max_histories;
+                                  outputs are written and valid for the histories run */
+} gdpm_status;
+
+typedef struct gdpm_context_s* gdpm_context;
+typedef struct gdpm_phantom_s* gdpm_phantom;
+typedef struct gdpm_source_s* gdpm_source;
+typedef struct gdpm_job_s* gdpm_job;
+
+/* Material as a pseudo-element (the paper keeps DPM's material data, section
+ * 2.1, which is not reproduced; the closed-form models need Z, Z/A and I). */
+typedef struct {
+    double z;         /* effective atomic number, > 0 */
+    double z_over_a;  /* electrons per nucleon (mol/g per mol of electrons), > 0 */
+    double i_ev;      /* mean excitation energy (eV), > 0 */
+} gdpm_material;
+
+/* Energy spectrum (section 2.3.2). kind 0: monoenergetic e_mono.  kind 1:
+ * piecewise-linear pdf through (e_mev[i], pdf[i]), i < n_pts, energies strictly
+ * increasing, pdf >= 0 with positive area; sampled by exact inverse CDF. */
+typedef struct {
+    int kind;
+    int n_pts;
+    const double* e_mev;
+    const double* pdf;
+    double e_mono;
+} gdpm_spectrum;
+
+/* One beam (one gantry angle / control point) with its fluence map (section
+ * 2.3.1).  The isocentre plane is spanned by e1 and e2 = dir x e1; beamlet
+ * (jx, jy) covers [jx*bw - nbx*bw/2, (jx+1)*bw - nbx*bw/2) along e1 and the
+ * same with bh, nby along e2.  sad_cm > 0: point source at iso - sad*dir;
+ * sad_cm <= 0: parallel beam along dir.  intensity: nbx*nby values >= 0,
+ * index jx + nbx*jy, or NULL for an open field (all 1). */
+typedef struct {
+    double iso_cm[3];
+    double dir[3];      /* unit vector, source -> isocentre */
+    double e1[3];       /* unit vector orthogonal to dir */
+    double sad_cm;
+    int nbx, nby;
+    double bw_cm, bh_cm;
+    const float* intensity;
+} gdpm_beam;
+
+typedef struct {
+    int particle;            /* 0 photon, 1 electron */
+    gdpm_spectrum spectrum;  /* energies within (ecut, 30] MeV */
+    int n_beams;             /* >= 1; beamlets of all beams form one index I */
+    const gdpm_beam* beams;
+} gdpm_source_desc;
+
+/* run flags: physics switches used by the tests' closed-form special cases */
+#define GDPM_NO_COMPTON 1u
+#define GDPM_NO_PHOTO 2u
+#define GDPM_NO_PAIR 4u
+#define GDPM_NO_MS 8u
+#define GDPM_NO_MOLLER 16u
+#define GDPM_NO_BREMS 32u
+#define GDPM_KERMA 64u   /* charged secondaries deposited where they are created */
+
+typedef struct {
+    uint64_t seed;             /* Philox key: (seed lo32, seed hi32 ^ job_id) */
+    uint32_t job_id;
+    uint64_t n_histories;      /* fixed history count, or the first estimate if target_unc > 0 */
+    double target_unc;         /* 0: run n_histories; > 0: run until mean(sigma/D_max over
+                                  D > D_max/2) <= target_unc */
+    int n_batches;             /* N_b >= 2 (0 means 10) */
+    double ecut_photon_mev;    /* photon absorption energy = bremsstrahlung threshold (0 -> 0.05) */
+    double ecut_electron_mev;  /* electron absorption energy = Moller threshold (0 -> 0.2) */
+    uint64_t max_histories;    /* cap in target mode (0 -> 100 * n_histories) */
+    uint32_t flags;            /* GDPM_NO_* / GDPM_KERMA */
+    uint64_t round_size;       /* histories per round; 0: n_histories / n_batches.  In fixed
+                                  mode history h goes to batch floor(h/round_size) mod N_b */
+    uint64_t hist0;            /* id of the first history (fixed mode) */
+} gdpm_run_params;
+
+enum { GDPM_EV_FLIGHTS = 0, GDPM_EV_REAL, GDPM_EV_ESTEPS, GDPM_EV_HARD_CAND, GDPM_EV_HARD,
+       GDPM_EV_DEPOSITS, GDPM_EV_PUSHES, GDPM_EV_HISTORIES };
+
+typedef struct {
+    uint64_t histories;
+    double e_in, e_dep, e_esc;   /* MeV: source kinetic energy, deposited, escaped */
+    double unc_mean_over_dmax;   /* mean sigma/D_max over D > D_max/2 */
+    double dmax;                 /* MeV/g per history */
+    double t_total_s;            /* wall time of the call */
+    double t_kernel_s;           /* device time of the transport kernels (HIP events) */
+    double t_photon_s, t_electron_s;  /* device time per pass type */
+    uint64_t events[8];          /* GDPM_EV_* counters */
+    uint32_t passes;             /* transport kernel launches */
+    uint32_t rounds;
+} gdpm_run_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `hip_device`.  opts_json may be NULL or a
+ * flat JSON object with any of: "ring_capacity_log2" (queue records per type,
+ * 2^k, default 24), "waves_per_cu" (persistent waves per CU, default 16),
+ * "rebin_bins" (energy bins of the queue re-binning, 0 = off, default 16). */
+gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out);
+gdpm_status gdpm_context_destroy(gdpm_context ctx);
+const char* gdpm_last_error(void);
+
+/* Material table shared by all phantoms of the context (ids 0..n-1, n <= 8).
+ * n_grid: nodes of the interpolation grid uniform in ln E (256..8192; 0 ->
+ * 1024).  Tables are generated from closed forms in double precision and
+ * stored in single precision; interpolation is linear (section 2.2.2). */
+gdpm_status gdpm_set_materials(gdpm_context ctx, const gdpm_material* m, int n, int n_grid);
+
+/* ---- phantom ------------------------------------------------------------ */
+
+/* nx, ny <= 2048, nz <= 1024; mat[v] < number of materials; density[v] > 0
+ * and finite.  Both arrays (nx*ny*nz) are copied to device memory. */
+gdpm_status gdpm_phantom_create(gdpm_context ctx, int nx, int ny, int nz, double dx, double dy,
+                                double dz, const uint8_t* mat, const float* density,
+                                gdpm_phantom* out);
+gdpm_status gdpm_phantom_destroy(gdpm_phantom ph);
+
+/* ---- source ------------------------------------------------------------- */
+
+/* The descriptor and everything it points to are copied.  The beamlet
+ * probabilities P(I) are normalised prefix sums of f_I in double precision. */
+gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* desc, gdpm_source* out);
+gdpm_status gdpm_source_destroy(gdpm_source src);
+
+/* ---- runs --------------------------------------------------------------- */
+
+/* Blocking run.  dose and sigma: host arrays of nx*ny*nz doubles (either may
+ * be NULL).  batch_edep: NULL or host n_batches*nx*ny*nz doubles receiving the
+ * energy (MeV) deposited per batch and voxel.  hist_out: NULL or host
+ * 2*n_histories doubles receiving (deposited, escaped) energy per history
+ * (fixed mode only, n_histories <= 2^24).  stats may be NULL. */
+gdpm_status gdpm_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
+                     const gdpm_run_params* prm, double* dose, double* sigma,
+                     double* batch_edep, double* hist_out, gdpm_run_stats* stats);
+
+/* Same computation with device outputs: d_dose, d_sigma are device pointers
+ * (nx*ny*nz doubles, e.g. a torch tensor's data_ptr()); work is ordered on
+ * hip_stream (NULL = the context's own stream).  The call returns once the
+ * work is queued or finished; gdpm_job_wait blocks until the outputs are
+ * complete. */
+gdpm_status gdpm_run_async(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
+                           const gdpm_run_params* prm, double* d_dose, double* d_sigma,
+                           void* hip_stream, gdpm_job* out);
+gdpm_status gdpm_job_wait(gdpm_job job, gdpm_run_stats* stats);
+gdpm_status gdpm_job_release(gdpm_job job);
+
+/* ---- inspection and test entry points ------------------------------------
+ * These expose the pieces of the transport so that tests can compare them
+ * with an independent reference; they are not needed to compute dose. */
+
+/* Host-only: build the interpolation tables for a material set and return
+ * them.  which: 0 photon {muC, muPE, muPair, muTot} (cm^2/g) per material and
+ * node of the photon grid; 1 electron {R (g/cm^2), muHard, muMoller,
+ * 1/lambda1 (cm^2/g)} per material and node of the electron grid; 2 inverse
+ * range E(w) on w = sqrt(R) per material; 3 MW screening log2 A on log2 t.
+ * grid[0..3] receives (ln-grid start, spacing, node count, materials).
+ * out: cap floats; *len receives the number needed. */
+gdpm_status gdpm_tables_host(const gdpm_material* m, int n, int n_grid, double ecut_g,
+                             double ecut_e, uint32_t flags, int which, float* out, size_t cap,
+                             size_t* len, double grid[4]);
+
+/* Device Philox4x32-10 on n counters: key2 (2 words), ctr (4n words), out (4n
+ * words); host arrays. */
+gdpm_status gdpm_test_philox(gdpm_context ctx, const uint32_t key[2], const uint32_t* ctr,
+                             uint32_t* out, int n);
+
+/* Device samplers, n samples, sample i drawn from the stream of history i,
+ * path 0 of `seed`: which 0 Compton (E) -> eps, cos; 1 Moller (T) -> W/T, cos
+ * of the primary; 2 bremsstrahlung (T) -> k; 3 MW deflection (t) -> mu;
+ * 4 multiple-scattering walk of (int)p2 hinges of t each -> Omega.Omega0;
+ * 5 annihilation pair -> cos of photon 1, dir1.dir2.  out1/out2: host arrays
+ * of n floats (out2 may be NULL). */
+gdpm_status gdpm_test_sample(gdpm_context ctx, int which, double e, double p1, double p2,
+                             uint64_t seed, int n, float* out1, float* out2);
+
+/* Device source sampling: n histories from hist0 of (seed, job); out: host
+ * n*8 floats E, beamlet, x, y, z, u, v, w (beamlet -1 if the particle misses
+ * the phantom). */
+gdpm_status gdpm_test_source(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, uint64_t seed,
+                             uint32_t job, uint64_t hist0, int n, float* out);
+
+/* Device table lookups at n energies for material mat (ecut/flags select the
+ * table set): which 0 muTot photon, 1 R, 2 muHard, 3 muMoller, 4 1/lambda1,
+ * 5 inverse range (input is R), 6 MW A (input is t). */
+gdpm_status gdpm_test_lookup(gdpm_context ctx, double ecut_g, double ecut_e, uint32_t flags,
+                             int which, int mat, const float* in, float* out, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GDPM_H */

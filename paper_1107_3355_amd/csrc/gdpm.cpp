@@ -1,0 +1,917 @@
+// Host runtime behind the C ABI of include/gdpm.h: device resources, the pass
+// scheduler and the batch statistics.
+//
+// Scheduling follows the paper's batch loop (section 2.2.1, Fig. 1): histories
+// are split into N_b batches; within a batch the photon and electron kernels
+// alternate until the source is exhausted and both secondary queues are empty;
+// per-voxel mean dose and its uncertainty come from the batch tallies.  Here a
+// batch slot is filled by one or more rounds of histories, the queues are ring
+// buffers sized for HBM, and the host only reads a few counters between passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/gdpm.h"
+#include "dev_types.h"
+#include "tables.h"
+
+namespace gdpm {
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, int ri, int with_source, uint32_t src_pass_max);
+hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri);
+hipError_t launch_transport(hipStream_t st, int ri, int blocks, Ctl* ctl, const Tables& T,
+                            const Geom& G, const SourceDev& S, const RunDev& R, int with_source);
+hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
+                        float lo, float inv);
+hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
+                        int nb, const double* inv_n, const uint2* vox, double vvox, double* dose,
+                        double* sigma);
+hipError_t launch_test_philox(hipStream_t st, uint32_t k0, uint32_t k1, const uint4* ctr, uint4* out,
+                              int n);
+hipError_t launch_test_sample(hipStream_t st, const Tables& T, int which, float e, float p1, float p2,
+                              uint32_t k0, uint32_t k1, int n, float* out1, float* out2);
+hipError_t launch_test_source(hipStream_t st, const SourceDev& S, const Geom& G, uint32_t k0,
+                              uint32_t k1, unsigned long long hist0, int n, float* out);
+hipError_t launch_test_lookup(hipStream_t st, const Tables& T, int which, int m, const float* in,
+                              float* out, int n);
+}  // namespace gdpm
+
+using namespace gdpm;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string g_err;
+
+gdpm_status fail(gdpm_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? GDPM_E_NOMEM : GDPM_E_DEVICE, "%s: %s",  \
+                        #call, hipGetErrorString(e_));                                       \
+    } while (0)
+
+// device allocation owned by a unique_ptr-like holder
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t n) {
+        reset();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess) bytes = n;
+        else p = nullptr;
+        return e;
+    }
+    hipError_t ensure(size_t n) { return n <= bytes ? hipSuccess : alloc(n); }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v) {
+    hipError_t e = b.alloc(v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    return hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+struct TableKey {
+    double ecut_g, ecut_e;
+    uint32_t flags;
+    bool operator<(const TableKey& o) const {
+        return std::tie(ecut_g, ecut_e, flags) < std::tie(o.ecut_g, o.ecut_e, o.flags);
+    }
+};
+
+struct DevTables {
+    HostTables host;
+    DevBuf phot, elec, rinv, rinv_scale, aw;
+    Tables view(const float* mumax) const {
+        Tables t;
+        t.phot = phot.as<const float4>();
+        t.mumax = mumax;
+        t.pg_lo = (float)host.pg_lo;
+        t.pg_inv = (float)(1.0 / host.pg_step);
+        t.pg_n = host.pg_n;
+        t.elec = elec.as<const float4>();
+        t.eg_lo = (float)host.eg_lo;
+        t.eg_inv = (float)(1.0 / host.eg_step);
+        t.eg_n = host.eg_n;
+        t.rinv = rinv.as<const float>();
+        t.rinv_scale = rinv_scale.as<const float>();
+        t.nr = host.nr;
+        t.aw = aw.as<const float>();
+        t.aw_lo = (float)host.aw_lo;
+        t.aw_inv = (float)(1.0 / host.aw_step);
+        t.aw_n = host.aw_n;
+        return t;
+    }
+};
+
+int json_int(const char* js, const char* key, int dflt) {
+    if (!js) return dflt;
+    std::string k = std::string("\"") + key + "\"";
+    const char* p = strstr(js, k.c_str());
+    if (!p) return dflt;
+    p = strchr(p + k.size(), ':');
+    if (!p) return dflt;
+    return atoi(p + 1);
+}
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct gdpm_context_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    int ring_log2 = 24;
+    int waves_per_cu = 16;
+    int rebin_bins = 16;
+    std::vector<MaterialParams> mats;
+    int n_grid = 1024;
+    std::map<TableKey, std::unique_ptr<DevTables>> tables;
+    DevBuf rings[2][2];
+    DevBuf ctl;
+    Ctl* host_ctl = nullptr;   // pinned mirror
+    DevBuf tally, dose, sigma, hist, inv_n, mumax;
+    std::vector<hipEvent_t> events;
+    bool busy = false;
+};
+
+struct gdpm_phantom_s {
+    gdpm_context ctx;
+    int nx, ny, nz;
+    double dx, dy, dz;
+    DevBuf vox;
+    std::vector<double> rho_max;   // per material, 0 if absent
+};
+
+struct gdpm_source_s {
+    gdpm_context ctx;
+    int particle;
+    double e_max;
+    int spec_kind, spec_n;
+    float e_mono;
+    DevBuf spec_e, spec_p, spec_c, cdf, guide, beams, beam_of;
+    int nf, n_guide, n_beams;
+    SourceDev view() const {
+        SourceDev s;
+        s.particle = particle;
+        s.spec_kind = spec_kind;
+        s.spec_n = spec_n;
+        s.e_mono = e_mono;
+        s.spec_e = spec_e.as<const float>();
+        s.spec_p = spec_p.as<const float>();
+        s.spec_c = spec_c.as<const float>();
+        s.cdf = cdf.as<const double>();
+        s.nf = nf;
+        s.guide = guide.as<const uint32_t>();
+        s.n_guide = n_guide;
+        s.beams = beams.as<const BeamDev>();
+        s.beam_of = beam_of.as<const uint16_t>();
+        s.n_beams = n_beams;
+        return s;
+    }
+};
+
+struct gdpm_job_s {
+    gdpm_context ctx;
+    gdpm_status status;
+    gdpm_run_stats stats;
+};
+
+namespace {
+
+Geom geom_of(const gdpm_phantom_s* ph) {
+    Geom g;
+    g.vox = ph->vox.as<const uint2>();
+    g.nx = ph->nx;
+    g.ny = ph->ny;
+    g.nz = ph->nz;
+    g.dx = (float)ph->dx;
+    g.dy = (float)ph->dy;
+    g.dz = (float)ph->dz;
+    g.idx = (float)(1.0 / ph->dx);
+    g.idy = (float)(1.0 / ph->dy);
+    g.idz = (float)(1.0 / ph->dz);
+    g.lx = (float)(ph->nx * ph->dx);
+    g.ly = (float)(ph->ny * ph->dy);
+    g.lz = (float)(ph->nz * ph->dz);
+    return g;
+}
+
+gdpm_status get_tables(gdpm_context ctx, double ecut_g, double ecut_e, uint32_t flags,
+                       DevTables** out) {
+    if (ctx->mats.empty()) return fail(GDPM_E_INVALID, "no materials set");
+    TableKey key{ecut_g, ecut_e, flags & 0x3Fu};
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) {
+        *out = it->second.get();
+        return GDPM_OK;
+    }
+    auto t = std::make_unique<DevTables>();
+    std::string err;
+    if (!build_tables(ctx->mats, ctx->n_grid, ecut_g, ecut_e, key.flags, &t->host, &err))
+        return fail(GDPM_E_INVALID, "%s", err.c_str());
+    HIP_TRY(upload(t->phot, t->host.phot));
+    HIP_TRY(upload(t->elec, t->host.elec));
+    HIP_TRY(upload(t->rinv, t->host.rinv));
+    HIP_TRY(upload(t->rinv_scale, t->host.rinv_scale));
+    HIP_TRY(upload(t->aw, t->host.aw));
+    *out = t.get();
+    ctx->tables[key] = std::move(t);
+    return GDPM_OK;
+}
+
+gdpm_status ensure_rings(gdpm_context ctx) {
+    const size_t cap = (size_t)1 << ctx->ring_log2;
+    for (int r = 0; r < 2; ++r)
+        for (int b = 0; b < 2; ++b) HIP_TRY(ctx->rings[r][b].ensure(cap * sizeof(Particle)));
+    return GDPM_OK;
+}
+
+int grid_blocks(gdpm_context ctx) { return std::max(1, ctx->cu_count * ctx->waves_per_cu / 4); }
+
+// ---------------------------------------------------------------------------
+// one run
+// ---------------------------------------------------------------------------
+struct RunPlan {
+    uint64_t n_hist;
+    int nb;
+    double ecut_g, ecut_e;
+    uint32_t flags;
+    bool target;
+};
+
+gdpm_status validate_params(const gdpm_run_params* p, const gdpm_source_s* src, RunPlan* plan) {
+    if (!p) return fail(GDPM_E_INVALID, "run parameters are NULL");
+    plan->nb = p->n_batches == 0 ? 10 : p->n_batches;
+    if (plan->nb < 2 || plan->nb > 1000) return fail(GDPM_E_INVALID, "n_batches must be in [2, 1000]");
+    plan->ecut_g = p->ecut_photon_mev == 0.0 ? 0.05 : p->ecut_photon_mev;
+    plan->ecut_e = p->ecut_electron_mev == 0.0 ? 0.2 : p->ecut_electron_mev;
+    if (!(plan->ecut_g > 0.0 && plan->ecut_g < 1.0) || !(plan->ecut_e > 0.0 && plan->ecut_e < 5.0))
+        return fail(GDPM_E_INVALID, "absorption energies out of range");
+    plan->target = p->target_unc > 0.0;
+    if (!(p->target_unc >= 0.0) || !std::isfinite(p->target_unc))
+        return fail(GDPM_E_INVALID, "target_unc must be finite and >= 0");
+    if (p->n_histories == 0) return fail(GDPM_E_INVALID, "n_histories must be > 0");
+    if (p->n_histories > ((uint64_t)1 << 48)) return fail(GDPM_E_INVALID, "n_histories too large");
+    plan->n_hist = p->n_histories;
+    plan->flags = p->flags;
+    if (p->flags & ~0x7Fu) return fail(GDPM_E_INVALID, "unknown flag bits");
+    if (src->particle == 1 && (p->flags & GDPM_KERMA))
+        return fail(GDPM_E_INVALID, "kerma mode needs a photon source");
+    return GDPM_OK;
+}
+
+struct Timers {
+    double photon = 0, electron = 0;
+    uint32_t passes = 0;
+};
+
+// run transport for histories [h0, h1) into tally slot `slot`
+gdpm_status run_round(gdpm_context ctx, const Tables& T, const Geom& G, const SourceDev& S,
+                      RunDev R, hipStream_t st, uint64_t h0, uint64_t h1, Timers* tm) {
+    Ctl* hc = ctx->host_ctl;
+    Ctl* dc = ctx->ctl.as<Ctl>();
+    // round start: queues are empty; set the source range
+    hc->src_next = h0;
+    hc->src_end = h1;
+    HIP_TRY(hipMemcpyAsync(&dc->src_next, &hc->src_next, 2 * sizeof(unsigned long long),
+                           hipMemcpyHostToDevice, st));
+    const int blocks = grid_blocks(ctx);
+    const int src_type = S.particle == 0 ? 0 : 1;
+    const int nbins = std::min(ctx->rebin_bins, kMaxBins);
+    const float blo = -5.0f, bhi = 5.0f;  // log2 E range of the bins (0.03 .. 32 MeV)
+    const float binv = nbins > 0 ? nbins / (bhi - blo) : 0.0f;
+    if (ctx->events.size() < 4) {
+        for (size_t i = ctx->events.size(); i < 4; ++i) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            ctx->events.push_back(e);
+        }
+    }
+    for (int iter = 0;; ++iter) {
+        for (int k = 0; k < 2; ++k) {
+            const int ri = k == 0 ? src_type : 1 - src_type;
+            const int with_src = k == 0 ? 1 : 0;
+            // the queue a pass reads was filled by the other pass: compact it
+            // and sort it by energy so that wavefronts draw similar particles
+            if (nbins > 1 && (iter > 0 || k == 1))
+                HIP_TRY(launch_rebin(st, std::min(blocks, 4096), dc, R, ri, nbins, blo, binv));
+            HIP_TRY(launch_setup(st, dc, ri, with_src, 1u << 30));
+            HIP_TRY(hipEventRecord(ctx->events[2 * k], st));
+            HIP_TRY(launch_transport(st, ri, blocks, dc, T, G, S, R, with_src));
+            HIP_TRY(hipEventRecord(ctx->events[2 * k + 1], st));
+            HIP_TRY(launch_finish(st, dc, ri));
+            tm->passes++;
+        }
+        HIP_TRY(hipMemcpyAsync(hc, dc, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int k = 0; k < 2; ++k) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
+            const int ri = k == 0 ? src_type : 1 - src_type;
+            (ri == 0 ? tm->photon : tm->electron) += ms * 1e-3;
+        }
+        if (hc->overflow)
+            return fail(GDPM_E_OVERFLOW,
+                        "a particle queue filled up (capacity 2^%d); raise ring_capacity_log2",
+                        ctx->ring_log2);
+        const bool empty = hc->ring[0].tail == hc->ring[0].head &&
+                           hc->ring[1].tail == hc->ring[1].head && hc->src_next >= hc->src_end;
+        if (empty) break;
+        if (iter > 100000) return fail(GDPM_E_DEVICE, "transport made no progress");
+    }
+    return GDPM_OK;
+}
+
+gdpm_status compute_stats(gdpm_context ctx, gdpm_phantom_s* ph, int nb,
+                          const std::vector<double>& nhist, hipStream_t st, double* d_dose,
+                          double* d_sigma, double* unc, double* dmax, double* edep) {
+    const size_t nv = (size_t)ph->nx * ph->ny * ph->nz;
+    std::vector<double> inv(nb);
+    for (int b = 0; b < nb; ++b) inv[b] = nhist[b] > 0 ? 1.0 / nhist[b] : 0.0;
+    HIP_TRY(ctx->inv_n.ensure(nb * sizeof(double)));
+    HIP_TRY(hipMemcpyAsync(ctx->inv_n.p, inv.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
+    Ctl* dc = ctx->ctl.as<Ctl>();
+    Ctl* hc = ctx->host_ctl;
+    hc->red[0] = hc->red[1] = hc->red[2] = hc->red[3] = 0.0;
+    hc->dmax_bits = 0;
+    HIP_TRY(hipMemcpyAsync(&dc->red[0], &hc->red[0], 4 * sizeof(double) + sizeof(unsigned long long),
+                           hipMemcpyHostToDevice, st));
+    const int blocks = (int)std::min<size_t>((nv + 255) / 256, 8192);
+    HIP_TRY(launch_stats(st, blocks, dc, ctx->tally.as<const double>(), nv, nb,
+                         ctx->inv_n.as<const double>(), ph->vox.as<const uint2>(),
+                         ph->dx * ph->dy * ph->dz, d_dose, d_sigma));
+    HIP_TRY(hipMemcpyAsync(&hc->red[0], &dc->red[0], 4 * sizeof(double) + sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double dm;
+    memcpy(&dm, &hc->dmax_bits, sizeof dm);
+    *dmax = dm;
+    *edep = hc->red[0];
+    *unc = (hc->red[2] > 0 && dm > 0) ? hc->red[1] / hc->red[2] / dm : 0.0;
+    return GDPM_OK;
+}
+
+gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdpm_run_params* prm,
+                   double* d_dose, double* d_sigma, double* h_batch, double* h_hist,
+                   hipStream_t st, gdpm_run_stats* out) {
+    const double t_start = now_s();
+    if (!ctx || !ph || !src) return fail(GDPM_E_INVALID, "NULL handle");
+    if (ph->ctx != ctx || src->ctx != ctx) return fail(GDPM_E_INVALID, "handle of another context");
+    RunPlan plan;
+    gdpm_status s = validate_params(prm, src, &plan);
+    if (s) return s;
+    if ((int)ph->rho_max.size() > (int)ctx->mats.size())
+        return fail(GDPM_E_INVALID, "phantom uses more materials than the context has");
+    if (h_hist && (plan.target || plan.n_hist > ((uint64_t)1 << 24)))
+        return fail(GDPM_E_INVALID, "per-history output needs fixed mode and <= 2^24 histories");
+    DevTables* tab = nullptr;
+    s = get_tables(ctx, plan.ecut_g, plan.ecut_e, plan.flags, &tab);
+    if (s) return s;
+    s = ensure_rings(ctx);
+    if (s) return s;
+    // Woodcock majorant of this phantom
+    std::vector<double> rmax(tab->host.n_mat, 0.0);
+    for (size_t m = 0; m < ph->rho_max.size(); ++m) rmax[m] = ph->rho_max[m];
+    const std::vector<float> mm = build_majorant(tab->host, rmax);
+    HIP_TRY(ctx->mumax.ensure(mm.size() * sizeof(float)));
+    HIP_TRY(hipMemcpyAsync(ctx->mumax.p, mm.data(), mm.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    const Tables T = tab->view(ctx->mumax.as<const float>());
+    const Geom G = geom_of(ph);
+    const SourceDev S = src->view();
+    const size_t nv = (size_t)ph->nx * ph->ny * ph->nz;
+    const int nb = plan.nb;
+
+    HIP_TRY(ctx->tally.ensure((size_t)nb * nv * sizeof(double)));
+    HIP_TRY(hipMemsetAsync(ctx->tally.p, 0, (size_t)nb * nv * sizeof(double), st));
+    double* dd = d_dose;
+    double* ds = d_sigma;
+    if (!dd) {
+        HIP_TRY(ctx->dose.ensure(nv * sizeof(double)));
+        dd = ctx->dose.as<double>();
+    }
+    if (!ds) {
+        HIP_TRY(ctx->sigma.ensure(nv * sizeof(double)));
+        ds = ctx->sigma.as<double>();
+    }
+    if (h_hist) {
+        HIP_TRY(ctx->hist.ensure(plan.n_hist * 2 * sizeof(double)));
+        HIP_TRY(hipMemsetAsync(ctx->hist.p, 0, plan.n_hist * 2 * sizeof(double), st));
+    }
+    // control block: empty queues, zero counters
+    Ctl* hc = ctx->host_ctl;
+    memset(hc, 0, sizeof(Ctl));
+    Ctl* dc = ctx->ctl.as<Ctl>();
+    HIP_TRY(hipMemcpyAsync(dc, hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+
+    RunDev R;
+    memset(&R, 0, sizeof R);
+    R.k0 = (uint32_t)prm->seed;
+    R.k1 = (uint32_t)(prm->seed >> 32) ^ prm->job_id;
+    R.ecut_g = (float)plan.ecut_g;
+    R.ecut_e = (float)plan.ecut_e;
+    R.flags = plan.flags;
+    R.hist = h_hist ? ctx->hist.as<double>() : nullptr;
+    R.hist0 = prm->hist0;
+    const uint32_t cap = 1u << ctx->ring_log2;
+    for (int r = 0; r < 2; ++r) {
+        R.buf[r][0] = ctx->rings[r][0].as<Particle>();
+        R.buf[r][1] = ctx->rings[r][1].as<Particle>();
+        R.mask[r] = cap - 1u;
+        R.soft[r] = cap / 2u;
+        R.hard[r] = cap;
+    }
+
+    std::vector<double> nhist(nb, 0.0);
+    Timers tm;
+    uint64_t done = 0;
+    uint32_t rounds = 0;
+    double unc = 0.0, dmax = 0.0, edep = 0.0;
+    const uint64_t max_hist = prm->max_histories ? prm->max_histories : 100 * plan.n_hist;
+    uint64_t round_size = prm->round_size ? prm->round_size : (plan.n_hist + nb - 1) / nb;
+    gdpm_status final = GDPM_OK;
+    const uint64_t hbase = plan.target ? 0 : prm->hist0;
+    for (;;) {
+        // one super-round: N_b rounds of round_size histories, one per batch slot
+        for (int b = 0; b < nb; ++b) {
+            uint64_t h0 = hbase + done, h1 = h0 + round_size;
+            if (!plan.target) h1 = std::min(h1, prm->hist0 + plan.n_hist);
+            if (h1 <= h0) continue;
+            R.tally = ctx->tally.as<double>() + (size_t)b * nv;
+            s = run_round(ctx, T, G, S, R, st, h0, h1, &tm);
+            if (s) return s;
+            nhist[b] += (double)(h1 - h0);
+            done += h1 - h0;
+            rounds++;
+        }
+        s = compute_stats(ctx, ph, nb, nhist, st, dd, ds, &unc, &dmax, &edep);
+        if (s) return s;
+        if (!plan.target) break;
+        if (unc <= prm->target_unc) break;
+        if (done >= max_hist) {
+            final = GDPM_E_NOT_CONVERGED;
+            fail(GDPM_E_NOT_CONVERGED, "uncertainty %.4g above target after %llu histories", unc,
+                 (unsigned long long)done);
+            break;
+        }
+        // histories still needed, from sigma ~ 1/sqrt(N), with a 5% margin
+        const double need = (double)done * ((unc / prm->target_unc) * (unc / prm->target_unc) * 1.05 - 1.0);
+        uint64_t more = (uint64_t)std::ceil(std::max(need, 0.02 * (double)done));
+        more = std::min<uint64_t>(more, max_hist - done);
+        round_size = std::max<uint64_t>(1, (more + nb - 1) / nb);
+    }
+    // counters
+    HIP_TRY(hipMemcpyAsync(hc, dc, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    if (h_batch)
+        HIP_TRY(hipMemcpyAsync(h_batch, ctx->tally.p, (size_t)nb * nv * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+    if (h_hist)
+        HIP_TRY(hipMemcpyAsync(h_hist, ctx->hist.p, plan.n_hist * 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (out) {
+        memset(out, 0, sizeof *out);
+        out->histories = done;
+        out->e_in = hc->e_in;
+        out->e_esc = hc->e_esc;
+        out->e_dep = edep;
+        out->unc_mean_over_dmax = unc;
+        out->dmax = dmax;
+        for (int i = 0; i < 8; ++i) out->events[i] = hc->ev[i];
+        out->events[GDPM_EV_HISTORIES] = done;
+        out->passes = tm.passes;
+        out->rounds = rounds;
+        out->t_photon_s = tm.photon;
+        out->t_electron_s = tm.electron;
+        out->t_kernel_s = tm.photon + tm.electron;
+        out->t_total_s = now_s() - t_start;
+    }
+    return final;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* gdpm_last_error(void) { return g_err.c_str(); }
+
+gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out) {
+    if (!out) return fail(GDPM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (hip_device < 0 || hip_device >= n) return fail(GDPM_E_INVALID, "no HIP device %d", hip_device);
+    HIP_TRY(hipSetDevice(hip_device));
+    auto ctx = std::make_unique<gdpm_context_s>();
+    ctx->device = hip_device;
+    ctx->ring_log2 = json_int(opts_json, "ring_capacity_log2", 24);
+    ctx->waves_per_cu = json_int(opts_json, "waves_per_cu", 16);
+    ctx->rebin_bins = json_int(opts_json, "rebin_bins", 16);
+    if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
+    if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > 64) return fail(GDPM_E_INVALID, "waves_per_cu in [1, 64]");
+    if (ctx->rebin_bins < 0 || ctx->rebin_bins > kMaxBins) return fail(GDPM_E_INVALID, "rebin_bins in [0, 64]");
+    HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device));
+    HIP_TRY(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    HIP_TRY(ctx->ctl.alloc(sizeof(Ctl)));
+    HIP_TRY(hipHostMalloc((void**)&ctx->host_ctl, sizeof(Ctl), hipHostMallocDefault));
+    memset(ctx->host_ctl, 0, sizeof(Ctl));
+    *out = ctx.release();
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_context_destroy(gdpm_context ctx) {
+    if (!ctx) return fail(GDPM_E_INVALID, "NULL context");
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_set_materials(gdpm_context ctx, const gdpm_material* m, int n, int n_grid) {
+    if (!ctx || !m) return fail(GDPM_E_INVALID, "NULL argument");
+    if (n < 1 || n > kMaxMaterials) return fail(GDPM_E_INVALID, "1..%d materials", kMaxMaterials);
+    if (n_grid == 0) n_grid = 1024;
+    if (n_grid < 256 || n_grid > 8192) return fail(GDPM_E_INVALID, "n_grid in [256, 8192]");
+    std::vector<MaterialParams> mats(n);
+    for (int i = 0; i < n; ++i) {
+        if (!(m[i].z > 0) || !(m[i].z_over_a > 0) || !(m[i].i_ev > 0) || !std::isfinite(m[i].z) ||
+            !std::isfinite(m[i].z_over_a) || !std::isfinite(m[i].i_ev))
+            return fail(GDPM_E_INVALID, "material %d: parameters must be positive and finite", i);
+        mats[i] = {m[i].z, m[i].z_over_a, m[i].i_ev};
+    }
+    ctx->mats = mats;
+    ctx->n_grid = n_grid;
+    ctx->tables.clear();
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_phantom_create(gdpm_context ctx, int nx, int ny, int nz, double dx, double dy,
+                                double dz, const uint8_t* mat, const float* density,
+                                gdpm_phantom* out) {
+    if (!ctx || !mat || !density || !out) return fail(GDPM_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (ctx->mats.empty()) return fail(GDPM_E_INVALID, "set materials first");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 2048 || ny > 2048 || nz > 1024)
+        return fail(GDPM_E_INVALID, "dimensions must be in [1,2048]x[1,2048]x[1,1024]");
+    if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) || !std::isfinite(dy) ||
+        !std::isfinite(dz))
+        return fail(GDPM_E_INVALID, "voxel sizes must be positive");
+    const size_t nv = (size_t)nx * ny * nz;
+    std::vector<uint2> vox(nv);
+    std::vector<double> rmax(ctx->mats.size(), 0.0);
+    for (size_t v = 0; v < nv; ++v) {
+        const float r = density[v];
+        if (mat[v] >= ctx->mats.size())
+            return fail(GDPM_E_INVALID, "voxel %zu: material %d not defined", v, (int)mat[v]);
+        if (!(r > 0.0f) || !std::isfinite(r))
+            return fail(GDPM_E_INVALID, "voxel %zu: density must be positive and finite", v);
+        uint32_t bits;
+        memcpy(&bits, &r, 4);
+        vox[v] = make_uint2(bits, mat[v]);
+        rmax[mat[v]] = std::max(rmax[mat[v]], (double)r);
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto ph = std::make_unique<gdpm_phantom_s>();
+    ph->ctx = ctx;
+    ph->nx = nx;
+    ph->ny = ny;
+    ph->nz = nz;
+    ph->dx = dx;
+    ph->dy = dy;
+    ph->dz = dz;
+    ph->rho_max = rmax;
+    HIP_TRY(upload(ph->vox, vox));
+    *out = ph.release();
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_phantom_destroy(gdpm_phantom ph) {
+    if (!ph) return fail(GDPM_E_INVALID, "NULL phantom");
+    delete ph;
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm_source* out) {
+    if (!ctx || !d || !out) return fail(GDPM_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (d->particle != 0 && d->particle != 1) return fail(GDPM_E_INVALID, "particle must be 0 or 1");
+    if (d->n_beams < 1 || !d->beams) return fail(GDPM_E_INVALID, "need at least one beam");
+    if (d->n_beams > 65535) return fail(GDPM_E_INVALID, "at most 65535 beams");
+    auto src = std::make_unique<gdpm_source_s>();
+    src->ctx = ctx;
+    src->particle = d->particle;
+    const gdpm_spectrum& sp = d->spectrum;
+    src->spec_kind = sp.kind;
+    std::vector<float> se, spp, sc;
+    if (sp.kind == 0) {
+        if (!(sp.e_mono > 0) || sp.e_mono > kEmax)
+            return fail(GDPM_E_INVALID, "monoenergetic energy must be in (0, 30] MeV");
+        src->e_mono = (float)sp.e_mono;
+        src->e_max = sp.e_mono;
+        src->spec_n = 0;
+    } else if (sp.kind == 1) {
+        if (sp.n_pts < 2 || !sp.e_mev || !sp.pdf) return fail(GDPM_E_INVALID, "spectrum needs >= 2 points");
+        double area = 0.0;
+        sc.push_back(0.0f);
+        std::vector<double> c(sp.n_pts, 0.0);
+        for (int i = 0; i < sp.n_pts; ++i) {
+            if (!(sp.e_mev[i] > 0) || sp.e_mev[i] > kEmax || !(sp.pdf[i] >= 0) || !std::isfinite(sp.pdf[i]))
+                return fail(GDPM_E_INVALID, "spectrum point %d out of range", i);
+            if (i > 0 && !(sp.e_mev[i] > sp.e_mev[i - 1]))
+                return fail(GDPM_E_INVALID, "spectrum energies must increase");
+            if (i > 0) {
+                area += 0.5 * (sp.pdf[i - 1] + sp.pdf[i]) * (sp.e_mev[i] - sp.e_mev[i - 1]);
+                c[i] = area;
+            }
+        }
+        if (!(area > 0)) return fail(GDPM_E_INVALID, "spectrum has zero area");
+        for (int i = 0; i < sp.n_pts; ++i) {
+            se.push_back((float)sp.e_mev[i]);
+            spp.push_back((float)sp.pdf[i]);
+        }
+        sc.clear();
+        for (int i = 0; i < sp.n_pts; ++i) sc.push_back((float)c[i]);
+        src->spec_n = sp.n_pts;
+        src->e_mono = 0.0f;
+        src->e_max = sp.e_mev[sp.n_pts - 1];
+    } else {
+        return fail(GDPM_E_INVALID, "spectrum kind must be 0 or 1");
+    }
+    // beams and the beamlet cumulative probabilities P(I): normalised prefix
+    // sums of f_I over all beams (section 2.3.1), in double precision
+    std::vector<BeamDev> beams(d->n_beams);
+    size_t nf = 0;
+    for (int b = 0; b < d->n_beams; ++b) {
+        const gdpm_beam& bm = d->beams[b];
+        if (bm.nbx < 1 || bm.nby < 1 || !(bm.bw_cm > 0) || !(bm.bh_cm > 0))
+            return fail(GDPM_E_INVALID, "beam %d: bad beamlet grid", b);
+        double dn = 0, en = 0, de = 0;
+        for (int i = 0; i < 3; ++i) {
+            dn += bm.dir[i] * bm.dir[i];
+            en += bm.e1[i] * bm.e1[i];
+            de += bm.dir[i] * bm.e1[i];
+            if (!std::isfinite(bm.iso_cm[i])) return fail(GDPM_E_INVALID, "beam %d: bad isocentre", b);
+        }
+        if (std::fabs(dn - 1) > 1e-6 || std::fabs(en - 1) > 1e-6 || std::fabs(de) > 1e-6)
+            return fail(GDPM_E_INVALID, "beam %d: dir and e1 must be orthonormal", b);
+        nf += (size_t)bm.nbx * bm.nby;
+    }
+    if (nf > ((size_t)1 << 30)) return fail(GDPM_E_INVALID, "too many beamlets");
+    std::vector<double> cdf(nf + 1, 0.0);
+    std::vector<uint16_t> beam_of(nf);
+    double tot = 0.0;
+    size_t gi = 0;
+    for (int b = 0; b < d->n_beams; ++b) {
+        const gdpm_beam& bm = d->beams[b];
+        BeamDev& o = beams[b];
+        const double e2[3] = {bm.dir[1] * bm.e1[2] - bm.dir[2] * bm.e1[1],
+                              bm.dir[2] * bm.e1[0] - bm.dir[0] * bm.e1[2],
+                              bm.dir[0] * bm.e1[1] - bm.dir[1] * bm.e1[0]};
+        for (int i = 0; i < 3; ++i) {
+            o.iso[i] = (float)bm.iso_cm[i];
+            o.dir[i] = (float)bm.dir[i];
+            o.e1[i] = (float)bm.e1[i];
+            o.e2[i] = (float)e2[i];
+        }
+        o.sad = (float)bm.sad_cm;
+        o.bw = (float)bm.bw_cm;
+        o.bh = (float)bm.bh_cm;
+        o.hx = (float)(0.5 * bm.nbx * bm.bw_cm);
+        o.hy = (float)(0.5 * bm.nby * bm.bh_cm);
+        o.nbx = bm.nbx;
+        o.nby = bm.nby;
+        o.off = (int)gi;
+        for (int j = 0; j < bm.nbx * bm.nby; ++j, ++gi) {
+            double f = bm.intensity ? (double)bm.intensity[j] : 1.0;
+            if (!std::isfinite(f)) return fail(GDPM_E_INVALID, "beam %d: intensity not finite", b);
+            if (f < 0.0) f = 0.0;
+            cdf[gi] = tot;
+            beam_of[gi] = (uint16_t)b;
+            tot += f;
+        }
+    }
+    if (!(tot > 0.0)) return fail(GDPM_E_INVALID, "fluence maps are all zero");
+    for (size_t i = 0; i < nf; ++i) cdf[i] /= tot;
+    cdf[nf] = 1.0;
+    // guide table (indexed search): guide[k] = I with P(I) <= k / G < P(I+1)
+    const size_t ng = std::max<size_t>(1, nf);
+    std::vector<uint32_t> guide(ng);
+    size_t I = 0;
+    for (size_t k = 0; k < ng; ++k) {
+        const double r = (double)k / (double)ng;
+        while (I + 1 < nf && cdf[I + 1] <= r) ++I;
+        guide[k] = (uint32_t)I;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(upload(src->spec_e, se));
+    HIP_TRY(upload(src->spec_p, spp));
+    HIP_TRY(upload(src->spec_c, sc));
+    HIP_TRY(upload(src->cdf, cdf));
+    HIP_TRY(upload(src->guide, guide));
+    HIP_TRY(upload(src->beams, beams));
+    HIP_TRY(upload(src->beam_of, beam_of));
+    src->nf = (int)nf;
+    src->n_guide = (int)ng;
+    src->n_beams = d->n_beams;
+    *out = src.release();
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_source_destroy(gdpm_source src) {
+    if (!src) return fail(GDPM_E_INVALID, "NULL source");
+    delete src;
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdpm_run_params* prm,
+                     double* dose, double* sigma, double* batch_edep, double* hist_out,
+                     gdpm_run_stats* stats) {
+    if (!ctx) return fail(GDPM_E_INVALID, "NULL context");
+    if (ctx->busy) return fail(GDPM_E_BUSY, "context busy");
+    HIP_TRY(hipSetDevice(ctx->device));
+    ctx->busy = true;
+    gdpm_status s = do_run(ctx, ph, src, prm, nullptr, nullptr, batch_edep, hist_out, ctx->stream, stats);
+    ctx->busy = false;
+    if (s != GDPM_OK && s != GDPM_E_NOT_CONVERGED) return s;
+    const size_t nv = (size_t)ph->nx * ph->ny * ph->nz;
+    if (dose) HIP_TRY(hipMemcpy(dose, ctx->dose.p, nv * sizeof(double), hipMemcpyDeviceToHost));
+    if (sigma) HIP_TRY(hipMemcpy(sigma, ctx->sigma.p, nv * sizeof(double), hipMemcpyDeviceToHost));
+    return s;
+}
+
+gdpm_status gdpm_run_async(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
+                           const gdpm_run_params* prm, double* d_dose, double* d_sigma,
+                           void* hip_stream, gdpm_job* out) {
+    if (!ctx || !out) return fail(GDPM_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (ctx->busy) return fail(GDPM_E_BUSY, "context busy");
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto job = std::make_unique<gdpm_job_s>();
+    job->ctx = ctx;
+    memset(&job->stats, 0, sizeof job->stats);
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    ctx->busy = true;
+    job->status = do_run(ctx, ph, src, prm, d_dose, d_sigma, nullptr, nullptr, st, &job->stats);
+    ctx->busy = false;
+    if (job->status != GDPM_OK && job->status != GDPM_E_NOT_CONVERGED) return job->status;
+    *out = job.release();
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_job_wait(gdpm_job job, gdpm_run_stats* stats) {
+    if (!job) return fail(GDPM_E_INVALID, "NULL job");
+    if (stats) *stats = job->stats;
+    return job->status;
+}
+
+gdpm_status gdpm_job_release(gdpm_job job) {
+    if (!job) return fail(GDPM_E_INVALID, "NULL job");
+    delete job;
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_tables_host(const gdpm_material* m, int n, int n_grid, double ecut_g, double ecut_e,
+                             uint32_t flags, int which, float* out, size_t cap, size_t* len,
+                             double grid[4]) {
+    if (!m || !len) return fail(GDPM_E_INVALID, "NULL argument");
+    if (n < 1 || n > kMaxMaterials) return fail(GDPM_E_INVALID, "1..%d materials", kMaxMaterials);
+    if (n_grid == 0) n_grid = 1024;
+    std::vector<MaterialParams> mats(n);
+    for (int i = 0; i < n; ++i) mats[i] = {m[i].z, m[i].z_over_a, m[i].i_ev};
+    HostTables T;
+    std::string err;
+    if (!build_tables(mats, n_grid, ecut_g, ecut_e, flags & 0x3Fu, &T, &err))
+        return fail(GDPM_E_INVALID, "%s", err.c_str());
+    const std::vector<float>* v = nullptr;
+    double g[4] = {0, 0, 0, (double)n};
+    switch (which) {
+    case 0: v = &T.phot; g[0] = T.pg_lo; g[1] = T.pg_step; g[2] = T.pg_n; break;
+    case 1: v = &T.elec; g[0] = T.eg_lo; g[1] = T.eg_step; g[2] = T.eg_n; break;
+    case 2: v = &T.rinv; g[0] = 0.0; g[1] = 0.0; g[2] = T.nr; break;
+    case 3: v = &T.aw; g[0] = T.aw_lo; g[1] = T.aw_step; g[2] = T.aw_n; break;
+    default: return fail(GDPM_E_INVALID, "which must be 0..3");
+    }
+    if (which == 2) {
+        // the grid spacing of the inverse range differs per material: return w_max of material 0
+        g[1] = 1.0 / T.rinv_scale[0];
+    }
+    *len = v->size();
+    if (grid) memcpy(grid, g, sizeof g);
+    if (out) {
+        if (cap < v->size()) return fail(GDPM_E_INVALID, "output holds %zu floats, %zu needed", cap, v->size());
+        memcpy(out, v->data(), v->size() * sizeof(float));
+    }
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_test_philox(gdpm_context ctx, const uint32_t key[2], const uint32_t* ctr,
+                             uint32_t* out, int n) {
+    if (!ctx || !key || !ctr || !out || n < 1) return fail(GDPM_E_INVALID, "bad arguments");
+    HIP_TRY(hipSetDevice(ctx->device));
+    DevBuf a, b;
+    HIP_TRY(a.alloc((size_t)n * 16));
+    HIP_TRY(b.alloc((size_t)n * 16));
+    HIP_TRY(hipMemcpy(a.p, ctr, (size_t)n * 16, hipMemcpyHostToDevice));
+    HIP_TRY(launch_test_philox(ctx->stream, key[0], key[1], a.as<const uint4>(), b.as<uint4>(), n));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(out, b.p, (size_t)n * 16, hipMemcpyDeviceToHost));
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_test_sample(gdpm_context ctx, int which, double e, double p1, double p2,
+                             uint64_t seed, int n, float* out1, float* out2) {
+    if (!ctx || !out1 || n < 1 || which < 0 || which > 5) return fail(GDPM_E_INVALID, "bad arguments");
+    HIP_TRY(hipSetDevice(ctx->device));
+    DevTables* tab = nullptr;
+    gdpm_status s = get_tables(ctx, 0.05, 0.2, 0u, &tab);
+    if (s) return s;
+    DevBuf a, b;
+    HIP_TRY(a.alloc((size_t)n * 4));
+    HIP_TRY(b.alloc((size_t)n * 4));
+    HIP_TRY(launch_test_sample(ctx->stream, tab->view(nullptr), which, (float)e, (float)p1, (float)p2,
+                               (uint32_t)seed, (uint32_t)(seed >> 32), n, a.as<float>(), b.as<float>()));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(out1, a.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (out2) HIP_TRY(hipMemcpy(out2, b.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_test_source(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, uint64_t seed,
+                             uint32_t job, uint64_t hist0, int n, float* out) {
+    if (!ctx || !ph || !src || !out || n < 1) return fail(GDPM_E_INVALID, "bad arguments");
+    HIP_TRY(hipSetDevice(ctx->device));
+    DevBuf a;
+    HIP_TRY(a.alloc((size_t)n * 32));
+    HIP_TRY(launch_test_source(ctx->stream, src->view(), geom_of(ph), (uint32_t)seed,
+                               (uint32_t)(seed >> 32) ^ job, (unsigned long long)hist0, n, a.as<float>()));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(out, a.p, (size_t)n * 32, hipMemcpyDeviceToHost));
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_test_lookup(gdpm_context ctx, double ecut_g, double ecut_e, uint32_t flags, int which,
+                             int mat, const float* in, float* out, int n) {
+    if (!ctx || !in || !out || n < 1 || which < 0 || which > 6) return fail(GDPM_E_INVALID, "bad arguments");
+    if (mat < 0 || mat >= (int)ctx->mats.size()) return fail(GDPM_E_INVALID, "material out of range");
+    HIP_TRY(hipSetDevice(ctx->device));
+    DevTables* tab = nullptr;
+    gdpm_status s = get_tables(ctx, ecut_g, ecut_e, flags, &tab);
+    if (s) return s;
+    DevBuf a, b;
+    HIP_TRY(a.alloc((size_t)n * 4));
+    HIP_TRY(b.alloc((size_t)n * 4));
+    HIP_TRY(hipMemcpy(a.p, in, (size_t)n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(launch_test_lookup(ctx->stream, tab->view(nullptr), which, mat, a.as<const float>(),
+                               b.as<float>(), n));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(out, b.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return GDPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1376 @@
+// Transport kernels of libgdpm for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// The paper separates photon and electron transport into different kernel
+// launches so that threads of a warp follow the same physics (section 2.2.1,
+// Fig. 1): particles live in a particle array and two secondary stacks, and the
+// host alternates source generation, photon kernels and electron kernels.
+// Here the same separation is kept (one queue per particle type, one kernel per
+// type) but the launch shape is built for CDNA:
+//   - a kernel is a persistent grid of wavefronts; each lane holds one
+//     particle and advances it by one event per iteration (one Woodcock flight
+//     for a photon, one condensed-history step for an electron); a lane whose
+//     particle ends takes the next one from the queue (or starts a new source
+//     history), so lanes stay busy instead of idling until the slowest particle
+//     of the wave finishes;
+//   - queue traffic is per wavefront: a ballot + mbcnt prefix gives each lane
+//     its slot and one atomic per 256 records reserves ring space, one atomic
+//     per 64 items claims input;
+//   - dose goes into double-precision tallies with hardware FP64 atomics, one
+//     per voxel visit of a charged particle (deposits merged in registers).
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11); a particle owns the
+// stream (history id, path id) and the draw order of each event is fixed, so
+// results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev_types.h"
+
+namespace gdpm {
+
+#define GDPM_DEV __device__ __forceinline__
+
+constexpr float kMec2f = 0.51099895f;
+constexpr float kTwoMec2f = 1.0219979f;
+constexpr float kLn2f = 0.693147180559945f;
+constexpr float kMwIsoF = 20.0f;
+
+// ---------------------------------------------------------------------------
+// hardware math (v_log_f32 is log2, v_exp_f32 is 2^x, v_sin/v_cos take turns)
+// ---------------------------------------------------------------------------
+GDPM_DEV float hlog2(float x) { return __builtin_amdgcn_logf(x); }
+GDPM_DEV float hexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+GDPM_DEV float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+GDPM_DEV float hrsq(float x) { return __builtin_amdgcn_rsqf(x); }
+GDPM_DEV float hrcp(float x) { return __builtin_amdgcn_rcpf(x); }
+GDPM_DEV float sin_turns(float t) { return __builtin_amdgcn_sinf(t); }
+GDPM_DEV float cos_turns(float t) { return __builtin_amdgcn_cosf(t); }
+GDPM_DEV float neg_ln(float u) { return -kLn2f * hlog2(u); }
+
+// ---------------------------------------------------------------------------
+// wavefront helpers
+// ---------------------------------------------------------------------------
+GDPM_DEV uint32_t lane_id() { return __lane_id(); }
+GDPM_DEV uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+GDPM_DEV uint64_t ballot(bool p) { return __ballot(p); }
+GDPM_DEV uint32_t first_lane(uint64_t m) { return (uint32_t)(__ffsll((unsigned long long)m) - 1); }
+GDPM_DEV uint32_t bcast(uint32_t v, uint32_t lane) { return __builtin_amdgcn_readlane(v, lane); }
+// device-coherent load of a counter, made wave-uniform
+GDPM_DEV uint32_t load_agent(uint32_t* p) {
+    return __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+GDPM_DEV double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+GDPM_DEV uint32_t wave_sum(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10
+// ---------------------------------------------------------------------------
+GDPM_DEV void philox(uint32_t k0, uint32_t k1, uint32_t& x0, uint32_t& x1, uint32_t& x2,
+                     uint32_t& x3) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
+        const uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+        const uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// A lane's stream: key (k0, k1), counter (hist lo, hist hi, path, ctr >> 2);
+// draw d is word d & 3 of its block; the current block is cached.
+struct Rng {
+    uint32_t hlo, hhi, path, ctr;
+    uint32_t b0, b1, b2, b3;
+};
+
+GDPM_DEV void rng_block(Rng& r, uint32_t k0, uint32_t k1) {
+    uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = r.ctr >> 2;
+    philox(k0, k1, x0, x1, x2, x3);
+    r.b0 = x0;
+    r.b1 = x1;
+    r.b2 = x2;
+    r.b3 = x3;
+}
+
+// (2 (x >> 9) + 1) 2^-24: exact in single and double precision, inside (0, 1)
+GDPM_DEV float uniform(Rng& r, uint32_t k0, uint32_t k1) {
+    const uint32_t w = r.ctr & 3u;
+    if (w == 0u) rng_block(r, k0, k1);
+    const uint32_t x = w == 0u ? r.b0 : (w == 1u ? r.b1 : (w == 2u ? r.b2 : r.b3));
+    r.ctr += 1u;
+    return (float)(x >> 9) * 0x1p-23f + 0x1p-24f;
+}
+
+// path id of the secondary created in role `word` at the parent's current counter
+GDPM_DEV uint32_t spawn_path(const Rng& r, uint32_t k0, uint32_t k1, int word) {
+    uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = 0x80000000u | r.ctr;
+    philox(k0, k1, x0, x1, x2, x3);
+    return word == 0 ? x0 : (word == 1 ? x1 : (word == 2 ? x2 : x3));
+}
+
+// ---------------------------------------------------------------------------
+// table lookups (linear in log2 E)
+// ---------------------------------------------------------------------------
+GDPM_DEV void grid(float lg, float lo, float inv, int n, int& i, float& t) {
+    float f = (lg - lo) * inv;
+    f = fminf(fmaxf(f, 0.0f), (float)(n - 1));
+    i = min((int)f, n - 2);
+    t = f - (float)i;
+}
+
+GDPM_DEV float4 lerp4(const float4* tab, int i, float t) {
+    const float4 a = tab[i], b = tab[i + 1];
+    return make_float4(fmaf(t, b.x - a.x, a.x), fmaf(t, b.y - a.y, a.y), fmaf(t, b.z - a.z, a.z),
+                       fmaf(t, b.w - a.w, a.w));
+}
+
+GDPM_DEV float lerp1(const float* tab, int i, float t) {
+    const float a = tab[i], b = tab[i + 1];
+    return fmaf(t, b - a, a);
+}
+
+GDPM_DEV float4 elec_at(const Tables& T, int m, float e) {
+    int i;
+    float t;
+    grid(hlog2(e), T.eg_lo, T.eg_inv, T.eg_n, i, t);
+    return lerp4(T.elec + m * T.eg_n, i, t);
+}
+
+// energy whose residual range is r (g/cm^2)
+GDPM_DEV float range_inv(const Tables& T, int m, float r) {
+    const float f = fminf(hsqrt(fmaxf(r, 0.0f)) * T.rinv_scale[m], (float)(T.nr - 1));
+    const int i = min((int)f, T.nr - 2);
+    return lerp1(T.rinv + m * T.nr, i, f - (float)i);
+}
+
+// modified-Wentzel deflection mu = (1 - cos)/2 for t = s / lambda_1
+GDPM_DEV float mw_mu(const Tables& T, float tt, float u) {
+    if (!(tt < kMwIsoF)) return u;
+    const float f = fminf((hlog2(tt) - T.aw_lo) * T.aw_inv, (float)(T.aw_n - 1));
+    const int i = min(max((int)f, 0), T.aw_n - 2);  // f < 0 extrapolates the first cell
+    const float a = hexp2(lerp1(T.aw, i, f - (float)i));
+    return a * u / (1.0f + a - u);
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+GDPM_DEV void rotate(float& u, float& v, float& w, float ct, float st, float turns) {
+    const float cp = cos_turns(turns), sp = sin_turns(turns);
+    const float r2 = u * u + v * v;
+    float nu, nv, nw;
+    if (r2 > 1e-12f) {
+        const float ir = hrsq(r2), r = r2 * ir;
+        nu = u * ct + st * (u * w * cp - v * sp) * ir;
+        nv = v * ct + st * (v * w * cp + u * sp) * ir;
+        nw = w * ct - st * cp * r;
+    } else {
+        nu = st * cp;
+        nv = st * sp;
+        nw = (w >= 0.0f ? ct : -ct);
+    }
+    const float n = hrsq(nu * nu + nv * nv + nw * nw);
+    u = nu * n;
+    v = nv * n;
+    w = nw * n;
+}
+
+GDPM_DEV int clampi(int x, int n) { return min(max(x, 0), n - 1); }
+
+GDPM_DEV int voxel_of(const Geom& G, float x, float y, float z, int& ix, int& iy, int& iz) {
+    ix = clampi((int)floorf(x * G.idx), G.nx);
+    iy = clampi((int)floorf(y * G.idy), G.ny);
+    iz = clampi((int)floorf(z * G.idz), G.nz);
+    return ix + G.nx * (iy + G.ny * iz);
+}
+
+GDPM_DEV uint32_t pack_vox(int ix, int iy, int iz) {
+    return (uint32_t)ix | ((uint32_t)iy << 11) | ((uint32_t)iz << 22);
+}
+
+GDPM_DEV bool outside(const Geom& G, float x, float y, float z) {
+    return !(x >= 0.0f && x < G.lx && y >= 0.0f && y < G.ly && z >= 0.0f && z < G.lz);
+}
+
+// distance to the exit face of voxel (ix, iy, iz) along the direction; axis of that face
+GDPM_DEV float face_dist(const Geom& G, float x, float y, float z, float u, float v, float w,
+                         int ix, int iy, int iz, int& ax) {
+    float best = 3.0e38f;
+    ax = 0;
+    if (u != 0.0f) {
+        const float d = ((u > 0.0f ? (float)(ix + 1) : (float)ix) * G.dx - x) / u;
+        best = d;
+    }
+    if (v != 0.0f) {
+        const float d = ((v > 0.0f ? (float)(iy + 1) : (float)iy) * G.dy - y) / v;
+        if (d < best) {
+            best = d;
+            ax = 1;
+        }
+    }
+    if (w != 0.0f) {
+        const float d = ((w > 0.0f ? (float)(iz + 1) : (float)iz) * G.dz - z) / w;
+        if (d < best) {
+            best = d;
+            ax = 2;
+        }
+    }
+    return fmaxf(best, 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// source: history h -> primary particle (section 2.3)
+// ---------------------------------------------------------------------------
+GDPM_DEV float spectrum_energy(const SourceDev& S, float u) {
+    if (S.spec_kind == 0) return S.e_mono;
+    const int n = S.spec_n;
+    const float r = u * S.spec_c[n - 1];
+    int j = 0;
+    while (j < n - 2 && S.spec_c[j + 1] <= r) ++j;
+    const float e0 = S.spec_e[j], e1 = S.spec_e[j + 1];
+    const float p0 = S.spec_p[j], sl = (S.spec_p[j + 1] - p0) / (e1 - e0);
+    const float d = r - S.spec_c[j];
+    const float den = p0 + hsqrt(fmaxf(0.0f, p0 * p0 + 2.0f * sl * d));
+    const float x = den > 0.0f ? 2.0f * d / den : 0.0f;
+    return fminf(fmaxf(e0 + x, e0), e1);
+}
+
+// beamlet I with P(I) <= r < P(I+1); start from the guide table, walk both ways
+GDPM_DEV int beamlet_of(const SourceDev& S, float u) {
+    const double r = (double)u;
+    int k = (int)(r * (double)S.n_guide);
+    k = min(k, S.n_guide - 1);
+    int i = (int)S.guide[k];
+    while (i > 0 && S.cdf[i] > r) --i;
+    while (i < S.nf - 1 && S.cdf[i + 1] <= r) ++i;
+    return i;
+}
+
+struct Primary {
+    float x, y, z, u, v, w, e;
+    int beamlet;
+    bool in;
+};
+
+GDPM_DEV Primary make_primary(const SourceDev& S, const Geom& G, Rng& r, uint32_t k0, uint32_t k1) {
+    Primary p;
+    p.e = spectrum_energy(S, uniform(r, k0, k1));
+    const int gi = beamlet_of(S, uniform(r, k0, k1));
+    const float ux = uniform(r, k0, k1), uy = uniform(r, k0, k1);
+    p.beamlet = gi;
+    const BeamDev& b = S.beams[S.beam_of[gi]];
+    const int j = gi - b.off;
+    const int jx = j % b.nbx, jy = j / b.nbx;
+    const float px = ((float)jx + ux) * b.bw - b.hx;
+    const float py = ((float)jy + uy) * b.bh - b.hy;
+    const float qx = b.iso[0] + px * b.e1[0] + py * b.e2[0];
+    const float qy = b.iso[1] + px * b.e1[1] + py * b.e2[1];
+    const float qz = b.iso[2] + px * b.e1[2] + py * b.e2[2];
+    float ox, oy, oz, tlo;
+    if (b.sad > 0.0f) {
+        ox = b.iso[0] - b.sad * b.dir[0];
+        oy = b.iso[1] - b.sad * b.dir[1];
+        oz = b.iso[2] - b.sad * b.dir[2];
+        const float dx = qx - ox, dy = qy - oy, dz = qz - oz;
+        const float n = hrsq(dx * dx + dy * dy + dz * dz);
+        p.u = dx * n;
+        p.v = dy * n;
+        p.w = dz * n;
+        tlo = 0.0f;
+    } else {
+        ox = qx;
+        oy = qy;
+        oz = qz;
+        p.u = b.dir[0];
+        p.v = b.dir[1];
+        p.w = b.dir[2];
+        tlo = -3.0e38f;
+    }
+    // slab-method ray-box entry
+    float tmin = tlo, tmax = 3.0e38f;
+    int ax = -1;
+    bool miss = false;
+    const float o[3] = {ox, oy, oz}, d[3] = {p.u, p.v, p.w}, L[3] = {G.lx, G.ly, G.lz};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] != 0.0f) {
+            const float ta = (0.0f - o[i]) / d[i], tb = (L[i] - o[i]) / d[i];
+            const float tn = fminf(ta, tb), tf = fmaxf(ta, tb);
+            if (tn > tmin) {
+                tmin = tn;
+                ax = i;
+            }
+            tmax = fminf(tmax, tf);
+        } else if (o[i] < 0.0f || o[i] > L[i]) {
+            miss = true;
+        }
+    }
+    p.in = !miss && tmax > tmin;
+    p.x = ox + tmin * p.u;
+    p.y = oy + tmin * p.v;
+    p.z = oz + tmin * p.w;
+    if (ax == 0) p.x = p.u > 0.0f ? 0.0f : G.lx;
+    if (ax == 1) p.y = p.v > 0.0f ? 0.0f : G.ly;
+    if (ax == 2) p.z = p.w > 0.0f ? 0.0f : G.lz;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// queue reservation and claiming (wave-uniform state)
+// ---------------------------------------------------------------------------
+struct PushState {
+    uint32_t next, end;  // reserved, unused ring slots [next, end)
+};
+
+// Reserve `n` consecutive logical positions for this wave; item j of the wave
+// lands in slot slot_of(j).  Returns false if the ring would exceed its hard
+// limit (the run is then marked overflowed and the items are dropped).
+struct Reservation {
+    uint32_t old_next, old_avail, new_base;
+    bool ok;
+};
+
+GDPM_DEV Reservation reserve(PushState& ps, RingCtl* rc, uint32_t head, uint32_t hard, uint32_t n,
+                             Ctl* ctl) {
+    Reservation r;
+    r.old_next = ps.next;
+    r.old_avail = ps.end - ps.next;
+    r.new_base = 0;
+    r.ok = true;
+    if (n <= r.old_avail) {
+        ps.next += n;
+        return r;
+    }
+    const uint32_t leader = first_lane(ballot(true));
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(&rc->tail, kPushChunk);
+    base = bcast(base, leader);
+    if (base + kPushChunk - head > hard) {
+        if (lane_id() == leader) atomicOr(&ctl->overflow, 1u);
+        r.ok = false;
+        ps.next = ps.end;
+        return r;
+    }
+    r.new_base = base;
+    ps.next = base + (n - r.old_avail);
+    ps.end = base + kPushChunk;
+    return r;
+}
+
+GDPM_DEV uint32_t slot_of(const Reservation& r, uint32_t j) {
+    return j < r.old_avail ? r.old_next + j : r.new_base + (j - r.old_avail);
+}
+
+GDPM_DEV void store(Particle* buf, uint32_t mask, uint32_t slot, const Particle& p) {
+    float4* d = reinterpret_cast<float4*>(buf + (slot & mask));
+    const float4* s = reinterpret_cast<const float4*>(&p);
+    d[0] = s[0];
+    d[1] = s[1];
+    d[2] = s[2];
+    d[3] = s[3];
+}
+
+GDPM_DEV Particle load(const Particle* buf, uint32_t mask, uint32_t slot) {
+    Particle p;
+    const float4* s = reinterpret_cast<const float4*>(buf + (slot & mask));
+    float4* d = reinterpret_cast<float4*>(&p);
+    d[0] = s[0];
+    d[1] = s[1];
+    d[2] = s[2];
+    d[3] = s[3];
+    return p;
+}
+
+// mark the unused tail of this wave's reservation as empty slots
+GDPM_DEV void release(PushState& ps, Particle* buf, uint32_t mask) {
+    for (uint32_t s = ps.next + lane_id(); s < ps.end; s += 64u)
+        reinterpret_cast<float*>(buf + (s & mask))[3] = -1.0f;
+    ps.next = ps.end;
+}
+
+struct ClaimState {
+    uint32_t next, end;  // claimed virtual indices not yet handed out
+    bool done;           // the pass has nothing left to claim
+};
+
+// ---------------------------------------------------------------------------
+// per-lane tallies
+// ---------------------------------------------------------------------------
+struct LaneTally {
+    int dv;          // voxel of the pending deposit (-1 none)
+    double de;       // pending deposit (MeV)
+    double e_in, e_esc;
+    double h_dep, h_esc;  // per-history accumulators (test mode)
+    uint32_t ev[7];
+};
+
+GDPM_DEV void tally_flush(LaneTally& t, const RunDev& R) {
+    if (t.dv >= 0 && t.de != 0.0) {
+        unsafeAtomicAdd(&R.tally[t.dv], t.de);
+        t.ev[EV_DEPOSITS]++;
+    }
+    t.dv = -1;
+    t.de = 0.0;
+}
+
+GDPM_DEV void deposit(LaneTally& t, const RunDev& R, int v, float e) {
+    if (v != t.dv) tally_flush(t, R);
+    t.dv = v;
+    t.de += (double)e;
+    t.h_dep += (double)e;
+}
+
+GDPM_DEV void history_flush(LaneTally& t, const RunDev& R, uint32_t hlo, uint32_t hhi) {
+    if (R.hist) {
+        const unsigned long long h = ((unsigned long long)hhi << 32 | hlo) - R.hist0;
+        if (t.h_dep != 0.0) unsafeAtomicAdd(&R.hist[2 * h], t.h_dep);
+        if (t.h_esc != 0.0) unsafeAtomicAdd(&R.hist[2 * h + 1], t.h_esc);
+    }
+    t.h_dep = 0.0;
+    t.h_esc = 0.0;
+}
+
+GDPM_DEV void tally_init(LaneTally& t) {
+    t.dv = -1;
+    t.de = 0.0;
+    t.e_in = t.e_esc = t.h_dep = t.h_esc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) t.ev[i] = 0u;
+}
+
+GDPM_DEV void tally_finish(LaneTally& t, const RunDev& R, Ctl* ctl) {
+    tally_flush(t, R);
+    const double ein = wave_sum(t.e_in), esc = wave_sum(t.e_esc);
+    uint32_t ev[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) ev[i] = wave_sum(t.ev[i]);
+    if (lane_id() == 0) {
+        if (ein != 0.0) unsafeAtomicAdd(&ctl->e_in, ein);
+        if (esc != 0.0) unsafeAtomicAdd(&ctl->e_esc, esc);
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            if (ev[i]) atomicAdd(&ctl->ev[i], (unsigned long long)ev[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pending secondaries of one event (at most two per queue)
+// ---------------------------------------------------------------------------
+struct Pending {
+    int n;
+    float e[2], u[2], v[2], w[2], a[2];
+    uint32_t word[2], flags[2];
+};
+
+GDPM_DEV void pend(Pending& q, float e, float u, float v, float w, uint32_t word, float a = 0.0f,
+                   uint32_t flags = 0u) {
+    const int k = q.n;
+    if (k == 0) {
+        q.e[0] = e; q.u[0] = u; q.v[0] = v; q.w[0] = w; q.word[0] = word; q.a[0] = a; q.flags[0] = flags;
+    } else {
+        q.e[1] = e; q.u[1] = u; q.v[1] = v; q.w[1] = w; q.word[1] = word; q.a[1] = a; q.flags[1] = flags;
+    }
+    q.n = k + 1;
+}
+
+// push the pending secondaries of all lanes into ring `ri`; they start at the
+// parent's position, with the parent's history and a spawned path
+GDPM_DEV void push_pending(Pending& q, int ri, PushState& ps, uint32_t head, Ctl* ctl,
+                           const RunDev& R, Particle* buf, float x, float y, float z,
+                           uint32_t vox, const Rng& rng, LaneTally& t) {
+    const uint64_t b0 = ballot(q.n >= 1), b1 = ballot(q.n >= 2);
+    const uint32_t n0 = (uint32_t)__popcll(b0), n = n0 + (uint32_t)__popcll(b1);
+    if (n == 0) return;
+    const Reservation res = reserve(ps, &ctl->ring[ri], head, R.hard[ri], n, ctl);
+    if (res.ok && q.n > 0) {
+        for (int k = 0; k < 2; ++k) {
+            if (k >= q.n) break;
+            const uint32_t j = k == 0 ? mbcnt(b0) : n0 + mbcnt(b1);
+            Particle p;
+            p.x = x; p.y = y; p.z = z;
+            p.e = k == 0 ? q.e[0] : q.e[1];
+            p.u = k == 0 ? q.u[0] : q.u[1];
+            p.v = k == 0 ? q.v[0] : q.v[1];
+            p.w = k == 0 ? q.w[0] : q.w[1];
+            p.nh = -1.0f;
+            p.hlo = rng.hlo;
+            p.hhi = rng.hhi;
+            p.path = spawn_path(rng, R.k0, R.k1, (int)(k == 0 ? q.word[0] : q.word[1]));
+            p.ctr = 0u;
+            p.vox = vox;
+            p.a = k == 0 ? q.a[0] : q.a[1];
+            p.flags = k == 0 ? q.flags[0] : q.flags[1];
+            p.pad = 0u;
+            store(buf, R.mask[ri], slot_of(res, j), p);
+        }
+        t.ev[EV_PUSHES] += (uint32_t)q.n;
+    }
+    q.n = 0;
+}
+
+// ---------------------------------------------------------------------------
+// pass set-up and completion (single thread, between passes)
+// ---------------------------------------------------------------------------
+__global__ void k_setup(Ctl* ctl, int ri, int with_source, uint32_t src_pass_max) {
+    RingCtl& r = ctl->ring[ri];
+    r.begin = r.head;
+    r.count = ctl->overflow ? 0u : r.tail - r.head;
+    r.claim = 0u;
+    if (with_source && !ctl->overflow) {
+        const unsigned long long left = ctl->src_end - ctl->src_next;
+        r.src_avail = (uint32_t)(left < src_pass_max ? left : src_pass_max);
+    } else {
+        r.src_avail = 0u;
+    }
+    r.src_base = ctl->src_next;
+}
+
+__global__ void k_finish(Ctl* ctl, int ri) {
+    RingCtl& r = ctl->ring[ri];
+    const uint32_t used = min(r.claim, r.count);
+    r.head = r.begin + used;
+    if (r.src_avail) {
+        const uint32_t s = r.claim > r.count ? min(r.claim - r.count, r.src_avail) : 0u;
+        ctl->src_next += s;
+    }
+    r.src_avail = 0u;
+    r.count = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// claiming input: virtual index < count is a ring record, else a new history
+// ---------------------------------------------------------------------------
+GDPM_DEV void claim_refill(ClaimState& cs, RingCtl* rc, uint32_t count, uint32_t total,
+                           bool allow_source) {
+    if (cs.done || cs.next != cs.end) return;
+    // the wave has used up its items: claim a new chunk if the pass has more
+    const uint32_t leader = first_lane(ballot(true));
+    uint32_t base = 0;
+    bool go = true;
+    if (!allow_source) {
+        // only ring items may be taken: stop once the claim counter passed them
+        if (lane_id() == leader) base = load_agent(&rc->claim);
+        base = bcast(base, leader);
+        go = base < count;
+    }
+    if (!go) {
+        cs.done = true;
+        return;
+    }
+    if (lane_id() == leader) base = atomicAdd(&rc->claim, kClaimChunk);
+    base = bcast(base, leader);
+    if (base >= total) {
+        cs.done = true;
+        return;
+    }
+    cs.next = base;
+    cs.end = min(base + kClaimChunk, total);
+}
+
+// ---------------------------------------------------------------------------
+// photon pass: Woodcock tracking (section 2.1), one flight per iteration
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, SourceDev S, RunDev R,
+                                                int with_source) {
+    RingCtl* rc = &ctl->ring[0];
+    const uint32_t begin = rc->begin, count = rc->count;
+    const uint32_t total = count + (with_source ? rc->src_avail : 0u);
+    const unsigned long long src_base = rc->src_base;
+    const uint32_t cur_g = ctl->ring[0].cur, cur_e = ctl->ring[1].cur;
+    Particle* bufg = R.buf[0][cur_g];
+    Particle* bufe = R.buf[1][cur_e];
+    const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
+    const uint32_t k0 = R.k0, k1 = R.k1;
+    const bool kerma = (R.flags & 64u) != 0u;
+
+    PushState pg{0u, 0u}, pe{0u, 0u};
+    ClaimState cs{0u, 0u, false};
+    LaneTally tl;
+    tally_init(tl);
+
+    bool active = false;
+    float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
+    Rng rng{0, 0, 0, 0, 0, 0, 0, 0};
+    bool allow_src = true;
+    int it = 0;
+
+    for (;;) {
+        if ((it++ % kCheckPeriod) == 0) {
+            // queue fill: new source histories start only while the electron
+            // queue is below its soft limit; stop everything after an overflow
+            const uint32_t tail_e = load_agent(&ctl->ring[1].tail);
+            allow_src = (tail_e - head_e) < R.soft[1];
+            if (load_agent(&ctl->overflow)) break;
+        }
+        // refill lanes
+        if (!cs.done) {
+            const uint64_t need = ballot(!active);
+            if (need) {
+                claim_refill(cs, rc, count, total, allow_src);
+                const uint32_t have = cs.end - cs.next;
+                const uint32_t rank = mbcnt(need);
+                const uint32_t take = min(have, (uint32_t)__popcll(need));
+                if (!active && rank < take) {
+                    const uint32_t vi = cs.next + rank;
+                    if (vi < count) {
+                        const Particle p = load(bufg, R.mask[0], begin + vi);
+                        if (p.e >= 0.0f) {
+                            x = p.x; y = p.y; z = p.z; e = p.e;
+                            u = p.u; v = p.v; w = p.w;
+                            rng.hlo = p.hlo; rng.hhi = p.hhi; rng.path = p.path; rng.ctr = p.ctr;
+                            if (rng.ctr & 3u) rng_block(rng, k0, k1);
+                            active = true;
+                        }
+                    } else {
+                        const unsigned long long h = src_base + (vi - count);
+                        rng.hlo = (uint32_t)h;
+                        rng.hhi = (uint32_t)(h >> 32);
+                        rng.path = 0u;
+                        rng.ctr = 0u;
+                        const Primary pr = make_primary(S, G, rng, k0, k1);
+                        tl.e_in += (double)pr.e;
+                        if (pr.in) {
+                            x = pr.x; y = pr.y; z = pr.z; u = pr.u; v = pr.v; w = pr.w; e = pr.e;
+                            active = true;
+                        } else {
+                            tl.e_esc += (double)pr.e;
+                            tl.h_esc += (double)pr.e;
+                            history_flush(tl, R, rng.hlo, rng.hhi);
+                        }
+                    }
+                }
+                cs.next += take;
+            }
+        }
+        if (!ballot(active)) {
+            if (cs.done) break;
+            continue;
+        }
+
+        Pending qe, qg;
+        qe.n = 0;
+        qg.n = 0;
+        int ix = 0, iy = 0, iz = 0;
+        if (active) {
+            if (e < R.ecut_g) {
+                const int vv = voxel_of(G, x, y, z, ix, iy, iz);
+                deposit(tl, R, vv, e);
+                tally_flush(tl, R);
+                active = false;
+            } else {
+                int gi;
+                float gt;
+                grid(hlog2(e), T.pg_lo, T.pg_inv, T.pg_n, gi, gt);
+                const float mumax = lerp1(T.mumax, gi, gt);
+                const float s = neg_ln(uniform(rng, k0, k1)) / mumax;
+                tl.ev[EV_FLIGHTS]++;
+                x = fmaf(s, u, x);
+                y = fmaf(s, v, y);
+                z = fmaf(s, w, z);
+                if (outside(G, x, y, z)) {
+                    tl.e_esc += (double)e;
+                    tl.h_esc += (double)e;
+                    active = false;
+                } else {
+                    const int vv = voxel_of(G, x, y, z, ix, iy, iz);
+                    const uint2 vx = G.vox[vv];
+                    const float rho = __uint_as_float(vx.x);
+                    const int m = (int)vx.y;
+                    const float4 mu = lerp4(T.phot + m * T.pg_n, gi, gt);
+                    if (uniform(rng, k0, k1) * mumax < rho * mu.w) {
+                        tl.ev[EV_REAL]++;
+                        const float r = uniform(rng, k0, k1) * mu.w;
+                        if (r < mu.x) {
+                            // Compton: Klein-Nishina by Butcher-Messel composition/rejection
+                            const float k = e * (1.0f / kMec2f);
+                            const float e0 = 1.0f / (1.0f + 2.0f * k);
+                            const float a1 = kLn2f * hlog2(1.0f + 2.0f * k);
+                            const float a2 = 0.5f * (1.0f - e0 * e0);
+                            float eps, t;
+                            for (;;) {
+                                const float ua = uniform(rng, k0, k1), ub = uniform(rng, k0, k1),
+                                            uc = uniform(rng, k0, k1);
+                                if (ua * (a1 + a2) < a1) eps = hexp2(-a1 * ub * (1.0f / kLn2f));
+                                else eps = hsqrt(e0 * e0 + (1.0f - e0 * e0) * ub);
+                                t = (1.0f - eps) / (k * eps);
+                                if (uc <= 1.0f - eps * t * (2.0f - t) / (1.0f + eps * eps)) break;
+                            }
+                            const float turns = uniform(rng, k0, k1);
+                            const float u0 = u, v0 = v, w0 = w;
+                            rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
+                            // exact split of E into E' and T
+                            const float ec = eps * e;
+                            float e1, te;
+                            if (2.0f * ec >= e) {
+                                e1 = ec;
+                                te = e - ec;
+                            } else {
+                                te = e - ec;
+                                e1 = e - te;
+                            }
+                            float eu = e * u0 - e1 * u, ev = e * v0 - e1 * v, ew = e * w0 - e1 * w;
+                            const float nn = eu * eu + ev * ev + ew * ew;
+                            if (nn > 0.0f) {
+                                const float in = hrsq(nn);
+                                eu *= in; ev *= in; ew *= in;
+                            } else {
+                                eu = u0; ev = v0; ew = w0;
+                            }
+                            if (kerma || te <= R.ecut_e) deposit(tl, R, vv, te);
+                            else pend(qe, te, eu, ev, ew, 0u);
+                            e = e1;
+                        } else if (r < mu.x + mu.y) {
+                            // photoelectric: the electron takes E along the photon
+                            if (kerma || e <= R.ecut_e) deposit(tl, R, vv, e);
+                            else pend(qe, e, u, v, w, 0u);
+                            active = false;
+                        } else {
+                            // pair: uniform split of E - 2 mc^2; positron keeps a = E - K
+                            const float kk = e - kTwoMec2f, aa = e - kk;
+                            const float tc = uniform(rng, k0, k1) * kk;
+                            float tm, tp;
+                            if (2.0f * tc >= kk) {
+                                tm = tc;
+                                tp = kk - tc;
+                            } else {
+                                tp = kk - tc;
+                                tm = kk - tp;
+                            }
+                            const bool pos_local = kerma || tp <= R.ecut_e;
+                            float ct = 0.0f, turns = 0.0f;
+                            if (pos_local) {
+                                ct = 2.0f * uniform(rng, k0, k1) - 1.0f;
+                                turns = uniform(rng, k0, k1);
+                            }
+                            if (kerma || tm <= R.ecut_e) deposit(tl, R, vv, tm);
+                            else pend(qe, tm, u, v, w, 0u);
+                            if (pos_local) {
+                                deposit(tl, R, vv, tp);
+                                const float st = hsqrt((1.0f - ct) * (1.0f + ct));
+                                const float du = st * cos_turns(turns), dv = st * sin_turns(turns);
+                                pend(qg, 0.5f * aa, du, dv, ct, 2u);
+                                pend(qg, 0.5f * aa, -du, -dv, -ct, 3u);
+                            } else {
+                                pend(qe, tp, u, v, w, 1u, aa, 1u);
+                            }
+                            active = false;
+                        }
+                        tally_flush(tl, R);
+                    }
+                }
+            }
+            if (!active) history_flush(tl, R, rng.hlo, rng.hhi);
+        }
+        // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
+        push_pending(qe, 1, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
+        push_pending(qg, 0, pg, head_g, ctl, R, bufg, x, y, z, 0u, rng, tl);
+    }
+    release(pe, bufe, R.mask[1]);
+    release(pg, bufg, R.mask[0]);
+    tally_finish(tl, R, ctl);
+}
+
+// ---------------------------------------------------------------------------
+// electron pass: class-II condensed history with a random hinge, one step per
+// iteration (section 2.1)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_electron(Ctl* ctl, Tables T, Geom G, SourceDev S,
+                                                  RunDev R, int with_source) {
+    RingCtl* rc = &ctl->ring[1];
+    const uint32_t begin = rc->begin, count = rc->count;
+    const uint32_t total = count + (with_source ? rc->src_avail : 0u);
+    const unsigned long long src_base = rc->src_base;
+    const uint32_t cur_g = ctl->ring[0].cur, cur_e = ctl->ring[1].cur;
+    Particle* bufg = R.buf[0][cur_g];
+    Particle* bufe = R.buf[1][cur_e];
+    const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
+    const uint32_t k0 = R.k0, k1 = R.k1;
+    const float ecut = R.ecut_e;
+    const bool no_ms = (R.flags & 8u) != 0u;
+
+    PushState pg{0u, 0u}, pe{0u, 0u};
+    ClaimState cs{0u, 0u, false};
+    LaneTally tl;
+    tally_init(tl);
+
+    bool active = false;
+    float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0, nh = -1.0f, aa = 0.0f;
+    int ix = 0, iy = 0, iz = 0;
+    bool positron = false;
+    Rng rng{0, 0, 0, 0, 0, 0, 0, 0};
+    bool allow_src = true;
+    int it = 0;
+
+    for (;;) {
+        if ((it++ % kCheckPeriod) == 0) {
+            const uint32_t tail_g = load_agent(&ctl->ring[0].tail);
+            const uint32_t tail_e = load_agent(&ctl->ring[1].tail);
+            allow_src = (tail_g - head_g) < R.soft[0] && (tail_e - head_e) < R.soft[1];
+            if (load_agent(&ctl->overflow)) break;
+        }
+        if (!cs.done) {
+            const uint64_t need = ballot(!active);
+            if (need) {
+                claim_refill(cs, rc, count, total, allow_src);
+                const uint32_t have = cs.end - cs.next;
+                const uint32_t rank = mbcnt(need);
+                const uint32_t take = min(have, (uint32_t)__popcll(need));
+                if (!active && rank < take) {
+                    const uint32_t vi = cs.next + rank;
+                    if (vi < count) {
+                        const Particle p = load(bufe, R.mask[1], begin + vi);
+                        if (p.e >= 0.0f) {
+                            x = p.x; y = p.y; z = p.z; e = p.e;
+                            u = p.u; v = p.v; w = p.w; nh = p.nh;
+                            ix = (int)(p.vox & 2047u);
+                            iy = (int)((p.vox >> 11) & 2047u);
+                            iz = (int)(p.vox >> 22);
+                            aa = p.a;
+                            positron = (p.flags & 1u) != 0u;
+                            rng.hlo = p.hlo; rng.hhi = p.hhi; rng.path = p.path; rng.ctr = p.ctr;
+                            if (rng.ctr & 3u) rng_block(rng, k0, k1);
+                            active = true;
+                        }
+                    } else {
+                        const unsigned long long h = src_base + (vi - count);
+                        rng.hlo = (uint32_t)h;
+                        rng.hhi = (uint32_t)(h >> 32);
+                        rng.path = 0u;
+                        rng.ctr = 0u;
+                        const Primary pr = make_primary(S, G, rng, k0, k1);
+                        tl.e_in += (double)pr.e;
+                        if (pr.in) {
+                            x = pr.x; y = pr.y; z = pr.z; u = pr.u; v = pr.v; w = pr.w; e = pr.e;
+                            voxel_of(G, x, y, z, ix, iy, iz);
+                            nh = -1.0f;
+                            aa = 0.0f;
+                            positron = false;
+                            active = true;
+                        } else {
+                            tl.e_esc += (double)pr.e;
+                            tl.h_esc += (double)pr.e;
+                            history_flush(tl, R, rng.hlo, rng.hhi);
+                        }
+                    }
+                }
+                cs.next += take;
+            }
+        }
+        if (!ballot(active)) {
+            if (cs.done) break;
+            continue;
+        }
+
+        Pending qe, qg;
+        qe.n = 0;
+        qg.n = 0;
+        if (active) {
+            const int vv = ix + G.nx * (iy + G.ny * iz);
+            if (e <= ecut) {
+                // absorption; a positron annihilates at rest into two photons
+                deposit(tl, R, vv, e);
+                if (positron) {
+                    const float ct = 2.0f * uniform(rng, k0, k1) - 1.0f;
+                    const float turns = uniform(rng, k0, k1);
+                    const float st = hsqrt((1.0f - ct) * (1.0f + ct));
+                    const float du = st * cos_turns(turns), dv = st * sin_turns(turns);
+                    pend(qg, 0.5f * aa, du, dv, ct, 0u);
+                    pend(qg, 0.5f * aa, -du, -dv, -ct, 1u);
+                }
+                active = false;
+            } else {
+                const uint2 vx = G.vox[vv];
+                const float rho = __uint_as_float(vx.x);
+                const int m = (int)vx.y;
+                if (nh < 0.0f) nh = neg_ln(uniform(rng, k0, k1));
+                tl.ev[EV_ESTEPS]++;
+                const float t0 = e;
+                const float4 q0 = elec_at(T, m, t0);
+                const float mus = rho * q0.y;
+                const float sh = mus > 0.0f ? nh / mus : 3.0e38f;
+                const float tfl = fmaxf(0.75f * t0, ecut);
+                const float rfl = tfl > ecut ? elec_at(T, m, tfl).x : 0.0f;
+                const float se = (q0.x - rfl) / rho;
+                const bool hard = sh < se;
+                const float s = hard ? sh : se;
+                const float xi = uniform(rng, k0, k1);
+                const float s1 = xi * s, s2 = s - s1;
+                const float tend = hard ? fminf(fmaxf(range_inv(T, m, q0.x - rho * s), tfl), t0) : tfl;
+                bool crossed = false;
+                int ax;
+                float db = face_dist(G, x, y, z, u, v, w, ix, iy, iz, ax);
+                float travelled = 0.0f;
+                if (db < s1) {
+                    x = fmaf(db, u, x); y = fmaf(db, v, y); z = fmaf(db, w, z);
+                    const float t1 = fminf(fmaxf(range_inv(T, m, q0.x - rho * db), tend), e);
+                    deposit(tl, R, vv, e - t1);
+                    e = t1;
+                    travelled = db;
+                    crossed = true;
+                } else {
+                    x = fmaf(s1, u, x); y = fmaf(s1, v, y); z = fmaf(s1, w, z);
+                    const float t1 = fminf(fmaxf(range_inv(T, m, q0.x - rho * s1), tend), e);
+                    deposit(tl, R, vv, e - t1);
+                    e = t1;
+                    // hinge: modified-Wentzel deflection for the whole step
+                    if (!no_ms) {
+                        const float tmid = 0.5f * (t0 + tend);
+                        const float tt = s * rho * elec_at(T, m, tmid).w;
+                        const float mu = mw_mu(T, tt, uniform(rng, k0, k1));
+                        const float turns = uniform(rng, k0, k1);
+                        rotate(u, v, w, 1.0f - 2.0f * mu, 2.0f * hsqrt(mu * (1.0f - mu)), turns);
+                    }
+                    db = face_dist(G, x, y, z, u, v, w, ix, iy, iz, ax);
+                    if (db < s2) {
+                        x = fmaf(db, u, x); y = fmaf(db, v, y); z = fmaf(db, w, z);
+                        const float t2 = fminf(fmaxf(range_inv(T, m, q0.x - rho * (s1 + db)), tend), e);
+                        deposit(tl, R, vv, e - t2);
+                        e = t2;
+                        travelled = s1 + db;
+                        crossed = true;
+                    } else {
+                        x = fmaf(s2, u, x); y = fmaf(s2, v, y); z = fmaf(s2, w, z);
+                        deposit(tl, R, vv, e - tend);
+                        e = tend;
+                    }
+                }
+                if (crossed) {
+                    nh -= mus * travelled;
+                    // move onto the face and into the next voxel
+                    if (ax == 0) {
+                        const int st = u > 0.0f ? 1 : -1;
+                        x = (float)(st > 0 ? ix + 1 : ix) * G.dx;
+                        ix += st;
+                    } else if (ax == 1) {
+                        const int st = v > 0.0f ? 1 : -1;
+                        y = (float)(st > 0 ? iy + 1 : iy) * G.dy;
+                        iy += st;
+                    } else {
+                        const int st = w > 0.0f ? 1 : -1;
+                        z = (float)(st > 0 ? iz + 1 : iz) * G.dz;
+                        iz += st;
+                    }
+                    if (ix < 0 || ix >= G.nx || iy < 0 || iy >= G.ny || iz < 0 || iz >= G.nz) {
+                        const float out = e + (positron ? aa : 0.0f);
+                        tl.e_esc += (double)out;
+                        tl.h_esc += (double)out;
+                        active = false;
+                    }
+                } else if (hard) {
+                    // delta scattering against the step-start majorant (mu_h grows with T)
+                    tl.ev[EV_HARD_CAND]++;
+                    const float4 q1 = elec_at(T, m, tend);
+                    if (uniform(rng, k0, k1) * q0.y < q1.y) {
+                        tl.ev[EV_HARD]++;
+                        if (uniform(rng, k0, k1) * q1.y < q1.z) {
+                            // Moller: proposal 1/eps^2 on [eps0, 1/2], rejection eps^2 B / 2.25
+                            const float tt = e, g = 1.0f + tt * (1.0f / kMec2f), e0 = ecut / tt;
+                            const float c1 = (g - 1.0f) / g, c2 = (2.0f * g - 1.0f) / (g * g);
+                            float eps;
+                            for (;;) {
+                                const float ua = uniform(rng, k0, k1);
+                                eps = e0 / (1.0f - ua * (1.0f - 2.0f * e0));
+                                const float ub = uniform(rng, k0, k1);
+                                const float ie = 1.0f / eps, io = 1.0f / (1.0f - eps);
+                                const float br = c1 * c1 + ie * (ie - c2) + io * (io - c2);
+                                if (ub * 2.25f <= eps * eps * br) break;
+                            }
+                            const float turns = uniform(rng, k0, k1);
+                            const float tp = tt - eps * tt;   // >= T/2
+                            const float wd = tt - tp;         // exact
+                            const float tm2 = tt + kTwoMec2f;
+                            const float cd = hsqrt(wd * tm2 / (tt * (wd + kTwoMec2f)));
+                            const float cpr = hsqrt(tp * tm2 / (tt * (tp + kTwoMec2f)));
+                            float du = u, dv = v, dw = w;
+                            rotate(du, dv, dw, cd, hsqrt(fmaxf(0.0f, 1.0f - cd * cd)), turns);
+                            rotate(u, v, w, cpr, hsqrt(fmaxf(0.0f, 1.0f - cpr * cpr)), turns + 0.5f);
+                            if (wd <= ecut) deposit(tl, R, vv, wd);
+                            else pend(qe, wd, du, dv, dw, 0u);
+                            e = tp;
+                        } else {
+                            // bremsstrahlung: proposal 1/k on [W_cb, T], rejection by the spectrum
+                            const float tt = e, wcb = R.ecut_g, lr = hlog2(tt / wcb);
+                            float kph;
+                            for (;;) {
+                                const float ua = uniform(rng, k0, k1);
+                                kph = wcb * hexp2(ua * lr);
+                                const float ub = uniform(rng, k0, k1);
+                                const float yy = kph / tt;
+                                if (ub * (4.0f / 3.0f) <= 4.0f / 3.0f - 4.0f / 3.0f * yy + yy * yy) break;
+                            }
+                            float kp, el;
+                            if (2.0f * kph >= tt) {
+                                kp = kph;
+                                el = tt - kph;
+                            } else {
+                                el = tt - kph;
+                                kp = tt - el;
+                            }
+                            pend(qg, kp, u, v, w, 0u);
+                            e = el;
+                        }
+                    }
+                    nh = -1.0f;
+                } else {
+                    nh -= mus * s;
+                }
+            }
+            if (!active) {
+                tally_flush(tl, R);
+                history_flush(tl, R, rng.hlo, rng.hhi);
+            }
+        }
+        push_pending(qe, 1, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
+        push_pending(qg, 0, pg, head_g, ctl, R, bufg, x, y, z, 0u, rng, tl);
+    }
+    // the pass was stopped by an overflow: particles still held are dropped
+    // (the run reports GDPM_E_OVERFLOW and its outputs are not valid)
+    release(pe, bufe, R.mask[1]);
+    release(pg, bufg, R.mask[0]);
+    if (active) tally_flush(tl, R);
+    tally_finish(tl, R, ctl);
+}
+
+// ---------------------------------------------------------------------------
+// queue compaction and energy re-binning: counting sort of [head, tail) by
+// log2-energy bin into the other buffer; empty slots are dropped
+// ---------------------------------------------------------------------------
+GDPM_DEV int energy_bin(float e, float lo, float inv, int nb) {
+    const int b = (int)((hlog2(e) - lo) * inv);
+    return min(max(b, 0), nb - 1);
+}
+
+__global__ void __launch_bounds__(256) k_bin_count(Ctl* ctl, RunDev R, int ri, int nb, float lo,
+                                                   float inv) {
+    if (ctl->overflow) return;
+    __shared__ uint32_t hist[kMaxBins];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const RingCtl& r = ctl->ring[ri];
+    const uint32_t n = r.tail - r.head;
+    const Particle* buf = R.buf[ri][r.cur];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float e = reinterpret_cast<const float*>(buf + ((r.head + i) & R.mask[ri]))[3];
+        if (e >= 0.0f) atomicAdd(&hist[energy_bin(e, lo, inv, nb)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        if (hist[i]) atomicAdd(&ctl->bin_count[i], hist[i]);
+}
+
+__global__ void k_bin_scan(Ctl* ctl, int nb) {
+    if (ctl->overflow) return;
+    uint32_t acc = 0u;
+    for (int i = 0; i < nb; ++i) {
+        ctl->bin_cursor[i] = acc;
+        acc += ctl->bin_count[i];
+        ctl->bin_count[i] = 0u;
+    }
+    ctl->n_valid = acc;
+}
+
+__global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri, int nb, float lo,
+                                                     float inv) {
+    if (ctl->overflow) return;
+    __shared__ uint32_t cnt[kMaxBins], base[kMaxBins];
+    const RingCtl& r = ctl->ring[ri];
+    const uint32_t n = r.tail - r.head;
+    const Particle* src = R.buf[ri][r.cur];
+    Particle* dst = R.buf[ri][r.cur ^ 1u];
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) cnt[i] = 0u;
+        __syncthreads();
+        const uint32_t i = i0 + threadIdx.x;
+        Particle p;
+        int b = -1;
+        uint32_t rank = 0u;
+        if (i < n) {
+            p = load(src, R.mask[ri], r.head + i);
+            if (p.e >= 0.0f) {
+                b = energy_bin(p.e, lo, inv, nb);
+                rank = atomicAdd(&cnt[b], 1u);
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nb; k += blockDim.x)
+            base[k] = cnt[k] ? atomicAdd(&ctl->bin_cursor[k], cnt[k]) : 0u;
+        __syncthreads();
+        if (b >= 0) store(dst, R.mask[ri], base[b] + rank, p);
+        __syncthreads();
+    }
+}
+
+__global__ void k_bin_swap(Ctl* ctl, int ri) {
+    if (ctl->overflow) return;
+    RingCtl& r = ctl->ring[ri];
+    r.cur ^= 1u;
+    r.head = 0u;
+    r.tail = ctl->n_valid;
+}
+
+// ---------------------------------------------------------------------------
+// batch statistics (section 2.2.1, section 3.1): per voxel the mean over the
+// batches of D_b = E_b / (rho V n_b) and its standard error
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_dose_stats(Ctl* ctl, const double* slots, size_t nvox,
+                                                    int nb, const double* inv_mass_n,
+                                                    const uint2* vox, double vvox, double* dose,
+                                                    double* sigma) {
+    double emax = 0.0, edep = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double rho = (double)__uint_as_float(vox[i].x);
+        const double im = 1.0 / (rho * vvox);
+        double s = 0.0, s2 = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const double eb = slots[(size_t)b * nvox + i];
+            edep += eb;
+            const double d = eb * im * inv_mass_n[b];
+            s += d;
+        }
+        const double mean = s / nb;
+        for (int b = 0; b < nb; ++b) {
+            const double d = slots[(size_t)b * nvox + i] * im * inv_mass_n[b] - mean;
+            s2 += d * d;
+        }
+        if (dose) dose[i] = mean;
+        if (sigma) sigma[i] = nb > 1 ? sqrt(s2 / ((double)nb * (nb - 1))) : 0.0;
+        emax = fmax(emax, mean);
+    }
+    // block reductions
+    __shared__ double sh[256];
+    sh[threadIdx.x] = emax;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(&ctl->dmax_bits, (unsigned long long)__double_as_longlong(sh[0]));
+    __syncthreads();
+    sh[threadIdx.x] = edep;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) unsafeAtomicAdd(&ctl->red[0], sh[0]);
+}
+
+// mean of sigma / D_max over voxels with D > D_max / 2
+__global__ void __launch_bounds__(256) k_unc(Ctl* ctl, const double* dose, const double* sigma,
+                                             size_t nvox) {
+    const double dmax = __longlong_as_double((long long)ctl->dmax_bits);
+    double s = 0.0, c = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (dose[i] > 0.5 * dmax) {
+            s += sigma[i];
+            c += 1.0;
+        }
+    }
+    __shared__ double sh[2][256];
+    sh[0][threadIdx.x] = s;
+    sh[1][threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        unsafeAtomicAdd(&ctl->red[1], sh[0][0]);
+        unsafeAtomicAdd(&ctl->red[2], sh[1][0]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// test kernels
+// ---------------------------------------------------------------------------
+__global__ void k_test_philox(uint32_t k0, uint32_t k1, const uint4* ctr, uint4* out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint4 c = ctr[i];
+    philox(k0, k1, c.x, c.y, c.z, c.w);
+    out[i] = c;
+}
+
+__global__ void k_test_sample(Tables T, int which, float e, float p1, float p2, uint32_t k0,
+                              uint32_t k1, int n, float* out1, float* out2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Rng r{(uint32_t)i, 0u, 0u, 0u, 0, 0, 0, 0};
+    float a = 0.0f, b = 0.0f;
+    if (which == 0) {
+        const float k = e / kMec2f, e0 = 1.0f / (1.0f + 2.0f * k);
+        const float a1 = kLn2f * hlog2(1.0f + 2.0f * k), a2 = 0.5f * (1.0f - e0 * e0);
+        float eps, t;
+        for (;;) {
+            const float ua = uniform(r, k0, k1), ub = uniform(r, k0, k1), uc = uniform(r, k0, k1);
+            if (ua * (a1 + a2) < a1) eps = hexp2(-a1 * ub * (1.0f / kLn2f));
+            else eps = hsqrt(e0 * e0 + (1.0f - e0 * e0) * ub);
+            t = (1.0f - eps) / (k * eps);
+            if (uc <= 1.0f - eps * t * (2.0f - t) / (1.0f + eps * eps)) break;
+        }
+        a = eps;
+        b = 1.0f - t;
+    } else if (which == 1) {
+        const float tt = e, g = 1.0f + tt / kMec2f, e0 = p1 / tt;
+        const float c1 = (g - 1.0f) / g, c2 = (2.0f * g - 1.0f) / (g * g);
+        float eps;
+        for (;;) {
+            const float ua = uniform(r, k0, k1);
+            eps = e0 / (1.0f - ua * (1.0f - 2.0f * e0));
+            const float ub = uniform(r, k0, k1);
+            const float ie = 1.0f / eps, io = 1.0f / (1.0f - eps);
+            if (ub * 2.25f <= eps * eps * (c1 * c1 + ie * (ie - c2) + io * (io - c2))) break;
+        }
+        const float tp = tt - eps * tt, wd = tt - tp;
+        a = wd / tt;
+        b = hsqrt(tp * (tt + kTwoMec2f) / (tt * (tp + kTwoMec2f)));
+    } else if (which == 2) {
+        const float tt = e, wcb = p1, lr = hlog2(tt / wcb);
+        float kph;
+        for (;;) {
+            const float ua = uniform(r, k0, k1);
+            kph = wcb * hexp2(ua * lr);
+            const float ub = uniform(r, k0, k1), yy = kph / tt;
+            if (ub * (4.0f / 3.0f) <= 4.0f / 3.0f - 4.0f / 3.0f * yy + yy * yy) break;
+        }
+        a = kph;
+    } else if (which == 3) {
+        a = mw_mu(T, e, uniform(r, k0, k1));
+    } else if (which == 4) {
+        float u = 0.0f, v = 0.0f, w = 1.0f;
+        const int nh = (int)p2;
+        for (int k = 0; k < nh; ++k) {
+            const float mu = mw_mu(T, e, uniform(r, k0, k1));
+            const float turns = uniform(r, k0, k1);
+            rotate(u, v, w, 1.0f - 2.0f * mu, 2.0f * hsqrt(mu * (1.0f - mu)), turns);
+        }
+        a = w;
+        b = u * u + v * v + w * w;
+    } else if (which == 5) {
+        const float ct = 2.0f * uniform(r, k0, k1) - 1.0f, turns = uniform(r, k0, k1);
+        const float st = hsqrt((1.0f - ct) * (1.0f + ct));
+        const float du = st * cos_turns(turns), dv = st * sin_turns(turns);
+        a = ct;
+        b = -(du * du + dv * dv + ct * ct);
+    }
+    out1[i] = a;
+    if (out2) out2[i] = b;
+}
+
+__global__ void k_test_source(SourceDev S, Geom G, uint32_t k0, uint32_t k1,
+                              unsigned long long hist0, int n, float* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long h = hist0 + i;
+    Rng r{(uint32_t)h, (uint32_t)(h >> 32), 0u, 0u, 0, 0, 0, 0};
+    const Primary p = make_primary(S, G, r, k0, k1);
+    float* o = out + 8 * (size_t)i;
+    o[0] = p.e;
+    o[1] = p.in ? (float)p.beamlet : -1.0f;
+    o[2] = p.x; o[3] = p.y; o[4] = p.z;
+    o[5] = p.u; o[6] = p.v; o[7] = p.w;
+}
+
+__global__ void k_test_lookup(Tables T, int which, int m, const float* in, float* out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = in[i];
+    float r = 0.0f;
+    if (which == 0) {
+        int gi;
+        float gt;
+        grid(hlog2(x), T.pg_lo, T.pg_inv, T.pg_n, gi, gt);
+        r = lerp4(T.phot + m * T.pg_n, gi, gt).w;
+    } else if (which >= 1 && which <= 4) {
+        const float4 q = elec_at(T, m, x);
+        r = which == 1 ? q.x : (which == 2 ? q.y : (which == 3 ? q.z : q.w));
+    } else if (which == 5) {
+        r = range_inv(T, m, x);
+    } else if (which == 6) {
+        // A from the table: at u = 1/2, mu = A / (2A + 1), so A = mu / (1 - 2 mu)
+        const float mu = mw_mu(T, x, 0.5f);
+        r = mu / (1.0f - 2.0f * mu);
+    }
+    out[i] = r;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers (the host runtime calls these; kernels stay in this unit)
+// ---------------------------------------------------------------------------
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, int ri, int with_source, uint32_t src_pass_max) {
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(1), 0, st, ctl, ri, with_source, src_pass_max);
+    return hipGetLastError();
+}
+hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, st, ctl, ri);
+    return hipGetLastError();
+}
+hipError_t launch_transport(hipStream_t st, int ri, int blocks, Ctl* ctl, const Tables& T,
+                            const Geom& G, const SourceDev& S, const RunDev& R, int with_source) {
+    if (ri == 0)
+        hipLaunchKernelGGL(k_photon, dim3(blocks), dim3(256), 0, st, ctl, T, G, S, R, with_source);
+    else
+        hipLaunchKernelGGL(k_electron, dim3(blocks), dim3(256), 0, st, ctl, T, G, S, R, with_source);
+    return hipGetLastError();
+}
+hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
+                        float lo, float inv) {
+    hipLaunchKernelGGL(k_bin_count, dim3(blocks), dim3(256), 0, st, ctl, R, ri, nb, lo, inv);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1), 0, st, ctl, nb);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks), dim3(256), 0, st, ctl, R, ri, nb, lo, inv);
+    hipLaunchKernelGGL(k_bin_swap, dim3(1), dim3(1), 0, st, ctl, ri);
+    return hipGetLastError();
+}
+hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
+                        int nb, const double* inv_n, const uint2* vox, double vvox, double* dose,
+                        double* sigma) {
+    hipLaunchKernelGGL(k_dose_stats, dim3(blocks), dim3(256), 0, st, ctl, slots, nvox, nb, inv_n,
+                       vox, vvox, dose, sigma);
+    hipLaunchKernelGGL(k_unc, dim3(blocks), dim3(256), 0, st, ctl, (const double*)dose,
+                       (const double*)sigma, nvox);
+    return hipGetLastError();
+}
+hipError_t launch_test_philox(hipStream_t st, uint32_t k0, uint32_t k1, const uint4* ctr, uint4* out,
+                              int n) {
+    hipLaunchKernelGGL(k_test_philox, dim3((n + 255) / 256), dim3(256), 0, st, k0, k1, ctr, out, n);
+    return hipGetLastError();
+}
+hipError_t launch_test_sample(hipStream_t st, const Tables& T, int which, float e, float p1, float p2,
+                              uint32_t k0, uint32_t k1, int n, float* out1, float* out2) {
+    hipLaunchKernelGGL(k_test_sample, dim3((n + 255) / 256), dim3(256), 0, st, T, which, e, p1, p2,
+                       k0, k1, n, out1, out2);
+    return hipGetLastError();
+}
+hipError_t launch_test_source(hipStream_t st, const SourceDev& S, const Geom& G, uint32_t k0,
+                              uint32_t k1, unsigned long long hist0, int n, float* out) {
+    hipLaunchKernelGGL(k_test_source, dim3((n + 255) / 256), dim3(256), 0, st, S, G, k0, k1, hist0, n,
+                       out);
+    return hipGetLastError();
+}
+hipError_t launch_test_lookup(hipStream_t st, const Tables& T, int which, int m, const float* in,
+                              float* out, int n) {
+    hipLaunchKernelGGL(k_test_lookup, dim3((n + 255) / 256), dim3(256), 0, st, T, which, m, in, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace gdpm
