@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark of the dose engine on one MI355X.
+
+Workload: the synthetic CT patient (256x256x128 voxels of 0.2x0.2x0.25 cm,
+4 materials + density from seeded ellipsoids), a 9-beam coplanar IMRT plan with
+40x40 beamlet fluence maps and the 6 MV-like triangular spectrum, run until the
+mean sigma/D_max over D > D_max/2 is at most 1% (the paper's Table 3 reports
+this quantity for its IMRT/VMAT plans).  One step is one such dose job with a
+different seed; `value` is histories per second over the timed jobs, with the
+phantom, source and tables already resident in device memory.
+
+Also reported: the job latency (p50/p99 over the timed jobs), the roofline
+position of the dominant transport kernel (HIP-event times of every launch on
+the library's stream, algorithmic work from the kernel's own event counters),
+and the oracle (plain CPU transport) timed on a bounded sample of the same job.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "histories/s at 1% unc. (6MV, 256x256x128 CT phantom); p50/p99 dose-job latency"
+
+# Algorithmic single-precision work per transport event, counted from the
+# arithmetic each event needs (additions, multiplications, fused
+# multiply-adds counted as two, divisions, square roots and transcendental
+# functions counted as one each); the breakdown is in the design notes.
+FLOP_PER_ELECTRON_STEP = 180.0
+FLOP_PER_PHOTON_FLIGHT = 48.0
+FLOP_PER_PHOTON_INTERACTION = 110.0
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(workload, seconds):
+    """The oracle as it stands, on a bounded sample of the same job: a probe run
+    sizes the sample so that the timed run takes about `seconds`."""
+    import oracle
+    from paper_1107_3355_amd import inputs as I
+    threads = min(os.cpu_count() or 1, 16)
+
+    def timed(n, hist0):
+        t0 = time.perf_counter()
+        oracle.run(I.MATERIALS, workload.phantom, workload.source, seed=7, hist0=hist0, n_hist=n,
+                   n_batches=2, n_threads=threads, want_batches=False)
+        return time.perf_counter() - t0
+
+    n1, n2 = 2000, 20000
+    d1 = timed(n1, 0)
+    d2 = timed(n2, n1)
+    rate = (n2 - n1) / max(d2 - d1, 1e-3)          # setup time cancels
+    n = int(max(n2, min(20_000_000, rate * seconds)))
+    h0 = n1 + n2
+    dt = timed(n, h0)
+    return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} histories (ids {h0}..{h0 + n - 1}) of the same CT IMRT job, FP64 CPU "
+                      f"transport on {threads} threads, {dt:.1f} s including the run set-up"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--target", type=float, default=0.01)
+    ap.add_argument("--n0", type=int, default=100_000_000, help="first history estimate per job")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--opts", default=None, help="context options (JSON)")
+    ap.add_argument("--min-density", type=float, default=0.1,
+                    help="voxels below this density (the air around the patient) are left out "
+                         "of D_max and of the uncertainty statistic")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (histories would be "
+              "sharded across GPUs with one FP64 all-reduce of the tallies; see the design "
+              "notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1107_3355_amd import gdpm as G
+    from paper_1107_3355_amd import inputs as I
+
+    log("building the synthetic CT workload")
+    w = I.ct_imrt(target_unc=args.target)
+    ctx = G.Context(0, opts=args.opts, materials=I.MATERIALS)
+    ph = ctx.phantom(w.phantom)
+    src = ctx.source(w.source)
+
+    def job(seed):
+        # gdpm_run is blocking: it returns after the device work of the job is complete
+        return ctx.run(ph, src, seed=seed, n_hist=args.n0, target_unc=args.target,
+                       stat_min_density=args.min_density, want_dose=False)
+
+    n0 = args.n0
+    for i in range(args.warmup):
+        r = job(1000 + i)
+        log(f"warmup {i}: {r['histories']} histories, unc {r['unc']:.5f}, {r['t_total_s']:.2f} s")
+        n0 = r["histories"]
+    args.n0 = n0   # start timed jobs from the history count the warmup needed
+    runs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = job(1 + i)
+        runs.append(r)
+        log(f"step {i}: {r['histories']} histories, unc {r['unc']:.5f}, {r['t_total_s']:.3f} s, "
+            f"{r['histories'] / r['t_total_s']:.4g} hist/s")
+    wall = time.perf_counter() - t0
+    hist = sum(r["histories"] for r in runs)
+    lat = np.array([r["t_total_s"] for r in runs])
+
+    # roofline of the dominant transport kernel
+    te = sum(r["t_electron_s"] for r in runs)
+    tp = sum(r["t_photon_s"] for r in runs)
+    ne = sum(r["passes_electron"] for r in runs)
+    npp = sum(r["passes_photon"] for r in runs)
+    ev = {k: sum(r["events"][k] for r in runs) for k in runs[0]["events"]}
+    if te >= tp:
+        name, launches, t_k = "k_electron", ne, te
+        work = FLOP_PER_ELECTRON_STEP * ev["esteps"]
+    else:
+        name, launches, t_k = "k_photon", npp, tp
+        work = FLOP_PER_PHOTON_FLIGHT * ev["flights"] + FLOP_PER_PHOTON_INTERACTION * ev["real"]
+    avg = t_k / max(launches, 1)
+    achieved = work / max(launches, 1) / avg / 1e12
+    roof = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "avg_launch_ms": avg * 1e3, "launches": launches,
+            "share_of_kernel_time": t_k / max(te + tp, 1e-30)}
+
+    out = {
+        "metric": METRIC,
+        "value": hist / wall,
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name + "_to_1pct", "phantom_voxels": [256, 256, 128],
+                   "voxel_cm": [0.2, 0.2, 0.25], "beams": 9, "beamlets": 9 * 1600,
+                   "spectrum": "triangular 0.25-1.2-6 MeV", "target_unc": args.target,
+                   "n_batches": 10, "histories_per_job": int(np.mean([r["histories"] for r in runs])),
+                   "stat_min_density": args.min_density,
+                   "tally": "f64"},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "unc_reached": [r["unc"] for r in runs],
+        "events_per_history": {k: v / hist for k, v in ev.items() if k != "histories"},
+        "kernel_time_s": {"photon": tp, "electron": te},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    ph.close()
+    src.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

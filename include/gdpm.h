@@ -123,6 +123,8 @@ typedef struct {
     uint64_t round_size;       /* histories per round; 0: n_histories / n_batches.  In fixed
                                   mode history h goes to batch floor(h/round_size) mod N_b */
     uint64_t hist0;            /* id of the first history (fixed mode) */
+    double stat_min_density;   /* voxels below this density (g/cm^3) are left out of D_max and
+                                  of the uncertainty statistic (0: all voxels) */
 } gdpm_run_params;
 
 enum { GDPM_EV_FLIGHTS = 0, GDPM_EV_REAL, GDPM_EV_ESTEPS, GDPM_EV_HARD_CAND, GDPM_EV_HARD,
@@ -131,14 +133,17 @@ enum { GDPM_EV_FLIGHTS = 0, GDPM_EV_REAL, GDPM_EV_ESTEPS, GDPM_EV_HARD_CAND, GDP
 typedef struct {
     uint64_t histories;
     double e_in, e_dep, e_esc;   /* MeV: source kinetic energy, deposited, escaped */
-    double unc_mean_over_dmax;   /* mean sigma/D_max over D > D_max/2 */
-    double dmax;                 /* MeV/g per history */
+    double unc_mean_over_dmax;   /* mean sigma/D_max over D > D_max/2 (voxels at or above
+                                    stat_min_density) */
+    double dmax;                 /* MeV/g per history, same voxels */
     double t_total_s;            /* wall time of the call */
     double t_kernel_s;           /* device time of the transport kernels (HIP events) */
     double t_photon_s, t_electron_s;  /* device time per pass type */
     uint64_t events[8];          /* GDPM_EV_* counters */
     uint32_t passes;             /* transport kernel launches */
     uint32_t rounds;
+    uint32_t passes_photon;      /* photon kernel launches (t_photon_s covers them) */
+    uint32_t passes_electron;    /* electron kernel launches (t_electron_s covers them) */
 } gdpm_run_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -15,6 +15,9 @@ HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # hardware FP64 atomic add for the dose tallies
     "-munsafe-fp-atomics",
+    # no floating-point contraction: the exact energy splits need every product
+    # rounded on its own (fused multiply-adds are written out with fmaf)
+    "-ffp-contract=off",
     # no packed FP32 instructions (see the design notes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

@@ -33,8 +33,8 @@ hipError_t launch_transport(hipStream_t st, int ri, int blocks, Ctl* ctl, const 
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
                         float lo, float inv);
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
-                        int nb, const double* inv_n, const uint2* vox, double vvox, double* dose,
-                        double* sigma);
+                        int nb, const double* inv_n, const uint2* vox, double vvox, float min_rho,
+                        double* dose, double* sigma);
 hipError_t launch_test_philox(hipStream_t st, uint32_t k0, uint32_t k1, const uint4* ctr, uint4* out,
                               int n);
 hipError_t launch_test_sample(hipStream_t st, const Tables& T, int which, float e, float p1, float p2,
@@ -296,6 +296,8 @@ gdpm_status validate_params(const gdpm_run_params* p, const gdpm_source_s* src, 
     plan->n_hist = p->n_histories;
     plan->flags = p->flags;
     if (p->flags & ~0x7Fu) return fail(GDPM_E_INVALID, "unknown flag bits");
+    if (!(p->stat_min_density >= 0.0) || !std::isfinite(p->stat_min_density))
+        return fail(GDPM_E_INVALID, "stat_min_density must be finite and >= 0");
     if (src->particle == 1 && (p->flags & GDPM_KERMA))
         return fail(GDPM_E_INVALID, "kerma mode needs a photon source");
     return GDPM_OK;
@@ -303,7 +305,7 @@ gdpm_status validate_params(const gdpm_run_params* p, const gdpm_source_s* src, 
 
 struct Timers {
     double photon = 0, electron = 0;
-    uint32_t passes = 0;
+    uint32_t passes = 0, passes_photon = 0, passes_electron = 0;
 };
 
 // run transport for histories [h0, h1) into tally slot `slot`
@@ -342,6 +344,7 @@ gdpm_status run_round(gdpm_context ctx, const Tables& T, const Geom& G, const So
             HIP_TRY(hipEventRecord(ctx->events[2 * k + 1], st));
             HIP_TRY(launch_finish(st, dc, ri));
             tm->passes++;
+            (ri == 0 ? tm->passes_photon : tm->passes_electron)++;
         }
         HIP_TRY(hipMemcpyAsync(hc, dc, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -364,7 +367,8 @@ gdpm_status run_round(gdpm_context ctx, const Tables& T, const Geom& G, const So
 }
 
 gdpm_status compute_stats(gdpm_context ctx, gdpm_phantom_s* ph, int nb,
-                          const std::vector<double>& nhist, hipStream_t st, double* d_dose,
+                          const std::vector<double>& nhist, float min_rho, hipStream_t st,
+                          double* d_dose,
                           double* d_sigma, double* unc, double* dmax, double* edep) {
     const size_t nv = (size_t)ph->nx * ph->ny * ph->nz;
     std::vector<double> inv(nb);
@@ -380,7 +384,7 @@ gdpm_status compute_stats(gdpm_context ctx, gdpm_phantom_s* ph, int nb,
     const int blocks = (int)std::min<size_t>((nv + 255) / 256, 8192);
     HIP_TRY(launch_stats(st, blocks, dc, ctx->tally.as<const double>(), nv, nb,
                          ctx->inv_n.as<const double>(), ph->vox.as<const uint2>(),
-                         ph->dx * ph->dy * ph->dz, d_dose, d_sigma));
+                         ph->dx * ph->dy * ph->dz, min_rho, d_dose, d_sigma));
     HIP_TRY(hipMemcpyAsync(&hc->red[0], &dc->red[0], 4 * sizeof(double) + sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -484,7 +488,8 @@ gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdp
             done += h1 - h0;
             rounds++;
         }
-        s = compute_stats(ctx, ph, nb, nhist, st, dd, ds, &unc, &dmax, &edep);
+        s = compute_stats(ctx, ph, nb, nhist, (float)prm->stat_min_density, st, dd, ds, &unc,
+                          &dmax, &edep);
         if (s) return s;
         if (!plan.target) break;
         if (unc <= prm->target_unc) break;
@@ -520,6 +525,8 @@ gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdp
         for (int i = 0; i < 8; ++i) out->events[i] = hc->ev[i];
         out->events[GDPM_EV_HISTORIES] = done;
         out->passes = tm.passes;
+        out->passes_photon = tm.passes_photon;
+        out->passes_electron = tm.passes_electron;
         out->rounds = rounds;
         out->t_photon_s = tm.photon;
         out->t_electron_s = tm.electron;

@@ -260,7 +260,7 @@ bool build_tables(const std::vector<MaterialParams>& mats, int n_grid, double ec
     }
 
     // modified-Wentzel screening table: log2 A on log2 t in [1e-9, t_iso]
-    T.aw_n = 512;
+    T.aw_n = 4096;
     T.aw_lo = std::log2(1e-9);
     T.aw_step = (std::log2(kMwIsotropic) - T.aw_lo) / (T.aw_n - 1);
     T.aw.assign(T.aw_n, 0.0f);

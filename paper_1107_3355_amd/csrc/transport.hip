@@ -20,6 +20,10 @@
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11); a particle owns the
 // stream (history id, path id) and the draw order of each event is fixed, so
 // results do not depend on scheduling.
+// Energy is conserved exactly in single precision: when an energy X splits in
+// two, the larger part L >= X/2 is computed and the smaller is X - L, which is
+// exact (Sterbenz).  This unit is therefore compiled without floating-point
+// contraction; fused multiply-adds are written out with fmaf.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -157,12 +161,17 @@ GDPM_DEV float range_inv(const Tables& T, int m, float r) {
     return lerp1(T.rinv + m * T.nr, i, f - (float)i);
 }
 
+// screening A of the modified-Wentzel law for t = s / lambda_1 (t < t_iso)
+GDPM_DEV float mw_screening(const Tables& T, float tt) {
+    const float f = fminf((hlog2(tt) - T.aw_lo) * T.aw_inv, (float)(T.aw_n - 1));
+    const int i = min(max((int)f, 0), T.aw_n - 2);  // f < 0 extrapolates the first cell
+    return hexp2(lerp1(T.aw, i, f - (float)i));
+}
+
 // modified-Wentzel deflection mu = (1 - cos)/2 for t = s / lambda_1
 GDPM_DEV float mw_mu(const Tables& T, float tt, float u) {
     if (!(tt < kMwIsoF)) return u;
-    const float f = fminf((hlog2(tt) - T.aw_lo) * T.aw_inv, (float)(T.aw_n - 1));
-    const int i = min(max((int)f, 0), T.aw_n - 2);  // f < 0 extrapolates the first cell
-    const float a = hexp2(lerp1(T.aw, i, f - (float)i));
+    const float a = mw_screening(T, tt);
     return a * u / (1.0f + a - u);
 }
 
@@ -712,7 +721,8 @@ __global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, Sour
                             const float turns = uniform(rng, k0, k1);
                             const float u0 = u, v0 = v, w0 = w;
                             rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
-                            // exact split of E into E' and T
+                            // exact split of E into E' and T (the unit is built without
+                            // contraction, so the product is rounded on its own)
                             const float ec = eps * e;
                             float e1, te;
                             if (2.0f * ec >= e) {
@@ -965,9 +975,10 @@ __global__ void __launch_bounds__(256) k_electron(Ctl* ctl, Tables T, Geom G, So
                         iz += st;
                     }
                     if (ix < 0 || ix >= G.nx || iy < 0 || iy >= G.ny || iz < 0 || iz >= G.nz) {
-                        const float out = e + (positron ? aa : 0.0f);
-                        tl.e_esc += (double)out;
-                        tl.h_esc += (double)out;
+                        // a positron takes its annihilation energy along (summed in FP64)
+                        const double out = (double)e + (positron ? (double)aa : 0.0);
+                        tl.e_esc += out;
+                        tl.h_esc += out;
                         active = false;
                     }
                 } else if (hard) {
@@ -1129,8 +1140,8 @@ __global__ void k_bin_swap(Ctl* ctl, int ri) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_dose_stats(Ctl* ctl, const double* slots, size_t nvox,
                                                     int nb, const double* inv_mass_n,
-                                                    const uint2* vox, double vvox, double* dose,
-                                                    double* sigma) {
+                                                    const uint2* vox, double vvox, float min_rho,
+                                                    double* dose, double* sigma) {
     double emax = 0.0, edep = 0.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
          i += (size_t)gridDim.x * blockDim.x) {
@@ -1150,7 +1161,7 @@ __global__ void __launch_bounds__(256) k_dose_stats(Ctl* ctl, const double* slot
         }
         if (dose) dose[i] = mean;
         if (sigma) sigma[i] = nb > 1 ? sqrt(s2 / ((double)nb * (nb - 1))) : 0.0;
-        emax = fmax(emax, mean);
+        if (rho >= (double)min_rho) emax = fmax(emax, mean);
     }
     // block reductions
     __shared__ double sh[256];
@@ -1173,12 +1184,12 @@ __global__ void __launch_bounds__(256) k_dose_stats(Ctl* ctl, const double* slot
 
 // mean of sigma / D_max over voxels with D > D_max / 2
 __global__ void __launch_bounds__(256) k_unc(Ctl* ctl, const double* dose, const double* sigma,
-                                             size_t nvox) {
+                                             const uint2* vox, float min_rho, size_t nvox) {
     const double dmax = __longlong_as_double((long long)ctl->dmax_bits);
     double s = 0.0, c = 0.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
          i += (size_t)gridDim.x * blockDim.x) {
-        if (dose[i] > 0.5 * dmax) {
+        if (dose[i] > 0.5 * dmax && __uint_as_float(vox[i].x) >= min_rho) {
             s += sigma[i];
             c += 1.0;
         }
@@ -1307,9 +1318,7 @@ __global__ void k_test_lookup(Tables T, int which, int m, const float* in, float
     } else if (which == 5) {
         r = range_inv(T, m, x);
     } else if (which == 6) {
-        // A from the table: at u = 1/2, mu = A / (2A + 1), so A = mu / (1 - 2 mu)
-        const float mu = mw_mu(T, x, 0.5f);
-        r = mu / (1.0f - 2.0f * mu);
+        r = mw_screening(T, x);
     }
     out[i] = r;
 }
@@ -1342,12 +1351,12 @@ hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, i
     return hipGetLastError();
 }
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
-                        int nb, const double* inv_n, const uint2* vox, double vvox, double* dose,
-                        double* sigma) {
+                        int nb, const double* inv_n, const uint2* vox, double vvox, float min_rho,
+                        double* dose, double* sigma) {
     hipLaunchKernelGGL(k_dose_stats, dim3(blocks), dim3(256), 0, st, ctl, slots, nvox, nb, inv_n,
-                       vox, vvox, dose, sigma);
+                       vox, vvox, min_rho, dose, sigma);
     hipLaunchKernelGGL(k_unc, dim3(blocks), dim3(256), 0, st, ctl, (const double*)dose,
-                       (const double*)sigma, nvox);
+                       (const double*)sigma, vox, min_rho, nvox);
     return hipGetLastError();
 }
 hipError_t launch_test_philox(hipStream_t st, uint32_t k0, uint32_t k1, const uint4* ctr, uint4* out,

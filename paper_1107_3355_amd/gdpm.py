@@ -58,7 +58,8 @@ class RunParams(C.Structure):
                 ("target_unc", C.c_double), ("n_batches", C.c_int),
                 ("ecut_photon_mev", C.c_double), ("ecut_electron_mev", C.c_double),
                 ("max_histories", C.c_uint64), ("flags", C.c_uint32),
-                ("round_size", C.c_uint64), ("hist0", C.c_uint64)]
+                ("round_size", C.c_uint64), ("hist0", C.c_uint64),
+                ("stat_min_density", C.c_double)]
 
 
 class RunStats(C.Structure):
@@ -66,7 +67,8 @@ class RunStats(C.Structure):
                 ("e_esc", C.c_double), ("unc_mean_over_dmax", C.c_double), ("dmax", C.c_double),
                 ("t_total_s", C.c_double), ("t_kernel_s", C.c_double),
                 ("t_photon_s", C.c_double), ("t_electron_s", C.c_double),
-                ("events", C.c_uint64 * 8), ("passes", C.c_uint32), ("rounds", C.c_uint32)]
+                ("events", C.c_uint64 * 8), ("passes", C.c_uint32), ("rounds", C.c_uint32),
+                ("passes_photon", C.c_uint32), ("passes_electron", C.c_uint32)]
 
 
 def lib():
@@ -200,6 +202,7 @@ def _stats_dict(st):
             "unc": st.unc_mean_over_dmax, "dmax": st.dmax, "t_total_s": st.t_total_s,
             "t_kernel_s": st.t_kernel_s, "t_photon_s": st.t_photon_s,
             "t_electron_s": st.t_electron_s, "passes": int(st.passes), "rounds": int(st.rounds),
+            "passes_photon": int(st.passes_photon), "passes_electron": int(st.passes_electron),
             "events": {k: int(st.events[i]) for i, k in enumerate(EV_NAMES)}}
 
 
@@ -225,10 +228,11 @@ class Context:
 
     def run(self, phantom: Phantom, source: Source, *, seed=1, n_hist=1000, n_batches=10,
             round_size=0, hist0=0, job_id=0, ecut_g=0.05, ecut_e=0.2, flags=0, target_unc=0.0,
-            max_histories=0, want_batches=False, want_hist=False, want_dose=True):
+            max_histories=0, stat_min_density=0.0, want_batches=False, want_hist=False,
+            want_dose=True):
         nv = phantom.desc.nvox
         prm = RunParams(seed, job_id, n_hist, target_unc, n_batches, ecut_g, ecut_e,
-                        max_histories, flags, round_size, hist0)
+                        max_histories, flags, round_size, hist0, stat_min_density)
         dose = np.zeros(nv) if want_dose else None
         sigma = np.zeros(nv) if want_dose else None
         batch = np.zeros((n_batches, nv)) if want_batches else None
@@ -252,7 +256,8 @@ class Context:
                         kw.get("target_unc", 0.0), kw.get("n_batches", 10),
                         kw.get("ecut_g", 0.05), kw.get("ecut_e", 0.2),
                         kw.get("max_histories", 0), kw.get("flags", 0),
-                        kw.get("round_size", 0), kw.get("hist0", 0))
+                        kw.get("round_size", 0), kw.get("hist0", 0),
+                        kw.get("stat_min_density", 0.0))
         job = C.c_void_p()
         _check(lib().gdpm_run_async(self.handle, phantom.handle, source.handle, C.byref(prm),
                                     C.c_void_p(d_dose), C.c_void_p(d_sigma),

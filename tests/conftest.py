@@ -20,3 +20,13 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def root():
     return ROOT
+
+
+@pytest.fixture(scope="session")
+def gctx():
+    """One libgdpm context on GPU 0 for the whole GPU test session."""
+    from paper_1107_3355_amd import gdpm as G
+    from paper_1107_3355_amd import inputs as I
+    ctx = G.Context(0, materials=I.MATERIALS)
+    yield ctx
+    ctx.close()

@@ -22,19 +22,24 @@ def t_values(d1, s1, d2, s2):
     return t
 
 
-def pass_rate(d1, s1, d2, s2, n_batches=10, frac=0.1):
-    """Fraction of voxels with D > frac * D_max (either estimate) whose |t| < t_crit."""
-    dmax = max(d1.max(), d2.max())
-    region = (np.maximum(d1, d2) > frac * dmax)
+def pass_rate(d1, s1, d2, s2, n_batches=10, frac=0.1, mask=None):
+    """Fraction of voxels with D > frac * D_max (either estimate) whose |t| < t_crit;
+    `mask` restricts both D_max and the region (e.g. to voxels inside the body)."""
+    if mask is None:
+        mask = np.ones(d1.shape, dtype=bool)
+    dmax = max(d1[mask].max(), d2[mask].max())
+    region = (np.maximum(d1, d2) > frac * dmax) & mask
     t = t_values(d1, s1, d2, s2)
     ok = np.abs(t[region]) < t_crit(n_batches)
     return float(ok.mean()), int(region.sum())
 
 
-def unc_over_dmax(dose, sigma):
+def unc_over_dmax(dose, sigma, mask=None):
     """Mean of sigma / D_max over voxels with D > 0.5 D_max (section 3.1)."""
-    dmax = dose.max()
-    hi = dose > 0.5 * dmax
+    if mask is None:
+        mask = np.ones(dose.shape, dtype=bool)
+    dmax = dose[mask].max()
+    hi = (dose > 0.5 * dmax) & mask
     return float((sigma[hi] / dmax).mean())
 
 

@@ -1,0 +1,349 @@
+"""Transport parity: the HIP path against the oracle.
+
+Two kinds of comparison (section 3.1 of the paper compares CPU and GPU codes
+statistically):
+  * statistical, independent Philox seeds on both sides: per-voxel t-test
+    t = (D_1 - D_2)/sqrt(s_1^2 + s_2^2), |t| < t_{0.975, N_b-1}, passing in at
+    least 95% of the voxels above 10% of D_max; the batch-resolved region sum
+    within 2 standard errors; energy balance below 1e-6 on both sides;
+  * per history, same seed: both sides draw the same streams, so most
+    histories follow the same path and deposit the same energy (a history
+    leaves lockstep when a single-precision value lands next to a decision
+    threshold or a table value differs from the closed form).
+Plus closed-form special cases on the GPU, determinism, independence of the
+launch configuration, edge cases and error paths."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats as sst
+
+import oracle
+from paper_1107_3355_amd import gdpm as G
+from paper_1107_3355_amd import inputs as I
+from tests import stats as S
+from tests.gpu_common import balance, gpu_run, lockstep_fraction, oracle_run, report
+
+pytestmark = pytest.mark.gpu
+MATS = I.MATERIALS
+
+
+def _compare_stat(gctx, ph, src, n, flags=0, name="", min_rate=0.95, min_rho=0.0):
+    """min_rho > 0 leaves low-density voxels (air around a patient) out of D_max and of
+    the compared region: their dose estimates are dominated by rare local deposits."""
+    g = gpu_run(gctx, ph, src, seed=1, n_hist=n, flags=flags, want_batches=True)
+    o = oracle_run(MATS, ph, src, seed=2, n_hist=n, flags=flags)
+    mask = ph.rho.ravel() >= min_rho
+    rate, nreg = S.pass_rate(g["dose"], g["sigma"], o["dose"], o["sigma"], mask=mask)
+    hi, _ = S.pass_rate(g["dose"], g["sigma"], o["dose"], o["sigma"], frac=0.5, mask=mask)
+    allr, _ = S.pass_rate(g["dose"], g["sigma"], o["dose"], o["sigma"], frac=0.0, mask=mask)
+    dmax = max(g["dose"][mask].max(), o["dose"][mask].max())
+    region = (np.maximum(g["dose"], o["dose"]) > 0.1 * dmax) & mask
+    nb = n / 10
+    diff, se = S.region_sum_test(g["batch_edep"], nb, o["batch_edep"], nb, region)
+    report(name, pass_rate=round(rate, 4), p_high=round(hi, 4), p_all=round(allr, 4), voxels=nreg,
+           sum_diff_sigma=round(diff / se, 3),
+           unc_g=round(S.unc_over_dmax(g["dose"], g["sigma"], mask), 5),
+           unc_o=round(S.unc_over_dmax(o["dose"], o["sigma"], mask), 5), bal_g=balance(g),
+           bal_o=balance(o))
+    assert balance(g) < 1e-6 and balance(o) < 1e-6
+    assert nreg >= 200
+    assert rate >= min_rate
+    assert abs(diff) <= 2 * se
+    return g, o
+
+
+def _compare_lockstep(gctx, ph, src, n, flags=0, name="", min_frac=0.9, hist0=0):
+    g = gpu_run(gctx, ph, src, seed=3, n_hist=n, n_batches=2, flags=flags, want_hist=True,
+                hist0=hist0)
+    o = oracle_run(MATS, ph, src, seed=3, n_hist=n, n_batches=2, flags=flags, want_hist=True,
+                   hist0=hist0)
+    e_in = oracle.sample_source(src, ph, seed=3, hist0=hist0, n=n)[:, 0]
+    p, s = gctx.phantom(ph), gctx.source(src)
+    e_in_g = gctx.sample_source(p, s, seed=3, hist0=hist0, n=n)[:, 0].astype(np.float64)
+    p.close()
+    s.close()
+    frac = lockstep_fraction(g["hist"], o["hist"], e_in)
+    report(name + "/lockstep", frac=round(frac, 4), ev_g=g["events"], ev_o=o["events"])
+    # per-history energy balance on both sides
+    assert np.allclose(g["hist"].sum(axis=1), e_in_g, rtol=1e-9)
+    assert np.allclose(o["hist"].sum(axis=1), e_in, rtol=1e-12)
+    assert frac >= min_frac
+    # event counts agree to within the histories that left lockstep
+    for k in ("flights", "real", "esteps", "pushes"):
+        a, b = g["events"][k], o["events"][k]
+        assert abs(a - b) <= max(20, 0.05 * b), k
+    return g, o
+
+
+# --------------------------------------------------------------------------
+# water cube, 2 MeV parallel photons (32^3 voxels of 0.5 cm)
+# --------------------------------------------------------------------------
+
+def test_water_kerma_statistical(gctx):
+    w = I.water_cube_2mev()
+    _compare_stat(gctx, w.phantom, w.source, 200_000, flags=G.KERMA, name="water_kerma")
+
+
+def test_water_full_statistical(gctx):
+    w = I.water_cube_2mev()
+    _compare_stat(gctx, w.phantom, w.source, 200_000, name="water_full")
+
+
+def test_water_full_lockstep(gctx):
+    w = I.water_cube_2mev()
+    _compare_lockstep(gctx, w.phantom, w.source, 20_011, name="water_full", min_frac=0.95)
+
+
+# --------------------------------------------------------------------------
+# slab heterogeneity phantom: water/lung/bone/water
+# --------------------------------------------------------------------------
+
+def test_slab_photon_statistical(gctx):
+    w = I.slab_photon(n=50, d=0.6)
+    _compare_stat(gctx, w.phantom, w.source, 300_000, name="slab50_photon")
+
+
+def test_slab_electron_statistical(gctx):
+    w = I.slab_electron(n=50, d=0.6)
+    _compare_stat(gctx, w.phantom, w.source, 20_000, name="slab50_electron")
+
+
+def test_slab_photon_full_size_lockstep(gctx):
+    w = I.slab_photon()
+    _compare_lockstep(gctx, w.phantom, w.source, 4_003, name="slab100_photon", min_frac=0.9)
+
+
+def test_slab_electron_full_size_lockstep(gctx):
+    w = I.slab_electron()
+    _compare_lockstep(gctx, w.phantom, w.source, 301, name="slab100_electron", min_frac=0.5)
+
+
+# --------------------------------------------------------------------------
+# synthetic CT with a 9-beam fluence-map plan
+# --------------------------------------------------------------------------
+
+def test_ct_small_statistical(gctx):
+    ph = I.ct_phantom((48, 48, 24), (1.0, 1.0, 1.25))
+    src = I.Source(I.PHOTON, I.triangular_spectrum(), I.imrt_plan(ph, nb=10))
+    _compare_stat(gctx, ph, src, 300_000, name="ct48_imrt", min_rho=0.1)
+
+
+_CT = {}
+
+
+def _ct_full():
+    if "w" not in _CT:
+        _CT["w"] = I.ct_imrt()
+    return _CT["w"]
+
+
+def test_ct_full_size_lockstep(gctx):
+    """Full-size CT (256x256x128) in the benchmark's launch configuration:
+    sampled histories computed one by one by the oracle."""
+    w = _ct_full()
+    _compare_lockstep(gctx, w.phantom, w.source, 2_000, name="ct256_imrt", min_frac=0.9,
+                      hist0=10_000_000)
+
+
+def test_ct_full_size_energy_balance(gctx):
+    w = _ct_full()
+    r = gpu_run(gctx, w.phantom, w.source, seed=1, n_hist=5_000_000, stat_min_density=0.1)
+    report("ct256_balance", bal=balance(r), unc=r["unc"], t_kernel=r["t_kernel_s"])
+    assert balance(r) < 1e-6
+    assert np.all(r["dose"] >= 0) and np.all(r["sigma"] >= 0)
+
+
+# --------------------------------------------------------------------------
+# closed-form special cases on the GPU
+# --------------------------------------------------------------------------
+
+def _layered(mats, rhos, dz, lateral=2.0):
+    nz = len(mats)
+    ph = I.homogeneous((1, 1, nz), (lateral, lateral, dz), I.ID_WATER, 1.0)
+    ph.mat[:, 0, 0] = mats
+    ph.rho[:, 0, 0] = rhos
+    return ph
+
+
+def test_gpu_photoelectric_layers_beer_lambert(gctx):
+    nz, dz, e = 24, 0.5, 0.06
+    rhos = np.where(np.arange(nz) % 2 == 0, 1.85, 0.6).astype(np.float32)
+    ph = _layered([I.ID_BONE] * nz, rhos, dz)
+    src = I.Source(I.PHOTON, I.mono(e), [I.parallel_beam_z(ph, 0.5)])
+    n = 400_000
+    r = gpu_run(gctx, ph, src, n_hist=n, flags=G.NO_COMPTON | G.NO_PAIR, want_batches=True)
+    counts = np.append(r["batch_edep"].sum(axis=0), r["e_esc"]) / np.float32(e)
+    assert np.allclose(counts, np.round(counts), atol=1e-3)
+    mu = oracle.phys(oracle.MU_PHOTO, I.BONE, e)
+    tau = np.concatenate([[0.0], np.cumsum(rhos * mu * dz)])
+    p = np.append(np.exp(-tau[:-1]) - np.exp(-tau[1:]), np.exp(-tau[-1]))
+    assert sst.chisquare(np.round(counts), p * n).pvalue > 1e-4
+
+
+def test_gpu_narrow_beam_uncollided(gctx):
+    mats = [I.ID_WATER] * 6 + [I.ID_BONE] * 4 + [I.ID_LUNG] * 6 + [I.ID_WATER] * 4
+    rhos = np.array([MATS[m].rho_nominal for m in mats], dtype=np.float32)
+    dz, e = 1.0, 2.0
+    ph = _layered(mats, rhos, dz)
+    src = I.Source(I.PHOTON, I.mono(e), [I.parallel_beam_z(ph, 0.01)])
+    n = 1_000_000
+    r = gpu_run(gctx, ph, src, n_hist=n, flags=G.KERMA, want_hist=True)
+    k = int((r["hist"][:, 0] == 0.0).sum())
+    mu = lambda m: sum(oracle.phys(w, MATS[m], e) for w in (0, 1, 2))
+    p = math.exp(-sum(rho * mu(m) * dz for m, rho in zip(mats, rhos)))
+    report("narrow_beam", k=k, expect=n * p)
+    assert abs(k - n * p) < 4 * math.sqrt(n * p * (1 - p))
+
+
+@pytest.mark.parametrize("hetero", [False, True])
+def test_gpu_csda_pencil(gctx, hetero):
+    from tests.test_oracle_transport import _csda_profile
+    dz, t0 = 0.1, 3.0
+    mats = ([I.ID_WATER] * 5 + [I.ID_BONE] * 5 + [I.ID_LUNG] * 10 + [I.ID_WATER] * 10) if hetero \
+        else [I.ID_WATER] * 30
+    rhos = np.array([MATS[m].rho_nominal for m in mats], dtype=np.float32)
+    ph = _layered(mats, rhos, dz)
+    src = I.Source(I.ELECTRON, I.mono(t0), [I.parallel_beam_z(ph, 0.01)])
+    r = gpu_run(gctx, ph, src, n_hist=64, n_batches=2,
+                flags=G.NO_MS | G.NO_MOLLER | G.NO_BREMS, want_batches=True)
+    got = r["batch_edep"].sum(axis=0) / 64
+    exp = _csda_profile(mats, rhos.astype(np.float64), dz, t0)
+    # single-precision tables: 1e-3 of the energy per layer, plus 1 keV
+    assert np.all(np.abs(got - exp) <= 1e-3 * exp + 1e-3)
+    assert abs(got.sum() - t0) < 1e-5
+
+
+# --------------------------------------------------------------------------
+# determinism and independence from the launch configuration
+# --------------------------------------------------------------------------
+
+def test_determinism_and_launch_independence(gctx):
+    w = I.water_cube_2mev(50_000)
+    a = gpu_run(gctx, w.phantom, w.source, n_hist=50_000, seed=9)
+    b = gpu_run(gctx, w.phantom, w.source, n_hist=50_000, seed=9)
+    assert a["events"] == b["events"]
+    np.testing.assert_allclose(a["dose"], b["dose"], rtol=1e-12, atol=1e-300)
+    for opts in ('{"waves_per_cu": 4, "rebin_bins": 0}', '{"waves_per_cu": 8, "rebin_bins": 32}'):
+        c2 = G.Context(0, opts=opts, materials=MATS)
+        try:
+            c = gpu_run(c2, w.phantom, w.source, n_hist=50_000, seed=9)
+        finally:
+            c2.close()
+        assert c["events"] == a["events"], opts
+        np.testing.assert_allclose(c["dose"], a["dose"], rtol=1e-12, atol=1e-300)
+
+
+# --------------------------------------------------------------------------
+# edge cases and errors
+# --------------------------------------------------------------------------
+
+def test_ragged_history_counts(gctx):
+    w = I.water_cube_2mev()
+    for n in (1, 7, 12_345):
+        g = gpu_run(gctx, w.phantom, w.source, n_hist=n, want_hist=True, seed=4)
+        o = oracle_run(MATS, w.phantom, w.source, n_hist=n, want_hist=True, seed=4)
+        assert g["histories"] == n
+        assert balance(g) < 1e-6
+        assert lockstep_fraction(g["hist"], o["hist"], np.full(n, 2.0)) >= (0.9 if n > 10 else 0.0)
+
+
+def test_beam_missing_phantom(gctx):
+    ph = I.homogeneous((4, 4, 4), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
+    b = I.Beam(iso=(50.0, 50.0, 2.0), dir=(0.0, 0.0, 1.0), e1=(1.0, 0.0, 0.0), sad=0.0,
+               nbx=1, nby=1, bw=1.0, bh=1.0)
+    r = gpu_run(gctx, ph, I.Source(I.PHOTON, I.mono(1.0), [b]), n_hist=1000)
+    assert r["e_dep"] == 0.0 and r["e_in"] == pytest.approx(1000.0) and r["e_esc"] == pytest.approx(1000.0)
+
+
+def test_single_voxel_phantom(gctx):
+    ph = I.homogeneous((1, 1, 1), (3.0, 3.0, 3.0), I.ID_BONE, 1.85)
+    src = I.Source(I.PHOTON, I.mono(6.0), [I.parallel_beam_z(ph, 2.0)])
+    g = gpu_run(gctx, ph, src, n_hist=20_000, want_hist=True)
+    o = oracle_run(MATS, ph, src, n_hist=20_000, want_hist=True)
+    assert balance(g) < 1e-6
+    assert lockstep_fraction(g["hist"], o["hist"], np.full(20_000, 6.0)) > 0.9
+
+
+def test_zero_intensity_beamlets_never_chosen(gctx):
+    ph = I.homogeneous((20, 20, 10), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
+    f = np.zeros((4, 4), dtype=np.float32)
+    f[1, 2] = 1.0
+    b = I.gantry_beam(ph, 30.0, nb=4, bsize=2.0, intensity=f)
+    src = I.Source(I.PHOTON, I.mono(1.0), [b])
+    p, s = gctx.phantom(ph), gctx.source(src)
+    out = gctx.sample_source(p, s, n=10_000)
+    p.close()
+    s.close()
+    assert set(np.unique(out[:, 1]).tolist()) <= {6.0, -1.0}
+
+
+def test_invalid_inputs_rejected(gctx):
+    ph = I.homogeneous((4, 4, 4), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
+    bad = I.homogeneous((4, 4, 4), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
+    bad.rho[0, 0, 0] = 0.0
+    with pytest.raises(G.GdpmError) as e:
+        gctx.phantom(bad)
+    assert e.value.status == 1
+    bad.rho[0, 0, 0] = 1.0
+    bad.mat[0, 0, 0] = 9
+    with pytest.raises(G.GdpmError):
+        gctx.phantom(bad)
+    b = I.parallel_beam_z(ph, 1.0)
+    b.intensity = np.zeros((1, 1), dtype=np.float32)
+    with pytest.raises(G.GdpmError):
+        gctx.source(I.Source(I.PHOTON, I.mono(1.0), [b]))
+    with pytest.raises(G.GdpmError):
+        gctx.source(I.Source(I.PHOTON, I.mono(40.0), [I.parallel_beam_z(ph, 1.0)]))
+    p = gctx.phantom(ph)
+    s = gctx.source(I.Source(I.ELECTRON, I.mono(5.0), [I.parallel_beam_z(ph, 1.0)]))
+    with pytest.raises(G.GdpmError):
+        gctx.run(p, s, n_hist=10, flags=G.KERMA)      # kerma needs photons
+    with pytest.raises(G.GdpmError):
+        gctx.run(p, s, n_hist=0)
+    with pytest.raises(G.GdpmError):
+        gctx.run(p, s, n_hist=10, n_batches=1)
+    p.close()
+    s.close()
+
+
+def test_queue_overflow_reported():
+    """A queue too small for the workload stops the run with GDPM_E_OVERFLOW
+    (forced from the host by a 4096-record capacity); the context stays usable."""
+    c = G.Context(0, opts='{"ring_capacity_log2": 12}', materials=MATS)
+    try:
+        w = I.water_cube_2mev()
+        with pytest.raises(G.GdpmError) as e:
+            gpu_run(c, w.phantom, w.source, n_hist=200_000)
+        assert e.value.status == 4
+        r = gpu_run(c, w.phantom, w.source, n_hist=100)
+        assert balance(r) < 1e-6
+    finally:
+        c.close()
+
+
+def test_target_uncertainty_mode(gctx):
+    w = I.water_cube_2mev()
+    r = gpu_run(gctx, w.phantom, w.source, n_hist=20_000, target_unc=0.03, seed=5)
+    report("target", unc=r["unc"], hist=r["histories"], rounds=r["rounds"])
+    assert r["unc"] <= 0.03
+    assert r["histories"] > 20_000
+    assert balance(r) < 1e-6
+
+
+def test_run_async_device_outputs(gctx):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("torch has no GPU here")
+    w = I.water_cube_2mev()
+    nv = w.phantom.nvox
+    d = torch.zeros(nv, dtype=torch.float64, device="cuda")
+    s = torch.zeros(nv, dtype=torch.float64, device="cuda")
+    p, src = gctx.phantom(w.phantom), gctx.source(w.source)
+    st = gctx.run_async(p, src, d.data_ptr(), s.data_ptr(), n_hist=20_000, seed=6)
+    ref = gctx.run(p, src, n_hist=20_000, seed=6)
+    p.close()
+    src.close()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(d.cpu().numpy(), ref["dose"], rtol=1e-12, atol=1e-300)
+    assert st["histories"] == 20_000
