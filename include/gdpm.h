@@ -150,8 +150,10 @@ typedef struct {
 
 /* Create a context on HIP device `hip_device`.  opts_json may be NULL or a
  * flat JSON object with any of: "ring_capacity_log2" (queue records per type,
- * 2^k, default 24), "waves_per_cu" (persistent waves per CU, default 16),
- * "rebin_bins" (energy bins of the queue re-binning, 0 = off, default 16). */
+ * 2^k, default 24), "waves_per_cu" (wavefronts of the persistent workgroup
+ * each CU runs, default 16), "rebin_bins" (energy bins of the queue
+ * re-binning, 0 = off, default 16), "lds_tables" (1: stage interpolation tables
+ * in LDS when they fit, default; 0: read them through the caches). */
 gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out);
 gdpm_status gdpm_context_destroy(gdpm_context ctx);
 const char* gdpm_last_error(void);

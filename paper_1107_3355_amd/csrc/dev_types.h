@@ -70,6 +70,7 @@ struct Tables {
     const float* aw;       // [aw_n] log2 A at log2 t = aw_lo + i / aw_inv
     float aw_lo, aw_inv;
     int aw_n;
+    int n_mat;
 };
 
 struct Geom {

@@ -21,15 +21,18 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/gdpm.h"
+#include "gdpm.h"
 #include "dev_types.h"
 #include "tables.h"
 
 namespace gdpm {
 hipError_t launch_setup(hipStream_t st, Ctl* ctl, int ri, int with_source, uint32_t src_pass_max);
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri);
-hipError_t launch_transport(hipStream_t st, int ri, int blocks, Ctl* ctl, const Tables& T,
-                            const Geom& G, const SourceDev& S, const RunDev& R, int with_source);
+size_t transport_lds_bytes(int ri, const Tables& T);
+hipError_t transport_lds_optin(size_t bytes);
+hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, Ctl* ctl,
+                            const Tables& T, const Geom& G, const SourceDev& S, const RunDev& R,
+                            int with_source);
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
                         float lo, float inv);
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
@@ -134,6 +137,7 @@ struct DevTables {
         t.aw_lo = (float)host.aw_lo;
         t.aw_inv = (float)(1.0 / host.aw_step);
         t.aw_n = host.aw_n;
+        t.n_mat = host.n_mat;
         return t;
     }
 };
@@ -164,6 +168,9 @@ struct gdpm_context_s {
     int ring_log2 = 24;
     int waves_per_cu = 16;
     int rebin_bins = 16;
+    int lds_tables = 1;          // stage interpolation tables in LDS when they fit
+    int max_lds = 0;             // dynamic LDS bytes a workgroup may use
+    bool lds_optin = false;
     std::vector<MaterialParams> mats;
     int n_grid = 1024;
     std::map<TableKey, std::unique_ptr<DevTables>> tables;
@@ -267,7 +274,9 @@ gdpm_status ensure_rings(gdpm_context ctx) {
     return GDPM_OK;
 }
 
-int grid_blocks(gdpm_context ctx) { return std::max(1, ctx->cu_count * ctx->waves_per_cu / 4); }
+// persistent transport grid: one workgroup of waves_per_cu wavefronts per CU
+int grid_blocks(gdpm_context ctx) { return std::max(1, ctx->cu_count); }
+int block_threads(gdpm_context ctx) { return std::min(1024, 64 * ctx->waves_per_cu); }
 
 // ---------------------------------------------------------------------------
 // one run
@@ -337,10 +346,11 @@ gdpm_status run_round(gdpm_context ctx, const Tables& T, const Geom& G, const So
             // the queue a pass reads was filled by the other pass: compact it
             // and sort it by energy so that wavefronts draw similar particles
             if (nbins > 1 && (iter > 0 || k == 1))
-                HIP_TRY(launch_rebin(st, std::min(blocks, 4096), dc, R, ri, nbins, blo, binv));
+                HIP_TRY(launch_rebin(st, 4 * blocks, dc, R, ri, nbins, blo, binv));
             HIP_TRY(launch_setup(st, dc, ri, with_src, 1u << 30));
             HIP_TRY(hipEventRecord(ctx->events[2 * k], st));
-            HIP_TRY(launch_transport(st, ri, blocks, dc, T, G, S, R, with_src));
+            const bool lds = ctx->lds_tables && transport_lds_bytes(ri, T) <= (size_t)ctx->max_lds;
+            HIP_TRY(launch_transport(st, ri, blocks, block_threads(ctx), lds, dc, T, G, S, R, with_src));
             HIP_TRY(hipEventRecord(ctx->events[2 * k + 1], st));
             HIP_TRY(launch_finish(st, dc, ri));
             tm->passes++;
@@ -557,10 +567,17 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->ring_log2 = json_int(opts_json, "ring_capacity_log2", 24);
     ctx->waves_per_cu = json_int(opts_json, "waves_per_cu", 16);
     ctx->rebin_bins = json_int(opts_json, "rebin_bins", 16);
+    ctx->lds_tables = json_int(opts_json, "lds_tables", 1);
     if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
     if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > 64) return fail(GDPM_E_INVALID, "waves_per_cu in [1, 64]");
     if (ctx->rebin_bins < 0 || ctx->rebin_bins > kMaxBins) return fail(GDPM_E_INVALID, "rebin_bins in [0, 64]");
     HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device));
+    HIP_TRY(hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device));
+    if (ctx->lds_tables) {
+        // the staged kernels may use all of it (above 64 KB an opt-in is needed)
+        if (transport_lds_optin((size_t)ctx->max_lds) != hipSuccess) ctx->lds_tables = 0;
+        (void)hipGetLastError();
+    }
     HIP_TRY(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
     HIP_TRY(ctx->ctl.alloc(sizeof(Ctl)));
     HIP_TRY(hipHostMalloc((void**)&ctx->host_ctl, sizeof(Ctl), hipHostMallocDefault));

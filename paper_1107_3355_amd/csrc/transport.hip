@@ -82,49 +82,106 @@ GDPM_DEV void philox(uint32_t k0, uint32_t k1, uint32_t& x0, uint32_t& x1, uint3
                      uint32_t& x3) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
-        const uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
-        const uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+        // one 32x32 -> 64-bit product per multiplier
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
         x0 = y0;
-        x1 = lo1;
+        x1 = (uint32_t)p1;
         x2 = y2;
-        x3 = lo0;
+        x3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
 }
 
-// A lane's stream: key (k0, k1), counter (hist lo, hist hi, path, ctr >> 2);
-// draw d is word d & 3 of its block; the current block is cached.
+// A lane's stream: key (k0, k1), counter (hist lo, hist hi, path, draw >> 2);
+// draw d is word d & 3 of its block.  Two blocks are buffered: A (block `blk`,
+// next word `i`, 4 = used up) and C (block blk + 1 when `ahead`).  Blocks are
+// generated in rng_topup, once per iteration and with the wavefront converged;
+// a lane that runs out inside an event takes the out-of-line slow path.
 struct Rng {
-    uint32_t hlo, hhi, path, ctr;
-    uint32_t b0, b1, b2, b3;
+    uint32_t hlo, hhi, path;
+    uint32_t blk, i, skip;
+    uint32_t a0, a1, a2, a3;
+    uint32_t c0, c1, c2, c3;
+    bool ahead;
 };
 
-GDPM_DEV void rng_block(Rng& r, uint32_t k0, uint32_t k1) {
-    uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = r.ctr >> 2;
+// counter of the next draw
+GDPM_DEV uint32_t rng_ctr(const Rng& r) { return 4u * r.blk + r.i; }
+
+// position the stream at draw `ctr` (no block generated yet)
+GDPM_DEV void rng_start(Rng& r, uint32_t hlo, uint32_t hhi, uint32_t path, uint32_t ctr) {
+    r.hlo = hlo;
+    r.hhi = hhi;
+    r.path = path;
+    r.blk = (ctr >> 2) - 1u;  // A is "used up"; the next block is ctr >> 2
+    r.i = 4u;
+    r.skip = ctr & 3u;
+    r.ahead = false;
+}
+
+__device__ __attribute__((noinline)) uint4 rng_block_slow(uint32_t k0, uint32_t k1, uint32_t hlo,
+                                                         uint32_t hhi, uint32_t path, uint32_t blk) {
+    uint32_t x0 = hlo, x1 = hhi, x2 = path, x3 = blk;
     philox(k0, k1, x0, x1, x2, x3);
-    r.b0 = x0;
-    r.b1 = x1;
-    r.b2 = x2;
-    r.b3 = x3;
+    return make_uint4(x0, x1, x2, x3);
+}
+
+// make sure A has a word left and C holds the following block
+GDPM_DEV void rng_topup(Rng& r, uint32_t k0, uint32_t k1) {
+    if (r.i == 4u) {
+        if (r.ahead) {
+            r.a0 = r.c0; r.a1 = r.c1; r.a2 = r.c2; r.a3 = r.c3;
+            r.ahead = false;
+        } else {
+            uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = r.blk + 1u;
+            philox(k0, k1, x0, x1, x2, x3);
+            r.a0 = x0; r.a1 = x1; r.a2 = x2; r.a3 = x3;
+        }
+        r.blk += 1u;
+        r.i = r.skip;
+        r.skip = 0u;
+    }
+    if (!r.ahead) {
+        uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = r.blk + 1u;
+        philox(k0, k1, x0, x1, x2, x3);
+        r.c0 = x0; r.c1 = x1; r.c2 = x2; r.c3 = x3;
+        r.ahead = true;
+    }
 }
 
 // (2 (x >> 9) + 1) 2^-24: exact in single and double precision, inside (0, 1)
 GDPM_DEV float uniform(Rng& r, uint32_t k0, uint32_t k1) {
-    const uint32_t w = r.ctr & 3u;
-    if (w == 0u) rng_block(r, k0, k1);
-    const uint32_t x = w == 0u ? r.b0 : (w == 1u ? r.b1 : (w == 2u ? r.b2 : r.b3));
-    r.ctr += 1u;
+    if (r.i == 4u) {
+        if (r.ahead) {
+            r.a0 = r.c0; r.a1 = r.c1; r.a2 = r.c2; r.a3 = r.c3;
+            r.ahead = false;
+        } else {
+            const uint4 b = rng_block_slow(k0, k1, r.hlo, r.hhi, r.path, r.blk + 1u);
+            r.a0 = b.x; r.a1 = b.y; r.a2 = b.z; r.a3 = b.w;
+        }
+        r.blk += 1u;
+        r.i = r.skip;
+        r.skip = 0u;
+    }
+    const uint32_t w = r.i;
+    const uint32_t x = w == 0u ? r.a0 : (w == 1u ? r.a1 : (w == 2u ? r.a2 : r.a3));
+    r.i = w + 1u;
     return (float)(x >> 9) * 0x1p-23f + 0x1p-24f;
 }
 
 // path id of the secondary created in role `word` at the parent's current counter
 GDPM_DEV uint32_t spawn_path(const Rng& r, uint32_t k0, uint32_t k1, int word) {
-    uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = 0x80000000u | r.ctr;
+    uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = 0x80000000u | rng_ctr(r);
     philox(k0, k1, x0, x1, x2, x3);
     return word == 0 ? x0 : (word == 1 ? x1 : (word == 2 ? x2 : x3));
 }
+
+// non-exact division through the hardware reciprocal (about 1 ulp)
+GDPM_DEV float fdiv(float a, float b) { return a * hrcp(b); }
 
 // ---------------------------------------------------------------------------
 // table lookups (linear in log2 E)
@@ -147,18 +204,23 @@ GDPM_DEV float lerp1(const float* tab, int i, float t) {
     return fmaf(t, b - a, a);
 }
 
-GDPM_DEV float4 elec_at(const Tables& T, int m, float e) {
+GDPM_DEV float4 elec_at(const Tables& T, const float4* etab, int m, float e) {
     int i;
     float t;
     grid(hlog2(e), T.eg_lo, T.eg_inv, T.eg_n, i, t);
-    return lerp4(T.elec + m * T.eg_n, i, t);
+    return lerp4(etab + m * T.eg_n, i, t);
 }
+GDPM_DEV float4 elec_at(const Tables& T, int m, float e) { return elec_at(T, T.elec, m, e); }
 
-// energy whose residual range is r (g/cm^2)
-GDPM_DEV float range_inv(const Tables& T, int m, float r) {
-    const float f = fminf(hsqrt(fmaxf(r, 0.0f)) * T.rinv_scale[m], (float)(T.nr - 1));
+// energy whose residual range is r (g/cm^2); rtab holds the material's nodes
+// followed (after all materials) by the per-material scales
+GDPM_DEV float range_inv(const Tables& T, const float* rtab, const float* rscale, int m, float r) {
+    const float f = fminf(hsqrt(fmaxf(r, 0.0f)) * rscale[m], (float)(T.nr - 1));
     const int i = min((int)f, T.nr - 2);
-    return lerp1(T.rinv + m * T.nr, i, f - (float)i);
+    return lerp1(rtab + m * T.nr, i, f - (float)i);
+}
+GDPM_DEV float range_inv(const Tables& T, int m, float r) {
+    return range_inv(T, T.rinv, T.rinv_scale, m, r);
 }
 
 // screening A of the modified-Wentzel law for t = s / lambda_1 (t < t_iso)
@@ -172,7 +234,7 @@ GDPM_DEV float mw_screening(const Tables& T, float tt) {
 GDPM_DEV float mw_mu(const Tables& T, float tt, float u) {
     if (!(tt < kMwIsoF)) return u;
     const float a = mw_screening(T, tt);
-    return a * u / (1.0f + a - u);
+    return fdiv(a * u, 1.0f + a - u);
 }
 
 // ---------------------------------------------------------------------------
@@ -221,18 +283,18 @@ GDPM_DEV float face_dist(const Geom& G, float x, float y, float z, float u, floa
     float best = 3.0e38f;
     ax = 0;
     if (u != 0.0f) {
-        const float d = ((u > 0.0f ? (float)(ix + 1) : (float)ix) * G.dx - x) / u;
+        const float d = fdiv((u > 0.0f ? (float)(ix + 1) : (float)ix) * G.dx - x, u);
         best = d;
     }
     if (v != 0.0f) {
-        const float d = ((v > 0.0f ? (float)(iy + 1) : (float)iy) * G.dy - y) / v;
+        const float d = fdiv((v > 0.0f ? (float)(iy + 1) : (float)iy) * G.dy - y, v);
         if (d < best) {
             best = d;
             ax = 1;
         }
     }
     if (w != 0.0f) {
-        const float d = ((w > 0.0f ? (float)(iz + 1) : (float)iz) * G.dz - z) / w;
+        const float d = fdiv((w > 0.0f ? (float)(iz + 1) : (float)iz) * G.dz - z, w);
         if (d < best) {
             best = d;
             ax = 2;
@@ -477,55 +539,132 @@ GDPM_DEV void tally_finish(LaneTally& t, const RunDev& R, Ctl* ctl) {
 }
 
 // ---------------------------------------------------------------------------
-// pending secondaries of one event (at most two per queue)
+// samplers (the draw order is part of the contract with the reference)
 // ---------------------------------------------------------------------------
-struct Pending {
-    int n;
-    float e[2], u[2], v[2], w[2], a[2];
-    uint32_t word[2], flags[2];
-};
 
-GDPM_DEV void pend(Pending& q, float e, float u, float v, float w, uint32_t word, float a = 0.0f,
-                   uint32_t flags = 0u) {
-    const int k = q.n;
-    if (k == 0) {
-        q.e[0] = e; q.u[0] = u; q.v[0] = v; q.w[0] = w; q.word[0] = word; q.a[0] = a; q.flags[0] = flags;
-    } else {
-        q.e[1] = e; q.u[1] = u; q.v[1] = v; q.w[1] = w; q.word[1] = word; q.a[1] = a; q.flags[1] = flags;
+// Klein-Nishina by Butcher-Messel composition and rejection: eps = E'/E and
+// t = 1 - cos(theta); then the azimuth (in turns)
+GDPM_DEV void sample_compton(Rng& r, uint32_t k0, uint32_t k1, float e, float& eps, float& t,
+                             float& turns) {
+    const float k = e * (1.0f / kMec2f);
+    const float e0 = hrcp(1.0f + 2.0f * k);
+    const float a1 = kLn2f * hlog2(1.0f + 2.0f * k);
+    const float a2 = 0.5f * (1.0f - e0 * e0);
+    const float ik = hrcp(k);
+    for (;;) {
+        const float ua = uniform(r, k0, k1), ub = uniform(r, k0, k1), uc = uniform(r, k0, k1);
+        if (ua * (a1 + a2) < a1) eps = hexp2(-a1 * ub * (1.0f / kLn2f));
+        else eps = hsqrt(e0 * e0 + (1.0f - e0 * e0) * ub);
+        t = (1.0f - eps) * ik * hrcp(eps);
+        if (uc <= 1.0f - fdiv(eps * t * (2.0f - t), 1.0f + eps * eps)) break;
     }
-    q.n = k + 1;
+    turns = uniform(r, k0, k1);
 }
 
-// push the pending secondaries of all lanes into ring `ri`; they start at the
-// parent's position, with the parent's history and a spawned path
-GDPM_DEV void push_pending(Pending& q, int ri, PushState& ps, uint32_t head, Ctl* ctl,
-                           const RunDev& R, Particle* buf, float x, float y, float z,
-                           uint32_t vox, const Rng& rng, LaneTally& t) {
+// Moller: eps = W/T by a 1/eps^2 proposal on [W_cc/T, 1/2] and rejection
+// eps^2 B(eps) / 2.25; then the azimuth
+GDPM_DEV void sample_moller(Rng& r, uint32_t k0, uint32_t k1, float tt, float wcc, float& eps,
+                            float& turns) {
+    const float g = 1.0f + tt * (1.0f / kMec2f), e0 = fdiv(wcc, tt);
+    const float ig = hrcp(g);
+    const float c1 = (g - 1.0f) * ig, c2 = (2.0f * g - 1.0f) * ig * ig;
+    for (;;) {
+        const float ua = uniform(r, k0, k1);
+        eps = fdiv(e0, 1.0f - ua * (1.0f - 2.0f * e0));
+        const float ub = uniform(r, k0, k1);
+        const float ie = hrcp(eps), io = hrcp(1.0f - eps);
+        const float br = c1 * c1 + ie * (ie - c2) + io * (io - c2);
+        if (ub * 2.25f <= eps * eps * br) break;
+    }
+    turns = uniform(r, k0, k1);
+}
+
+// bremsstrahlung photon energy: 1/k proposal on [W_cb, T], rejection by the
+// complete-screening spectrum
+GDPM_DEV float sample_brems(Rng& r, uint32_t k0, uint32_t k1, float tt, float wcb) {
+    const float lr = hlog2(tt) - hlog2(wcb);
+    const float it = hrcp(tt);
+    float kph;
+    for (;;) {
+        const float ua = uniform(r, k0, k1);
+        kph = wcb * hexp2(ua * lr);
+        const float ub = uniform(r, k0, k1);
+        const float yy = kph * it;
+        if (ub * (4.0f / 3.0f) <= 4.0f / 3.0f - 4.0f / 3.0f * yy + yy * yy) break;
+    }
+    return kph;
+}
+
+// isotropic direction of the first annihilation photon (cos, then azimuth)
+GDPM_DEV void sample_iso(Rng& r, uint32_t k0, uint32_t k1, float& du, float& dv, float& dw) {
+    const float ct = 2.0f * uniform(r, k0, k1) - 1.0f;
+    const float turns = uniform(r, k0, k1);
+    const float st = hsqrt((1.0f - ct) * (1.0f + ct));
+    du = st * cos_turns(turns);
+    dv = st * sin_turns(turns);
+    dw = ct;
+}
+
+// ---------------------------------------------------------------------------
+// secondaries of one event, pushed once per iteration with the wave converged
+// ---------------------------------------------------------------------------
+// charged: up to two; the second (a positron) shares the first one's direction
+struct PendCharged {
+    int n;
+    float e0, du, dv, dw;   // first particle and the common direction
+    float a0;               // first particle: annihilation energy if it is a positron
+    uint32_t role, flag0;   // first particle: role word, positron flag
+    float e1, a1;           // second particle (always the pair positron, role 1)
+};
+// photons: one (role word wb) or two back to back (roles wb, wb + 1)
+struct PendPhoton {
+    int n;
+    float e, u, v, w;
+    uint32_t wb;
+};
+
+GDPM_DEV void write_particle(Particle* buf, uint32_t mask, uint32_t slot, float x, float y, float z,
+                             float e, float u, float v, float w, uint32_t hlo, uint32_t hhi,
+                             uint32_t path, uint32_t vox, float a, uint32_t flags) {
+    float4* d = reinterpret_cast<float4*>(buf + (slot & mask));
+    d[0] = make_float4(x, y, z, e);
+    d[1] = make_float4(u, v, w, -1.0f);
+    d[2] = make_float4(__uint_as_float(hlo), __uint_as_float(hhi), __uint_as_float(path), 0.0f);
+    d[3] = make_float4(__uint_as_float(vox), a, __uint_as_float(flags), 0.0f);
+}
+
+GDPM_DEV void push_charged(PendCharged& q, PushState& ps, uint32_t head, Ctl* ctl, const RunDev& R,
+                           Particle* buf, float x, float y, float z, uint32_t vox, const Rng& rng,
+                           LaneTally& t) {
     const uint64_t b0 = ballot(q.n >= 1), b1 = ballot(q.n >= 2);
     const uint32_t n0 = (uint32_t)__popcll(b0), n = n0 + (uint32_t)__popcll(b1);
     if (n == 0) return;
-    const Reservation res = reserve(ps, &ctl->ring[ri], head, R.hard[ri], n, ctl);
+    const Reservation res = reserve(ps, &ctl->ring[1], head, R.hard[1], n, ctl);
     if (res.ok && q.n > 0) {
-        for (int k = 0; k < 2; ++k) {
-            if (k >= q.n) break;
-            const uint32_t j = k == 0 ? mbcnt(b0) : n0 + mbcnt(b1);
-            Particle p;
-            p.x = x; p.y = y; p.z = z;
-            p.e = k == 0 ? q.e[0] : q.e[1];
-            p.u = k == 0 ? q.u[0] : q.u[1];
-            p.v = k == 0 ? q.v[0] : q.v[1];
-            p.w = k == 0 ? q.w[0] : q.w[1];
-            p.nh = -1.0f;
-            p.hlo = rng.hlo;
-            p.hhi = rng.hhi;
-            p.path = spawn_path(rng, R.k0, R.k1, (int)(k == 0 ? q.word[0] : q.word[1]));
-            p.ctr = 0u;
-            p.vox = vox;
-            p.a = k == 0 ? q.a[0] : q.a[1];
-            p.flags = k == 0 ? q.flags[0] : q.flags[1];
-            p.pad = 0u;
-            store(buf, R.mask[ri], slot_of(res, j), p);
-        }
+        write_particle(buf, R.mask[1], slot_of(res, mbcnt(b0)), x, y, z, q.e0, q.du, q.dv, q.dw,
+                       rng.hlo, rng.hhi, spawn_path(rng, R.k0, R.k1, (int)q.role), vox, q.a0,
+                       q.flag0);
+        if (q.n > 1)
+            write_particle(buf, R.mask[1], slot_of(res, n0 + mbcnt(b1)), x, y, z, q.e1, q.du, q.dv,
+                           q.dw, rng.hlo, rng.hhi, spawn_path(rng, R.k0, R.k1, 1), vox, q.a1, 1u);
+        t.ev[EV_PUSHES] += (uint32_t)q.n;
+    }
+    q.n = 0;
+}
+
+GDPM_DEV void push_photons(PendPhoton& q, PushState& ps, uint32_t head, Ctl* ctl, const RunDev& R,
+                           Particle* buf, float x, float y, float z, const Rng& rng, LaneTally& t) {
+    const uint64_t b0 = ballot(q.n >= 1), b1 = ballot(q.n >= 2);
+    const uint32_t n0 = (uint32_t)__popcll(b0), n = n0 + (uint32_t)__popcll(b1);
+    if (n == 0) return;
+    const Reservation res = reserve(ps, &ctl->ring[0], head, R.hard[0], n, ctl);
+    if (res.ok && q.n > 0) {
+        write_particle(buf, R.mask[0], slot_of(res, mbcnt(b0)), x, y, z, q.e, q.u, q.v, q.w,
+                       rng.hlo, rng.hhi, spawn_path(rng, R.k0, R.k1, (int)q.wb), 0u, 0.0f, 0u);
+        if (q.n > 1)
+            write_particle(buf, R.mask[0], slot_of(res, n0 + mbcnt(b1)), x, y, z, q.e, -q.u, -q.v,
+                           -q.w, rng.hlo, rng.hhi, spawn_path(rng, R.k0, R.k1, (int)q.wb + 1), 0u,
+                           0.0f, 0u);
         t.ev[EV_PUSHES] += (uint32_t)q.n;
     }
     q.n = 0;
@@ -591,20 +730,70 @@ GDPM_DEV void claim_refill(ClaimState& cs, RingCtl* rc, uint32_t count, uint32_t
 }
 
 // ---------------------------------------------------------------------------
+// input of one iteration: refill empty lanes from the pass's queue or source
+// ---------------------------------------------------------------------------
+struct Refill {
+    bool ring;            // took a queue record (loaded into the lane)
+    bool source;          // took a new history `h`
+    unsigned long long h;
+};
+
+GDPM_DEV Refill refill(bool active, ClaimState& cs, RingCtl* rc, uint32_t begin, uint32_t count,
+                       uint32_t total, bool allow_src, unsigned long long src_base,
+                       const Particle* buf, uint32_t mask, Particle& p) {
+    Refill f{false, false, 0ull};
+    if (cs.done) return f;
+    const uint64_t need = ballot(!active);
+    if (!need) return f;
+    claim_refill(cs, rc, count, total, allow_src);
+    const uint32_t have = cs.end - cs.next;
+    const uint32_t rank = mbcnt(need);
+    const uint32_t take = min(have, (uint32_t)__popcll(need));
+    if (!active && rank < take) {
+        const uint32_t vi = cs.next + rank;
+        if (vi < count) {
+            p = load(buf, mask, begin + vi);
+            f.ring = p.e >= 0.0f;
+        } else {
+            f.source = true;
+            f.h = src_base + (vi - count);
+        }
+    }
+    cs.next += take;
+    return f;
+}
+
+// ---------------------------------------------------------------------------
 // photon pass: Woodcock tracking (section 2.1), one flight per iteration
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, SourceDev S, RunDev R,
-                                                int with_source) {
+// Interpolation tables are staged in LDS (kLds) when they fit; one workgroup
+// per CU shares them.
+extern __shared__ float4 lds_tables[];
+
+template <bool kLds>
+__global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, SourceDev S, RunDev R,
+                                                 int with_source) {
+    const float4* ptab = T.phot;
+    const float* mtab = T.mumax;
+    if constexpr (kLds) {
+        const int np = T.n_mat * T.pg_n;
+        for (int i = threadIdx.x; i < np; i += blockDim.x) lds_tables[i] = T.phot[i];
+        float* lm = reinterpret_cast<float*>(lds_tables + np);
+        for (int i = threadIdx.x; i < T.pg_n; i += blockDim.x) lm[i] = T.mumax[i];
+        __syncthreads();
+        ptab = lds_tables;
+        mtab = lm;
+    }
     RingCtl* rc = &ctl->ring[0];
     const uint32_t begin = rc->begin, count = rc->count;
     const uint32_t total = count + (with_source ? rc->src_avail : 0u);
     const unsigned long long src_base = rc->src_base;
-    const uint32_t cur_g = ctl->ring[0].cur, cur_e = ctl->ring[1].cur;
-    Particle* bufg = R.buf[0][cur_g];
-    Particle* bufe = R.buf[1][cur_e];
+    Particle* bufg = R.buf[0][ctl->ring[0].cur];
+    Particle* bufe = R.buf[1][ctl->ring[1].cur];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
     const uint32_t k0 = R.k0, k1 = R.k1;
     const bool kerma = (R.flags & 64u) != 0u;
+    const float ecut_e = R.ecut_e, ecut_g = R.ecut_g;
 
     PushState pg{0u, 0u}, pe{0u, 0u};
     ClaimState cs{0u, 0u, false};
@@ -613,69 +802,54 @@ __global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, Sour
 
     bool active = false;
     float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
-    Rng rng{0, 0, 0, 0, 0, 0, 0, 0};
+    Rng rng;
+    rng_start(rng, 0u, 0u, 0u, 0u);
     bool allow_src = true;
     int it = 0;
 
     for (;;) {
         if ((it++ % kCheckPeriod) == 0) {
-            // queue fill: new source histories start only while the electron
-            // queue is below its soft limit; stop everything after an overflow
-            const uint32_t tail_e = load_agent(&ctl->ring[1].tail);
-            allow_src = (tail_e - head_e) < R.soft[1];
+            // new source histories start only while the electron queue is below
+            // its soft limit; everything stops after an overflow
+            allow_src = (load_agent(&ctl->ring[1].tail) - head_e) < R.soft[1];
             if (load_agent(&ctl->overflow)) break;
         }
-        // refill lanes
-        if (!cs.done) {
-            const uint64_t need = ballot(!active);
-            if (need) {
-                claim_refill(cs, rc, count, total, allow_src);
-                const uint32_t have = cs.end - cs.next;
-                const uint32_t rank = mbcnt(need);
-                const uint32_t take = min(have, (uint32_t)__popcll(need));
-                if (!active && rank < take) {
-                    const uint32_t vi = cs.next + rank;
-                    if (vi < count) {
-                        const Particle p = load(bufg, R.mask[0], begin + vi);
-                        if (p.e >= 0.0f) {
-                            x = p.x; y = p.y; z = p.z; e = p.e;
-                            u = p.u; v = p.v; w = p.w;
-                            rng.hlo = p.hlo; rng.hhi = p.hhi; rng.path = p.path; rng.ctr = p.ctr;
-                            if (rng.ctr & 3u) rng_block(rng, k0, k1);
-                            active = true;
-                        }
-                    } else {
-                        const unsigned long long h = src_base + (vi - count);
-                        rng.hlo = (uint32_t)h;
-                        rng.hhi = (uint32_t)(h >> 32);
-                        rng.path = 0u;
-                        rng.ctr = 0u;
-                        const Primary pr = make_primary(S, G, rng, k0, k1);
-                        tl.e_in += (double)pr.e;
-                        if (pr.in) {
-                            x = pr.x; y = pr.y; z = pr.z; u = pr.u; v = pr.v; w = pr.w; e = pr.e;
-                            active = true;
-                        } else {
-                            tl.e_esc += (double)pr.e;
-                            tl.h_esc += (double)pr.e;
-                            history_flush(tl, R, rng.hlo, rng.hhi);
-                        }
-                    }
-                }
-                cs.next += take;
-            }
+        Particle p;
+        const Refill f = refill(active, cs, rc, begin, count, total, allow_src, src_base, bufg,
+                                R.mask[0], p);
+        if (f.ring) {
+            x = p.x; y = p.y; z = p.z; e = p.e;
+            u = p.u; v = p.v; w = p.w;
+            rng_start(rng, p.hlo, p.hhi, p.path, p.ctr);
+            active = true;
+        } else if (f.source) {
+            rng_start(rng, (uint32_t)f.h, (uint32_t)(f.h >> 32), 0u, 0u);
         }
-        if (!ballot(active)) {
+        if (!ballot(active || f.source)) {
             if (cs.done) break;
             continue;
         }
+        rng_topup(rng, k0, k1);
+        if (f.source) {
+            const Primary pr = make_primary(S, G, rng, k0, k1);
+            tl.e_in += (double)pr.e;
+            if (pr.in) {
+                x = pr.x; y = pr.y; z = pr.z; u = pr.u; v = pr.v; w = pr.w; e = pr.e;
+                active = true;
+            } else {
+                tl.e_esc += (double)pr.e;
+                tl.h_esc += (double)pr.e;
+                history_flush(tl, R, rng.hlo, rng.hhi);
+            }
+        }
 
-        Pending qe, qg;
+        PendCharged qe;
+        PendPhoton qg;
         qe.n = 0;
         qg.n = 0;
         int ix = 0, iy = 0, iz = 0;
         if (active) {
-            if (e < R.ecut_g) {
+            if (e < ecut_g) {
                 const int vv = voxel_of(G, x, y, z, ix, iy, iz);
                 deposit(tl, R, vv, e);
                 tally_flush(tl, R);
@@ -684,8 +858,8 @@ __global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, Sour
                 int gi;
                 float gt;
                 grid(hlog2(e), T.pg_lo, T.pg_inv, T.pg_n, gi, gt);
-                const float mumax = lerp1(T.mumax, gi, gt);
-                const float s = neg_ln(uniform(rng, k0, k1)) / mumax;
+                const float mumax = lerp1(mtab, gi, gt);
+                const float s = neg_ln(uniform(rng, k0, k1)) * hrcp(mumax);
                 tl.ev[EV_FLIGHTS]++;
                 x = fmaf(s, u, x);
                 y = fmaf(s, v, y);
@@ -699,26 +873,13 @@ __global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, Sour
                     const uint2 vx = G.vox[vv];
                     const float rho = __uint_as_float(vx.x);
                     const int m = (int)vx.y;
-                    const float4 mu = lerp4(T.phot + m * T.pg_n, gi, gt);
+                    const float4 mu = lerp4(ptab + m * T.pg_n, gi, gt);
                     if (uniform(rng, k0, k1) * mumax < rho * mu.w) {
                         tl.ev[EV_REAL]++;
                         const float r = uniform(rng, k0, k1) * mu.w;
                         if (r < mu.x) {
-                            // Compton: Klein-Nishina by Butcher-Messel composition/rejection
-                            const float k = e * (1.0f / kMec2f);
-                            const float e0 = 1.0f / (1.0f + 2.0f * k);
-                            const float a1 = kLn2f * hlog2(1.0f + 2.0f * k);
-                            const float a2 = 0.5f * (1.0f - e0 * e0);
-                            float eps, t;
-                            for (;;) {
-                                const float ua = uniform(rng, k0, k1), ub = uniform(rng, k0, k1),
-                                            uc = uniform(rng, k0, k1);
-                                if (ua * (a1 + a2) < a1) eps = hexp2(-a1 * ub * (1.0f / kLn2f));
-                                else eps = hsqrt(e0 * e0 + (1.0f - e0 * e0) * ub);
-                                t = (1.0f - eps) / (k * eps);
-                                if (uc <= 1.0f - eps * t * (2.0f - t) / (1.0f + eps * eps)) break;
-                            }
-                            const float turns = uniform(rng, k0, k1);
+                            float eps, t, turns;
+                            sample_compton(rng, k0, k1, e, eps, t, turns);
                             const float u0 = u, v0 = v, w0 = w;
                             rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
                             // exact split of E into E' and T (the unit is built without
@@ -732,24 +893,33 @@ __global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, Sour
                                 te = e - ec;
                                 e1 = e - te;
                             }
-                            float eu = e * u0 - e1 * u, ev = e * v0 - e1 * v, ew = e * w0 - e1 * w;
-                            const float nn = eu * eu + ev * ev + ew * ew;
-                            if (nn > 0.0f) {
-                                const float in = hrsq(nn);
-                                eu *= in; ev *= in; ew *= in;
+                            if (kerma || te <= ecut_e) {
+                                deposit(tl, R, vv, te);
                             } else {
-                                eu = u0; ev = v0; ew = w0;
+                                // electron along the momentum transfer E d0 - E' d
+                                float eu = e * u0 - e1 * u, ev = e * v0 - e1 * v, ew = e * w0 - e1 * w;
+                                const float nn = eu * eu + ev * ev + ew * ew;
+                                if (nn > 0.0f) {
+                                    const float in = hrsq(nn);
+                                    eu *= in; ev *= in; ew *= in;
+                                } else {
+                                    eu = u0; ev = v0; ew = w0;
+                                }
+                                qe.n = 1; qe.e0 = te; qe.du = eu; qe.dv = ev; qe.dw = ew;
+                                qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
                             }
-                            if (kerma || te <= R.ecut_e) deposit(tl, R, vv, te);
-                            else pend(qe, te, eu, ev, ew, 0u);
                             e = e1;
                         } else if (r < mu.x + mu.y) {
                             // photoelectric: the electron takes E along the photon
-                            if (kerma || e <= R.ecut_e) deposit(tl, R, vv, e);
-                            else pend(qe, e, u, v, w, 0u);
+                            if (kerma || e <= ecut_e) {
+                                deposit(tl, R, vv, e);
+                            } else {
+                                qe.n = 1; qe.e0 = e; qe.du = u; qe.dv = v; qe.dw = w;
+                                qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
+                            }
                             active = false;
                         } else {
-                            // pair: uniform split of E - 2 mc^2; positron keeps a = E - K
+                            // pair: uniform split of E - 2 mc^2; the positron keeps a = E - K
                             const float kk = e - kTwoMec2f, aa = e - kk;
                             const float tc = uniform(rng, k0, k1) * kk;
                             float tm, tp;
@@ -760,22 +930,23 @@ __global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, Sour
                                 tp = kk - tc;
                                 tm = kk - tp;
                             }
-                            const bool pos_local = kerma || tp <= R.ecut_e;
-                            float ct = 0.0f, turns = 0.0f;
-                            if (pos_local) {
-                                ct = 2.0f * uniform(rng, k0, k1) - 1.0f;
-                                turns = uniform(rng, k0, k1);
-                            }
-                            if (kerma || tm <= R.ecut_e) deposit(tl, R, vv, tm);
-                            else pend(qe, tm, u, v, w, 0u);
-                            if (pos_local) {
+                            const bool e_local = kerma || tm <= ecut_e;
+                            const bool p_local = kerma || tp <= ecut_e;
+                            if (p_local) {
+                                float du, dv, dw;
+                                sample_iso(rng, k0, k1, du, dv, dw);
                                 deposit(tl, R, vv, tp);
-                                const float st = hsqrt((1.0f - ct) * (1.0f + ct));
-                                const float du = st * cos_turns(turns), dv = st * sin_turns(turns);
-                                pend(qg, 0.5f * aa, du, dv, ct, 2u);
-                                pend(qg, 0.5f * aa, -du, -dv, -ct, 3u);
-                            } else {
-                                pend(qe, tp, u, v, w, 1u, aa, 1u);
+                                qg.n = 2; qg.e = 0.5f * aa; qg.u = du; qg.v = dv; qg.w = dw; qg.wb = 2u;
+                            }
+                            if (e_local) deposit(tl, R, vv, tm);
+                            qe.du = u; qe.dv = v; qe.dw = w;
+                            if (!e_local) {
+                                qe.n = 1; qe.e0 = tm; qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
+                                if (!p_local) {
+                                    qe.n = 2; qe.e1 = tp; qe.a1 = aa;
+                                }
+                            } else if (!p_local) {
+                                qe.n = 1; qe.e0 = tp; qe.a0 = aa; qe.role = 1u; qe.flag0 = 1u;
                             }
                             active = false;
                         }
@@ -786,8 +957,8 @@ __global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, Sour
             if (!active) history_flush(tl, R, rng.hlo, rng.hhi);
         }
         // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
-        push_pending(qe, 1, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
-        push_pending(qg, 0, pg, head_g, ctl, R, bufg, x, y, z, 0u, rng, tl);
+        push_charged(qe, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
+        push_photons(qg, pg, head_g, ctl, R, bufg, x, y, z, rng, tl);
     }
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
@@ -798,15 +969,29 @@ __global__ void __launch_bounds__(256) k_photon(Ctl* ctl, Tables T, Geom G, Sour
 // electron pass: class-II condensed history with a random hinge, one step per
 // iteration (section 2.1)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_electron(Ctl* ctl, Tables T, Geom G, SourceDev S,
-                                                  RunDev R, int with_source) {
+template <bool kLds>
+__global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, SourceDev S,
+                                                   RunDev R, int with_source) {
+    const float4* etab = T.elec;
+    const float* rtab = T.rinv;
+    const float* rscale = T.rinv_scale;
+    if constexpr (kLds) {
+        const int ne = T.n_mat * T.eg_n, nr = T.n_mat * T.nr;
+        for (int i = threadIdx.x; i < ne; i += blockDim.x) lds_tables[i] = T.elec[i];
+        float* lr = reinterpret_cast<float*>(lds_tables + ne);
+        for (int i = threadIdx.x; i < nr; i += blockDim.x) lr[i] = T.rinv[i];
+        for (int i = threadIdx.x; i < T.n_mat; i += blockDim.x) lr[nr + i] = T.rinv_scale[i];
+        __syncthreads();
+        etab = lds_tables;
+        rtab = lr;
+        rscale = lr + nr;
+    }
     RingCtl* rc = &ctl->ring[1];
     const uint32_t begin = rc->begin, count = rc->count;
     const uint32_t total = count + (with_source ? rc->src_avail : 0u);
     const unsigned long long src_base = rc->src_base;
-    const uint32_t cur_g = ctl->ring[0].cur, cur_e = ctl->ring[1].cur;
-    Particle* bufg = R.buf[0][cur_g];
-    Particle* bufe = R.buf[1][cur_e];
+    Particle* bufg = R.buf[0][ctl->ring[0].cur];
+    Particle* bufe = R.buf[1][ctl->ring[1].cur];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
     const uint32_t k0 = R.k0, k1 = R.k1;
     const float ecut = R.ecut_e;
@@ -820,72 +1005,65 @@ __global__ void __launch_bounds__(256) k_electron(Ctl* ctl, Tables T, Geom G, So
     bool active = false;
     float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0, nh = -1.0f, aa = 0.0f;
     int ix = 0, iy = 0, iz = 0;
+    float rho = 1.0f;   // density and material of the current voxel, reloaded
+    int mat = 0;        // when the particle enters a voxel
     bool positron = false;
-    Rng rng{0, 0, 0, 0, 0, 0, 0, 0};
+    Rng rng;
+    rng_start(rng, 0u, 0u, 0u, 0u);
     bool allow_src = true;
     int it = 0;
 
     for (;;) {
         if ((it++ % kCheckPeriod) == 0) {
-            const uint32_t tail_g = load_agent(&ctl->ring[0].tail);
-            const uint32_t tail_e = load_agent(&ctl->ring[1].tail);
-            allow_src = (tail_g - head_g) < R.soft[0] && (tail_e - head_e) < R.soft[1];
+            allow_src = (load_agent(&ctl->ring[0].tail) - head_g) < R.soft[0] &&
+                        (load_agent(&ctl->ring[1].tail) - head_e) < R.soft[1];
             if (load_agent(&ctl->overflow)) break;
         }
-        if (!cs.done) {
-            const uint64_t need = ballot(!active);
-            if (need) {
-                claim_refill(cs, rc, count, total, allow_src);
-                const uint32_t have = cs.end - cs.next;
-                const uint32_t rank = mbcnt(need);
-                const uint32_t take = min(have, (uint32_t)__popcll(need));
-                if (!active && rank < take) {
-                    const uint32_t vi = cs.next + rank;
-                    if (vi < count) {
-                        const Particle p = load(bufe, R.mask[1], begin + vi);
-                        if (p.e >= 0.0f) {
-                            x = p.x; y = p.y; z = p.z; e = p.e;
-                            u = p.u; v = p.v; w = p.w; nh = p.nh;
-                            ix = (int)(p.vox & 2047u);
-                            iy = (int)((p.vox >> 11) & 2047u);
-                            iz = (int)(p.vox >> 22);
-                            aa = p.a;
-                            positron = (p.flags & 1u) != 0u;
-                            rng.hlo = p.hlo; rng.hhi = p.hhi; rng.path = p.path; rng.ctr = p.ctr;
-                            if (rng.ctr & 3u) rng_block(rng, k0, k1);
-                            active = true;
-                        }
-                    } else {
-                        const unsigned long long h = src_base + (vi - count);
-                        rng.hlo = (uint32_t)h;
-                        rng.hhi = (uint32_t)(h >> 32);
-                        rng.path = 0u;
-                        rng.ctr = 0u;
-                        const Primary pr = make_primary(S, G, rng, k0, k1);
-                        tl.e_in += (double)pr.e;
-                        if (pr.in) {
-                            x = pr.x; y = pr.y; z = pr.z; u = pr.u; v = pr.v; w = pr.w; e = pr.e;
-                            voxel_of(G, x, y, z, ix, iy, iz);
-                            nh = -1.0f;
-                            aa = 0.0f;
-                            positron = false;
-                            active = true;
-                        } else {
-                            tl.e_esc += (double)pr.e;
-                            tl.h_esc += (double)pr.e;
-                            history_flush(tl, R, rng.hlo, rng.hhi);
-                        }
-                    }
-                }
-                cs.next += take;
-            }
+        Particle p;
+        const Refill f = refill(active, cs, rc, begin, count, total, allow_src, src_base, bufe,
+                                R.mask[1], p);
+        if (f.ring) {
+            x = p.x; y = p.y; z = p.z; e = p.e;
+            u = p.u; v = p.v; w = p.w; nh = p.nh;
+            ix = (int)(p.vox & 2047u);
+            iy = (int)((p.vox >> 11) & 2047u);
+            iz = (int)(p.vox >> 22);
+            aa = p.a;
+            positron = (p.flags & 1u) != 0u;
+            rng_start(rng, p.hlo, p.hhi, p.path, p.ctr);
+            const uint2 vx = G.vox[ix + G.nx * (iy + G.ny * iz)];
+            rho = __uint_as_float(vx.x);
+            mat = (int)vx.y;
+            active = true;
+        } else if (f.source) {
+            rng_start(rng, (uint32_t)f.h, (uint32_t)(f.h >> 32), 0u, 0u);
         }
-        if (!ballot(active)) {
+        if (!ballot(active || f.source)) {
             if (cs.done) break;
             continue;
         }
+        rng_topup(rng, k0, k1);
+        if (f.source) {
+            const Primary pr = make_primary(S, G, rng, k0, k1);
+            tl.e_in += (double)pr.e;
+            if (pr.in) {
+                x = pr.x; y = pr.y; z = pr.z; u = pr.u; v = pr.v; w = pr.w; e = pr.e;
+                const uint2 vx = G.vox[voxel_of(G, x, y, z, ix, iy, iz)];
+                rho = __uint_as_float(vx.x);
+                mat = (int)vx.y;
+                nh = -1.0f;
+                aa = 0.0f;
+                positron = false;
+                active = true;
+            } else {
+                tl.e_esc += (double)pr.e;
+                tl.h_esc += (double)pr.e;
+                history_flush(tl, R, rng.hlo, rng.hhi);
+            }
+        }
 
-        Pending qe, qg;
+        PendCharged qe;
+        PendPhoton qg;
         qe.n = 0;
         qg.n = 0;
         if (active) {
@@ -894,52 +1072,48 @@ __global__ void __launch_bounds__(256) k_electron(Ctl* ctl, Tables T, Geom G, So
                 // absorption; a positron annihilates at rest into two photons
                 deposit(tl, R, vv, e);
                 if (positron) {
-                    const float ct = 2.0f * uniform(rng, k0, k1) - 1.0f;
-                    const float turns = uniform(rng, k0, k1);
-                    const float st = hsqrt((1.0f - ct) * (1.0f + ct));
-                    const float du = st * cos_turns(turns), dv = st * sin_turns(turns);
-                    pend(qg, 0.5f * aa, du, dv, ct, 0u);
-                    pend(qg, 0.5f * aa, -du, -dv, -ct, 1u);
+                    float du, dv, dw;
+                    sample_iso(rng, k0, k1, du, dv, dw);
+                    qg.n = 2; qg.e = 0.5f * aa; qg.u = du; qg.v = dv; qg.w = dw; qg.wb = 0u;
                 }
                 active = false;
             } else {
-                const uint2 vx = G.vox[vv];
-                const float rho = __uint_as_float(vx.x);
-                const int m = (int)vx.y;
+                const float irho = hrcp(rho);
+                const int m = mat;
                 if (nh < 0.0f) nh = neg_ln(uniform(rng, k0, k1));
                 tl.ev[EV_ESTEPS]++;
                 const float t0 = e;
-                const float4 q0 = elec_at(T, m, t0);
+                const float4 q0 = elec_at(T, etab, m, t0);
                 const float mus = rho * q0.y;
-                const float sh = mus > 0.0f ? nh / mus : 3.0e38f;
+                const float sh = mus > 0.0f ? nh * hrcp(mus) : 3.0e38f;
                 const float tfl = fmaxf(0.75f * t0, ecut);
-                const float rfl = tfl > ecut ? elec_at(T, m, tfl).x : 0.0f;
-                const float se = (q0.x - rfl) / rho;
+                const float rfl = tfl > ecut ? elec_at(T, etab, m, tfl).x : 0.0f;
+                const float se = (q0.x - rfl) * irho;
                 const bool hard = sh < se;
                 const float s = hard ? sh : se;
                 const float xi = uniform(rng, k0, k1);
                 const float s1 = xi * s, s2 = s - s1;
-                const float tend = hard ? fminf(fmaxf(range_inv(T, m, q0.x - rho * s), tfl), t0) : tfl;
+                const float tend = hard ? fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * s), tfl), t0) : tfl;
                 bool crossed = false;
                 int ax;
                 float db = face_dist(G, x, y, z, u, v, w, ix, iy, iz, ax);
                 float travelled = 0.0f;
                 if (db < s1) {
                     x = fmaf(db, u, x); y = fmaf(db, v, y); z = fmaf(db, w, z);
-                    const float t1 = fminf(fmaxf(range_inv(T, m, q0.x - rho * db), tend), e);
+                    const float t1 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * db), tend), e);
                     deposit(tl, R, vv, e - t1);
                     e = t1;
                     travelled = db;
                     crossed = true;
                 } else {
                     x = fmaf(s1, u, x); y = fmaf(s1, v, y); z = fmaf(s1, w, z);
-                    const float t1 = fminf(fmaxf(range_inv(T, m, q0.x - rho * s1), tend), e);
+                    const float t1 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * s1), tend), e);
                     deposit(tl, R, vv, e - t1);
                     e = t1;
                     // hinge: modified-Wentzel deflection for the whole step
                     if (!no_ms) {
                         const float tmid = 0.5f * (t0 + tend);
-                        const float tt = s * rho * elec_at(T, m, tmid).w;
+                        const float tt = s * rho * elec_at(T, etab, m, tmid).w;
                         const float mu = mw_mu(T, tt, uniform(rng, k0, k1));
                         const float turns = uniform(rng, k0, k1);
                         rotate(u, v, w, 1.0f - 2.0f * mu, 2.0f * hsqrt(mu * (1.0f - mu)), turns);
@@ -947,7 +1121,7 @@ __global__ void __launch_bounds__(256) k_electron(Ctl* ctl, Tables T, Geom G, So
                     db = face_dist(G, x, y, z, u, v, w, ix, iy, iz, ax);
                     if (db < s2) {
                         x = fmaf(db, u, x); y = fmaf(db, v, y); z = fmaf(db, w, z);
-                        const float t2 = fminf(fmaxf(range_inv(T, m, q0.x - rho * (s1 + db)), tend), e);
+                        const float t2 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * (s1 + db)), tend), e);
                         deposit(tl, R, vv, e - t2);
                         e = t2;
                         travelled = s1 + db;
@@ -980,49 +1154,41 @@ __global__ void __launch_bounds__(256) k_electron(Ctl* ctl, Tables T, Geom G, So
                         tl.e_esc += out;
                         tl.h_esc += out;
                         active = false;
+                    } else {
+                        // the next voxel's density and material, needed by the next step
+                        const uint2 vx = G.vox[ix + G.nx * (iy + G.ny * iz)];
+                        rho = __uint_as_float(vx.x);
+                        mat = (int)vx.y;
                     }
                 } else if (hard) {
                     // delta scattering against the step-start majorant (mu_h grows with T)
                     tl.ev[EV_HARD_CAND]++;
-                    const float4 q1 = elec_at(T, m, tend);
+                    const float4 q1 = elec_at(T, etab, m, tend);
                     if (uniform(rng, k0, k1) * q0.y < q1.y) {
                         tl.ev[EV_HARD]++;
                         if (uniform(rng, k0, k1) * q1.y < q1.z) {
-                            // Moller: proposal 1/eps^2 on [eps0, 1/2], rejection eps^2 B / 2.25
-                            const float tt = e, g = 1.0f + tt * (1.0f / kMec2f), e0 = ecut / tt;
-                            const float c1 = (g - 1.0f) / g, c2 = (2.0f * g - 1.0f) / (g * g);
-                            float eps;
-                            for (;;) {
-                                const float ua = uniform(rng, k0, k1);
-                                eps = e0 / (1.0f - ua * (1.0f - 2.0f * e0));
-                                const float ub = uniform(rng, k0, k1);
-                                const float ie = 1.0f / eps, io = 1.0f / (1.0f - eps);
-                                const float br = c1 * c1 + ie * (ie - c2) + io * (io - c2);
-                                if (ub * 2.25f <= eps * eps * br) break;
-                            }
-                            const float turns = uniform(rng, k0, k1);
+                            float eps, turns;
+                            const float tt = e;
+                            sample_moller(rng, k0, k1, tt, ecut, eps, turns);
                             const float tp = tt - eps * tt;   // >= T/2
                             const float wd = tt - tp;         // exact
                             const float tm2 = tt + kTwoMec2f;
-                            const float cd = hsqrt(wd * tm2 / (tt * (wd + kTwoMec2f)));
-                            const float cpr = hsqrt(tp * tm2 / (tt * (tp + kTwoMec2f)));
+                            const float itt = hrcp(tt);
+                            const float cd = hsqrt(wd * tm2 * itt * hrcp(wd + kTwoMec2f));
+                            const float cpr = hsqrt(tp * tm2 * itt * hrcp(tp + kTwoMec2f));
                             float du = u, dv = v, dw = w;
                             rotate(du, dv, dw, cd, hsqrt(fmaxf(0.0f, 1.0f - cd * cd)), turns);
                             rotate(u, v, w, cpr, hsqrt(fmaxf(0.0f, 1.0f - cpr * cpr)), turns + 0.5f);
-                            if (wd <= ecut) deposit(tl, R, vv, wd);
-                            else pend(qe, wd, du, dv, dw, 0u);
+                            if (wd <= ecut) {
+                                deposit(tl, R, vv, wd);
+                            } else {
+                                qe.n = 1; qe.e0 = wd; qe.du = du; qe.dv = dv; qe.dw = dw;
+                                qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
+                            }
                             e = tp;
                         } else {
-                            // bremsstrahlung: proposal 1/k on [W_cb, T], rejection by the spectrum
-                            const float tt = e, wcb = R.ecut_g, lr = hlog2(tt / wcb);
-                            float kph;
-                            for (;;) {
-                                const float ua = uniform(rng, k0, k1);
-                                kph = wcb * hexp2(ua * lr);
-                                const float ub = uniform(rng, k0, k1);
-                                const float yy = kph / tt;
-                                if (ub * (4.0f / 3.0f) <= 4.0f / 3.0f - 4.0f / 3.0f * yy + yy * yy) break;
-                            }
+                            const float tt = e;
+                            const float kph = sample_brems(rng, k0, k1, tt, R.ecut_g);
                             float kp, el;
                             if (2.0f * kph >= tt) {
                                 kp = kph;
@@ -1031,7 +1197,7 @@ __global__ void __launch_bounds__(256) k_electron(Ctl* ctl, Tables T, Geom G, So
                                 el = tt - kph;
                                 kp = tt - el;
                             }
-                            pend(qg, kp, u, v, w, 0u);
+                            qg.n = 1; qg.e = kp; qg.u = u; qg.v = v; qg.w = w; qg.wb = 0u;
                             e = el;
                         }
                     }
@@ -1045,14 +1211,13 @@ __global__ void __launch_bounds__(256) k_electron(Ctl* ctl, Tables T, Geom G, So
                 history_flush(tl, R, rng.hlo, rng.hhi);
             }
         }
-        push_pending(qe, 1, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
-        push_pending(qg, 0, pg, head_g, ctl, R, bufg, x, y, z, 0u, rng, tl);
+        push_charged(qe, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
+        push_photons(qg, pg, head_g, ctl, R, bufg, x, y, z, rng, tl);
     }
     // the pass was stopped by an overflow: particles still held are dropped
     // (the run reports GDPM_E_OVERFLOW and its outputs are not valid)
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
-    if (active) tally_flush(tl, R);
     tally_finish(tl, R, ctl);
 }
 
@@ -1226,45 +1391,23 @@ __global__ void k_test_sample(Tables T, int which, float e, float p1, float p2, 
                               uint32_t k1, int n, float* out1, float* out2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    Rng r{(uint32_t)i, 0u, 0u, 0u, 0, 0, 0, 0};
+    Rng r;
+    rng_start(r, (uint32_t)i, 0u, 0u, 0u);
+    rng_topup(r, k0, k1);
     float a = 0.0f, b = 0.0f;
     if (which == 0) {
-        const float k = e / kMec2f, e0 = 1.0f / (1.0f + 2.0f * k);
-        const float a1 = kLn2f * hlog2(1.0f + 2.0f * k), a2 = 0.5f * (1.0f - e0 * e0);
-        float eps, t;
-        for (;;) {
-            const float ua = uniform(r, k0, k1), ub = uniform(r, k0, k1), uc = uniform(r, k0, k1);
-            if (ua * (a1 + a2) < a1) eps = hexp2(-a1 * ub * (1.0f / kLn2f));
-            else eps = hsqrt(e0 * e0 + (1.0f - e0 * e0) * ub);
-            t = (1.0f - eps) / (k * eps);
-            if (uc <= 1.0f - eps * t * (2.0f - t) / (1.0f + eps * eps)) break;
-        }
+        float eps, t, turns;
+        sample_compton(r, k0, k1, e, eps, t, turns);
         a = eps;
         b = 1.0f - t;
     } else if (which == 1) {
-        const float tt = e, g = 1.0f + tt / kMec2f, e0 = p1 / tt;
-        const float c1 = (g - 1.0f) / g, c2 = (2.0f * g - 1.0f) / (g * g);
-        float eps;
-        for (;;) {
-            const float ua = uniform(r, k0, k1);
-            eps = e0 / (1.0f - ua * (1.0f - 2.0f * e0));
-            const float ub = uniform(r, k0, k1);
-            const float ie = 1.0f / eps, io = 1.0f / (1.0f - eps);
-            if (ub * 2.25f <= eps * eps * (c1 * c1 + ie * (ie - c2) + io * (io - c2))) break;
-        }
-        const float tp = tt - eps * tt, wd = tt - tp;
+        float eps, turns;
+        sample_moller(r, k0, k1, e, p1, eps, turns);
+        const float tt = e, tp = tt - eps * tt, wd = tt - tp;
         a = wd / tt;
         b = hsqrt(tp * (tt + kTwoMec2f) / (tt * (tp + kTwoMec2f)));
     } else if (which == 2) {
-        const float tt = e, wcb = p1, lr = hlog2(tt / wcb);
-        float kph;
-        for (;;) {
-            const float ua = uniform(r, k0, k1);
-            kph = wcb * hexp2(ua * lr);
-            const float ub = uniform(r, k0, k1), yy = kph / tt;
-            if (ub * (4.0f / 3.0f) <= 4.0f / 3.0f - 4.0f / 3.0f * yy + yy * yy) break;
-        }
-        a = kph;
+        a = sample_brems(r, k0, k1, e, p1);
     } else if (which == 3) {
         a = mw_mu(T, e, uniform(r, k0, k1));
     } else if (which == 4) {
@@ -1278,11 +1421,10 @@ __global__ void k_test_sample(Tables T, int which, float e, float p1, float p2, 
         a = w;
         b = u * u + v * v + w * w;
     } else if (which == 5) {
-        const float ct = 2.0f * uniform(r, k0, k1) - 1.0f, turns = uniform(r, k0, k1);
-        const float st = hsqrt((1.0f - ct) * (1.0f + ct));
-        const float du = st * cos_turns(turns), dv = st * sin_turns(turns);
-        a = ct;
-        b = -(du * du + dv * dv + ct * ct);
+        float du, dv, dw;
+        sample_iso(r, k0, k1, du, dv, dw);
+        a = dw;
+        b = -(du * du + dv * dv + dw * dw);
     }
     out1[i] = a;
     if (out2) out2[i] = b;
@@ -1293,7 +1435,9 @@ __global__ void k_test_source(SourceDev S, Geom G, uint32_t k0, uint32_t k1,
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const unsigned long long h = hist0 + i;
-    Rng r{(uint32_t)h, (uint32_t)(h >> 32), 0u, 0u, 0, 0, 0, 0};
+    Rng r;
+    rng_start(r, (uint32_t)h, (uint32_t)(h >> 32), 0u, 0u);
+    rng_topup(r, k0, k1);
     const Primary p = make_primary(S, G, r, k0, k1);
     float* o = out + 8 * (size_t)i;
     o[0] = p.e;
@@ -1334,12 +1478,40 @@ hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, st, ctl, ri);
     return hipGetLastError();
 }
-hipError_t launch_transport(hipStream_t st, int ri, int blocks, Ctl* ctl, const Tables& T,
-                            const Geom& G, const SourceDev& S, const RunDev& R, int with_source) {
-    if (ri == 0)
-        hipLaunchKernelGGL(k_photon, dim3(blocks), dim3(256), 0, st, ctl, T, G, S, R, with_source);
-    else
-        hipLaunchKernelGGL(k_electron, dim3(blocks), dim3(256), 0, st, ctl, T, G, S, R, with_source);
+// LDS bytes the table staging of a pass needs
+size_t transport_lds_bytes(int ri, const Tables& T) {
+    if (ri == 0) return (size_t)T.n_mat * T.pg_n * sizeof(float4) + (size_t)T.pg_n * sizeof(float);
+    return (size_t)T.n_mat * T.eg_n * sizeof(float4) + ((size_t)T.n_mat * T.nr + T.n_mat) * sizeof(float);
+}
+
+// allow the staged kernels to use `bytes` of dynamic LDS
+hipError_t transport_lds_optin(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_photon<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_electron<true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, Ctl* ctl,
+                            const Tables& T, const Geom& G, const SourceDev& S, const RunDev& R,
+                            int with_source) {
+    const size_t bytes = lds ? transport_lds_bytes(ri, T) : 0;
+    if (ri == 0) {
+        if (lds)
+            hipLaunchKernelGGL(k_photon<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, G, S,
+                               R, with_source);
+        else
+            hipLaunchKernelGGL(k_photon<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, G, S, R,
+                               with_source);
+    } else {
+        if (lds)
+            hipLaunchKernelGGL(k_electron<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, G,
+                               S, R, with_source);
+        else
+            hipLaunchKernelGGL(k_electron<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, G, S,
+                               R, with_source);
+    }
     return hipGetLastError();
 }
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
