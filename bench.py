@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--opts", default=None, help="context options (JSON)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this many MiB before the "
+                         "timed jobs (a reference kernel of known traffic for hardware counters)")
     ap.add_argument("--min-density", type=float, default=0.1,
                     help="voxels below this density (the air around the patient) are left out "
                          "of D_max and of the uncertainty statistic")
@@ -101,6 +104,17 @@ def main():
         # gdpm_run is blocking: it returns after the device work of the job is complete
         return ctx.run(ph, src, seed=seed, n_hist=args.n0, target_unc=args.target,
                        stat_min_density=args.min_density, want_dose=False)
+
+    if args.copy_mib:
+        import torch
+        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"reference copy: {args.copy_mib} MiB read, {args.copy_mib} MiB written")
+        del a, b
 
     n0 = args.n0
     for i in range(args.warmup):

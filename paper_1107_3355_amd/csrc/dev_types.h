@@ -7,8 +7,8 @@ namespace gdpm {
 
 constexpr int kMaxMaterials = 8;
 constexpr uint32_t kPushChunk = 256;    // ring slots a wavefront reserves at a time
-constexpr uint32_t kClaimChunk = 64;    // queue items a wavefront claims at a time
-constexpr int kCheckPeriod = 8;         // iterations between queue fill checks
+constexpr uint32_t kClaimMin = 32;      // smallest and largest number of queue items a
+constexpr uint32_t kClaimMax = 256;     // wavefront claims with one atomic
 constexpr int kMaxBins = 64;            // energy bins of the queue re-binning
 
 // event counters (same order as the GDPM_EV_* enumeration of the C ABI)

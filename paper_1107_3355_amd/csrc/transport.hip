@@ -61,9 +61,9 @@ GDPM_DEV uint64_t ballot(bool p) { return __ballot(p); }
 GDPM_DEV uint32_t first_lane(uint64_t m) { return (uint32_t)(__ffsll((unsigned long long)m) - 1); }
 GDPM_DEV uint32_t bcast(uint32_t v, uint32_t lane) { return __builtin_amdgcn_readlane(v, lane); }
 // device-coherent load of a counter, made wave-uniform
-GDPM_DEV uint32_t load_agent(uint32_t* p) {
+GDPM_DEV uint32_t load_agent(const uint32_t* p) {
     return __builtin_amdgcn_readfirstlane(
-        __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
 GDPM_DEV double wave_sum(double v) {
@@ -475,8 +475,24 @@ GDPM_DEV void release(PushState& ps, Particle* buf, uint32_t mask) {
 
 struct ClaimState {
     uint32_t next, end;  // claimed virtual indices not yet handed out
+    uint32_t seen;       // the pass's claim counter as this wave last saw it
     bool done;           // the pass has nothing left to claim
 };
+
+// Admission of new source histories: a pass starts new histories only while
+// the queues it feeds are below their soft limits.  The counters are shared by
+// every wavefront, so they are read once per claim, not once per iteration.
+struct Gate {
+    const Ctl* ctl;
+    uint32_t head0, head1, soft0, soft1;
+    bool both;   // also gate on queue 0 (the electron pass feeds both queues)
+};
+
+GDPM_DEV bool gate_open(const Gate& g) {
+    bool open = (load_agent(&g.ctl->ring[1].tail) - g.head1) < g.soft1;
+    if (g.both) open = open && (load_agent(&g.ctl->ring[0].tail) - g.head0) < g.soft0;
+    return open;
+}
 
 // ---------------------------------------------------------------------------
 // per-lane tallies
@@ -703,30 +719,36 @@ __global__ void k_finish(Ctl* ctl, int ri) {
 // claiming input: virtual index < count is a ring record, else a new history
 // ---------------------------------------------------------------------------
 GDPM_DEV void claim_refill(ClaimState& cs, RingCtl* rc, uint32_t count, uint32_t total,
-                           bool allow_source) {
+                           const Gate& g) {
     if (cs.done || cs.next != cs.end) return;
-    // the wave has used up its items: claim a new chunk if the pass has more
-    const uint32_t leader = first_lane(ballot(true));
-    uint32_t base = 0;
-    bool go = true;
-    if (!allow_source) {
-        // only ring items may be taken: stop once the claim counter passed them
-        if (lane_id() == leader) base = load_agent(&rc->claim);
-        base = bcast(base, leader);
-        go = base < count;
-    }
-    if (!go) {
+    // the wave has used up its items: claim a new chunk if the pass has more.
+    // Chunks shrink as the pass drains (guided self-scheduling), so that the
+    // last items spread over many wavefronts.
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t left = total - min(cs.seen, total);
+    const uint32_t chunk = min(max(left / (2u * waves), kClaimMin), kClaimMax);
+    if (load_agent(&g.ctl->overflow)) {
         cs.done = true;
         return;
     }
-    if (lane_id() == leader) base = atomicAdd(&rc->claim, kClaimChunk);
+    if (cs.seen + chunk > count && total > count && !gate_open(g)) {
+        // only queue items may be taken: stop once the claim counter passed them
+        if (load_agent(&rc->claim) >= count) {
+            cs.done = true;
+            return;
+        }
+    }
+    const uint32_t leader = first_lane(ballot(true));
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(&rc->claim, chunk);
     base = bcast(base, leader);
+    cs.seen = base + chunk;
     if (base >= total) {
         cs.done = true;
         return;
     }
     cs.next = base;
-    cs.end = min(base + kClaimChunk, total);
+    cs.end = min(base + chunk, total);
 }
 
 // ---------------------------------------------------------------------------
@@ -739,13 +761,13 @@ struct Refill {
 };
 
 GDPM_DEV Refill refill(bool active, ClaimState& cs, RingCtl* rc, uint32_t begin, uint32_t count,
-                       uint32_t total, bool allow_src, unsigned long long src_base,
+                       uint32_t total, const Gate& gate, unsigned long long src_base,
                        const Particle* buf, uint32_t mask, Particle& p) {
     Refill f{false, false, 0ull};
     if (cs.done) return f;
     const uint64_t need = ballot(!active);
     if (!need) return f;
-    claim_refill(cs, rc, count, total, allow_src);
+    claim_refill(cs, rc, count, total, gate);
     const uint32_t have = cs.end - cs.next;
     const uint32_t rank = mbcnt(need);
     const uint32_t take = min(have, (uint32_t)__popcll(need));
@@ -796,26 +818,21 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Sou
     const float ecut_e = R.ecut_e, ecut_g = R.ecut_g;
 
     PushState pg{0u, 0u}, pe{0u, 0u};
-    ClaimState cs{0u, 0u, false};
+    ClaimState cs{0u, 0u, 0u, false};
     LaneTally tl;
     tally_init(tl);
+    // new source histories start only while the electron queue is below its
+    // soft limit
+    const Gate gate{ctl, head_g, head_e, R.soft[0], R.soft[1], false};
 
     bool active = false;
     float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
     Rng rng;
     rng_start(rng, 0u, 0u, 0u, 0u);
-    bool allow_src = true;
-    int it = 0;
 
     for (;;) {
-        if ((it++ % kCheckPeriod) == 0) {
-            // new source histories start only while the electron queue is below
-            // its soft limit; everything stops after an overflow
-            allow_src = (load_agent(&ctl->ring[1].tail) - head_e) < R.soft[1];
-            if (load_agent(&ctl->overflow)) break;
-        }
         Particle p;
-        const Refill f = refill(active, cs, rc, begin, count, total, allow_src, src_base, bufg,
+        const Refill f = refill(active, cs, rc, begin, count, total, gate, src_base, bufg,
                                 R.mask[0], p);
         if (f.ring) {
             x = p.x; y = p.y; z = p.z; e = p.e;
@@ -998,9 +1015,10 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, S
     const bool no_ms = (R.flags & 8u) != 0u;
 
     PushState pg{0u, 0u}, pe{0u, 0u};
-    ClaimState cs{0u, 0u, false};
+    ClaimState cs{0u, 0u, 0u, false};
     LaneTally tl;
     tally_init(tl);
+    const Gate gate{ctl, head_g, head_e, R.soft[0], R.soft[1], true};
 
     bool active = false;
     float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0, nh = -1.0f, aa = 0.0f;
@@ -1010,17 +1028,10 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, S
     bool positron = false;
     Rng rng;
     rng_start(rng, 0u, 0u, 0u, 0u);
-    bool allow_src = true;
-    int it = 0;
 
     for (;;) {
-        if ((it++ % kCheckPeriod) == 0) {
-            allow_src = (load_agent(&ctl->ring[0].tail) - head_g) < R.soft[0] &&
-                        (load_agent(&ctl->ring[1].tail) - head_e) < R.soft[1];
-            if (load_agent(&ctl->overflow)) break;
-        }
         Particle p;
-        const Refill f = refill(active, cs, rc, begin, count, total, allow_src, src_base, bufe,
+        const Refill f = refill(active, cs, rc, begin, count, total, gate, src_base, bufe,
                                 R.mask[1], p);
         if (f.ring) {
             x = p.x; y = p.y; z = p.z; e = p.e;
