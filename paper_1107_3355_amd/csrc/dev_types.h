@@ -10,6 +10,9 @@ constexpr uint32_t kPushChunk = 256;    // ring slots a wavefront reserves at a 
 constexpr uint32_t kClaimMin = 32;      // smallest and largest number of queue items a
 constexpr uint32_t kClaimMax = 256;     // wavefront claims with one atomic
 constexpr int kMaxBins = 64;            // energy bins of the queue re-binning
+constexpr uint32_t kTailLanes = 32;     // a drained wavefront with fewer particles
+                                        // than this hands them to the next pass ...
+constexpr uint32_t kTailMinPerLane = 4; // ... if the pass had this many per lane
 
 // event counters (same order as the GDPM_EV_* enumeration of the C ABI)
 enum { EV_FLIGHTS = 0, EV_REAL, EV_ESTEPS, EV_HARD_CAND, EV_HARD, EV_DEPOSITS, EV_PUSHES,
@@ -32,17 +35,13 @@ static_assert(sizeof(Particle) == 64, "particle record is 64 bytes");
 struct RingCtl {
     uint32_t head, tail;     // records in [head, tail)
     uint32_t begin, count;   // input of the running pass: [begin, begin + count)
-    uint32_t claim;          // claim counter of the running pass (virtual index)
-    uint32_t src_avail;      // source histories the running pass may start
+    uint32_t claim;          // claim counter of the running pass
     uint32_t cur;            // which of the two buffers holds the ring
-    uint32_t pad;
-    unsigned long long src_base;  // history id of virtual index `count`
 };
 
 // Device-resident control block of a run.
 struct Ctl {
     RingCtl ring[2];                  // 0 photons, 1 electrons/positrons
-    unsigned long long src_next, src_end;
     uint32_t overflow;
     uint32_t pad0;
     unsigned long long ev[8];
@@ -112,9 +111,7 @@ struct RunDev {
     unsigned long long hist0;
     Particle* buf[2][2];       // [ring][buffer]
     uint32_t mask[2];          // capacity - 1
-    uint32_t soft[2];          // fill above which no new source history starts
     uint32_t hard[2];          // fill above which a reservation fails
-    uint32_t pad2[2];
 };
 
 }  // namespace gdpm

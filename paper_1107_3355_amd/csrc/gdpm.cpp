@@ -26,13 +26,14 @@
 #include "tables.h"
 
 namespace gdpm {
-hipError_t launch_setup(hipStream_t st, Ctl* ctl, int ri, int with_source, uint32_t src_pass_max);
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, int ri);
+hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const Geom& G, const SourceDev& S,
+                         const RunDev& R, int ri, unsigned long long h0, uint32_t n);
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri);
 size_t transport_lds_bytes(int ri, const Tables& T);
 hipError_t transport_lds_optin(size_t bytes);
 hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, Ctl* ctl,
-                            const Tables& T, const Geom& G, const SourceDev& S, const RunDev& R,
-                            int with_source);
+                            const Tables& T, const Geom& G, const RunDev& R);
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
                         float lo, float inv);
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
@@ -165,10 +166,11 @@ struct gdpm_context_s {
     int device = 0;
     hipStream_t stream = nullptr;
     int cu_count = 0;
-    int ring_log2 = 24;
+    int ring_log2 = 25;
     int waves_per_cu = 16;
     int rebin_bins = 16;
     int lds_tables = 1;          // stage interpolation tables in LDS when they fit
+    int pass_histories = 0;      // new histories per iteration (0: a quarter of a queue)
     int max_lds = 0;             // dynamic LDS bytes a workgroup may use
     bool lds_optin = false;
     std::vector<MaterialParams> mats;
@@ -317,21 +319,23 @@ struct Timers {
     uint32_t passes = 0, passes_photon = 0, passes_electron = 0;
 };
 
-// run transport for histories [h0, h1) into tally slot `slot`
+// run transport for histories [h0, h1) into the tally slot R.tally.  Each
+// iteration: new histories into the queue of the source particle type, then
+// one pass per particle type, the source type first.
 gdpm_status run_round(gdpm_context ctx, const Tables& T, const Geom& G, const SourceDev& S,
                       RunDev R, hipStream_t st, uint64_t h0, uint64_t h1, Timers* tm) {
-    Ctl* hc = ctx->host_ctl;
+    Ctl* hc = ctx->host_ctl;   // mirrors the device block after each iteration
     Ctl* dc = ctx->ctl.as<Ctl>();
-    // round start: queues are empty; set the source range
-    hc->src_next = h0;
-    hc->src_end = h1;
-    HIP_TRY(hipMemcpyAsync(&dc->src_next, &hc->src_next, 2 * sizeof(unsigned long long),
-                           hipMemcpyHostToDevice, st));
     const int blocks = grid_blocks(ctx);
     const int src_type = S.particle == 0 ? 0 : 1;
     const int nbins = std::min(ctx->rebin_bins, kMaxBins);
     const float blo = -5.0f, bhi = 5.0f;  // log2 E range of the bins (0.03 .. 32 MeV)
     const float binv = nbins > 0 ? nbins / (bhi - blo) : 0.0f;
+    // new histories per iteration: at most half a queue, less what the fuller
+    // queue still holds, so that the pushes of a pass stay below the capacity
+    // (a full queue is still detected and reported as an overflow)
+    const uint32_t cap = 1u << ctx->ring_log2;
+    const uint32_t budget = ctx->pass_histories > 0 ? (uint32_t)ctx->pass_histories : cap / 2u;
     if (ctx->events.size() < 4) {
         for (size_t i = ctx->events.size(); i < 4; ++i) {
             hipEvent_t e;
@@ -339,18 +343,26 @@ gdpm_status run_round(gdpm_context ctx, const Tables& T, const Geom& G, const So
             ctx->events.push_back(e);
         }
     }
+    uint64_t next = h0;
     for (int iter = 0;; ++iter) {
+        const uint32_t fill = std::max(hc->ring[0].tail - hc->ring[0].head,
+                                       hc->ring[1].tail - hc->ring[1].head);
+        const uint64_t room = fill < budget ? budget - fill : 0u;
+        const uint32_t n_src = (uint32_t)std::min<uint64_t>(h1 - next, room);
+        if (n_src > 0) {
+            const int sb = (int)std::min<uint64_t>((n_src + 255) / 256, 8u * (uint64_t)blocks);
+            HIP_TRY(launch_source(st, sb, dc, G, S, R, src_type, next, n_src));
+            next += n_src;
+        }
         for (int k = 0; k < 2; ++k) {
             const int ri = k == 0 ? src_type : 1 - src_type;
-            const int with_src = k == 0 ? 1 : 0;
-            // the queue a pass reads was filled by the other pass: compact it
-            // and sort it by energy so that wavefronts draw similar particles
-            if (nbins > 1 && (iter > 0 || k == 1))
-                HIP_TRY(launch_rebin(st, 4 * blocks, dc, R, ri, nbins, blo, binv));
-            HIP_TRY(launch_setup(st, dc, ri, with_src, 1u << 30));
+            // compact the queue and sort it by energy so that wavefronts draw
+            // particles of similar energy
+            if (nbins > 1) HIP_TRY(launch_rebin(st, 4 * blocks, dc, R, ri, nbins, blo, binv));
+            HIP_TRY(launch_setup(st, dc, ri));
             HIP_TRY(hipEventRecord(ctx->events[2 * k], st));
             const bool lds = ctx->lds_tables && transport_lds_bytes(ri, T) <= (size_t)ctx->max_lds;
-            HIP_TRY(launch_transport(st, ri, blocks, block_threads(ctx), lds, dc, T, G, S, R, with_src));
+            HIP_TRY(launch_transport(st, ri, blocks, block_threads(ctx), lds, dc, T, G, R));
             HIP_TRY(hipEventRecord(ctx->events[2 * k + 1], st));
             HIP_TRY(launch_finish(st, dc, ri));
             tm->passes++;
@@ -369,7 +381,7 @@ gdpm_status run_round(gdpm_context ctx, const Tables& T, const Geom& G, const So
                         "a particle queue filled up (capacity 2^%d); raise ring_capacity_log2",
                         ctx->ring_log2);
         const bool empty = hc->ring[0].tail == hc->ring[0].head &&
-                           hc->ring[1].tail == hc->ring[1].head && hc->src_next >= hc->src_end;
+                           hc->ring[1].tail == hc->ring[1].head && next >= h1;
         if (empty) break;
         if (iter > 100000) return fail(GDPM_E_DEVICE, "transport made no progress");
     }
@@ -472,7 +484,6 @@ gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdp
         R.buf[r][0] = ctx->rings[r][0].as<Particle>();
         R.buf[r][1] = ctx->rings[r][1].as<Particle>();
         R.mask[r] = cap - 1u;
-        R.soft[r] = cap / 2u;
         R.hard[r] = cap;
     }
 
@@ -564,13 +575,15 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     HIP_TRY(hipSetDevice(hip_device));
     auto ctx = std::make_unique<gdpm_context_s>();
     ctx->device = hip_device;
-    ctx->ring_log2 = json_int(opts_json, "ring_capacity_log2", 24);
+    ctx->ring_log2 = json_int(opts_json, "ring_capacity_log2", 25);
     ctx->waves_per_cu = json_int(opts_json, "waves_per_cu", 16);
     ctx->rebin_bins = json_int(opts_json, "rebin_bins", 16);
     ctx->lds_tables = json_int(opts_json, "lds_tables", 1);
+    ctx->pass_histories = json_int(opts_json, "pass_histories", 0);
     if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
     if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > 64) return fail(GDPM_E_INVALID, "waves_per_cu in [1, 64]");
     if (ctx->rebin_bins < 0 || ctx->rebin_bins > kMaxBins) return fail(GDPM_E_INVALID, "rebin_bins in [0, 64]");
+    if (ctx->pass_histories < 0) return fail(GDPM_E_INVALID, "pass_histories must be >= 0");
     HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device));
     HIP_TRY(hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device));
     if (ctx->lds_tables) {

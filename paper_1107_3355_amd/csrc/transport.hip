@@ -473,27 +473,27 @@ GDPM_DEV void release(PushState& ps, Particle* buf, uint32_t mask) {
     ps.next = ps.end;
 }
 
+// Tail of a large pass: once a wavefront has nothing left to claim and fewer
+// than kTailLanes particles, it hands them to the next pass of the same type
+// instead of running them to the end at low lane occupancy.  The record keeps
+// the whole state, random stream position included, so nothing physical
+// changes.  Returns true if the lane wrote a record.
+GDPM_DEV bool requeue(bool active, PushState& ps, uint32_t head, Ctl* ctl, RingCtl* rc, uint32_t hard,
+                      Particle* buf, uint32_t mask, const Particle& p) {
+    const uint64_t b = ballot(active);
+    const uint32_t n = (uint32_t)__popcll(b);
+    if (n == 0) return false;
+    const Reservation res = reserve(ps, rc, head, hard, n, ctl);
+    if (!res.ok || !active) return false;
+    store(buf, mask, slot_of(res, mbcnt(b)), p);
+    return true;
+}
+
 struct ClaimState {
-    uint32_t next, end;  // claimed virtual indices not yet handed out
+    uint32_t next, end;  // claimed queue positions not yet handed out
     uint32_t seen;       // the pass's claim counter as this wave last saw it
     bool done;           // the pass has nothing left to claim
 };
-
-// Admission of new source histories: a pass starts new histories only while
-// the queues it feeds are below their soft limits.  The counters are shared by
-// every wavefront, so they are read once per claim, not once per iteration.
-struct Gate {
-    const Ctl* ctl;
-    uint32_t head0, head1, soft0, soft1;
-    bool both;   // also gate on queue 0 (the electron pass feeds both queues)
-};
-
-GDPM_DEV bool gate_open(const Gate& g) {
-    bool open = (load_agent(&g.ctl->ring[1].tail) - g.head1) < g.soft1;
-    if (g.both) open = open && (load_agent(&g.ctl->ring[0].tail) - g.head0) < g.soft0;
-    return open;
-}
-
 // ---------------------------------------------------------------------------
 // per-lane tallies
 // ---------------------------------------------------------------------------
@@ -689,100 +689,124 @@ GDPM_DEV void push_photons(PendPhoton& q, PushState& ps, uint32_t head, Ctl* ctl
 // ---------------------------------------------------------------------------
 // pass set-up and completion (single thread, between passes)
 // ---------------------------------------------------------------------------
-__global__ void k_setup(Ctl* ctl, int ri, int with_source, uint32_t src_pass_max) {
+__global__ void k_setup(Ctl* ctl, int ri) {
     RingCtl& r = ctl->ring[ri];
     r.begin = r.head;
     r.count = ctl->overflow ? 0u : r.tail - r.head;
     r.claim = 0u;
-    if (with_source && !ctl->overflow) {
-        const unsigned long long left = ctl->src_end - ctl->src_next;
-        r.src_avail = (uint32_t)(left < src_pass_max ? left : src_pass_max);
-    } else {
-        r.src_avail = 0u;
-    }
-    r.src_base = ctl->src_next;
 }
 
 __global__ void k_finish(Ctl* ctl, int ri) {
     RingCtl& r = ctl->ring[ri];
-    const uint32_t used = min(r.claim, r.count);
-    r.head = r.begin + used;
-    if (r.src_avail) {
-        const uint32_t s = r.claim > r.count ? min(r.claim - r.count, r.src_avail) : 0u;
-        ctl->src_next += s;
-    }
-    r.src_avail = 0u;
+    r.head = r.begin + min(r.claim, r.count);
     r.count = 0u;
 }
 
 // ---------------------------------------------------------------------------
-// claiming input: virtual index < count is a ring record, else a new history
+// claiming input: positions [0, count) of the pass's queue segment
 // ---------------------------------------------------------------------------
-GDPM_DEV void claim_refill(ClaimState& cs, RingCtl* rc, uint32_t count, uint32_t total,
-                           const Gate& g) {
+GDPM_DEV void claim_refill(ClaimState& cs, RingCtl* rc, uint32_t count, const Ctl* ctl) {
     if (cs.done || cs.next != cs.end) return;
     // the wave has used up its items: claim a new chunk if the pass has more.
     // Chunks shrink as the pass drains (guided self-scheduling), so that the
-    // last items spread over many wavefronts.
+    // last items spread over many wavefronts.  The shared counters are touched
+    // once per claim, never per iteration.
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-    const uint32_t left = total - min(cs.seen, total);
+    const uint32_t left = count - min(cs.seen, count);
     const uint32_t chunk = min(max(left / (2u * waves), kClaimMin), kClaimMax);
-    if (load_agent(&g.ctl->overflow)) {
+    if (load_agent(&ctl->overflow)) {   // a queue overflowed: the run is void
         cs.done = true;
         return;
-    }
-    if (cs.seen + chunk > count && total > count && !gate_open(g)) {
-        // only queue items may be taken: stop once the claim counter passed them
-        if (load_agent(&rc->claim) >= count) {
-            cs.done = true;
-            return;
-        }
     }
     const uint32_t leader = first_lane(ballot(true));
     uint32_t base = 0;
     if (lane_id() == leader) base = atomicAdd(&rc->claim, chunk);
     base = bcast(base, leader);
     cs.seen = base + chunk;
-    if (base >= total) {
+    if (base >= count) {
         cs.done = true;
         return;
     }
     cs.next = base;
-    cs.end = min(base + chunk, total);
+    cs.end = min(base + chunk, count);
 }
 
-// ---------------------------------------------------------------------------
-// input of one iteration: refill empty lanes from the pass's queue or source
-// ---------------------------------------------------------------------------
-struct Refill {
-    bool ring;            // took a queue record (loaded into the lane)
-    bool source;          // took a new history `h`
-    unsigned long long h;
-};
-
-GDPM_DEV Refill refill(bool active, ClaimState& cs, RingCtl* rc, uint32_t begin, uint32_t count,
-                       uint32_t total, const Gate& gate, unsigned long long src_base,
-                       const Particle* buf, uint32_t mask, Particle& p) {
-    Refill f{false, false, 0ull};
-    if (cs.done) return f;
+// refill the lanes without a particle from the wave's claimed items; returns
+// true in the lanes that loaded a record
+GDPM_DEV bool refill(bool active, ClaimState& cs, RingCtl* rc, uint32_t begin, uint32_t count,
+                     const Ctl* ctl, const Particle* buf, uint32_t mask, Particle& p) {
+    if (cs.done) return false;
     const uint64_t need = ballot(!active);
-    if (!need) return f;
-    claim_refill(cs, rc, count, total, gate);
+    if (!need) return false;
+    claim_refill(cs, rc, count, ctl);
     const uint32_t have = cs.end - cs.next;
     const uint32_t rank = mbcnt(need);
     const uint32_t take = min(have, (uint32_t)__popcll(need));
+    bool got = false;
     if (!active && rank < take) {
-        const uint32_t vi = cs.next + rank;
-        if (vi < count) {
-            p = load(buf, mask, begin + vi);
-            f.ring = p.e >= 0.0f;
-        } else {
-            f.source = true;
-            f.h = src_base + (vi - count);
-        }
+        p = load(buf, mask, begin + cs.next + rank);
+        got = p.e >= 0.0f;
     }
     cs.next += take;
-    return f;
+    return got;
+}
+
+// ---------------------------------------------------------------------------
+// source pass: histories [h0, h0 + n) -> primaries appended to the queue of
+// the source particle type (section 2.3); a primary whose ray misses the
+// phantom leaves an empty slot and counts as escaped
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_source(Ctl* ctl, Geom G, SourceDev S, RunDev R, int ri,
+                                                unsigned long long h0, uint32_t n) {
+    if (ctl->overflow) return;
+    const RingCtl& r = ctl->ring[ri];
+    const uint32_t tail = r.tail;
+    if (tail + n - r.head > R.hard[ri]) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->overflow, 1u);
+        return;
+    }
+    Particle* buf = R.buf[ri][r.cur];
+    const uint32_t k0 = R.k0, k1 = R.k1;
+    double e_in = 0.0, e_esc = 0.0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned long long h = h0 + i;
+        Rng rng;
+        rng_start(rng, (uint32_t)h, (uint32_t)(h >> 32), 0u, 0u);
+        rng_topup(rng, k0, k1);
+        const Primary pr = make_primary(S, G, rng, k0, k1);
+        e_in += (double)pr.e;
+        if (pr.in) {
+            uint32_t vox = 0u;
+            if (ri == 1) {
+                int ix, iy, iz;
+                voxel_of(G, pr.x, pr.y, pr.z, ix, iy, iz);
+                vox = pack_vox(ix, iy, iz);
+            }
+            // the stream continues at the draw after the source's draws
+            float4* d = reinterpret_cast<float4*>(buf + ((tail + i) & R.mask[ri]));
+            d[0] = make_float4(pr.x, pr.y, pr.z, pr.e);
+            d[1] = make_float4(pr.u, pr.v, pr.w, -1.0f);
+            d[2] = make_float4(__uint_as_float(rng.hlo), __uint_as_float(rng.hhi), 0.0f,
+                               __uint_as_float(rng_ctr(rng)));
+            d[3] = make_float4(__uint_as_float(vox), 0.0f, 0.0f, 0.0f);
+        } else {
+            reinterpret_cast<float*>(buf + ((tail + i) & R.mask[ri]))[3] = -1.0f;
+            e_esc += (double)pr.e;
+            if (R.hist) unsafeAtomicAdd(&R.hist[2 * (h - R.hist0) + 1], (double)pr.e);
+        }
+    }
+    e_in = wave_sum(e_in);
+    e_esc = wave_sum(e_esc);
+    if (lane_id() == 0) {
+        if (e_in != 0.0) unsafeAtomicAdd(&ctl->e_in, e_in);
+        if (e_esc != 0.0) unsafeAtomicAdd(&ctl->e_esc, e_esc);
+    }
+}
+
+// make the records written by the source pass part of the queue
+__global__ void k_commit(Ctl* ctl, int ri, uint32_t n) {
+    if (ctl->overflow) return;
+    ctl->ring[ri].tail += n;
 }
 
 // ---------------------------------------------------------------------------
@@ -793,8 +817,7 @@ GDPM_DEV Refill refill(bool active, ClaimState& cs, RingCtl* rc, uint32_t begin,
 extern __shared__ float4 lds_tables[];
 
 template <bool kLds>
-__global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, SourceDev S, RunDev R,
-                                                 int with_source) {
+__global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, RunDev R) {
     const float4* ptab = T.phot;
     const float* mtab = T.mumax;
     if constexpr (kLds) {
@@ -808,8 +831,7 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Sou
     }
     RingCtl* rc = &ctl->ring[0];
     const uint32_t begin = rc->begin, count = rc->count;
-    const uint32_t total = count + (with_source ? rc->src_avail : 0u);
-    const unsigned long long src_base = rc->src_base;
+    const bool big = count >= kTailMinPerLane * gridDim.x * blockDim.x;
     Particle* bufg = R.buf[0][ctl->ring[0].cur];
     Particle* bufe = R.buf[1][ctl->ring[1].cur];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
@@ -821,9 +843,6 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Sou
     ClaimState cs{0u, 0u, 0u, false};
     LaneTally tl;
     tally_init(tl);
-    // new source histories start only while the electron queue is below its
-    // soft limit
-    const Gate gate{ctl, head_g, head_e, R.soft[0], R.soft[1], false};
 
     bool active = false;
     float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
@@ -832,33 +851,17 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Sou
 
     for (;;) {
         Particle p;
-        const Refill f = refill(active, cs, rc, begin, count, total, gate, src_base, bufg,
-                                R.mask[0], p);
-        if (f.ring) {
+        if (refill(active, cs, rc, begin, count, ctl, bufg, R.mask[0], p)) {
             x = p.x; y = p.y; z = p.z; e = p.e;
             u = p.u; v = p.v; w = p.w;
             rng_start(rng, p.hlo, p.hhi, p.path, p.ctr);
             active = true;
-        } else if (f.source) {
-            rng_start(rng, (uint32_t)f.h, (uint32_t)(f.h >> 32), 0u, 0u);
         }
-        if (!ballot(active || f.source)) {
+        if (!ballot(active)) {
             if (cs.done) break;
             continue;
         }
         rng_topup(rng, k0, k1);
-        if (f.source) {
-            const Primary pr = make_primary(S, G, rng, k0, k1);
-            tl.e_in += (double)pr.e;
-            if (pr.in) {
-                x = pr.x; y = pr.y; z = pr.z; u = pr.u; v = pr.v; w = pr.w; e = pr.e;
-                active = true;
-            } else {
-                tl.e_esc += (double)pr.e;
-                tl.h_esc += (double)pr.e;
-                history_flush(tl, R, rng.hlo, rng.hhi);
-            }
-        }
 
         PendCharged qe;
         PendPhoton qg;
@@ -976,6 +979,16 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Sou
         // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
         push_charged(qe, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
         push_photons(qg, pg, head_g, ctl, R, bufg, x, y, z, rng, tl);
+        if (cs.done && big && __popcll(ballot(active)) < kTailLanes) {
+            Particle q;
+            q.x = x; q.y = y; q.z = z; q.e = e;
+            q.u = u; q.v = v; q.w = w; q.nh = -1.0f;
+            q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
+            q.vox = 0u; q.a = 0.0f; q.flags = 0u; q.pad = 0u;
+            if (requeue(active, pg, head_g, ctl, &ctl->ring[0], R.hard[0], bufg, R.mask[0], q))
+                history_flush(tl, R, rng.hlo, rng.hhi);
+            break;
+        }
     }
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
@@ -987,8 +1000,7 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Sou
 // iteration (section 2.1)
 // ---------------------------------------------------------------------------
 template <bool kLds>
-__global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, SourceDev S,
-                                                   RunDev R, int with_source) {
+__global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, RunDev R) {
     const float4* etab = T.elec;
     const float* rtab = T.rinv;
     const float* rscale = T.rinv_scale;
@@ -1005,8 +1017,7 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, S
     }
     RingCtl* rc = &ctl->ring[1];
     const uint32_t begin = rc->begin, count = rc->count;
-    const uint32_t total = count + (with_source ? rc->src_avail : 0u);
-    const unsigned long long src_base = rc->src_base;
+    const bool big = count >= kTailMinPerLane * gridDim.x * blockDim.x;
     Particle* bufg = R.buf[0][ctl->ring[0].cur];
     Particle* bufe = R.buf[1][ctl->ring[1].cur];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
@@ -1018,7 +1029,6 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, S
     ClaimState cs{0u, 0u, 0u, false};
     LaneTally tl;
     tally_init(tl);
-    const Gate gate{ctl, head_g, head_e, R.soft[0], R.soft[1], true};
 
     bool active = false;
     float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0, nh = -1.0f, aa = 0.0f;
@@ -1031,9 +1041,7 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, S
 
     for (;;) {
         Particle p;
-        const Refill f = refill(active, cs, rc, begin, count, total, gate, src_base, bufe,
-                                R.mask[1], p);
-        if (f.ring) {
+        if (refill(active, cs, rc, begin, count, ctl, bufe, R.mask[1], p)) {
             x = p.x; y = p.y; z = p.z; e = p.e;
             u = p.u; v = p.v; w = p.w; nh = p.nh;
             ix = (int)(p.vox & 2047u);
@@ -1046,32 +1054,12 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, S
             rho = __uint_as_float(vx.x);
             mat = (int)vx.y;
             active = true;
-        } else if (f.source) {
-            rng_start(rng, (uint32_t)f.h, (uint32_t)(f.h >> 32), 0u, 0u);
         }
-        if (!ballot(active || f.source)) {
+        if (!ballot(active)) {
             if (cs.done) break;
             continue;
         }
         rng_topup(rng, k0, k1);
-        if (f.source) {
-            const Primary pr = make_primary(S, G, rng, k0, k1);
-            tl.e_in += (double)pr.e;
-            if (pr.in) {
-                x = pr.x; y = pr.y; z = pr.z; u = pr.u; v = pr.v; w = pr.w; e = pr.e;
-                const uint2 vx = G.vox[voxel_of(G, x, y, z, ix, iy, iz)];
-                rho = __uint_as_float(vx.x);
-                mat = (int)vx.y;
-                nh = -1.0f;
-                aa = 0.0f;
-                positron = false;
-                active = true;
-            } else {
-                tl.e_esc += (double)pr.e;
-                tl.h_esc += (double)pr.e;
-                history_flush(tl, R, rng.hlo, rng.hhi);
-            }
-        }
 
         PendCharged qe;
         PendPhoton qg;
@@ -1224,6 +1212,16 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, S
         }
         push_charged(qe, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
         push_photons(qg, pg, head_g, ctl, R, bufg, x, y, z, rng, tl);
+        if (cs.done && big && __popcll(ballot(active)) < kTailLanes) {
+            Particle q;
+            q.x = x; q.y = y; q.z = z; q.e = e;
+            q.u = u; q.v = v; q.w = w; q.nh = nh;
+            q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
+            q.vox = pack_vox(ix, iy, iz); q.a = aa; q.flags = positron ? 1u : 0u; q.pad = 0u;
+            if (requeue(active, pe, head_e, ctl, &ctl->ring[1], R.hard[1], bufe, R.mask[1], q))
+                history_flush(tl, R, rng.hlo, rng.hhi);
+            break;
+        }
     }
     // the pass was stopped by an overflow: particles still held are dropped
     // (the run reports GDPM_E_OVERFLOW and its outputs are not valid)
@@ -1481,8 +1479,14 @@ __global__ void k_test_lookup(Tables T, int which, int m, const float* in, float
 // ---------------------------------------------------------------------------
 // host launchers (the host runtime calls these; kernels stay in this unit)
 // ---------------------------------------------------------------------------
-hipError_t launch_setup(hipStream_t st, Ctl* ctl, int ri, int with_source, uint32_t src_pass_max) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(1), 0, st, ctl, ri, with_source, src_pass_max);
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, int ri) {
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(1), 0, st, ctl, ri);
+    return hipGetLastError();
+}
+hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const Geom& G, const SourceDev& S,
+                         const RunDev& R, int ri, unsigned long long h0, uint32_t n) {
+    hipLaunchKernelGGL(k_source, dim3(blocks), dim3(256), 0, st, ctl, G, S, R, ri, h0, n);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, st, ctl, ri, n);
     return hipGetLastError();
 }
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri) {
@@ -1505,23 +1509,18 @@ hipError_t transport_lds_optin(size_t bytes) {
 }
 
 hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, Ctl* ctl,
-                            const Tables& T, const Geom& G, const SourceDev& S, const RunDev& R,
-                            int with_source) {
+                            const Tables& T, const Geom& G, const RunDev& R) {
     const size_t bytes = lds ? transport_lds_bytes(ri, T) : 0;
     if (ri == 0) {
         if (lds)
-            hipLaunchKernelGGL(k_photon<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, G, S,
-                               R, with_source);
+            hipLaunchKernelGGL(k_photon<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, G, R);
         else
-            hipLaunchKernelGGL(k_photon<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, G, S, R,
-                               with_source);
+            hipLaunchKernelGGL(k_photon<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, G, R);
     } else {
         if (lds)
-            hipLaunchKernelGGL(k_electron<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, G,
-                               S, R, with_source);
+            hipLaunchKernelGGL(k_electron<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, G, R);
         else
-            hipLaunchKernelGGL(k_electron<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, G, S,
-                               R, with_source);
+            hipLaunchKernelGGL(k_electron<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, G, R);
     }
     return hipGetLastError();
 }

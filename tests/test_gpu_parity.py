@@ -224,7 +224,8 @@ def test_determinism_and_launch_independence(gctx):
     b = gpu_run(gctx, w.phantom, w.source, n_hist=50_000, seed=9)
     assert a["events"] == b["events"]
     np.testing.assert_allclose(a["dose"], b["dose"], rtol=1e-12, atol=1e-300)
-    for opts in ('{"waves_per_cu": 4, "rebin_bins": 0}', '{"waves_per_cu": 8, "rebin_bins": 32}'):
+    for opts in ('{"waves_per_cu": 4, "rebin_bins": 0}', '{"waves_per_cu": 8, "rebin_bins": 32}',
+                 '{"ring_capacity_log2": 21, "pass_histories": 700}'):
         c2 = G.Context(0, opts=opts, materials=MATS)
         try:
             c = gpu_run(c2, w.phantom, w.source, n_hist=50_000, seed=9)
@@ -309,8 +310,9 @@ def test_invalid_inputs_rejected(gctx):
 
 def test_queue_overflow_reported():
     """A queue too small for the workload stops the run with GDPM_E_OVERFLOW
-    (forced from the host by a 4096-record capacity); the context stays usable."""
-    c = G.Context(0, opts='{"ring_capacity_log2": 12}', materials=MATS)
+    (forced from the host: 4096-record queues, 4000 new histories per
+    iteration, whose secondaries cannot fit); the context stays usable."""
+    c = G.Context(0, opts='{"ring_capacity_log2": 12, "pass_histories": 4000}', materials=MATS)
     try:
         w = I.water_cube_2mev()
         with pytest.raises(G.GdpmError) as e:
