@@ -11,8 +11,10 @@ phantom, source and tables already resident in device memory.
 
 Also reported: the job latency (p50/p99 over the timed jobs), the roofline
 position of the dominant transport kernel (HIP-event times of every launch on
-the library's stream, algorithmic work from the kernel's own event counters),
-and the oracle (plain CPU transport) timed on a bounded sample of the same job.
+the library's stream; algorithmic bytes from the kernels' own counters of voxel
+lookups, queue records and tally deposits; measured HBM traffic from the
+committed hardware-counter summary), and the oracle (plain CPU transport) timed
+on a bounded sample of the same job.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
 """
@@ -29,14 +31,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "histories/s at 1% unc. (6MV, 256x256x128 CT phantom); p50/p99 dose-job latency"
 
-# Algorithmic single-precision work per transport event, counted from the
-# arithmetic each event needs (additions, multiplications, fused
-# multiply-adds counted as two, divisions, square roots and transcendental
-# functions counted as one each); the breakdown is in the design notes.
-FLOP_PER_ELECTRON_STEP = 180.0
-FLOP_PER_PHOTON_FLIGHT = 48.0
-FLOP_PER_PHOTON_INTERACTION = 110.0
-PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32
+# Algorithmic memory traffic of the transport passes (bytes per unit of work):
+# every Woodcock flight and every electron step needs the density and material
+# of one voxel (an 8-byte record), every particle taken from or put into a queue
+# is a 64-byte record, and every tally deposit is one FP64 value.
+BYTES_PER_VOXEL_LOOKUP = 8
+BYTES_PER_RECORD = 64
+BYTES_PER_DEPOSIT = 8
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1107_3355_amd", "csrc", "transport.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_ct256x256x128_imrt9.txt")
 
 
 def log(*a):
@@ -66,6 +70,42 @@ def cpu_baseline(workload, seconds):
     return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} histories (ids {h0}..{h0 + n - 1}) of the same CT IMRT job, FP64 CPU "
                       f"transport on {threads} threads, {dt:.1f} s including the run set-up"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    there is none or the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    kv = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith(" "))
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if kv.get("transport_hip_sha256", "").strip() != src:
+        return None
+    v = kv.get(f"{kernel}_hbm_bytes_per_launch")
+    return float(v) if v else None
+
+
+def reference_copy(nbytes):
+    """One plain device-to-device copy of `nbytes` through the HIP runtime (its
+    blit kernel): a kernel of known traffic that calibrates the hardware
+    counters read by a profiler run of this same command."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    n = ctypes.c_size_t(nbytes)
+    for ptr in (a, b):
+        if hip.hipMalloc(ctypes.byref(ptr), n) != 0:
+            raise RuntimeError("hipMalloc failed")
+    try:
+        if hip.hipMemset(a, 1, n) != 0 or hip.hipMemcpy(b, a, n, 3) != 0 or hip.hipDeviceSynchronize() != 0:
+            raise RuntimeError("reference copy failed")
+    finally:
+        hip.hipFree(a)
+        hip.hipFree(b)
 
 
 def main():
@@ -106,15 +146,8 @@ def main():
                        stat_min_density=args.min_density, want_dose=False)
 
     if args.copy_mib:
-        import torch
-        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
+        reference_copy(args.copy_mib << 20)
         log(f"reference copy: {args.copy_mib} MiB read, {args.copy_mib} MiB written")
-        del a, b
 
     n0 = args.n0
     for i in range(args.warmup):
@@ -133,22 +166,25 @@ def main():
     hist = sum(r["histories"] for r in runs)
     lat = np.array([r["t_total_s"] for r in runs])
 
-    # roofline of the dominant transport kernel
+    # roofline of the dominant transport kernel: algorithmic bytes per launch
+    # over the launch's average HIP-event duration
     te = sum(r["t_electron_s"] for r in runs)
     tp = sum(r["t_photon_s"] for r in runs)
     ne = sum(r["passes_electron"] for r in runs)
     npp = sum(r["passes_photon"] for r in runs)
     ev = {k: sum(r["events"][k] for r in runs) for k in runs[0]["events"]}
-    if te >= tp:
-        name, launches, t_k = "k_electron", ne, te
-        work = FLOP_PER_ELECTRON_STEP * ev["esteps"]
-    else:
-        name, launches, t_k = "k_photon", npp, tp
-        work = FLOP_PER_PHOTON_FLIGHT * ev["flights"] + FLOP_PER_PHOTON_INTERACTION * ev["real"]
+    k = 1 if te >= tp else 0
+    name, launches, t_k = ("k_electron", ne, te) if k else ("k_photon", npp, tp)
+    lookups = ev["esteps"] if k else ev["flights"]
+    nbytes = (BYTES_PER_VOXEL_LOOKUP * lookups
+              + BYTES_PER_RECORD * sum(r["records_loaded"][k] + r["records_stored"][k] for r in runs)
+              + BYTES_PER_DEPOSIT * sum(r["deposits"][k] for r in runs))
     avg = t_k / max(launches, 1)
-    achieved = work / max(launches, 1) / avg / 1e12
-    roof = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+    achieved = nbytes / max(launches, 1) / avg / 1e9
+    roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "traffic": measured_traffic(name),
+            "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
             "avg_launch_ms": avg * 1e3, "launches": launches,
             "share_of_kernel_time": t_k / max(te + tp, 1e-30)}
 

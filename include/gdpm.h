@@ -144,6 +144,10 @@ typedef struct {
     uint32_t rounds;
     uint32_t passes_photon;      /* photon kernel launches (t_photon_s covers them) */
     uint32_t passes_electron;    /* electron kernel launches (t_electron_s covers them) */
+    /* per pass type (0 photon, 1 electron): 64-byte queue records the passes
+     * loaded and stored (secondaries and particles handed to the next pass),
+     * and FP64 tally deposits; the memory traffic the passes cannot avoid */
+    uint64_t records_loaded[2], records_stored[2], deposits[2];
 } gdpm_run_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -45,6 +45,8 @@ struct Ctl {
     uint32_t overflow;
     uint32_t pad0;
     unsigned long long ev[8];
+    unsigned long long pass_ev[2][3];  // per pass type: records loaded, records
+                                       // stored, tally deposits
     double e_in, e_esc;
     uint32_t bin_count[kMaxBins];
     uint32_t bin_cursor[kMaxBins];

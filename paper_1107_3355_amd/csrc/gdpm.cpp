@@ -548,6 +548,11 @@ gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdp
         out->passes = tm.passes;
         out->passes_photon = tm.passes_photon;
         out->passes_electron = tm.passes_electron;
+        for (int k = 0; k < 2; ++k) {
+            out->records_loaded[k] = hc->pass_ev[k][0];
+            out->records_stored[k] = hc->pass_ev[k][1];
+            out->deposits[k] = hc->pass_ev[k][2];
+        }
         out->rounds = rounds;
         out->t_photon_s = tm.photon;
         out->t_electron_s = tm.electron;

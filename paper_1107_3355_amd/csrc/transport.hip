@@ -500,9 +500,10 @@ struct ClaimState {
 struct LaneTally {
     int dv;          // voxel of the pending deposit (-1 none)
     double de;       // pending deposit (MeV)
-    double e_in, e_esc;
+    double e_esc;
     double h_dep, h_esc;  // per-history accumulators (test mode)
     uint32_t ev[7];
+    uint32_t ld, rq;      // records loaded from the queue, records handed on
 };
 
 GDPM_DEV void tally_flush(LaneTally& t, const RunDev& R) {
@@ -534,23 +535,28 @@ GDPM_DEV void history_flush(LaneTally& t, const RunDev& R, uint32_t hlo, uint32_
 GDPM_DEV void tally_init(LaneTally& t) {
     t.dv = -1;
     t.de = 0.0;
-    t.e_in = t.e_esc = t.h_dep = t.h_esc = 0.0;
+    t.e_esc = t.h_dep = t.h_esc = 0.0;
 #pragma unroll
     for (int i = 0; i < 7; ++i) t.ev[i] = 0u;
+    t.ld = t.rq = 0u;
 }
 
-GDPM_DEV void tally_finish(LaneTally& t, const RunDev& R, Ctl* ctl) {
+// fold the lane counters into the run's; `ri` is the pass's particle type
+GDPM_DEV void tally_finish(LaneTally& t, const RunDev& R, Ctl* ctl, int ri) {
     tally_flush(t, R);
-    const double ein = wave_sum(t.e_in), esc = wave_sum(t.e_esc);
+    const double esc = wave_sum(t.e_esc);
     uint32_t ev[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i) ev[i] = wave_sum(t.ev[i]);
+    const uint32_t ld = wave_sum(t.ld), rq = wave_sum(t.rq);
     if (lane_id() == 0) {
-        if (ein != 0.0) unsafeAtomicAdd(&ctl->e_in, ein);
         if (esc != 0.0) unsafeAtomicAdd(&ctl->e_esc, esc);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             if (ev[i]) atomicAdd(&ctl->ev[i], (unsigned long long)ev[i]);
+        atomicAdd(&ctl->pass_ev[ri][0], (unsigned long long)ld);
+        atomicAdd(&ctl->pass_ev[ri][1], (unsigned long long)(ev[EV_PUSHES] + rq));
+        atomicAdd(&ctl->pass_ev[ri][2], (unsigned long long)ev[EV_DEPOSITS]);
     }
 }
 
@@ -852,6 +858,7 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Run
     for (;;) {
         Particle p;
         if (refill(active, cs, rc, begin, count, ctl, bufg, R.mask[0], p)) {
+            tl.ld++;
             x = p.x; y = p.y; z = p.z; e = p.e;
             u = p.u; v = p.v; w = p.w;
             rng_start(rng, p.hlo, p.hhi, p.path, p.ctr);
@@ -985,14 +992,16 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Run
             q.u = u; q.v = v; q.w = w; q.nh = -1.0f;
             q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
             q.vox = 0u; q.a = 0.0f; q.flags = 0u; q.pad = 0u;
-            if (requeue(active, pg, head_g, ctl, &ctl->ring[0], R.hard[0], bufg, R.mask[0], q))
+            if (requeue(active, pg, head_g, ctl, &ctl->ring[0], R.hard[0], bufg, R.mask[0], q)) {
+                tl.rq++;
                 history_flush(tl, R, rng.hlo, rng.hhi);
+            }
             break;
         }
     }
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
-    tally_finish(tl, R, ctl);
+    tally_finish(tl, R, ctl, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1042,6 +1051,7 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, R
     for (;;) {
         Particle p;
         if (refill(active, cs, rc, begin, count, ctl, bufe, R.mask[1], p)) {
+            tl.ld++;
             x = p.x; y = p.y; z = p.z; e = p.e;
             u = p.u; v = p.v; w = p.w; nh = p.nh;
             ix = (int)(p.vox & 2047u);
@@ -1218,8 +1228,10 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, R
             q.u = u; q.v = v; q.w = w; q.nh = nh;
             q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
             q.vox = pack_vox(ix, iy, iz); q.a = aa; q.flags = positron ? 1u : 0u; q.pad = 0u;
-            if (requeue(active, pe, head_e, ctl, &ctl->ring[1], R.hard[1], bufe, R.mask[1], q))
+            if (requeue(active, pe, head_e, ctl, &ctl->ring[1], R.hard[1], bufe, R.mask[1], q)) {
+                tl.rq++;
                 history_flush(tl, R, rng.hlo, rng.hhi);
+            }
             break;
         }
     }
@@ -1227,7 +1239,7 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, R
     // (the run reports GDPM_E_OVERFLOW and its outputs are not valid)
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
-    tally_finish(tl, R, ctl);
+    tally_finish(tl, R, ctl, 1);
 }
 
 // ---------------------------------------------------------------------------

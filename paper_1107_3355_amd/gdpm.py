@@ -68,7 +68,9 @@ class RunStats(C.Structure):
                 ("t_total_s", C.c_double), ("t_kernel_s", C.c_double),
                 ("t_photon_s", C.c_double), ("t_electron_s", C.c_double),
                 ("events", C.c_uint64 * 8), ("passes", C.c_uint32), ("rounds", C.c_uint32),
-                ("passes_photon", C.c_uint32), ("passes_electron", C.c_uint32)]
+                ("passes_photon", C.c_uint32), ("passes_electron", C.c_uint32),
+                ("records_loaded", C.c_uint64 * 2), ("records_stored", C.c_uint64 * 2),
+                ("deposits", C.c_uint64 * 2)]
 
 
 def lib():
@@ -203,7 +205,10 @@ def _stats_dict(st):
             "t_kernel_s": st.t_kernel_s, "t_photon_s": st.t_photon_s,
             "t_electron_s": st.t_electron_s, "passes": int(st.passes), "rounds": int(st.rounds),
             "passes_photon": int(st.passes_photon), "passes_electron": int(st.passes_electron),
-            "events": {k: int(st.events[i]) for i, k in enumerate(EV_NAMES)}}
+            "events": {k: int(st.events[i]) for i, k in enumerate(EV_NAMES)},
+            "records_loaded": [int(v) for v in st.records_loaded],
+            "records_stored": [int(v) for v in st.records_stored],
+            "deposits": [int(v) for v in st.deposits]}
 
 
 class Context:
