@@ -10,6 +10,8 @@ constexpr uint32_t kPushChunk = 256;    // ring slots a wavefront reserves at a 
 constexpr uint32_t kClaimMin = 32;      // smallest and largest number of queue items a
 constexpr uint32_t kClaimMax = 256;     // wavefront claims with one atomic
 constexpr int kMaxBins = 64;            // energy bins of the queue re-binning
+constexpr int kMaxJobs = 256;           // dose jobs transported together
+constexpr int kMaxKeys = 4096;          // re-binning keys (job x energy bin)
 constexpr uint32_t kTailLanes = 32;     // a drained wavefront with fewer particles
                                         // than this hands them to the next pass ...
 constexpr uint32_t kTailMinPerLane = 4; // ... if the pass had this many per lane
@@ -27,7 +29,7 @@ struct alignas(16) Particle {
     uint32_t vox;            // charged particles: ix | iy << 11 | iz << 22
     float a;                 // positron: energy of its two annihilation photons together
     uint32_t flags;          // bit 0: positron
-    uint32_t pad;
+    uint32_t job;            // bits 0-15: job slot; bits 16-31: batch slot of the history
 };
 static_assert(sizeof(Particle) == 64, "particle record is 64 bytes");
 
@@ -39,21 +41,33 @@ struct RingCtl {
     uint32_t cur;            // which of the two buffers holds the ring
 };
 
-// Device-resident control block of a run.
+// Device-resident control block of the transport (the host reads it back
+// after every scheduler iteration).
 struct Ctl {
     RingCtl ring[2];                  // 0 photons, 1 electrons/positrons
     uint32_t overflow;
-    uint32_t pad0;
+    uint32_t n_valid;                 // records kept by the last compaction
     unsigned long long ev[8];
     unsigned long long pass_ev[2][3];  // per pass type: records loaded, records
                                        // stored, tally deposits
-    double e_in, e_esc;
-    uint32_t bin_count[kMaxBins];
-    uint32_t bin_cursor[kMaxBins];
-    uint32_t n_valid;
-    uint32_t pad1;
     double red[4];                    // statistics reductions
     unsigned long long dmax_bits;
+};
+
+// Per-job counters and the job segments of the running pass.  The first four
+// arrays are read back by the host after every iteration: a job whose births
+// equal its deaths has no particle left in the queues.
+struct JobCtl {
+    unsigned long long births[kMaxJobs];   // queue records created (primaries, secondaries)
+    unsigned long long deaths[kMaxJobs];   // particles ended (absorbed, escaped)
+    double e_in[kMaxJobs];                 // source kinetic energy (MeV)
+    double e_esc[kMaxJobs];                // energy leaving the phantom (MeV)
+    uint32_t seg_begin[kMaxJobs];          // the job's records in the pass input:
+    uint32_t seg_count[kMaxJobs];          //   [seg_begin, seg_begin + seg_count)
+    uint32_t claim[kMaxJobs];              // claim counter of the job's segment
+    unsigned long long left[kMaxJobs / 64];  // jobs with unclaimed records
+    uint32_t bin_count[kMaxKeys];
+    uint32_t bin_cursor[kMaxKeys];
 };
 
 // Interpolation tables (single precision, linear in log2 E).
@@ -103,14 +117,34 @@ struct SourceDev {
     int n_beams;
 };
 
-struct RunDev {
-    uint32_t k0, k1;           // Philox key
-    float ecut_g, ecut_e;
-    uint32_t flags;
-    uint32_t pad;
-    double* tally;             // energy tally of the active batch slot (MeV per voxel)
+// One dose job: its phantom, source, random key and tallies.
+struct JobDev {
+    Geom G;
+    SourceDev S;
+    const float* mumax;        // [pg_n] Woodcock majorant of the job's phantom, 1/cm
+    double* tally;             // [n_batches][nv] energy tallies (MeV per voxel)
+    unsigned long long nv;     // voxels of the phantom
     double* hist;              // per-history (deposited, escaped) or null
-    unsigned long long hist0;
+    unsigned long long hist0;  // history id of hist[0]
+    uint32_t k0, k1;           // Philox key
+    uint32_t flags;            // GDPM_* run flags
+    uint32_t pad;
+};
+
+// A run of new histories for the source pass: ids [h0, h0 + n) of job `job`,
+// batch slot `batch`, written to queue slots tail + off + i.
+struct SrcSeg {
+    unsigned long long h0;
+    uint32_t n, off;
+    uint32_t job, batch;
+};
+
+struct RunDev {
+    float ecut_g, ecut_e;      // shared by every job (the tables depend on them)
+    const JobDev* jobs;
+    JobCtl* jc;
+    int n_jobs;                // job slots in use
+    int nb;                    // energy bins per job of the re-binning
     Particle* buf[2][2];       // [ring][buffer]
     uint32_t mask[2];          // capacity - 1
     uint32_t hard[2];          // fill above which a reservation fails

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -26,14 +27,14 @@
 #include "tables.h"
 
 namespace gdpm {
-hipError_t launch_setup(hipStream_t st, Ctl* ctl, int ri);
-hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const Geom& G, const SourceDev& S,
-                         const RunDev& R, int ri, unsigned long long h0, uint32_t n);
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri);
+hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, const SrcSeg* segs,
+                         int nseg, uint32_t total, int ri);
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri);
-size_t transport_lds_bytes(int ri, const Tables& T);
+size_t transport_lds_bytes(int ri, const Tables& T, int waves);
 hipError_t transport_lds_optin(size_t bytes);
 hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, Ctl* ctl,
-                            const Tables& T, const Geom& G, const RunDev& R);
+                            const Tables& T, const RunDev& R);
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
                         float lo, float inv);
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
@@ -167,7 +168,7 @@ struct gdpm_context_s {
     hipStream_t stream = nullptr;
     int cu_count = 0;
     int ring_log2 = 25;
-    int waves_per_cu = 16;
+    int waves_per_cu = 12;
     int rebin_bins = 16;
     int lds_tables = 1;          // stage interpolation tables in LDS when they fit
     int pass_histories = 0;      // new histories per iteration (0: a quarter of a queue)
@@ -179,7 +180,11 @@ struct gdpm_context_s {
     DevBuf rings[2][2];
     DevBuf ctl;
     Ctl* host_ctl = nullptr;   // pinned mirror
-    DevBuf tally, dose, sigma, hist, inv_n, mumax;
+    DevBuf jobs_dev, jc, segs, inv_n;
+    JobDev* h_jobs = nullptr;  // pinned: job table, source segments, the read-back
+    SrcSeg* h_segs = nullptr;  // part of the job counters, statistics reductions
+    void* h_jc = nullptr;
+    double* h_red = nullptr;
     std::vector<hipEvent_t> events;
     bool busy = false;
 };
@@ -227,6 +232,16 @@ struct gdpm_job_s {
 };
 
 namespace {
+
+constexpr int kMaxBlockThreads = 768;   // launch bound of the transport kernels
+constexpr int kMaxSegs = 4096;          // source segments per iteration (both types)
+// the host reads back the first four arrays of JobCtl after every iteration
+struct JobCtlMirror {
+    unsigned long long births[kMaxJobs], deaths[kMaxJobs];
+    double e_in[kMaxJobs], e_esc[kMaxJobs];
+};
+constexpr size_t kJcMirrorBytes = sizeof(JobCtlMirror);
+static_assert(offsetof(JobCtl, seg_begin) == kJcMirrorBytes, "JobCtl starts with the read-back arrays");
 
 Geom geom_of(const gdpm_phantom_s* ph) {
     Geom g;
@@ -278,7 +293,7 @@ gdpm_status ensure_rings(gdpm_context ctx) {
 
 // persistent transport grid: one workgroup of waves_per_cu wavefronts per CU
 int grid_blocks(gdpm_context ctx) { return std::max(1, ctx->cu_count); }
-int block_threads(gdpm_context ctx) { return std::min(1024, 64 * ctx->waves_per_cu); }
+int block_threads(gdpm_context ctx) { return std::min(kMaxBlockThreads, 64 * ctx->waves_per_cu); }
 
 // ---------------------------------------------------------------------------
 // one run
@@ -319,166 +334,97 @@ struct Timers {
     uint32_t passes = 0, passes_photon = 0, passes_electron = 0;
 };
 
-// run transport for histories [h0, h1) into the tally slot R.tally.  Each
-// iteration: new histories into the queue of the source particle type, then
-// one pass per particle type, the source type first.
-gdpm_status run_round(gdpm_context ctx, const Tables& T, const Geom& G, const SourceDev& S,
-                      RunDev R, hipStream_t st, uint64_t h0, uint64_t h1, Timers* tm) {
-    Ctl* hc = ctx->host_ctl;   // mirrors the device block after each iteration
-    Ctl* dc = ctx->ctl.as<Ctl>();
-    const int blocks = grid_blocks(ctx);
-    const int src_type = S.particle == 0 ? 0 : 1;
-    const int nbins = std::min(ctx->rebin_bins, kMaxBins);
-    const float blo = -5.0f, bhi = 5.0f;  // log2 E range of the bins (0.03 .. 32 MeV)
-    const float binv = nbins > 0 ? nbins / (bhi - blo) : 0.0f;
-    // new histories per iteration: at most half a queue, less what the fuller
-    // queue still holds, so that the pushes of a pass stay below the capacity
-    // (a full queue is still detected and reported as an overflow)
-    const uint32_t cap = 1u << ctx->ring_log2;
-    const uint32_t budget = ctx->pass_histories > 0 ? (uint32_t)ctx->pass_histories : cap / 2u;
-    if (ctx->events.size() < 4) {
-        for (size_t i = ctx->events.size(); i < 4; ++i) {
-            hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e));
-            ctx->events.push_back(e);
-        }
-    }
-    uint64_t next = h0;
-    for (int iter = 0;; ++iter) {
-        const uint32_t fill = std::max(hc->ring[0].tail - hc->ring[0].head,
-                                       hc->ring[1].tail - hc->ring[1].head);
-        const uint64_t room = fill < budget ? budget - fill : 0u;
-        const uint32_t n_src = (uint32_t)std::min<uint64_t>(h1 - next, room);
-        if (n_src > 0) {
-            const int sb = (int)std::min<uint64_t>((n_src + 255) / 256, 8u * (uint64_t)blocks);
-            HIP_TRY(launch_source(st, sb, dc, G, S, R, src_type, next, n_src));
-            next += n_src;
-        }
-        for (int k = 0; k < 2; ++k) {
-            const int ri = k == 0 ? src_type : 1 - src_type;
-            // compact the queue and sort it by energy so that wavefronts draw
-            // particles of similar energy
-            if (nbins > 1) HIP_TRY(launch_rebin(st, 4 * blocks, dc, R, ri, nbins, blo, binv));
-            HIP_TRY(launch_setup(st, dc, ri));
-            HIP_TRY(hipEventRecord(ctx->events[2 * k], st));
-            const bool lds = ctx->lds_tables && transport_lds_bytes(ri, T) <= (size_t)ctx->max_lds;
-            HIP_TRY(launch_transport(st, ri, blocks, block_threads(ctx), lds, dc, T, G, R));
-            HIP_TRY(hipEventRecord(ctx->events[2 * k + 1], st));
-            HIP_TRY(launch_finish(st, dc, ri));
-            tm->passes++;
-            (ri == 0 ? tm->passes_photon : tm->passes_electron)++;
-        }
-        HIP_TRY(hipMemcpyAsync(hc, dc, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        for (int k = 0; k < 2; ++k) {
-            float ms = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
-            const int ri = k == 0 ? src_type : 1 - src_type;
-            (ri == 0 ? tm->photon : tm->electron) += ms * 1e-3;
-        }
-        if (hc->overflow)
-            return fail(GDPM_E_OVERFLOW,
-                        "a particle queue filled up (capacity 2^%d); raise ring_capacity_log2",
-                        ctx->ring_log2);
-        const bool empty = hc->ring[0].tail == hc->ring[0].head &&
-                           hc->ring[1].tail == hc->ring[1].head && next >= h1;
-        if (empty) break;
-        if (iter > 100000) return fail(GDPM_E_DEVICE, "transport made no progress");
-    }
-    return GDPM_OK;
-}
+// ---------------------------------------------------------------------------
+// the transport engine: up to kMaxJobs dose jobs share the particle queues and
+// every kernel launch.  Each job keeps its own phantom, source, random key,
+// batch tallies and statistics; a job's results do not depend on which other
+// jobs run beside it (its particles draw only from the job's own streams).
+//
+// Batches follow the paper's scheme (section 2.2.1): a job's histories are cut
+// into super-rounds of N_b rounds, round b of a super-round feeding batch
+// slot b.  Records carry their batch slot, so rounds and jobs overlap in the
+// queues; a super-round is complete when all its histories were started and
+// the job's particle births equal its deaths.
+// ---------------------------------------------------------------------------
+struct EJob {
+    gdpm_phantom_s* ph = nullptr;
+    gdpm_source_s* src = nullptr;
+    gdpm_run_params prm{};
+    RunPlan plan{};
+    int slot = -1;
+    size_t nv = 0;
+    DevBuf tally, mumax, hist, dose_buf, sigma_buf;
+    double* d_dose = nullptr;   // outputs in device memory
+    double* d_sigma = nullptr;
+    uint64_t hbase = 0;         // id of the job's first history
+    uint64_t issued = 0;        // histories started (relative ids [0, issued))
+    uint64_t sr_start = 0, sr_end = 0;  // the running super-round
+    uint64_t round_size = 0;
+    uint64_t max_hist = 0;
+    std::vector<double> nhist;  // histories per batch slot
+    uint32_t rounds = 0;
+    double unc = 0, dmax = 0, edep = 0, e_in = 0, e_esc = 0;
+    unsigned long long births = 0, deaths = 0;
+    gdpm_status status = GDPM_OK;
+    bool done = false;
+    std::string err;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    size_t footprint = 0;       // device bytes the job owns while admitted
+};
 
-gdpm_status compute_stats(gdpm_context ctx, gdpm_phantom_s* ph, int nb,
-                          const std::vector<double>& nhist, float min_rho, hipStream_t st,
-                          double* d_dose,
-                          double* d_sigma, double* unc, double* dmax, double* edep) {
+size_t job_footprint(const gdpm_phantom_s* ph, const RunPlan& plan, bool own_outputs, int pg_n) {
     const size_t nv = (size_t)ph->nx * ph->ny * ph->nz;
-    std::vector<double> inv(nb);
-    for (int b = 0; b < nb; ++b) inv[b] = nhist[b] > 0 ? 1.0 / nhist[b] : 0.0;
-    HIP_TRY(ctx->inv_n.ensure(nb * sizeof(double)));
-    HIP_TRY(hipMemcpyAsync(ctx->inv_n.p, inv.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
-    Ctl* dc = ctx->ctl.as<Ctl>();
-    Ctl* hc = ctx->host_ctl;
-    hc->red[0] = hc->red[1] = hc->red[2] = hc->red[3] = 0.0;
-    hc->dmax_bits = 0;
-    HIP_TRY(hipMemcpyAsync(&dc->red[0], &hc->red[0], 4 * sizeof(double) + sizeof(unsigned long long),
-                           hipMemcpyHostToDevice, st));
-    const int blocks = (int)std::min<size_t>((nv + 255) / 256, 8192);
-    HIP_TRY(launch_stats(st, blocks, dc, ctx->tally.as<const double>(), nv, nb,
-                         ctx->inv_n.as<const double>(), ph->vox.as<const uint2>(),
-                         ph->dx * ph->dy * ph->dz, min_rho, d_dose, d_sigma));
-    HIP_TRY(hipMemcpyAsync(&hc->red[0], &dc->red[0], 4 * sizeof(double) + sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    double dm;
-    memcpy(&dm, &hc->dmax_bits, sizeof dm);
-    *dmax = dm;
-    *edep = hc->red[0];
-    *unc = (hc->red[2] > 0 && dm > 0) ? hc->red[1] / hc->red[2] / dm : 0.0;
-    return GDPM_OK;
+    return (size_t)plan.nb * nv * sizeof(double) + (own_outputs ? 2 * nv * sizeof(double) : 0) +
+           (size_t)pg_n * sizeof(float);
 }
 
-gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdpm_run_params* prm,
-                   double* d_dose, double* d_sigma, double* h_batch, double* h_hist,
-                   hipStream_t st, gdpm_run_stats* out) {
-    const double t_start = now_s();
-    if (!ctx || !ph || !src) return fail(GDPM_E_INVALID, "NULL handle");
-    if (ph->ctx != ctx || src->ctx != ctx) return fail(GDPM_E_INVALID, "handle of another context");
-    RunPlan plan;
-    gdpm_status s = validate_params(prm, src, &plan);
-    if (s) return s;
-    if ((int)ph->rho_max.size() > (int)ctx->mats.size())
-        return fail(GDPM_E_INVALID, "phantom uses more materials than the context has");
-    if (h_hist && (plan.target || plan.n_hist > ((uint64_t)1 << 24)))
-        return fail(GDPM_E_INVALID, "per-history output needs fixed mode and <= 2^24 histories");
+struct Engine {
+    gdpm_context ctx = nullptr;
+    hipStream_t st = nullptr;
     DevTables* tab = nullptr;
-    s = get_tables(ctx, plan.ecut_g, plan.ecut_e, plan.flags, &tab);
-    if (s) return s;
-    s = ensure_rings(ctx);
-    if (s) return s;
-    // Woodcock majorant of this phantom
-    std::vector<double> rmax(tab->host.n_mat, 0.0);
-    for (size_t m = 0; m < ph->rho_max.size(); ++m) rmax[m] = ph->rho_max[m];
-    const std::vector<float> mm = build_majorant(tab->host, rmax);
-    HIP_TRY(ctx->mumax.ensure(mm.size() * sizeof(float)));
-    HIP_TRY(hipMemcpyAsync(ctx->mumax.p, mm.data(), mm.size() * sizeof(float), hipMemcpyHostToDevice, st));
-    const Tables T = tab->view(ctx->mumax.as<const float>());
-    const Geom G = geom_of(ph);
-    const SourceDev S = src->view();
-    const size_t nv = (size_t)ph->nx * ph->ny * ph->nz;
-    const int nb = plan.nb;
+    TableKey key{};
+    RunDev R{};
+    Tables T{};
+    std::vector<EJob*> slots;
+    int n_slots = 0;            // slots in use: [0, n_slots)
+    Timers tm;
+    uint32_t iter = 0, idle = 0;
+    unsigned long long ev_base[8] = {};
 
-    HIP_TRY(ctx->tally.ensure((size_t)nb * nv * sizeof(double)));
-    HIP_TRY(hipMemsetAsync(ctx->tally.p, 0, (size_t)nb * nv * sizeof(double), st));
-    double* dd = d_dose;
-    double* ds = d_sigma;
-    if (!dd) {
-        HIP_TRY(ctx->dose.ensure(nv * sizeof(double)));
-        dd = ctx->dose.as<double>();
+    gdpm_status init(gdpm_context c, hipStream_t s, const RunPlan& plan);
+    gdpm_status admit(EJob* j);
+    gdpm_status step();
+    gdpm_status settle();       // super-round ends, statistics, finished jobs
+    void release(EJob* j);
+    bool any_active() const {
+        for (int i = 0; i < n_slots; ++i)
+            if (slots[i] && !slots[i]->done) return true;
+        return false;
     }
-    if (!ds) {
-        HIP_TRY(ctx->sigma.ensure(nv * sizeof(double)));
-        ds = ctx->sigma.as<double>();
-    }
-    if (h_hist) {
-        HIP_TRY(ctx->hist.ensure(plan.n_hist * 2 * sizeof(double)));
-        HIP_TRY(hipMemsetAsync(ctx->hist.p, 0, plan.n_hist * 2 * sizeof(double), st));
-    }
-    // control block: empty queues, zero counters
+};
+
+gdpm_status Engine::init(gdpm_context c, hipStream_t s, const RunPlan& plan) {
+    ctx = c;
+    st = s;
+    slots.assign(kMaxJobs, nullptr);
+    n_slots = 0;
+    key = TableKey{plan.ecut_g, plan.ecut_e, plan.flags & 0x3Fu};
+    gdpm_status e = get_tables(ctx, plan.ecut_g, plan.ecut_e, plan.flags, &tab);
+    if (e) return e;
+    e = ensure_rings(ctx);
+    if (e) return e;
+    T = tab->view(nullptr);
     Ctl* hc = ctx->host_ctl;
     memset(hc, 0, sizeof(Ctl));
-    Ctl* dc = ctx->ctl.as<Ctl>();
-    HIP_TRY(hipMemcpyAsync(dc, hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
-
-    RunDev R;
+    HIP_TRY(hipMemcpyAsync(ctx->ctl.p, hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(ctx->jc.p, 0, sizeof(JobCtl), st));
+    memset(ctx->h_jc, 0, kJcMirrorBytes);
     memset(&R, 0, sizeof R);
-    R.k0 = (uint32_t)prm->seed;
-    R.k1 = (uint32_t)(prm->seed >> 32) ^ prm->job_id;
     R.ecut_g = (float)plan.ecut_g;
     R.ecut_e = (float)plan.ecut_e;
-    R.flags = plan.flags;
-    R.hist = h_hist ? ctx->hist.as<double>() : nullptr;
-    R.hist0 = prm->hist0;
+    R.jobs = ctx->jobs_dev.as<const JobDev>();
+    R.jc = ctx->jc.as<JobCtl>();
+    R.n_jobs = 0;
     const uint32_t cap = 1u << ctx->ring_log2;
     for (int r = 0; r < 2; ++r) {
         R.buf[r][0] = ctx->rings[r][0].as<Particle>();
@@ -486,80 +432,340 @@ gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdp
         R.mask[r] = cap - 1u;
         R.hard[r] = cap;
     }
-
-    std::vector<double> nhist(nb, 0.0);
-    Timers tm;
-    uint64_t done = 0;
-    uint32_t rounds = 0;
-    double unc = 0.0, dmax = 0.0, edep = 0.0;
-    const uint64_t max_hist = prm->max_histories ? prm->max_histories : 100 * plan.n_hist;
-    uint64_t round_size = prm->round_size ? prm->round_size : (plan.n_hist + nb - 1) / nb;
-    gdpm_status final = GDPM_OK;
-    const uint64_t hbase = plan.target ? 0 : prm->hist0;
-    for (;;) {
-        // one super-round: N_b rounds of round_size histories, one per batch slot
-        for (int b = 0; b < nb; ++b) {
-            uint64_t h0 = hbase + done, h1 = h0 + round_size;
-            if (!plan.target) h1 = std::min(h1, prm->hist0 + plan.n_hist);
-            if (h1 <= h0) continue;
-            R.tally = ctx->tally.as<double>() + (size_t)b * nv;
-            s = run_round(ctx, T, G, S, R, st, h0, h1, &tm);
-            if (s) return s;
-            nhist[b] += (double)(h1 - h0);
-            done += h1 - h0;
-            rounds++;
+    if (ctx->events.size() < 4) {
+        for (size_t i = ctx->events.size(); i < 4; ++i) {
+            hipEvent_t ev;
+            HIP_TRY(hipEventCreate(&ev));
+            ctx->events.push_back(ev);
         }
-        s = compute_stats(ctx, ph, nb, nhist, (float)prm->stat_min_density, st, dd, ds, &unc,
-                          &dmax, &edep);
-        if (s) return s;
-        if (!plan.target) break;
-        if (unc <= prm->target_unc) break;
-        if (done >= max_hist) {
-            final = GDPM_E_NOT_CONVERGED;
-            fail(GDPM_E_NOT_CONVERGED, "uncertainty %.4g above target after %llu histories", unc,
-                 (unsigned long long)done);
+    }
+    tm = Timers{};
+    iter = idle = 0;
+    return GDPM_OK;
+}
+
+// validate a job against the engine and give it a slot, buffers and its first super-round
+gdpm_status Engine::admit(EJob* j) {
+    if (!j->ph || !j->src) return fail(GDPM_E_INVALID, "NULL handle");
+    if (j->ph->ctx != ctx || j->src->ctx != ctx) return fail(GDPM_E_INVALID, "handle of another context");
+    if (TableKey{j->plan.ecut_g, j->plan.ecut_e, j->plan.flags & 0x3Fu} < key ||
+        key < TableKey{j->plan.ecut_g, j->plan.ecut_e, j->plan.flags & 0x3Fu})
+        return fail(GDPM_E_INVALID, "jobs run together must share cutoffs and physics flags");
+    if ((int)j->ph->rho_max.size() > tab->host.n_mat)
+        return fail(GDPM_E_INVALID, "phantom uses more materials than the context has");
+    int slot = -1;
+    for (int i = 0; i < kMaxJobs; ++i)
+        if (!slots[i]) {
+            slot = i;
             break;
         }
-        // histories still needed, from sigma ~ 1/sqrt(N), with a 5% margin
-        const double need = (double)done * ((unc / prm->target_unc) * (unc / prm->target_unc) * 1.05 - 1.0);
-        uint64_t more = (uint64_t)std::ceil(std::max(need, 0.02 * (double)done));
-        more = std::min<uint64_t>(more, max_hist - done);
-        round_size = std::max<uint64_t>(1, (more + nb - 1) / nb);
+    if (slot < 0) return fail(GDPM_E_BUSY, "all %d job slots are in use", kMaxJobs);
+    const RunPlan& plan = j->plan;
+    const size_t nv = (size_t)j->ph->nx * j->ph->ny * j->ph->nz;
+    j->nv = nv;
+    j->slot = slot;
+    // Woodcock majorant of this job's phantom
+    std::vector<double> rmax(tab->host.n_mat, 0.0);
+    for (size_t m = 0; m < j->ph->rho_max.size(); ++m) rmax[m] = j->ph->rho_max[m];
+    const std::vector<float> mm = build_majorant(tab->host, rmax);
+    HIP_TRY(j->mumax.alloc(mm.size() * sizeof(float)));
+    HIP_TRY(hipMemcpyAsync(j->mumax.p, mm.data(), mm.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    HIP_TRY(j->tally.alloc((size_t)plan.nb * nv * sizeof(double)));
+    HIP_TRY(hipMemsetAsync(j->tally.p, 0, (size_t)plan.nb * nv * sizeof(double), st));
+    if (!j->d_dose) {
+        HIP_TRY(j->dose_buf.alloc(nv * sizeof(double)));
+        j->d_dose = j->dose_buf.as<double>();
     }
-    // counters
+    if (!j->d_sigma) {
+        HIP_TRY(j->sigma_buf.alloc(nv * sizeof(double)));
+        j->d_sigma = j->sigma_buf.as<double>();
+    }
+    double* hist = nullptr;
+    if (j->hist.bytes) {
+        HIP_TRY(hipMemsetAsync(j->hist.p, 0, j->hist.bytes, st));
+        hist = j->hist.as<double>();
+    }
+    JobDev& d = ctx->h_jobs[slot];
+    memset(&d, 0, sizeof d);
+    d.G = geom_of(j->ph);
+    d.S = j->src->view();
+    d.mumax = j->mumax.as<const float>();
+    d.tally = j->tally.as<double>();
+    d.nv = nv;
+    d.hist = hist;
+    d.hist0 = j->prm.hist0;
+    d.k0 = (uint32_t)j->prm.seed;
+    d.k1 = (uint32_t)(j->prm.seed >> 32) ^ j->prm.job_id;
+    d.flags = plan.flags;
+    HIP_TRY(hipMemcpyAsync(ctx->jobs_dev.as<JobDev>() + slot, &d, sizeof d, hipMemcpyHostToDevice, st));
+    // the job's counters start from zero
+    JobCtl* dj = ctx->jc.as<JobCtl>();
+    HIP_TRY(hipMemsetAsync(&dj->births[slot], 0, sizeof(unsigned long long), st));
+    HIP_TRY(hipMemsetAsync(&dj->deaths[slot], 0, sizeof(unsigned long long), st));
+    HIP_TRY(hipMemsetAsync(&dj->e_in[slot], 0, sizeof(double), st));
+    HIP_TRY(hipMemsetAsync(&dj->e_esc[slot], 0, sizeof(double), st));
+    j->births = j->deaths = 0;
+    // schedule: fixed mode is one super-round; target mode starts from n_histories
+    j->hbase = plan.target ? 0 : j->prm.hist0;
+    j->issued = 0;
+    j->nhist.assign(plan.nb, 0.0);
+    j->max_hist = j->prm.max_histories ? j->prm.max_histories : 100 * plan.n_hist;
+    j->round_size = j->prm.round_size ? j->prm.round_size : (plan.n_hist + plan.nb - 1) / plan.nb;
+    j->sr_start = 0;
+    j->sr_end = plan.target ? (uint64_t)plan.nb * j->round_size
+                            : std::min<uint64_t>(plan.n_hist, (uint64_t)plan.nb * j->round_size);
+    j->done = false;
+    j->status = GDPM_OK;
+    j->t_admit = now_s();
+    slots[slot] = j;
+    n_slots = std::max(n_slots, slot + 1);
+    return GDPM_OK;
+}
+
+void Engine::release(EJob* j) {
+    if (j->slot >= 0 && slots[j->slot] == j) slots[j->slot] = nullptr;
+    while (n_slots > 0 && !slots[n_slots - 1]) --n_slots;
+    j->slot = -1;
+}
+
+// one scheduler iteration: new histories, a photon pass, an electron pass
+gdpm_status Engine::step() {
+    Ctl* hc = ctx->host_ctl;
+    Ctl* dc = ctx->ctl.as<Ctl>();
+    const int blocks = grid_blocks(ctx);
+    const uint32_t cap = 1u << ctx->ring_log2;
+    // new histories: at most half a queue (or pass_histories) less what the
+    // fuller queue holds, shared evenly by the jobs that still start histories
+    const uint32_t budget = ctx->pass_histories > 0 ? (uint32_t)ctx->pass_histories : cap / 2u;
+    const uint32_t fill = std::max(hc->ring[0].tail - hc->ring[0].head, hc->ring[1].tail - hc->ring[1].head);
+    uint64_t room = fill < budget ? budget - fill : 0u;
+    std::vector<EJob*> want;
+    for (int i = 0; i < n_slots; ++i) {
+        EJob* j = slots[i];
+        if (j && !j->done && j->issued < j->sr_end) want.push_back(j);
+    }
+    int nseg[2] = {0, 0};
+    uint32_t total[2] = {0u, 0u};
+    SrcSeg* hs = ctx->h_segs;
+    const int seg_cap = kMaxSegs / 2;   // per source type
+    for (size_t k = 0; k < want.size() && room > 0; ++k) {
+        EJob* j = want[k];
+        const uint64_t share = std::max<uint64_t>(1, room / (want.size() - k));
+        uint64_t n = std::min<uint64_t>(share, j->sr_end - j->issued);
+        const int ri = j->src->particle == 0 ? 0 : 1;
+        while (n > 0 && nseg[ri] < seg_cap) {
+            const uint64_t rel = j->issued - j->sr_start;
+            const uint32_t b = (uint32_t)std::min<uint64_t>(rel / j->round_size, j->plan.nb - 1);
+            const uint64_t round_end = std::min(j->sr_end, j->sr_start + (b + 1) * j->round_size);
+            const uint64_t m = std::min(n, round_end - j->issued);
+            SrcSeg& sg = hs[ri * seg_cap + nseg[ri]++];
+            sg.h0 = j->hbase + j->issued;
+            sg.n = (uint32_t)m;
+            sg.off = total[ri];
+            sg.job = (uint32_t)j->slot;
+            sg.batch = b;
+            total[ri] += (uint32_t)m;
+            j->issued += m;
+            j->nhist[b] += (double)m;
+            room -= m;
+            n -= m;
+        }
+    }
+    R.n_jobs = std::max(n_slots, 1);
+    for (int ri = 0; ri < 2; ++ri) {
+        if (!nseg[ri]) continue;
+        SrcSeg* dseg = ctx->segs.as<SrcSeg>() + ri * seg_cap;
+        HIP_TRY(hipMemcpyAsync(dseg, hs + ri * seg_cap, nseg[ri] * sizeof(SrcSeg), hipMemcpyHostToDevice, st));
+        const int sb = (int)std::min<uint64_t>((total[ri] + 255) / 256, 4u * (uint64_t)blocks);
+        HIP_TRY(launch_source(st, sb, dc, R, dseg, nseg[ri], total[ri], ri));
+    }
+    // energy bins per job so that jobs x bins fits the re-binning keys
+    const int nb = std::max(1, std::min(std::min(ctx->rebin_bins, kMaxBins), kMaxKeys / R.n_jobs));
+    const float blo = -5.0f, bhi = 5.0f;  // log2 E range of the bins (0.03 .. 32 MeV)
+    const float binv = nb / (bhi - blo);
+    for (int ri = 0; ri < 2; ++ri) {
+        // compact the queue and sort it by job and energy
+        HIP_TRY(launch_rebin(st, 4 * blocks, dc, R, ri, nb, blo, binv));
+        HIP_TRY(launch_setup(st, dc, R, ri));
+        HIP_TRY(hipEventRecord(ctx->events[2 * ri], st));
+        const int threads = block_threads(ctx);
+        const bool lds = ctx->lds_tables && transport_lds_bytes(ri, T, threads / 64) <= (size_t)ctx->max_lds;
+        HIP_TRY(launch_transport(st, ri, blocks, threads, lds, dc, T, R));
+        HIP_TRY(hipEventRecord(ctx->events[2 * ri + 1], st));
+        HIP_TRY(launch_finish(st, dc, ri));
+        tm.passes++;
+        (ri == 0 ? tm.passes_photon : tm.passes_electron)++;
+    }
     HIP_TRY(hipMemcpyAsync(hc, dc, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ctx->h_jc, ctx->jc.p, kJcMirrorBytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int ri = 0; ri < 2; ++ri) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->events[2 * ri], ctx->events[2 * ri + 1]));
+        (ri == 0 ? tm.photon : tm.electron) += ms * 1e-3;
+    }
+    ++iter;
+    if (hc->overflow)
+        return fail(GDPM_E_OVERFLOW, "a particle queue filled up (capacity 2^%d); raise ring_capacity_log2",
+                    ctx->ring_log2);
+    return GDPM_OK;
+}
+
+gdpm_status compute_stats(gdpm_context ctx, EJob* j, hipStream_t st) {
+    const int nb = j->plan.nb;
+    const size_t nv = j->nv;
+    std::vector<double> inv(nb);
+    for (int b = 0; b < nb; ++b) inv[b] = j->nhist[b] > 0 ? 1.0 / j->nhist[b] : 0.0;
+    HIP_TRY(ctx->inv_n.ensure(nb * sizeof(double)));
+    HIP_TRY(hipMemcpyAsync(ctx->inv_n.p, inv.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
+    Ctl* dc = ctx->ctl.as<Ctl>();
+    double* red = ctx->h_red;
+    memset(red, 0, 4 * sizeof(double) + sizeof(unsigned long long));
+    HIP_TRY(hipMemcpyAsync(&dc->red[0], red, 4 * sizeof(double) + sizeof(unsigned long long),
+                           hipMemcpyHostToDevice, st));
+    const int blocks = (int)std::min<size_t>((nv + 255) / 256, 8192);
+    HIP_TRY(launch_stats(st, blocks, dc, j->tally.as<const double>(), nv, nb, ctx->inv_n.as<const double>(),
+                         j->ph->vox.as<const uint2>(), j->ph->dx * j->ph->dy * j->ph->dz,
+                         (float)j->prm.stat_min_density, j->d_dose, j->d_sigma));
+    HIP_TRY(hipMemcpyAsync(red, &dc->red[0], 4 * sizeof(double) + sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double dm;
+    memcpy(&dm, red + 4, sizeof dm);
+    j->dmax = dm;
+    j->edep = red[0];
+    j->unc = (red[2] > 0 && dm > 0) ? red[1] / red[2] / dm : 0.0;
+    return GDPM_OK;
+}
+
+// after an iteration: jobs whose super-round is complete get their statistics
+// and either finish or start the next super-round
+gdpm_status Engine::settle() {
+    bool progress = false;
+    const JobCtlMirror* m = reinterpret_cast<const JobCtlMirror*>(ctx->h_jc);
+    for (int i = 0; i < n_slots; ++i) {
+        EJob* j = slots[i];
+        if (!j || j->done) continue;
+        j->births = m->births[i];
+        j->deaths = m->deaths[i];
+        j->e_in = m->e_in[i];
+        j->e_esc = m->e_esc[i];
+        if (j->issued < j->sr_end || j->births != j->deaths) continue;
+        progress = true;
+        gdpm_status s = compute_stats(ctx, j, st);
+        if (s) return s;
+        j->rounds += (uint32_t)j->plan.nb;
+        const gdpm_run_params& p = j->prm;
+        bool finished = !j->plan.target || j->unc <= p.target_unc;
+        if (!finished && j->issued >= j->max_hist) {
+            finished = true;
+            j->status = GDPM_E_NOT_CONVERGED;
+            char buf[160];
+            snprintf(buf, sizeof buf, "uncertainty %.4g above target after %llu histories", j->unc,
+                     (unsigned long long)j->issued);
+            j->err = buf;
+        }
+        if (finished) {
+            j->done = true;
+            j->t_done = now_s();
+            continue;
+        }
+        // histories still needed, from sigma ~ 1/sqrt(N), with a 5% margin
+        const double done = (double)j->issued;
+        const double need = done * ((j->unc / p.target_unc) * (j->unc / p.target_unc) * 1.05 - 1.0);
+        uint64_t more = (uint64_t)std::ceil(std::max(need, 0.02 * done));
+        more = std::min<uint64_t>(more, j->max_hist - j->issued);
+        j->round_size = std::max<uint64_t>(1, (more + j->plan.nb - 1) / j->plan.nb);
+        j->sr_start = j->issued;
+        j->sr_end = j->issued + (uint64_t)j->plan.nb * j->round_size;
+    }
+    // nothing left anywhere but a job still waits: the bookkeeping is broken
+    const Ctl* hc = ctx->host_ctl;
+    const bool empty = hc->ring[0].tail == hc->ring[0].head && hc->ring[1].tail == hc->ring[1].head;
+    bool issuing = false;
+    for (int i = 0; i < n_slots; ++i)
+        if (slots[i] && !slots[i]->done && slots[i]->issued < slots[i]->sr_end) issuing = true;
+    idle = (!progress && empty && !issuing) ? idle + 1 : 0;
+    if (idle > 2) return fail(GDPM_E_DEVICE, "transport made no progress (particle accounting)");
+    return GDPM_OK;
+}
+
+void fill_stats(const Engine& E, const EJob* j, double t_start, gdpm_run_stats* out) {
+    memset(out, 0, sizeof *out);
+    const Ctl* hc = E.ctx->host_ctl;
+    out->histories = j->issued;
+    out->e_in = j->e_in;
+    out->e_esc = j->e_esc;
+    out->e_dep = j->edep;
+    out->unc_mean_over_dmax = j->unc;
+    out->dmax = j->dmax;
+    for (int i = 0; i < 8; ++i) out->events[i] = hc->ev[i];
+    out->events[GDPM_EV_HISTORIES] = j->issued;
+    out->passes = E.tm.passes;
+    out->passes_photon = E.tm.passes_photon;
+    out->passes_electron = E.tm.passes_electron;
+    for (int k = 0; k < 2; ++k) {
+        out->records_loaded[k] = hc->pass_ev[k][0];
+        out->records_stored[k] = hc->pass_ev[k][1];
+        out->deposits[k] = hc->pass_ev[k][2];
+    }
+    out->rounds = j->rounds;
+    out->t_photon_s = E.tm.photon;
+    out->t_electron_s = E.tm.electron;
+    out->t_kernel_s = E.tm.photon + E.tm.electron;
+    out->t_total_s = (j->t_done > 0 ? j->t_done : now_s()) - t_start;
+}
+
+gdpm_status make_job(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdpm_run_params* prm,
+                     EJob* j) {
+    if (!ph || !src) return fail(GDPM_E_INVALID, "NULL handle");
+    if (ph->ctx != ctx || src->ctx != ctx) return fail(GDPM_E_INVALID, "handle of another context");
+    gdpm_status s = validate_params(prm, src, &j->plan);
+    if (s) return s;
+    j->ph = ph;
+    j->src = src;
+    j->prm = *prm;
+    return GDPM_OK;
+}
+
+// one job through the engine, blocking; outputs stay in device memory
+gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdpm_run_params* prm,
+                   double* d_dose, double* d_sigma, double* h_batch, double* h_hist,
+                   hipStream_t st, gdpm_run_stats* out, EJob* keep) {
+    const double t_start = now_s();
+    if (!ctx) return fail(GDPM_E_INVALID, "NULL context");
+    EJob local;
+    EJob* j = keep ? keep : &local;
+    gdpm_status s = make_job(ctx, ph, src, prm, j);
+    if (s) return s;
+    if (h_hist && (j->plan.target || j->plan.n_hist > ((uint64_t)1 << 24)))
+        return fail(GDPM_E_INVALID, "per-history output needs fixed mode and <= 2^24 histories");
+    j->d_dose = d_dose;
+    j->d_sigma = d_sigma;
+    if (h_hist) HIP_TRY(j->hist.alloc(j->plan.n_hist * 2 * sizeof(double)));
+    Engine E;
+    s = E.init(ctx, st, j->plan);
+    if (s) return s;
+    s = E.admit(j);
+    if (s) return s;
+    while (!j->done) {
+        s = E.step();
+        if (s) return s;
+        s = E.settle();
+        if (s) return s;
+    }
+    const size_t nv = j->nv;
     if (h_batch)
-        HIP_TRY(hipMemcpyAsync(h_batch, ctx->tally.p, (size_t)nb * nv * sizeof(double),
+        HIP_TRY(hipMemcpyAsync(h_batch, j->tally.p, (size_t)j->plan.nb * nv * sizeof(double),
                                hipMemcpyDeviceToHost, st));
     if (h_hist)
-        HIP_TRY(hipMemcpyAsync(h_hist, ctx->hist.p, plan.n_hist * 2 * sizeof(double),
+        HIP_TRY(hipMemcpyAsync(h_hist, j->hist.p, j->plan.n_hist * 2 * sizeof(double),
                                hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (out) {
-        memset(out, 0, sizeof *out);
-        out->histories = done;
-        out->e_in = hc->e_in;
-        out->e_esc = hc->e_esc;
-        out->e_dep = edep;
-        out->unc_mean_over_dmax = unc;
-        out->dmax = dmax;
-        for (int i = 0; i < 8; ++i) out->events[i] = hc->ev[i];
-        out->events[GDPM_EV_HISTORIES] = done;
-        out->passes = tm.passes;
-        out->passes_photon = tm.passes_photon;
-        out->passes_electron = tm.passes_electron;
-        for (int k = 0; k < 2; ++k) {
-            out->records_loaded[k] = hc->pass_ev[k][0];
-            out->records_stored[k] = hc->pass_ev[k][1];
-            out->deposits[k] = hc->pass_ev[k][2];
-        }
-        out->rounds = rounds;
-        out->t_photon_s = tm.photon;
-        out->t_electron_s = tm.electron;
-        out->t_kernel_s = tm.photon + tm.electron;
-        out->t_total_s = now_s() - t_start;
-    }
-    return final;
+    if (out) fill_stats(E, j, t_start, out);
+    E.release(j);
+    if (j->status == GDPM_E_NOT_CONVERGED) fail(GDPM_E_NOT_CONVERGED, "%s", j->err.c_str());
+    return j->status;
 }
 
 }  // namespace
@@ -581,12 +787,13 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     auto ctx = std::make_unique<gdpm_context_s>();
     ctx->device = hip_device;
     ctx->ring_log2 = json_int(opts_json, "ring_capacity_log2", 25);
-    ctx->waves_per_cu = json_int(opts_json, "waves_per_cu", 16);
+    ctx->waves_per_cu = json_int(opts_json, "waves_per_cu", 12);
     ctx->rebin_bins = json_int(opts_json, "rebin_bins", 16);
     ctx->lds_tables = json_int(opts_json, "lds_tables", 1);
     ctx->pass_histories = json_int(opts_json, "pass_histories", 0);
     if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
-    if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > 64) return fail(GDPM_E_INVALID, "waves_per_cu in [1, 64]");
+    if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > kMaxBlockThreads / 64)
+        return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);
     if (ctx->rebin_bins < 0 || ctx->rebin_bins > kMaxBins) return fail(GDPM_E_INVALID, "rebin_bins in [0, 64]");
     if (ctx->pass_histories < 0) return fail(GDPM_E_INVALID, "pass_histories must be >= 0");
     HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device));
@@ -600,6 +807,13 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     HIP_TRY(ctx->ctl.alloc(sizeof(Ctl)));
     HIP_TRY(hipHostMalloc((void**)&ctx->host_ctl, sizeof(Ctl), hipHostMallocDefault));
     memset(ctx->host_ctl, 0, sizeof(Ctl));
+    HIP_TRY(ctx->jobs_dev.alloc(kMaxJobs * sizeof(JobDev)));
+    HIP_TRY(ctx->jc.alloc(sizeof(JobCtl)));
+    HIP_TRY(ctx->segs.alloc(kMaxSegs * sizeof(SrcSeg)));
+    HIP_TRY(hipHostMalloc((void**)&ctx->h_jobs, kMaxJobs * sizeof(JobDev), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&ctx->h_segs, kMaxSegs * sizeof(SrcSeg), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&ctx->h_jc, kJcMirrorBytes, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&ctx->h_red, 8 * sizeof(double), hipHostMallocDefault));
     *out = ctx.release();
     return GDPM_OK;
 }
@@ -610,6 +824,10 @@ gdpm_status gdpm_context_destroy(gdpm_context ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
+    if (ctx->h_jobs) (void)hipHostFree(ctx->h_jobs);
+    if (ctx->h_segs) (void)hipHostFree(ctx->h_segs);
+    if (ctx->h_jc) (void)hipHostFree(ctx->h_jc);
+    if (ctx->h_red) (void)hipHostFree(ctx->h_red);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return GDPM_OK;
@@ -818,12 +1036,15 @@ gdpm_status gdpm_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const g
     if (ctx->busy) return fail(GDPM_E_BUSY, "context busy");
     HIP_TRY(hipSetDevice(ctx->device));
     ctx->busy = true;
-    gdpm_status s = do_run(ctx, ph, src, prm, nullptr, nullptr, batch_edep, hist_out, ctx->stream, stats);
+    EJob job;
+    gdpm_status s = do_run(ctx, ph, src, prm, nullptr, nullptr, batch_edep, hist_out, ctx->stream,
+                           stats, &job);
     ctx->busy = false;
     if (s != GDPM_OK && s != GDPM_E_NOT_CONVERGED) return s;
-    const size_t nv = (size_t)ph->nx * ph->ny * ph->nz;
-    if (dose) HIP_TRY(hipMemcpy(dose, ctx->dose.p, nv * sizeof(double), hipMemcpyDeviceToHost));
-    if (sigma) HIP_TRY(hipMemcpy(sigma, ctx->sigma.p, nv * sizeof(double), hipMemcpyDeviceToHost));
+    const std::string msg = g_err;
+    if (dose) HIP_TRY(hipMemcpy(dose, job.d_dose, job.nv * sizeof(double), hipMemcpyDeviceToHost));
+    if (sigma) HIP_TRY(hipMemcpy(sigma, job.d_sigma, job.nv * sizeof(double), hipMemcpyDeviceToHost));
+    g_err = msg;
     return s;
 }
 
@@ -839,7 +1060,7 @@ gdpm_status gdpm_run_async(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
     memset(&job->stats, 0, sizeof job->stats);
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     ctx->busy = true;
-    job->status = do_run(ctx, ph, src, prm, d_dose, d_sigma, nullptr, nullptr, st, &job->stats);
+    job->status = do_run(ctx, ph, src, prm, d_dose, d_sigma, nullptr, nullptr, st, &job->stats, nullptr);
     ctx->busy = false;
     if (job->status != GDPM_OK && job->status != GDPM_E_NOT_CONVERGED) return job->status;
     *out = job.release();

@@ -473,60 +473,174 @@ GDPM_DEV void release(PushState& ps, Particle* buf, uint32_t mask) {
     ps.next = ps.end;
 }
 
-// Tail of a large pass: once a wavefront has nothing left to claim and fewer
-// than kTailLanes particles, it hands them to the next pass of the same type
-// instead of running them to the end at low lane occupancy.  The record keeps
-// the whole state, random stream position included, so nothing physical
-// changes.  Returns true if the lane wrote a record.
+// Counters kept per wavefront (scalar registers): updated only where the
+// wavefront is converged, from ballots of the lanes concerned.
+struct WaveTally {
+    uint32_t events;      // flights (photon pass) or steps (electron pass)
+    uint32_t pushes;      // secondaries written, all jobs
+    uint32_t ld, rq;      // records loaded from the queue, records handed on
+    uint32_t born, died;  // records created and particles ended, current job
+};
+
+// Hand particles to the next pass of the same type (the record keeps the whole
+// state, random stream position included, so nothing physical changes).
+// Returns true in the lanes that wrote a record.
 GDPM_DEV bool requeue(bool active, PushState& ps, uint32_t head, Ctl* ctl, RingCtl* rc, uint32_t hard,
-                      Particle* buf, uint32_t mask, const Particle& p) {
+                      Particle* buf, uint32_t mask, const Particle& p, WaveTally& c) {
     const uint64_t b = ballot(active);
     const uint32_t n = (uint32_t)__popcll(b);
     if (n == 0) return false;
     const Reservation res = reserve(ps, rc, head, hard, n, ctl);
+    if (res.ok) c.rq += n;
     if (!res.ok || !active) return false;
     store(buf, mask, slot_of(res, mbcnt(b)), p);
     return true;
 }
 
-struct ClaimState {
-    uint32_t next, end;  // claimed queue positions not yet handed out
-    uint32_t seen;       // the pass's claim counter as this wave last saw it
-    bool done;           // the pass has nothing left to claim
+// ---------------------------------------------------------------------------
+// the job a wavefront works on: loaded when the wavefront switches jobs and
+// held in scalar registers (a wavefront only ever holds one job's particles)
+// ---------------------------------------------------------------------------
+struct WJob {
+    Geom G;
+    const float* mumax;
+    double* tally;
+    unsigned long long nv;
+    double* hist;
+    unsigned long long hist0;
+    uint32_t k0, k1, flags;
+    int j;
+    uint32_t seg_begin, seg_count;   // the job's records in the running pass
 };
+
+template <class T>
+GDPM_DEV T uniform_copy(const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized fields");
+    T out;
+    const uint32_t* a = reinterpret_cast<const uint32_t*>(&v);
+    uint32_t* b = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) b[i] = __builtin_amdgcn_readfirstlane(a[i]);
+    return out;
+}
+
+GDPM_DEV void load_job(WJob& w, const RunDev& R, int j) {
+    j = __builtin_amdgcn_readfirstlane(j);
+    const JobDev& d = R.jobs[j];
+    w.G = uniform_copy(d.G);
+    w.mumax = uniform_copy(d.mumax);
+    w.tally = uniform_copy(d.tally);
+    w.nv = uniform_copy(d.nv);
+    w.hist = uniform_copy(d.hist);
+    w.hist0 = uniform_copy(d.hist0);
+    w.k0 = __builtin_amdgcn_readfirstlane(d.k0);
+    w.k1 = __builtin_amdgcn_readfirstlane(d.k1);
+    w.flags = __builtin_amdgcn_readfirstlane(d.flags);
+    w.j = j;
+    w.seg_begin = __builtin_amdgcn_readfirstlane(R.jc->seg_begin[j]);
+    w.seg_count = __builtin_amdgcn_readfirstlane(R.jc->seg_count[j]);
+}
+
+// first job of a wavefront: the pass input is split over the wavefronts of the
+// grid in proportion to the jobs' record counts; -1 if the pass is empty
+GDPM_DEV int first_job(const RunDev& R, uint32_t total) {
+    if (total == 0) return -1;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t pos = (uint32_t)(((unsigned long long)w * total + total / 2) / waves);
+    int lo = 0, hi = R.n_jobs - 1;   // last job whose segment starts at or before pos
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (__builtin_amdgcn_readfirstlane(R.jc->seg_begin[mid]) <= pos) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+GDPM_DEV unsigned long long load_agent64(const unsigned long long* p) {
+    const unsigned long long v = __hip_atomic_load(const_cast<unsigned long long*>(p),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (unsigned long long)hi << 32 | lo;
+}
+
+// the next job after j (cyclically) with unclaimed records in this pass, or -1
+GDPM_DEV int next_job(const JobCtl* jc, int j, int n_jobs) {
+    if (n_jobs <= 1) return -1;
+    const int nw = (n_jobs + 63) >> 6;
+    for (int k = 0; k <= nw; ++k) {
+        const int wi = ((j >> 6) + k) % nw;
+        unsigned long long m = load_agent64(&jc->left[wi]);
+        if (k == 0) {
+            const int b = j & 63;   // only jobs after j in j's own word
+            m = b == 63 ? 0ull : m & (~0ull << (b + 1));
+        } else if (k == nw) {
+            m &= (1ull << (j & 63)) - 1ull;   // jobs before j in j's word, last
+        }
+        if (m) {
+            const int c = wi * 64 + (__ffsll(m) - 1);
+            if (c < n_jobs && c != j) return c;
+        }
+    }
+    return -1;
+}
+
+// the job's majorant table: a copy in this wavefront's LDS slice when the
+// tables are staged, else the global array
+template <bool kLds>
+GDPM_DEV const float* job_majorant(const WJob& W, float* lmw, int n) {
+    if constexpr (kLds) {
+        for (int i = (int)lane_id(); i < n; i += 64) lmw[i] = W.mumax[i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        return lmw;
+    } else {
+        return W.mumax;
+    }
+}
+
+struct ClaimState {
+    uint32_t next, end;  // claimed positions of the job's segment not yet handed out
+    uint32_t seen;       // the job's claim counter as this wave last saw it
+    bool done;           // the job's segment has nothing left to claim
+};
+
 // ---------------------------------------------------------------------------
 // per-lane tallies
 // ---------------------------------------------------------------------------
 struct LaneTally {
     int dv;          // voxel of the pending deposit (-1 none)
     double de;       // pending deposit (MeV)
-    double e_esc;
+    double e_esc;    // escaped energy of the current job
     double h_dep, h_esc;  // per-history accumulators (test mode)
     uint32_t ev[7];
-    uint32_t ld, rq;      // records loaded from the queue, records handed on
 };
 
-GDPM_DEV void tally_flush(LaneTally& t, const RunDev& R) {
+
+// deposits go to the batch slot `pb` of the particle's history
+GDPM_DEV void tally_flush(LaneTally& t, const WJob& W, uint32_t pb) {
     if (t.dv >= 0 && t.de != 0.0) {
-        unsafeAtomicAdd(&R.tally[t.dv], t.de);
+        unsafeAtomicAdd(&W.tally[(unsigned long long)pb * W.nv + (unsigned)t.dv], t.de);
         t.ev[EV_DEPOSITS]++;
     }
     t.dv = -1;
     t.de = 0.0;
 }
 
-GDPM_DEV void deposit(LaneTally& t, const RunDev& R, int v, float e) {
-    if (v != t.dv) tally_flush(t, R);
+GDPM_DEV void deposit(LaneTally& t, const WJob& W, uint32_t pb, int v, float e) {
+    if (v != t.dv) tally_flush(t, W, pb);
     t.dv = v;
     t.de += (double)e;
     t.h_dep += (double)e;
 }
 
-GDPM_DEV void history_flush(LaneTally& t, const RunDev& R, uint32_t hlo, uint32_t hhi) {
-    if (R.hist) {
-        const unsigned long long h = ((unsigned long long)hhi << 32 | hlo) - R.hist0;
-        if (t.h_dep != 0.0) unsafeAtomicAdd(&R.hist[2 * h], t.h_dep);
-        if (t.h_esc != 0.0) unsafeAtomicAdd(&R.hist[2 * h + 1], t.h_esc);
+GDPM_DEV void history_flush(LaneTally& t, const WJob& W, uint32_t hlo, uint32_t hhi) {
+    if (W.hist) {
+        const unsigned long long h = ((unsigned long long)hhi << 32 | hlo) - W.hist0;
+        if (t.h_dep != 0.0) unsafeAtomicAdd(&W.hist[2 * h], t.h_dep);
+        if (t.h_esc != 0.0) unsafeAtomicAdd(&W.hist[2 * h + 1], t.h_esc);
     }
     t.h_dep = 0.0;
     t.h_esc = 0.0;
@@ -538,24 +652,34 @@ GDPM_DEV void tally_init(LaneTally& t) {
     t.e_esc = t.h_dep = t.h_esc = 0.0;
 #pragma unroll
     for (int i = 0; i < 7; ++i) t.ev[i] = 0u;
-    t.ld = t.rq = 0u;
 }
 
-// fold the lane counters into the run's; `ri` is the pass's particle type
-GDPM_DEV void tally_finish(LaneTally& t, const RunDev& R, Ctl* ctl, int ri) {
-    tally_flush(t, R);
+// fold the per-job counters into the job's (before a switch, at the end)
+GDPM_DEV void job_flush(LaneTally& t, WaveTally& c, const WJob& W, JobCtl* jc) {
     const double esc = wave_sum(t.e_esc);
+    if (lane_id() == 0) {
+        if (esc != 0.0) unsafeAtomicAdd(&jc->e_esc[W.j], esc);
+        if (c.born) atomicAdd(&jc->births[W.j], (unsigned long long)c.born);
+        if (c.died) atomicAdd(&jc->deaths[W.j], (unsigned long long)c.died);
+    }
+    t.e_esc = 0.0;
+    c.pushes += c.born;
+    c.born = c.died = 0u;
+}
+
+// fold the pass counters into the run's; `ri` is the pass's particle type
+GDPM_DEV void pass_finish(LaneTally& t, const WaveTally& c, Ctl* ctl, int ri) {
     uint32_t ev[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i) ev[i] = wave_sum(t.ev[i]);
-    const uint32_t ld = wave_sum(t.ld), rq = wave_sum(t.rq);
+    ev[ri == 0 ? EV_FLIGHTS : EV_ESTEPS] += c.events;
+    ev[EV_PUSHES] += c.pushes;
     if (lane_id() == 0) {
-        if (esc != 0.0) unsafeAtomicAdd(&ctl->e_esc, esc);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             if (ev[i]) atomicAdd(&ctl->ev[i], (unsigned long long)ev[i]);
-        atomicAdd(&ctl->pass_ev[ri][0], (unsigned long long)ld);
-        atomicAdd(&ctl->pass_ev[ri][1], (unsigned long long)(ev[EV_PUSHES] + rq));
+        atomicAdd(&ctl->pass_ev[ri][0], (unsigned long long)c.ld);
+        atomicAdd(&ctl->pass_ev[ri][1], (unsigned long long)(c.pushes + c.rq));
         atomicAdd(&ctl->pass_ev[ri][2], (unsigned long long)ev[EV_DEPOSITS]);
     }
 }
@@ -647,76 +771,92 @@ struct PendPhoton {
 
 GDPM_DEV void write_particle(Particle* buf, uint32_t mask, uint32_t slot, float x, float y, float z,
                              float e, float u, float v, float w, uint32_t hlo, uint32_t hhi,
-                             uint32_t path, uint32_t vox, float a, uint32_t flags) {
+                             uint32_t path, uint32_t vox, float a, uint32_t flags, uint32_t job) {
     float4* d = reinterpret_cast<float4*>(buf + (slot & mask));
     d[0] = make_float4(x, y, z, e);
     d[1] = make_float4(u, v, w, -1.0f);
     d[2] = make_float4(__uint_as_float(hlo), __uint_as_float(hhi), __uint_as_float(path), 0.0f);
-    d[3] = make_float4(__uint_as_float(vox), a, __uint_as_float(flags), 0.0f);
+    d[3] = make_float4(__uint_as_float(vox), a, __uint_as_float(flags), __uint_as_float(job));
 }
 
+// secondaries inherit the job and the batch slot (`jb`) of their history
 GDPM_DEV void push_charged(PendCharged& q, PushState& ps, uint32_t head, Ctl* ctl, const RunDev& R,
-                           Particle* buf, float x, float y, float z, uint32_t vox, const Rng& rng,
-                           LaneTally& t) {
+                           const WJob& W, uint32_t jb, Particle* buf, float x, float y, float z,
+                           uint32_t vox, const Rng& rng, WaveTally& c) {
     const uint64_t b0 = ballot(q.n >= 1), b1 = ballot(q.n >= 2);
     const uint32_t n0 = (uint32_t)__popcll(b0), n = n0 + (uint32_t)__popcll(b1);
     if (n == 0) return;
     const Reservation res = reserve(ps, &ctl->ring[1], head, R.hard[1], n, ctl);
     if (res.ok && q.n > 0) {
         write_particle(buf, R.mask[1], slot_of(res, mbcnt(b0)), x, y, z, q.e0, q.du, q.dv, q.dw,
-                       rng.hlo, rng.hhi, spawn_path(rng, R.k0, R.k1, (int)q.role), vox, q.a0,
-                       q.flag0);
+                       rng.hlo, rng.hhi, spawn_path(rng, W.k0, W.k1, (int)q.role), vox, q.a0,
+                       q.flag0, jb);
         if (q.n > 1)
             write_particle(buf, R.mask[1], slot_of(res, n0 + mbcnt(b1)), x, y, z, q.e1, q.du, q.dv,
-                           q.dw, rng.hlo, rng.hhi, spawn_path(rng, R.k0, R.k1, 1), vox, q.a1, 1u);
-        t.ev[EV_PUSHES] += (uint32_t)q.n;
+                           q.dw, rng.hlo, rng.hhi, spawn_path(rng, W.k0, W.k1, 1), vox, q.a1, 1u, jb);
     }
+    if (res.ok) c.born += n;
     q.n = 0;
 }
 
 GDPM_DEV void push_photons(PendPhoton& q, PushState& ps, uint32_t head, Ctl* ctl, const RunDev& R,
-                           Particle* buf, float x, float y, float z, const Rng& rng, LaneTally& t) {
+                           const WJob& W, uint32_t jb, Particle* buf, float x, float y, float z,
+                           const Rng& rng, WaveTally& c) {
     const uint64_t b0 = ballot(q.n >= 1), b1 = ballot(q.n >= 2);
     const uint32_t n0 = (uint32_t)__popcll(b0), n = n0 + (uint32_t)__popcll(b1);
     if (n == 0) return;
     const Reservation res = reserve(ps, &ctl->ring[0], head, R.hard[0], n, ctl);
     if (res.ok && q.n > 0) {
         write_particle(buf, R.mask[0], slot_of(res, mbcnt(b0)), x, y, z, q.e, q.u, q.v, q.w,
-                       rng.hlo, rng.hhi, spawn_path(rng, R.k0, R.k1, (int)q.wb), 0u, 0.0f, 0u);
+                       rng.hlo, rng.hhi, spawn_path(rng, W.k0, W.k1, (int)q.wb), 0u, 0.0f, 0u, jb);
         if (q.n > 1)
             write_particle(buf, R.mask[0], slot_of(res, n0 + mbcnt(b1)), x, y, z, q.e, -q.u, -q.v,
-                           -q.w, rng.hlo, rng.hhi, spawn_path(rng, R.k0, R.k1, (int)q.wb + 1), 0u,
-                           0.0f, 0u);
-        t.ev[EV_PUSHES] += (uint32_t)q.n;
+                           -q.w, rng.hlo, rng.hhi, spawn_path(rng, W.k0, W.k1, (int)q.wb + 1), 0u,
+                           0.0f, 0u, jb);
     }
+    if (res.ok) c.born += n;
     q.n = 0;
 }
 
 // ---------------------------------------------------------------------------
-// pass set-up and completion (single thread, between passes)
+// pass set-up and completion (one block, between passes): the job segments
+// come from the re-binning that precedes every pass
 // ---------------------------------------------------------------------------
-__global__ void k_setup(Ctl* ctl, int ri) {
-    RingCtl& r = ctl->ring[ri];
-    r.begin = r.head;
-    r.count = ctl->overflow ? 0u : r.tail - r.head;
-    r.claim = 0u;
+__global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri) {
+    JobCtl* jc = R.jc;
+    if (threadIdx.x == 0) {
+        RingCtl& r = ctl->ring[ri];
+        r.begin = r.head;
+        r.count = ctl->overflow ? 0u : r.tail - r.head;
+        r.claim = 0u;
+    }
+    for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) jc->claim[j] = 0u;
+    const int nw = (R.n_jobs + 63) >> 6;
+    for (int k = threadIdx.x; k < kMaxJobs / 64; k += blockDim.x) {
+        unsigned long long m = 0ull;
+        if (k < nw && !ctl->overflow)
+            for (int b = 0; b < 64 && k * 64 + b < R.n_jobs; ++b)
+                if (jc->seg_count[k * 64 + b] > 0u) m |= 1ull << b;
+        jc->left[k] = m;
+    }
 }
 
 __global__ void k_finish(Ctl* ctl, int ri) {
     RingCtl& r = ctl->ring[ri];
-    r.head = r.begin + min(r.claim, r.count);
+    r.head = r.begin + r.count;
     r.count = 0u;
 }
 
 // ---------------------------------------------------------------------------
-// claiming input: positions [0, count) of the pass's queue segment
+// claiming input: positions [0, seg_count) of the job's segment
 // ---------------------------------------------------------------------------
-GDPM_DEV void claim_refill(ClaimState& cs, RingCtl* rc, uint32_t count, const Ctl* ctl) {
+GDPM_DEV void claim_refill(ClaimState& cs, JobCtl* jc, const WJob& W, const Ctl* ctl) {
     if (cs.done || cs.next != cs.end) return;
-    // the wave has used up its items: claim a new chunk if the pass has more.
-    // Chunks shrink as the pass drains (guided self-scheduling), so that the
+    // the wave has used up its items: claim a new chunk if the job has more.
+    // Chunks shrink as the segment drains (guided self-scheduling), so that the
     // last items spread over many wavefronts.  The shared counters are touched
     // once per claim, never per iteration.
+    const uint32_t count = W.seg_count;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     const uint32_t left = count - min(cs.seen, count);
     const uint32_t chunk = min(max(left / (2u * waves), kClaimMin), kClaimMax);
@@ -726,10 +866,11 @@ GDPM_DEV void claim_refill(ClaimState& cs, RingCtl* rc, uint32_t count, const Ct
     }
     const uint32_t leader = first_lane(ballot(true));
     uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(&rc->claim, chunk);
+    if (lane_id() == leader) base = atomicAdd(&jc->claim[W.j], chunk);
     base = bcast(base, leader);
     cs.seen = base + chunk;
     if (base >= count) {
+        if (lane_id() == leader) atomicAnd(&jc->left[W.j >> 6], ~(1ull << (W.j & 63)));
         cs.done = true;
         return;
     }
@@ -739,73 +880,102 @@ GDPM_DEV void claim_refill(ClaimState& cs, RingCtl* rc, uint32_t count, const Ct
 
 // refill the lanes without a particle from the wave's claimed items; returns
 // true in the lanes that loaded a record
-GDPM_DEV bool refill(bool active, ClaimState& cs, RingCtl* rc, uint32_t begin, uint32_t count,
-                     const Ctl* ctl, const Particle* buf, uint32_t mask, Particle& p) {
+GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uint32_t begin,
+                     const Ctl* ctl, const Particle* buf, uint32_t mask, Particle& p, WaveTally& c) {
     if (cs.done) return false;
     const uint64_t need = ballot(!active);
     if (!need) return false;
-    claim_refill(cs, rc, count, ctl);
+    claim_refill(cs, jc, W, ctl);
     const uint32_t have = cs.end - cs.next;
     const uint32_t rank = mbcnt(need);
     const uint32_t take = min(have, (uint32_t)__popcll(need));
     bool got = false;
     if (!active && rank < take) {
-        p = load(buf, mask, begin + cs.next + rank);
+        p = load(buf, mask, begin + W.seg_begin + cs.next + rank);
         got = p.e >= 0.0f;
     }
     cs.next += take;
+    c.ld += take;
     return got;
 }
 
 // ---------------------------------------------------------------------------
-// source pass: histories [h0, h0 + n) -> primaries appended to the queue of
-// the source particle type (section 2.3); a primary whose ray misses the
-// phantom leaves an empty slot and counts as escaped
+// source pass: segments of new histories (job, first id, count, batch slot) ->
+// primaries appended to the queue of the source particle type (section 2.3);
+// a primary whose ray misses the phantom leaves an empty slot and counts as
+// escaped
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_source(Ctl* ctl, Geom G, SourceDev S, RunDev R, int ri,
-                                                unsigned long long h0, uint32_t n) {
+GDPM_DEV double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += sh[i];
+    return s;
+}
+
+__global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg* segs, int nseg,
+                                                uint32_t total, int ri) {
+    __shared__ double sh[4];
     if (ctl->overflow) return;
     const RingCtl& r = ctl->ring[ri];
     const uint32_t tail = r.tail;
-    if (tail + n - r.head > R.hard[ri]) {
+    if (tail + total - r.head > R.hard[ri]) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->overflow, 1u);
         return;
     }
     Particle* buf = R.buf[ri][r.cur];
-    const uint32_t k0 = R.k0, k1 = R.k1;
-    double e_in = 0.0, e_esc = 0.0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const unsigned long long h = h0 + i;
-        Rng rng;
-        rng_start(rng, (uint32_t)h, (uint32_t)(h >> 32), 0u, 0u);
-        rng_topup(rng, k0, k1);
-        const Primary pr = make_primary(S, G, rng, k0, k1);
-        e_in += (double)pr.e;
-        if (pr.in) {
-            uint32_t vox = 0u;
-            if (ri == 1) {
-                int ix, iy, iz;
-                voxel_of(G, pr.x, pr.y, pr.z, ix, iy, iz);
-                vox = pack_vox(ix, iy, iz);
+    const uint32_t nthreads = gridDim.x * blockDim.x;
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int s = 0; s < nseg; ++s) {
+        const SrcSeg sg = uniform_copy(segs[s]);
+        const JobDev& d = R.jobs[sg.job];
+        const Geom G = uniform_copy(d.G);
+        const SourceDev S = uniform_copy(d.S);
+        const uint32_t k0 = __builtin_amdgcn_readfirstlane(d.k0);
+        const uint32_t k1 = __builtin_amdgcn_readfirstlane(d.k1);
+        double* hist = uniform_copy(d.hist);
+        const unsigned long long hist0 = uniform_copy(d.hist0);
+        const uint32_t jb = sg.job | (sg.batch << 16);
+        double e_in = 0.0, e_esc = 0.0, born = 0.0;
+        for (uint32_t i = tid; i < sg.n; i += nthreads) {
+            const unsigned long long h = sg.h0 + i;
+            Rng rng;
+            rng_start(rng, (uint32_t)h, (uint32_t)(h >> 32), 0u, 0u);
+            rng_topup(rng, k0, k1);
+            const Primary pr = make_primary(S, G, rng, k0, k1);
+            e_in += (double)pr.e;
+            float4* q = reinterpret_cast<float4*>(buf + ((tail + sg.off + i) & R.mask[ri]));
+            if (pr.in) {
+                uint32_t vox = 0u;
+                if (ri == 1) {
+                    int ix, iy, iz;
+                    voxel_of(G, pr.x, pr.y, pr.z, ix, iy, iz);
+                    vox = pack_vox(ix, iy, iz);
+                }
+                // the stream continues at the draw after the source's draws
+                q[0] = make_float4(pr.x, pr.y, pr.z, pr.e);
+                q[1] = make_float4(pr.u, pr.v, pr.w, -1.0f);
+                q[2] = make_float4(__uint_as_float(rng.hlo), __uint_as_float(rng.hhi), 0.0f,
+                                   __uint_as_float(rng_ctr(rng)));
+                q[3] = make_float4(__uint_as_float(vox), 0.0f, 0.0f, __uint_as_float(jb));
+                born += 1.0;
+            } else {
+                reinterpret_cast<float*>(q)[3] = -1.0f;
+                e_esc += (double)pr.e;
+                if (hist) unsafeAtomicAdd(&hist[2 * (h - hist0) + 1], (double)pr.e);
             }
-            // the stream continues at the draw after the source's draws
-            float4* d = reinterpret_cast<float4*>(buf + ((tail + i) & R.mask[ri]));
-            d[0] = make_float4(pr.x, pr.y, pr.z, pr.e);
-            d[1] = make_float4(pr.u, pr.v, pr.w, -1.0f);
-            d[2] = make_float4(__uint_as_float(rng.hlo), __uint_as_float(rng.hhi), 0.0f,
-                               __uint_as_float(rng_ctr(rng)));
-            d[3] = make_float4(__uint_as_float(vox), 0.0f, 0.0f, 0.0f);
-        } else {
-            reinterpret_cast<float*>(buf + ((tail + i) & R.mask[ri]))[3] = -1.0f;
-            e_esc += (double)pr.e;
-            if (R.hist) unsafeAtomicAdd(&R.hist[2 * (h - R.hist0) + 1], (double)pr.e);
         }
-    }
-    e_in = wave_sum(e_in);
-    e_esc = wave_sum(e_esc);
-    if (lane_id() == 0) {
-        if (e_in != 0.0) unsafeAtomicAdd(&ctl->e_in, e_in);
-        if (e_esc != 0.0) unsafeAtomicAdd(&ctl->e_esc, e_esc);
+        e_in = block_sum(e_in, sh);
+        e_esc = block_sum(e_esc, sh);
+        born = block_sum(born, sh);
+        if (threadIdx.x == 0) {
+            if (e_in != 0.0) unsafeAtomicAdd(&R.jc->e_in[sg.job], e_in);
+            if (e_esc != 0.0) unsafeAtomicAdd(&R.jc->e_esc[sg.job], e_esc);
+            if (born != 0.0) atomicAdd(&R.jc->births[sg.job], (unsigned long long)born);
+        }
     }
 }
 
@@ -819,21 +989,21 @@ __global__ void k_commit(Ctl* ctl, int ri, uint32_t n) {
 // photon pass: Woodcock tracking (section 2.1), one flight per iteration
 // ---------------------------------------------------------------------------
 // Interpolation tables are staged in LDS (kLds) when they fit; one workgroup
-// per CU shares them.
+// per CU shares them, and each wavefront keeps its job's majorant in its own
+// LDS slice.
 extern __shared__ float4 lds_tables[];
 
 template <bool kLds>
-__global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, RunDev R) {
+__global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     const float4* ptab = T.phot;
-    const float* mtab = T.mumax;
+    float* lmw = nullptr;
     if constexpr (kLds) {
         const int np = T.n_mat * T.pg_n;
         for (int i = threadIdx.x; i < np; i += blockDim.x) lds_tables[i] = T.phot[i];
-        float* lm = reinterpret_cast<float*>(lds_tables + np);
-        for (int i = threadIdx.x; i < T.pg_n; i += blockDim.x) lm[i] = T.mumax[i];
+        lmw = reinterpret_cast<float*>(lds_tables + np) +
+              __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * T.pg_n;
         __syncthreads();
         ptab = lds_tables;
-        mtab = lm;
     }
     RingCtl* rc = &ctl->ring[0];
     const uint32_t begin = rc->begin, count = rc->count;
@@ -841,167 +1011,198 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Run
     Particle* bufg = R.buf[0][ctl->ring[0].cur];
     Particle* bufe = R.buf[1][ctl->ring[1].cur];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
-    const uint32_t k0 = R.k0, k1 = R.k1;
-    const bool kerma = (R.flags & 64u) != 0u;
+    JobCtl* jc = R.jc;
     const float ecut_e = R.ecut_e, ecut_g = R.ecut_g;
 
+    int j = first_job(R, count);
     PushState pg{0u, 0u}, pe{0u, 0u};
-    ClaimState cs{0u, 0u, 0u, false};
     LaneTally tl;
     tally_init(tl);
-
-    bool active = false;
-    float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
-    Rng rng;
-    rng_start(rng, 0u, 0u, 0u, 0u);
-
-    for (;;) {
-        Particle p;
-        if (refill(active, cs, rc, begin, count, ctl, bufg, R.mask[0], p)) {
-            tl.ld++;
-            x = p.x; y = p.y; z = p.z; e = p.e;
-            u = p.u; v = p.v; w = p.w;
-            rng_start(rng, p.hlo, p.hhi, p.path, p.ctr);
-            active = true;
-        }
-        if (!ballot(active)) {
-            if (cs.done) break;
-            continue;
-        }
-        rng_topup(rng, k0, k1);
-
-        PendCharged qe;
-        PendPhoton qg;
-        qe.n = 0;
-        qg.n = 0;
-        int ix = 0, iy = 0, iz = 0;
-        if (active) {
-            if (e < ecut_g) {
-                const int vv = voxel_of(G, x, y, z, ix, iy, iz);
-                deposit(tl, R, vv, e);
-                tally_flush(tl, R);
-                active = false;
+    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u};
+    bool last_job = false;   // no other job has records left in this pass
+    // one job at a time: a wavefront switches jobs with all its lanes empty
+    while (j >= 0) {
+        WJob W;
+        load_job(W, R, j);
+        const float* mtab = job_majorant<kLds>(W, lmw, T.pg_n);
+        ClaimState cs{0u, 0u, 0u, false};
+        bool active = false;
+        float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
+        uint32_t pb = 0u;   // batch slot of the lane's history
+        Rng rng;
+        rng_start(rng, 0u, 0u, 0u, 0u);
+        int next = -1;
+        for (;;) {
+            const uint32_t k0 = W.k0, k1 = W.k1;
+            const bool kerma = (W.flags & 64u) != 0u;
+            Particle p;
+            if (refill(active, cs, jc, W, begin, ctl, bufg, R.mask[0], p, wt)) {
+                x = p.x; y = p.y; z = p.z; e = p.e;
+                u = p.u; v = p.v; w = p.w;
+                pb = p.job >> 16;
+                rng_start(rng, p.hlo, p.hhi, p.path, p.ctr);
+                active = true;
+            }
+            if (!ballot(active)) {
+                if (cs.done && last_job) break;
+                if (!cs.done) continue;
             } else {
-                int gi;
-                float gt;
-                grid(hlog2(e), T.pg_lo, T.pg_inv, T.pg_n, gi, gt);
-                const float mumax = lerp1(mtab, gi, gt);
-                const float s = neg_ln(uniform(rng, k0, k1)) * hrcp(mumax);
-                tl.ev[EV_FLIGHTS]++;
-                x = fmaf(s, u, x);
-                y = fmaf(s, v, y);
-                z = fmaf(s, w, z);
-                if (outside(G, x, y, z)) {
-                    tl.e_esc += (double)e;
-                    tl.h_esc += (double)e;
+            rng_topup(rng, k0, k1);
+            const uint64_t act0 = ballot(active);
+            wt.events += (uint32_t)__popcll(ballot(active && !(e < ecut_g)));
+
+            PendCharged qe;
+            PendPhoton qg;
+            qe.n = 0;
+            qg.n = 0;
+            int ix = 0, iy = 0, iz = 0;
+            if (active) {
+                if (e < ecut_g) {
+                    const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
+                    deposit(tl, W, pb, vv, e);
+                    tally_flush(tl, W, pb);
                     active = false;
                 } else {
-                    const int vv = voxel_of(G, x, y, z, ix, iy, iz);
-                    const uint2 vx = G.vox[vv];
-                    const float rho = __uint_as_float(vx.x);
-                    const int m = (int)vx.y;
-                    const float4 mu = lerp4(ptab + m * T.pg_n, gi, gt);
-                    if (uniform(rng, k0, k1) * mumax < rho * mu.w) {
-                        tl.ev[EV_REAL]++;
-                        const float r = uniform(rng, k0, k1) * mu.w;
-                        if (r < mu.x) {
-                            float eps, t, turns;
-                            sample_compton(rng, k0, k1, e, eps, t, turns);
-                            const float u0 = u, v0 = v, w0 = w;
-                            rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
-                            // exact split of E into E' and T (the unit is built without
-                            // contraction, so the product is rounded on its own)
-                            const float ec = eps * e;
-                            float e1, te;
-                            if (2.0f * ec >= e) {
-                                e1 = ec;
-                                te = e - ec;
-                            } else {
-                                te = e - ec;
-                                e1 = e - te;
-                            }
-                            if (kerma || te <= ecut_e) {
-                                deposit(tl, R, vv, te);
-                            } else {
-                                // electron along the momentum transfer E d0 - E' d
-                                float eu = e * u0 - e1 * u, ev = e * v0 - e1 * v, ew = e * w0 - e1 * w;
-                                const float nn = eu * eu + ev * ev + ew * ew;
-                                if (nn > 0.0f) {
-                                    const float in = hrsq(nn);
-                                    eu *= in; ev *= in; ew *= in;
+                    int gi;
+                    float gt;
+                    grid(hlog2(e), T.pg_lo, T.pg_inv, T.pg_n, gi, gt);
+                    const float mumax = lerp1(mtab, gi, gt);
+                    const float s = neg_ln(uniform(rng, k0, k1)) * hrcp(mumax);
+                    x = fmaf(s, u, x);
+                    y = fmaf(s, v, y);
+                    z = fmaf(s, w, z);
+                    if (outside(W.G, x, y, z)) {
+                        tl.e_esc += (double)e;
+                        tl.h_esc += (double)e;
+                        active = false;
+                    } else {
+                        const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
+                        const uint2 vx = W.G.vox[vv];
+                        const float rho = __uint_as_float(vx.x);
+                        const int m = (int)vx.y;
+                        const float4 mu = lerp4(ptab + m * T.pg_n, gi, gt);
+                        if (uniform(rng, k0, k1) * mumax < rho * mu.w) {
+                            tl.ev[EV_REAL]++;
+                            const float r = uniform(rng, k0, k1) * mu.w;
+                            if (r < mu.x) {
+                                float eps, t, turns;
+                                sample_compton(rng, k0, k1, e, eps, t, turns);
+                                const float u0 = u, v0 = v, w0 = w;
+                                rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
+                                // exact split of E into E' and T (the unit is built without
+                                // contraction, so the product is rounded on its own)
+                                const float ec = eps * e;
+                                float e1, te;
+                                if (2.0f * ec >= e) {
+                                    e1 = ec;
+                                    te = e - ec;
                                 } else {
-                                    eu = u0; ev = v0; ew = w0;
+                                    te = e - ec;
+                                    e1 = e - te;
                                 }
-                                qe.n = 1; qe.e0 = te; qe.du = eu; qe.dv = ev; qe.dw = ew;
-                                qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
-                            }
-                            e = e1;
-                        } else if (r < mu.x + mu.y) {
-                            // photoelectric: the electron takes E along the photon
-                            if (kerma || e <= ecut_e) {
-                                deposit(tl, R, vv, e);
-                            } else {
-                                qe.n = 1; qe.e0 = e; qe.du = u; qe.dv = v; qe.dw = w;
-                                qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
-                            }
-                            active = false;
-                        } else {
-                            // pair: uniform split of E - 2 mc^2; the positron keeps a = E - K
-                            const float kk = e - kTwoMec2f, aa = e - kk;
-                            const float tc = uniform(rng, k0, k1) * kk;
-                            float tm, tp;
-                            if (2.0f * tc >= kk) {
-                                tm = tc;
-                                tp = kk - tc;
-                            } else {
-                                tp = kk - tc;
-                                tm = kk - tp;
-                            }
-                            const bool e_local = kerma || tm <= ecut_e;
-                            const bool p_local = kerma || tp <= ecut_e;
-                            if (p_local) {
-                                float du, dv, dw;
-                                sample_iso(rng, k0, k1, du, dv, dw);
-                                deposit(tl, R, vv, tp);
-                                qg.n = 2; qg.e = 0.5f * aa; qg.u = du; qg.v = dv; qg.w = dw; qg.wb = 2u;
-                            }
-                            if (e_local) deposit(tl, R, vv, tm);
-                            qe.du = u; qe.dv = v; qe.dw = w;
-                            if (!e_local) {
-                                qe.n = 1; qe.e0 = tm; qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
-                                if (!p_local) {
-                                    qe.n = 2; qe.e1 = tp; qe.a1 = aa;
+                                if (kerma || te <= ecut_e) {
+                                    deposit(tl, W, pb, vv, te);
+                                } else {
+                                    // electron along the momentum transfer E d0 - E' d
+                                    float eu = e * u0 - e1 * u, ev = e * v0 - e1 * v, ew = e * w0 - e1 * w;
+                                    const float nn = eu * eu + ev * ev + ew * ew;
+                                    if (nn > 0.0f) {
+                                        const float in = hrsq(nn);
+                                        eu *= in; ev *= in; ew *= in;
+                                    } else {
+                                        eu = u0; ev = v0; ew = w0;
+                                    }
+                                    qe.n = 1; qe.e0 = te; qe.du = eu; qe.dv = ev; qe.dw = ew;
+                                    qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
                                 }
-                            } else if (!p_local) {
-                                qe.n = 1; qe.e0 = tp; qe.a0 = aa; qe.role = 1u; qe.flag0 = 1u;
+                                e = e1;
+                            } else if (r < mu.x + mu.y) {
+                                // photoelectric: the electron takes E along the photon
+                                if (kerma || e <= ecut_e) {
+                                    deposit(tl, W, pb, vv, e);
+                                } else {
+                                    qe.n = 1; qe.e0 = e; qe.du = u; qe.dv = v; qe.dw = w;
+                                    qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
+                                }
+                                active = false;
+                            } else {
+                                // pair: uniform split of E - 2 mc^2; the positron keeps a = E - K
+                                const float kk = e - kTwoMec2f, aa = e - kk;
+                                const float tc = uniform(rng, k0, k1) * kk;
+                                float tm, tp;
+                                if (2.0f * tc >= kk) {
+                                    tm = tc;
+                                    tp = kk - tc;
+                                } else {
+                                    tp = kk - tc;
+                                    tm = kk - tp;
+                                }
+                                const bool e_local = kerma || tm <= ecut_e;
+                                const bool p_local = kerma || tp <= ecut_e;
+                                if (p_local) {
+                                    float du, dv, dw;
+                                    sample_iso(rng, k0, k1, du, dv, dw);
+                                    deposit(tl, W, pb, vv, tp);
+                                    qg.n = 2; qg.e = 0.5f * aa; qg.u = du; qg.v = dv; qg.w = dw; qg.wb = 2u;
+                                }
+                                if (e_local) deposit(tl, W, pb, vv, tm);
+                                qe.du = u; qe.dv = v; qe.dw = w;
+                                if (!e_local) {
+                                    qe.n = 1; qe.e0 = tm; qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
+                                    if (!p_local) {
+                                        qe.n = 2; qe.e1 = tp; qe.a1 = aa;
+                                    }
+                                } else if (!p_local) {
+                                    qe.n = 1; qe.e0 = tp; qe.a0 = aa; qe.role = 1u; qe.flag0 = 1u;
+                                }
+                                active = false;
                             }
-                            active = false;
+                            tally_flush(tl, W, pb);
                         }
-                        tally_flush(tl, R);
                     }
                 }
+                if (!active) {
+                        history_flush(tl, W, rng.hlo, rng.hhi);
+                }
             }
-            if (!active) history_flush(tl, R, rng.hlo, rng.hhi);
-        }
-        // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
-        push_charged(qe, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
-        push_photons(qg, pg, head_g, ctl, R, bufg, x, y, z, rng, tl);
-        if (cs.done && big && __popcll(ballot(active)) < kTailLanes) {
-            Particle q;
-            q.x = x; q.y = y; q.z = z; q.e = e;
-            q.u = u; q.v = v; q.w = w; q.nh = -1.0f;
-            q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
-            q.vox = 0u; q.a = 0.0f; q.flags = 0u; q.pad = 0u;
-            if (requeue(active, pg, head_g, ctl, &ctl->ring[0], R.hard[0], bufg, R.mask[0], q)) {
-                tl.rq++;
-                history_flush(tl, R, rng.hlo, rng.hhi);
+            // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
+            // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
+            wt.died += (uint32_t)__popcll(act0 & ~ballot(active));
+            const uint32_t jb = (uint32_t)W.j | (pb << 16);
+            push_charged(qe, pe, head_e, ctl, R, W, jb, bufe, x, y, z, pack_vox(ix, iy, iz), rng, wt);
+            push_photons(qg, pg, head_g, ctl, R, W, jb, bufg, x, y, z, rng, wt);
             }
-            break;
+            if (cs.done) {
+                // this job has nothing left to claim in the pass: move to a job
+                // that has records left, or at the tail of a large pass stop
+                // early; the particles still held go to the next pass
+                int nj = -1;
+                if (!last_job) {
+                    nj = next_job(jc, W.j, R.n_jobs);
+                    last_job = nj < 0;
+                }
+                if (nj >= 0 || (big && __popcll(ballot(active)) < kTailLanes)) {
+                    Particle q;
+                    q.x = x; q.y = y; q.z = z; q.e = e;
+                    q.u = u; q.v = v; q.w = w; q.nh = -1.0f;
+                    q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
+                    q.vox = 0u; q.a = 0.0f; q.flags = 0u; q.job = (uint32_t)W.j | (pb << 16);
+                    if (requeue(active, pg, head_g, ctl, &ctl->ring[0], R.hard[0], bufg, R.mask[0], q, wt)) {
+                        history_flush(tl, W, rng.hlo, rng.hhi);
+                    }
+                    active = false;
+                    next = nj;
+                    break;
+                }
+            }
         }
+        tally_flush(tl, W, pb);
+        job_flush(tl, wt, W, jc);
+        j = next;
     }
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
-    tally_finish(tl, R, ctl, 0);
+    pass_finish(tl, wt, ctl, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1009,7 +1210,7 @@ __global__ void __launch_bounds__(1024) k_photon(Ctl* ctl, Tables T, Geom G, Run
 // iteration (section 2.1)
 // ---------------------------------------------------------------------------
 template <bool kLds>
-__global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, RunDev R) {
+__global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) {
     const float4* etab = T.elec;
     const float* rtab = T.rinv;
     const float* rscale = T.rinv_scale;
@@ -1030,284 +1231,348 @@ __global__ void __launch_bounds__(1024) k_electron(Ctl* ctl, Tables T, Geom G, R
     Particle* bufg = R.buf[0][ctl->ring[0].cur];
     Particle* bufe = R.buf[1][ctl->ring[1].cur];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
-    const uint32_t k0 = R.k0, k1 = R.k1;
+    JobCtl* jc = R.jc;
     const float ecut = R.ecut_e;
-    const bool no_ms = (R.flags & 8u) != 0u;
 
+    int j = first_job(R, count);
     PushState pg{0u, 0u}, pe{0u, 0u};
-    ClaimState cs{0u, 0u, 0u, false};
     LaneTally tl;
     tally_init(tl);
-
-    bool active = false;
-    float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0, nh = -1.0f, aa = 0.0f;
-    int ix = 0, iy = 0, iz = 0;
-    float rho = 1.0f;   // density and material of the current voxel, reloaded
-    int mat = 0;        // when the particle enters a voxel
-    bool positron = false;
-    Rng rng;
-    rng_start(rng, 0u, 0u, 0u, 0u);
-
-    for (;;) {
-        Particle p;
-        if (refill(active, cs, rc, begin, count, ctl, bufe, R.mask[1], p)) {
-            tl.ld++;
-            x = p.x; y = p.y; z = p.z; e = p.e;
-            u = p.u; v = p.v; w = p.w; nh = p.nh;
-            ix = (int)(p.vox & 2047u);
-            iy = (int)((p.vox >> 11) & 2047u);
-            iz = (int)(p.vox >> 22);
-            aa = p.a;
-            positron = (p.flags & 1u) != 0u;
-            rng_start(rng, p.hlo, p.hhi, p.path, p.ctr);
-            const uint2 vx = G.vox[ix + G.nx * (iy + G.ny * iz)];
-            rho = __uint_as_float(vx.x);
-            mat = (int)vx.y;
-            active = true;
-        }
-        if (!ballot(active)) {
-            if (cs.done) break;
-            continue;
-        }
-        rng_topup(rng, k0, k1);
-
-        PendCharged qe;
-        PendPhoton qg;
-        qe.n = 0;
-        qg.n = 0;
-        if (active) {
-            const int vv = ix + G.nx * (iy + G.ny * iz);
-            if (e <= ecut) {
-                // absorption; a positron annihilates at rest into two photons
-                deposit(tl, R, vv, e);
-                if (positron) {
-                    float du, dv, dw;
-                    sample_iso(rng, k0, k1, du, dv, dw);
-                    qg.n = 2; qg.e = 0.5f * aa; qg.u = du; qg.v = dv; qg.w = dw; qg.wb = 0u;
-                }
-                active = false;
+    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u};
+    bool last_job = false;   // no other job has records left in this pass
+    // one job at a time: a wavefront switches jobs with all its lanes empty
+    while (j >= 0) {
+        WJob W;
+        load_job(W, R, j);
+        ClaimState cs{0u, 0u, 0u, false};
+        bool active = false;
+        float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0, nh = -1.0f, aa = 0.0f;
+        int ix = 0, iy = 0, iz = 0;
+        float rho = 1.0f;   // density and material of the current voxel, reloaded
+        int mat = 0;        // when the particle enters a voxel
+        bool positron = false;
+        uint32_t pb = 0u;   // batch slot of the lane's history
+        Rng rng;
+        rng_start(rng, 0u, 0u, 0u, 0u);
+        int next = -1;
+        for (;;) {
+            const uint32_t k0 = W.k0, k1 = W.k1;
+            const bool no_ms = (W.flags & 8u) != 0u;
+            Particle p;
+            if (refill(active, cs, jc, W, begin, ctl, bufe, R.mask[1], p, wt)) {
+                x = p.x; y = p.y; z = p.z; e = p.e;
+                u = p.u; v = p.v; w = p.w; nh = p.nh;
+                ix = (int)(p.vox & 2047u);
+                iy = (int)((p.vox >> 11) & 2047u);
+                iz = (int)(p.vox >> 22);
+                aa = p.a;
+                positron = (p.flags & 1u) != 0u;
+                pb = p.job >> 16;
+                rng_start(rng, p.hlo, p.hhi, p.path, p.ctr);
+                const uint2 vx = W.G.vox[ix + W.G.nx * (iy + W.G.ny * iz)];
+                rho = __uint_as_float(vx.x);
+                mat = (int)vx.y;
+                active = true;
+            }
+            if (!ballot(active)) {
+                if (cs.done && last_job) break;
+                if (!cs.done) continue;
             } else {
-                const float irho = hrcp(rho);
-                const int m = mat;
-                if (nh < 0.0f) nh = neg_ln(uniform(rng, k0, k1));
-                tl.ev[EV_ESTEPS]++;
-                const float t0 = e;
-                const float4 q0 = elec_at(T, etab, m, t0);
-                const float mus = rho * q0.y;
-                const float sh = mus > 0.0f ? nh * hrcp(mus) : 3.0e38f;
-                const float tfl = fmaxf(0.75f * t0, ecut);
-                const float rfl = tfl > ecut ? elec_at(T, etab, m, tfl).x : 0.0f;
-                const float se = (q0.x - rfl) * irho;
-                const bool hard = sh < se;
-                const float s = hard ? sh : se;
-                const float xi = uniform(rng, k0, k1);
-                const float s1 = xi * s, s2 = s - s1;
-                const float tend = hard ? fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * s), tfl), t0) : tfl;
-                bool crossed = false;
-                int ax;
-                float db = face_dist(G, x, y, z, u, v, w, ix, iy, iz, ax);
-                float travelled = 0.0f;
-                if (db < s1) {
-                    x = fmaf(db, u, x); y = fmaf(db, v, y); z = fmaf(db, w, z);
-                    const float t1 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * db), tend), e);
-                    deposit(tl, R, vv, e - t1);
-                    e = t1;
-                    travelled = db;
-                    crossed = true;
-                } else {
-                    x = fmaf(s1, u, x); y = fmaf(s1, v, y); z = fmaf(s1, w, z);
-                    const float t1 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * s1), tend), e);
-                    deposit(tl, R, vv, e - t1);
-                    e = t1;
-                    // hinge: modified-Wentzel deflection for the whole step
-                    if (!no_ms) {
-                        const float tmid = 0.5f * (t0 + tend);
-                        const float tt = s * rho * elec_at(T, etab, m, tmid).w;
-                        const float mu = mw_mu(T, tt, uniform(rng, k0, k1));
-                        const float turns = uniform(rng, k0, k1);
-                        rotate(u, v, w, 1.0f - 2.0f * mu, 2.0f * hsqrt(mu * (1.0f - mu)), turns);
+            rng_topup(rng, k0, k1);
+            const uint64_t act0 = ballot(active);
+            wt.events += (uint32_t)__popcll(ballot(active && !(e <= ecut)));
+
+            PendCharged qe;
+            PendPhoton qg;
+            qe.n = 0;
+            qg.n = 0;
+            if (active) {
+                const int vv = ix + W.G.nx * (iy + W.G.ny * iz);
+                if (e <= ecut) {
+                    // absorption; a positron annihilates at rest into two photons
+                    deposit(tl, W, pb, vv, e);
+                    if (positron) {
+                        float du, dv, dw;
+                        sample_iso(rng, k0, k1, du, dv, dw);
+                        qg.n = 2; qg.e = 0.5f * aa; qg.u = du; qg.v = dv; qg.w = dw; qg.wb = 0u;
                     }
-                    db = face_dist(G, x, y, z, u, v, w, ix, iy, iz, ax);
-                    if (db < s2) {
+                    active = false;
+                } else {
+                    const float irho = hrcp(rho);
+                    const int m = mat;
+                    if (nh < 0.0f) nh = neg_ln(uniform(rng, k0, k1));
+                    const float t0 = e;
+                    const float4 q0 = elec_at(T, etab, m, t0);
+                    const float mus = rho * q0.y;
+                    const float sh = mus > 0.0f ? nh * hrcp(mus) : 3.0e38f;
+                    const float tfl = fmaxf(0.75f * t0, ecut);
+                    const float rfl = tfl > ecut ? elec_at(T, etab, m, tfl).x : 0.0f;
+                    const float se = (q0.x - rfl) * irho;
+                    const bool hard = sh < se;
+                    const float s = hard ? sh : se;
+                    const float xi = uniform(rng, k0, k1);
+                    const float s1 = xi * s, s2 = s - s1;
+                    const float tend = hard ? fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * s), tfl), t0) : tfl;
+                    bool crossed = false;
+                    int ax;
+                    float db = face_dist(W.G, x, y, z, u, v, w, ix, iy, iz, ax);
+                    float travelled = 0.0f;
+                    if (db < s1) {
                         x = fmaf(db, u, x); y = fmaf(db, v, y); z = fmaf(db, w, z);
-                        const float t2 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * (s1 + db)), tend), e);
-                        deposit(tl, R, vv, e - t2);
-                        e = t2;
-                        travelled = s1 + db;
+                        const float t1 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * db), tend), e);
+                        deposit(tl, W, pb, vv, e - t1);
+                        e = t1;
+                        travelled = db;
                         crossed = true;
                     } else {
-                        x = fmaf(s2, u, x); y = fmaf(s2, v, y); z = fmaf(s2, w, z);
-                        deposit(tl, R, vv, e - tend);
-                        e = tend;
-                    }
-                }
-                if (crossed) {
-                    nh -= mus * travelled;
-                    // move onto the face and into the next voxel
-                    if (ax == 0) {
-                        const int st = u > 0.0f ? 1 : -1;
-                        x = (float)(st > 0 ? ix + 1 : ix) * G.dx;
-                        ix += st;
-                    } else if (ax == 1) {
-                        const int st = v > 0.0f ? 1 : -1;
-                        y = (float)(st > 0 ? iy + 1 : iy) * G.dy;
-                        iy += st;
-                    } else {
-                        const int st = w > 0.0f ? 1 : -1;
-                        z = (float)(st > 0 ? iz + 1 : iz) * G.dz;
-                        iz += st;
-                    }
-                    if (ix < 0 || ix >= G.nx || iy < 0 || iy >= G.ny || iz < 0 || iz >= G.nz) {
-                        // a positron takes its annihilation energy along (summed in FP64)
-                        const double out = (double)e + (positron ? (double)aa : 0.0);
-                        tl.e_esc += out;
-                        tl.h_esc += out;
-                        active = false;
-                    } else {
-                        // the next voxel's density and material, needed by the next step
-                        const uint2 vx = G.vox[ix + G.nx * (iy + G.ny * iz)];
-                        rho = __uint_as_float(vx.x);
-                        mat = (int)vx.y;
-                    }
-                } else if (hard) {
-                    // delta scattering against the step-start majorant (mu_h grows with T)
-                    tl.ev[EV_HARD_CAND]++;
-                    const float4 q1 = elec_at(T, etab, m, tend);
-                    if (uniform(rng, k0, k1) * q0.y < q1.y) {
-                        tl.ev[EV_HARD]++;
-                        if (uniform(rng, k0, k1) * q1.y < q1.z) {
-                            float eps, turns;
-                            const float tt = e;
-                            sample_moller(rng, k0, k1, tt, ecut, eps, turns);
-                            const float tp = tt - eps * tt;   // >= T/2
-                            const float wd = tt - tp;         // exact
-                            const float tm2 = tt + kTwoMec2f;
-                            const float itt = hrcp(tt);
-                            const float cd = hsqrt(wd * tm2 * itt * hrcp(wd + kTwoMec2f));
-                            const float cpr = hsqrt(tp * tm2 * itt * hrcp(tp + kTwoMec2f));
-                            float du = u, dv = v, dw = w;
-                            rotate(du, dv, dw, cd, hsqrt(fmaxf(0.0f, 1.0f - cd * cd)), turns);
-                            rotate(u, v, w, cpr, hsqrt(fmaxf(0.0f, 1.0f - cpr * cpr)), turns + 0.5f);
-                            if (wd <= ecut) {
-                                deposit(tl, R, vv, wd);
-                            } else {
-                                qe.n = 1; qe.e0 = wd; qe.du = du; qe.dv = dv; qe.dw = dw;
-                                qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
-                            }
-                            e = tp;
+                        x = fmaf(s1, u, x); y = fmaf(s1, v, y); z = fmaf(s1, w, z);
+                        const float t1 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * s1), tend), e);
+                        deposit(tl, W, pb, vv, e - t1);
+                        e = t1;
+                        // hinge: modified-Wentzel deflection for the whole step
+                        if (!no_ms) {
+                            const float tmid = 0.5f * (t0 + tend);
+                            const float tt = s * rho * elec_at(T, etab, m, tmid).w;
+                            const float mu = mw_mu(T, tt, uniform(rng, k0, k1));
+                            const float turns = uniform(rng, k0, k1);
+                            rotate(u, v, w, 1.0f - 2.0f * mu, 2.0f * hsqrt(mu * (1.0f - mu)), turns);
+                        }
+                        db = face_dist(W.G, x, y, z, u, v, w, ix, iy, iz, ax);
+                        if (db < s2) {
+                            x = fmaf(db, u, x); y = fmaf(db, v, y); z = fmaf(db, w, z);
+                            const float t2 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * (s1 + db)), tend), e);
+                            deposit(tl, W, pb, vv, e - t2);
+                            e = t2;
+                            travelled = s1 + db;
+                            crossed = true;
                         } else {
-                            const float tt = e;
-                            const float kph = sample_brems(rng, k0, k1, tt, R.ecut_g);
-                            float kp, el;
-                            if (2.0f * kph >= tt) {
-                                kp = kph;
-                                el = tt - kph;
-                            } else {
-                                el = tt - kph;
-                                kp = tt - el;
-                            }
-                            qg.n = 1; qg.e = kp; qg.u = u; qg.v = v; qg.w = w; qg.wb = 0u;
-                            e = el;
+                            x = fmaf(s2, u, x); y = fmaf(s2, v, y); z = fmaf(s2, w, z);
+                            deposit(tl, W, pb, vv, e - tend);
+                            e = tend;
                         }
                     }
-                    nh = -1.0f;
-                } else {
-                    nh -= mus * s;
+                    if (crossed) {
+                        nh -= mus * travelled;
+                        // move onto the face and into the next voxel
+                        if (ax == 0) {
+                            const int st = u > 0.0f ? 1 : -1;
+                            x = (float)(st > 0 ? ix + 1 : ix) * W.G.dx;
+                            ix += st;
+                        } else if (ax == 1) {
+                            const int st = v > 0.0f ? 1 : -1;
+                            y = (float)(st > 0 ? iy + 1 : iy) * W.G.dy;
+                            iy += st;
+                        } else {
+                            const int st = w > 0.0f ? 1 : -1;
+                            z = (float)(st > 0 ? iz + 1 : iz) * W.G.dz;
+                            iz += st;
+                        }
+                        if (ix < 0 || ix >= W.G.nx || iy < 0 || iy >= W.G.ny || iz < 0 || iz >= W.G.nz) {
+                            // a positron takes its annihilation energy along (summed in FP64)
+                            const double out = (double)e + (positron ? (double)aa : 0.0);
+                            tl.e_esc += out;
+                            tl.h_esc += out;
+                            active = false;
+                        } else {
+                            // the next voxel's density and material, needed by the next step
+                            const uint2 vx = W.G.vox[ix + W.G.nx * (iy + W.G.ny * iz)];
+                            rho = __uint_as_float(vx.x);
+                            mat = (int)vx.y;
+                        }
+                    } else if (hard) {
+                        // delta scattering against the step-start majorant (mu_h grows with T)
+                        tl.ev[EV_HARD_CAND]++;
+                        const float4 q1 = elec_at(T, etab, m, tend);
+                        if (uniform(rng, k0, k1) * q0.y < q1.y) {
+                            tl.ev[EV_HARD]++;
+                            if (uniform(rng, k0, k1) * q1.y < q1.z) {
+                                float eps, turns;
+                                const float tt = e;
+                                sample_moller(rng, k0, k1, tt, ecut, eps, turns);
+                                const float tp = tt - eps * tt;   // >= T/2
+                                const float wd = tt - tp;         // exact
+                                const float tm2 = tt + kTwoMec2f;
+                                const float itt = hrcp(tt);
+                                const float cd = hsqrt(wd * tm2 * itt * hrcp(wd + kTwoMec2f));
+                                const float cpr = hsqrt(tp * tm2 * itt * hrcp(tp + kTwoMec2f));
+                                float du = u, dv = v, dw = w;
+                                rotate(du, dv, dw, cd, hsqrt(fmaxf(0.0f, 1.0f - cd * cd)), turns);
+                                rotate(u, v, w, cpr, hsqrt(fmaxf(0.0f, 1.0f - cpr * cpr)), turns + 0.5f);
+                                if (wd <= ecut) {
+                                    deposit(tl, W, pb, vv, wd);
+                                } else {
+                                    qe.n = 1; qe.e0 = wd; qe.du = du; qe.dv = dv; qe.dw = dw;
+                                    qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
+                                }
+                                e = tp;
+                            } else {
+                                const float tt = e;
+                                const float kph = sample_brems(rng, k0, k1, tt, R.ecut_g);
+                                float kp, el;
+                                if (2.0f * kph >= tt) {
+                                    kp = kph;
+                                    el = tt - kph;
+                                } else {
+                                    el = tt - kph;
+                                    kp = tt - el;
+                                }
+                                qg.n = 1; qg.e = kp; qg.u = u; qg.v = v; qg.w = w; qg.wb = 0u;
+                                e = el;
+                            }
+                        }
+                        nh = -1.0f;
+                    } else {
+                        nh -= mus * s;
+                    }
+                }
+                if (!active) {
+                        tally_flush(tl, W, pb);
+                    history_flush(tl, W, rng.hlo, rng.hhi);
                 }
             }
-            if (!active) {
-                tally_flush(tl, R);
-                history_flush(tl, R, rng.hlo, rng.hhi);
+            wt.died += (uint32_t)__popcll(act0 & ~ballot(active));
+            const uint32_t jb = (uint32_t)W.j | (pb << 16);
+            push_charged(qe, pe, head_e, ctl, R, W, jb, bufe, x, y, z, pack_vox(ix, iy, iz), rng, wt);
+            push_photons(qg, pg, head_g, ctl, R, W, jb, bufg, x, y, z, rng, wt);
+            }
+            if (cs.done) {
+                // this job has nothing left to claim in the pass: move to a job
+                // that has records left, or at the tail of a large pass stop
+                // early; the particles still held go to the next pass
+                int nj = -1;
+                if (!last_job) {
+                    nj = next_job(jc, W.j, R.n_jobs);
+                    last_job = nj < 0;
+                }
+                if (nj >= 0 || (big && __popcll(ballot(active)) < kTailLanes)) {
+                    Particle q;
+                    q.x = x; q.y = y; q.z = z; q.e = e;
+                    q.u = u; q.v = v; q.w = w; q.nh = nh;
+                    q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
+                    q.vox = pack_vox(ix, iy, iz); q.a = aa; q.flags = positron ? 1u : 0u;
+                    q.job = (uint32_t)W.j | (pb << 16);
+                    if (requeue(active, pe, head_e, ctl, &ctl->ring[1], R.hard[1], bufe, R.mask[1], q, wt)) {
+                        history_flush(tl, W, rng.hlo, rng.hhi);
+                    }
+                    active = false;
+                    next = nj;
+                    break;
+                }
             }
         }
-        push_charged(qe, pe, head_e, ctl, R, bufe, x, y, z, pack_vox(ix, iy, iz), rng, tl);
-        push_photons(qg, pg, head_g, ctl, R, bufg, x, y, z, rng, tl);
-        if (cs.done && big && __popcll(ballot(active)) < kTailLanes) {
-            Particle q;
-            q.x = x; q.y = y; q.z = z; q.e = e;
-            q.u = u; q.v = v; q.w = w; q.nh = nh;
-            q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
-            q.vox = pack_vox(ix, iy, iz); q.a = aa; q.flags = positron ? 1u : 0u; q.pad = 0u;
-            if (requeue(active, pe, head_e, ctl, &ctl->ring[1], R.hard[1], bufe, R.mask[1], q)) {
-                tl.rq++;
-                history_flush(tl, R, rng.hlo, rng.hhi);
-            }
-            break;
-        }
+        tally_flush(tl, W, pb);
+        job_flush(tl, wt, W, jc);
+        j = next;
     }
-    // the pass was stopped by an overflow: particles still held are dropped
-    // (the run reports GDPM_E_OVERFLOW and its outputs are not valid)
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
-    tally_finish(tl, R, ctl, 1);
+    pass_finish(tl, wt, ctl, 1);
 }
 
 // ---------------------------------------------------------------------------
-// queue compaction and energy re-binning: counting sort of [head, tail) by
-// log2-energy bin into the other buffer; empty slots are dropped
+// queue compaction and re-binning: counting sort of [head, tail) by the key
+// job x log2-energy bin into the other buffer; empty slots are dropped.  The
+// jobs' records end up in contiguous segments, each ordered by energy.
 // ---------------------------------------------------------------------------
 GDPM_DEV int energy_bin(float e, float lo, float inv, int nb) {
     const int b = (int)((hlog2(e) - lo) * inv);
     return min(max(b, 0), nb - 1);
 }
 
+GDPM_DEV int record_key(const Particle* buf, uint32_t mask, uint32_t slot, int nb, float lo, float inv,
+                        float& e) {
+    const float4 w0 = reinterpret_cast<const float4*>(buf + (slot & mask))[0];
+    const float4 w3 = reinterpret_cast<const float4*>(buf + (slot & mask))[3];
+    e = w0.w;
+    return (int)(__float_as_uint(w3.w) & 0xFFFFu) * nb + energy_bin(e, lo, inv, nb);
+}
+
 __global__ void __launch_bounds__(256) k_bin_count(Ctl* ctl, RunDev R, int ri, int nb, float lo,
                                                    float inv) {
     if (ctl->overflow) return;
-    __shared__ uint32_t hist[kMaxBins];
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0u;
+    extern __shared__ uint32_t hist[];
+    const int nk = R.n_jobs * nb;
+    for (int i = threadIdx.x; i < nk; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
     const RingCtl& r = ctl->ring[ri];
     const uint32_t n = r.tail - r.head;
     const Particle* buf = R.buf[ri][r.cur];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float e = reinterpret_cast<const float*>(buf + ((r.head + i) & R.mask[ri]))[3];
-        if (e >= 0.0f) atomicAdd(&hist[energy_bin(e, lo, inv, nb)], 1u);
+        float e;
+        const int k = record_key(buf, R.mask[ri], r.head + i, nb, lo, inv, e);
+        if (e >= 0.0f) atomicAdd(&hist[k], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nb; i += blockDim.x)
-        if (hist[i]) atomicAdd(&ctl->bin_count[i], hist[i]);
+    for (int i = threadIdx.x; i < nk; i += blockDim.x)
+        if (hist[i]) atomicAdd(&R.jc->bin_count[i], hist[i]);
 }
 
-__global__ void k_bin_scan(Ctl* ctl, int nb) {
+// exclusive scan of the key counts (one block of 1024 threads, <= 4 keys each);
+// also the jobs' segments and the number of records kept
+__global__ void __launch_bounds__(1024) k_bin_scan(Ctl* ctl, RunDev R, int nb) {
     if (ctl->overflow) return;
-    uint32_t acc = 0u;
-    for (int i = 0; i < nb; ++i) {
-        ctl->bin_cursor[i] = acc;
-        acc += ctl->bin_count[i];
-        ctl->bin_count[i] = 0u;
+    __shared__ uint32_t part[1024];
+    JobCtl* jc = R.jc;
+    const int nk = R.n_jobs * nb;
+    const int per = (nk + 1023) / 1024;
+    const int k0 = threadIdx.x * per;
+    uint32_t s = 0u;
+    for (int k = k0; k < k0 + per && k < nk; ++k) s += jc->bin_count[k];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
+        const uint32_t a = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += a;
+        __syncthreads();
     }
-    ctl->n_valid = acc;
+    uint32_t acc = part[threadIdx.x] - s;
+    for (int k = k0; k < k0 + per && k < nk; ++k) {
+        jc->bin_cursor[k] = acc;
+        acc += jc->bin_count[k];
+        jc->bin_count[k] = 0u;
+    }
+    __syncthreads();
+    const uint32_t total = part[1023];
+    for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) {
+        const uint32_t b0 = jc->bin_cursor[j * nb];
+        const uint32_t b1 = j + 1 < R.n_jobs ? jc->bin_cursor[(j + 1) * nb] : total;
+        jc->seg_begin[j] = b0;
+        jc->seg_count[j] = b1 - b0;
+    }
+    if (threadIdx.x == 0) ctl->n_valid = total;
 }
 
 __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri, int nb, float lo,
                                                      float inv) {
     if (ctl->overflow) return;
-    __shared__ uint32_t cnt[kMaxBins], base[kMaxBins];
+    extern __shared__ uint32_t cnt[];   // [nk] tile counts, then [nk] tile bases
+    const int nk = R.n_jobs * nb;
+    uint32_t* base = cnt + nk;
     const RingCtl& r = ctl->ring[ri];
     const uint32_t n = r.tail - r.head;
     const Particle* src = R.buf[ri][r.cur];
     Particle* dst = R.buf[ri][r.cur ^ 1u];
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
-        for (int i = threadIdx.x; i < nb; i += blockDim.x) cnt[i] = 0u;
+        for (int i = threadIdx.x; i < nk; i += blockDim.x) cnt[i] = 0u;
         __syncthreads();
         const uint32_t i = i0 + threadIdx.x;
         Particle p;
-        int b = -1;
+        int k = -1;
         uint32_t rank = 0u;
         if (i < n) {
             p = load(src, R.mask[ri], r.head + i);
             if (p.e >= 0.0f) {
-                b = energy_bin(p.e, lo, inv, nb);
-                rank = atomicAdd(&cnt[b], 1u);
+                k = (int)(p.job & 0xFFFFu) * nb + energy_bin(p.e, lo, inv, nb);
+                rank = atomicAdd(&cnt[k], 1u);
             }
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < nb; k += blockDim.x)
-            base[k] = cnt[k] ? atomicAdd(&ctl->bin_cursor[k], cnt[k]) : 0u;
+        for (int q = threadIdx.x; q < nk; q += blockDim.x)
+            base[q] = cnt[q] ? atomicAdd(&R.jc->bin_cursor[q], cnt[q]) : 0u;
         __syncthreads();
-        if (b >= 0) store(dst, R.mask[ri], base[b] + rank, p);
+        if (k >= 0) store(dst, R.mask[ri], base[k] + rank, p);
         __syncthreads();
     }
 }
@@ -1319,6 +1584,7 @@ __global__ void k_bin_swap(Ctl* ctl, int ri) {
     r.head = 0u;
     r.tail = ctl->n_valid;
 }
+
 
 // ---------------------------------------------------------------------------
 // batch statistics (section 2.2.1, section 3.1): per voxel the mean over the
@@ -1491,23 +1757,24 @@ __global__ void k_test_lookup(Tables T, int which, int m, const float* in, float
 // ---------------------------------------------------------------------------
 // host launchers (the host runtime calls these; kernels stay in this unit)
 // ---------------------------------------------------------------------------
-hipError_t launch_setup(hipStream_t st, Ctl* ctl, int ri) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(1), 0, st, ctl, ri);
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri) {
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, ctl, R, ri);
     return hipGetLastError();
 }
-hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const Geom& G, const SourceDev& S,
-                         const RunDev& R, int ri, unsigned long long h0, uint32_t n) {
-    hipLaunchKernelGGL(k_source, dim3(blocks), dim3(256), 0, st, ctl, G, S, R, ri, h0, n);
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, st, ctl, ri, n);
+hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, const SrcSeg* segs,
+                         int nseg, uint32_t total, int ri) {
+    hipLaunchKernelGGL(k_source, dim3(blocks), dim3(256), 0, st, ctl, R, segs, nseg, total, ri);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, st, ctl, ri, total);
     return hipGetLastError();
 }
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, st, ctl, ri);
     return hipGetLastError();
 }
-// LDS bytes the table staging of a pass needs
-size_t transport_lds_bytes(int ri, const Tables& T) {
-    if (ri == 0) return (size_t)T.n_mat * T.pg_n * sizeof(float4) + (size_t)T.pg_n * sizeof(float);
+// LDS bytes the table staging of a pass needs with `waves` wavefronts per block
+size_t transport_lds_bytes(int ri, const Tables& T, int waves) {
+    if (ri == 0)
+        return (size_t)T.n_mat * T.pg_n * sizeof(float4) + (size_t)waves * T.pg_n * sizeof(float);
     return (size_t)T.n_mat * T.eg_n * sizeof(float4) + ((size_t)T.n_mat * T.nr + T.n_mat) * sizeof(float);
 }
 
@@ -1521,26 +1788,30 @@ hipError_t transport_lds_optin(size_t bytes) {
 }
 
 hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, Ctl* ctl,
-                            const Tables& T, const Geom& G, const RunDev& R) {
-    const size_t bytes = lds ? transport_lds_bytes(ri, T) : 0;
+                            const Tables& T, const RunDev& R) {
+    const size_t bytes = lds ? transport_lds_bytes(ri, T, threads / 64) : 0;
     if (ri == 0) {
         if (lds)
-            hipLaunchKernelGGL(k_photon<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, G, R);
+            hipLaunchKernelGGL(k_photon<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
         else
-            hipLaunchKernelGGL(k_photon<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, G, R);
+            hipLaunchKernelGGL(k_photon<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, R);
     } else {
         if (lds)
-            hipLaunchKernelGGL(k_electron<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, G, R);
+            hipLaunchKernelGGL(k_electron<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
         else
-            hipLaunchKernelGGL(k_electron<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, G, R);
+            hipLaunchKernelGGL(k_electron<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, R);
     }
     return hipGetLastError();
 }
+// nb energy bins per job; R.n_jobs * nb <= kMaxKeys
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
                         float lo, float inv) {
-    hipLaunchKernelGGL(k_bin_count, dim3(blocks), dim3(256), 0, st, ctl, R, ri, nb, lo, inv);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1), 0, st, ctl, nb);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks), dim3(256), 0, st, ctl, R, ri, nb, lo, inv);
+    const size_t nk = (size_t)R.n_jobs * nb;
+    hipLaunchKernelGGL(k_bin_count, dim3(blocks), dim3(256), nk * sizeof(uint32_t), st, ctl, R, ri,
+                       nb, lo, inv);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, ctl, R, nb);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks), dim3(256), 2 * nk * sizeof(uint32_t), st, ctl, R,
+                       ri, nb, lo, inv);
     hipLaunchKernelGGL(k_bin_swap, dim3(1), dim3(1), 0, st, ctl, ri);
     return hipGetLastError();
 }
