@@ -167,6 +167,14 @@ typedef struct {
  * Results do not depend on any of these options (each particle draws from its
  * own random stream), only the speed does. */
 gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out);
+
+/* The launch settings the context uses now, after any autotuning ("autotune":
+ * 1 in opts_json makes gdpm_run_batch and servers size the queues from the
+ * submitted work and try block sizes and energy-bin counts on the first
+ * iterations, keeping the fastest for the rest of the run and for later runs
+ * of the context).  out: waves_per_cu, rebin_bins, ring_capacity_log2,
+ * pass_histories, autotune. */
+gdpm_status gdpm_context_settings(gdpm_context ctx, int out[5]);
 gdpm_status gdpm_context_destroy(gdpm_context ctx);
 const char* gdpm_last_error(void);
 
@@ -211,8 +219,78 @@ gdpm_status gdpm_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
 gdpm_status gdpm_run_async(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
                            const gdpm_run_params* prm, double* d_dose, double* d_sigma,
                            void* hip_stream, gdpm_job* out);
+/* Wait for a job of gdpm_run_async or of a server; returns the job's status
+ * (its message through gdpm_last_error).  Releasing a server job that has not
+ * finished returns GDPM_E_BUSY. */
 gdpm_status gdpm_job_wait(gdpm_job job, gdpm_run_stats* stats);
 gdpm_status gdpm_job_release(gdpm_job job);
+
+/* ---- many jobs ------------------------------------------------------------
+ * Several dose jobs transported together: every kernel launch advances the
+ * particles of all admitted jobs (shared photon and electron queues whose
+ * records carry the job, one persistent grid per pass).  Each job keeps its
+ * phantom, source, random key (seed, job_id), batches and statistics, and its
+ * dose equals the dose of the same job run alone (the same particles draw the
+ * same random numbers; only the order of the FP64 tally additions differs).
+ * Jobs run together must use the same cutoffs and physics flags (bits 0-5);
+ * the KERMA flag may differ.  In the returned gdpm_run_stats, histories,
+ * e_in, e_dep, e_esc, unc_mean_over_dmax, dmax, rounds and t_total_s are the
+ * job's own; events, passes, timings and the per-pass counters are totals of
+ * the engine over the call. */
+
+/* One job: handles of the caller's context; dose and sigma are host arrays of
+ * nx*ny*nz doubles (either may be NULL), written when the job finishes. */
+typedef struct {
+    gdpm_phantom phantom;
+    gdpm_source source;
+    gdpm_run_params params;
+    double* dose;
+    double* sigma;
+} gdpm_job_desc;
+
+/* Blocking batched run of n jobs (n >= 1).  Up to 256 jobs are admitted at
+ * once, more as earlier ones finish.  stats: NULL or n entries; status: NULL
+ * or n entries receiving each job's result (GDPM_OK, GDPM_E_NOT_CONVERGED...).
+ * Returns GDPM_OK when every job finished with GDPM_OK or
+ * GDPM_E_NOT_CONVERGED, else the first other error (a device error or queue
+ * overflow ends every job). */
+gdpm_status gdpm_run_batch(gdpm_context ctx, int n, const gdpm_job_desc* jobs,
+                           gdpm_run_stats* stats, gdpm_status* status);
+
+/* ---- serving ---------------------------------------------------------------
+ * A server owns the context's device (the context answers GDPM_E_BUSY to
+ * other runs while the server exists) and runs a request loop on its own host
+ * thread: queued jobs are admitted in arrival order while fewer than
+ * max_slots jobs run and their device footprint (batch tallies, dose and
+ * sigma, majorant) fits in hbm_budget_bytes (a job that alone exceeds the
+ * budget is admitted when nothing else runs); admitted jobs share every
+ * kernel launch (as in gdpm_run_batch) and each leaves as soon as its own
+ * uncertainty target or history count is reached, freeing its slot and
+ * memory for the next request.  Phantoms, sources and tables stay resident
+ * on the device.  Jobs must share cutoffs and physics flags (bits 0-5) with
+ * the first job submitted. */
+typedef struct gdpm_server_s* gdpm_server;
+
+typedef struct {
+    uint64_t submitted, finished, running, queued;
+    uint64_t histories;           /* histories of finished jobs */
+    double footprint_bytes;       /* device bytes held by admitted jobs now */
+    double high_water_bytes;      /* largest footprint_bytes so far */
+    double resident_bytes;        /* queues, control blocks, tables, phantoms and
+                                     sources of the context */
+} gdpm_server_info;
+
+/* max_slots in 1..256; hbm_budget_bytes > 0. */
+gdpm_status gdpm_server_create(gdpm_context ctx, uint64_t hbm_budget_bytes, int max_slots,
+                               gdpm_server* out);
+/* Queue one job; returns at once.  The descriptor is copied; its handles and
+ * host output arrays must stay valid until gdpm_job_wait returns.  The job's
+ * gdpm_run_stats.t_total_s is its latency from submission to completion. */
+gdpm_status gdpm_server_submit(gdpm_server srv, const gdpm_job_desc* job, gdpm_job* out);
+gdpm_status gdpm_server_info_get(gdpm_server srv, gdpm_server_info* info);
+/* Waits until every queued and running job has finished, then stops the
+ * loop.  Job handles stay valid until gdpm_job_release. */
+gdpm_status gdpm_server_destroy(gdpm_server srv);
 
 /* ---- inspection and test entry points ------------------------------------
  * These expose the pieces of the transport so that tests can compare them

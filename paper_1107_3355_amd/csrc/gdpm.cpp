@@ -15,9 +15,13 @@
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -171,7 +175,8 @@ struct gdpm_context_s {
     int waves_per_cu = 12;
     int rebin_bins = 16;
     int lds_tables = 1;          // stage interpolation tables in LDS when they fit
-    int pass_histories = 0;      // new histories per iteration (0: a quarter of a queue)
+    int pass_histories = 0;      // new histories per iteration (0: half a queue less its fill)
+    int autotune = 0;            // tune block size and re-binning online, queues from the work
     int max_lds = 0;             // dynamic LDS bytes a workgroup may use
     bool lds_optin = false;
     std::vector<MaterialParams> mats;
@@ -185,6 +190,7 @@ struct gdpm_context_s {
     SrcSeg* h_segs = nullptr;  // part of the job counters, statistics reductions
     void* h_jc = nullptr;
     double* h_red = nullptr;
+    double resident_bytes = 0.0;   // phantoms and sources alive in the context
     std::vector<hipEvent_t> events;
     bool busy = false;
 };
@@ -225,11 +231,6 @@ struct gdpm_source_s {
     }
 };
 
-struct gdpm_job_s {
-    gdpm_context ctx;
-    gdpm_status status;
-    gdpm_run_stats stats;
-};
 
 namespace {
 
@@ -389,7 +390,20 @@ struct Engine {
     int n_slots = 0;            // slots in use: [0, n_slots)
     Timers tm;
     uint32_t iter = 0, idle = 0;
-    unsigned long long ev_base[8] = {};
+    // online autotuning: launch settings change nothing in the results, so
+    // candidate (waves per CU, energy bins) pairs are tried on live iterations
+    // and the fastest, in transport events per kernel second, is kept
+    struct Tuner {
+        bool on = false, fixed = false;
+        std::vector<std::pair<int, int>> cand;
+        std::vector<double> score;
+        std::vector<int> samples;
+        int cur = 0;
+        unsigned long long last_events = 0;
+        double last_time = 0.0;
+    } tune;
+    void tune_begin();
+    void tune_account();
 
     gdpm_status init(gdpm_context c, hipStream_t s, const RunPlan& plan);
     gdpm_status admit(EJob* j);
@@ -402,6 +416,44 @@ struct Engine {
         return false;
     }
 };
+
+void Engine::tune_begin() {
+    tune = Tuner{};
+    tune.on = ctx->autotune != 0;
+    if (!tune.on) return;
+    for (int w : {8, 12})
+        for (int b : {4, 16}) tune.cand.emplace_back(w, b);
+    tune.score.assign(tune.cand.size(), 0.0);
+    tune.samples.assign(tune.cand.size(), 0);
+    ctx->waves_per_cu = tune.cand[0].first;
+    ctx->rebin_bins = tune.cand[0].second;
+}
+
+// after an iteration: score the candidate it ran with, move to the next
+void Engine::tune_account() {
+    if (!tune.on || tune.fixed) return;
+    const Ctl* hc = ctx->host_ctl;
+    const unsigned long long ev = hc->ev[GDPM_EV_FLIGHTS] + hc->ev[GDPM_EV_ESTEPS];
+    const double t = tm.photon + tm.electron;
+    const unsigned long long dev = ev - tune.last_events;
+    const double dt = t - tune.last_time;
+    tune.last_events = ev;
+    tune.last_time = t;
+    if (dev < 4000000ull || dt <= 0.0) return;   // too little work to judge
+    tune.score[tune.cur] += (double)dev / dt;
+    tune.samples[tune.cur]++;
+    const int n = (int)tune.cand.size();
+    tune.cur = (tune.cur + 1) % n;
+    if (*std::min_element(tune.samples.begin(), tune.samples.end()) >= 2) {
+        int best = 0;
+        for (int i = 1; i < n; ++i)
+            if (tune.score[i] / tune.samples[i] > tune.score[best] / tune.samples[best]) best = i;
+        tune.cur = best;
+        tune.fixed = true;
+    }
+    ctx->waves_per_cu = tune.cand[tune.cur].first;
+    ctx->rebin_bins = tune.cand[tune.cur].second;
+}
 
 gdpm_status Engine::init(gdpm_context c, hipStream_t s, const RunPlan& plan) {
     ctx = c;
@@ -441,6 +493,7 @@ gdpm_status Engine::init(gdpm_context c, hipStream_t s, const RunPlan& plan) {
     }
     tm = Timers{};
     iter = idle = 0;
+    tune_begin();
     return GDPM_OK;
 }
 
@@ -605,6 +658,7 @@ gdpm_status Engine::step() {
         (ri == 0 ? tm.photon : tm.electron) += ms * 1e-3;
     }
     ++iter;
+    tune_account();
     if (hc->overflow)
         return fail(GDPM_E_OVERFLOW, "a particle queue filled up (capacity 2^%d); raise ring_capacity_log2",
                     ctx->ring_log2);
@@ -770,6 +824,126 @@ gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdp
 
 }  // namespace
 
+// a job of gdpm_run_async (finished when created) or of a server
+struct gdpm_job_s {
+    gdpm_context ctx = nullptr;
+    gdpm_status status = GDPM_OK;
+    gdpm_run_stats stats{};
+    std::string err;
+    gdpm_server_s* srv = nullptr;
+    std::unique_ptr<EJob> ej;
+    double* dose = nullptr;    // host outputs of a server job
+    double* sigma = nullptr;
+    bool finished = true;
+};
+
+// the request loop of a server (see gdpm_server_create)
+struct gdpm_server_s {
+    gdpm_context ctx = nullptr;
+    uint64_t budget = 0;
+    int max_slots = 0;
+    std::thread th;
+    std::mutex m;
+    std::condition_variable cv_work, cv_done;
+    std::deque<gdpm_job_s*> pending;
+    std::vector<gdpm_job_s*> running;
+    bool stop = false;
+    bool key_set = false;
+    TableKey key{};
+    size_t used = 0, high_water = 0;
+    uint64_t submitted = 0, finished = 0, histories = 0;
+    void loop();
+};
+
+namespace {
+void finish_server_job(gdpm_server_s* S, gdpm_job_s* job, gdpm_status st, const std::string& msg) {
+    job->status = st;
+    job->err = msg;
+    job->finished = true;
+    S->finished++;
+    S->cv_done.notify_all();
+}
+}  // namespace
+
+void gdpm_server_s::loop() {
+    (void)hipSetDevice(ctx->device);
+    hipStream_t st = ctx->stream;
+    Engine E;
+    bool ready = false;
+    std::unique_lock<std::mutex> lk(m);
+    for (;;) {
+        // admission in arrival order, by slots and device footprint
+        while (!pending.empty() && (int)running.size() < max_slots) {
+            gdpm_job_s* job = pending.front();
+            EJob* j = job->ej.get();
+            const size_t fp = job_footprint(j->ph, j->plan, true, ready ? E.tab->host.pg_n : 0);
+            if (used + fp > budget && !running.empty()) break;
+            pending.pop_front();
+            gdpm_status s = GDPM_OK;
+            if (!ready) {
+                s = E.init(ctx, st, j->plan);
+                ready = s == GDPM_OK;
+            }
+            if (!s) s = E.admit(j);
+            if (s) {
+                finish_server_job(this, job, s, g_err);
+                continue;
+            }
+            j->footprint = fp;
+            used += fp;
+            high_water = std::max(high_water, used);
+            running.push_back(job);
+        }
+        if (running.empty()) {
+            if (stop && pending.empty()) break;
+            cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+            continue;
+        }
+        lk.unlock();
+        gdpm_status s = E.step();
+        if (!s) s = E.settle();
+        lk.lock();
+        if (s) {
+            // a device error or an overflow ends every running job
+            const std::string msg = g_err;
+            for (gdpm_job_s* job : running) {
+                E.release(job->ej.get());
+                finish_server_job(this, job, s, msg);
+            }
+            running.clear();
+            used = 0;
+            ready = false;
+            continue;
+        }
+        for (size_t i = 0; i < running.size();) {
+            gdpm_job_s* job = running[i];
+            EJob* j = job->ej.get();
+            if (!j->done) {
+                ++i;
+                continue;
+            }
+            gdpm_status cs = GDPM_OK;
+            if (job->dose && hipMemcpyAsync(job->dose, j->d_dose, j->nv * sizeof(double),
+                                            hipMemcpyDeviceToHost, st) != hipSuccess)
+                cs = GDPM_E_DEVICE;
+            if (job->sigma && hipMemcpyAsync(job->sigma, j->d_sigma, j->nv * sizeof(double),
+                                             hipMemcpyDeviceToHost, st) != hipSuccess)
+                cs = GDPM_E_DEVICE;
+            if (hipStreamSynchronize(st) != hipSuccess) cs = GDPM_E_DEVICE;
+            fill_stats(E, j, j->t_submit, &job->stats);
+            E.release(j);
+            j->tally.reset();
+            j->dose_buf.reset();
+            j->sigma_buf.reset();
+            j->mumax.reset();
+            used -= j->footprint;
+            histories += j->issued;
+            finish_server_job(this, job, cs ? cs : j->status, cs ? "copying the outputs failed" : j->err);
+            running.erase(running.begin() + i);
+        }
+    }
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -791,6 +965,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->rebin_bins = json_int(opts_json, "rebin_bins", 16);
     ctx->lds_tables = json_int(opts_json, "lds_tables", 1);
     ctx->pass_histories = json_int(opts_json, "pass_histories", 0);
+    ctx->autotune = json_int(opts_json, "autotune", 0);
     if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
     if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > kMaxBlockThreads / 64)
         return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);
@@ -887,12 +1062,14 @@ gdpm_status gdpm_phantom_create(gdpm_context ctx, int nx, int ny, int nz, double
     ph->dz = dz;
     ph->rho_max = rmax;
     HIP_TRY(upload(ph->vox, vox));
+    ctx->resident_bytes += (double)ph->vox.bytes;
     *out = ph.release();
     return GDPM_OK;
 }
 
 gdpm_status gdpm_phantom_destroy(gdpm_phantom ph) {
     if (!ph) return fail(GDPM_E_INVALID, "NULL phantom");
+    ph->ctx->resident_bytes -= (double)ph->vox.bytes;
     delete ph;
     return GDPM_OK;
 }
@@ -1067,15 +1244,207 @@ gdpm_status gdpm_run_async(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
     return GDPM_OK;
 }
 
+gdpm_status gdpm_run_batch(gdpm_context ctx, int n, const gdpm_job_desc* jobs,
+                           gdpm_run_stats* stats, gdpm_status* status) {
+    if (!ctx || !jobs || n < 1) return fail(GDPM_E_INVALID, "need a context and n >= 1 jobs");
+    if (ctx->busy) return fail(GDPM_E_BUSY, "context busy");
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::vector<std::unique_ptr<EJob>> ej;
+    for (int i = 0; i < n; ++i) {
+        ej.emplace_back(new EJob);
+        gdpm_status s = make_job(ctx, jobs[i].phantom, jobs[i].source, &jobs[i].params, ej.back().get());
+        if (s) return fail(s, "job %d: %s", i, g_err.c_str());
+    }
+    if (status)
+        for (int i = 0; i < n; ++i) status[i] = GDPM_OK;
+    ctx->busy = true;
+    struct Busy {
+        gdpm_context c;
+        ~Busy() { c->busy = false; }
+    } busy{ctx};
+    hipStream_t st = ctx->stream;
+    const double t0 = now_s();
+    if (ctx->autotune) {
+        // queue capacity from the work submitted: room for the first
+        // super-rounds of all jobs in a few iterations (2^21 .. 2^26 records)
+        double work = 0.0;
+        for (auto& j : ej) work += (double)j->plan.n_hist;
+        const int lg = (int)std::ceil(std::log2(std::max(work, 1.0)));
+        ctx->ring_log2 = std::min(26, std::max(21, lg));
+    }
+    Engine E;
+    gdpm_status s = E.init(ctx, st, ej[0]->plan);
+    if (s) return s;
+    int next = 0, left = n;
+    gdpm_status first_err = GDPM_OK;
+    while (left > 0) {
+        // admit while slots and memory allow
+        while (next < n) {
+            EJob* j = ej[next].get();
+            s = E.admit(j);
+            if (s == GDPM_E_BUSY || (s == GDPM_E_NOMEM && E.any_active())) {
+                (void)hipGetLastError();
+                break;
+            }
+            if (s) return fail(s, "job %d: %s", next, g_err.c_str());
+            ++next;
+        }
+        s = E.step();
+        if (!s) s = E.settle();
+        if (s) {
+            first_err = s;
+            break;
+        }
+        for (int i = 0; i < next; ++i) {
+            EJob* j = ej[i].get();
+            if (!j->done || j->slot < 0) continue;
+            // outputs of a finished job, then its device memory goes back
+            if (jobs[i].dose)
+                HIP_TRY(hipMemcpyAsync(jobs[i].dose, j->d_dose, j->nv * sizeof(double), hipMemcpyDeviceToHost, st));
+            if (jobs[i].sigma)
+                HIP_TRY(hipMemcpyAsync(jobs[i].sigma, j->d_sigma, j->nv * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (stats) fill_stats(E, j, t0, &stats[i]);
+            if (status) status[i] = j->status;
+            E.release(j);
+            j->tally.reset();
+            j->dose_buf.reset();
+            j->sigma_buf.reset();
+            j->mumax.reset();
+            --left;
+        }
+    }
+    if (first_err) {
+        const std::string msg = g_err;
+        if (status)
+            for (int i = 0; i < n; ++i)
+                if (!ej[i]->done) status[i] = first_err;
+        (void)hipStreamSynchronize(st);
+        g_err = msg;
+        return first_err;
+    }
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_context_settings(gdpm_context ctx, int out[5]) {
+    if (!ctx || !out) return fail(GDPM_E_INVALID, "NULL argument");
+    out[0] = ctx->waves_per_cu;
+    out[1] = ctx->rebin_bins;
+    out[2] = ctx->ring_log2;
+    out[3] = ctx->pass_histories;
+    out[4] = ctx->autotune;
+    return GDPM_OK;
+}
+
 gdpm_status gdpm_job_wait(gdpm_job job, gdpm_run_stats* stats) {
     if (!job) return fail(GDPM_E_INVALID, "NULL job");
+    if (job->srv) {
+        std::unique_lock<std::mutex> lk(job->srv->m);
+        job->srv->cv_done.wait(lk, [&] { return job->finished; });
+    }
     if (stats) *stats = job->stats;
+    if (job->status != GDPM_OK) g_err = job->err;
     return job->status;
 }
 
 gdpm_status gdpm_job_release(gdpm_job job) {
     if (!job) return fail(GDPM_E_INVALID, "NULL job");
+    if (job->srv) {
+        std::lock_guard<std::mutex> lk(job->srv->m);
+        if (!job->finished) return fail(GDPM_E_BUSY, "the job has not finished");
+    }
     delete job;
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_server_create(gdpm_context ctx, uint64_t hbm_budget_bytes, int max_slots,
+                               gdpm_server* out) {
+    if (!ctx || !out) return fail(GDPM_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > kMaxJobs) return fail(GDPM_E_INVALID, "max_slots in [1, %d]", kMaxJobs);
+    if (hbm_budget_bytes == 0) return fail(GDPM_E_INVALID, "hbm_budget_bytes must be > 0");
+    if (ctx->busy) return fail(GDPM_E_BUSY, "context busy");
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto srv = std::make_unique<gdpm_server_s>();
+    srv->ctx = ctx;
+    srv->budget = hbm_budget_bytes;
+    srv->max_slots = max_slots;
+    ctx->busy = true;
+    try {
+        srv->th = std::thread([s = srv.get()] { s->loop(); });
+    } catch (...) {
+        ctx->busy = false;
+        return fail(GDPM_E_NOMEM, "cannot start the server thread");
+    }
+    *out = srv.release();
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_server_submit(gdpm_server srv, const gdpm_job_desc* d, gdpm_job* out) {
+    if (!srv || !d || !out) return fail(GDPM_E_INVALID, "NULL argument");
+    *out = nullptr;
+    auto job = std::make_unique<gdpm_job_s>();
+    job->ctx = srv->ctx;
+    job->srv = srv;
+    job->ej.reset(new EJob);
+    gdpm_status s = make_job(srv->ctx, d->phantom, d->source, &d->params, job->ej.get());
+    if (s) return s;
+    const EJob& j = *job->ej;
+    const TableKey k{j.plan.ecut_g, j.plan.ecut_e, j.plan.flags & 0x3Fu};
+    job->dose = d->dose;
+    job->sigma = d->sigma;
+    job->finished = false;
+    job->ej->t_submit = now_s();
+    {
+        std::lock_guard<std::mutex> lk(srv->m);
+        if (srv->stop) return fail(GDPM_E_INVALID, "the server is stopping");
+        if (!srv->key_set) {
+            srv->key = k;
+            srv->key_set = true;
+        } else if (k < srv->key || srv->key < k) {
+            return fail(GDPM_E_INVALID, "jobs of a server must share cutoffs and physics flags");
+        }
+        srv->pending.push_back(job.get());
+        srv->submitted++;
+    }
+    srv->cv_work.notify_all();
+    *out = job.release();
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_server_info_get(gdpm_server srv, gdpm_server_info* info) {
+    if (!srv || !info) return fail(GDPM_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->m);
+    memset(info, 0, sizeof *info);
+    info->submitted = srv->submitted;
+    info->finished = srv->finished;
+    info->running = srv->running.size();
+    info->queued = srv->pending.size();
+    info->histories = srv->histories;
+    info->footprint_bytes = (double)srv->used;
+    info->high_water_bytes = (double)srv->high_water;
+    gdpm_context ctx = srv->ctx;
+    double res = (double)(ctx->ctl.bytes + ctx->jobs_dev.bytes + ctx->jc.bytes + ctx->segs.bytes);
+    for (int r = 0; r < 2; ++r)
+        for (int b = 0; b < 2; ++b) res += (double)ctx->rings[r][b].bytes;
+    for (auto& t : ctx->tables)
+        res += (double)(t.second->phot.bytes + t.second->elec.bytes + t.second->rinv.bytes +
+                        t.second->rinv_scale.bytes + t.second->aw.bytes);
+    res += ctx->resident_bytes;
+    info->resident_bytes = res;
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_server_destroy(gdpm_server srv) {
+    if (!srv) return fail(GDPM_E_INVALID, "NULL server");
+    {
+        std::lock_guard<std::mutex> lk(srv->m);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    if (srv->th.joinable()) srv->th.join();
+    srv->ctx->busy = false;
+    delete srv;
     return GDPM_OK;
 }
 

@@ -24,7 +24,9 @@ EXPORTS = ("gdpm_context_create", "gdpm_context_destroy", "gdpm_last_error", "gd
            "gdpm_phantom_create", "gdpm_phantom_destroy", "gdpm_source_create",
            "gdpm_source_destroy", "gdpm_run", "gdpm_run_async", "gdpm_job_wait",
            "gdpm_job_release", "gdpm_tables_host", "gdpm_test_philox", "gdpm_test_sample",
-           "gdpm_test_source", "gdpm_test_lookup")
+           "gdpm_test_source", "gdpm_test_lookup", "gdpm_run_batch", "gdpm_context_settings",
+           "gdpm_server_create", "gdpm_server_submit", "gdpm_server_info_get",
+           "gdpm_server_destroy")
 
 
 class GdpmError(RuntimeError):
@@ -73,6 +75,18 @@ class RunStats(C.Structure):
                 ("deposits", C.c_uint64 * 2)]
 
 
+class JobDesc(C.Structure):
+    _fields_ = [("phantom", C.c_void_p), ("source", C.c_void_p), ("params", RunParams),
+                ("dose", C.POINTER(C.c_double)), ("sigma", C.POINTER(C.c_double))]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("finished", C.c_uint64), ("running", C.c_uint64),
+                ("queued", C.c_uint64), ("histories", C.c_uint64),
+                ("footprint_bytes", C.c_double), ("high_water_bytes", C.c_double),
+                ("resident_bytes", C.c_double)]
+
+
 def lib():
     """Load libgdpm.so (built in-tree by build.py); raises when it is missing."""
     global _lib
@@ -104,6 +118,13 @@ def lib():
             "gdpm_test_source": [vp, vp, vp, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int, fp],
             "gdpm_test_lookup": [vp, C.c_double, C.c_double, C.c_uint32, C.c_int, C.c_int, fp, fp,
                                  C.c_int],
+            "gdpm_run_batch": [vp, C.c_int, C.POINTER(JobDesc), C.POINTER(RunStats),
+                               C.POINTER(C.c_int)],
+            "gdpm_context_settings": [vp, C.POINTER(C.c_int)],
+            "gdpm_server_create": [vp, C.c_uint64, C.c_int, C.POINTER(vp)],
+            "gdpm_server_submit": [vp, C.POINTER(JobDesc), C.POINTER(vp)],
+            "gdpm_server_info_get": [vp, C.POINTER(ServerInfo)],
+            "gdpm_server_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -231,6 +252,37 @@ class Context:
     def source(self, src) -> Source:
         return Source(self, src)
 
+    def settings(self):
+        """Launch settings in use (after any autotuning)."""
+        a = (C.c_int * 5)()
+        _check(lib().gdpm_context_settings(self.handle, a))
+        return dict(zip(("waves_per_cu", "rebin_bins", "ring_capacity_log2", "pass_histories",
+                         "autotune"), list(a)))
+
+    def run_batch(self, jobs, want_dose=True):
+        """Run several jobs together.  jobs: sequence of (phantom, source, params dict);
+        params take the keyword arguments of run().  Returns one result dict per job."""
+        n = len(jobs)
+        descs = (JobDesc * n)()
+        outs = []
+        for i, (ph, src, kw) in enumerate(jobs):
+            prm = _params(kw)
+            nv = ph.desc.nvox
+            dose = np.zeros(nv) if want_dose else None
+            sigma = np.zeros(nv) if want_dose else None
+            descs[i] = JobDesc(ph.handle, src.handle, prm, _dp(dose), _dp(sigma))
+            outs.append((dose, sigma))
+        stats = (RunStats * n)()
+        status = (C.c_int * n)()
+        _check(lib().gdpm_run_batch(self.handle, n, descs, stats, status))
+        res = []
+        for i in range(n):
+            r = _stats_dict(stats[i])
+            r["status"] = STATUS[status[i]]
+            r["dose"], r["sigma"] = outs[i]
+            res.append(r)
+        return res
+
     def run(self, phantom: Phantom, source: Source, *, seed=1, n_hist=1000, n_batches=10,
             round_size=0, hist0=0, job_id=0, ecut_g=0.05, ecut_e=0.2, flags=0, target_unc=0.0,
             max_histories=0, stat_min_density=0.0, want_batches=False, want_hist=False,
@@ -306,6 +358,70 @@ class Context:
     def close(self):
         if self.handle:
             lib().gdpm_context_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _params(kw):
+    return RunParams(kw.get("seed", 1), kw.get("job_id", 0), kw.get("n_hist", 1000),
+                     kw.get("target_unc", 0.0), kw.get("n_batches", 10), kw.get("ecut_g", 0.05),
+                     kw.get("ecut_e", 0.2), kw.get("max_histories", 0), kw.get("flags", 0),
+                     kw.get("round_size", 0), kw.get("hist0", 0), kw.get("stat_min_density", 0.0))
+
+
+class ServerJob:
+    """A queued or running job of a Server; wait() returns its result dict."""
+
+    def __init__(self, handle, dose, sigma, desc):
+        self.handle, self.dose, self.sigma = handle, dose, sigma
+        self._desc = desc   # keeps the descriptor's arrays alive until the job ends
+
+    def wait(self):
+        st = RunStats()
+        rc = lib().gdpm_job_wait(self.handle, C.byref(st))
+        msg = lib().gdpm_last_error().decode() if rc not in (0, 6) else ""
+        lib().gdpm_job_release(self.handle)
+        self.handle = None
+        if rc not in (0, 6):
+            raise GdpmError(rc, msg)
+        r = _stats_dict(st)
+        r["status"] = STATUS[rc]
+        r["dose"], r["sigma"] = self.dose, self.sigma
+        return r
+
+
+class Server:
+    """Request loop of libgdpm on a context: admission by device footprint and
+    slots, continuous batching of the admitted jobs (gdpm_server_*)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 64):
+        self.ctx = ctx
+        self.handle = C.c_void_p()
+        _check(lib().gdpm_server_create(ctx.handle, int(hbm_budget_bytes), max_slots,
+                                        C.byref(self.handle)))
+
+    def submit(self, phantom: Phantom, source: Source, want_dose=True, **kw) -> ServerJob:
+        nv = phantom.desc.nvox
+        dose = np.zeros(nv) if want_dose else None
+        sigma = np.zeros(nv) if want_dose else None
+        desc = JobDesc(phantom.handle, source.handle, _params(kw), _dp(dose), _dp(sigma))
+        job = C.c_void_p()
+        _check(lib().gdpm_server_submit(self.handle, C.byref(desc), C.byref(job)))
+        return ServerJob(job, dose, sigma, desc)
+
+    def info(self):
+        i = ServerInfo()
+        _check(lib().gdpm_server_info_get(self.handle, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in ServerInfo._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().gdpm_server_destroy(self.handle))
             self.handle = C.c_void_p()
 
     def __enter__(self):

@@ -289,3 +289,58 @@ def ct_imrt(n_hist: int = 100_000_000, n=(256, 256, 128), d=(0.2, 0.2, 0.25),
     ph = ct_phantom(n, d)
     src = Source(PHOTON, triangular_spectrum(), imrt_plan(ph))
     return Workload("ct256x256x128_imrt9_6MVlike", ph, src, n_hist, target_unc=target_unc)
+
+
+def batch_jobs(n_jobs: int = 64, seed: int = 4001, side=(48, 256), d: float = 0.25,
+               hist=(1e5, 1e7), target_unc: float = 0.0) -> List[Workload]:
+    """Independent dose jobs of uneven size for the batched form: cubes of side
+    uniform in `side` voxels of `d` cm with random lung/bone ellipsoids;
+    histories log-uniform in `hist`; half the jobs use the 6 MV-like spectrum,
+    the others a monoenergetic 1-20 MeV beam, photons or electrons with equal
+    odds; a parallel 10x10 cm field along +z, clipped to the phantom."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n_jobs):
+        n = int(rng.integers(side[0], side[1] + 1))
+        ph = ellipsoid_phantom(n, d, seed=seed * 1000 + k)
+        field = min(10.0, n * d)
+        if rng.random() < 0.5:
+            src = Source(PHOTON, triangular_spectrum(), [parallel_beam_z(ph, field)])
+            kind = "6MVlike"
+        else:
+            e = float(rng.uniform(1.0, 20.0))
+            particle = PHOTON if rng.random() < 0.5 else ELECTRON
+            src = Source(particle, mono(e), [parallel_beam_z(ph, field)])
+            kind = f"{'photon' if particle == PHOTON else 'electron'}{e:.1f}MeV"
+        nh = int(round(10 ** rng.uniform(np.log10(hist[0]), np.log10(hist[1]))))
+        out.append(Workload(f"cube{n}_{kind}", ph, src, nh, target_unc=target_unc))
+    return out
+
+
+def serving_requests(duration_s: float = 300.0, rate: float = 2.0, seed: int = 5001,
+                     ct=None, small_ct=None):
+    """Poisson request stream of the serving form: arrival times at `rate` jobs/s
+    over `duration_s`; each request is a VMAT-like arc (180 control points, 40x40
+    fluence per point) on the 256x256x128 CT or a 9-beam IMRT job on a
+    128x128x64 CT of 0.4x0.4x0.5 cm voxels (same extent), with equal odds, at a
+    requested uncertainty of 1% or 2% with equal odds.  Returns (arrival time,
+    Workload) pairs; phantoms are shared between requests of the same kind."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ct = ct if ct is not None else ct_phantom()
+    small_ct = small_ct if small_ct is not None else ct_phantom((128, 128, 64), (0.4, 0.4, 0.5))
+    t, out = 0.0, []
+    k = 0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration_s:
+            break
+        unc = 0.01 if rng.random() < 0.5 else 0.02
+        if rng.random() < 0.5:
+            src = Source(PHOTON, triangular_spectrum(), vmat_arc(ct, seed=seed + 7 * k))
+            w = Workload(f"vmat180_ct256_{unc:.0%}", ct, src, 20_000_000, target_unc=unc)
+        else:
+            src = Source(PHOTON, triangular_spectrum(), imrt_plan(small_ct, seed=seed + 7 * k))
+            w = Workload(f"imrt9_ct128_{unc:.0%}", small_ct, src, 5_000_000, target_unc=unc)
+        out.append((t, w))
+        k += 1
+    return out

@@ -1,0 +1,205 @@
+"""Many jobs through one engine: the batched form (gdpm_run_batch) and the
+server (gdpm_server_*).
+
+A job's particles draw only from the job's own Philox streams (seed, job_id),
+so its dose in a mix must equal its dose alone up to the order of the FP64
+tally additions; that is checked to a relative 1e-9 of the job's maximum dose.
+Energy balance is checked per job.  Plus admission by slots and footprint, the
+online autotuner (which may change launch settings, never results), and error
+paths."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1107_3355_amd import gdpm as G
+from paper_1107_3355_amd import inputs as I
+from tests.gpu_common import balance, report
+
+pytestmark = pytest.mark.gpu
+MATS = I.MATERIALS
+
+
+def small_jobs(n=5, seed=4101):
+    """Uneven small jobs: photons and electrons, spectra and lines, fixed and
+    target-uncertainty mode."""
+    ws = I.batch_jobs(n, seed=seed, side=(12, 28), d=0.5, hist=(3e3, 4e4))
+    out = []
+    for k, w in enumerate(ws):
+        kw = dict(seed=11 + k, job_id=k, n_hist=w.n_hist, n_batches=10)
+        if k == 1:
+            # super-rounds until 5% (about 1e6 histories on these cubes)
+            kw.update(target_unc=0.05, n_hist=20_000, max_histories=5_000_000)
+        out.append((w, kw))
+    return out
+
+
+def same_dose(a, b, what):
+    scale = max(np.abs(a).max(), np.abs(b).max(), 1e-300)
+    err = np.abs(a - b).max() / scale
+    report(what, max_rel_diff=f"{err:.2e}")
+    assert err < 1e-9, what
+
+
+def solo(ctx, w, kw):
+    p, s = ctx.phantom(w.phantom), ctx.source(w.source)
+    try:
+        return ctx.run(p, s, **kw)
+    finally:
+        p.close()
+        s.close()
+
+
+def test_batch_equals_solo(gctx):
+    jobs = small_jobs()
+    handles = [(gctx.phantom(w.phantom), gctx.source(w.source), kw) for w, kw in jobs]
+    try:
+        res = gctx.run_batch(handles)
+    finally:
+        for p, s, _ in handles:
+            p.close()
+            s.close()
+    for (w, kw), r in zip(jobs, res):
+        assert r["status"] in ("GDPM_OK", "GDPM_E_NOT_CONVERGED")
+        a = solo(gctx, w, kw)
+        assert r["histories"] == a["histories"], w.name
+        assert balance(r) < 1e-6, w.name
+        same_dose(r["dose"], a["dose"], f"batch vs solo {w.name}")
+        same_dose(r["sigma"], a["sigma"], f"batch vs solo sigma {w.name}")
+        assert abs(r["e_in"] - a["e_in"]) <= 1e-12 * a["e_in"]
+        if kw.get("target_unc"):
+            assert r["status"] == "GDPM_OK" and r["unc"] <= kw["target_unc"]
+            assert r["rounds"] > 10   # more than one super-round
+
+
+def test_batch_more_jobs_than_slots(gctx):
+    """300 tiny jobs: admitted 256 at a time, the rest as slots free up."""
+    ph = I.homogeneous((6, 6, 6), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
+    src = I.Source(I.PHOTON, I.mono(1.25), [I.parallel_beam_z(ph, 4.0)])
+    p, s = gctx.phantom(ph), gctx.source(src)
+    try:
+        res = gctx.run_batch([(p, s, dict(seed=5, job_id=k, n_hist=300 + k, n_batches=2))
+                              for k in range(300)])
+        ref = gctx.run(p, s, seed=5, job_id=299, n_hist=599, n_batches=2)
+    finally:
+        p.close()
+        s.close()
+    assert all(r["status"] == "GDPM_OK" for r in res)
+    assert [r["histories"] for r in res] == [300 + k for k in range(300)]
+    assert max(balance(r) for r in res) < 1e-6
+    same_dose(res[-1]["dose"], ref["dose"], "job 299 of 300 vs solo")
+
+
+def test_autotune_changes_speed_not_results():
+    ws = I.batch_jobs(3, seed=4201, side=(32, 40), d=0.5, hist=(2e5, 4e5))
+    ctx = G.Context(0, opts='{"autotune": 1}', materials=MATS)
+    try:
+        hs = [(ctx.phantom(w.phantom), ctx.source(w.source),
+               dict(seed=3 + k, job_id=k, n_hist=w.n_hist)) for k, w in enumerate(ws)]
+        res = ctx.run_batch(hs)
+        st = ctx.settings()
+        report("autotune", **st)
+        assert st["waves_per_cu"] in (8, 12) and st["rebin_bins"] in (4, 16)
+        assert 21 <= st["ring_capacity_log2"] <= 26
+        for p, s, _ in hs:
+            p.close()
+            s.close()
+    finally:
+        ctx.close()
+    ctx2 = G.Context(0, materials=MATS)
+    try:
+        for k, (w, r) in enumerate(zip(ws, res)):
+            a = solo(ctx2, w, dict(seed=3 + k, job_id=k, n_hist=w.n_hist))
+            same_dose(r["dose"], a["dose"], f"autotuned batch vs solo {w.name}")
+    finally:
+        ctx2.close()
+
+
+def test_server_alone_and_in_the_mix():
+    """Job A alone, then job B (longer) with A submitted again while B runs:
+    A's dose is the same both times and B's equals B alone."""
+    wa = I.water_cube_2mev(30_000)
+    wb = I.batch_jobs(1, seed=4301, side=(40, 40), d=0.5, hist=(2e6, 2e6))[0]
+    ka = dict(seed=21, job_id=1, n_hist=wa.n_hist)
+    kb = dict(seed=22, job_id=2, n_hist=wb.n_hist)
+    ctx = G.Context(0, materials=MATS)
+    try:
+        pa, sa = ctx.phantom(wa.phantom), ctx.source(wa.source)
+        pb, sb = ctx.phantom(wb.phantom), ctx.source(wb.source)
+        srv = G.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=8)
+        try:
+            alone = srv.submit(pa, sa, **ka).wait()
+            jb = srv.submit(pb, sb, **kb)
+            ja = srv.submit(pa, sa, **ka)
+            mixed = ja.wait()
+            rb = jb.wait()
+            info = srv.info()
+        finally:
+            srv.close()
+        solo_b = ctx.run(pb, sb, **kb)   # the server is gone: the context runs again
+        for h in (pa, sa, pb, sb):
+            h.close()
+    finally:
+        ctx.close()
+    report("server", latency_alone=f"{alone['t_total_s']:.3f}", latency_mixed=f"{mixed['t_total_s']:.3f}",
+           **{k: info[k] for k in ("submitted", "finished", "histories")})
+    assert info["submitted"] == 3 and info["finished"] == 3
+    assert info["histories"] == 2 * wa.n_hist + wb.n_hist
+    assert info["high_water_bytes"] > 0 and info["footprint_bytes"] == 0
+    same_dose(mixed["dose"], alone["dose"], "server: A in the mix vs alone")
+    same_dose(rb["dose"], solo_b["dose"], "server: B vs gdpm_run")
+    for r in (alone, mixed, rb):
+        assert balance(r) < 1e-6
+
+
+def test_server_admission_waits_for_memory():
+    """A budget that holds one job at a time: the second job is queued until the
+    first leaves, and still gets the same dose."""
+    w = I.water_cube_2mev(20_000)
+    ctx = G.Context(0, materials=MATS)
+    try:
+        p, s = ctx.phantom(w.phantom), ctx.source(w.source)
+        nv = w.phantom.nvox
+        one_job = 10 * nv * 8 + 2 * nv * 8 + 64 * 1024
+        srv = G.Server(ctx, hbm_budget_bytes=int(1.5 * one_job), max_slots=8)
+        try:
+            j1 = srv.submit(p, s, seed=31, job_id=1, n_hist=w.n_hist)
+            j2 = srv.submit(p, s, seed=32, job_id=2, n_hist=w.n_hist)
+            r1, r2 = j1.wait(), j2.wait()
+            info = srv.info()
+        finally:
+            srv.close()
+        solo2 = ctx.run(p, s, seed=32, job_id=2, n_hist=w.n_hist)
+        p.close()
+        s.close()
+    finally:
+        ctx.close()
+    assert info["high_water_bytes"] <= 1.5 * one_job
+    same_dose(r2["dose"], solo2["dose"], "server: queued job vs solo")
+    assert balance(r1) < 1e-6 and balance(r2) < 1e-6
+
+
+def test_server_errors():
+    w = I.water_cube_2mev(1000)
+    ctx = G.Context(0, materials=MATS)
+    try:
+        p, s = ctx.phantom(w.phantom), ctx.source(w.source)
+        with pytest.raises(G.GdpmError) as e:
+            G.Server(ctx, hbm_budget_bytes=0)
+        assert e.value.status == 1
+        srv = G.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=2)
+        try:
+            with pytest.raises(G.GdpmError) as e:   # the context belongs to the server
+                ctx.run(p, s, n_hist=100)
+            assert e.value.status == 5
+            j = srv.submit(p, s, seed=1, n_hist=2000)
+            with pytest.raises(G.GdpmError) as e:   # other cutoffs than the first job
+                srv.submit(p, s, seed=1, n_hist=100, ecut_e=0.3)
+            assert e.value.status == 1
+            assert j.wait()["histories"] == 2000
+        finally:
+            srv.close()
+        p.close()
+        s.close()
+    finally:
+        ctx.close()
