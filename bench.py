@@ -72,6 +72,101 @@ def cpu_baseline(workload, seconds):
                       f"transport on {threads} threads, {dt:.1f} s including the run set-up"}
 
 
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, dtype=float), q)) if len(a) else None
+
+
+def batched_form(G, I, n_jobs):
+    """Uneven dose jobs (cubes of 48-256 voxels, 1e5-1e7 histories, spectra and
+    lines, photons and electrons): all in one batched run against the same jobs
+    as sequential single-job runs.  Latency of a job: from the start of the
+    whole set to the job's completion."""
+    ws = I.batch_jobs(n_jobs)
+    ctx = G.Context(0, materials=I.MATERIALS)
+    hs = [(ctx.phantom(w.phantom), ctx.source(w.source), dict(seed=100 + k, job_id=k, n_hist=w.n_hist))
+          for k, w in enumerate(ws)]
+    hist = sum(w.n_hist for w in ws)
+    ctx.run(hs[0][0], hs[0][1], n_hist=10_000, want_dose=False)   # tables and queues
+    t0 = time.perf_counter()
+    res = ctx.run_batch(hs, want_dose=False)
+    tb = time.perf_counter() - t0
+    lat_b = [r["t_total_s"] for r in res]
+    t0 = time.perf_counter()
+    lat_s = []
+    for p, s, kw in hs:
+        ctx.run(p, s, want_dose=False, **kw)
+        lat_s.append(time.perf_counter() - t0)
+    ts = time.perf_counter() - t0
+    for p, s, _ in hs:
+        p.close()
+        s.close()
+    ctx.close()
+    return {"workload": f"{n_jobs} jobs, cubes 48-256 voxels of 0.25 cm, 1e5-1e7 histories each",
+            "histories": hist,
+            "batched": {"seconds": tb, "histories_per_s": hist / tb,
+                        "latency_s": {"p50": pct(lat_b, 50), "p99": pct(lat_b, 99)}},
+            "sequential": {"seconds": ts, "histories_per_s": hist / ts,
+                           "latency_s": {"p50": pct(lat_s, 50), "p99": pct(lat_s, 99)}},
+            "speedup": ts / tb}
+
+
+def served_form(G, I, seconds, rate, ct):
+    """Poisson request stream (VMAT arcs on the 256x256x128 CT and IMRT jobs on a
+    128x128x64 CT, to 1% or 2%) into a server that admits by device footprint and
+    batches the admitted jobs, against the same requests run one at a time in
+    arrival order (queueing latency from the arrival times and measured run
+    times)."""
+    import threading
+    reqs = I.serving_requests(duration_s=seconds, rate=rate, ct=ct)
+    ctx = G.Context(0, materials=I.MATERIALS)
+    phs, hs = {}, []
+    for k, (t, w) in enumerate(reqs):
+        key = id(w.phantom)
+        if key not in phs:
+            phs[key] = ctx.phantom(w.phantom)
+        hs.append((t, phs[key], ctx.source(w.source),
+                   dict(seed=500 + k, job_id=k, n_hist=w.n_hist, target_unc=w.target_unc,
+                        stat_min_density=0.1)))
+    ctx.run(hs[0][1], hs[0][2], n_hist=10_000, want_dose=False)   # tables and queues
+    budget = 64 << 30
+    srv = G.Server(ctx, hbm_budget_bytes=budget, max_slots=64)
+    jobs = []
+    t0 = time.perf_counter()
+    for t, p, s, kw in hs:
+        d = t - (time.perf_counter() - t0)
+        if d > 0:
+            time.sleep(d)
+        jobs.append(srv.submit(p, s, want_dose=False, **kw))
+    res = [j.wait() for j in jobs]
+    wall = time.perf_counter() - t0
+    info = srv.info()
+    srv.close()
+    lat = [r["t_total_s"] for r in res]
+    hist = sum(r["histories"] for r in res)
+    # the same requests, one plain run at a time in arrival order
+    run_s, done, lat_seq = [], 0.0, []
+    for (t, p, s, kw) in hs:
+        a = time.perf_counter()
+        ctx.run(p, s, want_dose=False, **kw)
+        run_s.append(time.perf_counter() - a)
+        done = max(done, t) + run_s[-1]
+        lat_seq.append(done - t)
+    for _, _, s, _ in hs:
+        s.close()
+    for p in phs.values():
+        p.close()
+    ctx.close()
+    return {"workload": f"Poisson {rate} jobs/s for {seconds} s: {len(reqs)} requests, VMAT-180 on "
+                        "256x256x128 CT or IMRT-9 on 128x128x64 CT, to 1% or 2%",
+            "histories": hist,
+            "served": {"seconds": wall, "histories_per_s": hist / wall,
+                       "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+                       "memory_high_water_bytes": info["high_water_bytes"] + info["resident_bytes"],
+                       "hbm_budget_bytes": budget},
+            "one_at_a_time": {"seconds": max(done, 0.0), "histories_per_s": hist / max(sum(run_s), 1e-9),
+                              "latency_s": {"p50": pct(lat_seq, 50), "p99": pct(lat_seq, 99)}}}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed hardware-counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
@@ -121,6 +216,11 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB before the "
                          "timed jobs (a reference kernel of known traffic for hardware counters)")
+    ap.add_argument("--batched-jobs", type=int, default=64,
+                    help="jobs of the batched-form comparison (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="length of the served request stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="requests per second")
     ap.add_argument("--min-density", type=float, default=0.1,
                     help="voxels below this density (the air around the patient) are left out "
                          "of D_max and of the uncertainty statistic")
@@ -213,6 +313,14 @@ def main():
         "kernel_time_s": {"photon": tp, "electron": te},
         "roofline": roof,
     }
+    if args.batched_jobs > 0:
+        log(f"batched form: {args.batched_jobs} jobs")
+        out["batched_form"] = batched_form(G, I, args.batched_jobs)
+        log(f"batched form: speed-up {out['batched_form']['speedup']:.2f}x over sequential runs")
+    if args.serve_seconds > 0:
+        log(f"served form: {args.serve_seconds} s of requests at {args.serve_rate}/s")
+        out["served_form"] = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom)
+        log("served form: p50/p99 " + str(out["served_form"]["served"]["latency_s"]))
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
