@@ -82,20 +82,27 @@ def batched_form(G, I, n_jobs):
     as sequential single-job runs.  Latency of a job: from the start of the
     whole set to the job's completion."""
     ws = I.batch_jobs(n_jobs)
+    log(f"batched form: {n_jobs} jobs generated ({sum(w.n_hist for w in ws):.3g} histories)")
     ctx = G.Context(0, materials=I.MATERIALS)
     hs = [(ctx.phantom(w.phantom), ctx.source(w.source), dict(seed=100 + k, job_id=k, n_hist=w.n_hist))
           for k, w in enumerate(ws)]
     hist = sum(w.n_hist for w in ws)
     ctx.run(hs[0][0], hs[0][1], n_hist=10_000, want_dose=False)   # tables and queues
+    log("batched form: inputs on the device, batched run")
     t0 = time.perf_counter()
     res = ctx.run_batch(hs, want_dose=False)
     tb = time.perf_counter() - t0
+    log(f"batched form: batched run {tb:.3f} s, now one job at a time")
     lat_b = [r["t_total_s"] for r in res]
+    bal = max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res)
+    repairs = sum(r["accounting_repairs"] for r in res)
     t0 = time.perf_counter()
     lat_s = []
-    for p, s, kw in hs:
+    for k, (p, s, kw) in enumerate(hs):
         ctx.run(p, s, want_dose=False, **kw)
         lat_s.append(time.perf_counter() - t0)
+        if k % 16 == 15:
+            log(f"batched form: {k + 1} sequential jobs done")
     ts = time.perf_counter() - t0
     for p, s, _ in hs:
         p.close()
@@ -107,7 +114,7 @@ def batched_form(G, I, n_jobs):
                         "latency_s": {"p50": pct(lat_b, 50), "p99": pct(lat_b, 99)}},
             "sequential": {"seconds": ts, "histories_per_s": hist / ts,
                            "latency_s": {"p50": pct(lat_s, 50), "p99": pct(lat_s, 99)}},
-            "speedup": ts / tb}
+            "speedup": ts / tb, "energy_balance_max": bal, "accounting_repairs": repairs}
 
 
 def served_form(G, I, seconds, rate, ct):
@@ -129,6 +136,7 @@ def served_form(G, I, seconds, rate, ct):
                         stat_min_density=0.1)))
     ctx.run(hs[0][1], hs[0][2], n_hist=10_000, want_dose=False)   # tables and queues
     budget = 64 << 30
+    log(f"served form: {len(reqs)} requests")
     srv = G.Server(ctx, hbm_budget_bytes=budget, max_slots=64)
     jobs = []
     t0 = time.perf_counter()
@@ -137,17 +145,23 @@ def served_form(G, I, seconds, rate, ct):
         if d > 0:
             time.sleep(d)
         jobs.append(srv.submit(p, s, want_dose=False, **kw))
-    res = [j.wait() for j in jobs]
+    res = []
+    for k, j in enumerate(jobs):
+        res.append(j.wait())
+        log(f"served form: request {k} done after {res[-1]['t_total_s']:.2f} s")
     wall = time.perf_counter() - t0
     info = srv.info()
     srv.close()
     lat = [r["t_total_s"] for r in res]
     hist = sum(r["histories"] for r in res)
+    bal = max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res)
+    repairs = sum(r["accounting_repairs"] for r in res)
     # the same requests, one plain run at a time in arrival order
     run_s, done, lat_seq = [], 0.0, []
-    for (t, p, s, kw) in hs:
+    for k, (t, p, s, kw) in enumerate(hs):
         a = time.perf_counter()
         ctx.run(p, s, want_dose=False, **kw)
+        log(f"served form: request {k} alone in {time.perf_counter() - a:.2f} s")
         run_s.append(time.perf_counter() - a)
         done = max(done, t) + run_s[-1]
         lat_seq.append(done - t)
@@ -158,7 +172,7 @@ def served_form(G, I, seconds, rate, ct):
     ctx.close()
     return {"workload": f"Poisson {rate} jobs/s for {seconds} s: {len(reqs)} requests, VMAT-180 on "
                         "256x256x128 CT or IMRT-9 on 128x128x64 CT, to 1% or 2%",
-            "histories": hist,
+            "histories": hist, "energy_balance_max": bal, "accounting_repairs": repairs,
             "served": {"seconds": wall, "histories_per_s": hist / wall,
                        "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
                        "memory_high_water_bytes": info["high_water_bytes"] + info["resident_bytes"],
@@ -309,6 +323,8 @@ def main():
                    "tally": "f64"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "unc_reached": [r["unc"] for r in runs],
+        "energy_balance_max": max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in runs),
+        "accounting_repairs": sum(r["accounting_repairs"] for r in runs),
         "events_per_history": {k: v / hist for k, v in ev.items() if k != "histories"},
         "kernel_time_s": {"photon": tp, "electron": te},
         "roofline": roof,

@@ -148,6 +148,12 @@ typedef struct {
      * loaded and stored (secondaries and particles handed to the next pass),
      * and FP64 tally deposits; the memory traffic the passes cannot avoid */
     uint64_t records_loaded[2], records_stored[2], deposits[2];
+    /* consistency of the particle accounting: the number of times the run
+     * found the queues empty while the job's particle births and deaths
+     * differed, and the summed difference (births - deaths); 0 and 0 in a
+     * sound run.  A nonzero gap is also visible in the energy balance. */
+    uint32_t accounting_repairs;
+    int64_t accounting_gap;
 } gdpm_run_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -164,6 +170,9 @@ typedef struct {
  * Each wavefront reserves queue slots 256 at a time, so a queue needs well
  * over 256 slots per wavefront of the grid (2^21 and up on a 256-CU device
  * with 16 wavefronts per CU); smaller queues overflow.
+ * "share" (how the jobs run together share the new histories of an iteration:
+ * 1, default, evenly; 0 in admission order, the oldest job taking what it can
+ * use), "autotune" (see gdpm_context_settings).
  * Results do not depend on any of these options (each particle draws from its
  * own random stream), only the speed does. */
 gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out);

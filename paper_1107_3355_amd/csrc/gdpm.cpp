@@ -41,6 +41,8 @@ hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, boo
                             const Tables& T, const RunDev& R);
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
                         float lo, float inv);
+hipError_t launch_count_records(hipStream_t st, int blocks, const Ctl* ctl, const RunDev& R,
+                                unsigned long long* counts);
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
                         int nb, const double* inv_n, const uint2* vox, double vvox, float min_rho,
                         double* dose, double* sigma);
@@ -177,6 +179,7 @@ struct gdpm_context_s {
     int lds_tables = 1;          // stage interpolation tables in LDS when they fit
     int pass_histories = 0;      // new histories per iteration (0: half a queue less its fill)
     int autotune = 0;            // tune block size and re-binning online, queues from the work
+    int share = 1;               // new histories: 1 evenly over the jobs, 0 oldest job first
     int max_lds = 0;             // dynamic LDS bytes a workgroup may use
     bool lds_optin = false;
     std::vector<MaterialParams> mats;
@@ -185,7 +188,7 @@ struct gdpm_context_s {
     DevBuf rings[2][2];
     DevBuf ctl;
     Ctl* host_ctl = nullptr;   // pinned mirror
-    DevBuf jobs_dev, jc, segs, inv_n;
+    DevBuf jobs_dev, jc, segs, inv_n, counts;
     JobDev* h_jobs = nullptr;  // pinned: job table, source segments, the read-back
     SrcSeg* h_segs = nullptr;  // part of the job counters, statistics reductions
     void* h_jc = nullptr;
@@ -366,10 +369,13 @@ struct EJob {
     uint32_t rounds = 0;
     double unc = 0, dmax = 0, edep = 0, e_in = 0, e_esc = 0;
     unsigned long long births = 0, deaths = 0;
+    long long death_offset = 0;   // counter repairs (see Engine::settle)
+    uint32_t repairs = 0;
     gdpm_status status = GDPM_OK;
     bool done = false;
     std::string err;
     double t_submit = 0, t_admit = 0, t_done = 0;
+    uint64_t seq = 0;           // admission order
     size_t footprint = 0;       // device bytes the job owns while admitted
 };
 
@@ -390,6 +396,7 @@ struct Engine {
     int n_slots = 0;            // slots in use: [0, n_slots)
     Timers tm;
     uint32_t iter = 0, idle = 0;
+    uint64_t admitted = 0;
     // online autotuning: launch settings change nothing in the results, so
     // candidate (waves per CU, energy bins) pairs are tried on live iterations
     // and the fastest, in transport events per kernel second, is kept
@@ -570,6 +577,7 @@ gdpm_status Engine::admit(EJob* j) {
     j->done = false;
     j->status = GDPM_OK;
     j->t_admit = now_s();
+    j->seq = admitted++;
     slots[slot] = j;
     n_slots = std::max(n_slots, slot + 1);
     return GDPM_OK;
@@ -588,7 +596,9 @@ gdpm_status Engine::step() {
     const int blocks = grid_blocks(ctx);
     const uint32_t cap = 1u << ctx->ring_log2;
     // new histories: at most half a queue (or pass_histories) less what the
-    // fuller queue holds, shared evenly by the jobs that still start histories
+    // fuller queue holds, split evenly over the jobs that still start
+    // histories (option share = 0: the oldest job takes what it can use and
+    // younger jobs fill the rest)
     const uint32_t budget = ctx->pass_histories > 0 ? (uint32_t)ctx->pass_histories : cap / 2u;
     const uint32_t fill = std::max(hc->ring[0].tail - hc->ring[0].head, hc->ring[1].tail - hc->ring[1].head);
     uint64_t room = fill < budget ? budget - fill : 0u;
@@ -597,13 +607,14 @@ gdpm_status Engine::step() {
         EJob* j = slots[i];
         if (j && !j->done && j->issued < j->sr_end) want.push_back(j);
     }
+    std::stable_sort(want.begin(), want.end(), [](const EJob* a, const EJob* b) { return a->seq < b->seq; });
     int nseg[2] = {0, 0};
     uint32_t total[2] = {0u, 0u};
     SrcSeg* hs = ctx->h_segs;
     const int seg_cap = kMaxSegs / 2;   // per source type
     for (size_t k = 0; k < want.size() && room > 0; ++k) {
         EJob* j = want[k];
-        const uint64_t share = std::max<uint64_t>(1, room / (want.size() - k));
+        const uint64_t share = ctx->share ? std::max<uint64_t>(1, room / (want.size() - k)) : room;
         uint64_t n = std::min<uint64_t>(share, j->sr_end - j->issued);
         const int ri = j->src->particle == 0 ? 0 : 1;
         while (n > 0 && nseg[ri] < seg_cap) {
@@ -701,7 +712,7 @@ gdpm_status Engine::settle() {
         EJob* j = slots[i];
         if (!j || j->done) continue;
         j->births = m->births[i];
-        j->deaths = m->deaths[i];
+        j->deaths = m->deaths[i] + (unsigned long long)j->death_offset;
         j->e_in = m->e_in[i];
         j->e_esc = m->e_esc[i];
         if (j->issued < j->sr_end || j->births != j->deaths) continue;
@@ -740,7 +751,35 @@ gdpm_status Engine::settle() {
     for (int i = 0; i < n_slots; ++i)
         if (slots[i] && !slots[i]->done && slots[i]->issued < slots[i]->sr_end) issuing = true;
     idle = (!progress && empty && !issuing) ? idle + 1 : 0;
-    if (idle > 2) return fail(GDPM_E_DEVICE, "transport made no progress (particle accounting)");
+    if (idle > 2) {
+        // The queues are empty and nothing starts, yet a job's births and
+        // deaths differ.  Count the job's records on the device: if none is
+        // left the counters drifted; align them and record the repair (it is
+        // reported in the job's statistics), else stop with the numbers.
+        HIP_TRY(ctx->counts.ensure(kMaxJobs * sizeof(unsigned long long)));
+        HIP_TRY(hipMemsetAsync(ctx->counts.p, 0, kMaxJobs * sizeof(unsigned long long), st));
+        HIP_TRY(launch_count_records(st, 4 * grid_blocks(ctx), ctx->ctl.as<const Ctl>(), R,
+                                     ctx->counts.as<unsigned long long>()));
+        std::vector<unsigned long long> live(kMaxJobs);
+        HIP_TRY(hipMemcpyAsync(live.data(), ctx->counts.p, kMaxJobs * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        int repaired = 0;
+        for (int i = 0; i < n_slots; ++i) {
+            EJob* j = slots[i];
+            if (!j || j->done || j->births == j->deaths) continue;
+            if (live[i] || j->repairs >= 3)
+                return fail(GDPM_E_DEVICE,
+                            "transport made no progress: job %d has %llu particles born, %llu ended, "
+                            "%llu records queued, %u repairs", i, (unsigned long long)j->births,
+                            (unsigned long long)j->deaths, (unsigned long long)live[i], j->repairs);
+            j->death_offset += (long long)j->births - (long long)j->deaths;
+            j->repairs++;
+            repaired++;
+        }
+        if (!repaired) return fail(GDPM_E_DEVICE, "transport made no progress (no job left to finish)");
+        idle = 0;
+    }
     return GDPM_OK;
 }
 
@@ -764,6 +803,8 @@ void fill_stats(const Engine& E, const EJob* j, double t_start, gdpm_run_stats* 
         out->deposits[k] = hc->pass_ev[k][2];
     }
     out->rounds = j->rounds;
+    out->accounting_repairs = j->repairs;
+    out->accounting_gap = j->death_offset;
     out->t_photon_s = E.tm.photon;
     out->t_electron_s = E.tm.electron;
     out->t_kernel_s = E.tm.photon + E.tm.electron;
@@ -966,6 +1007,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->lds_tables = json_int(opts_json, "lds_tables", 1);
     ctx->pass_histories = json_int(opts_json, "pass_histories", 0);
     ctx->autotune = json_int(opts_json, "autotune", 0);
+    ctx->share = json_int(opts_json, "share", 1);
     if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
     if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > kMaxBlockThreads / 64)
         return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);

@@ -1577,6 +1577,23 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri,
     }
 }
 
+// live records per job in both queues (a consistency check of the host's
+// particle accounting; counts[j] += records of job j)
+__global__ void __launch_bounds__(256) k_count_records(const Ctl* ctl, RunDev R,
+                                                       unsigned long long* counts) {
+    for (int ri = 0; ri < 2; ++ri) {
+        const RingCtl& r = ctl->ring[ri];
+        const uint32_t n = r.tail - r.head;
+        const Particle* buf = R.buf[ri][r.cur];
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const float4* q = reinterpret_cast<const float4*>(buf + ((r.head + i) & R.mask[ri]));
+            const float e = q[0].w;
+            const uint32_t j = __float_as_uint(q[3].w) & 0xFFFFu;
+            if (e >= 0.0f && (int)j < R.n_jobs) atomicAdd(&counts[j], 1ull);
+        }
+    }
+}
+
 __global__ void k_bin_swap(Ctl* ctl, int ri) {
     if (ctl->overflow) return;
     RingCtl& r = ctl->ring[ri];
@@ -1813,6 +1830,11 @@ hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, i
     hipLaunchKernelGGL(k_bin_scatter, dim3(blocks), dim3(256), 2 * nk * sizeof(uint32_t), st, ctl, R,
                        ri, nb, lo, inv);
     hipLaunchKernelGGL(k_bin_swap, dim3(1), dim3(1), 0, st, ctl, ri);
+    return hipGetLastError();
+}
+hipError_t launch_count_records(hipStream_t st, int blocks, const Ctl* ctl, const RunDev& R,
+                                unsigned long long* counts) {
+    hipLaunchKernelGGL(k_count_records, dim3(blocks), dim3(256), 0, st, ctl, R, counts);
     return hipGetLastError();
 }
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,

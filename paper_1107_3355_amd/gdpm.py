@@ -72,7 +72,8 @@ class RunStats(C.Structure):
                 ("events", C.c_uint64 * 8), ("passes", C.c_uint32), ("rounds", C.c_uint32),
                 ("passes_photon", C.c_uint32), ("passes_electron", C.c_uint32),
                 ("records_loaded", C.c_uint64 * 2), ("records_stored", C.c_uint64 * 2),
-                ("deposits", C.c_uint64 * 2)]
+                ("deposits", C.c_uint64 * 2), ("accounting_repairs", C.c_uint32),
+                ("accounting_gap", C.c_int64)]
 
 
 class JobDesc(C.Structure):
@@ -229,7 +230,9 @@ def _stats_dict(st):
             "events": {k: int(st.events[i]) for i, k in enumerate(EV_NAMES)},
             "records_loaded": [int(v) for v in st.records_loaded],
             "records_stored": [int(v) for v in st.records_stored],
-            "deposits": [int(v) for v in st.deposits]}
+            "deposits": [int(v) for v in st.deposits],
+            "accounting_repairs": int(st.accounting_repairs),
+            "accounting_gap": int(st.accounting_gap)}
 
 
 class Context:
