@@ -136,26 +136,35 @@ def served_form(G, I, seconds, rate, ct):
                         stat_min_density=0.1)))
     ctx.run(hs[0][1], hs[0][2], n_hist=10_000, want_dose=False)   # tables and queues
     budget = 64 << 30
-    log(f"served form: {len(reqs)} requests")
-    srv = G.Server(ctx, hbm_budget_bytes=budget, max_slots=64)
-    jobs = []
-    t0 = time.perf_counter()
-    for t, p, s, kw in hs:
-        d = t - (time.perf_counter() - t0)
-        if d > 0:
-            time.sleep(d)
-        jobs.append(srv.submit(p, s, want_dose=False, **kw))
-    res = []
-    for k, j in enumerate(jobs):
-        res.append(j.wait())
-        log(f"served form: request {k} done after {res[-1]['t_total_s']:.2f} s")
-    wall = time.perf_counter() - t0
-    info = srv.info()
-    srv.close()
-    lat = [r["t_total_s"] for r in res]
-    hist = sum(r["histories"] for r in res)
-    bal = max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res)
-    repairs = sum(r["accounting_repairs"] for r in res)
+    served = {}
+    hist = 0
+    bal, repairs = 0.0, 0
+    for slots in (1, 2, 64):
+        log(f"served form: {len(reqs)} requests, at most {slots} running together")
+        srv = G.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
+        jobs = []
+        t0 = time.perf_counter()
+        for t, p, s, kw in hs:
+            d = t - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            jobs.append(srv.submit(p, s, want_dose=False, **kw))
+        res = []
+        for k, j in enumerate(jobs):
+            res.append(j.wait())
+            log(f"served form: request {k} done after {res[-1]['t_total_s']:.2f} s")
+        wall = time.perf_counter() - t0
+        info = srv.info()
+        srv.close()
+        lat = [r["t_total_s"] for r in res]
+        hist = sum(r["histories"] for r in res)
+        bal = max(bal, max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res))
+        repairs += sum(r["accounting_repairs"] for r in res)
+        served[f"slots_{slots}"] = {
+            # throughput over the span from the first arrival to the last completion
+            "seconds": wall, "histories_per_s": hist / max(wall - hs[0][0], 1e-9),
+            "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+            "memory_high_water_bytes": info["high_water_bytes"] + info["resident_bytes"]}
     # the same requests, one plain run at a time in arrival order
     run_s, done, lat_seq = [], 0.0, []
     for k, (t, p, s, kw) in enumerate(hs):
@@ -173,11 +182,8 @@ def served_form(G, I, seconds, rate, ct):
     return {"workload": f"Poisson {rate} jobs/s for {seconds} s: {len(reqs)} requests, VMAT-180 on "
                         "256x256x128 CT or IMRT-9 on 128x128x64 CT, to 1% or 2%",
             "histories": hist, "energy_balance_max": bal, "accounting_repairs": repairs,
-            "served": {"seconds": wall, "histories_per_s": hist / wall,
-                       "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
-                       "memory_high_water_bytes": info["high_water_bytes"] + info["resident_bytes"],
-                       "hbm_budget_bytes": budget},
-            "one_at_a_time": {"seconds": max(done, 0.0), "histories_per_s": hist / max(sum(run_s), 1e-9),
+            "hbm_budget_bytes": budget, "served": served,
+            "one_at_a_time": {"seconds": max(done, 0.0), "histories_per_s": hist / max(done - hs[0][0], 1e-9),
                               "latency_s": {"p50": pct(lat_seq, 50), "p99": pct(lat_seq, 99)}}}
 
 
@@ -325,6 +331,7 @@ def main():
         "unc_reached": [r["unc"] for r in runs],
         "energy_balance_max": max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in runs),
         "accounting_repairs": sum(r["accounting_repairs"] for r in runs),
+        "transport_anomalies": sum(r["transport_anomalies"] for r in runs),
         "events_per_history": {k: v / hist for k, v in ev.items() if k != "histories"},
         "kernel_time_s": {"photon": tp, "electron": te},
         "roofline": roof,
@@ -336,7 +343,7 @@ def main():
     if args.serve_seconds > 0:
         log(f"served form: {args.serve_seconds} s of requests at {args.serve_rate}/s")
         out["served_form"] = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom)
-        log("served form: p50/p99 " + str(out["served_form"]["served"]["latency_s"]))
+        log("served form: p50/p99 " + str({k: v["latency_s"] for k, v in out["served_form"]["served"].items()}))
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

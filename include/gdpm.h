@@ -154,6 +154,10 @@ typedef struct {
      * sound run.  A nonzero gap is also visible in the energy balance. */
     uint32_t accounting_repairs;
     int64_t accounting_gap;
+    /* particles ended by a loop bound of the transport kernels (a rejection
+     * sampler fed a non-finite value, or a wavefront past its iteration
+     * bound); 0 in a sound run, events and passes of the whole run */
+    uint64_t transport_anomalies;
 } gdpm_run_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -15,6 +15,10 @@ constexpr int kMaxKeys = 4096;          // re-binning keys (job x energy bin)
 constexpr uint32_t kTailLanes = 32;     // a drained wavefront with fewer particles
                                         // than this hands them to the next pass ...
 constexpr uint32_t kTailMinPerLane = 4; // ... if the pass had this many per lane
+constexpr float kMaxEnergy = 1.0e6f;    // MeV; a larger or non-finite energy marks a
+                                        // damaged record
+constexpr uint32_t kMaxWaveIterations = 1u << 21;  // bound of a wavefront's loop in one
+                                        // pass (about 1e3 in practice)
 
 // event counters (same order as the GDPM_EV_* enumeration of the C ABI)
 enum { EV_FLIGHTS = 0, EV_REAL, EV_ESTEPS, EV_HARD_CAND, EV_HARD, EV_DEPOSITS, EV_PUSHES,
@@ -52,6 +56,7 @@ struct Ctl {
                                        // stored, tally deposits
     double red[4];                    // statistics reductions
     unsigned long long dmax_bits;
+    unsigned long long anomalies;     // particles ended by a loop bound (0 in a sound run)
 };
 
 // Per-job counters and the job segments of the running pass.  The first four

@@ -805,6 +805,7 @@ void fill_stats(const Engine& E, const EJob* j, double t_start, gdpm_run_stats* 
     out->rounds = j->rounds;
     out->accounting_repairs = j->repairs;
     out->accounting_gap = j->death_offset;
+    out->transport_anomalies = hc->anomalies;
     out->t_photon_s = E.tm.photon;
     out->t_electron_s = E.tm.electron;
     out->t_kernel_s = E.tm.photon + E.tm.electron;

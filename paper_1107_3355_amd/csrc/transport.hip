@@ -480,6 +480,7 @@ struct WaveTally {
     uint32_t pushes;      // secondaries written, all jobs
     uint32_t ld, rq;      // records loaded from the queue, records handed on
     uint32_t born, died;  // records created and particles ended, current job
+    uint32_t bad;         // particles ended by the iteration bound of a wavefront
 };
 
 // Hand particles to the next pass of the same type (the record keeps the whole
@@ -675,6 +676,7 @@ GDPM_DEV void pass_finish(LaneTally& t, const WaveTally& c, Ctl* ctl, int ri) {
     ev[ri == 0 ? EV_FLIGHTS : EV_ESTEPS] += c.events;
     ev[EV_PUSHES] += c.pushes;
     if (lane_id() == 0) {
+        if (c.bad) atomicAdd(&ctl->anomalies, (unsigned long long)c.bad);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             if (ev[i]) atomicAdd(&ctl->ev[i], (unsigned long long)ev[i]);
@@ -1018,7 +1020,8 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     PushState pg{0u, 0u}, pe{0u, 0u};
     LaneTally tl;
     tally_init(tl);
-    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u};
+    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    uint32_t iters = 0u;
     bool last_job = false;   // no other job has records left in this pass
     // one job at a time: a wavefront switches jobs with all its lanes empty
     while (j >= 0) {
@@ -1056,6 +1059,13 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             qe.n = 0;
             qg.n = 0;
             int ix = 0, iy = 0, iz = 0;
+            if (active && !(e <= kMaxEnergy)) {
+                // a non-finite energy can only come from a damaged record: end the
+                // particle (counted as an anomaly) rather than feed it to a
+                // rejection sampler that would never accept
+                atomicAdd(&ctl->anomalies, 1ull);
+                active = false;
+            }
             if (active) {
                 if (e < ecut_g) {
                     const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
@@ -1172,6 +1182,16 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             push_charged(qe, pe, head_e, ctl, R, W, jb, bufe, x, y, z, pack_vox(ix, iy, iz), rng, wt);
             push_photons(qg, pg, head_g, ctl, R, W, jb, bufg, x, y, z, rng, wt);
             }
+            if (++iters > kMaxWaveIterations) {
+                // safety net, never reached in a sound run: end the particles
+                // still held (counted as anomalies) so the grid always drains
+                const uint32_t n = (uint32_t)__popcll(ballot(active));
+                wt.died += n;
+                wt.bad += n;
+                active = false;
+                last_job = true;
+                break;
+            }
             if (cs.done) {
                 // this job has nothing left to claim in the pass: move to a job
                 // that has records left, or at the tail of a large pass stop
@@ -1238,7 +1258,8 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     PushState pg{0u, 0u}, pe{0u, 0u};
     LaneTally tl;
     tally_init(tl);
-    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u};
+    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    uint32_t iters = 0u;
     bool last_job = false;   // no other job has records left in this pass
     // one job at a time: a wavefront switches jobs with all its lanes empty
     while (j >= 0) {
@@ -1286,6 +1307,12 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
             PendPhoton qg;
             qe.n = 0;
             qg.n = 0;
+            if (active && !(e <= kMaxEnergy)) {
+                // a non-finite energy can only come from a damaged record (see the
+                // photon pass)
+                atomicAdd(&ctl->anomalies, 1ull);
+                active = false;
+            }
             if (active) {
                 const int vv = ix + W.G.nx * (iy + W.G.ny * iz);
                 if (e <= ecut) {
@@ -1434,6 +1461,16 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
             const uint32_t jb = (uint32_t)W.j | (pb << 16);
             push_charged(qe, pe, head_e, ctl, R, W, jb, bufe, x, y, z, pack_vox(ix, iy, iz), rng, wt);
             push_photons(qg, pg, head_g, ctl, R, W, jb, bufg, x, y, z, rng, wt);
+            }
+            if (++iters > kMaxWaveIterations) {
+                // safety net, never reached in a sound run: end the particles
+                // still held (counted as anomalies) so the grid always drains
+                const uint32_t n = (uint32_t)__popcll(ballot(active));
+                wt.died += n;
+                wt.bad += n;
+                active = false;
+                last_job = true;
+                break;
             }
             if (cs.done) {
                 // this job has nothing left to claim in the pass: move to a job

@@ -73,7 +73,7 @@ class RunStats(C.Structure):
                 ("passes_photon", C.c_uint32), ("passes_electron", C.c_uint32),
                 ("records_loaded", C.c_uint64 * 2), ("records_stored", C.c_uint64 * 2),
                 ("deposits", C.c_uint64 * 2), ("accounting_repairs", C.c_uint32),
-                ("accounting_gap", C.c_int64)]
+                ("accounting_gap", C.c_int64), ("transport_anomalies", C.c_uint64)]
 
 
 class JobDesc(C.Structure):
@@ -232,7 +232,8 @@ def _stats_dict(st):
             "records_stored": [int(v) for v in st.records_stored],
             "deposits": [int(v) for v in st.deposits],
             "accounting_repairs": int(st.accounting_repairs),
-            "accounting_gap": int(st.accounting_gap)}
+            "accounting_gap": int(st.accounting_gap),
+            "transport_anomalies": int(st.transport_anomalies)}
 
 
 class Context:

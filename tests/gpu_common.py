@@ -29,6 +29,7 @@ def oracle_run(materials, ph, src, **kw):
 def balance(r):
     # a sound run never needs its particle accounting repaired
     assert r.get("accounting_repairs", 0) == 0, r.get("accounting_gap")
+    assert r.get("transport_anomalies", 0) == 0
     return abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"]
 
 
