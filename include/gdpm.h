@@ -165,11 +165,14 @@ typedef struct {
 /* Create a context on HIP device `hip_device`.  opts_json may be NULL or a
  * flat JSON object with any of: "ring_capacity_log2" (queue records per type,
  * 2^k, default 25), "waves_per_cu" (wavefronts of the persistent workgroup
- * each CU runs, default 16), "rebin_bins" (energy bins of the queue
- * re-binning, 0 = off, default 16), "lds_tables" (1: stage interpolation tables
- * in LDS when they fit, default; 0: read them through the caches),
- * "pass_histories" (new histories started per scheduler iteration, default 0 =
- * a quarter of the queue capacity less what the fuller queue holds; a larger
+ * each CU runs, 1..12, default 12), "rebin_bins" (energy bins per job of the
+ * queue re-binning, default 16), "rebin_photons", "rebin_electrons" (1:
+ * re-bin the queue of that particle type also when a single job runs;
+ * default 0: a job running alone reads its queues unsorted, which measured
+ * faster), "lds_tables" (1: stage interpolation tables in LDS when they fit,
+ * default; 0: read them through the caches), "pass_histories" (new histories
+ * started per scheduler iteration, default 0 = half the queue capacity less
+ * what the fuller queue holds; a larger
  * value can overflow the queues, which gdpm_run reports as GDPM_E_OVERFLOW).
  * Each wavefront reserves queue slots 256 at a time, so a queue needs well
  * over 256 slots per wavefront of the grid (2^21 and up on a 256-CU device

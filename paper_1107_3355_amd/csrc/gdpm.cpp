@@ -31,7 +31,7 @@
 #include "tables.h"
 
 namespace gdpm {
-hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri);
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri, int rebinned);
 hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, const SrcSeg* segs,
                          int nseg, uint32_t total, int ri);
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri);
@@ -180,6 +180,8 @@ struct gdpm_context_s {
     int pass_histories = 0;      // new histories per iteration (0: half a queue less its fill)
     int autotune = 0;            // tune block size and re-binning online, queues from the work
     int share = 1;               // new histories: 1 evenly over the jobs, 0 oldest job first
+    int rebin_photons = 0;       // 1: re-bin a lone job's photon queue too
+    int rebin_electrons = 0;     // 1: re-bin a lone job's electron queue too
     int max_lds = 0;             // dynamic LDS bytes a workgroup may use
     bool lds_optin = false;
     std::vector<MaterialParams> mats;
@@ -647,10 +649,18 @@ gdpm_status Engine::step() {
     const int nb = std::max(1, std::min(std::min(ctx->rebin_bins, kMaxBins), kMaxKeys / R.n_jobs));
     const float blo = -5.0f, bhi = 5.0f;  // log2 E range of the bins (0.03 .. 32 MeV)
     const float binv = nb / (bhi - blo);
+    int active_jobs = 0;
+    for (int i = 0; i < n_slots; ++i) active_jobs += slots[i] != nullptr;
     for (int ri = 0; ri < 2; ++ri) {
-        // compact the queue and sort it by job and energy
-        HIP_TRY(launch_rebin(st, 4 * blocks, dc, R, ri, nb, blo, binv));
-        HIP_TRY(launch_setup(st, dc, R, ri));
+        // compact the queue and sort it by job and energy so that each job's
+        // records form a segment; a lone job (slot 0) skips it by default
+        // (measured faster: with lanes refilled every iteration energy order
+        // gains nothing, and push order keeps some spatial locality), the pass
+        // then reads the queue as it is, empty slots included
+        const bool rebin = (ri == 0 ? ctx->rebin_photons : ctx->rebin_electrons) || active_jobs != 1 ||
+                           !slots[0];
+        if (rebin) HIP_TRY(launch_rebin(st, 4 * blocks, dc, R, ri, nb, blo, binv));
+        HIP_TRY(launch_setup(st, dc, R, ri, rebin ? 1 : 0));
         HIP_TRY(hipEventRecord(ctx->events[2 * ri], st));
         const int threads = block_threads(ctx);
         const bool lds = ctx->lds_tables && transport_lds_bytes(ri, T, threads / 64) <= (size_t)ctx->max_lds;
@@ -1009,6 +1019,8 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->pass_histories = json_int(opts_json, "pass_histories", 0);
     ctx->autotune = json_int(opts_json, "autotune", 0);
     ctx->share = json_int(opts_json, "share", 1);
+    ctx->rebin_photons = json_int(opts_json, "rebin_photons", 0);
+    ctx->rebin_electrons = json_int(opts_json, "rebin_electrons", 0);
     if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
     if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > kMaxBlockThreads / 64)
         return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);

@@ -824,14 +824,21 @@ GDPM_DEV void push_photons(PendPhoton& q, PushState& ps, uint32_t head, Ctl* ctl
 // pass set-up and completion (one block, between passes): the job segments
 // come from the re-binning that precedes every pass
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri) {
+// rebinned = 0: the queue was not re-binned (one job only): its whole content,
+// empty slots included, is the job's segment
+__global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri, int rebinned) {
     JobCtl* jc = R.jc;
     if (threadIdx.x == 0) {
         RingCtl& r = ctl->ring[ri];
         r.begin = r.head;
         r.count = ctl->overflow ? 0u : r.tail - r.head;
         r.claim = 0u;
+        if (!rebinned) {
+            jc->seg_begin[0] = 0u;
+            jc->seg_count[0] = r.count;
+        }
     }
+    __syncthreads();
     for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) jc->claim[j] = 0u;
     const int nw = (R.n_jobs + 63) >> 6;
     for (int k = threadIdx.x; k < kMaxJobs / 64; k += blockDim.x) {
@@ -1811,8 +1818,8 @@ __global__ void k_test_lookup(Tables T, int which, int m, const float* in, float
 // ---------------------------------------------------------------------------
 // host launchers (the host runtime calls these; kernels stay in this unit)
 // ---------------------------------------------------------------------------
-hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, ctl, R, ri);
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri, int rebinned) {
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, ctl, R, ri, rebinned);
     return hipGetLastError();
 }
 hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, const SrcSeg* segs,

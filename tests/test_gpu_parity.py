@@ -224,8 +224,10 @@ def test_determinism_and_launch_independence(gctx):
     b = gpu_run(gctx, w.phantom, w.source, n_hist=50_000, seed=9)
     assert a["events"] == b["events"]
     np.testing.assert_allclose(a["dose"], b["dose"], rtol=1e-12, atol=1e-300)
-    for opts in ('{"waves_per_cu": 4, "rebin_bins": 0}', '{"waves_per_cu": 8, "rebin_bins": 32}',
-                 '{"ring_capacity_log2": 21, "pass_histories": 700}'):
+    for opts in ('{"waves_per_cu": 4, "rebin_bins": 1, "rebin_photons": 1, "rebin_electrons": 1}',
+                 '{"waves_per_cu": 8, "rebin_bins": 32, "rebin_photons": 1, "rebin_electrons": 1}',
+                 '{"ring_capacity_log2": 21, "pass_histories": 700}',
+                 '{"rebin_photons": 1, "rebin_electrons": 0}'):
         c2 = G.Context(0, opts=opts, materials=MATS)
         try:
             c = gpu_run(c2, w.phantom, w.source, n_hist=50_000, seed=9)
