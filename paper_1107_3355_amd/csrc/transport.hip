@@ -1039,6 +1039,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
         bool active = false;
         float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
         uint32_t pb = 0u;   // batch slot of the lane's history
+        int pm = -1;        // >= 0: a real interaction waits, in a voxel of this material
         Rng rng;
         rng_start(rng, 0u, 0u, 0u, 0u);
         int next = -1;
@@ -1059,7 +1060,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             } else {
             rng_topup(rng, k0, k1);
             const uint64_t act0 = ballot(active);
-            wt.events += (uint32_t)__popcll(ballot(active && !(e < ecut_g)));
+            wt.events += (uint32_t)__popcll(ballot(active && pm < 0 && !(e < ecut_g)));
 
             PendCharged qe;
             PendPhoton qg;
@@ -1072,8 +1073,9 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                 // rejection sampler that would never accept
                 atomicAdd(&ctl->anomalies, 1ull);
                 active = false;
+                pm = -1;
             }
-            if (active) {
+            if (active && pm < 0) {
                 if (e < ecut_g) {
                     const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
                     deposit(tl, W, pb, vv, e);
@@ -1100,81 +1102,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                         const float4 mu = lerp4(ptab + m * T.pg_n, gi, gt);
                         if (uniform(rng, k0, k1) * mumax < rho * mu.w) {
                             tl.ev[EV_REAL]++;
-                            const float r = uniform(rng, k0, k1) * mu.w;
-                            if (r < mu.x) {
-                                float eps, t, turns;
-                                sample_compton(rng, k0, k1, e, eps, t, turns);
-                                const float u0 = u, v0 = v, w0 = w;
-                                rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
-                                // exact split of E into E' and T (the unit is built without
-                                // contraction, so the product is rounded on its own)
-                                const float ec = eps * e;
-                                float e1, te;
-                                if (2.0f * ec >= e) {
-                                    e1 = ec;
-                                    te = e - ec;
-                                } else {
-                                    te = e - ec;
-                                    e1 = e - te;
-                                }
-                                if (kerma || te <= ecut_e) {
-                                    deposit(tl, W, pb, vv, te);
-                                } else {
-                                    // electron along the momentum transfer E d0 - E' d
-                                    float eu = e * u0 - e1 * u, ev = e * v0 - e1 * v, ew = e * w0 - e1 * w;
-                                    const float nn = eu * eu + ev * ev + ew * ew;
-                                    if (nn > 0.0f) {
-                                        const float in = hrsq(nn);
-                                        eu *= in; ev *= in; ew *= in;
-                                    } else {
-                                        eu = u0; ev = v0; ew = w0;
-                                    }
-                                    qe.n = 1; qe.e0 = te; qe.du = eu; qe.dv = ev; qe.dw = ew;
-                                    qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
-                                }
-                                e = e1;
-                            } else if (r < mu.x + mu.y) {
-                                // photoelectric: the electron takes E along the photon
-                                if (kerma || e <= ecut_e) {
-                                    deposit(tl, W, pb, vv, e);
-                                } else {
-                                    qe.n = 1; qe.e0 = e; qe.du = u; qe.dv = v; qe.dw = w;
-                                    qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
-                                }
-                                active = false;
-                            } else {
-                                // pair: uniform split of E - 2 mc^2; the positron keeps a = E - K
-                                const float kk = e - kTwoMec2f, aa = e - kk;
-                                const float tc = uniform(rng, k0, k1) * kk;
-                                float tm, tp;
-                                if (2.0f * tc >= kk) {
-                                    tm = tc;
-                                    tp = kk - tc;
-                                } else {
-                                    tp = kk - tc;
-                                    tm = kk - tp;
-                                }
-                                const bool e_local = kerma || tm <= ecut_e;
-                                const bool p_local = kerma || tp <= ecut_e;
-                                if (p_local) {
-                                    float du, dv, dw;
-                                    sample_iso(rng, k0, k1, du, dv, dw);
-                                    deposit(tl, W, pb, vv, tp);
-                                    qg.n = 2; qg.e = 0.5f * aa; qg.u = du; qg.v = dv; qg.w = dw; qg.wb = 2u;
-                                }
-                                if (e_local) deposit(tl, W, pb, vv, tm);
-                                qe.du = u; qe.dv = v; qe.dw = w;
-                                if (!e_local) {
-                                    qe.n = 1; qe.e0 = tm; qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
-                                    if (!p_local) {
-                                        qe.n = 2; qe.e1 = tp; qe.a1 = aa;
-                                    }
-                                } else if (!p_local) {
-                                    qe.n = 1; qe.e0 = tp; qe.a0 = aa; qe.role = 1u; qe.flag0 = 1u;
-                                }
-                                active = false;
-                            }
-                            tally_flush(tl, W, pb);
+                            pm = m;   // the interaction waits (see below)
                         }
                     }
                 }
@@ -1182,7 +1110,102 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                         history_flush(tl, W, rng.hlo, rng.hhi);
                 }
             }
-            // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
+            // Real interactions are sampled together once kRealBatch lanes have
+            // one (or the wavefront has no other live lane, or the pass has
+            // nothing left to claim): the lanes of a wavefront share their
+            // sampling code instead of a few running it each iteration.  A lane
+            // waits where it is without drawing, so each particle's draws keep
+            // their order; the voxel and the cross sections are recomputed from
+            // the same inputs.
+            {
+                const uint64_t br = ballot(pm >= 0);
+                if (br && (cs.done || (uint32_t)__popcll(br) >= kRealBatch || br == ballot(active))) {
+                    if (pm >= 0) {
+                        const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
+                        int gi;
+                        float gt;
+                        grid(hlog2(e), T.pg_lo, T.pg_inv, T.pg_n, gi, gt);
+                        const float4 mu = lerp4(ptab + pm * T.pg_n, gi, gt);
+                        const float r = uniform(rng, k0, k1) * mu.w;
+                        if (r < mu.x) {
+                            float eps, t, turns;
+                            sample_compton(rng, k0, k1, e, eps, t, turns);
+                            const float u0 = u, v0 = v, w0 = w;
+                            rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
+                            // exact split of E into E' and T (the unit is built without
+                            // contraction, so the product is rounded on its own)
+                            const float ec = eps * e;
+                            float e1, te;
+                            if (2.0f * ec >= e) {
+                                e1 = ec;
+                                te = e - ec;
+                            } else {
+                                te = e - ec;
+                                e1 = e - te;
+                            }
+                            if (kerma || te <= ecut_e) {
+                                deposit(tl, W, pb, vv, te);
+                            } else {
+                                // electron along the momentum transfer E d0 - E' d
+                                float eu = e * u0 - e1 * u, ev = e * v0 - e1 * v, ew = e * w0 - e1 * w;
+                                const float nn = eu * eu + ev * ev + ew * ew;
+                                if (nn > 0.0f) {
+                                    const float in = hrsq(nn);
+                                    eu *= in; ev *= in; ew *= in;
+                                } else {
+                                    eu = u0; ev = v0; ew = w0;
+                                }
+                                qe.n = 1; qe.e0 = te; qe.du = eu; qe.dv = ev; qe.dw = ew;
+                                qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
+                            }
+                            e = e1;
+                        } else if (r < mu.x + mu.y) {
+                            // photoelectric: the electron takes E along the photon
+                            if (kerma || e <= ecut_e) {
+                                deposit(tl, W, pb, vv, e);
+                            } else {
+                                qe.n = 1; qe.e0 = e; qe.du = u; qe.dv = v; qe.dw = w;
+                                qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
+                            }
+                            active = false;
+                        } else {
+                            // pair: uniform split of E - 2 mc^2; the positron keeps a = E - K
+                            const float kk = e - kTwoMec2f, aa = e - kk;
+                            const float tc = uniform(rng, k0, k1) * kk;
+                            float tm, tp;
+                            if (2.0f * tc >= kk) {
+                                tm = tc;
+                                tp = kk - tc;
+                            } else {
+                                tp = kk - tc;
+                                tm = kk - tp;
+                            }
+                            const bool e_local = kerma || tm <= ecut_e;
+                            const bool p_local = kerma || tp <= ecut_e;
+                            if (p_local) {
+                                float du, dv, dw;
+                                sample_iso(rng, k0, k1, du, dv, dw);
+                                deposit(tl, W, pb, vv, tp);
+                                qg.n = 2; qg.e = 0.5f * aa; qg.u = du; qg.v = dv; qg.w = dw; qg.wb = 2u;
+                            }
+                            if (e_local) deposit(tl, W, pb, vv, tm);
+                            qe.du = u; qe.dv = v; qe.dw = w;
+                            if (!e_local) {
+                                qe.n = 1; qe.e0 = tm; qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
+                                if (!p_local) {
+                                    qe.n = 2; qe.e1 = tp; qe.a1 = aa;
+                                }
+                            } else if (!p_local) {
+                                qe.n = 1; qe.e0 = tp; qe.a0 = aa; qe.role = 1u; qe.flag0 = 1u;
+                            }
+                            active = false;
+                        }
+                        tally_flush(tl, W, pb);
+                        if (!active) history_flush(tl, W, rng.hlo, rng.hhi);
+                        pm = -1;
+                    }
+                }
+            }
             // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
             wt.died += (uint32_t)__popcll(act0 & ~ballot(active));
             const uint32_t jb = (uint32_t)W.j | (pb << 16);
@@ -1279,6 +1302,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
         float rho = 1.0f;   // density and material of the current voxel, reloaded
         int mat = 0;        // when the particle enters a voxel
         bool positron = false;
+        float hq = -1.0f;   // >= 0: a hard event waits; the step-start mu_h per g/cm^2
         uint32_t pb = 0u;   // batch slot of the lane's history
         Rng rng;
         rng_start(rng, 0u, 0u, 0u, 0u);
@@ -1308,7 +1332,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
             } else {
             rng_topup(rng, k0, k1);
             const uint64_t act0 = ballot(active);
-            wt.events += (uint32_t)__popcll(ballot(active && !(e <= ecut)));
+            wt.events += (uint32_t)__popcll(ballot(active && hq < 0.0f && !(e <= ecut)));
 
             PendCharged qe;
             PendPhoton qg;
@@ -1319,8 +1343,9 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                 // photon pass)
                 atomicAdd(&ctl->anomalies, 1ull);
                 active = false;
+                hq = -1.0f;
             }
-            if (active) {
+            if (active && hq < 0.0f) {
                 const int vv = ix + W.G.nx * (iy + W.G.ny * iz);
                 if (e <= ecut) {
                     // absorption; a positron annihilates at rest into two photons
@@ -1414,10 +1439,32 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                             mat = (int)vx.y;
                         }
                     } else if (hard) {
-                        // delta scattering against the step-start majorant (mu_h grows with T)
+                        hq = q0.y;   // the hard event waits (see below)
+                    } else {
+                        nh -= mus * s;
+                    }
+                }
+                if (!active) {
+                        tally_flush(tl, W, pb);
+                    history_flush(tl, W, rng.hlo, rng.hhi);
+                }
+            }
+            // Hard events are rare (a few per hundred steps): run as they come,
+            // their sampling would occupy the whole wavefront for one or two
+            // lanes in most iterations.  A lane with one waits, where it is and
+            // without drawing, until kHardBatch lanes wait, the wavefront has no
+            // other live lane, or the pass has nothing left to claim; then they
+            // are sampled together.  Each particle's draws keep their order.
+            {
+                const uint64_t bh = ballot(hq >= 0.0f);
+                if (bh && (cs.done || (uint32_t)__popcll(bh) >= kHardBatch || bh == ballot(active))) {
+                    if (hq >= 0.0f) {
+                        // delta scattering against the step-start majorant
+                        // (mu_h grows with T; the step ended at e)
+                        const int vv = ix + W.G.nx * (iy + W.G.ny * iz);
                         tl.ev[EV_HARD_CAND]++;
-                        const float4 q1 = elec_at(T, etab, m, tend);
-                        if (uniform(rng, k0, k1) * q0.y < q1.y) {
+                        const float4 q1 = elec_at(T, etab, mat, e);
+                        if (uniform(rng, k0, k1) * hq < q1.y) {
                             tl.ev[EV_HARD]++;
                             if (uniform(rng, k0, k1) * q1.y < q1.z) {
                                 float eps, turns;
@@ -1455,13 +1502,8 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                             }
                         }
                         nh = -1.0f;
-                    } else {
-                        nh -= mus * s;
+                        hq = -1.0f;
                     }
-                }
-                if (!active) {
-                        tally_flush(tl, W, pb);
-                    history_flush(tl, W, rng.hlo, rng.hhi);
                 }
             }
             wt.died += (uint32_t)__popcll(act0 & ~ballot(active));
