@@ -158,6 +158,9 @@ typedef struct {
      * sampler fed a non-finite value, or a wavefront past its iteration
      * bound); 0 in a sound run, events and passes of the whole run */
     uint64_t transport_anomalies;
+    /* scheduler iterations launched as a replayed HIP graph, and the graphs
+     * recorded for them (option "graphs"; 0 and 0 when it is off) */
+    uint32_t graph_launches, graphs_recorded;
 } gdpm_run_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -179,7 +182,10 @@ typedef struct {
  * with 16 wavefronts per CU); smaller queues overflow.
  * "share" (how the jobs run together share the new histories of an iteration:
  * 1, default, evenly; 0 in admission order, the oldest job taking what it can
- * use), "autotune" (see gdpm_context_settings).
+ * use), "autotune" (see gdpm_context_settings), "graphs" (1, default: each
+ * scheduler iteration's launches, copies included, are recorded once per
+ * launch configuration as a HIP graph and replayed; 0: launched one by one.
+ * Runs on the legacy default stream always launch one by one).
  * Results do not depend on any of these options (each particle draws from its
  * own random stream), only the speed does. */
 gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out);

@@ -152,6 +152,14 @@ struct SrcSeg {
     uint32_t job, batch;
 };
 
+// the source pass of one particle type in one scheduler iteration: segments
+// and histories; read by the kernels from device memory, so that a recorded
+// launch sequence stays valid while these change
+struct SrcHdr {
+    uint32_t nseg, total;
+    uint32_t pad0, pad1;
+};
+
 struct RunDev {
     float ecut_g, ecut_e;      // shared by every job (the tables depend on them)
     const JobDev* jobs;

@@ -33,7 +33,7 @@
 namespace gdpm {
 hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri, int rebinned);
 hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, const SrcSeg* segs,
-                         int nseg, uint32_t total, int ri);
+                         const SrcHdr* hdr, int ri);
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri);
 size_t transport_lds_bytes(int ri, const Tables& T, int waves);
 hipError_t transport_lds_optin(size_t bytes);
@@ -169,6 +169,25 @@ double now_s() {
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
+// Everything that fixes one scheduler iteration's launch sequence (grids,
+// kernel arguments, copy sizes); equal keys replay the same recorded graph.
+// Compared bytewise: built on a zeroed object.
+struct StepGraphKey {
+    hipStream_t st;
+    int seg_copy[2];     // source segments copied per particle type (0: no source pass)
+    int src_blocks[2];
+    int rebin[2], lds[2];
+    int blocks, threads, nb;
+    float blo, binv;
+    RunDev R;
+    Tables T;
+};
+struct StepGraph {
+    StepGraphKey key;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+
 struct gdpm_context_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -182,6 +201,7 @@ struct gdpm_context_s {
     int share = 1;               // new histories: 1 evenly over the jobs, 0 oldest job first
     int rebin_photons = 0;       // 1: re-bin a lone job's photon queue too
     int rebin_electrons = 0;     // 1: re-bin a lone job's electron queue too
+    int graphs = 1;              // replay each iteration's launches as a recorded HIP graph
     int max_lds = 0;             // dynamic LDS bytes a workgroup may use
     bool lds_optin = false;
     std::vector<MaterialParams> mats;
@@ -193,6 +213,10 @@ struct gdpm_context_s {
     DevBuf jobs_dev, jc, segs, inv_n, counts;
     JobDev* h_jobs = nullptr;  // pinned: job table, source segments, the read-back
     SrcSeg* h_segs = nullptr;  // part of the job counters, statistics reductions
+    DevBuf src_hdr;            // per particle type: segments and histories of the
+    SrcHdr* h_hdr = nullptr;   // iteration's source pass (device, pinned host)
+    std::vector<StepGraph> step_graphs;   // recorded iterations, by launch settings
+    uint64_t graph_clock = 0;
     void* h_jc = nullptr;
     double* h_red = nullptr;
     double resident_bytes = 0.0;   // phantoms and sources alive in the context
@@ -241,6 +265,12 @@ namespace {
 
 constexpr int kMaxBlockThreads = 768;   // launch bound of the transport kernels
 constexpr int kMaxSegs = 4096;          // source segments per iteration (both types)
+constexpr size_t kMaxStepGraphs = 32;   // recorded iterations kept per context
+uint64_t pow2_at_least(uint64_t n, uint64_t lo) {
+    uint64_t p = lo;
+    while (p < n) p <<= 1;
+    return p;
+}
 // the host reads back the first four arrays of JobCtl after every iteration
 struct JobCtlMirror {
     unsigned long long births[kMaxJobs], deaths[kMaxJobs];
@@ -338,6 +368,7 @@ gdpm_status validate_params(const gdpm_run_params* p, const gdpm_source_s* src, 
 struct Timers {
     double photon = 0, electron = 0;
     uint32_t passes = 0, passes_photon = 0, passes_electron = 0;
+    uint32_t graph_launches = 0, graphs_recorded = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -417,6 +448,8 @@ struct Engine {
     gdpm_status init(gdpm_context c, hipStream_t s, const RunPlan& plan);
     gdpm_status admit(EJob* j);
     gdpm_status step();
+    gdpm_status issue(const StepGraphKey& k, bool recording);
+    gdpm_status replay(const StepGraphKey& k);
     gdpm_status settle();       // super-round ends, statistics, finished jobs
     void release(EJob* j);
     bool any_active() const {
@@ -594,7 +627,6 @@ void Engine::release(EJob* j) {
 // one scheduler iteration: new histories, a photon pass, an electron pass
 gdpm_status Engine::step() {
     Ctl* hc = ctx->host_ctl;
-    Ctl* dc = ctx->ctl.as<Ctl>();
     const int blocks = grid_blocks(ctx);
     const uint32_t cap = 1u << ctx->ring_log2;
     // new histories: at most half a queue (or pass_histories) less what the
@@ -638,40 +670,48 @@ gdpm_status Engine::step() {
         }
     }
     R.n_jobs = std::max(n_slots, 1);
-    for (int ri = 0; ri < 2; ++ri) {
-        if (!nseg[ri]) continue;
-        SrcSeg* dseg = ctx->segs.as<SrcSeg>() + ri * seg_cap;
-        HIP_TRY(hipMemcpyAsync(dseg, hs + ri * seg_cap, nseg[ri] * sizeof(SrcSeg), hipMemcpyHostToDevice, st));
-        const int sb = (int)std::min<uint64_t>((total[ri] + 255) / 256, 4u * (uint64_t)blocks);
-        HIP_TRY(launch_source(st, sb, dc, R, dseg, nseg[ri], total[ri], ri));
-    }
+    for (int ri = 0; ri < 2; ++ri) ctx->h_hdr[ri] = SrcHdr{(uint32_t)nseg[ri], total[ri], 0u, 0u};
     // energy bins per job so that jobs x bins fits the re-binning keys
     const int nb = std::max(1, std::min(std::min(ctx->rebin_bins, kMaxBins), kMaxKeys / R.n_jobs));
     const float blo = -5.0f, bhi = 5.0f;  // log2 E range of the bins (0.03 .. 32 MeV)
-    const float binv = nb / (bhi - blo);
     int active_jobs = 0;
     for (int i = 0; i < n_slots; ++i) active_jobs += slots[i] != nullptr;
+    // A graph needs a launch sequence that does not change between iterations:
+    // copy sizes and source grids are rounded up to powers of two (the kernels
+    // read the true counts from the header), so a few recordings serve a run.
+    // The legacy default stream cannot record; runs on it launch directly.
+    const bool graph = ctx->graphs != 0 && st != nullptr;
+    StepGraphKey k;
+    memset(&k, 0, sizeof k);
+    k.st = st;
+    for (int ri = 0; ri < 2; ++ri) {
+        if (!nseg[ri]) continue;
+        const uint64_t need = std::min<uint64_t>((total[ri] + 255) / 256, 4u * (uint64_t)blocks);
+        k.seg_copy[ri] = graph ? (int)std::min<uint64_t>(pow2_at_least(nseg[ri], 8), seg_cap) : nseg[ri];
+        k.src_blocks[ri] = (int)(graph ? std::min<uint64_t>(pow2_at_least(need, 1), 4u * (uint64_t)blocks) : need);
+    }
+    k.blocks = blocks;
+    k.threads = block_threads(ctx);
+    k.nb = nb;
+    k.blo = blo;
+    k.binv = nb / (bhi - blo);
     for (int ri = 0; ri < 2; ++ri) {
         // compact the queue and sort it by job and energy so that each job's
         // records form a segment; a lone job (slot 0) skips it by default
         // (measured faster: with lanes refilled every iteration energy order
         // gains nothing, and push order keeps some spatial locality), the pass
         // then reads the queue as it is, empty slots included
-        const bool rebin = (ri == 0 ? ctx->rebin_photons : ctx->rebin_electrons) || active_jobs != 1 ||
-                           !slots[0];
-        if (rebin) HIP_TRY(launch_rebin(st, 4 * blocks, dc, R, ri, nb, blo, binv));
-        HIP_TRY(launch_setup(st, dc, R, ri, rebin ? 1 : 0));
-        HIP_TRY(hipEventRecord(ctx->events[2 * ri], st));
-        const int threads = block_threads(ctx);
-        const bool lds = ctx->lds_tables && transport_lds_bytes(ri, T, threads / 64) <= (size_t)ctx->max_lds;
-        HIP_TRY(launch_transport(st, ri, blocks, threads, lds, dc, T, R));
-        HIP_TRY(hipEventRecord(ctx->events[2 * ri + 1], st));
-        HIP_TRY(launch_finish(st, dc, ri));
+        k.rebin[ri] = (ri == 0 ? ctx->rebin_photons : ctx->rebin_electrons) || active_jobs != 1 || !slots[0];
+        k.lds[ri] = ctx->lds_tables && transport_lds_bytes(ri, T, k.threads / 64) <= (size_t)ctx->max_lds;
         tm.passes++;
         (ri == 0 ? tm.passes_photon : tm.passes_electron)++;
     }
-    HIP_TRY(hipMemcpyAsync(hc, dc, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(ctx->h_jc, ctx->jc.p, kJcMirrorBytes, hipMemcpyDeviceToHost, st));
+    k.R = R;
+    k.T = T;
+    {
+        const gdpm_status s = graph ? replay(k) : issue(k, false);
+        if (s != GDPM_OK) return s;
+    }
     HIP_TRY(hipStreamSynchronize(st));
     for (int ri = 0; ri < 2; ++ri) {
         float ms = 0.0f;
@@ -683,6 +723,75 @@ gdpm_status Engine::step() {
     if (hc->overflow)
         return fail(GDPM_E_OVERFLOW, "a particle queue filled up (capacity 2^%d); raise ring_capacity_log2",
                     ctx->ring_log2);
+    return GDPM_OK;
+}
+
+// the launch sequence of one iteration: source passes, then for photons and
+// electrons re-binning, set-up, transport (between two timing events) and
+// completion, then the read-back of the counters
+gdpm_status Engine::issue(const StepGraphKey& k, bool recording) {
+    Ctl* dc = ctx->ctl.as<Ctl>();
+    SrcHdr* dh = ctx->src_hdr.as<SrcHdr>();
+    const int seg_cap = kMaxSegs / 2;
+    HIP_TRY(hipMemcpyAsync(dh, ctx->h_hdr, 2 * sizeof(SrcHdr), hipMemcpyHostToDevice, st));
+    for (int ri = 0; ri < 2; ++ri) {
+        if (!k.seg_copy[ri]) continue;
+        SrcSeg* dseg = ctx->segs.as<SrcSeg>() + ri * seg_cap;
+        HIP_TRY(hipMemcpyAsync(dseg, ctx->h_segs + ri * seg_cap, k.seg_copy[ri] * sizeof(SrcSeg),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_source(st, k.src_blocks[ri], dc, k.R, dseg, dh + ri, ri));
+    }
+    for (int ri = 0; ri < 2; ++ri) {
+        if (k.rebin[ri]) HIP_TRY(launch_rebin(st, 4 * k.blocks, dc, k.R, ri, k.nb, k.blo, k.binv));
+        HIP_TRY(launch_setup(st, dc, k.R, ri, k.rebin[ri]));
+        // a recorded event becomes a node of the graph that records it at replay
+        HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri], st, hipEventRecordExternal)
+                          : hipEventRecord(ctx->events[2 * ri], st));
+        HIP_TRY(launch_transport(st, ri, k.blocks, k.threads, k.lds[ri] != 0, dc, k.T, k.R));
+        HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri + 1], st, hipEventRecordExternal)
+                          : hipEventRecord(ctx->events[2 * ri + 1], st));
+        HIP_TRY(launch_finish(st, dc, ri));
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->host_ctl, dc, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ctx->h_jc, ctx->jc.p, kJcMirrorBytes, hipMemcpyDeviceToHost, st));
+    return GDPM_OK;
+}
+
+// launch the iteration as a graph: replay the recording for these settings, or
+// record one (the least recently used of kMaxStepGraphs makes room)
+gdpm_status Engine::replay(const StepGraphKey& k) {
+    auto& cache = ctx->step_graphs;
+    StepGraph* hit = nullptr;
+    for (auto& g : cache)
+        if (memcmp(&g.key, &k, sizeof k) == 0) hit = &g;
+    if (!hit) {
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const gdpm_status s = issue(k, true);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &graph);
+        if (s != GDPM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        if (e != hipSuccess) return fail(GDPM_E_DEVICE, "recording an iteration: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(GDPM_E_DEVICE, "instantiating an iteration: %s", hipGetErrorString(ei));
+        if (cache.size() >= kMaxStepGraphs) {
+            auto old = std::min_element(cache.begin(), cache.end(), [](const StepGraph& a, const StepGraph& b) {
+                return a.last_use < b.last_use;
+            });
+            (void)hipGraphExecDestroy(old->exec);
+            cache.erase(old);
+        }
+        cache.push_back(StepGraph{k, exec, 0});
+        hit = &cache.back();
+        tm.graphs_recorded++;
+    }
+    hit->last_use = ++ctx->graph_clock;
+    HIP_TRY(hipGraphLaunch(hit->exec, st));
+    tm.graph_launches++;
     return GDPM_OK;
 }
 
@@ -816,6 +925,8 @@ void fill_stats(const Engine& E, const EJob* j, double t_start, gdpm_run_stats* 
     out->accounting_repairs = j->repairs;
     out->accounting_gap = j->death_offset;
     out->transport_anomalies = hc->anomalies;
+    out->graph_launches = E.tm.graph_launches;
+    out->graphs_recorded = E.tm.graphs_recorded;
     out->t_photon_s = E.tm.photon;
     out->t_electron_s = E.tm.electron;
     out->t_kernel_s = E.tm.photon + E.tm.electron;
@@ -1021,6 +1132,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->share = json_int(opts_json, "share", 1);
     ctx->rebin_photons = json_int(opts_json, "rebin_photons", 0);
     ctx->rebin_electrons = json_int(opts_json, "rebin_electrons", 0);
+    ctx->graphs = json_int(opts_json, "graphs", 1);
     if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
     if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > kMaxBlockThreads / 64)
         return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);
@@ -1042,6 +1154,10 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     HIP_TRY(ctx->segs.alloc(kMaxSegs * sizeof(SrcSeg)));
     HIP_TRY(hipHostMalloc((void**)&ctx->h_jobs, kMaxJobs * sizeof(JobDev), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void**)&ctx->h_segs, kMaxSegs * sizeof(SrcSeg), hipHostMallocDefault));
+    memset(ctx->h_segs, 0, kMaxSegs * sizeof(SrcSeg));
+    HIP_TRY(ctx->src_hdr.alloc(2 * sizeof(SrcHdr)));
+    HIP_TRY(hipHostMalloc((void**)&ctx->h_hdr, 2 * sizeof(SrcHdr), hipHostMallocDefault));
+    memset(ctx->h_hdr, 0, 2 * sizeof(SrcHdr));
     HIP_TRY(hipHostMalloc(&ctx->h_jc, kJcMirrorBytes, hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void**)&ctx->h_red, 8 * sizeof(double), hipHostMallocDefault));
     *out = ctx.release();
@@ -1052,7 +1168,9 @@ gdpm_status gdpm_context_destroy(gdpm_context ctx) {
     if (!ctx) return fail(GDPM_E_INVALID, "NULL context");
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& g : ctx->step_graphs) (void)hipGraphExecDestroy(g.exec);
     for (auto e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->h_hdr) (void)hipHostFree(ctx->h_hdr);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
     if (ctx->h_jobs) (void)hipHostFree(ctx->h_jobs);
     if (ctx->h_segs) (void)hipHostFree(ctx->h_segs);

@@ -925,10 +925,12 @@ GDPM_DEV double block_sum(double v, double* sh) {
     return s;
 }
 
-__global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg* segs, int nseg,
-                                                uint32_t total, int ri) {
+__global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg* segs,
+                                                const SrcHdr* hdr, int ri) {
     __shared__ double sh[4];
     if (ctl->overflow) return;
+    const int nseg = (int)__builtin_amdgcn_readfirstlane(hdr->nseg);
+    const uint32_t total = __builtin_amdgcn_readfirstlane(hdr->total);
     const RingCtl& r = ctl->ring[ri];
     const uint32_t tail = r.tail;
     if (tail + total - r.head > R.hard[ri]) {
@@ -989,9 +991,9 @@ __global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg
 }
 
 // make the records written by the source pass part of the queue
-__global__ void k_commit(Ctl* ctl, int ri, uint32_t n) {
+__global__ void k_commit(Ctl* ctl, int ri, const SrcHdr* hdr) {
     if (ctl->overflow) return;
-    ctl->ring[ri].tail += n;
+    ctl->ring[ri].tail += hdr->total;
 }
 
 // ---------------------------------------------------------------------------
@@ -1865,9 +1867,9 @@ hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri, int r
     return hipGetLastError();
 }
 hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, const SrcSeg* segs,
-                         int nseg, uint32_t total, int ri) {
-    hipLaunchKernelGGL(k_source, dim3(blocks), dim3(256), 0, st, ctl, R, segs, nseg, total, ri);
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, st, ctl, ri, total);
+                         const SrcHdr* hdr, int ri) {
+    hipLaunchKernelGGL(k_source, dim3(blocks), dim3(256), 0, st, ctl, R, segs, hdr, ri);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, st, ctl, ri, hdr);
     return hipGetLastError();
 }
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri) {

@@ -72,6 +72,28 @@ def test_batch_equals_solo(gctx):
             assert r["rounds"] > 10   # more than one super-round
 
 
+def test_batch_graphs_equal_direct_launches():
+    """The batched form with each iteration replayed from a recorded HIP graph
+    (the default) against direct launches: same doses, same events."""
+    jobs = small_jobs(seed=4103)
+    res = {}
+    for graphs in (0, 1):
+        c2 = G.Context(0, opts=f'{{"graphs": {graphs}}}', materials=MATS)
+        handles = [(c2.phantom(w.phantom), c2.source(w.source), kw) for w, kw in jobs]
+        try:
+            res[graphs] = c2.run_batch(handles)
+        finally:
+            for p, s, _ in handles:
+                p.close()
+                s.close()
+            c2.close()
+    for (w, _), a, b in zip(jobs, res[0], res[1]):
+        assert a["graph_launches"] == 0 and b["graph_launches"] > 0, w.name
+        assert a["events"] == b["events"], w.name
+        same_dose(b["dose"], a["dose"], f"graphs vs direct {w.name}")
+        assert balance(b) < 1e-6
+
+
 def test_batch_more_jobs_than_slots(gctx):
     """300 tiny jobs: admitted 256 at a time, the rest as slots free up."""
     ph = I.homogeneous((6, 6, 6), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)

@@ -237,6 +237,38 @@ def test_determinism_and_launch_independence(gctx):
         np.testing.assert_allclose(c["dose"], a["dose"], rtol=1e-12, atol=1e-300)
 
 
+def test_graph_replay_equals_direct_launches(gctx):
+    """Iterations replayed from recorded HIP graphs (the default) against the
+    same run launched kernel by kernel: many replays of few recordings, with the
+    engine's host work and read-backs between them, and every replay feeding
+    the next one's input; the doses agree to FP64 summation order and the
+    events exactly.  Slab electrons and CT photons, pass_histories small enough
+    for dozens of iterations with source passes of changing size."""
+    slab = I.slab_electron(n=50, d=0.6)
+    ct = I.ct_phantom((48, 48, 24), (1.0, 1.0, 1.25))
+    cases = [("slab50_electron", slab.phantom, slab.source, 20_000, 1),
+             ("ct48_imrt", ct, I.Source(I.PHOTON, I.triangular_spectrum(), I.imrt_plan(ct, nb=10)), 60_000, 7)]
+    for name, ph, src, n, seed in cases:
+        runs = {}
+        for graphs in (0, 1):
+            c2 = G.Context(0, opts=f'{{"graphs": {graphs}, "pass_histories": 1500, "ring_capacity_log2": 21}}',
+                           materials=MATS)
+            try:
+                runs[graphs] = gpu_run(c2, ph, src, n_hist=n, seed=seed)
+            finally:
+                c2.close()
+        a, b = runs[0], runs[1]
+        report(f"graphs/{name}", launches=b["graph_launches"], recorded=b["graphs_recorded"],
+               passes=b["passes"])
+        assert a["graph_launches"] == 0 and a["graphs_recorded"] == 0
+        assert b["graph_launches"] >= 10
+        assert b["graphs_recorded"] <= max(2, b["graph_launches"] // 3)
+        assert a["events"] == b["events"], name
+        np.testing.assert_allclose(b["dose"], a["dose"], rtol=1e-12, atol=1e-300)
+        assert balance(b) < 1e-6
+        assert b["t_photon_s"] > 0 and b["t_electron_s"] > 0   # timing events replayed too
+
+
 # --------------------------------------------------------------------------
 # edge cases and errors
 # --------------------------------------------------------------------------
