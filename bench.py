@@ -41,6 +41,7 @@ BYTES_PER_DEPOSIT = 8
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1107_3355_amd", "csrc", "transport.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_ct256x256x128_imrt9.txt")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_ct256x256x128_imrt9.txt")
 
 
 def log(*a):
@@ -76,14 +77,14 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=float), q)) if len(a) else None
 
 
-def batched_form(G, I, n_jobs):
+def batched_form(G, I, n_jobs, opts=None):
     """Uneven dose jobs (cubes of 48-256 voxels, 1e5-1e7 histories, spectra and
     lines, photons and electrons): all in one batched run against the same jobs
     as sequential single-job runs.  Latency of a job: from the start of the
     whole set to the job's completion."""
     ws = I.batch_jobs(n_jobs)
     log(f"batched form: {n_jobs} jobs generated ({sum(w.n_hist for w in ws):.3g} histories)")
-    ctx = G.Context(0, materials=I.MATERIALS)
+    ctx = G.Context(0, opts=opts, materials=I.MATERIALS)
     hs = [(ctx.phantom(w.phantom), ctx.source(w.source), dict(seed=100 + k, job_id=k, n_hist=w.n_hist))
           for k, w in enumerate(ws)]
     hist = sum(w.n_hist for w in ws)
@@ -96,6 +97,7 @@ def batched_form(G, I, n_jobs):
     lat_b = [r["t_total_s"] for r in res]
     bal = max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res)
     repairs = sum(r["accounting_repairs"] for r in res)
+    log_accounting("batched form", res)
     t0 = time.perf_counter()
     lat_s = []
     for k, (p, s, kw) in enumerate(hs):
@@ -117,7 +119,18 @@ def batched_form(G, I, n_jobs):
             "speedup": ts / tb, "energy_balance_max": bal, "accounting_repairs": repairs}
 
 
-def served_form(G, I, seconds, rate, ct):
+def log_accounting(what, res):
+    """Report jobs whose particle accounting needed a repair or failed a check
+    (their signed energy balance and births - deaths gap)."""
+    for k, r in enumerate(res):
+        if r["accounting_repairs"] or r.get("accounting_mismatches"):
+            log(f"{what}: job {k}: accounting repairs {r['accounting_repairs']}, gap {r['accounting_gap']}, "
+                f"checks failed {r.get('accounting_mismatches', 0)}, "
+                f"balance {(r['e_dep'] + r['e_esc'] - r['e_in']) / r['e_in']:+.3e}, "
+                f"histories {r['histories']}, passes {r['passes']}")
+
+
+def served_form(G, I, seconds, rate, ct, opts=None):
     """Poisson request stream (VMAT arcs on the 256x256x128 CT and IMRT jobs on a
     128x128x64 CT, to 1% or 2%) into a server that admits by device footprint and
     batches the admitted jobs, against the same requests run one at a time in
@@ -125,7 +138,7 @@ def served_form(G, I, seconds, rate, ct):
     times)."""
     import threading
     reqs = I.serving_requests(duration_s=seconds, rate=rate, ct=ct)
-    ctx = G.Context(0, materials=I.MATERIALS)
+    ctx = G.Context(0, opts=opts, materials=I.MATERIALS)
     phs, hs = {}, []
     for k, (t, w) in enumerate(reqs):
         key = id(w.phantom)
@@ -160,6 +173,7 @@ def served_form(G, I, seconds, rate, ct):
         hist = sum(r["histories"] for r in res)
         bal = max(bal, max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res))
         repairs += sum(r["accounting_repairs"] for r in res)
+        log_accounting(f"served form, {slots} slots", res)
         served[f"slots_{slots}"] = {
             # throughput over the span from the first arrival to the last completion
             "seconds": wall, "histories_per_s": hist / max(wall - hs[0][0], 1e-9),
@@ -169,7 +183,9 @@ def served_form(G, I, seconds, rate, ct):
     run_s, done, lat_seq = [], 0.0, []
     for k, (t, p, s, kw) in enumerate(hs):
         a = time.perf_counter()
-        ctx.run(p, s, want_dose=False, **kw)
+        r = ctx.run(p, s, want_dose=False, **kw)
+        log_accounting(f"served form, request {k} alone", [r])
+        repairs += r["accounting_repairs"]
         log(f"served form: request {k} alone in {time.perf_counter() - a:.2f} s")
         run_s.append(time.perf_counter() - a)
         done = max(done, t) + run_s[-1]
@@ -187,21 +203,38 @@ def served_form(G, I, seconds, rate, ct):
                               "latency_s": {"p50": pct(lat_seq, 50), "p99": pct(lat_seq, 99)}}}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed hardware-counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+def profiled_values(path):
+    """The machine-readable lines of a committed counter summary, or None when
     there is none or the kernel source changed since it was taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(path).read()
     except OSError:
         return None
-    kv = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith(" "))
+    kv = {a.strip(): b.strip() for a, b in (line.split(":", 1) for line in text.splitlines()
+                                            if ":" in line and not line.startswith(" "))}
     src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if kv.get("transport_hip_sha256", "").strip() != src:
-        return None
-    v = kv.get(f"{kernel}_hbm_bytes_per_launch")
+    return kv if kv.get("transport_hip_sha256") == src else None
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE scaled by a
+    plain copy), or None."""
+    kv = profiled_values(TRAFFIC_SUMMARY)
+    v = kv.get(f"{kernel}_hbm_bytes_per_launch") if kv else None
     return float(v) if v else None
+
+
+def measured_counters(kernel):
+    """VALU busy and lane use, occupancy, L2 hit rate and atomics per second of
+    `kernel` from the committed counter summary, or None."""
+    kv = profiled_values(COUNTER_SUMMARY)
+    if not kv:
+        return None
+    keys = ("valu_busy_pct", "valu_lane_use_pct", "occupancy_waves_per_cu", "l2_hit_pct", "atomics_per_s")
+    if not all(f"{kernel}_{k}" in kv for k in keys):
+        return None
+    return {k: float(kv[f"{kernel}_{k}"]) for k in keys}
 
 
 def reference_copy(nbytes):
@@ -304,6 +337,7 @@ def main():
     roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
             "traffic": measured_traffic(name),
+            "counters": measured_counters(name),
             "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
             "avg_launch_ms": avg * 1e3, "launches": launches,
             "share_of_kernel_time": t_k / max(te + tp, 1e-30)}
@@ -338,11 +372,11 @@ def main():
     }
     if args.batched_jobs > 0:
         log(f"batched form: {args.batched_jobs} jobs")
-        out["batched_form"] = batched_form(G, I, args.batched_jobs)
+        out["batched_form"] = batched_form(G, I, args.batched_jobs, args.opts)
         log(f"batched form: speed-up {out['batched_form']['speedup']:.2f}x over sequential runs")
     if args.serve_seconds > 0:
         log(f"served form: {args.serve_seconds} s of requests at {args.serve_rate}/s")
-        out["served_form"] = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom)
+        out["served_form"] = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom, args.opts)
         log("served form: p50/p99 " + str({k: v["latency_s"] for k, v in out["served_form"]["served"].items()}))
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")

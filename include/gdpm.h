@@ -161,6 +161,10 @@ typedef struct {
     /* scheduler iterations launched as a replayed HIP graph, and the graphs
      * recorded for them (option "graphs"; 0 and 0 when it is off) */
     uint32_t graph_launches, graphs_recorded;
+    /* option "check_accounting": iterations after which some job's live queue
+     * records differed from its births less its deaths (0 in a sound run, and
+     * always 0 with the option off) */
+    uint32_t accounting_mismatches;
 } gdpm_run_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -185,7 +189,11 @@ typedef struct {
  * use), "autotune" (see gdpm_context_settings), "graphs" (1, default: each
  * scheduler iteration's launches, copies included, are recorded once per
  * launch configuration as a HIP graph and replayed; 0: launched one by one.
- * Runs on the legacy default stream always launch one by one).
+ * Runs on the legacy default stream always launch one by one),
+ * "check_accounting" (1: after every iteration count each job's live queue
+ * records on the device and compare them with its births less its deaths; a
+ * disagreement is printed to stderr and counted in the run statistics; a
+ * diagnostic, default 0).
  * Results do not depend on any of these options (each particle draws from its
  * own random stream), only the speed does. */
 gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out);

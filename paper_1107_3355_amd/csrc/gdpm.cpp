@@ -202,6 +202,7 @@ struct gdpm_context_s {
     int rebin_photons = 0;       // 1: re-bin a lone job's photon queue too
     int rebin_electrons = 0;     // 1: re-bin a lone job's electron queue too
     int graphs = 1;              // replay each iteration's launches as a recorded HIP graph
+    int check_accounting = 0;    // after every iteration, count each job's live records
     int max_lds = 0;             // dynamic LDS bytes a workgroup may use
     bool lds_optin = false;
     std::vector<MaterialParams> mats;
@@ -429,6 +430,9 @@ struct Engine {
     int n_slots = 0;            // slots in use: [0, n_slots)
     Timers tm;
     uint32_t iter = 0, idle = 0;
+    StepGraphKey last{};        // launch settings of the latest iteration
+    uint32_t mismatches = 0;    // iterations whose record count disagreed (check_accounting)
+    gdpm_status check_accounting();
     uint64_t admitted = 0;
     // online autotuning: launch settings change nothing in the results, so
     // candidate (waves per CU, energy bins) pairs are tried on live iterations
@@ -719,10 +723,48 @@ gdpm_status Engine::step() {
         (ri == 0 ? tm.photon : tm.electron) += ms * 1e-3;
     }
     ++iter;
+    last = k;
     tune_account();
+    if (ctx->check_accounting && !hc->overflow) {
+        const gdpm_status s = check_accounting();
+        if (s != GDPM_OK) return s;
+    }
     if (hc->overflow)
         return fail(GDPM_E_OVERFLOW, "a particle queue filled up (capacity 2^%d); raise ring_capacity_log2",
                     ctx->ring_log2);
+    return GDPM_OK;
+}
+
+// Diagnostic (option check_accounting): after an iteration every job's live
+// records in the queues must equal its particle births less its deaths.  A
+// disagreement is printed with the iteration's launch settings and queue state
+// and counted in the run statistics; the run goes on.
+gdpm_status Engine::check_accounting() {
+    HIP_TRY(ctx->counts.ensure(kMaxJobs * sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(ctx->counts.p, 0, kMaxJobs * sizeof(unsigned long long), st));
+    HIP_TRY(launch_count_records(st, 4 * grid_blocks(ctx), ctx->ctl.as<const Ctl>(), R,
+                                 ctx->counts.as<unsigned long long>()));
+    std::vector<unsigned long long> live(kMaxJobs);
+    HIP_TRY(hipMemcpyAsync(live.data(), ctx->counts.p, kMaxJobs * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const JobCtlMirror* m = reinterpret_cast<const JobCtlMirror*>(ctx->h_jc);
+    const Ctl* hc = ctx->host_ctl;
+    for (int i = 0; i < n_slots; ++i) {
+        const EJob* j = slots[i];
+        if (!j || j->done) continue;
+        const long long expect = (long long)m->births[i] - (long long)m->deaths[i] - j->death_offset;
+        if (expect == (long long)live[i]) continue;
+        ++mismatches;
+        fprintf(stderr,
+                "[gdpm] accounting check: iteration %u, slot %d (job %u): births %llu deaths %llu "
+                "(offset %lld) but %llu live records; slots %d, source segments %d/%d, re-binned %d/%d, "
+                "queues [%u, %u) [%u, %u) cur %u/%u, graph %d\n",
+                iter, i, j->prm.job_id, (unsigned long long)m->births[i], (unsigned long long)m->deaths[i],
+                (long long)j->death_offset, live[i], n_slots, last.seg_copy[0], last.seg_copy[1],
+                last.rebin[0], last.rebin[1], hc->ring[0].head, hc->ring[0].tail, hc->ring[1].head,
+                hc->ring[1].tail, hc->ring[0].cur, hc->ring[1].cur, ctx->graphs);
+    }
     return GDPM_OK;
 }
 
@@ -927,6 +969,7 @@ void fill_stats(const Engine& E, const EJob* j, double t_start, gdpm_run_stats* 
     out->transport_anomalies = hc->anomalies;
     out->graph_launches = E.tm.graph_launches;
     out->graphs_recorded = E.tm.graphs_recorded;
+    out->accounting_mismatches = E.mismatches;
     out->t_photon_s = E.tm.photon;
     out->t_electron_s = E.tm.electron;
     out->t_kernel_s = E.tm.photon + E.tm.electron;
@@ -1133,6 +1176,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->rebin_photons = json_int(opts_json, "rebin_photons", 0);
     ctx->rebin_electrons = json_int(opts_json, "rebin_electrons", 0);
     ctx->graphs = json_int(opts_json, "graphs", 1);
+    ctx->check_accounting = json_int(opts_json, "check_accounting", 0);
     if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
     if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > kMaxBlockThreads / 64)
         return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);

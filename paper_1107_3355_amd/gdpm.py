@@ -74,7 +74,8 @@ class RunStats(C.Structure):
                 ("records_loaded", C.c_uint64 * 2), ("records_stored", C.c_uint64 * 2),
                 ("deposits", C.c_uint64 * 2), ("accounting_repairs", C.c_uint32),
                 ("accounting_gap", C.c_int64), ("transport_anomalies", C.c_uint64),
-                ("graph_launches", C.c_uint32), ("graphs_recorded", C.c_uint32)]
+                ("graph_launches", C.c_uint32), ("graphs_recorded", C.c_uint32),
+                ("accounting_mismatches", C.c_uint32)]
 
 
 class JobDesc(C.Structure):
@@ -235,7 +236,8 @@ def _stats_dict(st):
             "accounting_repairs": int(st.accounting_repairs),
             "accounting_gap": int(st.accounting_gap),
             "transport_anomalies": int(st.transport_anomalies),
-            "graph_launches": int(st.graph_launches), "graphs_recorded": int(st.graphs_recorded)}
+            "graph_launches": int(st.graph_launches), "graphs_recorded": int(st.graphs_recorded),
+            "accounting_mismatches": int(st.accounting_mismatches)}
 
 
 class Context:
