@@ -154,9 +154,10 @@ typedef struct {
      * sound run.  A nonzero gap is also visible in the energy balance. */
     uint32_t accounting_repairs;
     int64_t accounting_gap;
-    /* particles ended by a loop bound of the transport kernels (a rejection
-     * sampler fed a non-finite value, or a wavefront past its iteration
-     * bound); 0 in a sound run, events and passes of the whole run */
+    /* particles ended by a safety net of the transport kernels (a non-finite
+     * or absurd energy, a wavefront past its iteration bound) and queue
+     * records dropped because they belong to no running job; 0 in a sound
+     * run; counted over the whole run, like events and passes */
     uint64_t transport_anomalies;
     /* scheduler iterations launched as a replayed HIP graph, and the graphs
      * recorded for them (option "graphs"; 0 and 0 when it is off) */

@@ -23,6 +23,7 @@ constexpr uint32_t kHardBatch = GDPM_HARD_BATCH;  // electron hard events sample
 #define GDPM_REAL_BATCH 24
 #endif
 constexpr uint32_t kRealBatch = GDPM_REAL_BATCH;  // photon interactions sampled together
+constexpr uint32_t kRefillMin = 8;      // empty lanes a wavefront refills at once
 constexpr float kMaxEnergy = 1.0e6f;    // MeV; a larger or non-finite energy marks a
                                         // damaged record
 constexpr uint32_t kMaxWaveIterations = 1u << 21;  // bound of a wavefront's loop in one

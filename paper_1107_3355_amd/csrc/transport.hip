@@ -888,12 +888,15 @@ GDPM_DEV void claim_refill(ClaimState& cs, JobCtl* jc, const WJob& W, const Ctl*
 }
 
 // refill the lanes without a particle from the wave's claimed items; returns
-// true in the lanes that loaded a record
+// true in the lanes that loaded a record.  Lanes wait until kRefillMin of them
+// are empty (or no lane is busy): a refill stalls the wavefront on record
+// loads, so it pays to do it for several lanes at once.
 GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uint32_t begin,
-                     const Ctl* ctl, const Particle* buf, uint32_t mask, Particle& p, WaveTally& c) {
+                     Ctl* ctl, const Particle* buf, uint32_t mask, Particle& p, WaveTally& c) {
     if (cs.done) return false;
     const uint64_t need = ballot(!active);
     if (!need) return false;
+    if ((uint32_t)__popcll(need) < kRefillMin && ballot(active)) return false;
     claim_refill(cs, jc, W, ctl);
     const uint32_t have = cs.end - cs.next;
     const uint32_t rank = mbcnt(need);
@@ -902,6 +905,12 @@ GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uin
     if (!active && rank < take) {
         p = load(buf, mask, begin + W.seg_begin + cs.next + rank);
         got = p.e >= 0.0f;
+        if (got && (p.job & 0xFFFFu) != (uint32_t)W.j) {
+            // a record of another job in this job's segment: only a broken
+            // bookkeeping puts it there; it is dropped and counted
+            atomicAdd(&ctl->anomalies, 1ull);
+            got = false;
+        }
     }
     cs.next += take;
     c.ld += take;
@@ -1588,7 +1597,7 @@ __global__ void __launch_bounds__(256) k_bin_count(Ctl* ctl, RunDev R, int ri, i
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float e;
         const int k = record_key(buf, R.mask[ri], r.head + i, nb, lo, inv, e);
-        if (e >= 0.0f) atomicAdd(&hist[k], 1u);
+        if (e >= 0.0f && k < nk) atomicAdd(&hist[k], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nk; i += blockDim.x)
@@ -1651,9 +1660,13 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri,
         uint32_t rank = 0u;
         if (i < n) {
             p = load(src, R.mask[ri], r.head + i);
-            if (p.e >= 0.0f) {
+            if (p.e >= 0.0f && (int)(p.job & 0xFFFFu) < R.n_jobs) {
                 k = (int)(p.job & 0xFFFFu) * nb + energy_bin(p.e, lo, inv, nb);
                 rank = atomicAdd(&cnt[k], 1u);
+            } else if (p.e >= 0.0f) {
+                // a record of a job no longer running: only a broken bookkeeping
+                // leaves one; it is dropped (the count pass skipped it) and counted
+                atomicAdd(&ctl->anomalies, 1ull);
             }
         }
         __syncthreads();

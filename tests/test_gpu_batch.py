@@ -94,6 +94,27 @@ def test_batch_graphs_equal_direct_launches():
         assert balance(b) < 1e-6
 
 
+def test_accounting_check_finds_nothing():
+    """The diagnostic accounting check (every iteration: live queue records of
+    each job against its births less deaths) on the batched form, several jobs
+    sharing the queues with re-binning, and on a multi-round target job."""
+    jobs = small_jobs(seed=4107)
+    c2 = G.Context(0, opts='{"check_accounting": 1, "pass_histories": 3000, "ring_capacity_log2": 21}',
+                   materials=MATS)
+    handles = [(c2.phantom(w.phantom), c2.source(w.source), kw) for w, kw in jobs]
+    try:
+        res = c2.run_batch(handles)
+    finally:
+        for p, s, _ in handles:
+            p.close()
+            s.close()
+        c2.close()
+    for (w, _), r in zip(jobs, res):
+        report(f"accounting check {w.name}", mismatches=r["accounting_mismatches"], passes=r["passes"])
+        assert r["accounting_mismatches"] == 0, w.name
+        assert balance(r) < 1e-6
+
+
 def test_batch_more_jobs_than_slots(gctx):
     """300 tiny jobs: admitted 256 at a time, the rest as slots free up."""
     ph = I.homogeneous((6, 6, 6), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
