@@ -189,8 +189,8 @@ typedef struct {
  * 1, default, evenly; 0 in admission order, the oldest job taking what it can
  * use), "autotune" (see gdpm_context_settings), "graphs" (1, default: each
  * scheduler iteration's launches, copies included, are recorded once per
- * launch configuration as a HIP graph and replayed; 0: launched one by one.
- * Runs on the legacy default stream always launch one by one),
+ * launch configuration as a HIP graph and replayed, on the stream of the run;
+ * 0: launched one by one),
  * "check_accounting" (1: after every iteration count each job's live queue
  * records on the device and compare them with its births less its deaths; a
  * disagreement is printed to stderr and counted in the run statistics; a

@@ -683,7 +683,8 @@ gdpm_status Engine::step() {
     // A graph needs a launch sequence that does not change between iterations:
     // copy sizes and source grids are rounded up to powers of two (the kernels
     // read the true counts from the header), so a few recordings serve a run.
-    // The legacy default stream cannot record; runs on it launch directly.
+    // (A null stream cannot record; it never reaches here, a run without a
+    // stream of its own uses the context's.)
     const bool graph = ctx->graphs != 0 && st != nullptr;
     StepGraphKey k;
     memset(&k, 0, sizeof k);

@@ -368,18 +368,40 @@ def test_target_uncertainty_mode(gctx):
 
 
 def test_run_async_device_outputs(gctx):
-    torch = pytest.importorskip("torch")
-    if not torch.cuda.is_available():
-        pytest.skip("torch has no GPU here")
+    """gdpm_run_async into device buffers (allocated through the HIP runtime),
+    on the context's stream (stream NULL) and on a stream of the caller, each
+    iteration replayed as a graph: the same dose and standard error as the
+    blocking gdpm_run with host outputs."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
     w = I.water_cube_2mev()
     nv = w.phantom.nvox
-    d = torch.zeros(nv, dtype=torch.float64, device="cuda")
-    s = torch.zeros(nv, dtype=torch.float64, device="cuda")
+    nbytes = C.c_size_t(nv * 8)
     p, src = gctx.phantom(w.phantom), gctx.source(w.source)
-    st = gctx.run_async(p, src, d.data_ptr(), s.data_ptr(), n_hist=20_000, seed=6)
     ref = gctx.run(p, src, n_hist=20_000, seed=6)
-    p.close()
-    src.close()
-    torch.cuda.synchronize()
-    np.testing.assert_allclose(d.cpu().numpy(), ref["dose"], rtol=1e-12, atol=1e-300)
-    assert st["histories"] == 20_000
+    stream = C.c_void_p()
+    assert hip.hipStreamCreate(C.byref(stream)) == 0
+    bufs = [C.c_void_p(), C.c_void_p()]
+    try:
+        for b in bufs:
+            assert hip.hipMalloc(C.byref(b), nbytes) == 0
+        for st_handle in (0, stream.value):
+            for b in bufs:
+                assert hip.hipMemset(b, 0, nbytes) == 0
+            st = gctx.run_async(p, src, bufs[0].value, bufs[1].value, stream=st_handle or 0,
+                                n_hist=20_000, seed=6)
+            assert hip.hipDeviceSynchronize() == 0
+            out = [np.empty(nv), np.empty(nv)]
+            for o, b in zip(out, bufs):
+                assert hip.hipMemcpy(o.ctypes.data_as(C.c_void_p), b, nbytes, 2) == 0   # device to host
+            np.testing.assert_allclose(out[0], ref["dose"], rtol=1e-12, atol=1e-300)
+            np.testing.assert_allclose(out[1], ref["sigma"], rtol=1e-12, atol=1e-300)
+            assert st["histories"] == 20_000
+            assert st["graph_launches"] > 0
+    finally:
+        for b in bufs:
+            if b.value:
+                hip.hipFree(b)
+        hip.hipStreamDestroy(stream)
+        p.close()
+        src.close()
