@@ -187,10 +187,11 @@ typedef struct {
  * with 16 wavefronts per CU); smaller queues overflow.
  * "share" (how the jobs run together share the new histories of an iteration:
  * 1, default, evenly; 0 in admission order, the oldest job taking what it can
- * use), "autotune" (see gdpm_context_settings), "graphs" (1, default: each
- * scheduler iteration's launches, copies included, are recorded once per
- * launch configuration as a HIP graph and replayed, on the stream of the run;
- * 0: launched one by one),
+ * use), "autotune" (see gdpm_context_settings), "graphs" (1, default: a
+ * scheduler iteration's launches, copies included, are recorded as a HIP
+ * graph the second time their launch configuration occurs in a run, and
+ * replayed from then on, on the stream of the run; each run, batch or server
+ * keeps its own recordings; 0: launched one by one),
  * "check_accounting" (1: after every iteration count each job's live queue
  * records on the device and compare them with its births less its deaths; a
  * disagreement is printed to stderr and counted in the run statistics; a

@@ -184,7 +184,7 @@ struct StepGraphKey {
 };
 struct StepGraph {
     StepGraphKey key;
-    hipGraphExec_t exec;
+    hipGraphExec_t exec;   // null: seen once, not recorded yet
     uint64_t last_use;
 };
 
@@ -216,8 +216,6 @@ struct gdpm_context_s {
     SrcSeg* h_segs = nullptr;  // part of the job counters, statistics reductions
     DevBuf src_hdr;            // per particle type: segments and histories of the
     SrcHdr* h_hdr = nullptr;   // iteration's source pass (device, pinned host)
-    std::vector<StepGraph> step_graphs;   // recorded iterations, by launch settings
-    uint64_t graph_clock = 0;
     void* h_jc = nullptr;
     double* h_red = nullptr;
     double resident_bytes = 0.0;   // phantoms and sources alive in the context
@@ -266,7 +264,7 @@ namespace {
 
 constexpr int kMaxBlockThreads = 768;   // launch bound of the transport kernels
 constexpr int kMaxSegs = 4096;          // source segments per iteration (both types)
-constexpr size_t kMaxStepGraphs = 32;   // recorded iterations kept per context
+constexpr size_t kMaxStepGraphs = 32;   // launch settings an engine remembers
 uint64_t pow2_at_least(uint64_t n, uint64_t lo) {
     uint64_t p = lo;
     while (p < n) p <<= 1;
@@ -431,6 +429,19 @@ struct Engine {
     Timers tm;
     uint32_t iter = 0, idle = 0;
     StepGraphKey last{};        // launch settings of the latest iteration
+    // recorded iterations, by launch settings; an engine records and replays
+    // them on the one thread that drives it, and they end with it
+    std::vector<StepGraph> graphs;
+    uint64_t graph_clock = 0;
+    Engine() = default;
+    Engine(const Engine&) = delete;
+    Engine& operator=(const Engine&) = delete;
+    ~Engine() { drop_graphs(); }
+    void drop_graphs() {
+        for (auto& g : graphs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
     uint32_t mismatches = 0;    // iterations whose record count disagreed (check_accounting)
     gdpm_status check_accounting();
     uint64_t admitted = 0;
@@ -502,6 +513,7 @@ void Engine::tune_account() {
 }
 
 gdpm_status Engine::init(gdpm_context c, hipStream_t s, const RunPlan& plan) {
+    drop_graphs();
     ctx = c;
     st = s;
     slots.assign(kMaxJobs, nullptr);
@@ -800,14 +812,25 @@ gdpm_status Engine::issue(const StepGraphKey& k, bool recording) {
     return GDPM_OK;
 }
 
-// launch the iteration as a graph: replay the recording for these settings, or
-// record one (the least recently used of kMaxStepGraphs makes room)
+// launch the iteration as a graph: settings seen for the first time launch
+// directly, the second time they are recorded, from then on replayed (the
+// least recently used of kMaxStepGraphs settings makes room for a new one)
 gdpm_status Engine::replay(const StepGraphKey& k) {
-    auto& cache = ctx->step_graphs;
     StepGraph* hit = nullptr;
-    for (auto& g : cache)
+    for (auto& g : graphs)
         if (memcmp(&g.key, &k, sizeof k) == 0) hit = &g;
     if (!hit) {
+        if (graphs.size() >= kMaxStepGraphs) {
+            auto old = std::min_element(graphs.begin(), graphs.end(), [](const StepGraph& a, const StepGraph& b) {
+                return a.last_use < b.last_use;
+            });
+            if (old->exec) (void)hipGraphExecDestroy(old->exec);
+            graphs.erase(old);
+        }
+        graphs.push_back(StepGraph{k, nullptr, ++graph_clock});
+        return issue(k, false);
+    }
+    if (!hit->exec) {
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         const gdpm_status s = issue(k, true);
         hipGraph_t graph = nullptr;
@@ -821,18 +844,10 @@ gdpm_status Engine::replay(const StepGraphKey& k) {
         const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (ei != hipSuccess) return fail(GDPM_E_DEVICE, "instantiating an iteration: %s", hipGetErrorString(ei));
-        if (cache.size() >= kMaxStepGraphs) {
-            auto old = std::min_element(cache.begin(), cache.end(), [](const StepGraph& a, const StepGraph& b) {
-                return a.last_use < b.last_use;
-            });
-            (void)hipGraphExecDestroy(old->exec);
-            cache.erase(old);
-        }
-        cache.push_back(StepGraph{k, exec, 0});
-        hit = &cache.back();
+        hit->exec = exec;
         tm.graphs_recorded++;
     }
-    hit->last_use = ++ctx->graph_clock;
+    hit->last_use = ++graph_clock;
     HIP_TRY(hipGraphLaunch(hit->exec, st));
     tm.graph_launches++;
     return GDPM_OK;
@@ -1213,7 +1228,6 @@ gdpm_status gdpm_context_destroy(gdpm_context ctx) {
     if (!ctx) return fail(GDPM_E_INVALID, "NULL context");
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    for (auto& g : ctx->step_graphs) (void)hipGraphExecDestroy(g.exec);
     for (auto e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->h_hdr) (void)hipHostFree(ctx->h_hdr);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
