@@ -1643,38 +1643,43 @@ __global__ void __launch_bounds__(1024) k_bin_scan(Ctl* ctl, RunDev R, int nb) {
 __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri, int nb, float lo,
                                                      float inv) {
     if (ctl->overflow) return;
-    extern __shared__ uint32_t cnt[];   // [nk] tile counts, then [nk] tile bases
+    extern __shared__ uint32_t cnt[];   // [nk] this block's counts, then ranks; [nk] its bases
     const int nk = R.n_jobs * nb;
     uint32_t* base = cnt + nk;
     const RingCtl& r = ctl->ring[ri];
     const uint32_t n = r.tail - r.head;
     const Particle* src = R.buf[ri][r.cur];
     Particle* dst = R.buf[ri][r.cur ^ 1u];
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
-        for (int i = threadIdx.x; i < nk; i += blockDim.x) cnt[i] = 0u;
-        __syncthreads();
-        const uint32_t i = i0 + threadIdx.x;
-        Particle p;
-        int k = -1;
-        uint32_t rank = 0u;
-        if (i < n) {
-            p = load(src, R.mask[ri], r.head + i);
-            if (p.e >= 0.0f && (int)(p.job & 0xFFFFu) < R.n_jobs) {
-                k = (int)(p.job & 0xFFFFu) * nb + energy_bin(p.e, lo, inv, nb);
-                rank = atomicAdd(&cnt[k], 1u);
-            } else if (p.e >= 0.0f) {
-                // a record of a job no longer running: only a broken bookkeeping
-                // leaves one; it is dropped (the count pass skipped it) and counted
-                atomicAdd(&ctl->anomalies, 1ull);
-            }
+    // each block moves one contiguous share of the queue: it counts its keys,
+    // takes its place in every key's run with one atomic per key, then moves
+    // its records (one global atomic per key and block, not per tile)
+    const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t i0 = min(n, blockIdx.x * per), i1 = min(n, i0 + per);
+    for (int q = threadIdx.x; q < nk; q += blockDim.x) cnt[q] = 0u;
+    __syncthreads();
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        float e;
+        const int k = record_key(src, R.mask[ri], r.head + i, nb, lo, inv, e);
+        if (e >= 0.0f && k < nk) atomicAdd(&cnt[k], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nk; q += blockDim.x) {
+        base[q] = cnt[q] ? atomicAdd(&R.jc->bin_cursor[q], cnt[q]) : 0u;
+        cnt[q] = 0u;
+    }
+    __syncthreads();
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const Particle p = load(src, R.mask[ri], r.head + i);
+        if (!(p.e >= 0.0f)) continue;
+        const int job = (int)(p.job & 0xFFFFu);
+        if (job < R.n_jobs) {
+            const int k = job * nb + energy_bin(p.e, lo, inv, nb);
+            store(dst, R.mask[ri], base[k] + atomicAdd(&cnt[k], 1u), p);
+        } else {
+            // a record of a job no longer running: only a broken bookkeeping
+            // leaves one; it is dropped (the count pass skipped it) and counted
+            atomicAdd(&ctl->anomalies, 1ull);
         }
-        __syncthreads();
-        for (int q = threadIdx.x; q < nk; q += blockDim.x)
-            base[q] = cnt[q] ? atomicAdd(&R.jc->bin_cursor[q], cnt[q]) : 0u;
-        __syncthreads();
-        if (k >= 0) store(dst, R.mask[ri], base[k] + rank, p);
-        __syncthreads();
     }
 }
 
