@@ -120,12 +120,12 @@ def batched_form(G, I, n_jobs, opts=None):
 
 
 def log_accounting(what, res):
-    """Report jobs whose particle accounting needed a repair or failed a check
+    """Report jobs whose particle accounting needed a repair, failed a check or met an anomaly
     (their signed energy balance and births - deaths gap)."""
     for k, r in enumerate(res):
-        if r["accounting_repairs"] or r.get("accounting_mismatches"):
+        if r["accounting_repairs"] or r.get("accounting_mismatches") or r.get("transport_anomalies"):
             log(f"{what}: job {k}: accounting repairs {r['accounting_repairs']}, gap {r['accounting_gap']}, "
-                f"checks failed {r.get('accounting_mismatches', 0)}, "
+                f"checks failed {r.get('accounting_mismatches', 0)}, anomalies {r.get('transport_anomalies', 0)}, "
                 f"balance {(r['e_dep'] + r['e_esc'] - r['e_in']) / r['e_in']:+.3e}, "
                 f"histories {r['histories']}, passes {r['passes']}")
 

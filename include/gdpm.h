@@ -174,9 +174,10 @@ typedef struct {
  * flat JSON object with any of: "ring_capacity_log2" (queue records per type,
  * 2^k, default 25), "waves_per_cu" (wavefronts of the persistent workgroup
  * each CU runs, 1..12, default 12), "rebin_bins" (energy bins per job of the
- * queue re-binning, default 16), "rebin_photons", "rebin_electrons" (1:
- * re-bin the queue of that particle type also when a single job runs;
- * default 0: a job running alone reads its queues unsorted, which measured
+ * queue re-binning, default 1: records are grouped by job only, which measured
+ * faster than energy order), "rebin_photons", "rebin_electrons" (1: re-bin
+ * the queue of that particle type also when a single job holds all the
+ * particles; default 0: then the queues are read unsorted, which measured
  * faster), "lds_tables" (1: stage interpolation tables in LDS when they fit,
  * default; 0: read them through the caches), "pass_histories" (new histories
  * started per scheduler iteration, default 0 = half the queue capacity less
@@ -195,7 +196,9 @@ typedef struct {
  * "check_accounting" (1: after every iteration count each job's live queue
  * records on the device and compare them with its births less its deaths; a
  * disagreement is printed to stderr and counted in the run statistics; a
- * diagnostic, default 0).
+ * diagnostic, default 0), "ring_start" (queue position, 0 <= p < 2^32, at
+ * which runs start; positions advance with every record and wrap modulo
+ * 2^32, which a value near 2^32 brings forward; default 0).
  * Results do not depend on any of these options (each particle draws from its
  * own random stream), only the speed does. */
 gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out);

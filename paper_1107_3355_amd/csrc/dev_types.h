@@ -42,7 +42,7 @@ struct alignas(16) Particle {
     uint32_t vox;            // charged particles: ix | iy << 11 | iz << 22
     float a;                 // positron: energy of its two annihilation photons together
     uint32_t flags;          // bit 0: positron
-    uint32_t job;            // bits 0-15: job slot; bits 16-31: batch slot of the history
+    uint32_t job;            // bits 0-7: job slot; 8-15: the slot's generation; 16-31: batch slot
 };
 static_assert(sizeof(Particle) == 64, "particle record is 64 bytes");
 
@@ -142,7 +142,8 @@ struct JobDev {
     unsigned long long hist0;  // history id of hist[0]
     uint32_t k0, k1;           // Philox key
     uint32_t flags;            // GDPM_* run flags
-    uint32_t pad;
+    uint32_t gen;              // generation of the slot (8 bits): records of an earlier
+                               // job in the same slot carry another one
 };
 
 // A run of new histories for the source pass: ids [h0, h0 + n) of job `job`,

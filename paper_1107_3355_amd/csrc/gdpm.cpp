@@ -16,6 +16,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -31,7 +32,7 @@
 #include "tables.h"
 
 namespace gdpm {
-hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri, int rebinned);
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri, int rebinned, int lone);
 hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, const SrcSeg* segs,
                          const SrcHdr* hdr, int ri);
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri);
@@ -160,6 +161,16 @@ int json_int(const char* js, const char* key, int dflt) {
     return atoi(p + 1);
 }
 
+unsigned long long json_u64(const char* js, const char* key, unsigned long long dflt) {
+    if (!js) return dflt;
+    std::string k = std::string("\"") + key + "\"";
+    const char* p = strstr(js, k.c_str());
+    if (!p) return dflt;
+    p = strchr(p + k.size(), ':');
+    if (!p) return dflt;
+    return strtoull(p + 1, nullptr, 10);
+}
+
 double now_s() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -177,6 +188,7 @@ struct StepGraphKey {
     int seg_copy[2];     // source segments copied per particle type (0: no source pass)
     int src_blocks[2];
     int rebin[2], lds[2];
+    int lone;            // the one job holding particles (queues not re-binned), or -1
     int blocks, threads, nb;
     float blo, binv;
     RunDev R;
@@ -194,7 +206,7 @@ struct gdpm_context_s {
     int cu_count = 0;
     int ring_log2 = 25;
     int waves_per_cu = 12;
-    int rebin_bins = 16;
+    int rebin_bins = 1;          // energy bins per job of the re-binning (1: by job only)
     int lds_tables = 1;          // stage interpolation tables in LDS when they fit
     int pass_histories = 0;      // new histories per iteration (0: half a queue less its fill)
     int autotune = 0;            // tune block size and re-binning online, queues from the work
@@ -203,6 +215,7 @@ struct gdpm_context_s {
     int rebin_electrons = 0;     // 1: re-bin a lone job's electron queue too
     int graphs = 1;              // replay each iteration's launches as a recorded HIP graph
     int check_accounting = 0;    // after every iteration, count each job's live records
+    uint32_t ring_start = 0;     // queue position a run starts at (positions run modulo 2^32)
     int max_lds = 0;             // dynamic LDS bytes a workgroup may use
     bool lds_optin = false;
     std::vector<MaterialParams> mats;
@@ -426,6 +439,7 @@ struct Engine {
     Tables T{};
     std::vector<EJob*> slots;
     int n_slots = 0;            // slots in use: [0, n_slots)
+    std::vector<uint32_t> slot_gen = std::vector<uint32_t>(kMaxJobs, 0u);   // 8-bit generations
     Timers tm;
     uint32_t iter = 0, idle = 0;
     StepGraphKey last{};        // launch settings of the latest iteration
@@ -479,7 +493,7 @@ void Engine::tune_begin() {
     tune.on = ctx->autotune != 0;
     if (!tune.on) return;
     for (int w : {8, 12})
-        for (int b : {4, 16}) tune.cand.emplace_back(w, b);
+        for (int b : {1, 16}) tune.cand.emplace_back(w, b);
     tune.score.assign(tune.cand.size(), 0.0);
     tune.samples.assign(tune.cand.size(), 0);
     ctx->waves_per_cu = tune.cand[0].first;
@@ -526,6 +540,7 @@ gdpm_status Engine::init(gdpm_context c, hipStream_t s, const RunPlan& plan) {
     T = tab->view(nullptr);
     Ctl* hc = ctx->host_ctl;
     memset(hc, 0, sizeof(Ctl));
+    for (int r = 0; r < 2; ++r) hc->ring[r].head = hc->ring[r].tail = hc->ring[r].begin = ctx->ring_start;
     HIP_TRY(hipMemcpyAsync(ctx->ctl.p, hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemsetAsync(ctx->jc.p, 0, sizeof(JobCtl), st));
     memset(ctx->h_jc, 0, kJcMirrorBytes);
@@ -608,6 +623,10 @@ gdpm_status Engine::admit(EJob* j) {
     d.k0 = (uint32_t)j->prm.seed;
     d.k1 = (uint32_t)(j->prm.seed >> 32) ^ j->prm.job_id;
     d.flags = plan.flags;
+    // a new generation of the slot: records of the slot's earlier jobs (none
+    // in a sound run) are then recognised as such and dropped
+    slot_gen[slot] = (slot_gen[slot] + 1u) & 0xFFu;
+    d.gen = slot_gen[slot];
     HIP_TRY(hipMemcpyAsync(ctx->jobs_dev.as<JobDev>() + slot, &d, sizeof d, hipMemcpyHostToDevice, st));
     // the job's counters start from zero
     JobCtl* dj = ctx->jc.as<JobCtl>();
@@ -690,8 +709,27 @@ gdpm_status Engine::step() {
     // energy bins per job so that jobs x bins fits the re-binning keys
     const int nb = std::max(1, std::min(std::min(ctx->rebin_bins, kMaxBins), kMaxKeys / R.n_jobs));
     const float blo = -5.0f, bhi = 5.0f;  // log2 E range of the bins (0.03 .. 32 MeV)
-    int active_jobs = 0;
-    for (int i = 0; i < n_slots; ++i) active_jobs += slots[i] != nullptr;
+    // The jobs that hold particles in this iteration: live records after the
+    // last one (births less deaths) or new histories now.  With one such job
+    // the queues need no re-binning: they are all its segment.
+    int holders = 0, lone = -1, first_slot = -1;
+    {
+        const JobCtlMirror* m = reinterpret_cast<const JobCtlMirror*>(ctx->h_jc);
+        std::vector<char> fresh(n_slots, 0);
+        for (int ri = 0; ri < 2; ++ri)
+            for (int q = 0; q < nseg[ri]; ++q) fresh[hs[ri * seg_cap + q].job] = 1;
+        for (int i = 0; i < n_slots; ++i) {
+            if (!slots[i]) continue;
+            if (first_slot < 0) first_slot = i;
+            const long long live =
+                (long long)(m->births[i] - m->deaths[i]) - slots[i]->death_offset;
+            if (live != 0 || fresh[i]) {
+                ++holders;
+                lone = i;
+            }
+        }
+        if (holders == 0) lone = first_slot;   // queues hold no particle at all
+    }
     // A graph needs a launch sequence that does not change between iterations:
     // copy sizes and source grids are rounded up to powers of two (the kernels
     // read the true counts from the header), so a few recordings serve a run.
@@ -713,16 +751,17 @@ gdpm_status Engine::step() {
     k.blo = blo;
     k.binv = nb / (bhi - blo);
     for (int ri = 0; ri < 2; ++ri) {
-        // compact the queue and sort it by job and energy so that each job's
-        // records form a segment; a lone job (slot 0) skips it by default
-        // (measured faster: with lanes refilled every iteration energy order
-        // gains nothing, and push order keeps some spatial locality), the pass
-        // then reads the queue as it is, empty slots included
-        k.rebin[ri] = (ri == 0 ? ctx->rebin_photons : ctx->rebin_electrons) || active_jobs != 1 || !slots[0];
+        // compact the queue and sort it by job (and energy, rebin_bins > 1) so
+        // that each job's records form a segment; skipped when one job holds
+        // all particles (measured faster: with lanes refilled every iteration
+        // energy order gains nothing, and push order keeps some spatial
+        // locality), the pass then reads the queue as it is, empty slots included
+        k.rebin[ri] = (ri == 0 ? ctx->rebin_photons : ctx->rebin_electrons) || holders > 1 || lone < 0;
         k.lds[ri] = ctx->lds_tables && transport_lds_bytes(ri, T, k.threads / 64) <= (size_t)ctx->max_lds;
         tm.passes++;
         (ri == 0 ? tm.passes_photon : tm.passes_electron)++;
     }
+    k.lone = (k.rebin[0] && k.rebin[1]) ? -1 : lone;
     k.R = R;
     k.T = T;
     {
@@ -798,7 +837,7 @@ gdpm_status Engine::issue(const StepGraphKey& k, bool recording) {
     }
     for (int ri = 0; ri < 2; ++ri) {
         if (k.rebin[ri]) HIP_TRY(launch_rebin(st, 4 * k.blocks, dc, k.R, ri, k.nb, k.blo, k.binv));
-        HIP_TRY(launch_setup(st, dc, k.R, ri, k.rebin[ri]));
+        HIP_TRY(launch_setup(st, dc, k.R, ri, k.rebin[ri], k.lone));
         // a recorded event becomes a node of the graph that records it at replay
         HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri], st, hipEventRecordExternal)
                           : hipEventRecord(ctx->events[2 * ri], st));
@@ -1184,7 +1223,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->device = hip_device;
     ctx->ring_log2 = json_int(opts_json, "ring_capacity_log2", 25);
     ctx->waves_per_cu = json_int(opts_json, "waves_per_cu", 12);
-    ctx->rebin_bins = json_int(opts_json, "rebin_bins", 16);
+    ctx->rebin_bins = json_int(opts_json, "rebin_bins", 1);
     ctx->lds_tables = json_int(opts_json, "lds_tables", 1);
     ctx->pass_histories = json_int(opts_json, "pass_histories", 0);
     ctx->autotune = json_int(opts_json, "autotune", 0);
@@ -1193,6 +1232,9 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->rebin_electrons = json_int(opts_json, "rebin_electrons", 0);
     ctx->graphs = json_int(opts_json, "graphs", 1);
     ctx->check_accounting = json_int(opts_json, "check_accounting", 0);
+    const unsigned long long ring_start = json_u64(opts_json, "ring_start", 0);
+    if (ring_start >= (1ull << 32)) return fail(GDPM_E_INVALID, "ring_start below 2^32");
+    ctx->ring_start = (uint32_t)ring_start;
     if (ctx->ring_log2 < 12 || ctx->ring_log2 > 28) return fail(GDPM_E_INVALID, "ring_capacity_log2 in [12, 28]");
     if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > kMaxBlockThreads / 64)
         return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);

@@ -468,8 +468,11 @@ GDPM_DEV Particle load(const Particle* buf, uint32_t mask, uint32_t slot) {
 
 // mark the unused tail of this wave's reservation as empty slots
 GDPM_DEV void release(PushState& ps, Particle* buf, uint32_t mask) {
-    for (uint32_t s = ps.next + lane_id(); s < ps.end; s += 64u)
-        reinterpret_cast<float*>(buf + (s & mask))[3] = -1.0f;
+    // by offset from ps.next: queue positions run modulo 2^32, and a reserved
+    // run may straddle the wrap (then ps.end < ps.next as numbers)
+    const uint32_t n = ps.end - ps.next;
+    for (uint32_t o = lane_id(); o < n; o += 64u)
+        reinterpret_cast<float*>(buf + ((ps.next + o) & mask))[3] = -1.0f;
     ps.next = ps.end;
 }
 
@@ -511,6 +514,7 @@ struct WJob {
     unsigned long long hist0;
     uint32_t k0, k1, flags;
     int j;
+    uint32_t tag;                    // slot | generation << 8: low half of the records' job word
     uint32_t seg_begin, seg_count;   // the job's records in the running pass
 };
 
@@ -538,6 +542,7 @@ GDPM_DEV void load_job(WJob& w, const RunDev& R, int j) {
     w.k1 = __builtin_amdgcn_readfirstlane(d.k1);
     w.flags = __builtin_amdgcn_readfirstlane(d.flags);
     w.j = j;
+    w.tag = (uint32_t)j | ((__builtin_amdgcn_readfirstlane(d.gen) & 0xFFu) << 8);
     w.seg_begin = __builtin_amdgcn_readfirstlane(R.jc->seg_begin[j]);
     w.seg_count = __builtin_amdgcn_readfirstlane(R.jc->seg_count[j]);
 }
@@ -824,21 +829,25 @@ GDPM_DEV void push_photons(PendPhoton& q, PushState& ps, uint32_t head, Ctl* ctl
 // pass set-up and completion (one block, between passes): the job segments
 // come from the re-binning that precedes every pass
 // ---------------------------------------------------------------------------
-// rebinned = 0: the queue was not re-binned (one job only): its whole content,
-// empty slots included, is the job's segment
-__global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri, int rebinned) {
+// rebinned = 0: the queue was not re-binned because only job `lone` holds
+// particles: the whole queue, empty slots included, is that job's segment and
+// the other jobs' segments are empty (they start at its end, so that a
+// wavefront's first job is `lone`)
+__global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri, int rebinned, int lone) {
     JobCtl* jc = R.jc;
-    if (threadIdx.x == 0) {
-        RingCtl& r = ctl->ring[ri];
-        r.begin = r.head;
-        r.count = ctl->overflow ? 0u : r.tail - r.head;
-        r.claim = 0u;
-        if (!rebinned) {
-            jc->seg_begin[0] = 0u;
-            jc->seg_count[0] = r.count;
+    RingCtl& r = ctl->ring[ri];
+    const uint32_t count = ctl->overflow ? 0u : r.tail - r.head;
+    if (!rebinned)
+        for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) {
+            jc->seg_begin[j] = j <= lone ? 0u : count;
+            jc->seg_count[j] = j == lone ? count : 0u;
         }
-    }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        r.begin = r.head;
+        r.count = count;
+        r.claim = 0u;
+    }
     for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) jc->claim[j] = 0u;
     const int nw = (R.n_jobs + 63) >> 6;
     for (int k = threadIdx.x; k < kMaxJobs / 64; k += blockDim.x) {
@@ -905,9 +914,10 @@ GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uin
     if (!active && rank < take) {
         p = load(buf, mask, begin + W.seg_begin + cs.next + rank);
         got = p.e >= 0.0f;
-        if (got && (p.job & 0xFFFFu) != (uint32_t)W.j) {
-            // a record of another job in this job's segment: only a broken
-            // bookkeeping puts it there; it is dropped and counted
+        if (got && (p.job & 0xFFFFu) != W.tag) {
+            // a record of another job (or of an earlier job in this slot) in
+            // this job's segment: only a broken bookkeeping puts it there; it
+            // is dropped and counted
             atomicAdd(&ctl->anomalies, 1ull);
             got = false;
         }
@@ -958,7 +968,7 @@ __global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg
         const uint32_t k1 = __builtin_amdgcn_readfirstlane(d.k1);
         double* hist = uniform_copy(d.hist);
         const unsigned long long hist0 = uniform_copy(d.hist0);
-        const uint32_t jb = sg.job | (sg.batch << 16);
+        const uint32_t jb = sg.job | ((__builtin_amdgcn_readfirstlane(d.gen) & 0xFFu) << 8) | (sg.batch << 16);
         double e_in = 0.0, e_esc = 0.0, born = 0.0;
         for (uint32_t i = tid; i < sg.n; i += nthreads) {
             const unsigned long long h = sg.h0 + i;
@@ -1219,7 +1229,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             }
             // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
             wt.died += (uint32_t)__popcll(act0 & ~ballot(active));
-            const uint32_t jb = (uint32_t)W.j | (pb << 16);
+            const uint32_t jb = W.tag | (pb << 16);
             push_charged(qe, pe, head_e, ctl, R, W, jb, bufe, x, y, z, pack_vox(ix, iy, iz), rng, wt);
             push_photons(qg, pg, head_g, ctl, R, W, jb, bufg, x, y, z, rng, wt);
             }
@@ -1247,7 +1257,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                     q.x = x; q.y = y; q.z = z; q.e = e;
                     q.u = u; q.v = v; q.w = w; q.nh = -1.0f;
                     q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
-                    q.vox = 0u; q.a = 0.0f; q.flags = 0u; q.job = (uint32_t)W.j | (pb << 16);
+                    q.vox = 0u; q.a = 0.0f; q.flags = 0u; q.job = W.tag | (pb << 16);
                     if (requeue(active, pg, head_g, ctl, &ctl->ring[0], R.hard[0], bufg, R.mask[0], q, wt)) {
                         history_flush(tl, W, rng.hlo, rng.hhi);
                     }
@@ -1518,7 +1528,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                 }
             }
             wt.died += (uint32_t)__popcll(act0 & ~ballot(active));
-            const uint32_t jb = (uint32_t)W.j | (pb << 16);
+            const uint32_t jb = W.tag | (pb << 16);
             push_charged(qe, pe, head_e, ctl, R, W, jb, bufe, x, y, z, pack_vox(ix, iy, iz), rng, wt);
             push_photons(qg, pg, head_g, ctl, R, W, jb, bufg, x, y, z, rng, wt);
             }
@@ -1547,7 +1557,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                     q.u = u; q.v = v; q.w = w; q.nh = nh;
                     q.hlo = rng.hlo; q.hhi = rng.hhi; q.path = rng.path; q.ctr = rng_ctr(rng);
                     q.vox = pack_vox(ix, iy, iz); q.a = aa; q.flags = positron ? 1u : 0u;
-                    q.job = (uint32_t)W.j | (pb << 16);
+                    q.job = W.tag | (pb << 16);
                     if (requeue(active, pe, head_e, ctl, &ctl->ring[1], R.hard[1], bufe, R.mask[1], q, wt)) {
                         history_flush(tl, W, rng.hlo, rng.hhi);
                     }
@@ -1576,12 +1586,23 @@ GDPM_DEV int energy_bin(float e, float lo, float inv, int nb) {
     return min(max(b, 0), nb - 1);
 }
 
-GDPM_DEV int record_key(const Particle* buf, uint32_t mask, uint32_t slot, int nb, float lo, float inv,
-                        float& e) {
+// the slot of a record's job if that job is running in it (slot below n_jobs,
+// same generation), else -1
+GDPM_DEV int record_job(const RunDev& R, uint32_t job_word) {
+    const int slot = (int)(job_word & 0xFFu);
+    if (slot >= R.n_jobs) return -1;
+    const uint32_t gen = R.jobs[slot].gen & 0xFFu;
+    return ((job_word >> 8) & 0xFFu) == gen ? slot : -1;
+}
+
+// re-binning key of the record in `slot` (-1: empty, or no running job's)
+GDPM_DEV int record_key(const RunDev& R, const Particle* buf, uint32_t mask, uint32_t slot, int nb,
+                        float lo, float inv, bool& live) {
     const float4 w0 = reinterpret_cast<const float4*>(buf + (slot & mask))[0];
     const float4 w3 = reinterpret_cast<const float4*>(buf + (slot & mask))[3];
-    e = w0.w;
-    return (int)(__float_as_uint(w3.w) & 0xFFFFu) * nb + energy_bin(e, lo, inv, nb);
+    live = w0.w >= 0.0f;
+    const int j = live ? record_job(R, __float_as_uint(w3.w)) : -1;
+    return j < 0 ? -1 : j * nb + energy_bin(w0.w, lo, inv, nb);
 }
 
 __global__ void __launch_bounds__(256) k_bin_count(Ctl* ctl, RunDev R, int ri, int nb, float lo,
@@ -1595,9 +1616,9 @@ __global__ void __launch_bounds__(256) k_bin_count(Ctl* ctl, RunDev R, int ri, i
     const uint32_t n = r.tail - r.head;
     const Particle* buf = R.buf[ri][r.cur];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        float e;
-        const int k = record_key(buf, R.mask[ri], r.head + i, nb, lo, inv, e);
-        if (e >= 0.0f && k < nk) atomicAdd(&hist[k], 1u);
+        bool live;
+        const int k = record_key(R, buf, R.mask[ri], r.head + i, nb, lo, inv, live);
+        if (k >= 0) atomicAdd(&hist[k], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nk; i += blockDim.x)
@@ -1658,9 +1679,9 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri,
     for (int q = threadIdx.x; q < nk; q += blockDim.x) cnt[q] = 0u;
     __syncthreads();
     for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        float e;
-        const int k = record_key(src, R.mask[ri], r.head + i, nb, lo, inv, e);
-        if (e >= 0.0f && k < nk) atomicAdd(&cnt[k], 1u);
+        bool live;
+        const int k = record_key(R, src, R.mask[ri], r.head + i, nb, lo, inv, live);
+        if (k >= 0) atomicAdd(&cnt[k], 1u);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < nk; q += blockDim.x) {
@@ -1671,8 +1692,8 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri,
     for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         const Particle p = load(src, R.mask[ri], r.head + i);
         if (!(p.e >= 0.0f)) continue;
-        const int job = (int)(p.job & 0xFFFFu);
-        if (job < R.n_jobs) {
+        const int job = record_job(R, p.job);
+        if (job >= 0) {
             const int k = job * nb + energy_bin(p.e, lo, inv, nb);
             store(dst, R.mask[ri], base[k] + atomicAdd(&cnt[k], 1u), p);
         } else {
@@ -1693,9 +1714,8 @@ __global__ void __launch_bounds__(256) k_count_records(const Ctl* ctl, RunDev R,
         const Particle* buf = R.buf[ri][r.cur];
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
             const float4* q = reinterpret_cast<const float4*>(buf + ((r.head + i) & R.mask[ri]));
-            const float e = q[0].w;
-            const uint32_t j = __float_as_uint(q[3].w) & 0xFFFFu;
-            if (e >= 0.0f && (int)j < R.n_jobs) atomicAdd(&counts[j], 1ull);
+            const int j = q[0].w >= 0.0f ? record_job(R, __float_as_uint(q[3].w)) : -1;
+            if (j >= 0) atomicAdd(&counts[j], 1ull);
         }
     }
 }
@@ -1880,8 +1900,8 @@ __global__ void k_test_lookup(Tables T, int which, int m, const float* in, float
 // ---------------------------------------------------------------------------
 // host launchers (the host runtime calls these; kernels stay in this unit)
 // ---------------------------------------------------------------------------
-hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri, int rebinned) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, ctl, R, ri, rebinned);
+hipError_t launch_setup(hipStream_t st, Ctl* ctl, const RunDev& R, int ri, int rebinned, int lone) {
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, ctl, R, ri, rebinned, lone);
     return hipGetLastError();
 }
 hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, const SrcSeg* segs,

@@ -50,3 +50,11 @@ def statistical(g, o, n_batches, frac=0.1):
     region = np.maximum(g["dose"], o["dose"]) > frac * dmax
     nb_hist = None
     return rate, nreg, region
+
+
+def physics_events(r):
+    """Event counts that follow from the physics alone.  'deposits' counts the
+    FP64 tally additions, which depend on scheduling: a lane merges deposits of
+    consecutive steps in one voxel, and a particle handed to the next pass or a
+    wavefront changing jobs flushes its sum early."""
+    return {k: v for k, v in r["events"].items() if k != "deposits"}

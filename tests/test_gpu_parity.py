@@ -22,7 +22,7 @@ import oracle
 from paper_1107_3355_amd import gdpm as G
 from paper_1107_3355_amd import inputs as I
 from tests import stats as S
-from tests.gpu_common import balance, gpu_run, lockstep_fraction, oracle_run, report
+from tests.gpu_common import balance, gpu_run, lockstep_fraction, oracle_run, physics_events, report
 
 pytestmark = pytest.mark.gpu
 MATS = I.MATERIALS
@@ -222,7 +222,7 @@ def test_determinism_and_launch_independence(gctx):
     w = I.water_cube_2mev(50_000)
     a = gpu_run(gctx, w.phantom, w.source, n_hist=50_000, seed=9)
     b = gpu_run(gctx, w.phantom, w.source, n_hist=50_000, seed=9)
-    assert a["events"] == b["events"]
+    assert physics_events(a) == physics_events(b)
     np.testing.assert_allclose(a["dose"], b["dose"], rtol=1e-12, atol=1e-300)
     for opts in ('{"waves_per_cu": 4, "rebin_bins": 1, "rebin_photons": 1, "rebin_electrons": 1}',
                  '{"waves_per_cu": 8, "rebin_bins": 32, "rebin_photons": 1, "rebin_electrons": 1}',
@@ -233,8 +233,32 @@ def test_determinism_and_launch_independence(gctx):
             c = gpu_run(c2, w.phantom, w.source, n_hist=50_000, seed=9)
         finally:
             c2.close()
-        assert c["events"] == a["events"], opts
+        assert physics_events(c) == physics_events(a), opts
         np.testing.assert_allclose(c["dose"], a["dose"], rtol=1e-12, atol=1e-300)
+
+
+def test_queue_positions_wrap(gctx):
+    """Queue positions run modulo 2^32 and are never reset while a server's
+    jobs follow each other.  A run started just below the wrap crosses it in its
+    first passes, with a wavefront's reserved run of slots straddling it.
+    Regression: the release of a wavefront's unused reserved slots compared
+    absolute positions, so across the wrap it marked none of them empty and
+    their stale records were transported again (more deaths than births,
+    energy gained).  Same physics events and dose as from position 0, no
+    repair, no anomaly; the same with the queues re-binned."""
+    w = I.water_cube_2mev(200_000)
+    ref = gpu_run(gctx, w.phantom, w.source, n_hist=200_000, seed=4)
+    start = 2**32 - 150_000   # not a multiple of the 256-slot reservations
+    for extra in ("", ', "rebin_photons": 1, "rebin_electrons": 1'):
+        c2 = G.Context(0, opts=f'{{"ring_start": {start}{extra}}}', materials=MATS)
+        try:
+            r = gpu_run(c2, w.phantom, w.source, n_hist=200_000, seed=4)
+        finally:
+            c2.close()
+        assert r["accounting_repairs"] == 0 and r["transport_anomalies"] == 0, extra
+        assert physics_events(r) == physics_events(ref), extra
+        np.testing.assert_allclose(r["dose"], ref["dose"], rtol=1e-12, atol=1e-300)
+        assert balance(r) < 1e-12
 
 
 def test_graph_replay_equals_direct_launches(gctx):
@@ -263,7 +287,7 @@ def test_graph_replay_equals_direct_launches(gctx):
         assert a["graph_launches"] == 0 and a["graphs_recorded"] == 0
         assert b["graph_launches"] >= 10
         assert b["graphs_recorded"] <= max(2, b["graph_launches"] // 3)
-        assert a["events"] == b["events"], name
+        assert physics_events(a) == physics_events(b), name
         np.testing.assert_allclose(b["dose"], a["dose"], rtol=1e-12, atol=1e-300)
         assert balance(b) < 1e-6
         assert b["t_photon_s"] > 0 and b["t_electron_s"] > 0   # timing events replayed too
