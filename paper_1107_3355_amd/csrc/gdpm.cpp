@@ -211,8 +211,8 @@ struct gdpm_context_s {
     int pass_histories = 0;      // new histories per iteration (0: half a queue less its fill)
     int autotune = 0;            // tune block size and re-binning online, queues from the work
     int share = 1;               // new histories: 1 evenly over the jobs, 0 oldest job first
-    int rebin_photons = 0;       // 1: re-bin a lone job's photon queue too
-    int rebin_electrons = 0;     // 1: re-bin a lone job's electron queue too
+    int rebin_photons = 0;       // 1: re-bin the photon queue also when one job holds all particles
+    int rebin_electrons = 0;     // 1: the same for the electron queue
     int graphs = 1;              // replay each iteration's launches as a recorded HIP graph
     int check_accounting = 0;    // after every iteration, count each job's live records
     uint32_t ring_start = 0;     // queue position a run starts at (positions run modulo 2^32)
