@@ -341,6 +341,14 @@ def main():
             "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
             "avg_launch_ms": avg * 1e3, "launches": launches,
             "share_of_kernel_time": t_k / max(te + tp, 1e-30)}
+    # the kernel's FP64 tally additions per second against the measured rate of
+    # scattered FP64 atomics into an array of one CT tally slot (and a small one)
+    peak = ctx.atomic_rate(8 * w.phantom.nvox)
+    deposits = sum(r["deposits"][k] for r in runs)
+    roof["atomics"] = {"tally_atomics_per_s": deposits / max(t_k, 1e-30), "measured_peak_per_s": peak,
+                       "frac": deposits / max(t_k, 1e-30) / peak,
+                       "measured_peak_per_s_256KiB": ctx.atomic_rate(256 << 10),
+                       "probe": f"random FP64 atomicAdd into {8 * w.phantom.nvox} B (one tally slot)"}
 
     out = {
         "metric": METRIC,

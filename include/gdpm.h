@@ -362,6 +362,15 @@ gdpm_status gdpm_test_sample(gdpm_context ctx, int which, double e, double p1, d
 gdpm_status gdpm_test_source(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, uint64_t seed,
                              uint32_t job, uint64_t hist0, int n, float* out);
 
+/* Measured rate of scattered FP64 atomic additions (the tally's access
+ * pattern, no transport) into a zeroed device array of `bytes` bytes
+ * (8 B .. 16 GiB; the library allocates and frees it): *ops_per_s receives
+ * additions per second of the second of two launches of 8 blocks of 256
+ * threads per CU, 64 additions each.  GDPM_E_DEVICE if the array does not sum
+ * to the additions made.  The peak against which the benchmark prices the
+ * transport kernels' tally atomics. */
+gdpm_status gdpm_test_atomic_rate(gdpm_context ctx, uint64_t bytes, double* ops_per_s);
+
 /* Device table lookups at n energies for material mat (ecut/flags select the
  * table set): which 0 muTot photon, 1 R, 2 muHard, 3 muMoller, 4 1/lambda1,
  * 5 inverse range (input is R), 6 MW A (input is t). */

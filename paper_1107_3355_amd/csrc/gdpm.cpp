@@ -55,6 +55,7 @@ hipError_t launch_test_source(hipStream_t st, const SourceDev& S, const Geom& G,
                               uint32_t k1, unsigned long long hist0, int n, float* out);
 hipError_t launch_test_lookup(hipStream_t st, const Tables& T, int which, int m, const float* in,
                               float* out, int n);
+hipError_t launch_atomic_rate(hipStream_t st, int blocks, double* buf, uint32_t n, uint32_t iters);
 }  // namespace gdpm
 
 using namespace gdpm;
@@ -1767,6 +1768,42 @@ gdpm_status gdpm_test_philox(gdpm_context ctx, const uint32_t key[2], const uint
     HIP_TRY(launch_test_philox(ctx->stream, key[0], key[1], a.as<const uint4>(), b.as<uint4>(), n));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     HIP_TRY(hipMemcpy(out, b.p, (size_t)n * 16, hipMemcpyDeviceToHost));
+    return GDPM_OK;
+}
+
+gdpm_status gdpm_test_atomic_rate(gdpm_context ctx, uint64_t bytes, double* ops_per_s) {
+    if (!ctx || !ops_per_s || bytes < 8 || bytes > (1ull << 34))
+        return fail(GDPM_E_INVALID, "bad arguments (8 B <= footprint <= 16 GiB)");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const uint64_t n = bytes / 8;
+    const int blocks = 8 * grid_blocks(ctx);
+    const uint32_t iters = 64;
+    DevBuf buf;
+    HIP_TRY(buf.alloc(n * 8));
+    HIP_TRY(hipMemsetAsync(buf.p, 0, n * 8, ctx->stream));
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    float ms = 0.0f;
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // the second launch is timed
+        e = hipEventRecord(a, ctx->stream);
+        if (e == hipSuccess) e = launch_atomic_rate(ctx->stream, blocks, buf.as<double>(), (uint32_t)n, iters);
+        if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    HIP_TRY(e);
+    // every addition landed: the array sums to the number made (exact in FP64)
+    std::vector<double> h(n);
+    HIP_TRY(hipMemcpy(h.data(), buf.p, n * 8, hipMemcpyDeviceToHost));
+    double sum = 0.0;
+    for (double v : h) sum += v;
+    const double ops = (double)blocks * 256.0 * iters;
+    if (sum != 2.0 * ops) return fail(GDPM_E_DEVICE, "atomic probe lost additions: %.0f of %.0f", sum, 2.0 * ops);
+    *ops_per_s = ms > 0.0f ? ops / (ms * 1e-3) : 0.0;
     return GDPM_OK;
 }
 

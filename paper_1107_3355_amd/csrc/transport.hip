@@ -1989,6 +1989,26 @@ hipError_t launch_test_source(hipStream_t st, const SourceDev& S, const Geom& G,
                        out);
     return hipGetLastError();
 }
+// scattered FP64 atomic additions: `iters` per thread at hashed addresses of
+// an array of n words (the dose tally's access pattern without the transport)
+__global__ void __launch_bounds__(256) k_atomic_rate(double* buf, uint32_t n, uint32_t iters) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t k = 0; k < iters; ++k) {
+        uint32_t h = t * 0x9E3779B9u + k * 0x85EBCA6Bu;
+        h ^= h >> 16;
+        h *= 0x7FEB352Du;
+        h ^= h >> 15;
+        h *= 0x846CA68Bu;
+        h ^= h >> 16;
+        unsafeAtomicAdd(&buf[h % n], 1.0);
+    }
+}
+
+hipError_t launch_atomic_rate(hipStream_t st, int blocks, double* buf, uint32_t n, uint32_t iters) {
+    hipLaunchKernelGGL(k_atomic_rate, dim3(blocks), dim3(256), 0, st, buf, n, iters);
+    return hipGetLastError();
+}
+
 hipError_t launch_test_lookup(hipStream_t st, const Tables& T, int which, int m, const float* in,
                               float* out, int n) {
     hipLaunchKernelGGL(k_test_lookup, dim3((n + 255) / 256), dim3(256), 0, st, T, which, m, in, out, n);

@@ -24,7 +24,7 @@ EXPORTS = ("gdpm_context_create", "gdpm_context_destroy", "gdpm_last_error", "gd
            "gdpm_phantom_create", "gdpm_phantom_destroy", "gdpm_source_create",
            "gdpm_source_destroy", "gdpm_run", "gdpm_run_async", "gdpm_job_wait",
            "gdpm_job_release", "gdpm_tables_host", "gdpm_test_philox", "gdpm_test_sample",
-           "gdpm_test_source", "gdpm_test_lookup", "gdpm_run_batch", "gdpm_context_settings",
+           "gdpm_test_atomic_rate", "gdpm_test_source", "gdpm_test_lookup", "gdpm_run_batch", "gdpm_context_settings",
            "gdpm_server_create", "gdpm_server_submit", "gdpm_server_info_get",
            "gdpm_server_destroy")
 
@@ -116,6 +116,7 @@ def lib():
             "gdpm_tables_host": [C.POINTER(Material), C.c_int, C.c_int, C.c_double, C.c_double,
                                  C.c_uint32, C.c_int, fp, C.c_size_t, C.POINTER(C.c_size_t), dp],
             "gdpm_test_philox": [vp, u32p, u32p, u32p, C.c_int],
+            "gdpm_test_atomic_rate": [vp, C.c_uint64, C.POINTER(C.c_double)],
             "gdpm_test_sample": [vp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_uint64,
                                  C.c_int, fp, fp],
             "gdpm_test_source": [vp, vp, vp, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int, fp],
@@ -336,6 +337,12 @@ class Context:
         return out
 
     # --- test entry points ---
+    def atomic_rate(self, nbytes: int) -> float:
+        """Scattered FP64 atomic additions per second into an array of nbytes."""
+        out = C.c_double()
+        _check(lib().gdpm_test_atomic_rate(self.handle, nbytes, C.byref(out)))
+        return out.value
+
     def philox(self, key: Sequence[int], ctr: np.ndarray) -> np.ndarray:
         ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
         out = np.empty_like(ctr)

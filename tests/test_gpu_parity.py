@@ -237,6 +237,16 @@ def test_determinism_and_launch_independence(gctx):
         np.testing.assert_allclose(c["dose"], a["dose"], rtol=1e-12, atol=1e-300)
 
 
+def test_atomic_rate_probe(gctx):
+    """The microbenchmark that gives the measured peak of scattered FP64 atomics
+    (it checks on the host that every addition landed)."""
+    big, small = gctx.atomic_rate(64 << 20), gctx.atomic_rate(256 << 10)
+    report("atomic probe", per_s_64MiB=f"{big:.3g}", per_s_256KiB=f"{small:.3g}")
+    assert big > 1e9 and small > 1e9
+    with pytest.raises(G.GdpmError):
+        gctx.atomic_rate(4)
+
+
 def test_queue_positions_wrap(gctx):
     """Queue positions run modulo 2^32 and are never reset while a server's
     jobs follow each other.  A run started just below the wrap crosses it in its
