@@ -98,7 +98,21 @@ typedef struct {
     gdpm_spectrum spectrum;  /* energies within (ecut, 30] MeV */
     int n_beams;             /* >= 1; beamlets of all beams form one index I */
     const gdpm_beam* beams;
+    /* how a history picks its beamlet (section 2.3.1): 0, the search of the
+     * cumulative probability P(I) <= r < P(I+1); 1, Metropolis sampling
+     * (Algorithm A1): a job's histories form GDPM_METRO_CHAINS chains, history
+     * h on chain h mod GDPM_METRO_CHAINS, each taken in increasing h from the
+     * job's first history and started at a beamlet drawn with equal
+     * probability among those of nonzero intensity (stream: history id
+     * (2^32-1)*2^32 + chain, path 0); at history h, after the energy, h's
+     * stream gives a trial beamlet J (equal probability among nonzero ones)
+     * and r, and the chain moves to J when r f_prev < f_J.  The chains
+     * converge to f_I (the first histories of a chain carry their start's
+     * bias); a chain's state lives with the job on the device. */
+    int beamlet_sampler;
 } gdpm_source_desc;
+
+#define GDPM_METRO_CHAINS 16384
 
 /* run flags: physics switches used by the tests' closed-form special cases */
 #define GDPM_NO_COMPTON 1u

@@ -36,10 +36,14 @@ class Beam(C.Structure):
                 ("bw", C.c_double), ("bh", C.c_double), ("intensity", C.POINTER(C.c_float))]
 
 
+METRO_CHAINS = 16384   # ORC_METRO_CHAINS of oracle.h
+
+
 class Source(C.Structure):
     _fields_ = [("particle", C.c_int), ("spec_kind", C.c_int), ("spec_n", C.c_int),
                 ("spec_e", C.POINTER(C.c_double)), ("spec_p", C.POINTER(C.c_double)),
-                ("e_mono", C.c_double), ("n_beams", C.c_int), ("beams", C.POINTER(Beam))]
+                ("e_mono", C.c_double), ("n_beams", C.c_int), ("beams", C.POINTER(Beam)),
+                ("beamlet_sampler", C.c_int)]
 
 
 class Params(C.Structure):
@@ -132,7 +136,8 @@ def _source(src, keep):
             beams[i].intensity = f.ctypes.data_as(C.POINTER(C.c_float))
     keep.refs.append(beams)
     sp = src.spectrum
-    s = Source(src.particle, sp.kind, 0, None, None, sp.e_mono, len(src.beams), beams)
+    s = Source(src.particle, sp.kind, 0, None, None, sp.e_mono, len(src.beams), beams,
+               getattr(src, "beamlet_sampler", 0))
     if sp.kind == 1:
         e = keep.arr(sp.e, np.float64)
         p = keep.arr(sp.p, np.float64)

@@ -404,6 +404,9 @@ typedef struct {
     int* beam_off;    /* first global beamlet of each beam */
     int nf;
     double* spec_c;   /* cumulative spectrum at spec_e */
+    double* f;        /* beamlet intensities (negative ones as 0) */
+    int* metro_bl;    /* Metropolis mode: beamlet of history metro_h0 + i */
+    uint64_t metro_h0;
     orc_params prm;
 } ctx_t;
 
@@ -827,6 +830,42 @@ static int beamlet_search(const ctx_t* c, double r) {
     return lo;
 }
 
+/* Algorithm A1 (section 2.3.1), Metropolis sampling of the beamlet index,
+ * for histories h0 .. h0+n-1.  The histories form ORC_METRO_CHAINS chains,
+ * history h on chain h mod ORC_METRO_CHAINS, each taken in increasing h.  A
+ * chain starts at a beamlet drawn with equal probability among those of
+ * nonzero intensity, from a stream of its own (history id (2^32-1)*2^32 +
+ * chain, path 0, a history id no run reaches).  At history h, after the draw
+ * of the energy, h's stream gives the trial beamlet J (equal probability among
+ * nonzero beamlets) and r; the chain moves to J when r < f_J / f_prev, tested
+ * as r f_prev < f_J, exact in double precision. */
+static int metropolis_chains(ctx_t* c, uint64_t h0, uint64_t n) {
+    int n_nz = 0;
+    for (int i = 0; i < c->nf; ++i) n_nz += c->f[i] > 0.0;
+    if (n_nz == 0) return 1;
+    int* nz = (int*)malloc(sizeof(int) * n_nz);
+    for (int i = 0, k = 0; i < c->nf; ++i)
+        if (c->f[i] > 0.0) nz[k++] = i;
+    c->metro_bl = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    c->metro_h0 = h0;
+    const uint64_t C = ORC_METRO_CHAINS;
+    for (uint64_t ch = 0; ch < C; ++ch) {
+        stream_t s0 = stream_make(c->prm.seed, c->prm.job_id, (0xFFFFFFFFull << 32) | ch, 0);
+        int prev = nz[(int)floor(draw(&s0) * n_nz)];
+        for (uint64_t h = h0 + (ch + C - h0 % C) % C; h < h0 + n; h += C) {
+            stream_t s = stream_make(c->prm.seed, c->prm.job_id, h, 0);
+            (void)draw(&s);   /* the energy's draw */
+            int J = nz[(int)floor(draw(&s) * n_nz)];
+            double r = draw(&s);
+            int I = r * c->f[prev] < c->f[J] ? J : prev;
+            c->metro_bl[h - h0] = I;
+            prev = I;
+        }
+    }
+    free(nz);
+    return 0;
+}
+
 /* sample the primary of history h; returns 1 if it enters the phantom */
 static int source_particle(const ctx_t* c, uint64_t h, particle_t* p, int* beamlet) {
     const orc_source* s = c->src;
@@ -834,7 +873,14 @@ static int source_particle(const ctx_t* c, uint64_t h, particle_t* p, int* beaml
     p->s = stream_make(c->prm.seed, c->prm.job_id, h, 0);
     p->type = s->particle == 0 ? 0 : 1;
     p->e = spectrum_energy(c, draw(&p->s));
-    int gi = beamlet_search(c, draw(&p->s));
+    int gi;
+    if (c->metro_bl) {
+        (void)draw(&p->s);   /* J and r of the chain step */
+        (void)draw(&p->s);
+        gi = c->metro_bl[h - c->metro_h0];
+    } else {
+        gi = beamlet_search(c, draw(&p->s));
+    }
     double ux = draw(&p->s), uy = draw(&p->s);
     *beamlet = gi;
     int b = c->beam_of[gi];
@@ -940,6 +986,7 @@ static int validate(const orc_material* mats, int n_mat, const orc_phantom* ph,
     for (size_t v = 0; v < nv; ++v)
         if (ph->mat[v] >= n_mat || !(ph->rho[v] > 0.0f)) return 1;
     if (src->n_beams < 1 || !src->beams) return 1;
+    if (src->beamlet_sampler != 0 && src->beamlet_sampler != 1) return 1;
     if (src->spec_kind == 0 && !(src->e_mono > 0)) return 1;
     if (src->spec_kind == 1 && (src->spec_n < 2 || !src->spec_e || !src->spec_p)) return 1;
     if (prm->n_batches < 1 || prm->round_size < 1) return 1;
@@ -973,6 +1020,7 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
     c.nf = 0;
     for (int b = 0; b < src->n_beams; ++b) c.nf += src->beams[b].nbx * src->beams[b].nby;
     c.cdf = (double*)malloc(sizeof(double) * (c.nf + 1));
+    c.f = (double*)malloc(sizeof(double) * c.nf);
     c.beam_of = (int*)malloc(sizeof(int) * c.nf);
     c.beam_off = (int*)malloc(sizeof(int) * src->n_beams);
     double tot = 0.0;
@@ -984,11 +1032,13 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
             double f = bm->intensity ? (double)bm->intensity[j] : 1.0;
             if (f < 0.0) f = 0.0;
             c.cdf[gi] = tot;
+            c.f[gi] = f;
             c.beam_of[gi] = b;
             tot += f;
         }
     }
     int bad = !(tot > 0.0);
+    if (!bad && src->beamlet_sampler == 1) bad = metropolis_chains(&c, prm->hist0, prm->n_hist);
     for (int i = 0; i < c.nf; ++i) c.cdf[i] /= tot;
     c.cdf[c.nf] = 1.0;
     if (src->spec_kind == 1) {
@@ -1001,6 +1051,7 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
     }
     if (bad) {
         free(c.mats); free(c.cdf); free(c.beam_of); free(c.beam_off); free(c.spec_c);
+        free(c.f); free(c.metro_bl);
         return 1;
     }
 
@@ -1067,6 +1118,7 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
     if (!batch_edep) free(slots);
     free(nhist); free(jobs); free(th);
     free(c.mats); free(c.cdf); free(c.beam_of); free(c.beam_off); free(c.spec_c);
+    free(c.f); free(c.metro_bl);
     return 0;
 }
 
@@ -1206,6 +1258,7 @@ int orc_sample_source(const orc_source* src, const orc_phantom* ph, uint64_t see
     c.nf = 0;
     for (int b = 0; b < src->n_beams; ++b) c.nf += src->beams[b].nbx * src->beams[b].nby;
     c.cdf = (double*)malloc(sizeof(double) * (c.nf + 1));
+    c.f = (double*)malloc(sizeof(double) * c.nf);
     c.beam_of = (int*)malloc(sizeof(int) * c.nf);
     c.beam_off = (int*)malloc(sizeof(int) * src->n_beams);
     double tot = 0.0;
@@ -1217,9 +1270,14 @@ int orc_sample_source(const orc_source* src, const orc_phantom* ph, uint64_t see
             double f = bm->intensity ? (double)bm->intensity[j] : 1.0;
             if (f < 0.0) f = 0.0;
             c.cdf[gi] = tot;
+            c.f[gi] = f;
             c.beam_of[gi] = b;
             tot += f;
         }
+    }
+    if (src->beamlet_sampler == 1 && metropolis_chains(&c, hist0, (uint64_t)n)) {
+        free(c.cdf); free(c.f); free(c.beam_of); free(c.beam_off);
+        return 1;
     }
     for (int i = 0; i < c.nf; ++i) c.cdf[i] /= tot;
     c.cdf[c.nf] = 1.0;
@@ -1243,5 +1301,6 @@ int orc_sample_source(const orc_source* src, const orc_phantom* ph, uint64_t see
         }
     }
     free(c.cdf); free(c.beam_of); free(c.beam_off); free(c.spec_c);
+    free(c.f); free(c.metro_bl);
     return 0;
 }

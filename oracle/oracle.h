@@ -50,7 +50,14 @@ typedef struct {
     double e_mono;
     int n_beams;
     const orc_beam* beams;
+    int beamlet_sampler;  /* 0: cumulative-probability search; 1: Metropolis chains
+                             (Algorithm A1, section 2.3.1; see ORC_METRO_CHAINS) */
 } orc_source;
+
+/* Metropolis beamlet sampling: the run's histories form this many chains,
+ * history h on chain h mod ORC_METRO_CHAINS, each taken in increasing h from
+ * the run's first history (hist0). */
+#define ORC_METRO_CHAINS 16384
 
 /* physics switches (test cases that reduce to closed forms) */
 #define ORC_NO_COMPTON 1u

@@ -129,7 +129,13 @@ struct SourceDev {
     const BeamDev* beams;
     const uint16_t* beam_of;   // beamlet -> beam
     int n_beams;
+    int metro;                 // 1: Metropolis beamlet chains (Algorithm A1)
+    int n_nz;                  // beamlets of nonzero intensity ...
+    const uint32_t* nz;        // ... their indices
+    const float* f;            // [nf] intensities (negative ones as 0)
 };
+
+constexpr uint32_t kMetroChains = 16384;   // Metropolis chains of a job
 
 // One dose job: its phantom, source, random key and tallies.
 struct JobDev {
@@ -144,6 +150,7 @@ struct JobDev {
     uint32_t flags;            // GDPM_* run flags
     uint32_t gen;              // generation of the slot (8 bits): records of an earlier
                                // job in the same slot carry another one
+    uint32_t* chains;          // [kMetroChains] Metropolis chain states, or null
 };
 
 // A run of new histories for the source pass: ids [h0, h0 + n) of job `job`,

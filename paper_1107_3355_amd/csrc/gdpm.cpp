@@ -56,6 +56,7 @@ hipError_t launch_test_source(hipStream_t st, const SourceDev& S, const Geom& G,
 hipError_t launch_test_lookup(hipStream_t st, const Tables& T, int which, int m, const float* in,
                               float* out, int n);
 hipError_t launch_atomic_rate(hipStream_t st, int blocks, double* buf, uint32_t n, uint32_t iters);
+hipError_t launch_metro_init(hipStream_t st, const SourceDev& S, uint32_t k0, uint32_t k1, uint32_t* chains);
 }  // namespace gdpm
 
 using namespace gdpm;
@@ -252,7 +253,9 @@ struct gdpm_source_s {
     int spec_kind, spec_n;
     float e_mono;
     DevBuf spec_e, spec_p, spec_c, cdf, guide, beams, beam_of;
+    DevBuf fl, nz;               // intensities and nonzero beamlets (Metropolis chains)
     int nf, n_guide, n_beams;
+    int metro = 0, n_nz = 0;
     SourceDev view() const {
         SourceDev s;
         s.particle = particle;
@@ -269,6 +272,10 @@ struct gdpm_source_s {
         s.beams = beams.as<const BeamDev>();
         s.beam_of = beam_of.as<const uint16_t>();
         s.n_beams = n_beams;
+        s.metro = metro;
+        s.n_nz = n_nz;
+        s.nz = nz.as<const uint32_t>();
+        s.f = fl.as<const float>();
         return s;
     }
 };
@@ -404,6 +411,7 @@ struct EJob {
     int slot = -1;
     size_t nv = 0;
     DevBuf tally, mumax, hist, dose_buf, sigma_buf;
+    DevBuf chains;               // Metropolis chain states of the job's source
     double* d_dose = nullptr;   // outputs in device memory
     double* d_sigma = nullptr;
     uint64_t hbase = 0;         // id of the job's first history
@@ -628,6 +636,12 @@ gdpm_status Engine::admit(EJob* j) {
     // in a sound run) are then recognised as such and dropped
     slot_gen[slot] = (slot_gen[slot] + 1u) & 0xFFu;
     d.gen = slot_gen[slot];
+    if (j->src->metro) {
+        // the job's Metropolis chains start afresh at its first history
+        HIP_TRY(j->chains.alloc(kMetroChains * sizeof(uint32_t)));
+        HIP_TRY(launch_metro_init(st, d.S, d.k0, d.k1, j->chains.as<uint32_t>()));
+        d.chains = j->chains.as<uint32_t>();
+    }
     HIP_TRY(hipMemcpyAsync(ctx->jobs_dev.as<JobDev>() + slot, &d, sizeof d, hipMemcpyHostToDevice, st));
     // the job's counters start from zero
     JobCtl* dj = ctx->jc.as<JobCtl>();
@@ -1198,6 +1212,7 @@ void gdpm_server_s::loop() {
             j->dose_buf.reset();
             j->sigma_buf.reset();
             j->mumax.reset();
+            j->chains.reset();
             used -= j->footprint;
             histories += j->issued;
             finish_server_job(this, job, cs ? cs : j->status, cs ? "copying the outputs failed" : j->err);
@@ -1355,6 +1370,8 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
     if (d->particle != 0 && d->particle != 1) return fail(GDPM_E_INVALID, "particle must be 0 or 1");
     if (d->n_beams < 1 || !d->beams) return fail(GDPM_E_INVALID, "need at least one beam");
     if (d->n_beams > 65535) return fail(GDPM_E_INVALID, "at most 65535 beams");
+    if (d->beamlet_sampler != 0 && d->beamlet_sampler != 1)
+        return fail(GDPM_E_INVALID, "beamlet_sampler must be 0 (search) or 1 (Metropolis)");
     auto src = std::make_unique<gdpm_source_s>();
     src->ctx = ctx;
     src->particle = d->particle;
@@ -1417,6 +1434,8 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
     if (nf > ((size_t)1 << 30)) return fail(GDPM_E_INVALID, "too many beamlets");
     std::vector<double> cdf(nf + 1, 0.0);
     std::vector<uint16_t> beam_of(nf);
+    std::vector<float> fl(nf);
+    std::vector<uint32_t> nzl;
     double tot = 0.0;
     size_t gi = 0;
     for (int b = 0; b < d->n_beams; ++b) {
@@ -1445,6 +1464,8 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
             if (f < 0.0) f = 0.0;
             cdf[gi] = tot;
             beam_of[gi] = (uint16_t)b;
+            fl[gi] = (float)f;
+            if (f > 0.0) nzl.push_back((uint32_t)gi);
             tot += f;
         }
     }
@@ -1468,6 +1489,12 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
     HIP_TRY(upload(src->guide, guide));
     HIP_TRY(upload(src->beams, beams));
     HIP_TRY(upload(src->beam_of, beam_of));
+    src->metro = d->beamlet_sampler;
+    if (src->metro) {
+        HIP_TRY(upload(src->fl, fl));
+        HIP_TRY(upload(src->nz, nzl));
+        src->n_nz = (int)nzl.size();
+    }
     src->nf = (int)nf;
     src->n_guide = (int)ng;
     src->n_beams = d->n_beams;
@@ -1586,6 +1613,7 @@ gdpm_status gdpm_run_batch(gdpm_context ctx, int n, const gdpm_job_desc* jobs,
             j->dose_buf.reset();
             j->sigma_buf.reset();
             j->mumax.reset();
+            j->chains.reset();
             --left;
         }
     }

@@ -337,10 +337,38 @@ struct Primary {
     bool in;
 };
 
-GDPM_DEV Primary make_primary(const SourceDev& S, const Geom& G, Rng& r, uint32_t k0, uint32_t k1) {
+// one step of a Metropolis chain (Algorithm A1, section 2.3.1): trial beamlet J
+// with equal probability among those of nonzero intensity, then r; the chain
+// moves to J when r < f_J / f_prev, tested as r f_prev < f_J in double
+// precision (exact for single-precision r and f)
+GDPM_DEV int metropolis_step(const SourceDev& S, float uj, float r, uint32_t& prev) {
+    const uint32_t J = S.nz[min((int)((double)uj * (double)S.n_nz), S.n_nz - 1)];
+    if ((double)r * (double)S.f[prev] < (double)S.f[J]) prev = J;
+    return (int)prev;
+}
+
+// chain start: a beamlet drawn with equal probability among those of nonzero
+// intensity, from the chain's own stream (history id (2^32-1) 2^32 + chain)
+GDPM_DEV uint32_t metropolis_start(const SourceDev& S, uint32_t chain, uint32_t k0, uint32_t k1) {
+    Rng r;
+    rng_start(r, chain, 0xFFFFFFFFu, 0u, 0u);
+    const float u = uniform(r, k0, k1);
+    return S.nz[min((int)((double)u * (double)S.n_nz), S.n_nz - 1)];
+}
+
+// the primary of the history whose stream is r; `chain` (Metropolis sources
+// only) holds the state of the history's chain and is advanced
+GDPM_DEV Primary make_primary(const SourceDev& S, const Geom& G, Rng& r, uint32_t k0, uint32_t k1,
+                              uint32_t* chain = nullptr) {
     Primary p;
     p.e = spectrum_energy(S, uniform(r, k0, k1));
-    const int gi = beamlet_of(S, uniform(r, k0, k1));
+    int gi;
+    if (chain) {
+        const float uj = uniform(r, k0, k1);
+        gi = metropolis_step(S, uj, uniform(r, k0, k1), *chain);
+    } else {
+        gi = beamlet_of(S, uniform(r, k0, k1));
+    }
     const float ux = uniform(r, k0, k1), uy = uniform(r, k0, k1);
     p.beamlet = gi;
     const BeamDev& b = S.beams[S.beam_of[gi]];
@@ -970,12 +998,13 @@ __global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg
         const unsigned long long hist0 = uniform_copy(d.hist0);
         const uint32_t jb = sg.job | ((__builtin_amdgcn_readfirstlane(d.gen) & 0xFFu) << 8) | (sg.batch << 16);
         double e_in = 0.0, e_esc = 0.0, born = 0.0;
-        for (uint32_t i = tid; i < sg.n; i += nthreads) {
+        // history sg.h0 + i; `chain` holds its Metropolis chain (or is null)
+        auto one = [&](uint32_t i, uint32_t* chain) {
             const unsigned long long h = sg.h0 + i;
             Rng rng;
             rng_start(rng, (uint32_t)h, (uint32_t)(h >> 32), 0u, 0u);
             rng_topup(rng, k0, k1);
-            const Primary pr = make_primary(S, G, rng, k0, k1);
+            const Primary pr = make_primary(S, G, rng, k0, k1, chain);
             e_in += (double)pr.e;
             float4* q = reinterpret_cast<float4*>(buf + ((tail + sg.off + i) & R.mask[ri]));
             if (pr.in) {
@@ -997,6 +1026,19 @@ __global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg
                 e_esc += (double)pr.e;
                 if (hist) unsafeAtomicAdd(&hist[2 * (h - hist0) + 1], (double)pr.e);
             }
+        };
+        if (S.metro) {
+            // a chain's histories in increasing order, by one thread (a chain
+            // runs across segments and iterations through its stored state)
+            uint32_t* chains = uniform_copy(d.chains);
+            for (uint32_t c = tid; c < kMetroChains; c += nthreads) {
+                uint32_t state = chains[c];
+                const uint32_t first = (uint32_t)((c + kMetroChains - sg.h0 % kMetroChains) % kMetroChains);
+                for (uint32_t i = first; i < sg.n; i += kMetroChains) one(i, &state);
+                chains[c] = state;
+            }
+        } else {
+            for (uint32_t i = tid; i < sg.n; i += nthreads) one(i, nullptr);
         }
         e_in = block_sum(e_in, sh);
         e_esc = block_sum(e_esc, sh);
@@ -1860,20 +1902,41 @@ __global__ void k_test_sample(Tables T, int which, float e, float p1, float p2, 
     if (out2) out2[i] = b;
 }
 
-__global__ void k_test_source(SourceDev S, Geom G, uint32_t k0, uint32_t k1,
-                              unsigned long long hist0, int n, float* out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+GDPM_DEV void test_source_one(const SourceDev& S, const Geom& G, uint32_t k0, uint32_t k1,
+                              unsigned long long hist0, int i, float* out, uint32_t* chain) {
     const unsigned long long h = hist0 + i;
     Rng r;
     rng_start(r, (uint32_t)h, (uint32_t)(h >> 32), 0u, 0u);
     rng_topup(r, k0, k1);
-    const Primary p = make_primary(S, G, r, k0, k1);
+    const Primary p = make_primary(S, G, r, k0, k1, chain);
     float* o = out + 8 * (size_t)i;
     o[0] = p.e;
     o[1] = p.in ? (float)p.beamlet : -1.0f;
     o[2] = p.x; o[3] = p.y; o[4] = p.z;
     o[5] = p.u; o[6] = p.v; o[7] = p.w;
+}
+
+// histories hist0 .. hist0+n-1 as a job starting at hist0 samples them; with
+// Metropolis chains one thread per chain, the chains freshly started
+__global__ void k_test_source(SourceDev S, Geom G, uint32_t k0, uint32_t k1,
+                              unsigned long long hist0, int n, float* out) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (S.metro) {
+        if (t >= kMetroChains) return;
+        uint32_t state = metropolis_start(S, t, k0, k1);
+        const uint32_t first = (uint32_t)((t + kMetroChains - hist0 % kMetroChains) % kMetroChains);
+        for (uint32_t i = first; i < (uint32_t)n; i += kMetroChains)
+            test_source_one(S, G, k0, k1, hist0, (int)i, out, &state);
+        return;
+    }
+    if ((int)t >= n) return;
+    test_source_one(S, G, k0, k1, hist0, (int)t, out, nullptr);
+}
+
+// the start of every Metropolis chain of a job
+__global__ void k_metro_init(SourceDev S, uint32_t k0, uint32_t k1, uint32_t* chains) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < kMetroChains) chains[c] = metropolis_start(S, c, k0, k1);
 }
 
 __global__ void k_test_lookup(Tables T, int which, int m, const float* in, float* out, int n) {
@@ -1985,8 +2048,12 @@ hipError_t launch_test_sample(hipStream_t st, const Tables& T, int which, float 
 }
 hipError_t launch_test_source(hipStream_t st, const SourceDev& S, const Geom& G, uint32_t k0,
                               uint32_t k1, unsigned long long hist0, int n, float* out) {
-    hipLaunchKernelGGL(k_test_source, dim3((n + 255) / 256), dim3(256), 0, st, S, G, k0, k1, hist0, n,
-                       out);
+    const int blocks = S.metro ? (int)(kMetroChains / 256) : (n + 255) / 256;
+    hipLaunchKernelGGL(k_test_source, dim3(blocks), dim3(256), 0, st, S, G, k0, k1, hist0, n, out);
+    return hipGetLastError();
+}
+hipError_t launch_metro_init(hipStream_t st, const SourceDev& S, uint32_t k0, uint32_t k1, uint32_t* chains) {
+    hipLaunchKernelGGL(k_metro_init, dim3(kMetroChains / 256), dim3(256), 0, st, S, k0, k1, chains);
     return hipGetLastError();
 }
 // scattered FP64 atomic additions: `iters` per thread at hashed addresses of

@@ -94,6 +94,7 @@ class Source:
     particle: int            # 0 photon, 1 electron
     spectrum: Spectrum
     beams: List[Beam] = field(default_factory=list)
+    beamlet_sampler: int = 0  # 0 cumulative-probability search, 1 Metropolis chains (Algorithm A1)
 
 
 PHOTON, ELECTRON = 0, 1

@@ -153,3 +153,32 @@ def test_source_lockstep(gctx, case):
     np.testing.assert_allclose(g[inside, 2:5], o[inside, 2:5], atol=2e-4)
     np.testing.assert_allclose(g[inside, 5:8], o[inside, 5:8], atol=2e-5)
     report("source", case=name, inside=float(inside.mean()))
+
+
+def test_metropolis_source_lockstep(gctx):
+    """Metropolis beamlet chains (Algorithm A1) on the device against the
+    oracle's: the same beamlet for every history of every chain (integer,
+    exact), on the full-size 9-beam CT plan with zero-intensity beamlets added,
+    over four steps of each chain from a first history that is not a multiple
+    of the chain count."""
+    import dataclasses
+    w = I.ct_imrt()
+    beams = []
+    for k, b in enumerate(w.source.beams):
+        f = np.array(b.intensity, dtype=np.float32, copy=True)
+        f.ravel()[k::7] = 0.0
+        beams.append(dataclasses.replace(b, intensity=f))
+    src = I.Source(w.source.particle, w.source.spectrum, beams, beamlet_sampler=1)
+    p = gctx.phantom(w.phantom)
+    s = gctx.source(src)
+    n = 4 * oracle.METRO_CHAINS + 777
+    g = gctx.sample_source(p, s, n=n, hist0=98765)
+    o = oracle.sample_source(src, w.phantom, n=n, hist0=98765)
+    p.close()
+    s.close()
+    assert np.array_equal(g[:, 1], o[:, 1].astype(np.float32))
+    inside = o[:, 1] >= 0
+    np.testing.assert_allclose(g[inside, 2:5], o[inside, 2:5], atol=2e-4)
+    zero = np.concatenate([np.asarray(b.intensity).ravel() == 0 for b in beams])
+    assert not zero[o[inside, 1].astype(int)].any()
+    report("metropolis source", inside=float(inside.mean()))

@@ -129,6 +129,62 @@ def test_beamlet_choice_follows_fluence():
     assert _chi2_p(counts.astype(float), ff / ff.sum() * n) > 1e-4
 
 
+def _metro_case(n_chains_steps):
+    ph = I.homogeneous((40, 40, 20), (0.5, 0.5, 0.5), I.ID_WATER, 1.0)
+    rng = np.random.default_rng(4)
+    f = rng.uniform(0, 1, size=(8, 8)).astype(np.float32)
+    f[2, 3] = 0.0
+    beams = [I.gantry_beam(ph, g, nb=8, bsize=1.0, intensity=f) for g in (0.0, 90.0)]
+    src = I.Source(I.PHOTON, I.mono(1.0), beams, beamlet_sampler=1)
+    n = oracle.METRO_CHAINS * n_chains_steps
+    bl = oracle.sample_source(src, ph, n=n)[:, 1].astype(int)
+    ff = np.concatenate([f.ravel(), f.ravel()]).astype(np.float64)
+    return bl, ff
+
+
+def test_metropolis_beamlets_converge_to_fluence():
+    """Algorithm A1 (section 2.3.1): past its first steps each chain samples the
+    beamlets with probability f_I / sum f (chi-square), never one of zero
+    intensity; and the paper's error e = |p_f - p_f*|_2 over the first N
+    histories falls as N grows (its Fig. 2(c))."""
+    C = oracle.METRO_CHAINS
+    bl, ff = _metro_case(100)
+    assert np.all(bl >= 0)
+    p_star = ff / ff.sum()
+    # every 10th step from the 20th on: the start is forgotten, and samples 10
+    # steps apart on a chain (each move happens with probability about 1/2) are
+    # as good as independent; different chains are independent
+    late = bl.reshape(100, C)[20::10].ravel()
+    counts = np.bincount(late, minlength=len(ff)).astype(float)
+    assert counts[2 * 8 + 3] == 0 and counts[64 + 2 * 8 + 3] == 0
+    assert _chi2_p(counts, p_star * len(late)) > 1e-4
+    errs = []
+    for n in (C * 3, C * 12, C * 100):
+        p = np.bincount(bl[:n], minlength=len(ff)) / n
+        errs.append(float(np.linalg.norm(p - p_star)))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.35 * errs[0]
+
+
+def test_metropolis_transition_rate():
+    """Step 3 of Algorithm A1 pinned by its closed form: with the chain at I
+    (stationary, probability p_I) and a uniform trial J among the n nonzero
+    beamlets, the chain moves to another beamlet with probability
+    sum_I p_I sum_{J != I} min(1, f_J / f_I) / n.  Measured over consecutive
+    histories of each chain."""
+    C = oracle.METRO_CHAINS
+    bl, ff = _metro_case(60)
+    chains = bl.reshape(60, C)[20:]          # row k: step k of every chain
+    moves = (chains[1:] != chains[:-1]).mean()
+    fz = ff[ff > 0]
+    p = fz / fz.sum()
+    ratio = np.minimum(1.0, fz[None, :] / fz[:, None])     # [I, J]
+    np.fill_diagonal(ratio, 0.0)
+    expect = float((p[:, None] * ratio).sum(axis=1).sum() / len(fz))
+    trials = chains[1:].size
+    assert abs(moves - expect) < 5 * math.sqrt(expect * (1 - expect) / trials) + 2e-3, (moves, expect)
+
+
 def test_point_source_geometry():
     ph = I.homogeneous((20, 20, 20), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
     b = I.point_beam_z(ph, field=10.0, ssd=90.0, sad=100.0)
