@@ -119,6 +119,39 @@ def batched_form(G, I, n_jobs, opts=None):
             "speedup": ts / tb, "energy_balance_max": bal, "accounting_repairs": repairs}
 
 
+def source_modes(G, I, w, args):
+    """The two beamlet samplers of section 2.3.1 on the CT plan: a job to the
+    target uncertainty with each, and the paper's Fig. 2 error e(N) =
+    |p_f - p_f*|_2 of the beamlet frequencies of one beam after N histories."""
+    import dataclasses
+    ctx = G.Context(0, opts=args.opts, materials=I.MATERIALS)
+    ph = ctx.phantom(w.phantom)
+    out = {"workload": "CT 256x256x128 IMRT-9 to the target; Fig. 2 metric on beam 0 (40x40 beamlets)"}
+    for k, name in ((0, "search"), (1, "metropolis")):
+        src = dataclasses.replace(w.source, beamlet_sampler=k)
+        s = ctx.source(src)
+        r = ctx.run(ph, s, seed=7, n_hist=args.n0, target_unc=args.target,
+                    stat_min_density=args.min_density, want_dose=False)
+        s.close()
+        b0 = w.source.beams[0]
+        one = I.Source(w.source.particle, w.source.spectrum, [b0], beamlet_sampler=k)
+        s1 = ctx.source(one)
+        f = np.asarray(b0.intensity, dtype=np.float64).ravel()
+        p_star = f / f.sum()
+        errs = {}
+        for n in (100_000, 1_000_000, 4_000_000):
+            bl = ctx.sample_source(ph, s1, seed=11, n=n)[:, 1]
+            bl = bl[bl >= 0].astype(np.int64)
+            errs[str(n)] = float(np.linalg.norm(np.bincount(bl, minlength=len(f)) / max(len(bl), 1) - p_star))
+        s1.close()
+        out[name] = {"histories_per_s": r["histories"] / r["t_total_s"], "seconds": r["t_total_s"],
+                     "histories": r["histories"], "unc": r["unc"], "fig2_error": errs}
+        log(f"source modes: {name}: {r['histories'] / r['t_total_s']:.4g} hist/s, e(N) {errs}")
+    ph.close()
+    ctx.close()
+    return out
+
+
 def log_accounting(what, res):
     """Report jobs whose particle accounting needed a repair, failed a check or met an anomaly
     (their signed energy balance and births - deaths gap)."""
@@ -274,6 +307,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="length of the served request stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2.0, help="requests per second")
+    ap.add_argument("--source-modes", type=int, default=1,
+                    help="1: also run the CT job with Metropolis beamlet sampling (section 2.3.1)")
     ap.add_argument("--min-density", type=float, default=0.1,
                     help="voxels below this density (the air around the patient) are left out "
                          "of D_max and of the uncertainty statistic")
@@ -382,6 +417,9 @@ def main():
         log(f"batched form: {args.batched_jobs} jobs")
         out["batched_form"] = batched_form(G, I, args.batched_jobs, args.opts)
         log(f"batched form: speed-up {out['batched_form']['speedup']:.2f}x over sequential runs")
+    if args.source_modes:
+        log("source modes: search and Metropolis beamlet sampling")
+        out["source_modes"] = source_modes(G, I, w, args)
     if args.serve_seconds > 0:
         log(f"served form: {args.serve_seconds} s of requests at {args.serve_rate}/s")
         out["served_form"] = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom, args.opts)
