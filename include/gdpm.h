@@ -110,6 +110,15 @@ typedef struct {
      * converge to f_I (the first histories of a chain carry their start's
      * bias); a chain's state lives with the job on the device. */
     int beamlet_sampler;
+    /* how a history picks its energy (section 2.3.2): 0, by sampling the
+     * spectrum; K in 1..64 (piecewise-linear spectra), from K energy intervals
+     * of equal width over the spectrum's support: a round of R histories gives
+     * positions C_k <= i < C_{k+1}, C_k = floor(R F(e_k) + 1/2), to interval k
+     * (F the spectrum's CDF at the interval's lower edge), so a round runs
+     * through the intervals in increasing energy, and inside its interval a
+     * history's energy follows the spectrum (inverse CDF at F_k + u (F_{k+1} -
+     * F_k)). */
+    int spectrum_strata;
 } gdpm_source_desc;
 
 #define GDPM_METRO_CHAINS 16384

@@ -43,7 +43,7 @@ class Source(C.Structure):
     _fields_ = [("particle", C.c_int), ("spec_kind", C.c_int), ("spec_n", C.c_int),
                 ("spec_e", C.POINTER(C.c_double)), ("spec_p", C.POINTER(C.c_double)),
                 ("e_mono", C.c_double), ("n_beams", C.c_int), ("beams", C.POINTER(Beam)),
-                ("beamlet_sampler", C.c_int)]
+                ("beamlet_sampler", C.c_int), ("spectrum_strata", C.c_int)]
 
 
 class Params(C.Structure):
@@ -137,7 +137,7 @@ def _source(src, keep):
     keep.refs.append(beams)
     sp = src.spectrum
     s = Source(src.particle, sp.kind, 0, None, None, sp.e_mono, len(src.beams), beams,
-               getattr(src, "beamlet_sampler", 0))
+               getattr(src, "beamlet_sampler", 0), getattr(src, "spectrum_strata", 0))
     if sp.kind == 1:
         e = keep.arr(sp.e, np.float64)
         p = keep.arr(sp.p, np.float64)

@@ -405,6 +405,7 @@ typedef struct {
     int nf;
     double* spec_c;   /* cumulative spectrum at spec_e */
     double* f;        /* beamlet intensities (negative ones as 0) */
+    double* strata_F; /* spectrum CDF at the K + 1 interval edges (stratified spectra) */
     int* metro_bl;    /* Metropolis mode: beamlet of history metro_h0 + i */
     uint64_t metro_h0;
     orc_params prm;
@@ -820,6 +821,42 @@ static double spectrum_energy(const ctx_t* c, double u) {
     return clampd(s->spec_e[j] + x, s->spec_e[j], s->spec_e[j + 1]);
 }
 
+/* spectrum CDF F(e), the area of the piecewise-linear pdf below e over its total */
+static double spectrum_cdf(const ctx_t* c, double e) {
+    const orc_source* s = c->src;
+    int n = s->spec_n;
+    if (e <= s->spec_e[0]) return 0.0;
+    if (e >= s->spec_e[n - 1]) return 1.0;
+    int j = 0;
+    while (j < n - 2 && s->spec_e[j + 1] <= e) ++j;
+    double t = (e - s->spec_e[j]) / (s->spec_e[j + 1] - s->spec_e[j]);
+    double pe = s->spec_p[j] + t * (s->spec_p[j + 1] - s->spec_p[j]);
+    return (c->spec_c[j] + 0.5 * (s->spec_p[j] + pe) * (e - s->spec_e[j])) / c->spec_c[n - 1];
+}
+
+/* section 2.3.2: the K energy intervals of equal width over the support */
+static void strata_setup(ctx_t* c) {
+    const orc_source* s = c->src;
+    int K = s->spectrum_strata;
+    c->strata_F = (double*)malloc(sizeof(double) * (K + 1));
+    double e0 = s->spec_e[0], e1 = s->spec_e[s->spec_n - 1];
+    for (int k = 0; k <= K; ++k) c->strata_F[k] = spectrum_cdf(c, e0 + (e1 - e0) * k / K);
+    c->strata_F[0] = 0.0;
+    c->strata_F[K] = 1.0;
+}
+
+/* energy of history h in a stratified run: its position i in its round of R
+ * histories picks the interval k with C_k <= i < C_{k+1}, C_k = floor(R F_k +
+ * 1/2); the energy is the spectrum's inverse CDF at F_k + u (F_{k+1} - F_k) */
+static double stratified_energy(const ctx_t* c, uint64_t h, double u) {
+    uint64_t off = h - c->prm.hist0, R = c->prm.round_size, N = c->prm.n_hist;
+    uint64_t a = off / R * R, b = a + R < N ? a + R : N;
+    double i = (double)(off - a), size = (double)(b - a);
+    int K = c->src->spectrum_strata, k = 0;
+    while (k < K - 1 && floor(size * c->strata_F[k + 1] + 0.5) <= i) ++k;
+    return spectrum_energy(c, c->strata_F[k] + u * (c->strata_F[k + 1] - c->strata_F[k]));
+}
+
 /* beamlet I with P(I) <= r < P(I+1), by bisection on the cumulative array */
 static int beamlet_search(const ctx_t* c, double r) {
     int lo = 0, hi = c->nf; /* P[lo] <= r < P[hi] */
@@ -872,7 +909,7 @@ static int source_particle(const ctx_t* c, uint64_t h, particle_t* p, int* beaml
     memset(p, 0, sizeof *p);
     p->s = stream_make(c->prm.seed, c->prm.job_id, h, 0);
     p->type = s->particle == 0 ? 0 : 1;
-    p->e = spectrum_energy(c, draw(&p->s));
+    p->e = c->strata_F ? stratified_energy(c, h, draw(&p->s)) : spectrum_energy(c, draw(&p->s));
     int gi;
     if (c->metro_bl) {
         (void)draw(&p->s);   /* J and r of the chain step */
@@ -987,6 +1024,8 @@ static int validate(const orc_material* mats, int n_mat, const orc_phantom* ph,
         if (ph->mat[v] >= n_mat || !(ph->rho[v] > 0.0f)) return 1;
     if (src->n_beams < 1 || !src->beams) return 1;
     if (src->beamlet_sampler != 0 && src->beamlet_sampler != 1) return 1;
+    if (src->spectrum_strata < 0 || src->spectrum_strata > 64) return 1;
+    if (src->spectrum_strata > 0 && src->spec_kind != 1) return 1;
     if (src->spec_kind == 0 && !(src->e_mono > 0)) return 1;
     if (src->spec_kind == 1 && (src->spec_n < 2 || !src->spec_e || !src->spec_p)) return 1;
     if (prm->n_batches < 1 || prm->round_size < 1) return 1;
@@ -1048,10 +1087,11 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
             c.spec_c[j + 1] = c.spec_c[j] + 0.5 * (src->spec_p[j] + src->spec_p[j + 1]) *
                                                 (src->spec_e[j + 1] - src->spec_e[j]);
         if (!(c.spec_c[src->spec_n - 1] > 0.0)) bad = 1;
+        else if (src->spectrum_strata > 0) strata_setup(&c);
     }
     if (bad) {
         free(c.mats); free(c.cdf); free(c.beam_of); free(c.beam_off); free(c.spec_c);
-        free(c.f); free(c.metro_bl);
+        free(c.f); free(c.metro_bl); free(c.strata_F);
         return 1;
     }
 
@@ -1118,7 +1158,7 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
     if (!batch_edep) free(slots);
     free(nhist); free(jobs); free(th);
     free(c.mats); free(c.cdf); free(c.beam_of); free(c.beam_off); free(c.spec_c);
-    free(c.f); free(c.metro_bl);
+    free(c.f); free(c.metro_bl); free(c.strata_F);
     return 0;
 }
 
@@ -1245,7 +1285,9 @@ int orc_sample_source(const orc_source* src, const orc_phantom* ph, uint64_t see
     prm.seed = seed;
     prm.job_id = job;
     prm.n_batches = 1;
-    prm.round_size = 1;
+    prm.hist0 = hist0;
+    prm.n_hist = n > 0 ? (uint64_t)n : 1;    /* the n histories form one round */
+    prm.round_size = prm.n_hist;
     if (validate(&dummy, 256, ph, src, &prm)) return 1;
     ctx_t c;
     memset(&c, 0, sizeof c);
@@ -1287,6 +1329,7 @@ int orc_sample_source(const orc_source* src, const orc_phantom* ph, uint64_t see
         for (int j = 0; j + 1 < src->spec_n; ++j)
             c.spec_c[j + 1] = c.spec_c[j] + 0.5 * (src->spec_p[j] + src->spec_p[j + 1]) *
                                                 (src->spec_e[j + 1] - src->spec_e[j]);
+        if (src->spectrum_strata > 0) strata_setup(&c);
     }
     for (int i = 0; i < n; ++i) {
         particle_t p;
@@ -1301,6 +1344,6 @@ int orc_sample_source(const orc_source* src, const orc_phantom* ph, uint64_t see
         }
     }
     free(c.cdf); free(c.beam_of); free(c.beam_off); free(c.spec_c);
-    free(c.f); free(c.metro_bl);
+    free(c.f); free(c.metro_bl); free(c.strata_F);
     return 0;
 }

@@ -52,6 +52,12 @@ typedef struct {
     const orc_beam* beams;
     int beamlet_sampler;  /* 0: cumulative-probability search; 1: Metropolis chains
                              (Algorithm A1, section 2.3.1; see ORC_METRO_CHAINS) */
+    int spectrum_strata;  /* 0: each history samples the spectrum; K > 0 (piecewise-linear
+                             spectra, K <= 64): section 2.3.2's energy intervals, K of
+                             equal width over the spectrum's support; a round of R
+                             histories gives positions C_k <= i < C_{k+1}, C_k =
+                             floor(R F(e_k) + 1/2), to interval k, in increasing energy,
+                             and the energy follows the spectrum inside the interval */
 } orc_source;
 
 /* Metropolis beamlet sampling: the run's histories form this many chains,

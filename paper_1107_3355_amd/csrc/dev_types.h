@@ -133,6 +133,8 @@ struct SourceDev {
     int n_nz;                  // beamlets of nonzero intensity ...
     const uint32_t* nz;        // ... their indices
     const float* f;            // [nf] intensities (negative ones as 0)
+    int strata;                // K > 0: energy intervals of a round (section 2.3.2)
+    const double* strata_F;    // [K + 1] spectrum CDF at the interval edges
 };
 
 constexpr uint32_t kMetroChains = 16384;   // Metropolis chains of a job
@@ -159,6 +161,7 @@ struct SrcSeg {
     unsigned long long h0;
     uint32_t n, off;
     uint32_t job, batch;
+    uint32_t rpos, rsize;      // position of h0 in its round, and the round's size
 };
 
 // the source pass of one particle type in one scheduler iteration: segments

@@ -254,8 +254,9 @@ struct gdpm_source_s {
     float e_mono;
     DevBuf spec_e, spec_p, spec_c, cdf, guide, beams, beam_of;
     DevBuf fl, nz;               // intensities and nonzero beamlets (Metropolis chains)
+    DevBuf strata_F;             // spectrum CDF at the energy-interval edges
     int nf, n_guide, n_beams;
-    int metro = 0, n_nz = 0;
+    int metro = 0, n_nz = 0, strata = 0;
     SourceDev view() const {
         SourceDev s;
         s.particle = particle;
@@ -276,6 +277,8 @@ struct gdpm_source_s {
         s.n_nz = n_nz;
         s.nz = nz.as<const uint32_t>();
         s.f = fl.as<const float>();
+        s.strata = strata;
+        s.strata_F = strata_F.as<const double>();
         return s;
     }
 };
@@ -709,6 +712,9 @@ gdpm_status Engine::step() {
             SrcSeg& sg = hs[ri * seg_cap + nseg[ri]++];
             sg.h0 = j->hbase + j->issued;
             sg.n = (uint32_t)m;
+            const uint64_t round_start = j->sr_start + (uint64_t)b * j->round_size;
+            sg.rpos = (uint32_t)(j->issued - round_start);
+            sg.rsize = (uint32_t)(round_end - round_start);
             sg.off = total[ri];
             sg.job = (uint32_t)j->slot;
             sg.batch = b;
@@ -1372,6 +1378,11 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
     if (d->n_beams > 65535) return fail(GDPM_E_INVALID, "at most 65535 beams");
     if (d->beamlet_sampler != 0 && d->beamlet_sampler != 1)
         return fail(GDPM_E_INVALID, "beamlet_sampler must be 0 (search) or 1 (Metropolis)");
+    if (d->spectrum_strata < 0 || d->spectrum_strata > 64)
+        return fail(GDPM_E_INVALID, "spectrum_strata in [0, 64]");
+    if (d->spectrum_strata > 0 && d->spectrum.kind != 1)
+        return fail(GDPM_E_INVALID, "energy intervals need a piecewise-linear spectrum");
+    std::vector<double> strata_F;
     auto src = std::make_unique<gdpm_source_s>();
     src->ctx = ctx;
     src->particle = d->particle;
@@ -1406,6 +1417,22 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
         }
         sc.clear();
         for (int i = 0; i < sp.n_pts; ++i) sc.push_back((float)c[i]);
+        // section 2.3.2: CDF of the spectrum at the edges of K equal-width
+        // intervals over its support (area of the pdf below e over the total)
+        if (d->spectrum_strata > 0) {
+            const int K = d->spectrum_strata;
+            const double e0 = sp.e_mev[0], e1 = sp.e_mev[sp.n_pts - 1];
+            strata_F.assign(K + 1, 0.0);
+            for (int k = 1; k < K; ++k) {
+                const double e = e0 + (e1 - e0) * k / K;
+                int j = 0;
+                while (j < sp.n_pts - 2 && sp.e_mev[j + 1] <= e) ++j;
+                const double t = (e - sp.e_mev[j]) / (sp.e_mev[j + 1] - sp.e_mev[j]);
+                const double pe = sp.pdf[j] + t * (sp.pdf[j + 1] - sp.pdf[j]);
+                strata_F[k] = (c[j] + 0.5 * (sp.pdf[j] + pe) * (e - sp.e_mev[j])) / area;
+            }
+            strata_F[K] = 1.0;
+        }
         src->spec_n = sp.n_pts;
         src->e_mono = 0.0f;
         src->e_max = sp.e_mev[sp.n_pts - 1];
@@ -1489,6 +1516,8 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
     HIP_TRY(upload(src->guide, guide));
     HIP_TRY(upload(src->beams, beams));
     HIP_TRY(upload(src->beam_of, beam_of));
+    src->strata = d->spectrum_strata;
+    if (src->strata) HIP_TRY(upload(src->strata_F, strata_F));
     src->metro = d->beamlet_sampler;
     if (src->metro) {
         HIP_TRY(upload(src->fl, fl));

@@ -356,12 +356,24 @@ GDPM_DEV uint32_t metropolis_start(const SourceDev& S, uint32_t chain, uint32_t 
     return S.nz[min((int)((double)u * (double)S.n_nz), S.n_nz - 1)];
 }
 
+// section 2.3.2: energy of the history at position i of a round of `size`:
+// interval k with C_k <= i < C_{k+1}, C_k = floor(size F_k + 1/2), and the
+// spectrum's inverse CDF at F_k + u (F_{k+1} - F_k)
+GDPM_DEV float stratified_energy(const SourceDev& S, uint32_t i, uint32_t size, float u) {
+    int k = 0;
+    while (k < S.strata - 1 && floor((double)size * S.strata_F[k + 1] + 0.5) <= (double)i) ++k;
+    const double f0 = S.strata_F[k], f1 = S.strata_F[k + 1];
+    return spectrum_energy(S, (float)(f0 + (double)u * (f1 - f0)));
+}
+
 // the primary of the history whose stream is r; `chain` (Metropolis sources
-// only) holds the state of the history's chain and is advanced
+// only) holds the state of the history's chain and is advanced; rpos and
+// rsize (stratified spectra only) place the history in its round
 GDPM_DEV Primary make_primary(const SourceDev& S, const Geom& G, Rng& r, uint32_t k0, uint32_t k1,
-                              uint32_t* chain = nullptr) {
+                              uint32_t* chain = nullptr, uint32_t rpos = 0u, uint32_t rsize = 1u) {
     Primary p;
-    p.e = spectrum_energy(S, uniform(r, k0, k1));
+    const float ue = uniform(r, k0, k1);
+    p.e = S.strata ? stratified_energy(S, rpos, rsize, ue) : spectrum_energy(S, ue);
     int gi;
     if (chain) {
         const float uj = uniform(r, k0, k1);
@@ -1004,7 +1016,7 @@ __global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg
             Rng rng;
             rng_start(rng, (uint32_t)h, (uint32_t)(h >> 32), 0u, 0u);
             rng_topup(rng, k0, k1);
-            const Primary pr = make_primary(S, G, rng, k0, k1, chain);
+            const Primary pr = make_primary(S, G, rng, k0, k1, chain, sg.rpos + i, sg.rsize);
             e_in += (double)pr.e;
             float4* q = reinterpret_cast<float4*>(buf + ((tail + sg.off + i) & R.mask[ri]));
             if (pr.in) {
@@ -1903,12 +1915,12 @@ __global__ void k_test_sample(Tables T, int which, float e, float p1, float p2, 
 }
 
 GDPM_DEV void test_source_one(const SourceDev& S, const Geom& G, uint32_t k0, uint32_t k1,
-                              unsigned long long hist0, int i, float* out, uint32_t* chain) {
+                              unsigned long long hist0, int i, int n, float* out, uint32_t* chain) {
     const unsigned long long h = hist0 + i;
     Rng r;
     rng_start(r, (uint32_t)h, (uint32_t)(h >> 32), 0u, 0u);
     rng_topup(r, k0, k1);
-    const Primary p = make_primary(S, G, r, k0, k1, chain);
+    const Primary p = make_primary(S, G, r, k0, k1, chain, (uint32_t)i, (uint32_t)n);
     float* o = out + 8 * (size_t)i;
     o[0] = p.e;
     o[1] = p.in ? (float)p.beamlet : -1.0f;
@@ -1926,11 +1938,11 @@ __global__ void k_test_source(SourceDev S, Geom G, uint32_t k0, uint32_t k1,
         uint32_t state = metropolis_start(S, t, k0, k1);
         const uint32_t first = (uint32_t)((t + kMetroChains - hist0 % kMetroChains) % kMetroChains);
         for (uint32_t i = first; i < (uint32_t)n; i += kMetroChains)
-            test_source_one(S, G, k0, k1, hist0, (int)i, out, &state);
+            test_source_one(S, G, k0, k1, hist0, (int)i, n, out, &state);
         return;
     }
     if ((int)t >= n) return;
-    test_source_one(S, G, k0, k1, hist0, (int)t, out, nullptr);
+    test_source_one(S, G, k0, k1, hist0, (int)t, n, out, nullptr);
 }
 
 // the start of every Metropolis chain of a job

@@ -52,7 +52,8 @@ class Beam(C.Structure):
 
 class SourceDesc(C.Structure):
     _fields_ = [("particle", C.c_int), ("spectrum", Spectrum), ("n_beams", C.c_int),
-                ("beams", C.POINTER(Beam)), ("beamlet_sampler", C.c_int)]
+                ("beams", C.POINTER(Beam)), ("beamlet_sampler", C.c_int),
+                ("spectrum_strata", C.c_int)]
 
 
 class RunParams(C.Structure):
@@ -214,7 +215,8 @@ class Source:
             keep += [e, p]
             spec.n_pts = len(e)
             spec.e_mev, spec.pdf = _dp(e), _dp(p)
-        d = SourceDesc(src.particle, spec, len(src.beams), beams, getattr(src, "beamlet_sampler", 0))
+        d = SourceDesc(src.particle, spec, len(src.beams), beams, getattr(src, "beamlet_sampler", 0),
+                       getattr(src, "spectrum_strata", 0))
         self.handle = C.c_void_p()
         _check(lib().gdpm_source_create(ctx.handle, C.byref(d), C.byref(self.handle)))
 

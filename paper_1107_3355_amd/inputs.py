@@ -95,6 +95,7 @@ class Source:
     spectrum: Spectrum
     beams: List[Beam] = field(default_factory=list)
     beamlet_sampler: int = 0  # 0 cumulative-probability search, 1 Metropolis chains (Algorithm A1)
+    spectrum_strata: int = 0  # 0 plain spectrum sampling, K > 0 energy intervals (section 2.3.2)
 
 
 PHOTON, ELECTRON = 0, 1

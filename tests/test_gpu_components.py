@@ -182,3 +182,29 @@ def test_metropolis_source_lockstep(gctx):
     zero = np.concatenate([np.asarray(b.intensity).ravel() == 0 for b in beams])
     assert not zero[o[inside, 1].astype(int)].any()
     report("metropolis source", inside=float(inside.mean()))
+
+
+def test_stratified_source_lockstep(gctx):
+    """Energy intervals (section 2.3.2): for one round of n histories the device
+    and the oracle put every history in the same interval and give it the same
+    energy to single-precision rounding; the beamlets are unchanged."""
+    import dataclasses
+    w = I.ct_imrt()
+    K = 16
+    src = dataclasses.replace(w.source, spectrum_strata=K)
+    p = gctx.phantom(w.phantom)
+    s = gctx.source(src)
+    n = 50_001
+    g = gctx.sample_source(p, s, n=n, hist0=4242)
+    o = oracle.sample_source(src, w.phantom, n=n, hist0=4242)
+    p.close()
+    s.close()
+    assert np.array_equal(g[:, 1], o[:, 1].astype(np.float32))
+    sp = src.spectrum
+    edges = sp.e[0] + (sp.e[-1] - sp.e[0]) * np.arange(K + 1) / K
+    kg = np.clip(np.searchsorted(edges, g[:, 0], side="right") - 1, 0, K - 1)
+    ko = np.clip(np.searchsorted(edges, o[:, 0], side="right") - 1, 0, K - 1)
+    assert np.mean(kg == ko) > 0.9999                  # an energy on an edge may round across
+    rel = np.abs(g[:, 0] / o[:, 0] - 1)
+    assert np.mean(rel < 2e-6) > 0.999 and rel.max() < 1e-4
+    assert np.all(np.diff(ko) >= 0)

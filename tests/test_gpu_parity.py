@@ -53,11 +53,14 @@ def _compare_stat(gctx, ph, src, n, flags=0, name="", min_rate=0.95, min_rho=0.0
     return g, o
 
 
-def _compare_lockstep(gctx, ph, src, n, flags=0, name="", min_frac=0.9, hist0=0):
+def _compare_lockstep(gctx, ph, src, n, flags=0, name="", min_frac=0.9, hist0=0, one_round=False):
+    # one_round: all n histories in the first round (the source sampler's view
+    # of them, which stratified spectra need for the per-history energies)
+    kw = dict(round_size=n) if one_round else {}
     g = gpu_run(gctx, ph, src, seed=3, n_hist=n, n_batches=2, flags=flags, want_hist=True,
-                hist0=hist0)
+                hist0=hist0, **kw)
     o = oracle_run(MATS, ph, src, seed=3, n_hist=n, n_batches=2, flags=flags, want_hist=True,
-                   hist0=hist0)
+                   hist0=hist0, **kw)
     e_in = oracle.sample_source(src, ph, seed=3, hist0=hist0, n=n)[:, 0]
     p, s = gctx.phantom(ph), gctx.source(src)
     e_in_g = gctx.sample_source(p, s, seed=3, hist0=hist0, n=n)[:, 0].astype(np.float64)
@@ -158,6 +161,20 @@ def test_ct_metropolis_source(gctx):
     src = I.Source(I.PHOTON, I.triangular_spectrum(), I.imrt_plan(ph, nb=10), beamlet_sampler=1)
     _compare_lockstep(gctx, ph, src, 3_000, name="ct48_imrt_metropolis", min_frac=0.9, hist0=40_000)
     _compare_stat(gctx, ph, src, 300_000, name="ct48_imrt_metropolis", min_rho=0.1, max_sigma=3.0)
+
+
+def test_stratified_spectrum_transport(gctx):
+    """Energy intervals of the spectrum (section 2.3.2) on the 100^3 slab: one
+    round (the source sampler's) in lockstep with the oracle; ten rounds
+    statistically equal to the oracle's dose with the same intervals."""
+    import dataclasses
+    w = I.slab_photon()
+    src = dataclasses.replace(w.source, spectrum_strata=12)
+    _compare_lockstep(gctx, w.phantom, src, 4_003, name="slab100_photon_strata", min_frac=0.9,
+                      one_round=True)
+    w2 = I.slab_photon(n=50, d=0.6)
+    _compare_stat(gctx, w2.phantom, dataclasses.replace(w2.source, spectrum_strata=12), 300_000,
+                  name="slab50_photon_strata")
 
 
 def test_ct_full_size_energy_balance(gctx):

@@ -129,6 +129,33 @@ def test_beamlet_choice_follows_fluence():
     assert _chi2_p(counts.astype(float), ff / ff.sum() * n) > 1e-4
 
 
+def test_stratified_spectrum():
+    """Section 2.3.2: K equal-width energy intervals; a round's histories go to
+    the intervals in increasing energy, in numbers R P_k (rounded cumulatively),
+    with the spectrum's shape inside each interval.  P_k and the conditional
+    CDFs from the triangular pdf's closed form."""
+    lo, pk, hi = 0.25, 1.2, 6.0
+    cdf = lambda x: np.where(x < pk, (x - lo) ** 2 / ((hi - lo) * (pk - lo)),
+                             1 - (hi - x) ** 2 / ((hi - lo) * (hi - pk)))
+    w = I.water_cube_2mev()
+    K, R = 8, 120_000
+    src = I.Source(I.PHOTON, I.triangular_spectrum(lo, pk, hi), [I.parallel_beam_z(w.phantom, 5.0)],
+                   spectrum_strata=K)
+    e = oracle.sample_source(src, w.phantom, n=R, hist0=777)[:, 0]
+    edges = lo + (hi - lo) * np.arange(K + 1) / K
+    F = cdf(edges)
+    k_of = np.clip(np.searchsorted(edges, e, side="right") - 1, 0, K - 1)
+    assert np.all(np.diff(k_of) >= 0)                         # interval by interval
+    counts = np.bincount(k_of, minlength=K)
+    expect = np.diff(np.floor(R * F + 0.5))
+    assert np.all(np.abs(counts - expect) <= 1), (counts, expect)
+    for k in range(K):
+        ek = np.sort(e[k_of == k])
+        cond = lambda x, k=k: (cdf(x) - F[k]) / (F[k + 1] - F[k])
+        assert sst.kstest(ek, cond).pvalue > 1e-4, k
+    assert sst.kstest(e, cdf).pvalue > 0.05   # stratified: closer than random sampling
+
+
 def _metro_case(n_chains_steps):
     ph = I.homogeneous((40, 40, 20), (0.5, 0.5, 0.5), I.ID_WATER, 1.0)
     rng = np.random.default_rng(4)
