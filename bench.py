@@ -120,21 +120,22 @@ def batched_form(G, I, n_jobs, opts=None):
 
 
 def source_modes(G, I, w, args):
-    """The two beamlet samplers of section 2.3.1 on the CT plan: a job to the
-    target uncertainty with each, and the paper's Fig. 2 error e(N) =
+    """The source modes of section 2.3 on the CT plan: the two beamlet samplers
+    (search, Metropolis chains) and the energy intervals of the spectrum; a job
+    to the target uncertainty with each, and the paper's Fig. 2 error e(N) =
     |p_f - p_f*|_2 of the beamlet frequencies of one beam after N histories."""
     import dataclasses
     ctx = G.Context(0, opts=args.opts, materials=I.MATERIALS)
     ph = ctx.phantom(w.phantom)
     out = {"workload": "CT 256x256x128 IMRT-9 to the target; Fig. 2 metric on beam 0 (40x40 beamlets)"}
-    for k, name in ((0, "search"), (1, "metropolis")):
-        src = dataclasses.replace(w.source, beamlet_sampler=k)
+    for k, strata, name in ((0, 0, "search"), (1, 0, "metropolis"), (0, 16, "search_16_energy_intervals")):
+        src = dataclasses.replace(w.source, beamlet_sampler=k, spectrum_strata=strata)
         s = ctx.source(src)
         r = ctx.run(ph, s, seed=7, n_hist=args.n0, target_unc=args.target,
                     stat_min_density=args.min_density, want_dose=False)
         s.close()
         b0 = w.source.beams[0]
-        one = I.Source(w.source.particle, w.source.spectrum, [b0], beamlet_sampler=k)
+        one = I.Source(w.source.particle, w.source.spectrum, [b0], beamlet_sampler=k, spectrum_strata=strata)
         s1 = ctx.source(one)
         f = np.asarray(b0.intensity, dtype=np.float64).ravel()
         p_star = f / f.sum()
@@ -308,7 +309,7 @@ def main():
                     help="length of the served request stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2.0, help="requests per second")
     ap.add_argument("--source-modes", type=int, default=1,
-                    help="1: also run the CT job with Metropolis beamlet sampling (section 2.3.1)")
+                    help="1: also run the CT job with the other source modes (section 2.3)")
     ap.add_argument("--min-density", type=float, default=0.1,
                     help="voxels below this density (the air around the patient) are left out "
                          "of D_max and of the uncertainty statistic")
