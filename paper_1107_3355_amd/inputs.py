@@ -225,6 +225,42 @@ def gantry_beam(ph: Phantom, gantry_deg: float, nb: int = 40, bsize: float = 0.5
                 bw=bsize, bh=bsize, intensity=intensity)
 
 
+def linac_beam(ph: Phantom, gantry_deg: float, collimator_deg: float = 0.0, couch_deg: float = 0.0,
+               nb: int = 40, bsize: float = 0.5, sad: float = 100.0,
+               intensity: Optional[np.ndarray] = None) -> Beam:
+    """Beam of a linac with gantry, collimator and couch angles (section 2.3:
+    the plan's geometry rotates the gantry, the collimator and the couch).
+    Phantom frame: z along the couch, y vertical (gantry 0 irradiates along -y),
+    isocentre at the phantom centre.  The gantry turns the beam about z (as
+    gantry_beam); the collimator turns the fluence map about the central axis
+    by collimator_deg (from e1 towards e2 = dir x e1); the couch turns the
+    patient about the vertical y axis by couch_deg, i.e. the beam by
+    -couch_deg.  Angles 0, 0 give gantry_beam's beam."""
+    b = gantry_beam(ph, gantry_deg, nb=nb, bsize=bsize, sad=sad, intensity=intensity)
+    d = np.array(b.dir, dtype=np.float64)
+    e1 = np.array(b.e1, dtype=np.float64)
+    e2 = np.cross(d, e1)
+    c = math.radians(collimator_deg)
+    e1 = math.cos(c) * e1 + math.sin(c) * e2
+    t = math.radians(-couch_deg)
+    ry = np.array([[math.cos(t), 0.0, math.sin(t)], [0.0, 1.0, 0.0], [-math.sin(t), 0.0, math.cos(t)]])
+    iso = np.array(b.iso, dtype=np.float64)
+    return Beam(iso=tuple(iso), dir=tuple(ry @ d), e1=tuple(ry @ e1), sad=sad, nbx=nb, nby=nb,
+                bw=bsize, bh=bsize, intensity=intensity)
+
+
+def noncoplanar_plan(ph: Phantom, nb: int = 40, seed: int = 1009) -> List[Beam]:
+    """Eight non-coplanar fields (the paper's head-and-neck IMRT plan had eight,
+    section 3.2): gantry, couch and collimator angles below, intensities
+    uniform in [0, 1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fields = [(0, 0, 0), (45, 20, 15), (90, 40, 30), (135, -20, 45), (180, 0, 90), (225, 30, 10),
+              (270, -40, 60), (315, 10, 5)]
+    return [linac_beam(ph, g, coll, couch, nb=nb,
+                       intensity=rng.uniform(0.0, 1.0, size=(nb, nb)).astype(np.float32))
+            for g, couch, coll in fields]
+
+
 def imrt_plan(ph: Phantom, n_beams: int = 9, nb: int = 40, seed: int = 1003) -> List[Beam]:
     rng = np.random.Generator(np.random.PCG64(seed + 7))
     beams = []

@@ -163,6 +163,15 @@ def test_ct_metropolis_source(gctx):
     _compare_stat(gctx, ph, src, 300_000, name="ct48_imrt_metropolis", min_rho=0.1, max_sigma=3.0)
 
 
+def test_ct_noncoplanar_plan(gctx):
+    """Eight non-coplanar fields with collimator and couch rotations on the
+    small CT: lockstep with the oracle and statistically equal dose."""
+    ph = I.ct_phantom((48, 48, 24), (1.0, 1.0, 1.25))
+    src = I.Source(I.PHOTON, I.triangular_spectrum(), I.noncoplanar_plan(ph, nb=10))
+    _compare_lockstep(gctx, ph, src, 3_000, name="ct48_noncoplanar", min_frac=0.9, hist0=5_000)
+    _compare_stat(gctx, ph, src, 300_000, name="ct48_noncoplanar", min_rho=0.1)
+
+
 def test_stratified_spectrum_transport(gctx):
     """Energy intervals of the spectrum (section 2.3.2) on the 100^3 slab: one
     round (the source sampler's) in lockstep with the oracle; ten rounds

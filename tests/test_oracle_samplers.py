@@ -212,6 +212,56 @@ def test_metropolis_transition_rate():
     assert abs(moves - expect) < 5 * math.sqrt(expect * (1 - expect) / trials) + 2e-3, (moves, expect)
 
 
+def test_linac_angles():
+    """Gantry, collimator and couch rotations of a beam: angles 0 reduce to the
+    coplanar gantry beam, the frame stays orthonormal, the collimator turns e1
+    towards e2 about the axis, the couch turns the axis about the vertical y
+    without changing its vertical part."""
+    ph = I.homogeneous((40, 40, 40), (0.5, 0.5, 0.5), I.ID_WATER, 1.0)
+    for g in (0.0, 37.0, 200.0):
+        a, b = I.linac_beam(ph, g), I.gantry_beam(ph, g)
+        assert np.allclose(a.dir, b.dir, atol=1e-15) and np.allclose(a.e1, b.e1, atol=1e-15)
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        g, c, t = rng.uniform(0, 360, 3)
+        bm = I.linac_beam(ph, g, c, t)
+        d, e1 = np.array(bm.dir), np.array(bm.e1)
+        assert abs(d @ d - 1) < 1e-12 and abs(e1 @ e1 - 1) < 1e-12 and abs(d @ e1) < 1e-12
+        b0 = I.linac_beam(ph, g)
+        d0 = np.array(b0.dir)
+        assert abs(d[1] - d0[1]) < 1e-12                     # the couch keeps the vertical part
+        # the beam's azimuth in the horizontal x-z plane, atan2(z, x), grows by
+        # the couch angle (the patient turning the other way)
+        ang = math.degrees(math.atan2(d[2], d[0]) - math.atan2(d0[2], d0[0]))
+        if np.hypot(d0[0], d0[2]) > 1e-6:
+            assert abs((ang - t + 180) % 360 - 180) < 1e-9
+    b0, b90 = I.linac_beam(ph, 30.0), I.linac_beam(ph, 30.0, collimator_deg=90.0)
+    assert np.allclose(np.array(b90.e1), np.cross(b0.dir, b0.e1), atol=1e-12)
+
+
+def test_noncoplanar_beam_geometry():
+    """Primaries of a non-coplanar point-source field (gantry 135, couch -20,
+    collimator 45): every ray comes from the source point iso - SAD dir, and at
+    the isocentre plane it lies inside the collimated 20x20 cm field."""
+    ph = I.homogeneous((60, 60, 60), (0.5, 0.5, 0.5), I.ID_WATER, 1.0)
+    bm = I.linac_beam(ph, 135.0, 45.0, -20.0, nb=40, bsize=0.5)
+    src = I.Source(I.PHOTON, I.mono(1.0), [bm])
+    out = oracle.sample_source(src, ph, n=20_000)
+    inside = out[:, 1] >= 0
+    x, d = out[inside, 2:5], out[inside, 5:8]
+    assert inside.mean() > 0.99
+    iso, ax = np.array(bm.iso), np.array(bm.dir)
+    s0 = iso - bm.sad * ax
+    cr = np.cross(x - s0, d)
+    assert np.abs(cr).max() < 1e-8
+    t = ((iso - s0) @ ax) / (d @ ax)                       # reach the isocentre plane
+    q = s0 + t[:, None] * d - iso
+    e1 = np.array(bm.e1)
+    e2 = np.cross(ax, e1)
+    assert np.abs(q @ e1).max() <= 10.0 + 1e-9 and np.abs(q @ e2).max() <= 10.0 + 1e-9
+    assert np.abs(q @ e1).max() > 9.9 and np.abs(q @ e2).max() > 9.9
+
+
 def test_point_source_geometry():
     ph = I.homogeneous((20, 20, 20), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
     b = I.point_beam_z(ph, field=10.0, ssd=90.0, sad=100.0)
