@@ -119,6 +119,15 @@ typedef struct {
      * history's energy follows the spectrum (inverse CDF at F_k + u (F_{k+1} -
      * F_k)). */
     int spectrum_strata;
+    /* the open source interface (section 2.3.3): n_phase_space > 0 records of
+     * 7 floats each, x, y, z (cm, phantom frame), u, v, w (unit vector, norm
+     * within 1e-5 of 1), E (MeV, in (0, 30]), copied at creation.  History h
+     * starts as record h mod n_phase_space: inside the phantom where it is,
+     * outside at the point where its forward ray enters the phantom (or it
+     * escapes); no random draws are spent on it.  Spectrum, beams and the two
+     * modes above are then unused (n_beams may be 0). */
+    uint64_t n_phase_space;
+    const float* phase_space;
 } gdpm_source_desc;
 
 #define GDPM_METRO_CHAINS 16384

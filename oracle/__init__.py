@@ -43,7 +43,8 @@ class Source(C.Structure):
     _fields_ = [("particle", C.c_int), ("spec_kind", C.c_int), ("spec_n", C.c_int),
                 ("spec_e", C.POINTER(C.c_double)), ("spec_p", C.POINTER(C.c_double)),
                 ("e_mono", C.c_double), ("n_beams", C.c_int), ("beams", C.POINTER(Beam)),
-                ("beamlet_sampler", C.c_int), ("spectrum_strata", C.c_int)]
+                ("beamlet_sampler", C.c_int), ("spectrum_strata", C.c_int),
+                ("n_phsp", C.c_uint64), ("phsp", C.POINTER(C.c_float))]
 
 
 class Params(C.Structure):
@@ -138,6 +139,11 @@ def _source(src, keep):
     sp = src.spectrum
     s = Source(src.particle, sp.kind, 0, None, None, sp.e_mono, len(src.beams), beams,
                getattr(src, "beamlet_sampler", 0), getattr(src, "spectrum_strata", 0))
+    ps = getattr(src, "phase_space", None)
+    if ps is not None:
+        ps = keep.arr(ps, np.float32).reshape(-1, 7)
+        s.n_phsp = len(ps)
+        s.phsp = ps.ctypes.data_as(C.POINTER(C.c_float))
     if sp.kind == 1:
         e = keep.arr(sp.e, np.float64)
         p = keep.arr(sp.p, np.float64)

@@ -903,12 +903,55 @@ static int metropolis_chains(ctx_t* c, uint64_t h0, uint64_t n) {
     return 0;
 }
 
+/* section 2.3.3: history h starts as phase-space record h mod n_phsp, inside
+ * the phantom where it is, outside at the point where its forward ray enters
+ * the phantom (none: the particle escapes); the record number is reported in
+ * place of a beamlet */
+static int phase_space_particle(const ctx_t* c, uint64_t h, particle_t* p, int* beamlet) {
+    const orc_source* s = c->src;
+    uint64_t k = h % s->n_phsp;
+    const float* r = s->phsp + 7 * k;
+    *beamlet = (int)k;
+    p->e = r[6];
+    double o[3] = {r[0], r[1], r[2]};
+    for (int i = 0; i < 3; ++i) p->d[i] = r[3 + i];
+    int inside = 1;
+    for (int i = 0; i < 3; ++i)
+        if (!(o[i] >= 0.0 && o[i] < c->len[i])) inside = 0;
+    if (inside) {
+        for (int i = 0; i < 3; ++i) p->x[i] = o[i];
+        vox_of(c, p->x, p->iv);
+        return 1;
+    }
+    double tmin = 0.0, tmax = INFINITY;
+    int ax = -1;
+    for (int i = 0; i < 3; ++i) {
+        if (p->d[i] != 0.0) {
+            double ta = (0.0 - o[i]) / p->d[i], tb = (c->len[i] - o[i]) / p->d[i];
+            double tn = fmin(ta, tb), tf = fmax(ta, tb);
+            if (tn > tmin) {
+                tmin = tn;
+                ax = i;
+            }
+            if (tf < tmax) tmax = tf;
+        } else if (o[i] < 0.0 || o[i] > c->len[i]) {
+            return 0;
+        }
+    }
+    if (!(tmax > tmin)) return 0;
+    for (int i = 0; i < 3; ++i) p->x[i] = o[i] + tmin * p->d[i];
+    if (ax >= 0) p->x[ax] = p->d[ax] > 0.0 ? 0.0 : c->len[ax];
+    vox_of(c, p->x, p->iv);
+    return 1;
+}
+
 /* sample the primary of history h; returns 1 if it enters the phantom */
 static int source_particle(const ctx_t* c, uint64_t h, particle_t* p, int* beamlet) {
     const orc_source* s = c->src;
     memset(p, 0, sizeof *p);
     p->s = stream_make(c->prm.seed, c->prm.job_id, h, 0);
     p->type = s->particle == 0 ? 0 : 1;
+    if (s->n_phsp) return phase_space_particle(c, h, p, beamlet);
     p->e = c->strata_F ? stratified_energy(c, h, draw(&p->s)) : spectrum_energy(c, draw(&p->s));
     int gi;
     if (c->metro_bl) {
@@ -1022,12 +1065,23 @@ static int validate(const orc_material* mats, int n_mat, const orc_phantom* ph,
     size_t nv = (size_t)ph->nx * ph->ny * ph->nz;
     for (size_t v = 0; v < nv; ++v)
         if (ph->mat[v] >= n_mat || !(ph->rho[v] > 0.0f)) return 1;
-    if (src->n_beams < 1 || !src->beams) return 1;
-    if (src->beamlet_sampler != 0 && src->beamlet_sampler != 1) return 1;
-    if (src->spectrum_strata < 0 || src->spectrum_strata > 64) return 1;
-    if (src->spectrum_strata > 0 && src->spec_kind != 1) return 1;
-    if (src->spec_kind == 0 && !(src->e_mono > 0)) return 1;
-    if (src->spec_kind == 1 && (src->spec_n < 2 || !src->spec_e || !src->spec_p)) return 1;
+    if (src->n_phsp > 0) {
+        if (!src->phsp) return 1;
+        for (uint64_t k = 0; k < src->n_phsp; ++k) {
+            const float* r = src->phsp + 7 * k;
+            double nn = (double)r[3] * r[3] + (double)r[4] * r[4] + (double)r[5] * r[5];
+            if (!(r[6] > 0.0f) || !(fabs(nn - 1.0) < 1e-5) || !isfinite(r[0]) || !isfinite(r[1]) ||
+                !isfinite(r[2]))
+                return 1;
+        }
+    } else {
+        if (src->n_beams < 1 || !src->beams) return 1;
+        if (src->beamlet_sampler != 0 && src->beamlet_sampler != 1) return 1;
+        if (src->spectrum_strata < 0 || src->spectrum_strata > 64) return 1;
+        if (src->spectrum_strata > 0 && src->spec_kind != 1) return 1;
+        if (src->spec_kind == 0 && !(src->e_mono > 0)) return 1;
+        if (src->spec_kind == 1 && (src->spec_n < 2 || !src->spec_e || !src->spec_p)) return 1;
+    }
     if (prm->n_batches < 1 || prm->round_size < 1) return 1;
     if (src->particle == 1 && (prm->flags & ORC_KERMA)) return 1;
     return 0;
@@ -1076,8 +1130,9 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
             tot += f;
         }
     }
-    int bad = !(tot > 0.0);
-    if (!bad && src->beamlet_sampler == 1) bad = metropolis_chains(&c, prm->hist0, prm->n_hist);
+    int bad = !(tot > 0.0) && src->n_phsp == 0;
+    if (!bad && src->n_phsp == 0 && src->beamlet_sampler == 1)
+        bad = metropolis_chains(&c, prm->hist0, prm->n_hist);
     for (int i = 0; i < c.nf; ++i) c.cdf[i] /= tot;
     c.cdf[c.nf] = 1.0;
     if (src->spec_kind == 1) {
@@ -1317,7 +1372,7 @@ int orc_sample_source(const orc_source* src, const orc_phantom* ph, uint64_t see
             tot += f;
         }
     }
-    if (src->beamlet_sampler == 1 && metropolis_chains(&c, hist0, (uint64_t)n)) {
+    if (src->n_phsp == 0 && src->beamlet_sampler == 1 && metropolis_chains(&c, hist0, (uint64_t)n)) {
         free(c.cdf); free(c.f); free(c.beam_of); free(c.beam_off);
         return 1;
     }

@@ -135,6 +135,8 @@ struct SourceDev {
     const float* f;            // [nf] intensities (negative ones as 0)
     int strata;                // K > 0: energy intervals of a round (section 2.3.2)
     const double* strata_F;    // [K + 1] spectrum CDF at the interval edges
+    const float* phsp;         // [n_phsp][7] phase-space records, or null (section 2.3.3)
+    unsigned long long n_phsp;
 };
 
 constexpr uint32_t kMetroChains = 16384;   // Metropolis chains of a job

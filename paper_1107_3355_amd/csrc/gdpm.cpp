@@ -255,6 +255,8 @@ struct gdpm_source_s {
     DevBuf spec_e, spec_p, spec_c, cdf, guide, beams, beam_of;
     DevBuf fl, nz;               // intensities and nonzero beamlets (Metropolis chains)
     DevBuf strata_F;             // spectrum CDF at the energy-interval edges
+    DevBuf phsp;                 // phase-space records (the open source interface)
+    unsigned long long n_phsp = 0;
     int nf, n_guide, n_beams;
     int metro = 0, n_nz = 0, strata = 0;
     SourceDev view() const {
@@ -279,6 +281,8 @@ struct gdpm_source_s {
         s.f = fl.as<const float>();
         s.strata = strata;
         s.strata_F = strata_F.as<const double>();
+        s.phsp = phsp.as<const float>();
+        s.n_phsp = n_phsp;
         return s;
     }
 };
@@ -1374,6 +1378,37 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
     if (!ctx || !d || !out) return fail(GDPM_E_INVALID, "NULL argument");
     *out = nullptr;
     if (d->particle != 0 && d->particle != 1) return fail(GDPM_E_INVALID, "particle must be 0 or 1");
+    if (d->n_phase_space > 0) {
+        // the open source interface: a phase space replaces beams and spectrum
+        if (!d->phase_space) return fail(GDPM_E_INVALID, "phase_space is NULL");
+        if (d->n_phase_space > ((uint64_t)1 << 31)) return fail(GDPM_E_INVALID, "at most 2^31 phase-space records");
+        auto src = std::make_unique<gdpm_source_s>();
+        src->ctx = ctx;
+        src->particle = d->particle;
+        double emax = 0.0;
+        for (uint64_t k = 0; k < d->n_phase_space; ++k) {
+            const float* r = d->phase_space + 7 * k;
+            const double nn = (double)r[3] * r[3] + (double)r[4] * r[4] + (double)r[5] * r[5];
+            if (!(r[6] > 0.0f) || r[6] > kEmax || !(std::fabs(nn - 1.0) < 1e-5) || !std::isfinite(r[0]) ||
+                !std::isfinite(r[1]) || !std::isfinite(r[2]))
+                return fail(GDPM_E_INVALID, "phase-space record %llu: energy in (0, 30] MeV, unit direction, "
+                            "finite position", (unsigned long long)k);
+            emax = std::max(emax, (double)r[6]);
+        }
+        src->spec_kind = 0;
+        src->e_mono = 0.0f;
+        src->e_max = emax;
+        src->spec_n = 0;
+        src->nf = 0;
+        src->n_guide = 0;
+        src->n_beams = 0;
+        std::vector<float> recs(d->phase_space, d->phase_space + 7 * d->n_phase_space);
+        HIP_TRY(hipSetDevice(ctx->device));
+        HIP_TRY(upload(src->phsp, recs));
+        src->n_phsp = d->n_phase_space;
+        *out = src.release();
+        return GDPM_OK;
+    }
     if (d->n_beams < 1 || !d->beams) return fail(GDPM_E_INVALID, "need at least one beam");
     if (d->n_beams > 65535) return fail(GDPM_E_INVALID, "at most 65535 beams");
     if (d->beamlet_sampler != 0 && d->beamlet_sampler != 1)

@@ -366,11 +366,58 @@ GDPM_DEV float stratified_energy(const SourceDev& S, uint32_t i, uint32_t size, 
     return spectrum_energy(S, (float)(f0 + (double)u * (f1 - f0)));
 }
 
+// section 2.3.3: the history whose stream is r starts as phase-space record
+// h mod n: inside the phantom where it is, outside where its forward ray
+// enters (else it escapes); the record number stands in for the beamlet
+GDPM_DEV Primary phase_space_primary(const SourceDev& S, const Geom& G, const Rng& rg) {
+    const unsigned long long h = (unsigned long long)rg.hhi << 32 | rg.hlo;
+    const unsigned long long k = h % S.n_phsp;
+    const float* rec = S.phsp + 7 * k;
+    Primary p;
+    p.beamlet = (int)k;
+    p.e = rec[6];
+    p.u = rec[3];
+    p.v = rec[4];
+    p.w = rec[5];
+    const float o[3] = {rec[0], rec[1], rec[2]}, d[3] = {p.u, p.v, p.w}, L[3] = {G.lx, G.ly, G.lz};
+    p.x = o[0];
+    p.y = o[1];
+    p.z = o[2];
+    p.in = true;
+    if (o[0] >= 0.0f && o[0] < G.lx && o[1] >= 0.0f && o[1] < G.ly && o[2] >= 0.0f && o[2] < G.lz) return p;
+    float tmin = 0.0f, tmax = 3.0e38f;
+    int ax = -1;
+    bool miss = false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] != 0.0f) {
+            const float ta = (0.0f - o[i]) / d[i], tb = (L[i] - o[i]) / d[i];
+            const float tn = fminf(ta, tb), tf = fmaxf(ta, tb);
+            if (tn > tmin) {
+                tmin = tn;
+                ax = i;
+            }
+            tmax = fminf(tmax, tf);
+        } else if (o[i] < 0.0f || o[i] > L[i]) {
+            miss = true;
+        }
+    }
+    p.in = !miss && tmax > tmin;
+    p.x = o[0] + tmin * p.u;
+    p.y = o[1] + tmin * p.v;
+    p.z = o[2] + tmin * p.w;
+    if (ax == 0) p.x = p.u > 0.0f ? 0.0f : G.lx;
+    if (ax == 1) p.y = p.v > 0.0f ? 0.0f : G.ly;
+    if (ax == 2) p.z = p.w > 0.0f ? 0.0f : G.lz;
+    return p;
+}
+
 // the primary of the history whose stream is r; `chain` (Metropolis sources
 // only) holds the state of the history's chain and is advanced; rpos and
 // rsize (stratified spectra only) place the history in its round
 GDPM_DEV Primary make_primary(const SourceDev& S, const Geom& G, Rng& r, uint32_t k0, uint32_t k1,
                               uint32_t* chain = nullptr, uint32_t rpos = 0u, uint32_t rsize = 1u) {
+    if (S.n_phsp) return phase_space_primary(S, G, r);
     Primary p;
     const float ue = uniform(r, k0, k1);
     p.e = S.strata ? stratified_energy(S, rpos, rsize, ue) : spectrum_energy(S, ue);

@@ -53,7 +53,8 @@ class Beam(C.Structure):
 class SourceDesc(C.Structure):
     _fields_ = [("particle", C.c_int), ("spectrum", Spectrum), ("n_beams", C.c_int),
                 ("beams", C.POINTER(Beam)), ("beamlet_sampler", C.c_int),
-                ("spectrum_strata", C.c_int)]
+                ("spectrum_strata", C.c_int), ("n_phase_space", C.c_uint64),
+                ("phase_space", C.POINTER(C.c_float))]
 
 
 class RunParams(C.Structure):
@@ -217,6 +218,12 @@ class Source:
             spec.e_mev, spec.pdf = _dp(e), _dp(p)
         d = SourceDesc(src.particle, spec, len(src.beams), beams, getattr(src, "beamlet_sampler", 0),
                        getattr(src, "spectrum_strata", 0))
+        ps = getattr(src, "phase_space", None)
+        if ps is not None:
+            ps = np.ascontiguousarray(ps, dtype=np.float32).reshape(-1, 7)
+            keep.append(ps)
+            d.n_phase_space = len(ps)
+            d.phase_space = _fp(ps)
         self.handle = C.c_void_p()
         _check(lib().gdpm_source_create(ctx.handle, C.byref(d), C.byref(self.handle)))
 

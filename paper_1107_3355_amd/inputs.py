@@ -96,6 +96,9 @@ class Source:
     beams: List[Beam] = field(default_factory=list)
     beamlet_sampler: int = 0  # 0 cumulative-probability search, 1 Metropolis chains (Algorithm A1)
     spectrum_strata: int = 0  # 0 plain spectrum sampling, K > 0 energy intervals (section 2.3.2)
+    # (n, 7) float32 records x, y, z, u, v, w, E: a phase space (section 2.3.3);
+    # history h starts as record h mod n, and beams and spectrum are unused
+    phase_space: Optional[np.ndarray] = None
 
 
 PHOTON, ELECTRON = 0, 1
@@ -259,6 +262,40 @@ def noncoplanar_plan(ph: Phantom, nb: int = 40, seed: int = 1009) -> List[Beam]:
     return [linac_beam(ph, g, coll, couch, nb=nb,
                        intensity=rng.uniform(0.0, 1.0, size=(nb, nb)).astype(np.float32))
             for g, couch, coll in fields]
+
+
+def point_phase_space(ph: Phantom, n: int, seed: int, sad: float = 100.0, field: float = 10.0,
+                      spectrum: Optional[Spectrum] = None, inside_frac: float = 0.0) -> np.ndarray:
+    """Synthetic phase space (section 2.3.3 stands in for a linac's): n records
+    of a point source SAD cm above the phantom centre (along -y, gantry 0),
+    directions uniform over a square field of `field` cm at the isocentre,
+    energies from `spectrum` (default 6 MV-like triangular) by numpy's PCG64;
+    records scored on a plane 5 cm above the phantom, plus a fraction of
+    records placed inside the phantom on the same rays.  float32, unit
+    directions."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lx, ly, lz = ph.extent
+    iso = np.array([lx / 2, ly / 2, lz / 2])
+    src = iso + np.array([0.0, sad, 0.0])
+    a = rng.uniform(-field / 2, field / 2, size=(n, 2))
+    tgt = iso[None, :] + np.stack([a[:, 0], np.zeros(n), a[:, 1]], axis=1)
+    d = tgt - src
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    t = (src[1] - (ly + 5.0)) / -d[:, 1]            # the scoring plane y = ly + 5
+    inside = rng.random(n) < inside_frac
+    t = np.where(inside, (src[1] - ly / 2) / -d[:, 1], t)
+    pos = src[None, :] + t[:, None] * d
+    sp = spectrum or triangular_spectrum()
+    if sp.kind == 0:
+        e = np.full(n, sp.e_mono)
+    else:   # inverse CDF on a fine grid of the piecewise-linear pdf
+        grid = np.linspace(sp.e[0], sp.e[-1], 4097)
+        pg = np.interp(grid, sp.e, sp.p)
+        cg = np.concatenate([[0.0], np.cumsum(0.5 * (pg[1:] + pg[:-1]) * np.diff(grid))])
+        e = np.interp(rng.random(n) * cg[-1], cg, grid)
+    out = np.concatenate([pos, d, e[:, None]], axis=1).astype(np.float32)
+    out[:, 3:6] /= np.linalg.norm(out[:, 3:6].astype(np.float64), axis=1)[:, None].astype(np.float32)
+    return out
 
 
 def imrt_plan(ph: Phantom, n_beams: int = 9, nb: int = 40, seed: int = 1003) -> List[Beam]:

@@ -208,3 +208,25 @@ def test_stratified_source_lockstep(gctx):
     rel = np.abs(g[:, 0] / o[:, 0] - 1)
     assert np.mean(rel < 2e-6) > 0.999 and rel.max() < 1e-4
     assert np.all(np.diff(ko) >= 0)
+
+
+def test_phase_space_source_lockstep(gctx):
+    """Phase-space primaries (section 2.3.3) on the device against the oracle:
+    the same record per history, the same entry points (single precision) and
+    the same escapes, over more histories than records."""
+    w = I.ct_imrt()
+    ps = I.point_phase_space(w.phantom, 30_000, seed=8, inside_frac=0.2)
+    ps[:50, 3:6] *= -1.0                         # a few rays that miss the phantom
+    src = I.Source(I.PHOTON, I.mono(1.0), [], phase_space=ps)
+    p = gctx.phantom(w.phantom)
+    s = gctx.source(src)
+    n = 70_001
+    g = gctx.sample_source(p, s, n=n, hist0=123)
+    o = oracle.sample_source(src, w.phantom, n=n, hist0=123)
+    p.close()
+    s.close()
+    assert np.array_equal(g[:, 1], o[:, 1].astype(np.float32))
+    inside = o[:, 1] >= 0
+    assert 0.9 < inside.mean() < 1.0
+    np.testing.assert_allclose(g[inside, 2:5], o[inside, 2:5], atol=2e-4)
+    np.testing.assert_array_equal(g[:, 0], o[:, 0].astype(np.float32))

@@ -172,6 +172,18 @@ def test_ct_noncoplanar_plan(gctx):
     _compare_stat(gctx, ph, src, 300_000, name="ct48_noncoplanar", min_rho=0.1)
 
 
+def test_phase_space_transport(gctx):
+    """A phase-space source (section 2.3.3) on the 100^3 slab: lockstep with the
+    oracle, and statistically equal dose on the coarse slab."""
+    w = I.slab_photon()
+    src = I.Source(I.PHOTON, I.mono(1.0), [], phase_space=I.point_phase_space(w.phantom, 20_000, seed=9,
+                                                                             inside_frac=0.1))
+    _compare_lockstep(gctx, w.phantom, src, 4_003, name="slab100_phase_space", min_frac=0.9)
+    w2 = I.slab_photon(n=50, d=0.6)
+    src2 = I.Source(I.PHOTON, I.mono(1.0), [], phase_space=I.point_phase_space(w2.phantom, 50_000, seed=9))
+    _compare_stat(gctx, w2.phantom, src2, 300_000, name="slab50_phase_space")
+
+
 def test_stratified_spectrum_transport(gctx):
     """Energy intervals of the spectrum (section 2.3.2) on the 100^3 slab: one
     round (the source sampler's) in lockstep with the oracle; ten rounds

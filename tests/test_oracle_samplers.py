@@ -262,6 +262,59 @@ def test_noncoplanar_beam_geometry():
     assert np.abs(q @ e1).max() > 9.9 and np.abs(q @ e2).max() > 9.9
 
 
+def test_phase_space_geometry():
+    """Section 2.3.3, a phase space as the source: history h starts as record
+    h mod n; a record inside the phantom starts where it is, one outside on the
+    phantom face its forward ray enters, one whose ray misses escapes."""
+    w = I.water_cube_2mev()
+    lx, ly, lz = w.phantom.extent
+    ps = I.point_phase_space(w.phantom, 500, seed=6, inside_frac=0.3)
+    away = ps[:3].copy()
+    away[:, 3:6] *= -1.0                       # three records pointing away from the phantom
+    away[:, 1] = ly + 5.0
+    ps = np.concatenate([ps, away])
+    n = len(ps)
+    src = I.Source(I.PHOTON, I.mono(1.0), [], phase_space=ps)
+    o = oracle.sample_source(src, w.phantom, n=2 * n, hist0=0)
+    assert np.array_equal(o[:n], o[n:], equal_nan=True)             # cycles through the records
+    rec = ps.astype(np.float64)
+    idx = o[:n, 1]
+    assert np.all(idx[:500] == np.arange(500)) and np.all(idx[500:] == -1)
+    x, d = o[:500, 2:5], o[:500, 5:8]
+    np.testing.assert_allclose(d, rec[:500, 3:6], rtol=0, atol=0)
+    np.testing.assert_allclose(o[:500, 0], rec[:500, 6], rtol=0, atol=0)
+    inside = (rec[:500, 1] < ly)
+    np.testing.assert_allclose(x[inside], rec[:500][inside, :3], atol=0)
+    out = ~inside
+    assert out.sum() > 100 and inside.sum() > 100
+    np.testing.assert_allclose(x[out, 1], ly)                        # the top face
+    t = (ly - rec[:500][out, 1]) / rec[:500][out, 4]
+    np.testing.assert_allclose(x[out], rec[:500][out, :3] + t[:, None] * rec[:500][out, 3:6], atol=1e-9)
+
+
+def test_phase_space_reproduces_its_beam():
+    """A phase space recorded from a beam (the primaries the beam source gives,
+    at their entry points) yields the beam's dose: statistically equal per
+    voxel, and the same incident energy."""
+    w = I.water_cube_2mev()
+    ph = w.phantom
+    n = 60_000
+    prim = oracle.sample_source(w.source, ph, n=n, seed=5)
+    assert np.all(prim[:, 1] >= 0)
+    ps = np.concatenate([prim[:, 2:5], prim[:, 5:8], prim[:, :1]], axis=1).astype(np.float32)
+    ps[:, 3:6] /= np.linalg.norm(ps[:, 3:6].astype(np.float64), axis=1)[:, None].astype(np.float32)
+    src = I.Source(I.PHOTON, I.mono(1.0), [], phase_space=ps)
+    a = oracle.run(I.MATERIALS, ph, w.source, seed=1, n_hist=n, n_batches=10, n_threads=8)
+    b = oracle.run(I.MATERIALS, ph, src, seed=2, n_hist=n, n_batches=10, n_threads=8)
+    assert abs(b["e_in"] / a["e_in"] - 1) < 1e-6
+    for r in (a, b):
+        assert abs(r["e_dep"] + r["e_esc"] - r["e_in"]) < 1e-9 * r["e_in"]
+    dmax = a["dose"].max()
+    m = (a["dose"] > 0.1 * dmax) & (b["dose"] > 0.1 * dmax)
+    t = (a["dose"][m] - b["dose"][m]) / np.sqrt(a["sigma"][m] ** 2 + b["sigma"][m] ** 2)
+    assert m.sum() > 200 and np.mean(np.abs(t) < 2.262) > 0.93
+
+
 def test_point_source_geometry():
     ph = I.homogeneous((20, 20, 20), (1.0, 1.0, 1.0), I.ID_WATER, 1.0)
     b = I.point_beam_z(ph, field=10.0, ssd=90.0, sad=100.0)
