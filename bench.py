@@ -148,6 +148,21 @@ def source_modes(G, I, w, args):
         out[name] = {"histories_per_s": r["histories"] / r["t_total_s"], "seconds": r["t_total_s"],
                      "histories": r["histories"], "unc": r["unc"], "fig2_error": errs}
         log(f"source modes: {name}: {r['histories'] / r['t_total_s']:.4g} hist/s, e(N) {errs}")
+    # the open source interface: a phase space of 1e6 primaries recorded from the
+    # plan's beams at their entry points, cycled through by the job's histories
+    s0 = ctx.source(w.source)
+    prim = ctx.sample_source(ph, s0, seed=13, n=1_000_000)
+    s0.close()
+    prim = prim[prim[:, 1] >= 0]
+    rec = np.concatenate([prim[:, 2:5], prim[:, 5:8], prim[:, :1]], axis=1).astype(np.float32)
+    rec[:, 3:6] /= np.linalg.norm(rec[:, 3:6].astype(np.float64), axis=1)[:, None].astype(np.float32)
+    s1 = ctx.source(I.Source(w.source.particle, w.source.spectrum, [], phase_space=rec))
+    r = ctx.run(ph, s1, seed=7, n_hist=args.n0, target_unc=args.target, stat_min_density=args.min_density,
+                want_dose=False)
+    s1.close()
+    out["phase_space_1e6_records"] = {"histories_per_s": r["histories"] / r["t_total_s"], "seconds": r["t_total_s"],
+                                      "histories": r["histories"], "unc": r["unc"]}
+    log(f"source modes: phase space: {r['histories'] / r['t_total_s']:.4g} hist/s")
     ph.close()
     ctx.close()
     return out
