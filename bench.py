@@ -330,9 +330,9 @@ def main():
                          "of D_max and of the uncertainty statistic")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (histories would be "
-              "sharded across GPUs with one FP64 all-reduce of the tallies; see the design "
-              "notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (histories would be "
+              "sharded across GPUs by history id, with one FP64 all-reduce of the batch tallies "
+              "at the end of a job). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     from paper_1107_3355_amd import gdpm as G

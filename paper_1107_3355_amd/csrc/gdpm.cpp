@@ -526,7 +526,7 @@ void Engine::tune_account() {
     const double dt = t - tune.last_time;
     tune.last_events = ev;
     tune.last_time = t;
-    if (dev < 4000000ull || dt <= 0.0) return;   // too little work to judge
+    if (dev < 4000000ull || dt <= 0.0) return;   // too little work to score
     tune.score[tune.cur] += (double)dev / dt;
     tune.samples[tune.cur]++;
     const int n = (int)tune.cand.size();
