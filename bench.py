@@ -39,6 +39,9 @@ BYTES_PER_VOXEL_LOOKUP = 8
 BYTES_PER_RECORD = 64
 BYTES_PER_DEPOSIT = 8
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+# vector-ALU lane instructions: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
+# instruction occupies a SIMD for 4 cycles; unpacked FP32 = 78.6 TFLOP/s of FMA)
+PEAK_VALU_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1107_3355_amd", "csrc", "transport.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_ct256x256x128_imrt9.txt")
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_ct256x256x128_imrt9.txt")
@@ -274,6 +277,14 @@ def measured_traffic(kernel):
     return float(v) if v else None
 
 
+def measured_lane_valu_per_event(kernel):
+    """Active-lane VALU instructions per flight (k_photon) or step (k_electron)
+    from the committed counter summary, or None."""
+    kv = profiled_values(COUNTER_SUMMARY)
+    v = kv.get(f"{kernel}_lane_valu_per_event") if kv else None
+    return float(v) if v else None
+
+
 def measured_counters(kernel):
     """VALU busy and lane use, occupancy, L2 hit rate and atomics per second of
     `kernel` from the committed counter summary, or None."""
@@ -385,13 +396,20 @@ def main():
               + BYTES_PER_DEPOSIT * sum(r["deposits"][k] for r in runs))
     avg = t_k / max(launches, 1)
     achieved = nbytes / max(launches, 1) / avg / 1e9
-    roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-            "traffic": measured_traffic(name),
-            "counters": measured_counters(name),
-            "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
-            "avg_launch_ms": avg * 1e3, "launches": launches,
-            "share_of_kernel_time": t_k / max(te + tp, 1e-30)}
+    hbm = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": achieved / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": nbytes / max(launches, 1)}
+    roof = dict(hbm, kernel=name, traffic=measured_traffic(name), counters=measured_counters(name),
+                avg_launch_ms=avg * 1e3, launches=launches, share_of_kernel_time=t_k / max(te + tp, 1e-30))
+    # The transport kernels are bound by vector-ALU issue (divergent scalar
+    # FP32 work), not by HBM: priced as the active-lane VALU instructions one
+    # transport event costs (from the committed counter profile of this kernel
+    # source) times the launch's events, against the chip's lane-instruction rate.
+    per_event = measured_lane_valu_per_event(name)
+    if per_event:
+        alu = per_event * lookups / max(launches, 1) / avg / 1e12
+        roof.update(bound="alu", achieved=alu, peak=PEAK_VALU_TLANE, unit="T lane-instructions/s",
+                    frac=alu / PEAK_VALU_TLANE, lane_valu_per_event=per_event, hbm=hbm)
+        roof.pop("algorithmic_bytes_per_launch")
     # the kernel's FP64 tally additions per second against the measured rate of
     # scattered FP64 atomics into an array of one CT tally slot (and a small one)
     peak = ctx.atomic_rate(8 * w.phantom.nvox)
