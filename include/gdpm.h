@@ -8,7 +8,10 @@
  *     properties and cross-section data (section 2.2.1);
  *   - a source with an energy spectrum (section 2.3.2), fluence maps grouped
  *     over all beam angles into beamlets of intensity f_I (section 2.3.1) and
- *     the linac gantry geometry (section 2.3);
+ *     the linac geometry (gantry, collimator and couch rotations: any beam
+ *     axis, section 2.3), sampled by search or by Metropolis chains (Algorithm
+ *     A1) and optionally by energy intervals (section 2.3.2); or a phase space
+ *     of primaries (the open source interface, section 2.3.3);
  *   - a number of histories split evenly into N_b batches (section 2.2.1),
  *     or an uncertainty target on the mean of sigma/D_max over voxels above
  *     half the maximum dose (section 3.1);
