@@ -72,6 +72,41 @@ def test_batch_equals_solo(gctx):
             assert r["rounds"] > 10   # more than one super-round
 
 
+def test_batch_source_modes_equal_solo(gctx):
+    """The source modes in a shared batch: Metropolis chains (run to a target
+    over several super-rounds, so the chains carry on across rounds), energy
+    intervals, a phase space and a plain job side by side; each job's dose
+    equals its dose alone (the chain state is the job's own, the interval of a
+    history depends on its place in its own round)."""
+    ph = I.ellipsoid_phantom(20, 0.5, seed=77)
+    plan = I.imrt_plan(ph, n_beams=5, nb=6, seed=78)
+    jobs = [
+        ("metropolis", I.Source(I.PHOTON, I.triangular_spectrum(), plan, beamlet_sampler=1),
+         dict(n_hist=20_000, target_unc=0.06, max_histories=4_000_000)),
+        ("intervals", I.Source(I.PHOTON, I.triangular_spectrum(), plan, spectrum_strata=8),
+         dict(n_hist=35_001)),
+        ("phase_space", I.Source(I.PHOTON, I.mono(1.0), [], phase_space=I.point_phase_space(ph, 5_000, seed=79)),
+         dict(n_hist=30_000)),
+        ("plain", I.Source(I.ELECTRON, I.mono(9.0), [I.parallel_beam_z(ph, 6.0)]), dict(n_hist=8_000)),
+    ]
+    handles = []
+    for k, (name, src, kw) in enumerate(jobs):
+        handles.append((gctx.phantom(ph), gctx.source(src), dict(kw, seed=31 + k, job_id=k, n_batches=10)))
+    try:
+        res = gctx.run_batch(handles)
+        for (name, _, _), (p, s, kw), r in zip(jobs, handles, res):
+            a = gctx.run(p, s, **kw)
+            assert r["histories"] == a["histories"], name
+            assert balance(r) < 1e-6, name
+            same_dose(r["dose"], a["dose"], f"batch vs solo {name}")
+            if name == "metropolis":   # more than one super-round: chains carried across
+                assert r["status"] in ("GDPM_OK", "GDPM_E_NOT_CONVERGED") and r["rounds"] > 10
+    finally:
+        for p, s, _ in handles:
+            p.close()
+            s.close()
+
+
 def test_batch_graphs_equal_direct_launches():
     """The batched form with each iteration replayed from a recorded HIP graph
     (the default) against direct launches: same doses, same events."""
