@@ -1182,7 +1182,6 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             } else {
             rng_topup(rng, k0, k1);
             const uint64_t act0 = ballot(active);
-            wt.events += (uint32_t)__popcll(ballot(active && pm < 0 && !(e < ecut_g)));
 
             PendCharged qe;
             PendPhoton qg;
@@ -1197,6 +1196,14 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                 active = false;
                 pm = -1;
             }
+            // energy grid cell of the flight and of a waiting interaction (the
+            // energy is unchanged in between); computed on every lane, since the
+            // grid clamps any energy, 0 and non-finite ones included, into the table
+            int gi;
+            float gt;
+            grid(hlog2(e), T.pg_lo, T.pg_inv, T.pg_n, gi, gt);
+            const float mumax = lerp1(mtab, gi, gt);
+            wt.events += (uint32_t)__popcll(ballot(active && pm < 0 && !(e < ecut_g)));
             if (active && pm < 0) {
                 if (e < ecut_g) {
                     const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
@@ -1204,10 +1211,6 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                     tally_flush(tl, W, pb);
                     active = false;
                 } else {
-                    int gi;
-                    float gt;
-                    grid(hlog2(e), T.pg_lo, T.pg_inv, T.pg_n, gi, gt);
-                    const float mumax = lerp1(mtab, gi, gt);
                     const float s = neg_ln(uniform(rng, k0, k1)) * hrcp(mumax);
                     x = fmaf(s, u, x);
                     y = fmaf(s, v, y);
@@ -1238,15 +1241,12 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             // sampling code instead of a few running it each iteration.  A lane
             // waits where it is without drawing, so each particle's draws keep
             // their order; the voxel and the cross sections are recomputed from
-            // the same inputs.
+            // the same inputs (the energy grid cell from this iteration's lookup).
             {
                 const uint64_t br = ballot(pm >= 0);
                 if (br && (cs.done || (uint32_t)__popcll(br) >= kRealBatch || br == ballot(active))) {
                     if (pm >= 0) {
                         const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
-                        int gi;
-                        float gt;
-                        grid(hlog2(e), T.pg_lo, T.pg_inv, T.pg_n, gi, gt);
                         const float4 mu = lerp4(ptab + pm * T.pg_n, gi, gt);
                         const float r = uniform(rng, k0, k1) * mu.w;
                         if (r < mu.x) {
@@ -1494,22 +1494,21 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                     const float xi = uniform(rng, k0, k1);
                     const float s1 = xi * s, s2 = s - s1;
                     const float tend = hard ? fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * s), tfl), t0) : tfl;
-                    bool crossed = false;
+                    // first half: to the hinge, or to the voxel face if that comes
+                    // first.  Lanes that cross and lanes that reach the hinge share
+                    // one move, one range lookup and one deposit.
                     int ax;
                     float db = face_dist(W.G, x, y, z, u, v, w, ix, iy, iz, ax);
-                    float travelled = 0.0f;
-                    if (db < s1) {
-                        x = fmaf(db, u, x); y = fmaf(db, v, y); z = fmaf(db, w, z);
-                        const float t1 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * db), tend), e);
+                    bool crossed = db < s1;
+                    float travelled = db;
+                    {
+                        const float d1 = crossed ? db : s1;
+                        x = fmaf(d1, u, x); y = fmaf(d1, v, y); z = fmaf(d1, w, z);
+                        const float t1 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * d1), tend), e);
                         deposit(tl, W, pb, vv, e - t1);
                         e = t1;
-                        travelled = db;
-                        crossed = true;
-                    } else {
-                        x = fmaf(s1, u, x); y = fmaf(s1, v, y); z = fmaf(s1, w, z);
-                        const float t1 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * s1), tend), e);
-                        deposit(tl, W, pb, vv, e - t1);
-                        e = t1;
+                    }
+                    if (!crossed) {
                         // hinge: modified-Wentzel deflection for the whole step
                         if (!no_ms) {
                             const float tmid = 0.5f * (t0 + tend);
@@ -1518,19 +1517,17 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                             const float turns = uniform(rng, k0, k1);
                             rotate(u, v, w, 1.0f - 2.0f * mu, 2.0f * hsqrt(mu * (1.0f - mu)), turns);
                         }
+                        // second half: to the step end or the face; a lane that
+                        // reaches the end loses exactly the energy left above tend
                         db = face_dist(W.G, x, y, z, u, v, w, ix, iy, iz, ax);
-                        if (db < s2) {
-                            x = fmaf(db, u, x); y = fmaf(db, v, y); z = fmaf(db, w, z);
-                            const float t2 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * (s1 + db)), tend), e);
-                            deposit(tl, W, pb, vv, e - t2);
-                            e = t2;
-                            travelled = s1 + db;
-                            crossed = true;
-                        } else {
-                            x = fmaf(s2, u, x); y = fmaf(s2, v, y); z = fmaf(s2, w, z);
-                            deposit(tl, W, pb, vv, e - tend);
-                            e = tend;
-                        }
+                        crossed = db < s2;
+                        travelled = s1 + db;
+                        const float d2 = crossed ? db : s2;
+                        x = fmaf(d2, u, x); y = fmaf(d2, v, y); z = fmaf(d2, w, z);
+                        float t2 = tend;
+                        if (crossed) t2 = fminf(fmaxf(range_inv(T, rtab, rscale, m, q0.x - rho * travelled), tend), e);
+                        deposit(tl, W, pb, vv, e - t2);
+                        e = t2;
                     }
                     if (crossed) {
                         nh -= mus * travelled;
