@@ -428,6 +428,33 @@ def test_invalid_inputs_rejected(gctx):
     s.close()
 
 
+def test_maximum_dimensions_lockstep(gctx):
+    """A phantom at both limits of the packed voxel index (2048 voxels along x,
+    1024 along z): a 6 MeV beam along the diagonal of the x-z plane crosses it
+    corner to corner, so photons and their electrons reach ix = 2047 and
+    iz = 1023 and cross thousands of faces of 0.01 x 0.02 cm voxels.  Every
+    history's deposited and escaped energies match the oracle's on the same
+    streams (lockstep), and one voxel more along any axis is rejected.  Near
+    x = 20 cm a single-precision position is rounded by about 2e-6 cm, 2e-4 of
+    a voxel, so over about 95 voxel-limited steps per history one history in
+    ten takes some face decision differently from the FP64 oracle (0.90 of the
+    histories stay in lockstep; the floor is 0.85)."""
+    ph = I.homogeneous((2048, 1, 1024), (0.01, 2.0, 0.02), I.ID_WATER, 1.0)
+    lx, ly, lz = ph.extent
+    r = 1.0 / math.sqrt(2.0)
+    beam = I.Beam(iso=(lx / 2, ly / 2, lz / 2), dir=(r, 0.0, r), e1=(0.0, 1.0, 0.0), sad=0.0,
+                  nbx=1, nby=1, bw=1.0, bh=1.0)
+    src = I.Source(I.PHOTON, I.mono(6.0), [beam])
+    g, o = _compare_lockstep(gctx, ph, src, 4_000, name="max_dims", min_frac=0.85)
+    assert g["events"]["esteps"] > 40_000     # voxel-limited electron steps (about 95 per history)
+    d = gpu_run(gctx, ph, src, seed=4, n_hist=20_000)["dose"].reshape(1024, 1, 2048)
+    assert d[1000:, 0, 1990:].sum() > 0.0                 # deposits in the far corner
+    for dims in ((2049, 1, 1), (1, 2049, 1), (1, 1, 1025)):
+        with pytest.raises(G.GdpmError) as e:
+            gctx.phantom(I.homogeneous(dims, (0.1, 0.1, 0.1), I.ID_WATER, 1.0))
+        assert e.value.status == 1
+
+
 def test_queue_overflow_reported():
     """A queue too small for the workload stops the run with GDPM_E_OVERFLOW
     (forced from the host: 4096-record queues, 4000 new histories per
