@@ -518,3 +518,30 @@ def test_run_async_device_outputs(gctx):
         hip.hipStreamDestroy(stream)
         p.close()
         src.close()
+
+
+def test_run_async_into_torch_tensors(gctx):
+    """The boundary with PyTorch as the caller: gdpm_run_async writes dose and
+    standard error into torch tensors (their data_ptr()) on torch's current
+    stream and on a second torch stream, and the tensors hold what the blocking
+    gdpm_run returns into host arrays."""
+    import torch
+    w = I.water_cube_2mev()
+    nv = w.phantom.nvox
+    p, src = gctx.phantom(w.phantom), gctx.source(w.source)
+    try:
+        ref = gctx.run(p, src, n_hist=20_000, seed=7)
+        side = torch.cuda.Stream(device="cuda:0")
+        for stream in (torch.cuda.current_stream(torch.device("cuda:0")), side):
+            dose = torch.zeros(nv, dtype=torch.float64, device="cuda:0")
+            sigma = torch.zeros(nv, dtype=torch.float64, device="cuda:0")
+            stream.wait_stream(torch.cuda.current_stream(torch.device("cuda:0")))
+            st = gctx.run_async(p, src, dose.data_ptr(), sigma.data_ptr(),
+                                stream=stream.cuda_stream, n_hist=20_000, seed=7)
+            torch.cuda.synchronize()
+            np.testing.assert_allclose(dose.cpu().numpy(), ref["dose"], rtol=1e-12, atol=1e-300)
+            np.testing.assert_allclose(sigma.cpu().numpy(), ref["sigma"], rtol=1e-12, atol=1e-300)
+            assert st["histories"] == 20_000
+    finally:
+        p.close()
+        src.close()
