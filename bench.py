@@ -42,7 +42,10 @@ PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 # vector-ALU lane instructions: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
 # instruction occupies a SIMD for 4 cycles; unpacked FP32 = 78.6 TFLOP/s of FMA)
 PEAK_VALU_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1107_3355_amd", "csrc", "transport.hip")
+# the kernels and the compile-time constants they are built with: a profile is
+# valid while the sha256 of these files, read in this order, is unchanged
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1107_3355_amd", "csrc", f)
+                  for f in ("transport.hip", "dev_types.h")]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_ct256x256x128_imrt9.txt")
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_ct256x256x128_imrt9.txt")
 
@@ -265,8 +268,11 @@ def profiled_values(path):
         return None
     kv = {a.strip(): b.strip() for a, b in (line.split(":", 1) for line in text.splitlines()
                                             if ":" in line and not line.startswith(" "))}
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    return kv if kv.get("transport_hip_sha256") == src else None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return kv if kv.get("kernel_source_sha256") == h.hexdigest() else None
 
 
 def measured_traffic(kernel):

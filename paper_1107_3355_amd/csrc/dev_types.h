@@ -16,14 +16,14 @@ constexpr uint32_t kTailLanes = 32;     // a drained wavefront with fewer partic
                                         // than this hands them to the next pass ...
 constexpr uint32_t kTailMinPerLane = 4; // ... if the pass had this many per lane
 #ifndef GDPM_HARD_BATCH
-#define GDPM_HARD_BATCH 8
+#define GDPM_HARD_BATCH 12
 #endif
 constexpr uint32_t kHardBatch = GDPM_HARD_BATCH;  // electron hard events sampled together
 #ifndef GDPM_REAL_BATCH
-#define GDPM_REAL_BATCH 24
+#define GDPM_REAL_BATCH 28
 #endif
 constexpr uint32_t kRealBatch = GDPM_REAL_BATCH;  // photon interactions sampled together
-constexpr uint32_t kRefillMin = 8;      // empty lanes a wavefront refills at once
+constexpr uint32_t kRefillMin = 12;     // empty lanes a wavefront refills at once
 constexpr float kMaxEnergy = 1.0e6f;    // MeV; a larger or non-finite energy marks a
                                         // damaged record
 constexpr uint32_t kMaxWaveIterations = 1u << 21;  // bound of a wavefront's loop in one
