@@ -130,13 +130,17 @@ def _source_cases():
             ("slab_electron", w3.phantom, w3.source)]
 
 
-@pytest.mark.parametrize("case", [0, 1, 2, 3])
+@pytest.mark.parametrize("case", [0, 1, 2, 3, 4])
 def test_source_lockstep(gctx, case):
     if case < 3:
         name, ph, src = _source_cases()[case]
-    else:
+    elif case == 3:
         w = I.ct_imrt()
         name, ph, src = "ct_imrt_full", w.phantom, w.source
+    else:
+        # the serving form's 180-control-point arc: 288,000 beamlets
+        ph = I.ct_imrt().phantom
+        name, src = "ct_vmat180_full", I.Source(I.PHOTON, I.triangular_spectrum(), I.vmat_arc(ph))
     p = gctx.phantom(ph)
     s = gctx.source(src)
     n = 20_000

@@ -149,6 +149,16 @@ def test_ct_full_size_lockstep(gctx):
                       hist0=10_000_000)
 
 
+def test_ct_vmat_arc_lockstep(gctx):
+    """The serving form's VMAT-like arc (180 control points of 40x40 beamlets:
+    288,000 beamlets, twenty times the IMRT plan's) on the full-size CT:
+    sampled histories computed one by one by the oracle."""
+    w = _ct_full()
+    src = I.Source(I.PHOTON, I.triangular_spectrum(), I.vmat_arc(w.phantom))
+    _compare_lockstep(gctx, w.phantom, src, 2_000, name="ct256_vmat180", min_frac=0.9,
+                      hist0=3_000_000)
+
+
 def test_ct_metropolis_source(gctx):
     """A CT job whose beamlets come from Metropolis chains (Algorithm A1): the
     same histories as the oracle's (lockstep, the chains run across the job's
