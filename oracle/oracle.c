@@ -1015,7 +1015,7 @@ static int source_particle(const ctx_t* c, uint64_t h, particle_t* p, int* beaml
 }
 
 /* ======================================================================== */
-/* Driver                                                                     */
+/* Runs: histories split over threads, tallies merged in a fixed order        */
 /* ======================================================================== */
 
 typedef struct {
