@@ -97,30 +97,44 @@ GDPM_DEV void philox(uint32_t k0, uint32_t k1, uint32_t& x0, uint32_t& x1, uint3
 }
 
 // A lane's stream: key (k0, k1), counter (hist lo, hist hi, path, draw >> 2);
-// draw d is word d & 3 of its block.  Two blocks are buffered: A (block `blk`,
-// next word `i`, 4 = used up) and C (block blk + 1 when `ahead`).  Blocks are
-// generated in rng_topup, once per iteration and with the wavefront converged;
-// a lane that runs out inside an event takes the out-of-line slow path.
-struct Rng {
+// draw d is word d & 3 of its block.  A (block `blk`, next word `i`, 4 = used
+// up) is followed by up to Q queued blocks: C (blk + 1) and, for Q = 2, D
+// (blk + 2).  Q = 1 marks C with the flag `qc`, Q = 2 counts C and D in `nq`
+// (each form compiled best for the kernel that uses it).  Blocks are generated
+// with the wavefront converged: rng_topup once per iteration (A has a word
+// left, C is queued), rng_deep at the start of a batch of photon interactions
+// (C and D queued: at least 9 draws, enough for most interactions).  A lane
+// that still runs out takes the out-of-line path, which costs a whole
+// wavefront's Philox for the few lanes in it.  Blocks are only ever generated
+// in counter order, so the draws are the same whatever is buffered.
+template <int Q>
+struct RngT {
     uint32_t hlo, hhi, path;
     uint32_t blk, i, skip;
     uint32_t a0, a1, a2, a3;
     uint32_t c0, c1, c2, c3;
-    bool ahead;
+    uint32_t d0, d1, d2, d3;   // Q == 2
+    uint32_t nq;               // Q == 2
+    bool qc;                   // Q == 1
 };
+using Rng = RngT<1>;       // electrons, sources, tests
+using RngDeep = RngT<2>;   // photons: an interaction draws more than a flight
 
 // counter of the next draw
-GDPM_DEV uint32_t rng_ctr(const Rng& r) { return 4u * r.blk + r.i; }
+template <int Q>
+GDPM_DEV uint32_t rng_ctr(const RngT<Q>& r) { return 4u * r.blk + r.i; }
 
 // position the stream at draw `ctr` (no block generated yet)
-GDPM_DEV void rng_start(Rng& r, uint32_t hlo, uint32_t hhi, uint32_t path, uint32_t ctr) {
+template <int Q>
+GDPM_DEV void rng_start(RngT<Q>& r, uint32_t hlo, uint32_t hhi, uint32_t path, uint32_t ctr) {
     r.hlo = hlo;
     r.hhi = hhi;
     r.path = path;
     r.blk = (ctr >> 2) - 1u;  // A is "used up"; the next block is ctr >> 2
     r.i = 4u;
     r.skip = ctr & 3u;
-    r.ahead = false;
+    r.qc = false;
+    r.nq = 0u;
 }
 
 __device__ __attribute__((noinline)) uint4 rng_block_slow(uint32_t k0, uint32_t k1, uint32_t hlo,
@@ -130,43 +144,77 @@ __device__ __attribute__((noinline)) uint4 rng_block_slow(uint32_t k0, uint32_t 
     return make_uint4(x0, x1, x2, x3);
 }
 
-// make sure A has a word left and C holds the following block
-GDPM_DEV void rng_topup(Rng& r, uint32_t k0, uint32_t k1) {
-    if (r.i == 4u) {
-        if (r.ahead) {
-            r.a0 = r.c0; r.a1 = r.c1; r.a2 = r.c2; r.a3 = r.c3;
-            r.ahead = false;
+template <int Q>
+GDPM_DEV uint4 rng_block(uint32_t k0, uint32_t k1, const RngT<Q>& r, uint32_t blk) {
+    uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = blk;
+    philox(k0, k1, x0, x1, x2, x3);
+    return make_uint4(x0, x1, x2, x3);
+}
+
+template <int Q>
+GDPM_DEV bool rng_queued(const RngT<Q>& r) {
+    if constexpr (Q == 1) return r.qc;
+    else return r.nq > 0u;
+}
+
+// A used up: the next block becomes A (from the queue, else generated here,
+// inline or out of line)
+template <int Q>
+GDPM_DEV void rng_advance(RngT<Q>& r, uint32_t k0, uint32_t k1, bool inline_block) {
+    if (rng_queued(r)) {
+        r.a0 = r.c0; r.a1 = r.c1; r.a2 = r.c2; r.a3 = r.c3;
+        if constexpr (Q == 1) {
+            r.qc = false;
         } else {
-            uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = r.blk + 1u;
-            philox(k0, k1, x0, x1, x2, x3);
-            r.a0 = x0; r.a1 = x1; r.a2 = x2; r.a3 = x3;
+            r.c0 = r.d0; r.c1 = r.d1; r.c2 = r.d2; r.c3 = r.d3;
+            r.nq -= 1u;
         }
-        r.blk += 1u;
-        r.i = r.skip;
-        r.skip = 0u;
+    } else {
+        const uint4 b = inline_block ? rng_block(k0, k1, r, r.blk + 1u)
+                                     : rng_block_slow(k0, k1, r.hlo, r.hhi, r.path, r.blk + 1u);
+        r.a0 = b.x; r.a1 = b.y; r.a2 = b.z; r.a3 = b.w;
     }
-    if (!r.ahead) {
-        uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = r.blk + 1u;
-        philox(k0, k1, x0, x1, x2, x3);
-        r.c0 = x0; r.c1 = x1; r.c2 = x2; r.c3 = x3;
-        r.ahead = true;
+    r.blk += 1u;
+    r.i = r.skip;
+    r.skip = 0u;
+}
+
+// queue the next missing block (C, else D)
+template <int Q>
+GDPM_DEV void rng_queue(RngT<Q>& r, uint32_t k0, uint32_t k1) {
+    if constexpr (Q == 1) {
+        const uint4 b = rng_block(k0, k1, r, r.blk + 1u);
+        r.c0 = b.x; r.c1 = b.y; r.c2 = b.z; r.c3 = b.w;
+        r.qc = true;
+    } else {
+        const uint4 b = rng_block(k0, k1, r, r.blk + 1u + r.nq);
+        if (r.nq == 0u) {
+            r.c0 = b.x; r.c1 = b.y; r.c2 = b.z; r.c3 = b.w;
+        } else {
+            r.d0 = b.x; r.d1 = b.y; r.d2 = b.z; r.d3 = b.w;
+        }
+        r.nq += 1u;
     }
 }
 
+// make sure A has a word left and C is queued
+template <int Q>
+GDPM_DEV void rng_topup(RngT<Q>& r, uint32_t k0, uint32_t k1) {
+    if (r.i == 4u) rng_advance(r, k0, k1, true);
+    if (!rng_queued(r)) rng_queue(r, k0, k1);
+}
+
+// make sure A has a word left and C and D are queued (at least 9 draws)
+GDPM_DEV void rng_deep(RngDeep& r, uint32_t k0, uint32_t k1) {
+    if (r.i == 4u) rng_advance(r, k0, k1, true);
+    if (r.nq < 2u) rng_queue(r, k0, k1);
+    if (r.nq < 2u) rng_queue(r, k0, k1);
+}
+
 // (2 (x >> 9) + 1) 2^-24: exact in single and double precision, inside (0, 1)
-GDPM_DEV float uniform(Rng& r, uint32_t k0, uint32_t k1) {
-    if (r.i == 4u) {
-        if (r.ahead) {
-            r.a0 = r.c0; r.a1 = r.c1; r.a2 = r.c2; r.a3 = r.c3;
-            r.ahead = false;
-        } else {
-            const uint4 b = rng_block_slow(k0, k1, r.hlo, r.hhi, r.path, r.blk + 1u);
-            r.a0 = b.x; r.a1 = b.y; r.a2 = b.z; r.a3 = b.w;
-        }
-        r.blk += 1u;
-        r.i = r.skip;
-        r.skip = 0u;
-    }
+template <int Q>
+GDPM_DEV float uniform(RngT<Q>& r, uint32_t k0, uint32_t k1) {
+    if (r.i == 4u) rng_advance(r, k0, k1, false);
     const uint32_t w = r.i;
     const uint32_t x = w == 0u ? r.a0 : (w == 1u ? r.a1 : (w == 2u ? r.a2 : r.a3));
     r.i = w + 1u;
@@ -174,7 +222,8 @@ GDPM_DEV float uniform(Rng& r, uint32_t k0, uint32_t k1) {
 }
 
 // path id of the secondary created in role `word` at the parent's current counter
-GDPM_DEV uint32_t spawn_path(const Rng& r, uint32_t k0, uint32_t k1, int word) {
+template <int Q>
+GDPM_DEV uint32_t spawn_path(const RngT<Q>& r, uint32_t k0, uint32_t k1, int word) {
     uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = 0x80000000u | rng_ctr(r);
     philox(k0, k1, x0, x1, x2, x3);
     return word == 0 ? x0 : (word == 1 ? x1 : (word == 2 ? x2 : x3));
@@ -784,7 +833,8 @@ GDPM_DEV void pass_finish(LaneTally& t, const WaveTally& c, Ctl* ctl, int ri) {
 
 // Klein-Nishina by Butcher-Messel composition and rejection: eps = E'/E and
 // t = 1 - cos(theta); then the azimuth (in turns)
-GDPM_DEV void sample_compton(Rng& r, uint32_t k0, uint32_t k1, float e, float& eps, float& t,
+template <int Q>
+GDPM_DEV void sample_compton(RngT<Q>& r, uint32_t k0, uint32_t k1, float e, float& eps, float& t,
                              float& turns) {
     const float k = e * (1.0f / kMec2f);
     const float e0 = hrcp(1.0f + 2.0f * k);
@@ -803,7 +853,8 @@ GDPM_DEV void sample_compton(Rng& r, uint32_t k0, uint32_t k1, float e, float& e
 
 // Moller: eps = W/T by a 1/eps^2 proposal on [W_cc/T, 1/2] and rejection
 // eps^2 B(eps) / 2.25; then the azimuth
-GDPM_DEV void sample_moller(Rng& r, uint32_t k0, uint32_t k1, float tt, float wcc, float& eps,
+template <int Q>
+GDPM_DEV void sample_moller(RngT<Q>& r, uint32_t k0, uint32_t k1, float tt, float wcc, float& eps,
                             float& turns) {
     const float g = 1.0f + tt * (1.0f / kMec2f), e0 = fdiv(wcc, tt);
     const float ig = hrcp(g);
@@ -821,7 +872,8 @@ GDPM_DEV void sample_moller(Rng& r, uint32_t k0, uint32_t k1, float tt, float wc
 
 // bremsstrahlung photon energy: 1/k proposal on [W_cb, T], rejection by the
 // complete-screening spectrum
-GDPM_DEV float sample_brems(Rng& r, uint32_t k0, uint32_t k1, float tt, float wcb) {
+template <int Q>
+GDPM_DEV float sample_brems(RngT<Q>& r, uint32_t k0, uint32_t k1, float tt, float wcb) {
     const float lr = hlog2(tt) - hlog2(wcb);
     const float it = hrcp(tt);
     float kph;
@@ -836,7 +888,8 @@ GDPM_DEV float sample_brems(Rng& r, uint32_t k0, uint32_t k1, float tt, float wc
 }
 
 // isotropic direction of the first annihilation photon (cos, then azimuth)
-GDPM_DEV void sample_iso(Rng& r, uint32_t k0, uint32_t k1, float& du, float& dv, float& dw) {
+template <int Q>
+GDPM_DEV void sample_iso(RngT<Q>& r, uint32_t k0, uint32_t k1, float& du, float& dv, float& dw) {
     const float ct = 2.0f * uniform(r, k0, k1) - 1.0f;
     const float turns = uniform(r, k0, k1);
     const float st = hsqrt((1.0f - ct) * (1.0f + ct));
@@ -874,9 +927,10 @@ GDPM_DEV void write_particle(Particle* buf, uint32_t mask, uint32_t slot, float 
 }
 
 // secondaries inherit the job and the batch slot (`jb`) of their history
+template <int Q>
 GDPM_DEV void push_charged(PendCharged& q, PushState& ps, uint32_t head, Ctl* ctl, const RunDev& R,
                            const WJob& W, uint32_t jb, Particle* buf, float x, float y, float z,
-                           uint32_t vox, const Rng& rng, WaveTally& c) {
+                           uint32_t vox, const RngT<Q>& rng, WaveTally& c) {
     const uint64_t b0 = ballot(q.n >= 1), b1 = ballot(q.n >= 2);
     const uint32_t n0 = (uint32_t)__popcll(b0), n = n0 + (uint32_t)__popcll(b1);
     if (n == 0) return;
@@ -893,9 +947,10 @@ GDPM_DEV void push_charged(PendCharged& q, PushState& ps, uint32_t head, Ctl* ct
     q.n = 0;
 }
 
+template <int Q>
 GDPM_DEV void push_photons(PendPhoton& q, PushState& ps, uint32_t head, Ctl* ctl, const RunDev& R,
                            const WJob& W, uint32_t jb, Particle* buf, float x, float y, float z,
-                           const Rng& rng, WaveTally& c) {
+                           const RngT<Q>& rng, WaveTally& c) {
     const uint64_t b0 = ballot(q.n >= 1), b1 = ballot(q.n >= 2);
     const uint32_t n0 = (uint32_t)__popcll(b0), n = n0 + (uint32_t)__popcll(b1);
     if (n == 0) return;
@@ -1162,7 +1217,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
         float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
         uint32_t pb = 0u;   // batch slot of the lane's history
         int pm = -1;        // >= 0: a real interaction waits, in a voxel of this material
-        Rng rng;
+        RngDeep rng;
         rng_start(rng, 0u, 0u, 0u, 0u);
         int next = -1;
         for (;;) {
@@ -1246,6 +1301,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                 const uint64_t br = ballot(pm >= 0);
                 if (br && (cs.done || (uint32_t)__popcll(br) >= kRealBatch || br == ballot(active))) {
                     if (pm >= 0) {
+                        rng_deep(rng, k0, k1);
                         const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
                         const float4 mu = lerp4(ptab + pm * T.pg_n, gi, gt);
                         const float r = uniform(rng, k0, k1) * mu.w;
