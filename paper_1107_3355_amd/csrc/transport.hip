@@ -32,6 +32,7 @@
 namespace gdpm {
 
 #define GDPM_DEV __device__ __forceinline__
+#define GDPM_HD __host__ __device__ inline
 
 constexpr float kMec2f = 0.51099895f;
 constexpr float kTwoMec2f = 1.0219979f;
@@ -747,6 +748,7 @@ struct ClaimState {
     uint32_t next, end;  // claimed positions of the job's segment not yet handed out
     uint32_t seen;       // the job's claim counter as this wave last saw it
     bool done;           // the job's segment has nothing left to claim
+    uint32_t st_lo, st_hi;  // positions whose records are staged in the wave's LDS slice
 };
 
 // ---------------------------------------------------------------------------
@@ -1038,12 +1040,49 @@ GDPM_DEV void claim_refill(ClaimState& cs, JobCtl* jc, const WJob& W, const Ctl*
     cs.end = min(base + chunk, count);
 }
 
+// Records of the wave's claimed chunk are staged in its LDS slice (kStage
+// records, 64 bytes each) by direct-to-LDS loads issued right after a refill,
+// so the next refills read them from LDS instead of waiting for memory.
+constexpr uint32_t kStage = 64;
+constexpr uint32_t kStageLow = 24;   // restage when fewer staged records are left
+
+GDPM_DEV Particle load_staged(const float4* st, uint32_t k) {
+    Particle p;
+    float4* d = reinterpret_cast<float4*>(&p);
+    d[0] = st[4 * k];
+    d[1] = st[4 * k + 1];
+    d[2] = st[4 * k + 2];
+    d[3] = st[4 * k + 3];
+    return p;
+}
+
+// stage the records of positions [cs.next, cs.next + kStage) (every lane: 4
+// loads of 16 bytes; lane L of load c fetches piece L % 4 of record 16 c + L / 4,
+// which lands at float4 64 c + L of the slice).  Positions past the chunk are
+// loaded too (the ring index is masked) and never used.
+GDPM_DEV void stage_records(ClaimState& cs, float4* st, const Particle* buf, uint32_t mask,
+                            uint32_t first) {
+    // the refill's reads of the slice are complete before it is overwritten
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+    const uint32_t l = lane_id();
+    for (uint32_t c = 0; c < 4; ++c) {
+        const uint32_t rec = 16u * c + (l >> 2);
+        const float4* src = reinterpret_cast<const float4*>(buf + ((first + cs.next + rec) & mask)) + (l & 3u);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(st + 64u * c), 16, 0, 0);
+    }
+    cs.st_lo = cs.next;
+    cs.st_hi = cs.next + kStage;
+}
+
 // refill the lanes without a particle from the wave's claimed items; returns
 // true in the lanes that loaded a record.  Lanes wait until kRefillMin of them
 // are empty (or no lane is busy): a refill stalls the wavefront on record
-// loads, so it pays to do it for several lanes at once.
+// loads, so it pays to do it for several lanes at once.  With a staging slice
+// (`st`, LDS) the records come from it when they are staged.
 GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uint32_t begin,
-                     Ctl* ctl, const Particle* buf, uint32_t mask, Particle& p, WaveTally& c) {
+                     Ctl* ctl, const Particle* buf, uint32_t mask, Particle& p, WaveTally& c,
+                     float4* st) {
     if (cs.done) return false;
     const uint64_t need = ballot(!active);
     if (!need) return false;
@@ -1052,9 +1091,14 @@ GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uin
     const uint32_t have = cs.end - cs.next;
     const uint32_t rank = mbcnt(need);
     const uint32_t take = min(have, (uint32_t)__popcll(need));
+    const uint32_t first = begin + W.seg_begin;
+    const bool staged = st != nullptr && take > 0u && cs.next >= cs.st_lo &&
+                        cs.next + take <= cs.st_hi;
+    if (staged) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the staging loads have landed
     bool got = false;
     if (!active && rank < take) {
-        p = load(buf, mask, begin + W.seg_begin + cs.next + rank);
+        p = staged ? load_staged(st, cs.next + rank - cs.st_lo)
+                   : load(buf, mask, first + cs.next + rank);
         got = p.e >= 0.0f;
         if (got && (p.job & 0xFFFFu) != W.tag) {
             // a record of another job (or of an earlier job in this slot) in
@@ -1066,6 +1110,11 @@ GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uin
     }
     cs.next += take;
     c.ld += take;
+    if (st != nullptr && cs.next < cs.end) {
+        // positions of a pass's segment do not wrap: plain comparisons
+        const uint32_t left = cs.next >= cs.st_lo && cs.next < cs.st_hi ? cs.st_hi - cs.next : 0u;
+        if (left <= kStageLow) stage_records(cs, st, buf, mask, first);
+    }
     return got;
 }
 
@@ -1179,15 +1228,28 @@ __global__ void k_commit(Ctl* ctl, int ri, const SrcHdr* hdr) {
 // LDS slice.
 extern __shared__ float4 lds_tables[];
 
+// LDS layout of a transport workgroup (float4 units): the tables (photons: the
+// cross sections, then one majorant slice of pg_n floats per wavefront;
+// electrons: the stopping and scattering data, the inverse range and its
+// scales), then one slice of kStage staged records per wavefront
+GDPM_HD uint32_t stage_offset(int ri, const Tables& T, int waves) {
+    const uint32_t floats = ri == 0 ? (uint32_t)(waves * T.pg_n)
+                                    : (uint32_t)(T.n_mat * T.nr + T.n_mat);
+    const uint32_t tab = ri == 0 ? (uint32_t)(T.n_mat * T.pg_n) : (uint32_t)(T.n_mat * T.eg_n);
+    return tab + (floats + 3u) / 4u;
+}
+
 template <bool kLds>
 __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     const float4* ptab = T.phot;
     float* lmw = nullptr;
+    float4* stage = nullptr;
     if constexpr (kLds) {
         const int np = T.n_mat * T.pg_n;
         for (int i = threadIdx.x; i < np; i += blockDim.x) lds_tables[i] = T.phot[i];
-        lmw = reinterpret_cast<float*>(lds_tables + np) +
-              __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * T.pg_n;
+        const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        lmw = reinterpret_cast<float*>(lds_tables + np) + wave * T.pg_n;
+        stage = lds_tables + stage_offset(0, T, blockDim.x >> 6) + wave * (4u * kStage);
         __syncthreads();
         ptab = lds_tables;
     }
@@ -1212,7 +1274,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
         WJob W;
         load_job(W, R, j);
         const float* mtab = job_majorant<kLds>(W, lmw, T.pg_n);
-        ClaimState cs{0u, 0u, 0u, false};
+        ClaimState cs{0u, 0u, 0u, false, 0u, 0u};
         bool active = false;
         float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
         uint32_t pb = 0u;   // batch slot of the lane's history
@@ -1224,7 +1286,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             const uint32_t k0 = W.k0, k1 = W.k1;
             const bool kerma = (W.flags & 64u) != 0u;
             Particle p;
-            if (refill(active, cs, jc, W, begin, ctl, bufg, R.mask[0], p, wt)) {
+            if (refill(active, cs, jc, W, begin, ctl, bufg, R.mask[0], p, wt, stage)) {
                 x = p.x; y = p.y; z = p.z; e = p.e;
                 u = p.u; v = p.v; w = p.w;
                 pb = p.job >> 16;
@@ -1442,8 +1504,11 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     const float4* etab = T.elec;
     const float* rtab = T.rinv;
     const float* rscale = T.rinv_scale;
+    float4* stage = nullptr;
     if constexpr (kLds) {
         const int ne = T.n_mat * T.eg_n, nr = T.n_mat * T.nr;
+        stage = lds_tables + stage_offset(1, T, blockDim.x >> 6) +
+                __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * (4u * kStage);
         for (int i = threadIdx.x; i < ne; i += blockDim.x) lds_tables[i] = T.elec[i];
         float* lr = reinterpret_cast<float*>(lds_tables + ne);
         for (int i = threadIdx.x; i < nr; i += blockDim.x) lr[i] = T.rinv[i];
@@ -1473,7 +1538,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     while (j >= 0) {
         WJob W;
         load_job(W, R, j);
-        ClaimState cs{0u, 0u, 0u, false};
+        ClaimState cs{0u, 0u, 0u, false, 0u, 0u};
         bool active = false;
         float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0, nh = -1.0f, aa = 0.0f;
         int ix = 0, iy = 0, iz = 0;
@@ -1489,7 +1554,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
             const uint32_t k0 = W.k0, k1 = W.k1;
             const bool no_ms = (W.flags & 8u) != 0u;
             Particle p;
-            if (refill(active, cs, jc, W, begin, ctl, bufe, R.mask[1], p, wt)) {
+            if (refill(active, cs, jc, W, begin, ctl, bufe, R.mask[1], p, wt, stage)) {
                 x = p.x; y = p.y; z = p.z; e = p.e;
                 u = p.u; v = p.v; w = p.w; nh = p.nh;
                 ix = (int)(p.vox & 2047u);
@@ -2091,9 +2156,7 @@ hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri) {
 }
 // LDS bytes the table staging of a pass needs with `waves` wavefronts per block
 size_t transport_lds_bytes(int ri, const Tables& T, int waves) {
-    if (ri == 0)
-        return (size_t)T.n_mat * T.pg_n * sizeof(float4) + (size_t)waves * T.pg_n * sizeof(float);
-    return (size_t)T.n_mat * T.eg_n * sizeof(float4) + ((size_t)T.n_mat * T.nr + T.n_mat) * sizeof(float);
+    return ((size_t)stage_offset(ri, T, waves) + (size_t)waves * 4u * kStage) * sizeof(float4);
 }
 
 // allow the staged kernels to use `bytes` of dynamic LDS
