@@ -289,7 +289,9 @@ def test_determinism_and_launch_independence(gctx):
     for opts in ('{"waves_per_cu": 4, "rebin_bins": 1, "rebin_photons": 1, "rebin_electrons": 1}',
                  '{"waves_per_cu": 8, "rebin_bins": 32, "rebin_photons": 1, "rebin_electrons": 1}',
                  '{"ring_capacity_log2": 21, "pass_histories": 700}',
-                 '{"rebin_photons": 1, "rebin_electrons": 0}'):
+                 '{"rebin_photons": 1, "rebin_electrons": 0}',
+                 # tables read through L2 and records loaded directly, no LDS staging
+                 '{"lds_tables": 0}'):
         c2 = G.Context(0, opts=opts, materials=MATS)
         try:
             c = gpu_run(c2, w.phantom, w.source, n_hist=50_000, seed=9)
