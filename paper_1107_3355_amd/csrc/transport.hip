@@ -1490,6 +1490,8 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
         job_flush(tl, wt, W, jc);
         j = next;
     }
+    // no staging load may still be writing this workgroup's LDS when it ends
+    if constexpr (kLds) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
     pass_finish(tl, wt, ctl, 0);
@@ -1790,6 +1792,8 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
         job_flush(tl, wt, W, jc);
         j = next;
     }
+    // no staging load may still be writing this workgroup's LDS when it ends
+    if constexpr (kLds) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
     pass_finish(tl, wt, ctl, 1);
