@@ -214,13 +214,14 @@ typedef struct {
  * the queue of that particle type also when a single job holds all the
  * particles; default 0: then the queues are read unsorted, which measured
  * faster), "lds_tables" (1: stage interpolation tables in LDS when they fit,
- * default; 0: read them through the caches), "pass_histories" (new histories
+ * together with each wavefront's next claimed queue records, default; 0: read
+ * the tables through the caches and load records directly), "pass_histories" (new histories
  * started per scheduler iteration, default 0 = half the queue capacity less
  * what the fuller queue holds; a larger
  * value can overflow the queues, which gdpm_run reports as GDPM_E_OVERFLOW).
  * Each wavefront reserves queue slots 256 at a time, so a queue needs well
  * over 256 slots per wavefront of the grid (2^21 and up on a 256-CU device
- * with 16 wavefronts per CU); smaller queues overflow.
+ * with 12 wavefronts per CU); smaller queues overflow.
  * "share" (how the jobs run together share the new histories of an iteration:
  * 1, default, evenly; 0 in admission order, the oldest job taking what it can
  * use), "autotune" (see gdpm_context_settings), "graphs" (1, default: a
