@@ -201,6 +201,13 @@ typedef struct {
      * records differed from its births less its deaths (0 in a sound run, and
      * always 0 with the option off) */
     uint32_t accounting_mismatches;
+    /* real interactions by type over the run (Compton, photoelectric, pair,
+     * Moller, bremsstrahlung), counted like events */
+    uint64_t interactions[5];
+    /* records handed to the next pass of the same type (0 photon, 1 electron):
+     * particles still held by a wavefront at the tail of a large pass, or when
+     * it switched jobs */
+    uint64_t records_requeued[2];
 } gdpm_run_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -223,8 +230,10 @@ typedef struct {
  * over 256 slots per wavefront of the grid (2^21 and up on a 256-CU device
  * with 12 wavefronts per CU); smaller queues overflow.
  * "share" (how the jobs run together share the new histories of an iteration:
- * 1, default, evenly; 0 in admission order, the oldest job taking what it can
- * use), "autotune" (see gdpm_context_settings), "graphs" (1, default: a
+ * 1, the only value accepted, evenly; 0, oldest job first, is rejected with
+ * GDPM_E_INVALID: a job taking the whole history budget of an iteration can
+ * overflow the queues, whose budget assumes few secondaries per history),
+ * "autotune" (see gdpm_context_settings), "graphs" (1, default: a
  * scheduler iteration's launches, copies included, are recorded as a HIP
  * graph the second time their launch configuration occurs in a run, and
  * replayed from then on, on the stream of the run; each run, batch or server
@@ -246,6 +255,15 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
  * of the context).  out: waves_per_cu, rebin_bins, ring_capacity_log2,
  * pass_histories, autotune. */
 gdpm_status gdpm_context_settings(gdpm_context ctx, int out[5]);
+/* The autotuner's record of the context's latest tuned run (inspection):
+ * *n candidates, the first min(cap, *n) written as (waves_per_cu, rebin_bins)
+ * pairs to cand[2i], cand[2i+1] with their mean score in transport events
+ * (photon flights and electron steps) per second of transport kernel time in
+ * score[i] (0 while unmeasured); *kept is the index of the candidate kept for
+ * the rest of the run, -1 while the tuner has not decided (and *n = 0 if no
+ * tuned run happened). */
+gdpm_status gdpm_context_tuning(gdpm_context ctx, int cap, int* n, int* cand, double* score,
+                                int* kept);
 gdpm_status gdpm_context_destroy(gdpm_context ctx);
 const char* gdpm_last_error(void);
 
@@ -257,8 +275,11 @@ gdpm_status gdpm_set_materials(gdpm_context ctx, const gdpm_material* m, int n, 
 
 /* ---- phantom ------------------------------------------------------------ */
 
-/* nx, ny <= 2048, nz <= 1024; mat[v] < number of materials; density[v] > 0
- * and finite.  Both arrays (nx*ny*nz) are copied to device memory. */
+/* nx, ny <= 2048, nz <= 1024 and nx*ny*nz <= 2^31 - 1 (the linear voxel index
+ * is a signed 32-bit integer on the device); mat[v] < number of materials;
+ * density[v] > 0 and finite.  Both arrays (nx*ny*nz) are copied to device
+ * memory.  The sizes are checked before anything else (a NULL context with
+ * bad sizes reports the sizes). */
 gdpm_status gdpm_phantom_create(gdpm_context ctx, int nx, int ny, int nz, double dx, double dy,
                                 double dz, const uint8_t* mat, const float* density,
                                 gdpm_phantom* out);
@@ -387,8 +408,10 @@ gdpm_status gdpm_test_philox(gdpm_context ctx, const uint32_t key[2], const uint
  * path 0 of `seed`: which 0 Compton (E) -> eps, cos; 1 Moller (T) -> W/T, cos
  * of the primary; 2 bremsstrahlung (T) -> k; 3 MW deflection (t) -> mu;
  * 4 multiple-scattering walk of (int)p2 hinges of t each -> Omega.Omega0;
- * 5 annihilation pair -> cos of photon 1, dir1.dir2.  out1/out2: host arrays
- * of n floats (out2 may be NULL). */
+ * 5 annihilation pair -> cos of photon 1, dir1.dir2; 6 pair production (E) ->
+ * T-/(E - 2mc^2), T- + T+ - (E - 2mc^2) (0: the split is exact); 7 Compton (E)
+ * -> cos of the electron, cos of the photon (against the incident direction).
+ * out1/out2: host arrays of n floats (out2 may be NULL). */
 gdpm_status gdpm_test_sample(gdpm_context ctx, int which, double e, double p1, double p2,
                              uint64_t seed, int n, float* out1, float* out2);
 

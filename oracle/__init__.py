@@ -54,9 +54,14 @@ class Params(C.Structure):
                 ("n_threads", C.c_int)]
 
 
+TYPE_NAMES = ("flight_real", "flight_virtual", "compton", "photo", "pair", "hard_real",
+              "hard_virtual", "moller", "brems")
+
+
 class Stats(C.Structure):
     _fields_ = [("e_in", C.c_double), ("e_dep", C.c_double), ("e_esc", C.c_double),
-                ("ev", C.c_uint64 * 8)]
+                ("ev", C.c_uint64 * 8), ("n_type", C.c_uint64 * len(TYPE_NAMES)),
+                ("p_type", C.c_double * len(TYPE_NAMES)), ("v_type", C.c_double * len(TYPE_NAMES))]
 
 
 def lib():
@@ -67,7 +72,8 @@ def lib():
         L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
         L.orc_run.argtypes = [C.POINTER(Material), C.c_int, C.POINTER(Phantom), C.POINTER(Source),
-                              C.POINTER(Params), dp, dp, dp, dp, C.POINTER(Stats)]
+                              C.POINTER(Params), dp, dp, dp, dp, C.POINTER(C.c_uint32),
+                              C.POINTER(Stats)]
         L.orc_run.restype = C.c_int
         L.orc_phys.argtypes = [C.c_int, C.POINTER(Material), C.c_double, C.c_double, C.c_double]
         L.orc_phys.restype = C.c_double
@@ -154,7 +160,7 @@ def _source(src, keep):
 
 def run(materials, phantom, source, *, seed=1, n_hist=1000, n_batches=10, round_size=None,
         hist0=0, job_id=0, ecut_g=0.05, ecut_e=0.2, flags=0, n_threads=None,
-        want_batches=True, want_hist=False):
+        want_batches=True, want_hist=False, want_hist_hard=False):
     """Run the reference transport; returns a dict of numpy arrays and stats."""
     L = lib()
     keep = _Keep()
@@ -172,13 +178,20 @@ def run(materials, phantom, source, *, seed=1, n_hist=1000, n_batches=10, round_
     dose = np.zeros(nv)
     sigma = np.zeros(nv)
     hist = np.zeros((n_hist, 2)) if want_hist else None
+    hard = np.zeros(n_hist, dtype=np.uint32) if want_hist_hard else None
     st = Stats()
     rc = L.orc_run(mats, len(materials), C.byref(ph), C.byref(src), C.byref(prm),
-                   _dptr(batch), _dptr(dose), _dptr(sigma), _dptr(hist), C.byref(st))
+                   _dptr(batch), _dptr(dose), _dptr(sigma), _dptr(hist),
+                   None if hard is None else hard.ctypes.data_as(C.POINTER(C.c_uint32)),
+                   C.byref(st))
     if rc != 0:
         raise ValueError("oracle rejected its inputs")
     out = {"dose": dose, "sigma": sigma, "e_in": st.e_in, "e_dep": st.e_dep, "e_esc": st.e_esc,
-           "events": {k: int(st.ev[i]) for i, k in enumerate(EV_NAMES)}}
+           "events": {k: int(st.ev[i]) for i, k in enumerate(EV_NAMES)},
+           "choices": {k: (int(st.n_type[i]), st.p_type[i], st.v_type[i])
+                       for i, k in enumerate(TYPE_NAMES)}}
+    if want_hist_hard:
+        out["hist_hard"] = hard
     if want_batches:
         out["batch_edep"] = batch
     if want_hist:

@@ -417,7 +417,21 @@ typedef struct {
     double* tally;
     double e_in, e_esc, h_dep, h_esc;
     uint64_t ev[8];
+    uint64_t n_type[ORC_NTYPES];   /* choices made, by type */
+    double p_type[ORC_NTYPES];     /* sum of each type's probability over the choices */
+    double v_type[ORC_NTYPES];     /* sum of p (1 - p) over the choices */
+    uint32_t h_hard;               /* real hard events of the running history */
 } work_t;
+
+/* record one choice among `n` types (probabilities p[0..n-1], summing to 1)
+ * that picked `chosen`; `first` is the index of p[0] among ORC_TYPE_* */
+static void count_choice(work_t* w, int first, int n, const double* p, int chosen) {
+    w->n_type[first + chosen]++;
+    for (int i = 0; i < n; ++i) {
+        w->p_type[first + i] += p[i];
+        w->v_type[first + i] += p[i] * (1.0 - p[i]);
+    }
+}
 
 static void push(work_t* w, const particle_t* p) {
     if (w->n == w->cap) {
@@ -524,6 +538,46 @@ static void make_charged(particle_t* q, int type, const particle_t* parent, cons
 /* Photon transport                                                          */
 /* ======================================================================== */
 
+/* Compton scattering of photon p (section 2.1's photon physics, read as
+ * free-electron Klein-Nishina): Butcher-Messel composition and rejection for
+ * eps = E'/E, an azimuth, the photon turned and left with E' = eps E; the
+ * electron takes T = E - E' along E d0 - E' d (momentum conservation). */
+static void compton(particle_t* p, double* te, double de[3]) {
+    double k = p->e / MC2, e0 = 1.0 / (1.0 + 2.0 * k);
+    double a1 = log(1.0 + 2.0 * k), a2 = 0.5 * (1.0 - e0 * e0);
+    double eps, t;
+    for (;;) {
+        double ua = draw(&p->s), ub = draw(&p->s), uc = draw(&p->s);
+        if (ua * (a1 + a2) < a1) eps = exp(-a1 * ub);
+        else eps = sqrt(e0 * e0 + (1.0 - e0 * e0) * ub);
+        t = (1.0 - eps) / (k * eps);
+        if (uc <= 1.0 - eps * t * (2.0 - t) / (1.0 + eps * eps)) break;
+    }
+    double phi = 2.0 * PI * draw(&p->s);
+    double d0[3] = {p->d[0], p->d[1], p->d[2]};
+    rotate(p->d, 1.0 - t, sqrt(fmax(0.0, t * (2.0 - t))), phi);
+    double e1 = eps * p->e;
+    *te = p->e - e1;
+    double nn = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        de[i] = p->e * d0[i] - e1 * p->d[i];
+        nn += de[i] * de[i];
+    }
+    nn = sqrt(nn);
+    for (int i = 0; i < 3; ++i) de[i] = nn > 0.0 ? de[i] / nn : d0[i];
+    p->e = e1;
+}
+
+/* pair production by photon p: the kinetic energy K = E - 2 mc^2 split
+ * uniformly (T- = u K, T+ = K - T-); the positron keeps its annihilation
+ * energy a = E - K */
+static void pair_split(particle_t* p, double* tm, double* tp, double* a) {
+    double kk = p->e - 2.0 * MC2;
+    *a = p->e - kk;
+    *tm = draw(&p->s) * kk;
+    *tp = kk - *tm;
+}
+
 static void track_photon(ctx_t* c, work_t* w, particle_t* p) {
     const double ecut_g = c->prm.ecut_g, ecut_e = c->prm.ecut_e;
     const int kerma = (c->prm.flags & ORC_KERMA) != 0;
@@ -548,42 +602,27 @@ static void track_photon(ctx_t* c, work_t* w, particle_t* p) {
         double mc, mp, mq;
         photon_mus(c, m, p->e, &mc, &mp, &mq);
         double mt = mc + mp + mq;
-        if (draw(&p->s) * mmax >= rho * mt) continue; /* fictitious interaction */
+        /* real with probability rho mu / mu_max, else fictitious */
+        const int real = draw(&p->s) * mmax < rho * mt;
+        const double pr[2] = {rho * mt / mmax, 1.0 - rho * mt / mmax};
+        count_choice(w, ORC_TYPE_FLIGHT_REAL, 2, pr, real ? 0 : 1);
+        if (!real) continue;
         w->ev[ORC_EV_REAL]++;
+        /* the interaction: Compton, photoelectric or pair with probabilities mu_i / mu */
         double r = draw(&p->s) * mt;
-        if (r < mc) {
-            /* Compton: Butcher-Messel composition and rejection on Klein-Nishina */
-            double k = p->e / MC2, e0 = 1.0 / (1.0 + 2.0 * k);
-            double a1 = log(1.0 + 2.0 * k), a2 = 0.5 * (1.0 - e0 * e0);
-            double eps, t;
-            for (;;) {
-                double ua = draw(&p->s), ub = draw(&p->s), uc = draw(&p->s);
-                if (ua * (a1 + a2) < a1) eps = exp(-a1 * ub);
-                else eps = sqrt(e0 * e0 + (1.0 - e0 * e0) * ub);
-                t = (1.0 - eps) / (k * eps);
-                if (uc <= 1.0 - eps * t * (2.0 - t) / (1.0 + eps * eps)) break;
-            }
-            double phi = 2.0 * PI * draw(&p->s);
-            double d0[3] = {p->d[0], p->d[1], p->d[2]};
-            rotate(p->d, 1.0 - t, sqrt(fmax(0.0, t * (2.0 - t))), phi);
-            double e1 = eps * p->e;
-            double te = p->e - e1;
-            /* electron along the momentum transfer E d0 - E' d */
-            double de[3], nn = 0.0;
-            for (int i = 0; i < 3; ++i) {
-                de[i] = p->e * d0[i] - e1 * p->d[i];
-                nn += de[i] * de[i];
-            }
-            nn = sqrt(nn);
-            for (int i = 0; i < 3; ++i) de[i] = nn > 0.0 ? de[i] / nn : d0[i];
+        int type = r < mc ? 0 : (r < mc + mp ? 1 : 2);
+        const double pt[3] = {mc / mt, mp / mt, mq / mt};
+        count_choice(w, ORC_TYPE_COMPTON, 3, pt, type);
+        if (type == 0) {
+            double te, de[3];
+            compton(p, &te, de);
             if (kerma || te <= ecut_e) deposit(w, v, te);
             else {
                 particle_t q;
                 make_charged(&q, 1, p, de, te, 0.0, iv, 0);
                 push(w, &q);
             }
-            p->e = e1;
-        } else if (r < mc + mp) {
+        } else if (type == 1) {
             /* photoelectric: the electron takes all the energy, along the photon */
             if (kerma || p->e <= ecut_e) deposit(w, v, p->e);
             else {
@@ -593,9 +632,9 @@ static void track_photon(ctx_t* c, work_t* w, particle_t* p) {
             }
             return;
         } else {
-            /* pair: uniform split of E - 2mc^2, both along the photon */
-            double kk = p->e - 2.0 * MC2, a = p->e - kk;
-            double tm = draw(&p->s) * kk, tp = kk - tm;
+            /* pair: both particles along the photon */
+            double tm, tp, a;
+            pair_split(p, &tm, &tp, &a);
             int pos_local = kerma || tp <= ecut_e;
             double ct = 0.0, phi = 0.0;
             if (pos_local) {
@@ -790,9 +829,17 @@ static void track_electron(ctx_t* c, work_t* w, particle_t* p) {
             w->ev[ORC_EV_HARD_CAND]++;
             double mm = muh_moller(c, m, tend);
             double muh1 = mm + muh_brems(c, m, tend);
-            if (draw(&p->s) * muh0 < muh1) {
+            const int accept = draw(&p->s) * muh0 < muh1;
+            const double pa[2] = {muh1 / muh0, 1.0 - muh1 / muh0};
+            count_choice(w, ORC_TYPE_HARD_REAL, 2, pa, accept ? 0 : 1);
+            if (accept) {
                 w->ev[ORC_EV_HARD]++;
-                if (draw(&p->s) * muh1 < mm) moller(c, w, p, v);
+                w->h_hard++;
+                /* Moller with probability mu_Moller / mu_hard, else bremsstrahlung */
+                const int type = draw(&p->s) * muh1 < mm ? 0 : 1;
+                const double pm[2] = {mm / muh1, 1.0 - mm / muh1};
+                count_choice(w, ORC_TYPE_MOLLER, 2, pm, type);
+                if (type == 0) moller(c, w, p, v);
                 else brems(c, w, p);
             }
             p->nh_set = 0;
@@ -1023,12 +1070,14 @@ typedef struct {
     work_t w;
     uint64_t h0, h1;
     double* hist_out;
+    uint32_t* hist_hard;
 } job_t;
 
-static void run_history(ctx_t* c, work_t* w, uint64_t h, double* hist_out) {
+static void run_history(ctx_t* c, work_t* w, uint64_t h, double* hist_out, uint32_t* hist_hard) {
     particle_t p;
     int beamlet;
     w->h_dep = w->h_esc = 0.0;
+    w->h_hard = 0;
     w->ev[ORC_EV_HISTORIES]++;
     int in = source_particle(c, h, &p, &beamlet);
     w->e_in += p.e;
@@ -1049,11 +1098,12 @@ static void run_history(ctx_t* c, work_t* w, uint64_t h, double* hist_out) {
         hist_out[2 * i] = w->h_dep;
         hist_out[2 * i + 1] = w->h_esc;
     }
+    if (hist_hard) hist_hard[h - c->prm.hist0] = w->h_hard;
 }
 
 static void* thread_main(void* arg) {
     job_t* j = (job_t*)arg;
-    for (uint64_t h = j->h0; h < j->h1; ++h) run_history(j->c, &j->w, h, j->hist_out);
+    for (uint64_t h = j->h0; h < j->h1; ++h) run_history(j->c, &j->w, h, j->hist_out, j->hist_hard);
     return NULL;
 }
 
@@ -1089,7 +1139,7 @@ static int validate(const orc_material* mats, int n_mat, const orc_phantom* ph,
 
 int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const orc_source* src,
             const orc_params* prm, double* batch_edep, double* dose, double* sigma,
-            double* hist_out, orc_stats* st) {
+            double* hist_out, uint32_t* hist_hard, orc_stats* st) {
     if (validate(mats, n_mat, ph, src, prm)) return 1;
     pthread_once(&gl_once, gl_init);
     ctx_t c;
@@ -1161,6 +1211,7 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
         jobs[t].c = &c;
         jobs[t].w.tally = (double*)malloc(sizeof(double) * nv);
         jobs[t].hist_out = hist_out;
+        jobs[t].hist_hard = hist_hard;
     }
     uint64_t R = prm->round_size, N = prm->n_hist;
     for (uint64_t r = 0; r * R < N; ++r) {
@@ -1188,6 +1239,11 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
         acc.e_in += jobs[t].w.e_in;
         acc.e_esc += jobs[t].w.e_esc;
         for (int k = 0; k < 8; ++k) acc.ev[k] += jobs[t].w.ev[k];
+        for (int k = 0; k < ORC_NTYPES; ++k) {
+            acc.n_type[k] += jobs[t].w.n_type[k];
+            acc.p_type[k] += jobs[t].w.p_type[k];
+            acc.v_type[k] += jobs[t].w.v_type[k];
+        }
         free(jobs[t].w.tally);
         free(jobs[t].w.st);
     }
@@ -1259,18 +1315,22 @@ void orc_sample(int which, double e, double p1, double p2, uint64_t seed, int n,
     for (int i = 0; i < n; ++i) {
         stream_t s = stream_make(seed, 0, (uint64_t)i, 0);
         double a = NAN, b = NAN;
-        if (which == 0) {
-            double k = e / MC2, e0 = 1.0 / (1.0 + 2.0 * k);
-            double a1 = log(1.0 + 2.0 * k), a2 = 0.5 * (1.0 - e0 * e0), eps, t;
-            for (;;) {
-                double ua = draw(&s), ub = draw(&s), uc = draw(&s);
-                if (ua * (a1 + a2) < a1) eps = exp(-a1 * ub);
-                else eps = sqrt(e0 * e0 + (1.0 - e0 * e0) * ub);
-                t = (1.0 - eps) / (k * eps);
-                if (uc <= 1.0 - eps * t * (2.0 - t) / (1.0 + eps * eps)) break;
+        if (which == 0 || which == 7) {
+            /* the transport's Compton interaction on a photon along +z */
+            particle_t p;
+            memset(&p, 0, sizeof p);
+            p.e = e;
+            p.d[2] = 1.0;
+            p.s = s;
+            double te, de[3];
+            compton(&p, &te, de);
+            if (which == 0) {
+                a = p.e / e;
+                b = p.d[2];
+            } else {
+                a = de[2];   /* electron direction cosine */
+                b = p.d[2];  /* photon direction cosine */
             }
-            a = eps;
-            b = 1.0 - t;
         } else if (which == 1) {
             /* run the transport's Moller sampler on a scratch particle */
             ctx_t c;
@@ -1326,6 +1386,16 @@ void orc_sample(int which, double e, double p1, double p2, uint64_t seed, int n,
             a = w.st[0].d[2];
             b = w.st[0].d[0] * w.st[1].d[0] + w.st[0].d[1] * w.st[1].d[1] + w.st[0].d[2] * w.st[1].d[2];
             free(w.st);
+        } else if (which == 6) {
+            /* the transport's pair split of a photon of energy e */
+            particle_t p;
+            memset(&p, 0, sizeof p);
+            p.e = e;
+            p.s = s;
+            double tm, tp, aa;
+            pair_split(&p, &tm, &tp, &aa);
+            a = tm / (e - 2.0 * MC2);
+            b = (tm + tp + aa) - e;   /* energy conservation */
         }
         out1[i] = a;
         if (out2) out2[i] = b;

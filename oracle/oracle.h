@@ -97,15 +97,31 @@ typedef struct {
 enum { ORC_EV_FLIGHTS = 0, ORC_EV_REAL, ORC_EV_ESTEPS, ORC_EV_HARD_CAND, ORC_EV_HARD,
        ORC_EV_DEPOSITS, ORC_EV_PUSHES, ORC_EV_HISTORIES };
 
-typedef struct { double e_in, e_dep, e_esc; uint64_t ev[8]; } orc_stats;
+/* the random choices of the transport, counted by outcome (a test of each
+ * choice rule: the count of an outcome minus the sum of its probabilities over
+ * the choices made is a martingale with variance sum p (1 - p)) */
+enum { ORC_TYPE_FLIGHT_REAL = 0, ORC_TYPE_FLIGHT_VIRTUAL,      /* Woodcock acceptance */
+       ORC_TYPE_COMPTON, ORC_TYPE_PHOTO, ORC_TYPE_PAIR,         /* real photon interactions */
+       ORC_TYPE_HARD_REAL, ORC_TYPE_HARD_VIRTUAL,               /* hard-event acceptance */
+       ORC_TYPE_MOLLER, ORC_TYPE_BREMS,                         /* real hard events */
+       ORC_NTYPES };
+
+typedef struct {
+    double e_in, e_dep, e_esc;
+    uint64_t ev[8];
+    uint64_t n_type[ORC_NTYPES];   /* choices by outcome */
+    double p_type[ORC_NTYPES];     /* sum of the outcome's probability over its choices */
+    double v_type[ORC_NTYPES];     /* sum of p (1 - p) over the same choices */
+} orc_stats;
 
 /* Full run.  batch_edep (n_batches*nvox, MeV), dose and sigma (nvox, MeV/g per
- * history) and hist_out (2*n_hist: deposited, escaped energy per history) may
- * each be NULL.  Returns 0 on success, nonzero on invalid input. */
+ * history), hist_out (2*n_hist: deposited, escaped energy per history) and
+ * hist_hard (n_hist: real hard events per history) may each be NULL.  Returns
+ * 0 on success, nonzero on invalid input. */
 int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph,
             const orc_source* src, const orc_params* prm,
             double* batch_edep, double* dose, double* sigma,
-            double* hist_out, orc_stats* st);
+            double* hist_out, uint32_t* hist_hard, orc_stats* st);
 
 /* ---- hooks used by the pin tests ---- */
 enum { ORC_MU_COMPTON = 0, ORC_MU_PHOTO, ORC_MU_PAIR, ORC_L_RESTRICTED, ORC_S_RAD_SOFT,
@@ -123,7 +139,10 @@ uint32_t orc_spawn_path(uint64_t seed, uint32_t job, uint64_t hist, uint32_t pat
                         uint32_t ctr, int word);
 /* which: 0 Compton (E) -> eps, cos; 1 Moller (T, wcc) -> eps; 2 bremsstrahlung
  * (T, wcb) -> k; 3 MW deflection (t) -> mu; 4 multiple-scattering walk of p2
- * hinges of t each -> Omega.Omega0; 5 annihilation pair -> cos1, dot(dir1, dir2) */
+ * hinges of t each -> Omega.Omega0; 5 annihilation pair -> cos1, dot(dir1, dir2);
+ * 6 pair production (E) -> T-/(E - 2mc^2), T- + T+ + a - E; 7 Compton (E) ->
+ * cos of the electron, cos of the photon (both against the incident direction).
+ * Samplers 0, 1, 2, 6 and 7 run the transport's own code on a particle along +z. */
 void orc_sample(int which, double e, double p1, double p2, uint64_t seed, int n,
                 double* out1, double* out2);
 /* source: n histories from hist0; out is n*8: E, beamlet, x, y, z, u, v, w

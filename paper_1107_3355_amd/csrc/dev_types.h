@@ -61,8 +61,11 @@ struct Ctl {
     uint32_t overflow;
     uint32_t n_valid;                 // records kept by the last compaction
     unsigned long long ev[8];
-    unsigned long long pass_ev[2][3];  // per pass type: records loaded, records
-                                       // stored, tally deposits
+    unsigned long long pass_ev[2][4];  // per pass type: records loaded, records
+                                       // stored, tally deposits, records handed
+                                       // to the next pass of the same type
+    unsigned long long itype[5];      // real interactions: Compton, photoelectric,
+                                       // pair, Moller, bremsstrahlung
     double red[4];                    // statistics reductions
     unsigned long long dmax_bits;
     unsigned long long anomalies;     // particles ended by a loop bound (0 in a sound run)

@@ -212,7 +212,7 @@ struct gdpm_context_s {
     int lds_tables = 1;          // stage interpolation tables in LDS when they fit
     int pass_histories = 0;      // new histories per iteration (0: half a queue less its fill)
     int autotune = 0;            // tune block size and re-binning online, queues from the work
-    int share = 1;               // new histories: 1 evenly over the jobs, 0 oldest job first
+    int share = 1;               // new histories: evenly over the jobs (the only policy)
     int rebin_photons = 0;       // 1: re-bin the photon queue also when one job holds all particles
     int rebin_electrons = 0;     // 1: the same for the electron queue
     int graphs = 1;              // replay each iteration's launches as a recorded HIP graph
@@ -234,6 +234,10 @@ struct gdpm_context_s {
     void* h_jc = nullptr;
     double* h_red = nullptr;
     double resident_bytes = 0.0;   // phantoms and sources alive in the context
+    // the autotuner's latest record: candidates, mean scores, the one kept (-1: undecided)
+    std::vector<std::pair<int, int>> tune_cand;
+    std::vector<double> tune_score;
+    int tune_kept = -1;
     std::vector<hipEvent_t> events;
     bool busy = false;
 };
@@ -292,6 +296,8 @@ namespace {
 
 constexpr int kMaxBlockThreads = 768;   // launch bound of the transport kernels
 constexpr int kMaxSegs = 4096;          // source segments per iteration (both types)
+constexpr int kMaxBatches = 1000;       // N_b of a job
+constexpr int kMaxGrid = 8192;          // nodes of an interpolation grid
 constexpr size_t kMaxStepGraphs = 32;   // launch settings an engine remembers
 uint64_t pow2_at_least(uint64_t n, uint64_t lo) {
     uint64_t p = lo;
@@ -354,6 +360,41 @@ gdpm_status ensure_rings(gdpm_context ctx) {
     return GDPM_OK;
 }
 
+// The device memory an engine runs in: the context's own buffers (queues
+// sized by ring_capacity_log2, two buffers per queue for the re-binning), or
+// fixed memory given to the engine (one buffer per queue: such an engine never
+// re-bins, records no graph and allocates nothing).
+struct EngineMem {
+    Particle* ring[2][2];
+    int ring_log2;
+    Ctl* ctl;
+    JobDev* jobs;
+    JobCtl* jc;
+    SrcSeg* segs;
+    SrcHdr* hdr;
+    double* inv_n;                 // kMaxBatches doubles
+    unsigned long long* counts;    // kMaxJobs counters
+    bool fixed;                    // given memory: no allocation, no graph, no re-binning
+};
+
+gdpm_status context_mem(gdpm_context ctx, EngineMem* m) {
+    gdpm_status e = ensure_rings(ctx);
+    if (e) return e;
+    memset(m, 0, sizeof *m);
+    for (int r = 0; r < 2; ++r)
+        for (int b = 0; b < 2; ++b) m->ring[r][b] = ctx->rings[r][b].as<Particle>();
+    m->ring_log2 = ctx->ring_log2;
+    m->ctl = ctx->ctl.as<Ctl>();
+    m->jobs = ctx->jobs_dev.as<JobDev>();
+    m->jc = ctx->jc.as<JobCtl>();
+    m->segs = ctx->segs.as<SrcSeg>();
+    m->hdr = ctx->src_hdr.as<SrcHdr>();
+    m->inv_n = ctx->inv_n.as<double>();
+    m->counts = ctx->counts.as<unsigned long long>();
+    m->fixed = false;
+    return GDPM_OK;
+}
+
 // persistent transport grid: one workgroup of waves_per_cu wavefronts per CU
 int grid_blocks(gdpm_context ctx) { return std::max(1, ctx->cu_count); }
 int block_threads(gdpm_context ctx) { return std::min(kMaxBlockThreads, 64 * ctx->waves_per_cu); }
@@ -372,7 +413,8 @@ struct RunPlan {
 gdpm_status validate_params(const gdpm_run_params* p, const gdpm_source_s* src, RunPlan* plan) {
     if (!p) return fail(GDPM_E_INVALID, "run parameters are NULL");
     plan->nb = p->n_batches == 0 ? 10 : p->n_batches;
-    if (plan->nb < 2 || plan->nb > 1000) return fail(GDPM_E_INVALID, "n_batches must be in [2, 1000]");
+    if (plan->nb < 2 || plan->nb > kMaxBatches)
+        return fail(GDPM_E_INVALID, "n_batches must be in [2, %d]", kMaxBatches);
     plan->ecut_g = p->ecut_photon_mev == 0.0 ? 0.05 : p->ecut_photon_mev;
     plan->ecut_e = p->ecut_electron_mev == 0.0 ? 0.2 : p->ecut_electron_mev;
     if (!(plan->ecut_g > 0.0 && plan->ecut_g < 1.0) || !(plan->ecut_e > 0.0 && plan->ecut_e < 5.0))
@@ -419,6 +461,11 @@ struct EJob {
     size_t nv = 0;
     DevBuf tally, mumax, hist, dose_buf, sigma_buf;
     DevBuf chains;               // Metropolis chain states of the job's source
+    // the job's device arrays: set by admit() from the buffers above, or given
+    // beforehand (an engine on fixed memory)
+    double* tally_p = nullptr;
+    float* mumax_p = nullptr;
+    uint32_t* chains_p = nullptr;
     double* d_dose = nullptr;   // outputs in device memory
     double* d_sigma = nullptr;
     uint64_t hbase = 0;         // id of the job's first history
@@ -449,6 +496,7 @@ size_t job_footprint(const gdpm_phantom_s* ph, const RunPlan& plan, bool own_out
 struct Engine {
     gdpm_context ctx = nullptr;
     hipStream_t st = nullptr;
+    EngineMem M{};              // device memory of the engine's queues and control blocks
     DevTables* tab = nullptr;
     TableKey key{};
     RunDev R{};
@@ -490,7 +538,7 @@ struct Engine {
     void tune_begin();
     void tune_account();
 
-    gdpm_status init(gdpm_context c, hipStream_t s, const RunPlan& plan);
+    gdpm_status init(gdpm_context c, hipStream_t s, const RunPlan& plan, const EngineMem* mem = nullptr);
     gdpm_status admit(EJob* j);
     gdpm_status step();
     gdpm_status issue(const StepGraphKey& k, bool recording);
@@ -506,7 +554,7 @@ struct Engine {
 
 void Engine::tune_begin() {
     tune = Tuner{};
-    tune.on = ctx->autotune != 0;
+    tune.on = ctx->autotune != 0 && !M.fixed;
     if (!tune.on) return;
     for (int w : {8, 12})
         for (int b : {1, 16}) tune.cand.emplace_back(w, b);
@@ -514,6 +562,9 @@ void Engine::tune_begin() {
     tune.samples.assign(tune.cand.size(), 0);
     ctx->waves_per_cu = tune.cand[0].first;
     ctx->rebin_bins = tune.cand[0].second;
+    ctx->tune_cand = tune.cand;
+    ctx->tune_score.assign(tune.cand.size(), 0.0);
+    ctx->tune_kept = -1;
 }
 
 // after an iteration: score the candidate it ran with, move to the next
@@ -529,6 +580,7 @@ void Engine::tune_account() {
     if (dev < 4000000ull || dt <= 0.0) return;   // too little work to score
     tune.score[tune.cur] += (double)dev / dt;
     tune.samples[tune.cur]++;
+    ctx->tune_score[tune.cur] = tune.score[tune.cur] / tune.samples[tune.cur];
     const int n = (int)tune.cand.size();
     tune.cur = (tune.cur + 1) % n;
     if (*std::min_element(tune.samples.begin(), tune.samples.end()) >= 2) {
@@ -537,48 +589,55 @@ void Engine::tune_account() {
             if (tune.score[i] / tune.samples[i] > tune.score[best] / tune.samples[best]) best = i;
         tune.cur = best;
         tune.fixed = true;
+        ctx->tune_kept = best;
     }
     ctx->waves_per_cu = tune.cand[tune.cur].first;
     ctx->rebin_bins = tune.cand[tune.cur].second;
 }
 
-gdpm_status Engine::init(gdpm_context c, hipStream_t s, const RunPlan& plan) {
+gdpm_status Engine::init(gdpm_context c, hipStream_t s, const RunPlan& plan, const EngineMem* mem) {
     drop_graphs();
     ctx = c;
     st = s;
     slots.assign(kMaxJobs, nullptr);
     n_slots = 0;
     key = TableKey{plan.ecut_g, plan.ecut_e, plan.flags & 0x3Fu};
-    gdpm_status e = get_tables(ctx, plan.ecut_g, plan.ecut_e, plan.flags, &tab);
-    if (e) return e;
-    e = ensure_rings(ctx);
-    if (e) return e;
+    gdpm_status e = GDPM_OK;
+    if (mem) {
+        // fixed memory: the table set must already be resident
+        auto it = ctx->tables.find(key);
+        if (it == ctx->tables.end())
+            return fail(GDPM_E_INVALID,
+                        "no resident tables for cutoffs (%g, %g) MeV and flags 0x%x: the default set is "
+                        "made by gdpm_set_materials, others by a first run of any other entry point",
+                        plan.ecut_g, plan.ecut_e, key.flags);
+        tab = it->second.get();
+        M = *mem;
+    } else {
+        e = get_tables(ctx, plan.ecut_g, plan.ecut_e, plan.flags, &tab);
+        if (e) return e;
+        e = context_mem(ctx, &M);
+        if (e) return e;
+    }
     T = tab->view(nullptr);
     Ctl* hc = ctx->host_ctl;
     memset(hc, 0, sizeof(Ctl));
     for (int r = 0; r < 2; ++r) hc->ring[r].head = hc->ring[r].tail = hc->ring[r].begin = ctx->ring_start;
-    HIP_TRY(hipMemcpyAsync(ctx->ctl.p, hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemsetAsync(ctx->jc.p, 0, sizeof(JobCtl), st));
+    HIP_TRY(hipMemcpyAsync(M.ctl, hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(M.jc, 0, sizeof(JobCtl), st));
     memset(ctx->h_jc, 0, kJcMirrorBytes);
     memset(&R, 0, sizeof R);
     R.ecut_g = (float)plan.ecut_g;
     R.ecut_e = (float)plan.ecut_e;
-    R.jobs = ctx->jobs_dev.as<const JobDev>();
-    R.jc = ctx->jc.as<JobCtl>();
+    R.jobs = M.jobs;
+    R.jc = M.jc;
     R.n_jobs = 0;
-    const uint32_t cap = 1u << ctx->ring_log2;
+    const uint32_t cap = 1u << M.ring_log2;
     for (int r = 0; r < 2; ++r) {
-        R.buf[r][0] = ctx->rings[r][0].as<Particle>();
-        R.buf[r][1] = ctx->rings[r][1].as<Particle>();
+        R.buf[r][0] = M.ring[r][0];
+        R.buf[r][1] = M.ring[r][1];
         R.mask[r] = cap - 1u;
         R.hard[r] = cap;
-    }
-    if (ctx->events.size() < 4) {
-        for (size_t i = ctx->events.size(); i < 4; ++i) {
-            hipEvent_t ev;
-            HIP_TRY(hipEventCreate(&ev));
-            ctx->events.push_back(ev);
-        }
     }
     tm = Timers{};
     iter = idle = 0;
@@ -610,10 +669,18 @@ gdpm_status Engine::admit(EJob* j) {
     std::vector<double> rmax(tab->host.n_mat, 0.0);
     for (size_t m = 0; m < j->ph->rho_max.size(); ++m) rmax[m] = j->ph->rho_max[m];
     const std::vector<float> mm = build_majorant(tab->host, rmax);
-    HIP_TRY(j->mumax.alloc(mm.size() * sizeof(float)));
-    HIP_TRY(hipMemcpyAsync(j->mumax.p, mm.data(), mm.size() * sizeof(float), hipMemcpyHostToDevice, st));
-    HIP_TRY(j->tally.alloc((size_t)plan.nb * nv * sizeof(double)));
-    HIP_TRY(hipMemsetAsync(j->tally.p, 0, (size_t)plan.nb * nv * sizeof(double), st));
+    if (M.fixed && (!j->mumax_p || !j->tally_p || !j->d_dose || !j->d_sigma))
+        return fail(GDPM_E_INVALID, "a job of an engine on fixed memory needs its arrays given");
+    if (!j->mumax_p) {
+        HIP_TRY(j->mumax.alloc(mm.size() * sizeof(float)));
+        j->mumax_p = j->mumax.as<float>();
+    }
+    HIP_TRY(hipMemcpyAsync(j->mumax_p, mm.data(), mm.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    if (!j->tally_p) {
+        HIP_TRY(j->tally.alloc((size_t)plan.nb * nv * sizeof(double)));
+        j->tally_p = j->tally.as<double>();
+    }
+    HIP_TRY(hipMemsetAsync(j->tally_p, 0, (size_t)plan.nb * nv * sizeof(double), st));
     if (!j->d_dose) {
         HIP_TRY(j->dose_buf.alloc(nv * sizeof(double)));
         j->d_dose = j->dose_buf.as<double>();
@@ -631,8 +698,8 @@ gdpm_status Engine::admit(EJob* j) {
     memset(&d, 0, sizeof d);
     d.G = geom_of(j->ph);
     d.S = j->src->view();
-    d.mumax = j->mumax.as<const float>();
-    d.tally = j->tally.as<double>();
+    d.mumax = j->mumax_p;
+    d.tally = j->tally_p;
     d.nv = nv;
     d.hist = hist;
     d.hist0 = j->prm.hist0;
@@ -645,13 +712,17 @@ gdpm_status Engine::admit(EJob* j) {
     d.gen = slot_gen[slot];
     if (j->src->metro) {
         // the job's Metropolis chains start afresh at its first history
-        HIP_TRY(j->chains.alloc(kMetroChains * sizeof(uint32_t)));
-        HIP_TRY(launch_metro_init(st, d.S, d.k0, d.k1, j->chains.as<uint32_t>()));
-        d.chains = j->chains.as<uint32_t>();
+        if (!j->chains_p) {
+            if (M.fixed) return fail(GDPM_E_INVALID, "a job of an engine on fixed memory needs its chain states given");
+            HIP_TRY(j->chains.alloc(kMetroChains * sizeof(uint32_t)));
+            j->chains_p = j->chains.as<uint32_t>();
+        }
+        HIP_TRY(launch_metro_init(st, d.S, d.k0, d.k1, j->chains_p));
+        d.chains = j->chains_p;
     }
-    HIP_TRY(hipMemcpyAsync(ctx->jobs_dev.as<JobDev>() + slot, &d, sizeof d, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(M.jobs + slot, &d, sizeof d, hipMemcpyHostToDevice, st));
     // the job's counters start from zero
-    JobCtl* dj = ctx->jc.as<JobCtl>();
+    JobCtl* dj = M.jc;
     HIP_TRY(hipMemsetAsync(&dj->births[slot], 0, sizeof(unsigned long long), st));
     HIP_TRY(hipMemsetAsync(&dj->deaths[slot], 0, sizeof(unsigned long long), st));
     HIP_TRY(hipMemsetAsync(&dj->e_in[slot], 0, sizeof(double), st));
@@ -685,11 +756,10 @@ void Engine::release(EJob* j) {
 gdpm_status Engine::step() {
     Ctl* hc = ctx->host_ctl;
     const int blocks = grid_blocks(ctx);
-    const uint32_t cap = 1u << ctx->ring_log2;
+    const uint32_t cap = 1u << M.ring_log2;
     // new histories: at most half a queue (or pass_histories) less what the
     // fuller queue holds, split evenly over the jobs that still start
-    // histories (option share = 0: the oldest job takes what it can use and
-    // younger jobs fill the rest)
+    // histories
     const uint32_t budget = ctx->pass_histories > 0 ? (uint32_t)ctx->pass_histories : cap / 2u;
     const uint32_t fill = std::max(hc->ring[0].tail - hc->ring[0].head, hc->ring[1].tail - hc->ring[1].head);
     uint64_t room = fill < budget ? budget - fill : 0u;
@@ -705,7 +775,7 @@ gdpm_status Engine::step() {
     const int seg_cap = kMaxSegs / 2;   // per source type
     for (size_t k = 0; k < want.size() && room > 0; ++k) {
         EJob* j = want[k];
-        const uint64_t share = ctx->share ? std::max<uint64_t>(1, room / (want.size() - k)) : room;
+        const uint64_t share = std::max<uint64_t>(1, room / (want.size() - k));
         uint64_t n = std::min<uint64_t>(share, j->sr_end - j->issued);
         const int ri = j->src->particle == 0 ? 0 : 1;
         while (n > 0 && nseg[ri] < seg_cap) {
@@ -760,7 +830,7 @@ gdpm_status Engine::step() {
     // read the true counts from the header), so a few recordings serve a run.
     // (A null stream cannot record; it never reaches here, a run without a
     // stream of its own uses the context's.)
-    const bool graph = ctx->graphs != 0 && st != nullptr;
+    const bool graph = ctx->graphs != 0 && st != nullptr && !M.fixed;
     StepGraphKey k;
     memset(&k, 0, sizeof k);
     k.st = st;
@@ -781,7 +851,7 @@ gdpm_status Engine::step() {
         // all particles (measured faster: with lanes refilled every iteration
         // energy order gains nothing, and push order keeps some spatial
         // locality), the pass then reads the queue as it is, empty slots included
-        k.rebin[ri] = (ri == 0 ? ctx->rebin_photons : ctx->rebin_electrons) || holders > 1 || lone < 0;
+        k.rebin[ri] = !M.fixed && ((ri == 0 ? ctx->rebin_photons : ctx->rebin_electrons) || holders > 1 || lone < 0);
         k.lds[ri] = ctx->lds_tables && transport_lds_bytes(ri, T, k.threads / 64) <= (size_t)ctx->max_lds;
         tm.passes++;
         (ri == 0 ? tm.passes_photon : tm.passes_electron)++;
@@ -808,7 +878,7 @@ gdpm_status Engine::step() {
     }
     if (hc->overflow)
         return fail(GDPM_E_OVERFLOW, "a particle queue filled up (capacity 2^%d); raise ring_capacity_log2",
-                    ctx->ring_log2);
+                    M.ring_log2);
     return GDPM_OK;
 }
 
@@ -817,12 +887,10 @@ gdpm_status Engine::step() {
 // disagreement is printed with the iteration's launch settings and queue state
 // and counted in the run statistics; the run goes on.
 gdpm_status Engine::check_accounting() {
-    HIP_TRY(ctx->counts.ensure(kMaxJobs * sizeof(unsigned long long)));
-    HIP_TRY(hipMemsetAsync(ctx->counts.p, 0, kMaxJobs * sizeof(unsigned long long), st));
-    HIP_TRY(launch_count_records(st, 4 * grid_blocks(ctx), ctx->ctl.as<const Ctl>(), R,
-                                 ctx->counts.as<unsigned long long>()));
+    HIP_TRY(hipMemsetAsync(M.counts, 0, kMaxJobs * sizeof(unsigned long long), st));
+    HIP_TRY(launch_count_records(st, 4 * grid_blocks(ctx), M.ctl, R, M.counts));
     std::vector<unsigned long long> live(kMaxJobs);
-    HIP_TRY(hipMemcpyAsync(live.data(), ctx->counts.p, kMaxJobs * sizeof(unsigned long long),
+    HIP_TRY(hipMemcpyAsync(live.data(), M.counts, kMaxJobs * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const JobCtlMirror* m = reinterpret_cast<const JobCtlMirror*>(ctx->h_jc);
@@ -849,13 +917,13 @@ gdpm_status Engine::check_accounting() {
 // electrons re-binning, set-up, transport (between two timing events) and
 // completion, then the read-back of the counters
 gdpm_status Engine::issue(const StepGraphKey& k, bool recording) {
-    Ctl* dc = ctx->ctl.as<Ctl>();
-    SrcHdr* dh = ctx->src_hdr.as<SrcHdr>();
+    Ctl* dc = M.ctl;
+    SrcHdr* dh = M.hdr;
     const int seg_cap = kMaxSegs / 2;
     HIP_TRY(hipMemcpyAsync(dh, ctx->h_hdr, 2 * sizeof(SrcHdr), hipMemcpyHostToDevice, st));
     for (int ri = 0; ri < 2; ++ri) {
         if (!k.seg_copy[ri]) continue;
-        SrcSeg* dseg = ctx->segs.as<SrcSeg>() + ri * seg_cap;
+        SrcSeg* dseg = M.segs + ri * seg_cap;
         HIP_TRY(hipMemcpyAsync(dseg, ctx->h_segs + ri * seg_cap, k.seg_copy[ri] * sizeof(SrcSeg),
                                hipMemcpyHostToDevice, st));
         HIP_TRY(launch_source(st, k.src_blocks[ri], dc, k.R, dseg, dh + ri, ri));
@@ -872,7 +940,7 @@ gdpm_status Engine::issue(const StepGraphKey& k, bool recording) {
         HIP_TRY(launch_finish(st, dc, ri));
     }
     HIP_TRY(hipMemcpyAsync(ctx->host_ctl, dc, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(ctx->h_jc, ctx->jc.p, kJcMirrorBytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ctx->h_jc, M.jc, kJcMirrorBytes, hipMemcpyDeviceToHost, st));
     return GDPM_OK;
 }
 
@@ -917,20 +985,19 @@ gdpm_status Engine::replay(const StepGraphKey& k) {
     return GDPM_OK;
 }
 
-gdpm_status compute_stats(gdpm_context ctx, EJob* j, hipStream_t st) {
+gdpm_status compute_stats(gdpm_context ctx, const EngineMem& M, EJob* j, hipStream_t st) {
     const int nb = j->plan.nb;
     const size_t nv = j->nv;
     std::vector<double> inv(nb);
     for (int b = 0; b < nb; ++b) inv[b] = j->nhist[b] > 0 ? 1.0 / j->nhist[b] : 0.0;
-    HIP_TRY(ctx->inv_n.ensure(nb * sizeof(double)));
-    HIP_TRY(hipMemcpyAsync(ctx->inv_n.p, inv.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
-    Ctl* dc = ctx->ctl.as<Ctl>();
+    HIP_TRY(hipMemcpyAsync(M.inv_n, inv.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
+    Ctl* dc = M.ctl;
     double* red = ctx->h_red;
     memset(red, 0, 4 * sizeof(double) + sizeof(unsigned long long));
     HIP_TRY(hipMemcpyAsync(&dc->red[0], red, 4 * sizeof(double) + sizeof(unsigned long long),
                            hipMemcpyHostToDevice, st));
     const int blocks = (int)std::min<size_t>((nv + 255) / 256, 8192);
-    HIP_TRY(launch_stats(st, blocks, dc, j->tally.as<const double>(), nv, nb, ctx->inv_n.as<const double>(),
+    HIP_TRY(launch_stats(st, blocks, dc, j->tally_p, nv, nb, M.inv_n,
                          j->ph->vox.as<const uint2>(), j->ph->dx * j->ph->dy * j->ph->dz,
                          (float)j->prm.stat_min_density, j->d_dose, j->d_sigma));
     HIP_TRY(hipMemcpyAsync(red, &dc->red[0], 4 * sizeof(double) + sizeof(unsigned long long),
@@ -958,7 +1025,7 @@ gdpm_status Engine::settle() {
         j->e_esc = m->e_esc[i];
         if (j->issued < j->sr_end || j->births != j->deaths) continue;
         progress = true;
-        gdpm_status s = compute_stats(ctx, j, st);
+        gdpm_status s = compute_stats(ctx, M, j, st);
         if (s) return s;
         j->rounds += (uint32_t)j->plan.nb;
         const gdpm_run_params& p = j->prm;
@@ -997,12 +1064,10 @@ gdpm_status Engine::settle() {
         // deaths differ.  Count the job's records on the device: if none is
         // left the counters drifted; align them and record the repair (it is
         // reported in the job's statistics), else stop with the numbers.
-        HIP_TRY(ctx->counts.ensure(kMaxJobs * sizeof(unsigned long long)));
-        HIP_TRY(hipMemsetAsync(ctx->counts.p, 0, kMaxJobs * sizeof(unsigned long long), st));
-        HIP_TRY(launch_count_records(st, 4 * grid_blocks(ctx), ctx->ctl.as<const Ctl>(), R,
-                                     ctx->counts.as<unsigned long long>()));
+        HIP_TRY(hipMemsetAsync(M.counts, 0, kMaxJobs * sizeof(unsigned long long), st));
+        HIP_TRY(launch_count_records(st, 4 * grid_blocks(ctx), M.ctl, R, M.counts));
         std::vector<unsigned long long> live(kMaxJobs);
-        HIP_TRY(hipMemcpyAsync(live.data(), ctx->counts.p, kMaxJobs * sizeof(unsigned long long),
+        HIP_TRY(hipMemcpyAsync(live.data(), M.counts, kMaxJobs * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         int repaired = 0;
@@ -1050,6 +1115,8 @@ void fill_stats(const Engine& E, const EJob* j, double t_start, gdpm_run_stats* 
     out->graph_launches = E.tm.graph_launches;
     out->graphs_recorded = E.tm.graphs_recorded;
     out->accounting_mismatches = E.mismatches;
+    for (int k = 0; k < 5; ++k) out->interactions[k] = hc->itype[k];
+    for (int k = 0; k < 2; ++k) out->records_requeued[k] = hc->pass_ev[k][3];
     out->t_photon_s = E.tm.photon;
     out->t_electron_s = E.tm.electron;
     out->t_kernel_s = E.tm.photon + E.tm.electron;
@@ -1068,6 +1135,7 @@ gdpm_status make_job(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const g
     return GDPM_OK;
 }
 
+// one job through the engine, blocking; outputs stay in device memory
 // one job through the engine, blocking; outputs stay in device memory
 gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdpm_run_params* prm,
                    double* d_dose, double* d_sigma, double* h_batch, double* h_hist,
@@ -1096,7 +1164,7 @@ gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdp
     }
     const size_t nv = j->nv;
     if (h_batch)
-        HIP_TRY(hipMemcpyAsync(h_batch, j->tally.p, (size_t)j->plan.nb * nv * sizeof(double),
+        HIP_TRY(hipMemcpyAsync(h_batch, j->tally_p, (size_t)j->plan.nb * nv * sizeof(double),
                                hipMemcpyDeviceToHost, st));
     if (h_hist)
         HIP_TRY(hipMemcpyAsync(h_hist, j->hist.p, j->plan.n_hist * 2 * sizeof(double),
@@ -1266,6 +1334,8 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
         return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);
     if (ctx->rebin_bins < 0 || ctx->rebin_bins > kMaxBins) return fail(GDPM_E_INVALID, "rebin_bins in [0, 64]");
     if (ctx->pass_histories < 0) return fail(GDPM_E_INVALID, "pass_histories must be >= 0");
+    if (ctx->share != 1)
+        return fail(GDPM_E_INVALID, "share must be 1: the oldest-job-first policy (0) can overflow the queues");
     HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device));
     HIP_TRY(hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device));
     if (ctx->lds_tables) {
@@ -1288,6 +1358,13 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     memset(ctx->h_hdr, 0, 2 * sizeof(SrcHdr));
     HIP_TRY(hipHostMalloc(&ctx->h_jc, kJcMirrorBytes, hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void**)&ctx->h_red, 8 * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(ctx->inv_n.alloc(kMaxBatches * sizeof(double)));
+    HIP_TRY(ctx->counts.alloc(kMaxJobs * sizeof(unsigned long long)));
+    for (int i = 0; i < 4; ++i) {   // timing events of the two transport passes
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreate(&ev));
+        ctx->events.push_back(ev);
+    }
     *out = ctx.release();
     return GDPM_OK;
 }
@@ -1312,7 +1389,7 @@ gdpm_status gdpm_set_materials(gdpm_context ctx, const gdpm_material* m, int n, 
     if (!ctx || !m) return fail(GDPM_E_INVALID, "NULL argument");
     if (n < 1 || n > kMaxMaterials) return fail(GDPM_E_INVALID, "1..%d materials", kMaxMaterials);
     if (n_grid == 0) n_grid = 1024;
-    if (n_grid < 256 || n_grid > 8192) return fail(GDPM_E_INVALID, "n_grid in [256, 8192]");
+    if (n_grid < 256 || n_grid > kMaxGrid) return fail(GDPM_E_INVALID, "n_grid in [256, %d]", kMaxGrid);
     std::vector<MaterialParams> mats(n);
     for (int i = 0; i < n; ++i) {
         if (!(m[i].z > 0) || !(m[i].z_over_a > 0) || !(m[i].i_ev > 0) || !std::isfinite(m[i].z) ||
@@ -1323,20 +1400,28 @@ gdpm_status gdpm_set_materials(gdpm_context ctx, const gdpm_material* m, int n, 
     ctx->mats = mats;
     ctx->n_grid = n_grid;
     ctx->tables.clear();
-    return GDPM_OK;
+    // the table set of the default absorption energies, resident from now on
+    HIP_TRY(hipSetDevice(ctx->device));
+    DevTables* t = nullptr;
+    return get_tables(ctx, 0.05, 0.2, 0u, &t);
 }
 
 gdpm_status gdpm_phantom_create(gdpm_context ctx, int nx, int ny, int nz, double dx, double dy,
                                 double dz, const uint8_t* mat, const float* density,
                                 gdpm_phantom* out) {
-    if (!ctx || !mat || !density || !out) return fail(GDPM_E_INVALID, "NULL argument");
+    if (!out) return fail(GDPM_E_INVALID, "NULL argument");
     *out = nullptr;
-    if (ctx->mats.empty()) return fail(GDPM_E_INVALID, "set materials first");
+    // the sizes first (host-only checks, testable without a device)
     if (nx < 1 || ny < 1 || nz < 1 || nx > 2048 || ny > 2048 || nz > 1024)
         return fail(GDPM_E_INVALID, "dimensions must be in [1,2048]x[1,2048]x[1,1024]");
+    if ((uint64_t)nx * (uint64_t)ny * (uint64_t)nz > (uint64_t)INT32_MAX)
+        return fail(GDPM_E_INVALID, "%d x %d x %d voxels: at most 2^31 - 1 voxels (the linear voxel "
+                    "index is a signed 32-bit integer)", nx, ny, nz);
     if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) || !std::isfinite(dy) ||
         !std::isfinite(dz))
         return fail(GDPM_E_INVALID, "voxel sizes must be positive");
+    if (!ctx || !mat || !density) return fail(GDPM_E_INVALID, "NULL argument");
+    if (ctx->mats.empty()) return fail(GDPM_E_INVALID, "set materials first");
     const size_t nv = (size_t)nx * ny * nz;
     std::vector<uint2> vox(nv);
     std::vector<double> rmax(ctx->mats.size(), 0.0);
@@ -1703,6 +1788,19 @@ gdpm_status gdpm_context_settings(gdpm_context ctx, int out[5]) {
     return GDPM_OK;
 }
 
+gdpm_status gdpm_context_tuning(gdpm_context ctx, int cap, int* n, int* cand, double* score, int* kept) {
+    if (!ctx || !n || !kept || cap < 0 || (cap > 0 && (!cand || !score)))
+        return fail(GDPM_E_INVALID, "NULL argument");
+    *n = (int)ctx->tune_cand.size();
+    *kept = ctx->tune_kept;
+    for (int i = 0; i < std::min(cap, *n); ++i) {
+        cand[2 * i] = ctx->tune_cand[i].first;
+        cand[2 * i + 1] = ctx->tune_cand[i].second;
+        score[i] = ctx->tune_score[i];
+    }
+    return GDPM_OK;
+}
+
 gdpm_status gdpm_job_wait(gdpm_job job, gdpm_run_stats* stats) {
     if (!job) return fail(GDPM_E_INVALID, "NULL job");
     if (job->srv) {
@@ -1901,7 +1999,7 @@ gdpm_status gdpm_test_atomic_rate(gdpm_context ctx, uint64_t bytes, double* ops_
 
 gdpm_status gdpm_test_sample(gdpm_context ctx, int which, double e, double p1, double p2,
                              uint64_t seed, int n, float* out1, float* out2) {
-    if (!ctx || !out1 || n < 1 || which < 0 || which > 5) return fail(GDPM_E_INVALID, "bad arguments");
+    if (!ctx || !out1 || n < 1 || which < 0 || which > 7) return fail(GDPM_E_INVALID, "bad arguments");
     HIP_TRY(hipSetDevice(ctx->device));
     DevTables* tab = nullptr;
     gdpm_status s = get_tables(ctx, 0.05, 0.2, 0u, &tab);

@@ -621,6 +621,8 @@ struct WaveTally {
     uint32_t ld, rq;      // records loaded from the queue, records handed on
     uint32_t born, died;  // records created and particles ended, current job
     uint32_t bad;         // particles ended by the iteration bound of a wavefront
+    uint32_t it[3];       // real interactions by type (photons: Compton,
+                          // photoelectric, pair; electrons: Moller, bremsstrahlung)
 };
 
 // Hand particles to the next pass of the same type (the record keeps the whole
@@ -826,6 +828,9 @@ GDPM_DEV void pass_finish(LaneTally& t, const WaveTally& c, Ctl* ctl, int ri) {
         atomicAdd(&ctl->pass_ev[ri][0], (unsigned long long)c.ld);
         atomicAdd(&ctl->pass_ev[ri][1], (unsigned long long)(c.pushes + c.rq));
         atomicAdd(&ctl->pass_ev[ri][2], (unsigned long long)ev[EV_DEPOSITS]);
+        if (c.rq) atomicAdd(&ctl->pass_ev[ri][3], (unsigned long long)c.rq);
+        for (int i = 0; i < (ri == 0 ? 3 : 2); ++i)
+            if (c.it[i]) atomicAdd(&ctl->itype[(ri == 0 ? 0 : 3) + i], (unsigned long long)c.it[i]);
     }
 }
 
@@ -898,6 +903,38 @@ GDPM_DEV void sample_iso(RngT<Q>& r, uint32_t k0, uint32_t k1, float& du, float&
     du = st * cos_turns(turns);
     dv = st * sin_turns(turns);
     dw = ct;
+}
+
+// Compton electron: along the momentum transfer E d0 - E' d of a photon
+// turned from d0 to d with E -> E' (no binding: momentum conservation)
+GDPM_DEV void compton_electron_dir(float e, float e1, float u0, float v0, float w0, float u, float v,
+                                   float w, float& eu, float& ev, float& ew) {
+    eu = e * u0 - e1 * u;
+    ev = e * v0 - e1 * v;
+    ew = e * w0 - e1 * w;
+    const float nn = eu * eu + ev * ev + ew * ew;
+    if (nn > 0.0f) {
+        const float in = hrsq(nn);
+        eu *= in; ev *= in; ew *= in;
+    } else {
+        eu = u0; ev = v0; ew = w0;
+    }
+}
+
+// pair production: K = E - 2 mc^2 split at the uniform u (T- = u K), the
+// larger part computed and the smaller taken as K minus it, so that
+// T- + T+ = K exactly; the positron keeps a = E - K
+GDPM_DEV void pair_split(float e, float u, float& tm, float& tp, float& aa) {
+    const float kk = e - kTwoMec2f;
+    aa = e - kk;
+    const float tc = u * kk;
+    if (2.0f * tc >= kk) {
+        tm = tc;
+        tp = kk - tc;
+    } else {
+        tp = kk - tc;
+        tm = kk - tp;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1266,7 +1303,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     PushState pg{0u, 0u}, pe{0u, 0u};
     LaneTally tl;
     tally_init(tl);
-    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u, {0u, 0u, 0u}};
     uint32_t iters = 0u;
     bool last_job = false;   // no other job has records left in this pass
     // one job at a time: a wavefront switches jobs with all its lanes empty
@@ -1362,12 +1399,14 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             {
                 const uint64_t br = ballot(pm >= 0);
                 if (br && (cs.done || (uint32_t)__popcll(br) >= kRealBatch || br == ballot(active))) {
+                    int itype = -1;   // the interaction sampled by this lane
                     if (pm >= 0) {
                         rng_deep(rng, k0, k1);
                         const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
                         const float4 mu = lerp4(ptab + pm * T.pg_n, gi, gt);
                         const float r = uniform(rng, k0, k1) * mu.w;
-                        if (r < mu.x) {
+                        itype = r < mu.x ? 0 : (r < mu.x + mu.y ? 1 : 2);
+                        if (itype == 0) {
                             float eps, t, turns;
                             sample_compton(rng, k0, k1, e, eps, t, turns);
                             const float u0 = u, v0 = v, w0 = w;
@@ -1386,20 +1425,13 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                             if (kerma || te <= ecut_e) {
                                 deposit(tl, W, pb, vv, te);
                             } else {
-                                // electron along the momentum transfer E d0 - E' d
-                                float eu = e * u0 - e1 * u, ev = e * v0 - e1 * v, ew = e * w0 - e1 * w;
-                                const float nn = eu * eu + ev * ev + ew * ew;
-                                if (nn > 0.0f) {
-                                    const float in = hrsq(nn);
-                                    eu *= in; ev *= in; ew *= in;
-                                } else {
-                                    eu = u0; ev = v0; ew = w0;
-                                }
+                                float eu, ev, ew;
+                                compton_electron_dir(e, e1, u0, v0, w0, u, v, w, eu, ev, ew);
                                 qe.n = 1; qe.e0 = te; qe.du = eu; qe.dv = ev; qe.dw = ew;
                                 qe.a0 = 0.0f; qe.role = 0u; qe.flag0 = 0u;
                             }
                             e = e1;
-                        } else if (r < mu.x + mu.y) {
+                        } else if (itype == 1) {
                             // photoelectric: the electron takes E along the photon
                             if (kerma || e <= ecut_e) {
                                 deposit(tl, W, pb, vv, e);
@@ -1410,16 +1442,8 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                             active = false;
                         } else {
                             // pair: uniform split of E - 2 mc^2; the positron keeps a = E - K
-                            const float kk = e - kTwoMec2f, aa = e - kk;
-                            const float tc = uniform(rng, k0, k1) * kk;
-                            float tm, tp;
-                            if (2.0f * tc >= kk) {
-                                tm = tc;
-                                tp = kk - tc;
-                            } else {
-                                tp = kk - tc;
-                                tm = kk - tp;
-                            }
+                            float tm, tp, aa;
+                            pair_split(e, uniform(rng, k0, k1), tm, tp, aa);
                             const bool e_local = kerma || tm <= ecut_e;
                             const bool p_local = kerma || tp <= ecut_e;
                             if (p_local) {
@@ -1444,6 +1468,8 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                         if (!active) history_flush(tl, W, rng.hlo, rng.hhi);
                         pm = -1;
                     }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) wt.it[i] += (uint32_t)__popcll(ballot(itype == i));
                 }
             }
             // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
@@ -1533,7 +1559,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     PushState pg{0u, 0u}, pe{0u, 0u};
     LaneTally tl;
     tally_init(tl);
-    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u, {0u, 0u, 0u}};
     uint32_t iters = 0u;
     bool last_job = false;   // no other job has records left in this pass
     // one job at a time: a wavefront switches jobs with all its lanes empty
@@ -1700,6 +1726,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
             {
                 const uint64_t bh = ballot(hq >= 0.0f);
                 if (bh && (cs.done || (uint32_t)__popcll(bh) >= kHardBatch || bh == ballot(active))) {
+                    int htype = -1;   // the hard event sampled by this lane
                     if (hq >= 0.0f) {
                         // delta scattering against the step-start majorant
                         // (mu_h grows with T; the step ended at e)
@@ -1708,7 +1735,8 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                         const float4 q1 = elec_at(T, etab, mat, e);
                         if (uniform(rng, k0, k1) * hq < q1.y) {
                             tl.ev[EV_HARD]++;
-                            if (uniform(rng, k0, k1) * q1.y < q1.z) {
+                            htype = uniform(rng, k0, k1) * q1.y < q1.z ? 0 : 1;
+                            if (htype == 0) {
                                 float eps, turns;
                                 const float tt = e;
                                 sample_moller(rng, k0, k1, tt, ecut, eps, turns);
@@ -1746,6 +1774,8 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                         nh = -1.0f;
                         hq = -1.0f;
                     }
+                    wt.it[0] += (uint32_t)__popcll(ballot(htype == 0));
+                    wt.it[1] += (uint32_t)__popcll(ballot(htype == 1));
                 }
             }
             wt.died += (uint32_t)__popcll(act0 & ~ballot(active));
@@ -2078,6 +2108,22 @@ __global__ void k_test_sample(Tables T, int which, float e, float p1, float p2, 
         sample_iso(r, k0, k1, du, dv, dw);
         a = dw;
         b = -(du * du + dv * dv + dw * dw);
+    } else if (which == 6) {
+        float tm, tp, aa;
+        pair_split(e, uniform(r, k0, k1), tm, tp, aa);
+        a = tm / (e - kTwoMec2f);
+        b = (tm + tp) - (e - kTwoMec2f);   // 0: the split is exact
+    } else if (which == 7) {
+        // the photon interaction's kinematics on a photon along +z
+        float eps, t, turns;
+        sample_compton(r, k0, k1, e, eps, t, turns);
+        float u = 0.0f, v = 0.0f, w = 1.0f;
+        rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
+        const float e1 = eps * e;
+        float eu, ev, ew;
+        compton_electron_dir(e, e1, 0.0f, 0.0f, 1.0f, u, v, w, eu, ev, ew);
+        a = ew;
+        b = w;
     }
     out1[i] = a;
     if (out2) out2[i] = b;

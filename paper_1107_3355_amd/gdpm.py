@@ -18,6 +18,7 @@ _lib = None
 
 NO_COMPTON, NO_PHOTO, NO_PAIR, NO_MS, NO_MOLLER, NO_BREMS, KERMA = 1, 2, 4, 8, 16, 32, 64
 EV_NAMES = ("flights", "real", "esteps", "hard_cand", "hard", "deposits", "pushes", "histories")
+INTERACTION_NAMES = ("compton", "photo", "pair", "moller", "brems")
 STATUS = {0: "GDPM_OK", 1: "GDPM_E_INVALID", 2: "GDPM_E_NOMEM", 3: "GDPM_E_DEVICE",
           4: "GDPM_E_OVERFLOW", 5: "GDPM_E_BUSY", 6: "GDPM_E_NOT_CONVERGED"}
 EXPORTS = ("gdpm_context_create", "gdpm_context_destroy", "gdpm_last_error", "gdpm_set_materials",
@@ -26,7 +27,7 @@ EXPORTS = ("gdpm_context_create", "gdpm_context_destroy", "gdpm_last_error", "gd
            "gdpm_job_release", "gdpm_tables_host", "gdpm_test_philox", "gdpm_test_sample",
            "gdpm_test_atomic_rate", "gdpm_test_source", "gdpm_test_lookup", "gdpm_run_batch", "gdpm_context_settings",
            "gdpm_server_create", "gdpm_server_submit", "gdpm_server_info_get",
-           "gdpm_server_destroy")
+           "gdpm_server_destroy", "gdpm_context_tuning")
 
 
 class GdpmError(RuntimeError):
@@ -77,7 +78,8 @@ class RunStats(C.Structure):
                 ("deposits", C.c_uint64 * 2), ("accounting_repairs", C.c_uint32),
                 ("accounting_gap", C.c_int64), ("transport_anomalies", C.c_uint64),
                 ("graph_launches", C.c_uint32), ("graphs_recorded", C.c_uint32),
-                ("accounting_mismatches", C.c_uint32)]
+                ("accounting_mismatches", C.c_uint32), ("interactions", C.c_uint64 * 5),
+                ("records_requeued", C.c_uint64 * 2)]
 
 
 class JobDesc(C.Structure):
@@ -127,6 +129,8 @@ def lib():
             "gdpm_run_batch": [vp, C.c_int, C.POINTER(JobDesc), C.POINTER(RunStats),
                                C.POINTER(C.c_int)],
             "gdpm_context_settings": [vp, C.POINTER(C.c_int)],
+            "gdpm_context_tuning": [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp,
+                                    C.POINTER(C.c_int)],
             "gdpm_server_create": [vp, C.c_uint64, C.c_int, C.POINTER(vp)],
             "gdpm_server_submit": [vp, C.POINTER(JobDesc), C.POINTER(vp)],
             "gdpm_server_info_get": [vp, C.POINTER(ServerInfo)],
@@ -247,7 +251,9 @@ def _stats_dict(st):
             "accounting_gap": int(st.accounting_gap),
             "transport_anomalies": int(st.transport_anomalies),
             "graph_launches": int(st.graph_launches), "graphs_recorded": int(st.graphs_recorded),
-            "accounting_mismatches": int(st.accounting_mismatches)}
+            "accounting_mismatches": int(st.accounting_mismatches),
+            "interactions": {k: int(st.interactions[i]) for i, k in enumerate(INTERACTION_NAMES)},
+            "records_requeued": [int(v) for v in st.records_requeued]}
 
 
 class Context:
@@ -276,6 +282,16 @@ class Context:
         _check(lib().gdpm_context_settings(self.handle, a))
         return dict(zip(("waves_per_cu", "rebin_bins", "ring_capacity_log2", "pass_histories",
                          "autotune"), list(a)))
+
+    def tuning(self):
+        """The autotuner's record: candidates (waves_per_cu, rebin_bins), their
+        mean scores (events per kernel second) and the index kept (-1: undecided)."""
+        n, kept = C.c_int(), C.c_int()
+        cand = (C.c_int * 128)()
+        score = (C.c_double * 64)()
+        _check(lib().gdpm_context_tuning(self.handle, 64, C.byref(n), cand, score, C.byref(kept)))
+        return ([(cand[2 * i], cand[2 * i + 1]) for i in range(n.value)],
+                [score[i] for i in range(n.value)], kept.value)
 
     def run_batch(self, jobs, want_dose=True):
         """Run several jobs together.  jobs: sequence of (phantom, source, params dict);

@@ -163,3 +163,20 @@ def test_mw_screening_table_matches_oracle():
         if k + 1 < n:
             a_mid = oracle.mw_A(2.0 ** (0.5 * (lt[k] + lt[k + 1])))
             assert abs(2.0 ** (0.5 * (t[k] + t[k + 1])) / a_mid - 1) < 2e-4
+
+
+def test_phantom_sizes_checked_before_the_device():
+    """The linear voxel index is a signed 32-bit integer on the device, so a
+    phantom of 2^31 voxels or more is rejected; the sizes are checked before
+    the context, so this runs without a GPU (NULL context, NULL arrays)."""
+    L = G.lib()
+    out = C.c_void_p()
+    for dims in ((2048, 2048, 512), (2048, 2048, 1024)):   # 2^31 and 2^32 voxels
+        st = L.gdpm_phantom_create(None, *dims, 0.1, 0.1, 0.1, None, None, C.byref(out))
+        assert st == 1
+        assert "2^31 - 1 voxels" in L.gdpm_last_error().decode()
+    # one voxel fewer than 2^31 passes the size checks and stops at the NULL context
+    st = L.gdpm_phantom_create(None, 2047, 2048, 512, 0.1, 0.1, 0.1, None, None, C.byref(out))
+    assert st == 1 and "NULL argument" in L.gdpm_last_error().decode()
+    st = L.gdpm_phantom_create(None, 2049, 1, 1, 0.1, 0.1, 0.1, None, None, C.byref(out))
+    assert st == 1 and "dimensions" in L.gdpm_last_error().decode()

@@ -29,6 +29,17 @@ def test_philox_bit_identical(gctx):
         assert np.array_equal(out[::10], ref)
 
 
+def test_philox_known_answer_vectors(gctx):
+    """The device generator against the published Philox4x32-10 vectors."""
+    import json
+    import os
+    kat = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.json")))
+    for vec in kat["vectors"]:
+        ctr = np.array([[int(x, 16) for x in vec["ctr"]]], dtype=np.uint32)
+        out = gctx.philox([int(x, 16) for x in vec["key"]], ctr)
+        assert [int(v) for v in out[0]] == [int(x, 16) for x in vec["out"]]
+
+
 def _close(a, b, rel):
     return np.abs(a - b) <= rel * np.maximum(np.abs(b), 1e-30)
 
@@ -234,3 +245,32 @@ def test_phase_space_source_lockstep(gctx):
     assert 0.9 < inside.mean() < 1.0
     np.testing.assert_allclose(g[inside, 2:5], o[inside, 2:5], atol=2e-4)
     np.testing.assert_array_equal(g[:, 0], o[:, 0].astype(np.float32))
+
+
+@pytest.mark.parametrize("e", [1.5, 6.0, 25.0])
+def test_pair_split(gctx, e):
+    """The kernel's pair split: T-/K uniform (same draws as the oracle's, so
+    equal to single-precision rounding) and T- + T+ = K exactly."""
+    ga, gb = gctx.sample(6, e, n=200_000, seed=19)
+    oa, _ = oracle.sample(6, e, n=200_000, seed=19)
+    assert np.all(gb == 0.0)
+    assert np.all(np.abs(ga - oa) <= 2e-6)
+    assert sst.kstest(ga, "uniform").pvalue > 1e-4
+
+
+@pytest.mark.parametrize("e", [0.1, 1.0, 6.0, 20.0])
+def test_compton_electron_direction(gctx, e):
+    """The kernel's Compton electron direction against the oracle's on the same
+    streams, and the two-body relation cot(theta_e) = (1 + k) tan(theta_g / 2)
+    to single precision."""
+    k = e / 0.51099895
+    ce, cg = gctx.sample(7, e, n=100_000, seed=23)
+    oe, og = oracle.sample(7, e, n=100_000, seed=23)
+    frac = np.mean((np.abs(ce - oe) <= 1e-4) & (np.abs(cg - og) <= 1e-4))
+    report("compton electron", e=e, lockstep=frac)
+    assert frac > 0.999
+    ce, cg = ce.astype(np.float64), cg.astype(np.float64)
+    se, sg = np.sqrt(np.maximum(0, 1 - ce * ce)), np.sqrt(np.maximum(0, 1 - cg * cg))
+    # single precision: cosines near 1 carry about 1e-7 absolute, sines near 0 about 5e-4
+    assert np.median(np.abs(ce * (1 + cg) - (1 + k) * sg * se)) < 1e-5 * (1 + k)
+    assert np.mean(np.abs(ce * (1 + cg) - (1 + k) * sg * se) < 1e-3 * (1 + k)) > 0.999

@@ -2,17 +2,30 @@
 
 Random numbers are an input of the method, not a formula of the paper (section
 2.2.2 replaces the CPU generator by a GPU library generator); the generator
-here is Philox4x32-10 (Salmon et al., SC'11).  Known-answer vectors of the
-published generator are not available in this environment, so the generator
-is pinned by the properties a uniform generator must have: the values lie on
-the stated 2^-24 grid inside (0,1), are uniform (chi-square), show no serial
-correlation, streams of different histories and paths are independent, and
-one counter bit changes about half of the output bits (avalanche)."""
+here is Philox4x32-10 (Salmon et al., SC'11).  It is pinned bit for bit by the
+published known-answer vectors (tests/golden/philox4x32_10_kat.json), and the
+stream mapping on top of it by the properties a uniform generator must have:
+the values lie on the stated 2^-24 grid inside (0,1), are uniform
+(chi-square), show no serial correlation, streams of different histories and
+paths are independent, and one counter bit changes about half of the output
+bits (avalanche)."""
+import json
+import os
+
 import numpy as np
 import pytest
 from scipy import stats as sst
 
 import oracle
+
+KAT = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.json")))
+
+
+@pytest.mark.parametrize("vec", KAT["vectors"])
+def test_philox_known_answer_vectors(vec):
+    ctr = [int(x, 16) for x in vec["ctr"]]
+    key = [int(x, 16) for x in vec["key"]]
+    assert oracle.philox(key, ctr) == [int(x, 16) for x in vec["out"]]
 
 
 def test_uniform_grid_and_range():
