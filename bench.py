@@ -54,12 +54,32 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_threads():
+    """Oracle threads: the host cores this process may use, at most 16 (a GPU
+    box gives each GPU a share of 16 cores, whatever the machine has)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def cpu_baseline(workload, seconds):
     """The oracle as it stands, on a bounded sample of the same job: a probe run
     sizes the sample so that the timed run takes about `seconds`."""
     import oracle
     from paper_1107_3355_amd import inputs as I
-    threads = min(os.cpu_count() or 1, 16)
+    threads = cpu_threads()
 
     def timed(n, hist0):
         t0 = time.perf_counter()
@@ -75,8 +95,10 @@ def cpu_baseline(workload, seconds):
     h0 = n1 + n2
     dt = timed(n, h0)
     return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "per_core": n / dt / threads, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{n} histories (ids {h0}..{h0 + n - 1}) of the same CT IMRT job, FP64 CPU "
-                      f"transport on {threads} threads, {dt:.1f} s including the run set-up"}
+                      f"transport on {threads} threads ({cpu_model()}; the host shows "
+                      f"{os.cpu_count()} CPUs, a GPU's share is 16), {dt:.1f} s including the run set-up"}
 
 
 def pct(a, q):
@@ -185,77 +207,154 @@ def log_accounting(what, res):
                 f"histories {r['histories']}, passes {r['passes']}")
 
 
-def served_form(G, I, seconds, rate, ct, opts=None):
+def run_stream(G, ctx, hs, times, slots, budget, label):
+    """Submit the requests at their arrival times to a server with at most
+    `slots` jobs running together; returns per-request latency (submission to
+    completion), histories and the span from the first arrival to the last
+    completion."""
+    srv = G.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
+    jobs = []
+    t0 = time.perf_counter()
+    for t, (p, s, kw) in zip(times, hs):
+        d = t - (time.perf_counter() - t0)
+        if d > 0:
+            time.sleep(d)
+        jobs.append(srv.submit(p, s, want_dose=False, **kw))
+    res = []
+    for k, j in enumerate(jobs):
+        res.append(j.wait())
+    wall = time.perf_counter() - t0
+    info = srv.info()
+    srv.close()
+    lat = [r["t_total_s"] for r in res]
+    hist = sum(r["histories"] for r in res)
+    log_accounting(label, res)
+    log(f"{label}: p50 {pct(lat, 50):.2f} s, p99 {pct(lat, 99):.2f} s, span {wall - times[0]:.2f} s")
+    return {"seconds": wall, "histories_per_s": hist / max(wall - times[0], 1e-9),
+            "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(np.mean(lat)),
+                          "max": float(np.max(lat))},
+            "memory_high_water_bytes": info["high_water_bytes"] + info["resident_bytes"],
+            "energy_balance_max": max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res),
+            "accounting_repairs": sum(r["accounting_repairs"] for r in res)}
+
+
+def fifo_latencies(times, service):
+    """Latencies of the requests run one at a time in arrival order, from their
+    arrival times and measured alone run times (a single-server queue)."""
+    done, lat = 0.0, []
+    for t, s in zip(times, service):
+        done = max(done, t) + s
+        lat.append(done - t)
+    return lat, done
+
+
+def served_form(G, I, seconds, rate, ct, opts=None, load=0.7):
     """Poisson request stream (VMAT arcs on the 256x256x128 CT and IMRT jobs on a
-    128x128x64 CT, to 1% or 2%) into a server that admits by device footprint and
-    batches the admitted jobs, against the same requests run one at a time in
-    arrival order (queueing latency from the arrival times and measured run
-    times)."""
-    import threading
+    128x128x64 CT, to 1% or 2%) into a server that admits by device footprint
+    and batches the admitted jobs.  Each request's run time alone gives the
+    service demand and the capacity (jobs/s) of one GPU for this mix; the
+    stream is served at the stated rate and, stretched in time, at `load` of
+    the capacity (a stable queue), by three policies: one job at a time in
+    arrival order (per-job launches), even sharing among up to 64 jobs, and up
+    to 64 jobs with the least remaining work first."""
     reqs = I.serving_requests(duration_s=seconds, rate=rate, ct=ct)
-    ctx = G.Context(0, opts=opts, materials=I.MATERIALS)
-    phs, hs = {}, []
-    for k, (t, w) in enumerate(reqs):
-        key = id(w.phantom)
-        if key not in phs:
-            phs[key] = ctx.phantom(w.phantom)
-        hs.append((t, phs[key], ctx.source(w.source),
-                   dict(seed=500 + k, job_id=k, n_hist=w.n_hist, target_unc=w.target_unc,
-                        stat_min_density=0.1)))
-    ctx.run(hs[0][1], hs[0][2], n_hist=10_000, want_dose=False)   # tables and queues
+    times = [t for t, _ in reqs]
     budget = 64 << 30
-    served = {}
-    hist = 0
-    bal, repairs = 0.0, 0
-    for slots in (1, 2, 64):
-        log(f"served form: {len(reqs)} requests, at most {slots} running together")
-        srv = G.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
-        jobs = []
-        t0 = time.perf_counter()
-        for t, p, s, kw in hs:
-            d = t - (time.perf_counter() - t0)
-            if d > 0:
-                time.sleep(d)
-            jobs.append(srv.submit(p, s, want_dose=False, **kw))
-        res = []
-        for k, j in enumerate(jobs):
-            res.append(j.wait())
-            log(f"served form: request {k} done after {res[-1]['t_total_s']:.2f} s")
-        wall = time.perf_counter() - t0
-        info = srv.info()
-        srv.close()
-        lat = [r["t_total_s"] for r in res]
-        hist = sum(r["histories"] for r in res)
-        bal = max(bal, max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res))
-        repairs += sum(r["accounting_repairs"] for r in res)
-        log_accounting(f"served form, {slots} slots", res)
-        served[f"slots_{slots}"] = {
-            # throughput over the span from the first arrival to the last completion
-            "seconds": wall, "histories_per_s": hist / max(wall - hs[0][0], 1e-9),
-            "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
-            "memory_high_water_bytes": info["high_water_bytes"] + info["resident_bytes"]}
-    # the same requests, one plain run at a time in arrival order
-    run_s, done, lat_seq = [], 0.0, []
-    for k, (t, p, s, kw) in enumerate(hs):
+    out = {"workload": f"Poisson {rate} jobs/s for {seconds} s: {len(reqs)} requests, VMAT-180 on "
+                       "256x256x128 CT or IMRT-9 on 128x128x64 CT, to 1% or 2%",
+           "requests": len(reqs), "hbm_budget_bytes": budget}
+    ctxs = {}
+    for name, o in (("fifo", opts), ("least_work_first", '{"issue_order": 1}')):
+        ctxs[name] = G.Context(0, opts=o, materials=I.MATERIALS)
+    hs = {name: [] for name in ctxs}
+    for name, ctx in ctxs.items():
+        phs = {}
+        for k, (t, w) in enumerate(reqs):
+            key = id(w.phantom)
+            if key not in phs:
+                phs[key] = ctx.phantom(w.phantom)
+            hs[name].append((phs[key], ctx.source(w.source),
+                             dict(seed=500 + k, job_id=k, n_hist=w.n_hist, target_unc=w.target_unc,
+                                  stat_min_density=0.1)))
+        ctx.run(hs[name][0][0], hs[name][0][1], n_hist=10_000, want_dose=False)   # tables and queues
+    # service demand: every request alone, back to back
+    ctx = ctxs["fifo"]
+    service, hist = [], 0
+    for k, (p, s, kw) in enumerate(hs["fifo"]):
         a = time.perf_counter()
         r = ctx.run(p, s, want_dose=False, **kw)
+        service.append(time.perf_counter() - a)
+        hist += r["histories"]
         log_accounting(f"served form, request {k} alone", [r])
-        repairs += r["accounting_repairs"]
-        log(f"served form: request {k} alone in {time.perf_counter() - a:.2f} s")
-        run_s.append(time.perf_counter() - a)
-        done = max(done, t) + run_s[-1]
-        lat_seq.append(done - t)
-    for _, _, s, _ in hs:
-        s.close()
-    for p in phs.values():
+    mean_s = float(np.mean(service))
+    out["service_s"] = {"mean": mean_s, "p50": pct(service, 50), "max": float(np.max(service)),
+                        "total": float(np.sum(service))}
+    out["capacity_jobs_per_s"] = 1.0 / mean_s
+    out["utilisation_at_stated_rate"] = rate * mean_s
+    out["histories"] = hist
+    log(f"served form: mean service {mean_s:.3f} s, capacity {1 / mean_s:.2f} jobs/s, "
+        f"load {rate * mean_s:.2f} at {rate} jobs/s")
+    streams = [("stated_rate", rate, times)]
+    rate_s = load / mean_s
+    streams.append((f"load_{load:g}", rate_s, [t * rate / rate_s for t in times]))
+    for sname, r_s, ts in streams:
+        lat, done = fifo_latencies(ts, service)
+        res = {"rate_jobs_per_s": r_s, "utilisation": r_s * mean_s,
+               "one_at_a_time_replayed": {"latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99),
+                                                        "mean": float(np.mean(lat)), "max": float(np.max(lat))},
+                                          "histories_per_s": hist / max(done - ts[0], 1e-9)}}
+        res["per_job_launches"] = run_stream(G, ctxs["fifo"], hs["fifo"], ts, 1, budget,
+                                             f"served {sname}: one job at a time")
+        res["shared_even"] = run_stream(G, ctxs["fifo"], hs["fifo"], ts, 64, budget,
+                                        f"served {sname}: 64 slots, even shares")
+        res["shared_least_work_first"] = run_stream(G, ctxs["least_work_first"], hs["least_work_first"], ts,
+                                                    64, budget, f"served {sname}: 64 slots, least work first")
+        out[sname] = res
+    for name, ctx in ctxs.items():
+        done_ph = set()
+        for p, s, _ in hs[name]:
+            s.close()
+            if id(p) not in done_ph:
+                done_ph.add(id(p))
+                p.close()
+        ctx.close()
+    return out
+
+
+def config_rates(G, I, args):
+    """Configs 1, 2A and 2B at their stated phantoms and history counts: GPU
+    histories/s of a fixed-count job with the inputs resident (the dose left on
+    the device), and the oracle's histories/s on a bounded sample of the same
+    job (the paper's Table 2 rows, CPU against GPU, on synthetic inputs)."""
+    import oracle
+    threads = cpu_threads()
+    cases = [("config1_water32_2MeV_parallel", I.water_cube_2mev(), 200_000, 200_000),
+             ("config2A_slab100_6MVlike_point", I.slab_photon(), 10_000_000, 200_000),
+             ("config2B_slab100_20MeV_electron_point", I.slab_electron(), 10_000_000, 20_000)]
+    ctx = G.Context(0, opts=args.opts, materials=I.MATERIALS)
+    out = {}
+    for name, w, n, n_cpu in cases:
+        p, s = ctx.phantom(w.phantom), ctx.source(w.source)
+        ctx.run(p, s, n_hist=min(n, 200_000), seed=2, want_dose=False)
+        t0 = time.perf_counter()
+        r = ctx.run(p, s, n_hist=n, seed=1, want_dose=False)
+        dt = time.perf_counter() - t0
+        res = {"histories": n, "gpu_seconds": dt, "gpu_histories_per_s": n / dt,
+               "energy_balance": abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"]}
+        if not args.no_cpu_baseline:
+            t0 = time.perf_counter()
+            oracle.run(I.MATERIALS, w.phantom, w.source, seed=7, n_hist=n_cpu, n_batches=10,
+                       n_threads=threads, want_batches=False)
+            dc = time.perf_counter() - t0
+            res.update(oracle_histories=n_cpu, oracle_seconds=dc, oracle_histories_per_s=n_cpu / dc,
+                       oracle_threads=threads, gpu_over_oracle=(n / dt) / (n_cpu / dc))
+        out[name] = res
+        log(f"configs: {name}: GPU {n / dt:.4g} hist/s" +
+            (f", oracle {res['oracle_histories_per_s']:.4g} hist/s" if "oracle_seconds" in res else ""))
         p.close()
+        s.close()
     ctx.close()
-    return {"workload": f"Poisson {rate} jobs/s for {seconds} s: {len(reqs)} requests, VMAT-180 on "
-                        "256x256x128 CT or IMRT-9 on 128x128x64 CT, to 1% or 2%",
-            "histories": hist, "energy_balance_max": bal, "accounting_repairs": repairs,
-            "hbm_budget_bytes": budget, "served": served,
-            "one_at_a_time": {"seconds": max(done, 0.0), "histories_per_s": hist / max(done - hs[0][0], 1e-9),
-                              "latency_s": {"p50": pct(lat_seq, 50), "p99": pct(lat_seq, 99)}}}
+    return out
 
 
 def profiled_values(path):
@@ -337,9 +436,15 @@ def main():
                          "timed jobs (a reference kernel of known traffic for hardware counters)")
     ap.add_argument("--batched-jobs", type=int, default=64,
                     help="jobs of the batched-form comparison (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=4.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the served request stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2.0, help="requests per second")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="utilisation of the stable stream (the stated stream stretched in time)")
+    ap.add_argument("--configs", type=int, default=1,
+                    help="1: also time configs 1, 2A and 2B on the GPU and the oracle")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the served form (a long stream's record), no CT jobs")
     ap.add_argument("--source-modes", type=int, default=1,
                     help="1: also run the CT job with the other source modes (section 2.3)")
     ap.add_argument("--min-density", type=float, default=0.1,
@@ -357,6 +462,11 @@ def main():
 
     log("building the synthetic CT workload")
     w = I.ct_imrt(target_unc=args.target)
+    if args.serve_only:
+        log(f"served form only: {args.serve_seconds} s of requests at {args.serve_rate}/s")
+        res = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom, args.opts, args.serve_load)
+        print(json.dumps({"served_form": res}), flush=True)
+        return
     ctx = G.Context(0, opts=args.opts, materials=I.MATERIALS)
     ph = ctx.phantom(w.phantom)
     src = ctx.source(w.source)
@@ -370,12 +480,12 @@ def main():
         reference_copy(args.copy_mib << 20)
         log(f"reference copy: {args.copy_mib} MiB read, {args.copy_mib} MiB written")
 
-    n0 = args.n0
     for i in range(args.warmup):
         r = job(1000 + i)
         log(f"warmup {i}: {r['histories']} histories, unc {r['unc']:.5f}, {r['t_total_s']:.2f} s")
-        n0 = r["histories"]
-    args.n0 = n0   # start timed jobs from the history count the warmup needed
+    # every timed job starts cold, from the same first estimate of its histories
+    # (n0), as a new plan would: a first super-round of n0 histories, then the
+    # histories the 1/sqrt(N) law asks for
     runs = []
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -442,6 +552,7 @@ def main():
                    "voxel_cm": [0.2, 0.2, 0.25], "beams": 9, "beamlets": 9 * 1600,
                    "spectrum": "triangular 0.25-1.2-6 MeV", "target_unc": args.target,
                    "n_batches": 10, "histories_per_job": int(np.mean([r["histories"] for r in runs])),
+                   "first_estimate": args.n0, "rounds_per_job": float(np.mean([r["rounds"] for r in runs])),
                    "stat_min_density": args.min_density,
                    "tally": "f64"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
@@ -462,8 +573,11 @@ def main():
         out["source_modes"] = source_modes(G, I, w, args)
     if args.serve_seconds > 0:
         log(f"served form: {args.serve_seconds} s of requests at {args.serve_rate}/s")
-        out["served_form"] = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom, args.opts)
-        log("served form: p50/p99 " + str({k: v["latency_s"] for k, v in out["served_form"]["served"].items()}))
+        out["served_form"] = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom, args.opts,
+                                         args.serve_load)
+    if args.configs:
+        log("configs 1, 2A, 2B")
+        out["configs"] = config_rates(G, I, args)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

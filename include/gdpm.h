@@ -118,9 +118,8 @@ typedef struct {
      * of equal width over the spectrum's support: a round of R histories gives
      * positions C_k <= i < C_{k+1}, C_k = floor(R F(e_k) + 1/2), to interval k
      * (F the spectrum's CDF at the interval's lower edge), so a round runs
-     * through the intervals in increasing energy, and inside its interval a
-     * history's energy follows the spectrum (inverse CDF at F_k + u (F_{k+1} -
-     * F_k)). */
+     * through the intervals in increasing energy; inside its interval a
+     * history's energy is uniform or follows the spectrum (strata_shape). */
     int spectrum_strata;
     /* the open source interface (section 2.3.3): n_phase_space > 0 records of
      * 7 floats each, x, y, z (cm, phantom frame), u, v, w (unit vector, norm
@@ -131,6 +130,11 @@ typedef struct {
      * modes above are then unused (n_beams may be 0). */
     uint64_t n_phase_space;
     const float* phase_space;
+    /* energy inside an interval of spectrum_strata: 0, uniform between the
+     * interval's edges (the paper's rule, section 2.3.2: the spectrum becomes
+     * its histogram over the intervals); 1, the spectrum's own shape (inverse
+     * CDF at F_k + u (F_{k+1} - F_k): the spectrum exactly). */
+    int strata_shape;
 } gdpm_source_desc;
 
 #define GDPM_METRO_CHAINS 16384
@@ -233,7 +237,15 @@ typedef struct {
  * 1, the only value accepted, evenly; 0, oldest job first, is rejected with
  * GDPM_E_INVALID: a job taking the whole history budget of an iteration can
  * overflow the queues, whose budget assumes few secondaries per history),
- * "autotune" (see gdpm_context_settings), "graphs" (1, default: a
+ * "issue_order" (which jobs of a batch or server start their histories
+ * first: 0, default, an even share of each iteration's budget for every job
+ * still starting histories; 1, the job with the fewest histories left in its
+ * planned super-round first, taking what it can use, then the next: shortest
+ * remaining work first, so that a small job admitted beside a large one is
+ * not slowed down by it),
+ * "autotune" (see gdpm_context_settings), "autotune_min_events" (transport
+ * events, photon flights plus electron steps, an iteration must have for the
+ * autotuner to score it; default 4000000), "graphs" (1, default: a
  * scheduler iteration's launches, copies included, are recorded as a HIP
  * graph the second time their launch configuration occurs in a run, and
  * replayed from then on, on the stream of the run; each run, batch or server
@@ -277,8 +289,9 @@ gdpm_status gdpm_set_materials(gdpm_context ctx, const gdpm_material* m, int n, 
 
 /* nx, ny <= 2048, nz <= 1024 and nx*ny*nz <= 2^31 - 1 (the linear voxel index
  * is a signed 32-bit integer on the device); mat[v] < number of materials;
- * density[v] > 0 and finite.  Both arrays (nx*ny*nz) are copied to device
- * memory.  The sizes are checked before anything else (a NULL context with
+ * density[v] in [2^-16, 2^16) g/cm^3 (a voxel is stored in 4 bytes: the
+ * density's exact single-precision value and the material).  Both arrays
+ * (nx*ny*nz) are copied to device memory.  The sizes are checked before anything else (a NULL context with
  * bad sizes reports the sizes). */
 gdpm_status gdpm_phantom_create(gdpm_context ctx, int nx, int ny, int nz, double dx, double dy,
                                 double dz, const uint8_t* mat, const float* density,

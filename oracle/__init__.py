@@ -44,7 +44,7 @@ class Source(C.Structure):
                 ("spec_e", C.POINTER(C.c_double)), ("spec_p", C.POINTER(C.c_double)),
                 ("e_mono", C.c_double), ("n_beams", C.c_int), ("beams", C.POINTER(Beam)),
                 ("beamlet_sampler", C.c_int), ("spectrum_strata", C.c_int),
-                ("n_phsp", C.c_uint64), ("phsp", C.POINTER(C.c_float))]
+                ("n_phsp", C.c_uint64), ("phsp", C.POINTER(C.c_float)), ("strata_shape", C.c_int)]
 
 
 class Params(C.Structure):
@@ -145,6 +145,7 @@ def _source(src, keep):
     sp = src.spectrum
     s = Source(src.particle, sp.kind, 0, None, None, sp.e_mono, len(src.beams), beams,
                getattr(src, "beamlet_sampler", 0), getattr(src, "spectrum_strata", 0))
+    s.strata_shape = getattr(src, "strata_shape", 0)
     ps = getattr(src, "phase_space", None)
     if ps is not None:
         ps = keep.arr(ps, np.float32).reshape(-1, 7)

@@ -406,6 +406,7 @@ typedef struct {
     double* spec_c;   /* cumulative spectrum at spec_e */
     double* f;        /* beamlet intensities (negative ones as 0) */
     double* strata_F; /* spectrum CDF at the K + 1 interval edges (stratified spectra) */
+    double* strata_e; /* the K + 1 interval edges (MeV) */
     int* metro_bl;    /* Metropolis mode: beamlet of history metro_h0 + i */
     uint64_t metro_h0;
     orc_params prm;
@@ -886,21 +887,31 @@ static void strata_setup(ctx_t* c) {
     const orc_source* s = c->src;
     int K = s->spectrum_strata;
     c->strata_F = (double*)malloc(sizeof(double) * (K + 1));
+    c->strata_e = (double*)malloc(sizeof(double) * (K + 1));
     double e0 = s->spec_e[0], e1 = s->spec_e[s->spec_n - 1];
-    for (int k = 0; k <= K; ++k) c->strata_F[k] = spectrum_cdf(c, e0 + (e1 - e0) * k / K);
+    for (int k = 0; k <= K; ++k) {
+        c->strata_e[k] = e0 + (e1 - e0) * k / K;
+        c->strata_F[k] = spectrum_cdf(c, c->strata_e[k]);
+    }
     c->strata_F[0] = 0.0;
     c->strata_F[K] = 1.0;
+    c->strata_e[K] = e1;
 }
 
 /* energy of history h in a stratified run: its position i in its round of R
  * histories picks the interval k with C_k <= i < C_{k+1}, C_k = floor(R F_k +
- * 1/2); the energy is the spectrum's inverse CDF at F_k + u (F_{k+1} - F_k) */
+ * 1/2) (the round's histories shared among the intervals by the spectrum, in
+ * increasing energy); inside the interval the energy is uniform, e_k + u
+ * (e_{k+1} - e_k) (the paper's rule), or, with strata_shape 1, the spectrum's
+ * inverse CDF at F_k + u (F_{k+1} - F_k) */
 static double stratified_energy(const ctx_t* c, uint64_t h, double u) {
     uint64_t off = h - c->prm.hist0, R = c->prm.round_size, N = c->prm.n_hist;
     uint64_t a = off / R * R, b = a + R < N ? a + R : N;
     double i = (double)(off - a), size = (double)(b - a);
     int K = c->src->spectrum_strata, k = 0;
     while (k < K - 1 && floor(size * c->strata_F[k + 1] + 0.5) <= i) ++k;
+    if (c->src->strata_shape == 0)
+        return c->strata_e[k] + u * (c->strata_e[k + 1] - c->strata_e[k]);
     return spectrum_energy(c, c->strata_F[k] + u * (c->strata_F[k + 1] - c->strata_F[k]));
 }
 
@@ -1129,6 +1140,7 @@ static int validate(const orc_material* mats, int n_mat, const orc_phantom* ph,
         if (src->beamlet_sampler != 0 && src->beamlet_sampler != 1) return 1;
         if (src->spectrum_strata < 0 || src->spectrum_strata > 64) return 1;
         if (src->spectrum_strata > 0 && src->spec_kind != 1) return 1;
+        if (src->strata_shape != 0 && src->strata_shape != 1) return 1;
         if (src->spec_kind == 0 && !(src->e_mono > 0)) return 1;
         if (src->spec_kind == 1 && (src->spec_n < 2 || !src->spec_e || !src->spec_p)) return 1;
     }
@@ -1196,7 +1208,7 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
     }
     if (bad) {
         free(c.mats); free(c.cdf); free(c.beam_of); free(c.beam_off); free(c.spec_c);
-        free(c.f); free(c.metro_bl); free(c.strata_F);
+        free(c.f); free(c.metro_bl); free(c.strata_F); free(c.strata_e);
         return 1;
     }
 
@@ -1269,7 +1281,7 @@ int orc_run(const orc_material* mats, int n_mat, const orc_phantom* ph, const or
     if (!batch_edep) free(slots);
     free(nhist); free(jobs); free(th);
     free(c.mats); free(c.cdf); free(c.beam_of); free(c.beam_off); free(c.spec_c);
-    free(c.f); free(c.metro_bl); free(c.strata_F);
+    free(c.f); free(c.metro_bl); free(c.strata_F); free(c.strata_e);
     return 0;
 }
 
@@ -1469,6 +1481,6 @@ int orc_sample_source(const orc_source* src, const orc_phantom* ph, uint64_t see
         }
     }
     free(c.cdf); free(c.beam_of); free(c.beam_off); free(c.spec_c);
-    free(c.f); free(c.metro_bl); free(c.strata_F);
+    free(c.f); free(c.metro_bl); free(c.strata_F); free(c.strata_e);
     return 0;
 }

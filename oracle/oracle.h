@@ -57,13 +57,15 @@ typedef struct {
                              equal width over the spectrum's support; a round of R
                              histories gives positions C_k <= i < C_{k+1}, C_k =
                              floor(R F(e_k) + 1/2), to interval k, in increasing energy,
-                             and the energy follows the spectrum inside the interval */
+                             and inside the interval the energy is uniform (strata_shape
+                             0, the paper's) or follows the spectrum (strata_shape 1) */
     uint64_t n_phsp;      /* > 0: a phase space (section 2.3.3, the open source
                              interface): history h starts as record h mod n_phsp of
                              phsp; beams and spectrum are then unused */
     const float* phsp;    /* n_phsp records x, y, z, u, v, w, E (cm, unit vector, MeV): a
                              record inside the phantom starts where it is, one outside
                              moves forward to its entry point or escapes; no draws */
+    int strata_shape;     /* energy inside an interval: 0 uniform, 1 the spectrum's shape */
 } orc_source;
 
 /* Metropolis beamlet sampling: the run's histories form this many chains,

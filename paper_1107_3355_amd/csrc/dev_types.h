@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 namespace gdpm {
 
@@ -105,8 +106,32 @@ struct Tables {
     int n_mat;
 };
 
+// A voxel of the phantom in 4 bytes: the density's single-precision mantissa
+// (bits 0-22), its exponent less kVoxExpBias (bits 23-27: densities in
+// [2^-16, 2^16) g/cm^3, every single-precision value there exactly) and the
+// material id (bits 28-31).  Half the bytes of a {density, material} pair, so
+// the random voxel gathers of the transport touch half the cache lines.
+constexpr uint32_t kVoxExpBias = 111u;   // single-precision exponent field of 2^-16
+static_assert(kMaxMaterials <= 16, "material ids take 4 bits of a packed voxel");
+__host__ __device__ inline bool voxel_density_ok(float rho) {
+    const float lo = 1.0f / 65536.0f, hi = 65536.0f;
+    return rho >= lo && rho < hi;
+}
+__host__ __device__ inline uint32_t pack_voxel(float rho, uint32_t mat) {
+    uint32_t bits;
+    memcpy(&bits, &rho, 4);
+    return (bits - (kVoxExpBias << 23)) | (mat << 28);
+}
+__host__ __device__ inline float voxel_density(uint32_t w) {
+    const uint32_t bits = (w & 0x0FFFFFFFu) + (kVoxExpBias << 23);
+    float r;
+    memcpy(&r, &bits, 4);
+    return r;
+}
+__host__ __device__ inline int voxel_material(uint32_t w) { return (int)(w >> 28); }
+
 struct Geom {
-    const uint2* vox;      // {float bits of density, material id}
+    const uint32_t* vox;   // packed voxels (pack_voxel)
     int nx, ny, nz;
     float dx, dy, dz;
     float idx, idy, idz;   // 1 / voxel size
@@ -138,6 +163,8 @@ struct SourceDev {
     const float* f;            // [nf] intensities (negative ones as 0)
     int strata;                // K > 0: energy intervals of a round (section 2.3.2)
     const double* strata_F;    // [K + 1] spectrum CDF at the interval edges
+    int strata_shape;          // inside an interval: 0 uniform energy, 1 the spectrum's shape
+    float strata_lo, strata_w; // lower edge of the first interval, interval width (MeV)
     const float* phsp;         // [n_phsp][7] phase-space records, or null (section 2.3.3)
     unsigned long long n_phsp;
 };

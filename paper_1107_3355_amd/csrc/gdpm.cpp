@@ -45,7 +45,7 @@ hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, i
 hipError_t launch_count_records(hipStream_t st, int blocks, const Ctl* ctl, const RunDev& R,
                                 unsigned long long* counts);
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
-                        int nb, const double* inv_n, const uint2* vox, double vvox, float min_rho,
+                        int nb, const double* inv_n, const uint32_t* vox, double vvox, float min_rho,
                         double* dose, double* sigma);
 hipError_t launch_test_philox(hipStream_t st, uint32_t k0, uint32_t k1, const uint4* ctr, uint4* out,
                               int n);
@@ -212,7 +212,9 @@ struct gdpm_context_s {
     int lds_tables = 1;          // stage interpolation tables in LDS when they fit
     int pass_histories = 0;      // new histories per iteration (0: half a queue less its fill)
     int autotune = 0;            // tune block size and re-binning online, queues from the work
+    int autotune_min_events = 4000000;   // transport events an iteration needs to be scored
     int share = 1;               // new histories: evenly over the jobs (the only policy)
+    int issue_order = 0;         // 0 even shares in admission order, 1 least work left first
     int rebin_photons = 0;       // 1: re-bin the photon queue also when one job holds all particles
     int rebin_electrons = 0;     // 1: the same for the electron queue
     int graphs = 1;              // replay each iteration's launches as a recorded HIP graph
@@ -262,7 +264,8 @@ struct gdpm_source_s {
     DevBuf phsp;                 // phase-space records (the open source interface)
     unsigned long long n_phsp = 0;
     int nf, n_guide, n_beams;
-    int metro = 0, n_nz = 0, strata = 0;
+    int metro = 0, n_nz = 0, strata = 0, strata_shape = 0;
+    float strata_lo = 0.0f, strata_w = 0.0f;   // lower edge and width of the intervals
     SourceDev view() const {
         SourceDev s;
         s.particle = particle;
@@ -285,6 +288,9 @@ struct gdpm_source_s {
         s.f = fl.as<const float>();
         s.strata = strata;
         s.strata_F = strata_F.as<const double>();
+        s.strata_shape = strata_shape;
+        s.strata_lo = strata_lo;
+        s.strata_w = strata_w;
         s.phsp = phsp.as<const float>();
         s.n_phsp = n_phsp;
         return s;
@@ -314,7 +320,7 @@ static_assert(offsetof(JobCtl, seg_begin) == kJcMirrorBytes, "JobCtl starts with
 
 Geom geom_of(const gdpm_phantom_s* ph) {
     Geom g;
-    g.vox = ph->vox.as<const uint2>();
+    g.vox = ph->vox.as<const uint32_t>();
     g.nx = ph->nx;
     g.ny = ph->ny;
     g.nz = ph->nz;
@@ -577,7 +583,7 @@ void Engine::tune_account() {
     const double dt = t - tune.last_time;
     tune.last_events = ev;
     tune.last_time = t;
-    if (dev < 4000000ull || dt <= 0.0) return;   // too little work to score
+    if (dev < (unsigned long long)ctx->autotune_min_events || dt <= 0.0) return;   // too little work to score
     tune.score[tune.cur] += (double)dev / dt;
     tune.samples[tune.cur]++;
     ctx->tune_score[tune.cur] = tune.score[tune.cur] / tune.samples[tune.cur];
@@ -759,7 +765,9 @@ gdpm_status Engine::step() {
     const uint32_t cap = 1u << M.ring_log2;
     // new histories: at most half a queue (or pass_histories) less what the
     // fuller queue holds, split evenly over the jobs that still start
-    // histories
+    // histories (issue_order 0), or given to the job with the least work left
+    // first, each job taking what it can use (issue_order 1: the estimated
+    // histories left of its planned super-round)
     const uint32_t budget = ctx->pass_histories > 0 ? (uint32_t)ctx->pass_histories : cap / 2u;
     const uint32_t fill = std::max(hc->ring[0].tail - hc->ring[0].head, hc->ring[1].tail - hc->ring[1].head);
     uint64_t room = fill < budget ? budget - fill : 0u;
@@ -769,13 +777,18 @@ gdpm_status Engine::step() {
         if (j && !j->done && j->issued < j->sr_end) want.push_back(j);
     }
     std::stable_sort(want.begin(), want.end(), [](const EJob* a, const EJob* b) { return a->seq < b->seq; });
+    const bool least_left = ctx->issue_order == 1;
+    if (least_left)
+        std::stable_sort(want.begin(), want.end(), [](const EJob* a, const EJob* b) {
+            return a->sr_end - a->issued < b->sr_end - b->issued;
+        });
     int nseg[2] = {0, 0};
     uint32_t total[2] = {0u, 0u};
     SrcSeg* hs = ctx->h_segs;
     const int seg_cap = kMaxSegs / 2;   // per source type
     for (size_t k = 0; k < want.size() && room > 0; ++k) {
         EJob* j = want[k];
-        const uint64_t share = std::max<uint64_t>(1, room / (want.size() - k));
+        const uint64_t share = least_left ? room : std::max<uint64_t>(1, room / (want.size() - k));
         uint64_t n = std::min<uint64_t>(share, j->sr_end - j->issued);
         const int ri = j->src->particle == 0 ? 0 : 1;
         while (n > 0 && nseg[ri] < seg_cap) {
@@ -998,7 +1011,7 @@ gdpm_status compute_stats(gdpm_context ctx, const EngineMem& M, EJob* j, hipStre
                            hipMemcpyHostToDevice, st));
     const int blocks = (int)std::min<size_t>((nv + 255) / 256, 8192);
     HIP_TRY(launch_stats(st, blocks, dc, j->tally_p, nv, nb, M.inv_n,
-                         j->ph->vox.as<const uint2>(), j->ph->dx * j->ph->dy * j->ph->dz,
+                         j->ph->vox.as<const uint32_t>(), j->ph->dx * j->ph->dy * j->ph->dz,
                          (float)j->prm.stat_min_density, j->d_dose, j->d_sigma));
     HIP_TRY(hipMemcpyAsync(red, &dc->red[0], 4 * sizeof(double) + sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, st));
@@ -1115,7 +1128,13 @@ void fill_stats(const Engine& E, const EJob* j, double t_start, gdpm_run_stats* 
     out->graph_launches = E.tm.graph_launches;
     out->graphs_recorded = E.tm.graphs_recorded;
     out->accounting_mismatches = E.mismatches;
-    for (int k = 0; k < 5; ++k) out->interactions[k] = hc->itype[k];
+    // the kernels count photoelectric, pair and Moller events; Compton and
+    // bremsstrahlung are the rest of the real interactions and hard events
+    out->interactions[1] = hc->itype[1];
+    out->interactions[2] = hc->itype[2];
+    out->interactions[3] = hc->itype[3];
+    out->interactions[0] = hc->ev[GDPM_EV_REAL] - hc->itype[1] - hc->itype[2];
+    out->interactions[4] = hc->ev[GDPM_EV_HARD] - hc->itype[3];
     for (int k = 0; k < 2; ++k) out->records_requeued[k] = hc->pass_ev[k][3];
     out->t_photon_s = E.tm.photon;
     out->t_electron_s = E.tm.electron;
@@ -1321,7 +1340,9 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->lds_tables = json_int(opts_json, "lds_tables", 1);
     ctx->pass_histories = json_int(opts_json, "pass_histories", 0);
     ctx->autotune = json_int(opts_json, "autotune", 0);
+    ctx->autotune_min_events = json_int(opts_json, "autotune_min_events", 4000000);
     ctx->share = json_int(opts_json, "share", 1);
+    ctx->issue_order = json_int(opts_json, "issue_order", 0);
     ctx->rebin_photons = json_int(opts_json, "rebin_photons", 0);
     ctx->rebin_electrons = json_int(opts_json, "rebin_electrons", 0);
     ctx->graphs = json_int(opts_json, "graphs", 1);
@@ -1334,6 +1355,9 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
         return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);
     if (ctx->rebin_bins < 0 || ctx->rebin_bins > kMaxBins) return fail(GDPM_E_INVALID, "rebin_bins in [0, 64]");
     if (ctx->pass_histories < 0) return fail(GDPM_E_INVALID, "pass_histories must be >= 0");
+    if (ctx->autotune_min_events < 1) return fail(GDPM_E_INVALID, "autotune_min_events must be >= 1");
+    if (ctx->issue_order != 0 && ctx->issue_order != 1)
+        return fail(GDPM_E_INVALID, "issue_order must be 0 (even shares) or 1 (least work left first)");
     if (ctx->share != 1)
         return fail(GDPM_E_INVALID, "share must be 1: the oldest-job-first policy (0) can overflow the queues");
     HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device));
@@ -1423,17 +1447,15 @@ gdpm_status gdpm_phantom_create(gdpm_context ctx, int nx, int ny, int nz, double
     if (!ctx || !mat || !density) return fail(GDPM_E_INVALID, "NULL argument");
     if (ctx->mats.empty()) return fail(GDPM_E_INVALID, "set materials first");
     const size_t nv = (size_t)nx * ny * nz;
-    std::vector<uint2> vox(nv);
+    std::vector<uint32_t> vox(nv);
     std::vector<double> rmax(ctx->mats.size(), 0.0);
     for (size_t v = 0; v < nv; ++v) {
         const float r = density[v];
         if (mat[v] >= ctx->mats.size())
             return fail(GDPM_E_INVALID, "voxel %zu: material %d not defined", v, (int)mat[v]);
-        if (!(r > 0.0f) || !std::isfinite(r))
-            return fail(GDPM_E_INVALID, "voxel %zu: density must be positive and finite", v);
-        uint32_t bits;
-        memcpy(&bits, &r, 4);
-        vox[v] = make_uint2(bits, mat[v]);
+        if (!voxel_density_ok(r))
+            return fail(GDPM_E_INVALID, "voxel %zu: density %g outside [2^-16, 2^16) g/cm^3", v, (double)r);
+        vox[v] = pack_voxel(r, mat[v]);
         rmax[mat[v]] = std::max(rmax[mat[v]], (double)r);
     }
     HIP_TRY(hipSetDevice(ctx->device));
@@ -1502,6 +1524,8 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
         return fail(GDPM_E_INVALID, "spectrum_strata in [0, 64]");
     if (d->spectrum_strata > 0 && d->spectrum.kind != 1)
         return fail(GDPM_E_INVALID, "energy intervals need a piecewise-linear spectrum");
+    if (d->strata_shape != 0 && d->strata_shape != 1)
+        return fail(GDPM_E_INVALID, "strata_shape must be 0 (uniform) or 1 (the spectrum's shape)");
     std::vector<double> strata_F;
     auto src = std::make_unique<gdpm_source_s>();
     src->ctx = ctx;
@@ -1637,7 +1661,13 @@ gdpm_status gdpm_source_create(gdpm_context ctx, const gdpm_source_desc* d, gdpm
     HIP_TRY(upload(src->beams, beams));
     HIP_TRY(upload(src->beam_of, beam_of));
     src->strata = d->spectrum_strata;
-    if (src->strata) HIP_TRY(upload(src->strata_F, strata_F));
+    if (src->strata) {
+        HIP_TRY(upload(src->strata_F, strata_F));
+        src->strata_shape = d->strata_shape;
+        const double e0 = sp.e_mev[0], e1 = sp.e_mev[sp.n_pts - 1];
+        src->strata_lo = (float)e0;
+        src->strata_w = (float)((e1 - e0) / src->strata);
+    }
     src->metro = d->beamlet_sampler;
     if (src->metro) {
         HIP_TRY(upload(src->fl, fl));

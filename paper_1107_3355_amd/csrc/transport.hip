@@ -407,11 +407,13 @@ GDPM_DEV uint32_t metropolis_start(const SourceDev& S, uint32_t chain, uint32_t 
 }
 
 // section 2.3.2: energy of the history at position i of a round of `size`:
-// interval k with C_k <= i < C_{k+1}, C_k = floor(size F_k + 1/2), and the
-// spectrum's inverse CDF at F_k + u (F_{k+1} - F_k)
+// interval k with C_k <= i < C_{k+1}, C_k = floor(size F_k + 1/2); inside it
+// the energy is uniform (strata_shape 0) or the spectrum's inverse CDF at
+// F_k + u (F_{k+1} - F_k) (strata_shape 1)
 GDPM_DEV float stratified_energy(const SourceDev& S, uint32_t i, uint32_t size, float u) {
     int k = 0;
     while (k < S.strata - 1 && floor((double)size * S.strata_F[k + 1] + 0.5) <= (double)i) ++k;
+    if (S.strata_shape == 0) return fmaf(u, S.strata_w, fmaf((float)k, S.strata_w, S.strata_lo));
     const double f0 = S.strata_F[k], f1 = S.strata_F[k + 1];
     return spectrum_energy(S, (float)(f0 + (double)u * (f1 - f0)));
 }
@@ -621,8 +623,9 @@ struct WaveTally {
     uint32_t ld, rq;      // records loaded from the queue, records handed on
     uint32_t born, died;  // records created and particles ended, current job
     uint32_t bad;         // particles ended by the iteration bound of a wavefront
-    uint32_t it[3];       // real interactions by type (photons: Compton,
-                          // photoelectric, pair; electrons: Moller, bremsstrahlung)
+    uint32_t it[2];       // real interactions by type (photons: photoelectric,
+                          // pair; electrons: Moller); Compton and bremsstrahlung
+                          // are the rest of the real interactions and hard events
 };
 
 // Hand particles to the next pass of the same type (the record keeps the whole
@@ -829,8 +832,12 @@ GDPM_DEV void pass_finish(LaneTally& t, const WaveTally& c, Ctl* ctl, int ri) {
         atomicAdd(&ctl->pass_ev[ri][1], (unsigned long long)(c.pushes + c.rq));
         atomicAdd(&ctl->pass_ev[ri][2], (unsigned long long)ev[EV_DEPOSITS]);
         if (c.rq) atomicAdd(&ctl->pass_ev[ri][3], (unsigned long long)c.rq);
-        for (int i = 0; i < (ri == 0 ? 3 : 2); ++i)
-            if (c.it[i]) atomicAdd(&ctl->itype[(ri == 0 ? 0 : 3) + i], (unsigned long long)c.it[i]);
+        if (ri == 0) {
+            if (c.it[0]) atomicAdd(&ctl->itype[1], (unsigned long long)c.it[0]);
+            if (c.it[1]) atomicAdd(&ctl->itype[2], (unsigned long long)c.it[1]);
+        } else if (c.it[0]) {
+            atomicAdd(&ctl->itype[3], (unsigned long long)c.it[0]);
+        }
     }
 }
 
@@ -1303,7 +1310,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     PushState pg{0u, 0u}, pe{0u, 0u};
     LaneTally tl;
     tally_init(tl);
-    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u, {0u, 0u, 0u}};
+    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u, {0u, 0u}};
     uint32_t iters = 0u;
     bool last_job = false;   // no other job has records left in this pass
     // one job at a time: a wavefront switches jobs with all its lanes empty
@@ -1375,9 +1382,9 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                         active = false;
                     } else {
                         const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
-                        const uint2 vx = W.G.vox[vv];
-                        const float rho = __uint_as_float(vx.x);
-                        const int m = (int)vx.y;
+                        const uint32_t vx = W.G.vox[vv];
+                        const float rho = voxel_density(vx);
+                        const int m = voxel_material(vx);
                         const float4 mu = lerp4(ptab + m * T.pg_n, gi, gt);
                         if (uniform(rng, k0, k1) * mumax < rho * mu.w) {
                             tl.ev[EV_REAL]++;
@@ -1468,8 +1475,8 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                         if (!active) history_flush(tl, W, rng.hlo, rng.hhi);
                         pm = -1;
                     }
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) wt.it[i] += (uint32_t)__popcll(ballot(itype == i));
+                    wt.it[0] += (uint32_t)__popcll(ballot(itype == 1));
+                    wt.it[1] += (uint32_t)__popcll(ballot(itype == 2));
                 }
             }
             // secondaries: electrons/positrons to queue 1, annihilation photons to queue 0
@@ -1559,7 +1566,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     PushState pg{0u, 0u}, pe{0u, 0u};
     LaneTally tl;
     tally_init(tl);
-    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u, {0u, 0u, 0u}};
+    WaveTally wt{0u, 0u, 0u, 0u, 0u, 0u, 0u, {0u, 0u}};
     uint32_t iters = 0u;
     bool last_job = false;   // no other job has records left in this pass
     // one job at a time: a wavefront switches jobs with all its lanes empty
@@ -1592,9 +1599,9 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                 positron = (p.flags & 1u) != 0u;
                 pb = p.job >> 16;
                 rng_start(rng, p.hlo, p.hhi, p.path, p.ctr);
-                const uint2 vx = W.G.vox[ix + W.G.nx * (iy + W.G.ny * iz)];
-                rho = __uint_as_float(vx.x);
-                mat = (int)vx.y;
+                const uint32_t vx = W.G.vox[ix + W.G.nx * (iy + W.G.ny * iz)];
+                rho = voxel_density(vx);
+                mat = voxel_material(vx);
                 active = true;
             }
             if (!ballot(active)) {
@@ -1702,9 +1709,9 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                             active = false;
                         } else {
                             // the next voxel's density and material, needed by the next step
-                            const uint2 vx = W.G.vox[ix + W.G.nx * (iy + W.G.ny * iz)];
-                            rho = __uint_as_float(vx.x);
-                            mat = (int)vx.y;
+                            const uint32_t vx = W.G.vox[ix + W.G.nx * (iy + W.G.ny * iz)];
+                            rho = voxel_density(vx);
+                            mat = voxel_material(vx);
                         }
                     } else if (hard) {
                         hq = q0.y;   // the hard event waits (see below)
@@ -1775,7 +1782,6 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                         hq = -1.0f;
                     }
                     wt.it[0] += (uint32_t)__popcll(ballot(htype == 0));
-                    wt.it[1] += (uint32_t)__popcll(ballot(htype == 1));
                 }
             }
             wt.died += (uint32_t)__popcll(act0 & ~ballot(active));
@@ -1988,12 +1994,12 @@ __global__ void k_bin_swap(Ctl* ctl, int ri) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_dose_stats(Ctl* ctl, const double* slots, size_t nvox,
                                                     int nb, const double* inv_mass_n,
-                                                    const uint2* vox, double vvox, float min_rho,
+                                                    const uint32_t* vox, double vvox, float min_rho,
                                                     double* dose, double* sigma) {
     double emax = 0.0, edep = 0.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
          i += (size_t)gridDim.x * blockDim.x) {
-        const double rho = (double)__uint_as_float(vox[i].x);
+        const double rho = (double)voxel_density(vox[i]);
         const double im = 1.0 / (rho * vvox);
         double s = 0.0, s2 = 0.0;
         for (int b = 0; b < nb; ++b) {
@@ -2032,12 +2038,12 @@ __global__ void __launch_bounds__(256) k_dose_stats(Ctl* ctl, const double* slot
 
 // mean of sigma / D_max over voxels with D > D_max / 2
 __global__ void __launch_bounds__(256) k_unc(Ctl* ctl, const double* dose, const double* sigma,
-                                             const uint2* vox, float min_rho, size_t nvox) {
+                                             const uint32_t* vox, float min_rho, size_t nvox) {
     const double dmax = __longlong_as_double((long long)ctl->dmax_bits);
     double s = 0.0, c = 0.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
          i += (size_t)gridDim.x * blockDim.x) {
-        if (dose[i] > 0.5 * dmax && __uint_as_float(vox[i].x) >= min_rho) {
+        if (dose[i] > 0.5 * dmax && voxel_density(vox[i]) >= min_rho) {
             s += sigma[i];
             c += 1.0;
         }
@@ -2252,7 +2258,7 @@ hipError_t launch_count_records(hipStream_t st, int blocks, const Ctl* ctl, cons
     return hipGetLastError();
 }
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
-                        int nb, const double* inv_n, const uint2* vox, double vvox, float min_rho,
+                        int nb, const double* inv_n, const uint32_t* vox, double vvox, float min_rho,
                         double* dose, double* sigma) {
     hipLaunchKernelGGL(k_dose_stats, dim3(blocks), dim3(256), 0, st, ctl, slots, nvox, nb, inv_n,
                        vox, vvox, min_rho, dose, sigma);

@@ -55,7 +55,7 @@ class SourceDesc(C.Structure):
     _fields_ = [("particle", C.c_int), ("spectrum", Spectrum), ("n_beams", C.c_int),
                 ("beams", C.POINTER(Beam)), ("beamlet_sampler", C.c_int),
                 ("spectrum_strata", C.c_int), ("n_phase_space", C.c_uint64),
-                ("phase_space", C.POINTER(C.c_float))]
+                ("phase_space", C.POINTER(C.c_float)), ("strata_shape", C.c_int)]
 
 
 class RunParams(C.Structure):
@@ -222,6 +222,7 @@ class Source:
             spec.e_mev, spec.pdf = _dp(e), _dp(p)
         d = SourceDesc(src.particle, spec, len(src.beams), beams, getattr(src, "beamlet_sampler", 0),
                        getattr(src, "spectrum_strata", 0))
+        d.strata_shape = getattr(src, "strata_shape", 0)
         ps = getattr(src, "phase_space", None)
         if ps is not None:
             ps = np.ascontiguousarray(ps, dtype=np.float32).reshape(-1, 7)

@@ -96,6 +96,7 @@ class Source:
     beams: List[Beam] = field(default_factory=list)
     beamlet_sampler: int = 0  # 0 cumulative-probability search, 1 Metropolis chains (Algorithm A1)
     spectrum_strata: int = 0  # 0 plain spectrum sampling, K > 0 energy intervals (section 2.3.2)
+    strata_shape: int = 0     # inside an interval: 0 uniform energy (section 2.3.2), 1 the spectrum's shape
     # (n, 7) float32 records x, y, z, u, v, w, E: a phase space (section 2.3.3);
     # history h starts as record h mod n, and beams and spectrum are unused
     phase_space: Optional[np.ndarray] = None

@@ -51,3 +51,30 @@ def region_sum_test(b1, n1, b2, n2, region):
     nb1, nb2 = len(s1), len(s2)
     se = np.sqrt(s1.var(ddof=1) / nb1 + s2.var(ddof=1) / nb2)
     return float(s1.mean() - s2.mean()), float(se)
+
+
+def batch_doses(batch_edep, rho, vvox, n_per_batch):
+    """D_b = E_b / (rho V n_b) per batch and voxel (section 2.2.1)"""
+    return batch_edep / (rho * vvox)[None, :] / np.asarray(n_per_batch, dtype=np.float64)[:, None]
+
+
+def unc_with_jackknife(d_b, mask=None):
+    """Mean sigma/D_max (section 3.1) of the batch doses d_b (N_b x voxels)
+    and its standard error by the delete-one jackknife over the batches; the
+    jackknife sees the correlation between voxels (a batch whose particles
+    happen to favour a region moves all its voxels together), which a
+    per-voxel error estimate does not."""
+    nb = len(d_b)
+
+    def unc(db):
+        k = len(db)
+        mean = db.mean(axis=0)
+        sig = np.sqrt(((db - mean) ** 2).sum(axis=0) / (k * (k - 1)))
+        return unc_over_dmax(mean, sig, mask)
+
+    full = unc(d_b)
+    # a 9-batch standard error estimates the error of a 9-batch mean: scale
+    # the delete-one values to N_b batches before taking their spread
+    loo = np.array([unc(np.delete(d_b, b, axis=0)) for b in range(nb)]) * np.sqrt((nb - 1) / nb)
+    var = (nb - 1) / nb * ((loo - loo.mean()) ** 2).sum()
+    return full, float(np.sqrt(var))

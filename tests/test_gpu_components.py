@@ -199,14 +199,16 @@ def test_metropolis_source_lockstep(gctx):
     report("metropolis source", inside=float(inside.mean()))
 
 
-def test_stratified_source_lockstep(gctx):
+@pytest.mark.parametrize("shape", [0, 1])
+def test_stratified_source_lockstep(gctx, shape):
     """Energy intervals (section 2.3.2): for one round of n histories the device
     and the oracle put every history in the same interval and give it the same
-    energy to single-precision rounding; the beamlets are unchanged."""
+    energy to single-precision rounding (uniform inside the interval, shape 0,
+    or the spectrum's shape, 1); the beamlets are unchanged."""
     import dataclasses
     w = I.ct_imrt()
     K = 16
-    src = dataclasses.replace(w.source, spectrum_strata=K)
+    src = dataclasses.replace(w.source, spectrum_strata=K, strata_shape=shape)
     p = gctx.phantom(w.phantom)
     s = gctx.source(src)
     n = 50_001

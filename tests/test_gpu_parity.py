@@ -33,8 +33,8 @@ MATS = I.MATERIALS
 # of the electron's energy, which moves that much from one voxel to the next.
 # Over the few to few tens of faces an electron crosses, the per-voxel L1
 # difference of in-lockstep histories stays below VOXEL_TOL of the incident
-# energy.
-VOXEL_TOL = 5e-3
+# energy (measured: at most 3.1e-4, on the slab with energy intervals).
+VOXEL_TOL = 1e-3
 
 
 def _batch_counts(n, nb=10):
@@ -76,22 +76,23 @@ def _compare_stat(gctx, ph, src, n, flags=0, name="", min_rate=0.95, min_rho=0.0
     region = (np.maximum(g["dose"], o["dose"]) > 0.1 * dmax) & mask
     nb = n / 10
     diff, se = S.region_sum_test(g["batch_edep"], nb, o["batch_edep"], nb, region)
-    unc_g = check_statistics(g, ph, n, min_rho=min_rho)
-    unc_o = S.unc_over_dmax(o["dose"], o["sigma"], mask)
-    n_hi = int(((g["dose"] > 0.5 * g["dose"][mask].max()) & mask).sum())
+    check_statistics(g, ph, n, min_rho=min_rho)
+    # equal histories on both sides: equal expected uncertainty; each side's
+    # sigma/D_max with its jackknife standard error over the batches
+    rho = ph.rho.ravel().astype(np.float64)
+    vvox = ph.dx * ph.dy * ph.dz
+    nbh = _batch_counts(n)
+    unc_g, se_g = S.unc_with_jackknife(S.batch_doses(g["batch_edep"], rho, vvox, nbh), mask)
+    unc_o, se_o = S.unc_with_jackknife(S.batch_doses(o["batch_edep"], rho, vvox, nbh), mask)
     report(name, pass_rate=round(rate, 4), p_high=round(hi, 4), p_all=round(allr, 4), voxels=nreg,
            sum_diff_sigma=round(diff / se, 3), unc_g=round(unc_g, 5), unc_o=round(unc_o, 5),
-           n_high=n_hi, bal_g=balance(g), bal_o=balance(o))
+           unc_diff_sigma=round((unc_g - unc_o) / np.hypot(se_g, se_o), 2), bal_g=balance(g),
+           bal_o=balance(o))
     assert balance(g) < 1e-6 and balance(o) < 1e-6
     assert nreg >= 500
     assert min_rate <= rate <= 0.99
     assert abs(diff) <= max_sigma * se
-    # equal histories on both sides: equal expected uncertainty.  A batch
-    # standard error has a relative sampling error of 1/sqrt(2 (N_b - 1)) per
-    # voxel; over n_high voxels, of which about one in eight is independent
-    # (neighbours share particle tracks), the two means differ by a relative
-    # 4 standard deviations at most: 4 * 0.236 * sqrt(2 * 8 / n_high)
-    assert abs(unc_g / unc_o - 1.0) <= max(0.05, 3.77 / np.sqrt(n_hi)), (unc_g, unc_o, n_hi)
+    assert abs(unc_g - unc_o) <= 4 * np.hypot(se_g, se_o), (unc_g, se_g, unc_o, se_o)
     return g, o
 
 
@@ -287,18 +288,48 @@ def test_phase_space_transport(gctx):
     _compare_stat(gctx, w2.phantom, src2, 300_000, name="slab50_phase_space")
 
 
-def test_stratified_spectrum_transport(gctx):
-    """Energy intervals of the spectrum (section 2.3.2) on the 100^3 slab: one
-    round (the source sampler's) in lockstep with the oracle; ten rounds
+@pytest.mark.parametrize("shape", [0, 1])
+def test_stratified_spectrum_transport(gctx, shape):
+    """Energy intervals of the spectrum (section 2.3.2; energy uniform inside an
+    interval, shape 0, or the spectrum's shape, 1) on the 100^3 slab: one round
+    (the source sampler's) in lockstep with the oracle; ten rounds
     statistically equal to the oracle's dose with the same intervals."""
     import dataclasses
     w = I.slab_photon()
-    src = dataclasses.replace(w.source, spectrum_strata=12)
-    _compare_lockstep(gctx, w.phantom, src, 4_003, name="slab100_photon_strata", min_frac=0.9,
+    src = dataclasses.replace(w.source, spectrum_strata=12, strata_shape=shape)
+    _compare_lockstep(gctx, w.phantom, src, 4_003, name=f"slab100_photon_strata{shape}", min_frac=0.9,
                       one_round=True)
     w2 = I.slab_photon(n=50, d=0.6)
-    _compare_stat(gctx, w2.phantom, dataclasses.replace(w2.source, spectrum_strata=12), 300_000,
-                  name="slab50_photon_strata")
+    _compare_stat(gctx, w2.phantom, dataclasses.replace(w2.source, spectrum_strata=12, strata_shape=shape),
+                  300_000, name=f"slab50_photon_strata{shape}")
+
+
+def test_interval_readings_dose_difference(gctx):
+    """The paper's uniform energy inside each of 16 intervals against the
+    spectrum-shaped reading, on the 6 MV-like slab: the dose of the two runs
+    (2e6 histories each, the same seed) compared region by region (batch
+    region sums over the voxels above 10% of D_max, and the t-test).  The
+    uniform rule's spectrum is the histogram of the real one: its mean energy
+    is 4.5e-5 lower; the measured dose difference is reported and must stay
+    within the statistical noise (2 standard errors of the region sum)."""
+    import dataclasses
+    w = I.slab_photon(n=50, d=0.6)
+    n = 2_000_000
+    runs = {}
+    for shape in (0, 1):
+        src = dataclasses.replace(w.source, spectrum_strata=16, strata_shape=shape)
+        runs[shape] = gpu_run(gctx, w.phantom, src, seed=5, n_hist=n, want_batches=True)
+    a, b = runs[0], runs[1]
+    dmax = max(a["dose"].max(), b["dose"].max())
+    region = np.maximum(a["dose"], b["dose"]) > 0.1 * dmax
+    diff, se = S.region_sum_test(a["batch_edep"], n / 10, b["batch_edep"], n / 10, region)
+    rate, nreg = S.pass_rate(a["dose"], a["sigma"], b["dose"], b["sigma"])
+    mean_rel = diff / (b["batch_edep"][:, region].sum(axis=1).mean() / (n / 10))
+    report("interval readings", region_sum_rel_diff=f"{mean_rel:.2e}", sigmas=round(diff / se, 2),
+           pass_rate=round(rate, 4), voxels=nreg, e_in_uniform=a["e_in"] / n, e_in_shape=b["e_in"] / n)
+    assert abs(a["e_in"] / b["e_in"] - 1) < 2e-4
+    assert abs(diff) <= 3 * se
+    assert rate >= 0.95
 
 
 def test_ct_full_size_energy_balance(gctx):

@@ -129,18 +129,21 @@ def test_beamlet_choice_follows_fluence():
     assert _chi2_p(counts.astype(float), ff / ff.sum() * n) > 1e-4
 
 
-def test_stratified_spectrum():
+@pytest.mark.parametrize("shape", [0, 1])
+def test_stratified_spectrum(shape):
     """Section 2.3.2: K equal-width energy intervals; a round's histories go to
-    the intervals in increasing energy, in numbers R P_k (rounded cumulatively),
-    with the spectrum's shape inside each interval.  P_k and the conditional
-    CDFs from the triangular pdf's closed form."""
+    the intervals in increasing energy, in numbers R P_k (rounded cumulatively);
+    inside an interval the energy is uniform (the paper's rule, shape 0) or
+    follows the spectrum (shape 1).  P_k and the conditional CDFs from the
+    triangular pdf's closed form; shape 0's mean energy is sum_k P_k times the
+    interval's midpoint."""
     lo, pk, hi = 0.25, 1.2, 6.0
     cdf = lambda x: np.where(x < pk, (x - lo) ** 2 / ((hi - lo) * (pk - lo)),
                              1 - (hi - x) ** 2 / ((hi - lo) * (hi - pk)))
     w = I.water_cube_2mev()
     K, R = 8, 120_000
     src = I.Source(I.PHOTON, I.triangular_spectrum(lo, pk, hi), [I.parallel_beam_z(w.phantom, 5.0)],
-                   spectrum_strata=K)
+                   spectrum_strata=K, strata_shape=shape)
     e = oracle.sample_source(src, w.phantom, n=R, hist0=777)[:, 0]
     edges = lo + (hi - lo) * np.arange(K + 1) / K
     F = cdf(edges)
@@ -151,9 +154,46 @@ def test_stratified_spectrum():
     assert np.all(np.abs(counts - expect) <= 1), (counts, expect)
     for k in range(K):
         ek = np.sort(e[k_of == k])
-        cond = lambda x, k=k: (cdf(x) - F[k]) / (F[k + 1] - F[k])
+        if shape == 0:
+            cond = lambda x, k=k: (x - edges[k]) / (edges[k + 1] - edges[k])
+        else:
+            cond = lambda x, k=k: (cdf(x) - F[k]) / (F[k + 1] - F[k])
         assert sst.kstest(ek, cond).pvalue > 1e-4, k
-    assert sst.kstest(e, cdf).pvalue > 0.05   # stratified: closer than random sampling
+    if shape == 0:
+        mid = 0.5 * (edges[:-1] + edges[1:])
+        width = edges[1] - edges[0]
+        # the round's mean: intervals in their realised numbers, uniform inside
+        assert abs(e.mean() - (counts * mid).sum() / R) < 5 * width / math.sqrt(12 * R)
+    else:
+        assert sst.kstest(e, cdf).pvalue > 0.05   # stratified: closer than random sampling
+
+
+def test_stratified_mean_energies_at_16_intervals():
+    """The two readings of the energy inside an interval at K = 16 on the
+    6 MV-like spectrum: the spectrum-shaped one keeps the spectrum's mean
+    energy (its closed form (lo + peak + hi) / 3); the uniform one gives the
+    mean of the histogram approximation, sum_k P_k (e_k + e_{k+1}) / 2.  The
+    difference (here 4.5e-5 of the mean, 0.11 keV) is the uniform rule's bias
+    in the mean energy."""
+    lo, pk, hi = 0.25, 1.2, 6.0
+    cdf = lambda x: np.where(x < pk, (x - lo) ** 2 / ((hi - lo) * (pk - lo)),
+                             1 - (hi - x) ** 2 / ((hi - lo) * (hi - pk)))
+    K, R = 16, 400_000
+    w = I.water_cube_2mev()
+    edges = lo + (hi - lo) * np.arange(K + 1) / K
+    P = np.diff(cdf(edges))
+    m_uniform = float((P * 0.5 * (edges[:-1] + edges[1:])).sum())
+    m_spec = (lo + pk + hi) / 3.0
+    means = {}
+    for shape in (0, 1):
+        src = I.Source(I.PHOTON, I.triangular_spectrum(lo, pk, hi), [I.parallel_beam_z(w.phantom, 5.0)],
+                       spectrum_strata=K, strata_shape=shape)
+        means[shape] = oracle.sample_source(src, w.phantom, n=R)[:, 0].mean()
+    print("mean energy: uniform", means[0], m_uniform, "spectrum", means[1], m_spec)
+    tol = 5 * (hi - lo) / K / math.sqrt(12 * R)
+    assert abs(means[0] - m_uniform) < tol
+    assert abs(means[1] - m_spec) < 2e-4
+    assert 1e-5 < abs(m_uniform / m_spec - 1) < 1e-4   # the two readings differ, slightly
 
 
 def _metro_case(n_chains_steps):
