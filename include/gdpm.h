@@ -330,6 +330,32 @@ gdpm_status gdpm_run_async(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
 gdpm_status gdpm_job_wait(gdpm_job job, gdpm_run_stats* stats);
 gdpm_status gdpm_job_release(gdpm_job job);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * computation of gdpm_run_async, blocking (it returns once d_dose and d_sigma
+ * are written, after a synchronisation of hip_stream), with nothing allocated
+ * by the call.  The run's queues, control blocks, Woodcock majorant,
+ * Metropolis chain states and batch tallies live in a static scratch array of
+ * 512 MiB that every device the library runs on holds from the first context
+ * created on it until the process ends; the caller still passes the outputs.
+ * d_dose, d_sigma: device arrays of nx*ny*nz doubles (caller-owned, written in
+ * full).  hip_stream: NULL = the context's stream.  stats may be NULL.
+ * Limits (GDPM_E_INVALID beyond them, before any work): n_batches * nx*ny*nz
+ * <= 33,423,360 (255 MiB of FP64 batch tallies: 10 batches of 3.3e6 voxels);
+ * queues of 2^21 records per particle type (GDPM_E_OVERFLOW if a pass does not
+ * fit, with the outputs invalid); no per-history or per-batch output; the
+ * table set of the run's absorption energies and physics flags must be
+ * resident (the default energies' set is made by gdpm_set_materials, any
+ * other by a first run of another entry point with them), else
+ * GDPM_E_INVALID.  Iterations are launched directly (no graph is recorded)
+ * and the queues are never re-binned.  Every call on one device shares that
+ * device's scratch array, which keeps the last call's contents (each call
+ * clears what must start at zero): calls that overlap on one device, from any
+ * context or thread, race and corrupt each other's results. */
+gdpm_status gdpm_run_noalloc(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
+                             const gdpm_run_params* prm, double* d_dose, double* d_sigma,
+                             void* hip_stream, gdpm_run_stats* stats);
+
 /* ---- many jobs ------------------------------------------------------------
  * Several dose jobs transported together: every kernel launch advances the
  * particles of all admitted jobs (shared photon and electron queues whose

@@ -62,6 +62,45 @@ hipError_t launch_metro_init(hipStream_t st, const SourceDev& S, uint32_t k0, ui
 using namespace gdpm;
 
 // ---------------------------------------------------------------------------
+// scratch memory of the allocation-free entry point (gdpm_run_noalloc): one
+// array per device, held from the library's first use on that device until the
+// process ends.  Host code never uses the array's name as an address: each
+// device's address comes from hipGetSymbolAddress at context creation.
+// Layout: control blocks, majorant and chain states (1 MiB), the two particle
+// queues of 2^21 records each (256 MiB), then the batch tallies (255 MiB).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = (size_t)512 << 20;
+constexpr int kScratchRingLog2 = 21;
+constexpr size_t kScratchCtlBytes = (size_t)1 << 20;
+constexpr size_t kScratchRingBytes = ((size_t)1 << kScratchRingLog2) * sizeof(Particle);
+constexpr size_t kScratchTallyBytes = kScratchBytes - kScratchCtlBytes - 2 * kScratchRingBytes;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+// each device's address of `scratch`, looked up once per device with that
+// device current (every device holds its own copy of the array)
+std::mutex g_scratch_mutex;
+std::map<int, unsigned char*> g_scratch_addr;
+
+hipError_t scratch_address(int device, unsigned char** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    *out = static_cast<unsigned char*>(p);
+    g_scratch_addr[device] = *out;
+    return hipSuccess;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
 namespace {
@@ -236,6 +275,7 @@ struct gdpm_context_s {
     void* h_jc = nullptr;
     double* h_red = nullptr;
     double resident_bytes = 0.0;   // phantoms and sources alive in the context
+    unsigned char* scratch = nullptr;  // this device's scratch array (gdpm_run_noalloc)
     // the autotuner's latest record: candidates, mean scores, the one kept (-1: undecided)
     std::vector<std::pair<int, int>> tune_cand;
     std::vector<double> tune_score;
@@ -1155,10 +1195,42 @@ gdpm_status make_job(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const g
 }
 
 // one job through the engine, blocking; outputs stay in device memory
-// one job through the engine, blocking; outputs stay in device memory
+// the scratch array carved into the engine's memory and one job's arrays
+// (see kScratchBytes); false if the job's batch tallies do not fit
+bool scratch_layout(unsigned char* base, EJob* j, EngineMem* M) {
+    if ((size_t)j->plan.nb * j->nv * sizeof(double) > kScratchTallyBytes) return false;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base + off;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    memset(M, 0, sizeof *M);
+    M->ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
+    M->jobs = reinterpret_cast<JobDev*>(take(kMaxJobs * sizeof(JobDev)));
+    M->jc = reinterpret_cast<JobCtl*>(take(sizeof(JobCtl)));
+    M->segs = reinterpret_cast<SrcSeg*>(take(kMaxSegs * sizeof(SrcSeg)));
+    M->hdr = reinterpret_cast<SrcHdr*>(take(2 * sizeof(SrcHdr)));
+    M->inv_n = reinterpret_cast<double*>(take(kMaxBatches * sizeof(double)));
+    M->counts = reinterpret_cast<unsigned long long*>(take(kMaxJobs * sizeof(unsigned long long)));
+    j->mumax_p = reinterpret_cast<float*>(take(kMaxGrid * sizeof(float)));
+    j->chains_p = reinterpret_cast<uint32_t*>(take(kMetroChains * sizeof(uint32_t)));
+    if (off > kScratchCtlBytes) return false;   // (a layout error; see the static sizes)
+    for (int r = 0; r < 2; ++r)
+        M->ring[r][0] = M->ring[r][1] =
+            reinterpret_cast<Particle*>(base + kScratchCtlBytes + r * kScratchRingBytes);
+    M->ring_log2 = kScratchRingLog2;
+    j->tally_p = reinterpret_cast<double*>(base + kScratchCtlBytes + 2 * kScratchRingBytes);
+    M->fixed = true;
+    return true;
+}
+
+// one job through the engine, blocking; outputs stay in device memory.  With
+// `scr` (this device's scratch array) the engine's queues, control blocks and
+// the job's arrays live there and nothing is allocated.
 gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdpm_run_params* prm,
                    double* d_dose, double* d_sigma, double* h_batch, double* h_hist,
-                   hipStream_t st, gdpm_run_stats* out, EJob* keep) {
+                   hipStream_t st, gdpm_run_stats* out, EJob* keep, unsigned char* scr = nullptr) {
     const double t_start = now_s();
     if (!ctx) return fail(GDPM_E_INVALID, "NULL context");
     EJob local;
@@ -1169,9 +1241,19 @@ gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdp
         return fail(GDPM_E_INVALID, "per-history output needs fixed mode and <= 2^24 histories");
     j->d_dose = d_dose;
     j->d_sigma = d_sigma;
+    EngineMem sm;
+    if (scr) {
+        j->nv = (size_t)ph->nx * ph->ny * ph->nz;
+        if (h_batch || h_hist) return fail(GDPM_E_INVALID, "no batch or history output from scratch memory");
+        if (!scratch_layout(scr, j, &sm))
+            return fail(GDPM_E_INVALID,
+                        "batch tallies of %zu bytes (n_batches %d x %zu voxels x 8) exceed the %zu bytes "
+                        "of the scratch memory", (size_t)j->plan.nb * j->nv * sizeof(double), j->plan.nb,
+                        j->nv, kScratchTallyBytes);
+    }
     if (h_hist) HIP_TRY(j->hist.alloc(j->plan.n_hist * 2 * sizeof(double)));
     Engine E;
-    s = E.init(ctx, st, j->plan);
+    s = E.init(ctx, st, j->plan, scr ? &sm : nullptr);
     if (s) return s;
     s = E.admit(j);
     if (s) return s;
@@ -1334,6 +1416,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     HIP_TRY(hipSetDevice(hip_device));
     auto ctx = std::make_unique<gdpm_context_s>();
     ctx->device = hip_device;
+    HIP_TRY(scratch_address(hip_device, &ctx->scratch));
     ctx->ring_log2 = json_int(opts_json, "ring_capacity_log2", 25);
     ctx->waves_per_cu = json_int(opts_json, "waves_per_cu", 12);
     ctx->rebin_bins = json_int(opts_json, "rebin_bins", 1);
@@ -1723,6 +1806,21 @@ gdpm_status gdpm_run_async(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
     if (job->status != GDPM_OK && job->status != GDPM_E_NOT_CONVERGED) return job->status;
     *out = job.release();
     return GDPM_OK;
+}
+
+gdpm_status gdpm_run_noalloc(gdpm_context ctx, gdpm_phantom ph, gdpm_source src,
+                             const gdpm_run_params* prm, double* d_dose, double* d_sigma,
+                             void* hip_stream, gdpm_run_stats* stats) {
+    if (!ctx || !d_dose || !d_sigma) return fail(GDPM_E_INVALID, "NULL context or output");
+    if (ctx->busy) return fail(GDPM_E_BUSY, "context busy");
+    if (!ctx->scratch) return fail(GDPM_E_DEVICE, "no scratch memory on device %d", ctx->device);
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    ctx->busy = true;
+    const gdpm_status s = do_run(ctx, ph, src, prm, d_dose, d_sigma, nullptr, nullptr, st, stats,
+                                 nullptr, ctx->scratch);
+    ctx->busy = false;
+    return s;
 }
 
 gdpm_status gdpm_run_batch(gdpm_context ctx, int n, const gdpm_job_desc* jobs,

@@ -27,7 +27,7 @@ EXPORTS = ("gdpm_context_create", "gdpm_context_destroy", "gdpm_last_error", "gd
            "gdpm_job_release", "gdpm_tables_host", "gdpm_test_philox", "gdpm_test_sample",
            "gdpm_test_atomic_rate", "gdpm_test_source", "gdpm_test_lookup", "gdpm_run_batch", "gdpm_context_settings",
            "gdpm_server_create", "gdpm_server_submit", "gdpm_server_info_get",
-           "gdpm_server_destroy", "gdpm_context_tuning")
+           "gdpm_server_destroy", "gdpm_run_noalloc", "gdpm_context_tuning")
 
 
 class GdpmError(RuntimeError):
@@ -115,6 +115,7 @@ def lib():
             "gdpm_source_destroy": [vp],
             "gdpm_run": [vp, vp, vp, C.POINTER(RunParams), dp, dp, dp, dp, C.POINTER(RunStats)],
             "gdpm_run_async": [vp, vp, vp, C.POINTER(RunParams), vp, vp, vp, C.POINTER(vp)],
+            "gdpm_run_noalloc": [vp, vp, vp, C.POINTER(RunParams), vp, vp, vp, C.POINTER(RunStats)],
             "gdpm_job_wait": [vp, C.POINTER(RunStats)],
             "gdpm_job_release": [vp],
             "gdpm_tables_host": [C.POINTER(Material), C.c_int, C.c_int, C.c_double, C.c_double,
@@ -358,6 +359,19 @@ class Context:
         rc = lib().gdpm_job_wait(job, C.byref(st))
         lib().gdpm_job_release(job)
         _check(rc)
+        out = _stats_dict(st)
+        out["status"] = STATUS[rc]
+        return out
+
+    def run_noalloc(self, phantom: Phantom, source: Source, d_dose: int, d_sigma: int,
+                    stream: int = 0, **kw):
+        """gdpm_run_noalloc: device outputs, the library's scratch memory, no
+        allocation; blocking.  Returns run statistics."""
+        st = RunStats()
+        rc = _check(lib().gdpm_run_noalloc(self.handle, phantom.handle, source.handle,
+                                           C.byref(_params(kw)), C.c_void_p(d_dose),
+                                           C.c_void_p(d_sigma),
+                                           C.c_void_p(stream) if stream else None, C.byref(st)))
         out = _stats_dict(st)
         out["status"] = STATUS[rc]
         return out
