@@ -51,7 +51,7 @@ class Params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("job_id", C.c_uint32), ("n_hist", C.c_uint64),
                 ("hist0", C.c_uint64), ("round_size", C.c_uint64), ("n_batches", C.c_int),
                 ("ecut_g", C.c_double), ("ecut_e", C.c_double), ("flags", C.c_uint32),
-                ("n_threads", C.c_int)]
+                ("n_threads", C.c_int), ("split_log2", C.c_int)]
 
 
 TYPE_NAMES = ("flight_real", "flight_virtual", "compton", "photo", "pair", "hard_real",
@@ -161,7 +161,7 @@ def _source(src, keep):
 
 def run(materials, phantom, source, *, seed=1, n_hist=1000, n_batches=10, round_size=None,
         hist0=0, job_id=0, ecut_g=0.05, ecut_e=0.2, flags=0, n_threads=None,
-        want_batches=True, want_hist=False, want_hist_hard=False):
+        want_batches=True, want_hist=False, want_hist_hard=False, split_log2=0):
     """Run the reference transport; returns a dict of numpy arrays and stats."""
     L = lib()
     keep = _Keep()
@@ -173,7 +173,7 @@ def run(materials, phantom, source, *, seed=1, n_hist=1000, n_batches=10, round_
     if n_threads is None:
         n_threads = min(os.cpu_count() or 1, 16)
     prm = Params(seed, job_id, n_hist, hist0, round_size, n_batches, ecut_g, ecut_e, flags,
-                 n_threads)
+                 n_threads, split_log2)
     nv = phantom.nvox
     batch = np.zeros((n_batches, nv)) if want_batches else None
     dose = np.zeros(nv)

@@ -388,6 +388,7 @@ typedef struct {
     int nh_set;
     int iv[3]; /* electron voxel */
     stream_t s;
+    double wt; /* statistical weight (1, or 2^-k for a split primary and its secondaries) */
 } particle_t;
 
 typedef struct {
@@ -422,6 +423,7 @@ typedef struct {
     double p_type[ORC_NTYPES];     /* sum of each type's probability over the choices */
     double v_type[ORC_NTYPES];     /* sum of p (1 - p) over the choices */
     uint32_t h_hard;               /* real hard events of the running history */
+    double wt;                     /* statistical weight of the particle being tracked */
 } work_t;
 
 /* record one choice among `n` types (probabilities p[0..n-1], summing to 1)
@@ -439,20 +441,23 @@ static void push(work_t* w, const particle_t* p) {
         w->cap = w->cap ? 2 * w->cap : 64;
         w->st = (particle_t*)realloc(w->st, (size_t)w->cap * sizeof(particle_t));
     }
-    w->st[w->n++] = *p;
+    w->st[w->n] = *p;
+    w->st[w->n].wt = w->wt;   /* a particle's secondaries carry its weight */
+    w->n++;
     w->ev[ORC_EV_PUSHES]++;
 }
 
+/* energy deposited and escaping, both scaled by the particle's weight */
 static void deposit(work_t* w, int v, double e) {
     if (e <= 0.0) return;
-    w->tally[v] += e;
-    w->h_dep += e;
+    w->tally[v] += e * w->wt;
+    w->h_dep += e * w->wt;
     w->ev[ORC_EV_DEPOSITS]++;
 }
 
 static void escape(work_t* w, double e) {
-    w->e_esc += e;
-    w->h_esc += e;
+    w->e_esc += e * w->wt;
+    w->h_esc += e * w->wt;
 }
 
 static int vox_of(const ctx_t* c, const double x[3], int iv[3]) {
@@ -1092,14 +1097,25 @@ static void run_history(ctx_t* c, work_t* w, uint64_t h, double* hist_out, uint3
     w->ev[ORC_EV_HISTORIES]++;
     int in = source_particle(c, h, &p, &beamlet);
     w->e_in += p.e;
+    w->wt = 1.0;
     if (!in) {
         escape(w, p.e);
     } else {
+        /* primary splitting: S = 2^k copies of the source particle, each of
+         * weight 1/S; copy i continues on stream path i at the draw after the
+         * source's (copy 0 is the unsplit primary) */
+        const int S = 1 << c->prm.split_log2;
         w->n = 0;
-        w->ev[ORC_EV_PUSHES]--; /* the primary is not a secondary */
-        push(w, &p);
+        w->wt = 1.0 / S;
+        for (int i = S - 1; i >= 0; --i) {
+            particle_t q = p;
+            q.s.path = (uint32_t)i;
+            w->ev[ORC_EV_PUSHES]--; /* the primaries are not secondaries */
+            push(w, &q);
+        }
         while (w->n > 0) {
             particle_t q = w->st[--w->n];
+            w->wt = q.wt;
             if (q.type == 0) track_photon(c, w, &q);
             else track_electron(c, w, &q);
         }
@@ -1145,6 +1161,7 @@ static int validate(const orc_material* mats, int n_mat, const orc_phantom* ph,
         if (src->spec_kind == 1 && (src->spec_n < 2 || !src->spec_e || !src->spec_p)) return 1;
     }
     if (prm->n_batches < 1 || prm->round_size < 1) return 1;
+    if (prm->split_log2 < 0 || prm->split_log2 > 6) return 1;
     if (src->particle == 1 && (prm->flags & ORC_KERMA)) return 1;
     return 0;
 }

@@ -93,6 +93,9 @@ typedef struct {
     double ecut_e;        /* electron absorption energy = Moller threshold */
     uint32_t flags;
     int n_threads;
+    int split_log2;       /* primary splitting (variance reduction): each history's
+                             primary becomes 2^k copies of weight 2^-k, copy i on stream
+                             path i from the draw after the source's; 0..6 (0: none) */
 } orc_params;
 
 /* event counters */
