@@ -164,6 +164,14 @@ typedef struct {
     uint64_t hist0;            /* id of the first history (fixed mode) */
     double stat_min_density;   /* voxels below this density (g/cm^3) are left out of D_max and
                                   of the uncertainty statistic (0: all voxels) */
+    int split_log2;            /* primary splitting, a variance reduction (the paper's
+                                  section 4 names particle splitting as one): each history's
+                                  source particle becomes S = 2^k copies of weight 1/S, copy
+                                  i on stream path i from the draw after the source's (copy 0
+                                  is the unsplit primary); deposits and escapes of a copy and
+                                  its secondaries count with its weight, so the dose keeps its
+                                  expectation and each history its energy exactly.  0..6
+                                  (0: none).  The queues hold S records per history. */
 } gdpm_run_params;
 
 enum { GDPM_EV_FLIGHTS = 0, GDPM_EV_REAL, GDPM_EV_ESTEPS, GDPM_EV_HARD_CAND, GDPM_EV_HARD,
@@ -242,7 +250,10 @@ typedef struct {
  * still starting histories; 1, the job with the fewest histories left in its
  * planned super-round first, taking what it can use, then the next: shortest
  * remaining work first, so that a small job admitted beside a large one is
- * not slowed down by it),
+ * not slowed down by it; 2, the earliest admitted job first, taking what it
+ * can use, then the next: arrival order, with later jobs filling the room an
+ * earlier job leaves, e.g. while its super-round drains; a job's new
+ * histories per iteration are bounded by its source in every order),
  * "autotune" (see gdpm_context_settings), "autotune_min_events" (transport
  * events, photon flights plus electron steps, an iteration must have for the
  * autotuner to score it; default 4000000), "graphs" (1, default: a
@@ -255,7 +266,15 @@ typedef struct {
  * disagreement is printed to stderr and counted in the run statistics; a
  * diagnostic, default 0), "ring_start" (queue position, 0 <= p < 2^32, at
  * which runs start; positions advance with every record and wrap modulo
- * 2^32, which a value near 2^32 brings forward; default 0).
+ * 2^32, which a value near 2^32 brings forward; default 0),
+ * "admit_draining" (servers: 1 admits a job only while every running job has
+ * issued all the histories of its current super-round, so that a new job
+ * fills the queues a running job leaves as it drains instead of sharing the
+ * device with jobs large enough to fill it alone; default 0: admission by
+ * slots and device footprint only), "solo_lanes" (1: a measurement form of
+ * the transport kernels in which a wavefront carries one particle at a time,
+ * so that it executes exactly the instructions of that particle's path; very
+ * slow; needs "lds_tables" on and "autotune" off; default 0).
  * Results do not depend on any of these options (each particle draws from its
  * own random stream), only the speed does. */
 gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out);

@@ -185,6 +185,8 @@ struct JobDev {
     uint32_t gen;              // generation of the slot (8 bits): records of an earlier
                                // job in the same slot carry another one
     uint32_t* chains;          // [kMetroChains] Metropolis chain states, or null
+    uint32_t split;            // primary splitting: 2^split copies of each history's primary
+                               // (tallied at weight 1; the host scales the job's sums by 2^-split)
 };
 
 // A run of new histories for the source pass: ids [h0, h0 + n) of job `job`,

@@ -38,8 +38,8 @@ hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, 
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri);
 size_t transport_lds_bytes(int ri, const Tables& T, int waves);
 hipError_t transport_lds_optin(size_t bytes);
-hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, Ctl* ctl,
-                            const Tables& T, const RunDev& R);
+hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, bool solo,
+                            Ctl* ctl, const Tables& T, const RunDev& R);
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
                         float lo, float inv);
 hipError_t launch_count_records(hipStream_t st, int blocks, const Ctl* ctl, const RunDev& R,
@@ -253,11 +253,13 @@ struct gdpm_context_s {
     int autotune = 0;            // tune block size and re-binning online, queues from the work
     int autotune_min_events = 4000000;   // transport events an iteration needs to be scored
     int share = 1;               // new histories: evenly over the jobs (the only policy)
-    int issue_order = 0;         // 0 even shares in admission order, 1 least work left first
+    int issue_order = 0;         // 0 even shares, 1 least work left first, 2 admission order first
     int rebin_photons = 0;       // 1: re-bin the photon queue also when one job holds all particles
     int rebin_electrons = 0;     // 1: the same for the electron queue
     int graphs = 1;              // replay each iteration's launches as a recorded HIP graph
     int check_accounting = 0;    // after every iteration, count each job's live records
+    int solo_lanes = 0;          // measurement form: one particle per wavefront at a time
+    int admit_draining = 0;      // server: admit a job only while every running job drains
     uint32_t ring_start = 0;     // queue position a run starts at (positions run modulo 2^32)
     int max_lds = 0;             // dynamic LDS bytes a workgroup may use
     bool lds_optin = false;
@@ -451,6 +453,7 @@ int block_threads(gdpm_context ctx) { return std::min(kMaxBlockThreads, 64 * ctx
 struct RunPlan {
     uint64_t n_hist;
     int nb;
+    int split;          // primary splitting: 2^split copies per history
     double ecut_g, ecut_e;
     uint32_t flags;
     bool target;
@@ -477,6 +480,8 @@ gdpm_status validate_params(const gdpm_run_params* p, const gdpm_source_s* src, 
         return fail(GDPM_E_INVALID, "stat_min_density must be finite and >= 0");
     if (src->particle == 1 && (p->flags & GDPM_KERMA))
         return fail(GDPM_E_INVALID, "kerma mode needs a photon source");
+    if (p->split_log2 < 0 || p->split_log2 > 6) return fail(GDPM_E_INVALID, "split_log2 in [0, 6]");
+    plan->split = p->split_log2;
     return GDPM_OK;
 }
 
@@ -752,6 +757,7 @@ gdpm_status Engine::admit(EJob* j) {
     d.k0 = (uint32_t)j->prm.seed;
     d.k1 = (uint32_t)(j->prm.seed >> 32) ^ j->prm.job_id;
     d.flags = plan.flags;
+    d.split = (uint32_t)plan.split;
     // a new generation of the slot: records of the slot's earlier jobs (none
     // in a sound run) are then recognised as such and dropped
     slot_gen[slot] = (slot_gen[slot] + 1u) & 0xFFu;
@@ -805,9 +811,10 @@ gdpm_status Engine::step() {
     const uint32_t cap = 1u << M.ring_log2;
     // new histories: at most half a queue (or pass_histories) less what the
     // fuller queue holds, split evenly over the jobs that still start
-    // histories (issue_order 0), or given to the job with the least work left
-    // first, each job taking what it can use (issue_order 1: the estimated
-    // histories left of its planned super-round)
+    // histories (issue_order 0), or given to one job first, which takes what it
+    // can use, the next job the rest, and so on: the job with the least work
+    // left first (issue_order 1: the histories left of its planned
+    // super-round), or the earliest admitted first (issue_order 2)
     const uint32_t budget = ctx->pass_histories > 0 ? (uint32_t)ctx->pass_histories : cap / 2u;
     const uint32_t fill = std::max(hc->ring[0].tail - hc->ring[0].head, hc->ring[1].tail - hc->ring[1].head);
     uint64_t room = fill < budget ? budget - fill : 0u;
@@ -817,8 +824,8 @@ gdpm_status Engine::step() {
         if (j && !j->done && j->issued < j->sr_end) want.push_back(j);
     }
     std::stable_sort(want.begin(), want.end(), [](const EJob* a, const EJob* b) { return a->seq < b->seq; });
-    const bool least_left = ctx->issue_order == 1;
-    if (least_left)
+    const bool greedy = ctx->issue_order != 0;
+    if (ctx->issue_order == 1)
         std::stable_sort(want.begin(), want.end(), [](const EJob* a, const EJob* b) {
             return a->sr_end - a->issued < b->sr_end - b->issued;
         });
@@ -828,8 +835,18 @@ gdpm_status Engine::step() {
     const int seg_cap = kMaxSegs / 2;   // per source type
     for (size_t k = 0; k < want.size() && room > 0; ++k) {
         EJob* j = want[k];
-        const uint64_t share = least_left ? room : std::max<uint64_t>(1, room / (want.size() - k));
+        const uint64_t share = greedy ? room : std::max<uint64_t>(1, room / (want.size() - k));
         uint64_t n = std::min<uint64_t>(share, j->sr_end - j->issued);
+        // A pass holds its input and the secondaries it creates: the budget
+        // assumes about one charged secondary per photon history below 7 MeV.
+        // Electron sources (a 20 MeV electron leaves about six records of
+        // secondaries, deltas and their own) and harder photon spectra start
+        // fewer histories per iteration, so that a job alone cannot overflow.
+        const double per_history = j->src->particle == 1 ? 8.0 : std::max(1.0, j->src->e_max / 7.0);
+        n = std::min<uint64_t>(n, (uint64_t)((double)budget / per_history));
+        // a split history takes 2^split queue records
+        const uint32_t copies = 1u << j->plan.split;
+        n = std::min<uint64_t>(n, room / copies);
         const int ri = j->src->particle == 0 ? 0 : 1;
         while (n > 0 && nseg[ri] < seg_cap) {
             const uint64_t rel = j->issued - j->sr_start;
@@ -842,13 +859,13 @@ gdpm_status Engine::step() {
             const uint64_t round_start = j->sr_start + (uint64_t)b * j->round_size;
             sg.rpos = (uint32_t)(j->issued - round_start);
             sg.rsize = (uint32_t)(round_end - round_start);
-            sg.off = total[ri];
+            sg.off = total[ri];   // in records: history i's copy c at off + i 2^split + c
             sg.job = (uint32_t)j->slot;
             sg.batch = b;
-            total[ri] += (uint32_t)m;
+            total[ri] += (uint32_t)(m * copies);
             j->issued += m;
             j->nhist[b] += (double)m;
-            room -= m;
+            room -= m * copies;
             n -= m;
         }
     }
@@ -987,7 +1004,8 @@ gdpm_status Engine::issue(const StepGraphKey& k, bool recording) {
         // a recorded event becomes a node of the graph that records it at replay
         HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri], st, hipEventRecordExternal)
                           : hipEventRecord(ctx->events[2 * ri], st));
-        HIP_TRY(launch_transport(st, ri, k.blocks, k.threads, k.lds[ri] != 0, dc, k.T, k.R));
+        HIP_TRY(launch_transport(st, ri, k.blocks, k.threads, k.lds[ri] != 0, ctx->solo_lanes != 0, dc, k.T,
+                                 k.R));
         HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri + 1], st, hipEventRecordExternal)
                           : hipEventRecord(ctx->events[2 * ri + 1], st));
         HIP_TRY(launch_finish(st, dc, ri));
@@ -1042,7 +1060,8 @@ gdpm_status compute_stats(gdpm_context ctx, const EngineMem& M, EJob* j, hipStre
     const int nb = j->plan.nb;
     const size_t nv = j->nv;
     std::vector<double> inv(nb);
-    for (int b = 0; b < nb; ++b) inv[b] = j->nhist[b] > 0 ? 1.0 / j->nhist[b] : 0.0;
+    // a split job's tallies hold 2^split copies at weight 1 each
+    for (int b = 0; b < nb; ++b) inv[b] = j->nhist[b] > 0 ? std::ldexp(1.0 / j->nhist[b], -j->plan.split) : 0.0;
     HIP_TRY(hipMemcpyAsync(M.inv_n, inv.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
     Ctl* dc = M.ctl;
     double* red = ctx->h_red;
@@ -1059,7 +1078,7 @@ gdpm_status compute_stats(gdpm_context ctx, const EngineMem& M, EJob* j, hipStre
     double dm;
     memcpy(&dm, red + 4, sizeof dm);
     j->dmax = dm;
-    j->edep = red[0];
+    j->edep = std::ldexp(red[0], -j->plan.split);
     j->unc = (red[2] > 0 && dm > 0) ? red[1] / red[2] / dm : 0.0;
     return GDPM_OK;
 }
@@ -1075,7 +1094,7 @@ gdpm_status Engine::settle() {
         j->births = m->births[i];
         j->deaths = m->deaths[i] + (unsigned long long)j->death_offset;
         j->e_in = m->e_in[i];
-        j->e_esc = m->e_esc[i];
+        j->e_esc = std::ldexp(m->e_esc[i], -j->plan.split);
         if (j->issued < j->sr_end || j->births != j->deaths) continue;
         progress = true;
         gdpm_status s = compute_stats(ctx, M, j, st);
@@ -1271,6 +1290,13 @@ gdpm_status do_run(gdpm_context ctx, gdpm_phantom ph, gdpm_source src, const gdp
         HIP_TRY(hipMemcpyAsync(h_hist, j->hist.p, j->plan.n_hist * 2 * sizeof(double),
                                hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (j->plan.split) {
+        // the device sums hold each copy at weight 1 (see compute_stats)
+        if (h_batch)
+            for (size_t i = 0, n = (size_t)j->plan.nb * nv; i < n; ++i) h_batch[i] = std::ldexp(h_batch[i], -j->plan.split);
+        if (h_hist)
+            for (size_t i = 0, n = (size_t)j->plan.n_hist * 2; i < n; ++i) h_hist[i] = std::ldexp(h_hist[i], -j->plan.split);
+    }
     if (out) fill_stats(E, j, t_start, out);
     E.release(j);
     if (j->status == GDPM_E_NOT_CONVERGED) fail(GDPM_E_NOT_CONVERGED, "%s", j->err.c_str());
@@ -1327,8 +1353,20 @@ void gdpm_server_s::loop() {
     bool ready = false;
     std::unique_lock<std::mutex> lk(m);
     for (;;) {
-        // admission in arrival order, by slots and device footprint
+        // admission in arrival order, by slots and device footprint; with
+        // admit_draining, only while every running job has issued all the
+        // histories of its current super-round (its particles drain from the
+        // queues, or it waits for its statistics): a new job then fills the
+        // device instead of sharing it with jobs that could fill it alone
         while (!pending.empty() && (int)running.size() < max_slots) {
+            if (ctx->admit_draining && !running.empty()) {
+                bool issuing = false;
+                for (gdpm_job_s* r : running) {
+                    const EJob* q = r->ej.get();
+                    issuing = issuing || (!q->done && q->issued < q->sr_end);
+                }
+                if (issuing) break;
+            }
             gdpm_job_s* job = pending.front();
             EJob* j = job->ej.get();
             const size_t fp = job_footprint(j->ph, j->plan, true, ready ? E.tab->host.pg_n : 0);
@@ -1430,6 +1468,8 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->rebin_electrons = json_int(opts_json, "rebin_electrons", 0);
     ctx->graphs = json_int(opts_json, "graphs", 1);
     ctx->check_accounting = json_int(opts_json, "check_accounting", 0);
+    ctx->solo_lanes = json_int(opts_json, "solo_lanes", 0);
+    ctx->admit_draining = json_int(opts_json, "admit_draining", 0);
     const unsigned long long ring_start = json_u64(opts_json, "ring_start", 0);
     if (ring_start >= (1ull << 32)) return fail(GDPM_E_INVALID, "ring_start below 2^32");
     ctx->ring_start = (uint32_t)ring_start;
@@ -1439,10 +1479,14 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     if (ctx->rebin_bins < 0 || ctx->rebin_bins > kMaxBins) return fail(GDPM_E_INVALID, "rebin_bins in [0, 64]");
     if (ctx->pass_histories < 0) return fail(GDPM_E_INVALID, "pass_histories must be >= 0");
     if (ctx->autotune_min_events < 1) return fail(GDPM_E_INVALID, "autotune_min_events must be >= 1");
-    if (ctx->issue_order != 0 && ctx->issue_order != 1)
-        return fail(GDPM_E_INVALID, "issue_order must be 0 (even shares) or 1 (least work left first)");
+    if (ctx->issue_order < 0 || ctx->issue_order > 2)
+        return fail(GDPM_E_INVALID, "issue_order must be 0 (even shares), 1 (least work left first) or 2 "
+                    "(admission order first)");
     if (ctx->share != 1)
         return fail(GDPM_E_INVALID, "share must be 1: the oldest-job-first policy (0) can overflow the queues");
+    if (ctx->admit_draining != 0 && ctx->admit_draining != 1) return fail(GDPM_E_INVALID, "admit_draining is 0 or 1");
+    if (ctx->solo_lanes != 0 && (ctx->solo_lanes != 1 || !ctx->lds_tables || ctx->autotune))
+        return fail(GDPM_E_INVALID, "solo_lanes is 0 or 1 and needs lds_tables on and autotune off");
     HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device));
     HIP_TRY(hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device));
     if (ctx->lds_tables) {

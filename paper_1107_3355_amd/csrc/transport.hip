@@ -768,7 +768,9 @@ struct LaneTally {
 };
 
 
-// deposits go to the batch slot `pb` of the particle's history
+// deposits go to the batch slot `pb` of the particle's history; a split job's
+// particles are tallied at weight 1 and the host scales the sums by 2^-split
+// (exact: a power of two commutes with every rounding of the sum)
 GDPM_DEV void tally_flush(LaneTally& t, const WJob& W, uint32_t pb) {
     if (t.dv >= 0 && t.de != 0.0) {
         unsafeAtomicAdd(&W.tally[(unsigned long long)pb * W.nv + (unsigned)t.dv], t.de);
@@ -1123,18 +1125,25 @@ GDPM_DEV void stage_records(ClaimState& cs, float4* st, const Particle* buf, uin
 // true in the lanes that loaded a record.  Lanes wait until kRefillMin of them
 // are empty (or no lane is busy): a refill stalls the wavefront on record
 // loads, so it pays to do it for several lanes at once.  With a staging slice
-// (`st`, LDS) the records come from it when they are staged.
+// (`st`, LDS) the records come from it when they are staged.  kSolo (a
+// measurement form): one particle per wavefront at a time, so the wavefront
+// executes exactly the instructions of that particle's path.
+template <bool kSolo>
 GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uint32_t begin,
                      Ctl* ctl, const Particle* buf, uint32_t mask, Particle& p, WaveTally& c,
                      float4* st) {
     if (cs.done) return false;
     const uint64_t need = ballot(!active);
     if (!need) return false;
-    if ((uint32_t)__popcll(need) < kRefillMin && ballot(active)) return false;
+    if constexpr (kSolo) {
+        if (ballot(active)) return false;
+    } else {
+        if ((uint32_t)__popcll(need) < kRefillMin && ballot(active)) return false;
+    }
     claim_refill(cs, jc, W, ctl);
     const uint32_t have = cs.end - cs.next;
     const uint32_t rank = mbcnt(need);
-    const uint32_t take = min(have, (uint32_t)__popcll(need));
+    const uint32_t take = kSolo ? min(have, 1u) : min(have, (uint32_t)__popcll(need));
     const uint32_t first = begin + W.seg_begin;
     const bool staged = st != nullptr && take > 0u && cs.next >= cs.st_lo &&
                         cs.next + take <= cs.st_hi;
@@ -1204,8 +1213,11 @@ __global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg
         double* hist = uniform_copy(d.hist);
         const unsigned long long hist0 = uniform_copy(d.hist0);
         const uint32_t jb = sg.job | ((__builtin_amdgcn_readfirstlane(d.gen) & 0xFFu) << 8) | (sg.batch << 16);
+        const uint32_t copies = 1u << __builtin_amdgcn_readfirstlane(d.split);
         double e_in = 0.0, e_esc = 0.0, born = 0.0;
-        // history sg.h0 + i; `chain` holds its Metropolis chain (or is null)
+        // history sg.h0 + i; `chain` holds its Metropolis chain (or is null).
+        // A split history writes its 2^split copies to consecutive records,
+        // copy c on stream path c (copy 0 is the unsplit primary).
         auto one = [&](uint32_t i, uint32_t* chain) {
             const unsigned long long h = sg.h0 + i;
             Rng rng;
@@ -1213,25 +1225,32 @@ __global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg
             rng_topup(rng, k0, k1);
             const Primary pr = make_primary(S, G, rng, k0, k1, chain, sg.rpos + i, sg.rsize);
             e_in += (double)pr.e;
-            float4* q = reinterpret_cast<float4*>(buf + ((tail + sg.off + i) & R.mask[ri]));
-            if (pr.in) {
-                uint32_t vox = 0u;
-                if (ri == 1) {
-                    int ix, iy, iz;
-                    voxel_of(G, pr.x, pr.y, pr.z, ix, iy, iz);
-                    vox = pack_vox(ix, iy, iz);
+            uint32_t vox = 0u;
+            if (pr.in && ri == 1) {
+                int ix, iy, iz;
+                voxel_of(G, pr.x, pr.y, pr.z, ix, iy, iz);
+                vox = pack_vox(ix, iy, iz);
+            }
+            for (uint32_t c = 0; c < copies; ++c) {
+                float4* q = reinterpret_cast<float4*>(buf + ((tail + sg.off + i * copies + c) & R.mask[ri]));
+                if (pr.in) {
+                    // the stream continues at the draw after the source's draws
+                    q[0] = make_float4(pr.x, pr.y, pr.z, pr.e);
+                    q[1] = make_float4(pr.u, pr.v, pr.w, -1.0f);
+                    q[2] = make_float4(__uint_as_float(rng.hlo), __uint_as_float(rng.hhi), __uint_as_float(c),
+                                       __uint_as_float(rng_ctr(rng)));
+                    q[3] = make_float4(__uint_as_float(vox), 0.0f, 0.0f, __uint_as_float(jb));
+                } else {
+                    reinterpret_cast<float*>(q)[3] = -1.0f;
                 }
-                // the stream continues at the draw after the source's draws
-                q[0] = make_float4(pr.x, pr.y, pr.z, pr.e);
-                q[1] = make_float4(pr.u, pr.v, pr.w, -1.0f);
-                q[2] = make_float4(__uint_as_float(rng.hlo), __uint_as_float(rng.hhi), 0.0f,
-                                   __uint_as_float(rng_ctr(rng)));
-                q[3] = make_float4(__uint_as_float(vox), 0.0f, 0.0f, __uint_as_float(jb));
-                born += 1.0;
+            }
+            if (pr.in) {
+                born += (double)copies;
             } else {
-                reinterpret_cast<float*>(q)[3] = -1.0f;
-                e_esc += (double)pr.e;
-                if (hist) unsafeAtomicAdd(&hist[2 * (h - hist0) + 1], (double)pr.e);
+                // all copies escape: weight 1 each, like the tallies
+                const double out = (double)pr.e * (double)copies;
+                e_esc += out;
+                if (hist) unsafeAtomicAdd(&hist[2 * (h - hist0) + 1], out);
             }
         };
         if (S.metro) {
@@ -1283,7 +1302,7 @@ GDPM_HD uint32_t stage_offset(int ri, const Tables& T, int waves) {
     return tab + (floats + 3u) / 4u;
 }
 
-template <bool kLds>
+template <bool kLds, bool kSolo>
 __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     const float4* ptab = T.phot;
     float* lmw = nullptr;
@@ -1299,7 +1318,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     }
     RingCtl* rc = &ctl->ring[0];
     const uint32_t begin = rc->begin, count = rc->count;
-    const bool big = count >= kTailMinPerLane * gridDim.x * blockDim.x;
+    const bool big = !kSolo && count >= kTailMinPerLane * gridDim.x * blockDim.x;
     Particle* bufg = R.buf[0][ctl->ring[0].cur];
     Particle* bufe = R.buf[1][ctl->ring[1].cur];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
@@ -1330,7 +1349,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             const uint32_t k0 = W.k0, k1 = W.k1;
             const bool kerma = (W.flags & 64u) != 0u;
             Particle p;
-            if (refill(active, cs, jc, W, begin, ctl, bufg, R.mask[0], p, wt, stage)) {
+            if (refill<kSolo>(active, cs, jc, W, begin, ctl, bufg, R.mask[0], p, wt, stage)) {
                 x = p.x; y = p.y; z = p.z; e = p.e;
                 u = p.u; v = p.v; w = p.w;
                 pb = p.job >> 16;
@@ -1534,7 +1553,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
 // electron pass: class-II condensed history with a random hinge, one step per
 // iteration (section 2.1)
 // ---------------------------------------------------------------------------
-template <bool kLds>
+template <bool kLds, bool kSolo>
 __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) {
     const float4* etab = T.elec;
     const float* rtab = T.rinv;
@@ -1555,7 +1574,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     }
     RingCtl* rc = &ctl->ring[1];
     const uint32_t begin = rc->begin, count = rc->count;
-    const bool big = count >= kTailMinPerLane * gridDim.x * blockDim.x;
+    const bool big = !kSolo && count >= kTailMinPerLane * gridDim.x * blockDim.x;
     Particle* bufg = R.buf[0][ctl->ring[0].cur];
     Particle* bufe = R.buf[1][ctl->ring[1].cur];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
@@ -1589,7 +1608,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
             const uint32_t k0 = W.k0, k1 = W.k1;
             const bool no_ms = (W.flags & 8u) != 0u;
             Particle p;
-            if (refill(active, cs, jc, W, begin, ctl, bufe, R.mask[1], p, wt, stage)) {
+            if (refill<kSolo>(active, cs, jc, W, begin, ctl, bufe, R.mask[1], p, wt, stage)) {
                 x = p.x; y = p.y; z = p.z; e = p.e;
                 u = p.u; v = p.v; w = p.w; nh = p.nh;
                 ix = (int)(p.vox & 2047u);
@@ -2217,26 +2236,34 @@ size_t transport_lds_bytes(int ri, const Tables& T, int waves) {
 
 // allow the staged kernels to use `bytes` of dynamic LDS
 hipError_t transport_lds_optin(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_photon<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_electron<true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void* kernels[] = {(const void*)k_photon<true, false>, (const void*)k_electron<true, false>,
+                             (const void*)k_photon<true, true>, (const void*)k_electron<true, true>};
+    for (const void* k : kernels) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, Ctl* ctl,
-                            const Tables& T, const RunDev& R) {
+// `solo`: the one-particle-per-wavefront measurement form (staged tables only)
+hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, bool solo,
+                            Ctl* ctl, const Tables& T, const RunDev& R) {
     const size_t bytes = lds ? transport_lds_bytes(ri, T, threads / 64) : 0;
+    if (solo && !lds) return hipErrorInvalidValue;
     if (ri == 0) {
-        if (lds)
-            hipLaunchKernelGGL(k_photon<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
+        if (solo)
+            hipLaunchKernelGGL((k_photon<true, true>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
+        else if (lds)
+            hipLaunchKernelGGL((k_photon<true, false>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
         else
-            hipLaunchKernelGGL(k_photon<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, R);
+            hipLaunchKernelGGL((k_photon<false, false>), dim3(blocks), dim3(threads), 0, st, ctl, T, R);
     } else {
-        if (lds)
-            hipLaunchKernelGGL(k_electron<true>, dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
+        if (solo)
+            hipLaunchKernelGGL((k_electron<true, true>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
+        else if (lds)
+            hipLaunchKernelGGL((k_electron<true, false>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
         else
-            hipLaunchKernelGGL(k_electron<false>, dim3(blocks), dim3(threads), 0, st, ctl, T, R);
+            hipLaunchKernelGGL((k_electron<false, false>), dim3(blocks), dim3(threads), 0, st, ctl, T, R);
     }
     return hipGetLastError();
 }

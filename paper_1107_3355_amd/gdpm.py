@@ -64,7 +64,7 @@ class RunParams(C.Structure):
                 ("ecut_photon_mev", C.c_double), ("ecut_electron_mev", C.c_double),
                 ("max_histories", C.c_uint64), ("flags", C.c_uint32),
                 ("round_size", C.c_uint64), ("hist0", C.c_uint64),
-                ("stat_min_density", C.c_double)]
+                ("stat_min_density", C.c_double), ("split_log2", C.c_int)]
 
 
 class RunStats(C.Structure):
@@ -322,10 +322,10 @@ class Context:
     def run(self, phantom: Phantom, source: Source, *, seed=1, n_hist=1000, n_batches=10,
             round_size=0, hist0=0, job_id=0, ecut_g=0.05, ecut_e=0.2, flags=0, target_unc=0.0,
             max_histories=0, stat_min_density=0.0, want_batches=False, want_hist=False,
-            want_dose=True):
+            want_dose=True, split_log2=0):
         nv = phantom.desc.nvox
         prm = RunParams(seed, job_id, n_hist, target_unc, n_batches, ecut_g, ecut_e,
-                        max_histories, flags, round_size, hist0, stat_min_density)
+                        max_histories, flags, round_size, hist0, stat_min_density, split_log2)
         dose = np.zeros(nv) if want_dose else None
         sigma = np.zeros(nv) if want_dose else None
         batch = np.zeros((n_batches, nv)) if want_batches else None
@@ -350,7 +350,7 @@ class Context:
                         kw.get("ecut_g", 0.05), kw.get("ecut_e", 0.2),
                         kw.get("max_histories", 0), kw.get("flags", 0),
                         kw.get("round_size", 0), kw.get("hist0", 0),
-                        kw.get("stat_min_density", 0.0))
+                        kw.get("stat_min_density", 0.0), kw.get("split_log2", 0))
         job = C.c_void_p()
         _check(lib().gdpm_run_async(self.handle, phantom.handle, source.handle, C.byref(prm),
                                     C.c_void_p(d_dose), C.c_void_p(d_sigma),
@@ -426,7 +426,8 @@ def _params(kw):
     return RunParams(kw.get("seed", 1), kw.get("job_id", 0), kw.get("n_hist", 1000),
                      kw.get("target_unc", 0.0), kw.get("n_batches", 10), kw.get("ecut_g", 0.05),
                      kw.get("ecut_e", 0.2), kw.get("max_histories", 0), kw.get("flags", 0),
-                     kw.get("round_size", 0), kw.get("hist0", 0), kw.get("stat_min_density", 0.0))
+                     kw.get("round_size", 0), kw.get("hist0", 0), kw.get("stat_min_density", 0.0),
+                     kw.get("split_log2", 0))
 
 
 class ServerJob:

@@ -365,3 +365,38 @@ def test_batch_and_served_jobs_match_oracle(gctx):
     finally:
         ctx.close()
     _vs_oracle(rc, ct, src_c, kc, "served CT")
+
+
+def test_server_admit_draining():
+    """Admission only while every running job drains: jobs still finish with
+    the dose they have alone, and no job is admitted while another is issuing
+    histories, so at most two large jobs run at once."""
+    wa = I.water_cube_2mev(400_000)
+    wb = I.batch_jobs(1, seed=4302, side=(40, 40), d=0.5, hist=(1.5e6, 1.5e6))[0]
+    ctx = G.Context(0, opts='{"admit_draining": 1, "issue_order": 2}', materials=MATS)
+    try:
+        pa, sa = ctx.phantom(wa.phantom), ctx.source(wa.source)
+        pb, sb = ctx.phantom(wb.phantom), ctx.source(wb.source)
+        kws = [(pa, sa, dict(seed=31 + k, job_id=k, n_hist=wa.n_hist)) if k % 2 == 0 else
+               (pb, sb, dict(seed=31 + k, job_id=k, n_hist=wb.n_hist)) for k in range(4)]
+        srv = G.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=8)
+        try:
+            jobs = [srv.submit(p, s, **kw) for p, s, kw in kws]
+            res = [j.wait() for j in jobs]
+            info = srv.info()
+        finally:
+            srv.close()
+        alone = [ctx.run(p, s, **kw) for p, s, kw in kws]
+        for h in (pa, sa, pb, sb):
+            h.close()
+    finally:
+        ctx.close()
+    assert info["submitted"] == 4 and info["finished"] == 4
+    for k, (r, a) in enumerate(zip(res, alone)):
+        same_dose(r["dose"], a["dose"], f"admit_draining: job {k} served vs alone")
+        assert balance(r) < 1e-6
+
+
+def test_admit_draining_validated():
+    with pytest.raises(G.GdpmError):
+        G.Context(0, opts='{"admit_draining": 2}', materials=MATS)

@@ -276,3 +276,30 @@ def test_compton_electron_direction(gctx, e):
     # single precision: cosines near 1 carry about 1e-7 absolute, sines near 0 about 5e-4
     assert np.median(np.abs(ce * (1 + cg) - (1 + k) * sg * se)) < 1e-5 * (1 + k)
     assert np.mean(np.abs(ce * (1 + cg) - (1 + k) * sg * se) < 1e-3 * (1 + k)) > 0.999
+
+
+@pytest.mark.parametrize("case", ["slab_photon", "slab_electron"])
+def test_solo_lanes_same_physics(case):
+    """The one-particle-per-wavefront measurement form runs the same kernels'
+    code with one lane busy: every particle takes the same path, so the physics
+    event counts are equal and the dose equals the normal form's up to the
+    order of the FP64 tally additions."""
+    from paper_1107_3355_amd import gdpm as G
+    from tests.gpu_common import gpu_run, physics_events
+    w = I.slab_photon(n=40, d=0.75) if case == "slab_photon" else I.slab_electron(n=40, d=0.75)
+    n = 20_000 if case == "slab_photon" else 4_000
+    out = []
+    for opts in ('{}', '{"solo_lanes": 1, "graphs": 0}'):
+        ctx = G.Context(0, opts=opts, materials=I.MATERIALS)
+        try:
+            out.append(gpu_run(ctx, w.phantom, w.source, n_hist=n, seed=5))
+        finally:
+            ctx.close()
+    a, b = out
+    assert physics_events(a) == physics_events(b)
+    assert a["interactions"] == b["interactions"]
+    err = np.abs(a["dose"] - b["dose"]).max() / a["dose"].max()
+    report(f"solo lanes {case}", max_rel_diff=f"{err:.2e}", t_normal=f"{a['t_kernel_s']:.4f}",
+           t_solo=f"{b['t_kernel_s']:.4f}")
+    assert err < 1e-9
+    assert b["transport_anomalies"] == 0

@@ -100,7 +100,7 @@ INTERACTIONS = ("compton", "photo", "pair", "moller", "brems")
 
 
 def _compare_lockstep(gctx, ph, src, n, flags=0, name="", min_frac=0.9, hist0=0, one_round=False,
-                      voxel_tol=VOXEL_TOL, ctx=None):
+                      voxel_tol=VOXEL_TOL, ctx=None, split_log2=0):
     """Same seed on both sides: per history, (deposited, escaped) agree for
     most histories; the events and interactions by type agree to within the
     histories that left lockstep; and where the energy landed: the per-voxel
@@ -111,6 +111,8 @@ def _compare_lockstep(gctx, ph, src, n, flags=0, name="", min_frac=0.9, hist0=0,
     # one_round: all n histories in the first round (the source sampler's view
     # of them, which stratified spectra need for the per-history energies)
     kw = dict(round_size=n) if one_round else {}
+    if split_log2:
+        kw["split_log2"] = split_log2
     c = ctx or gctx
     g = gpu_run(c, ph, src, seed=3, n_hist=n, n_batches=2, flags=flags, want_hist=True,
                 want_batches=True, hist0=hist0, **kw)
@@ -330,6 +332,40 @@ def test_interval_readings_dose_difference(gctx):
     assert abs(a["e_in"] / b["e_in"] - 1) < 2e-4
     assert abs(diff) <= 3 * se
     assert rate >= 0.95
+
+
+def test_primary_splitting(gctx):
+    """Primary splitting (2^k copies of weight 2^-k per history, a variance
+    reduction; section 4 of the paper names particle splitting): the device's
+    split histories in lockstep with the oracle's (per history and per voxel,
+    k = 2 on the 100^3 slab and k = 3 on the small CT), and the split dose
+    statistically equal to the oracle's unsplit dose (independent seeds; the
+    compared region is fixed by a third run, since the two doses have unequal
+    noise), with a lower uncertainty at equal histories."""
+    w = I.slab_photon()
+    _compare_lockstep(gctx, w.phantom, w.source, 4_003, name="slab100_photon_split4", min_frac=0.9,
+                      split_log2=2)
+    ph = I.ct_phantom((48, 48, 24), (1.0, 1.0, 1.25))
+    src = I.Source(I.PHOTON, I.triangular_spectrum(), I.imrt_plan(ph, nb=10))
+    _compare_lockstep(gctx, ph, src, 3_001, name="ct48_imrt_split8", min_frac=0.9, split_log2=3)
+    n = 200_000
+    mask = ph.rho.ravel() >= 0.1
+    pilot = oracle_run(MATS, ph, src, seed=998, n_hist=n, want_batches=False)
+    region = (pilot["dose"] > 0.1 * pilot["dose"][mask].max()) & mask
+    g = gpu_run(gctx, ph, src, seed=1, n_hist=n, want_batches=True, split_log2=2, stat_min_density=0.1)
+    o = oracle_run(MATS, ph, src, seed=2, n_hist=n)
+    check_statistics(g, ph, n, min_rho=0.1)
+    t = S.t_values(g["dose"], g["sigma"], o["dose"], o["sigma"])
+    rate = float((np.abs(t[region]) < S.t_crit(10)).mean())
+    diff, se = S.region_sum_test(g["batch_edep"], n / 10, o["batch_edep"], n / 10, region)
+    ug, uo = S.unc_over_dmax(g["dose"], g["sigma"], mask), S.unc_over_dmax(o["dose"], o["sigma"], mask)
+    report("ct48_split4_vs_unsplit_oracle", pass_rate=round(rate, 4), voxels=int(region.sum()),
+           sum_diff_sigma=round(diff / se, 2), unc_split=round(ug, 5), unc_unsplit=round(uo, 5),
+           t_kernel=g["t_kernel_s"])
+    assert balance(g) < 1e-6
+    assert region.sum() >= 500 and 0.95 <= rate <= 0.99
+    assert abs(diff) <= 2.5 * se
+    assert ug < 0.9 * uo
 
 
 def test_ct_full_size_energy_balance(gctx):
