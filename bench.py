@@ -33,9 +33,9 @@ METRIC = "histories/s at 1% unc. (6MV, 256x256x128 CT phantom); p50/p99 dose-job
 
 # Algorithmic memory traffic of the transport passes (bytes per unit of work):
 # every Woodcock flight and every electron step needs the density and material
-# of one voxel (an 8-byte record), every particle taken from or put into a queue
-# is a 64-byte record, and every tally deposit is one FP64 value.
-BYTES_PER_VOXEL_LOOKUP = 8
+# of one voxel (one packed 4-byte word), every particle taken from or put into a
+# queue is a 64-byte record, and every tally deposit is one FP64 value.
+BYTES_PER_VOXEL_LOOKUP = 4
 BYTES_PER_RECORD = 64
 BYTES_PER_DEPOSIT = 8
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
@@ -48,6 +48,21 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1107_3355_amd", "csrc", f)
                   for f in ("transport.hip", "dev_types.h")]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_ct256x256x128_imrt9.txt")
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_ct256x256x128_imrt9.txt")
+EVENT_COST_SUMMARY = os.path.join(ROOT, "profiles", "event_cost_solo_lanes.txt")
+# Regressors of a transport kernel's VALU instructions in the one-particle-per-
+# wavefront form: wavefronts launched (set-up, table staging, the end of the
+# pass), records loaded and stored, tally deposits, and the kernel's events.
+# A run's records loaded are the queue positions its passes read, empty ones
+# included (with one particle per wavefront most of a wavefront's push
+# reservation stays empty, and each empty position costs a refill).
+EVENT_TERMS = {
+    "k_photon": ("waves", "records_loaded", "records_stored", "deposits", "flights", "compton", "photo",
+                 "pair"),
+    "k_electron": ("waves", "records_loaded", "deposits", "esteps", "moller", "brems"),
+}
+# (an electron pass's stores are nearly all secondaries of its hard events and
+# its hard-event candidates nearly all real ones: as regressors they would be
+# collinear with the Moller and bremsstrahlung counts, whose costs absorb them)
 
 
 def log(*a):
@@ -196,6 +211,28 @@ def source_modes(G, I, w, args):
     return out
 
 
+def variance_reduction(G, I, w, args):
+    """Primary splitting (2^k copies of weight 2^-k per history) on the CT job
+    to the target uncertainty: time, histories and uncertainty for each k; the
+    efficiency gain of k is the unsplit job's time over the split job's."""
+    ctx = G.Context(0, opts=args.opts, materials=I.MATERIALS)
+    ph, src = ctx.phantom(w.phantom), ctx.source(w.source)
+    out = {"workload": "CT 256x256x128 IMRT-9 to the target, cold jobs from the same first estimate"}
+    base = None
+    for k in (0, 1, 2):
+        r = ctx.run(ph, src, seed=17, n_hist=args.n0, target_unc=args.target,
+                    stat_min_density=args.min_density, want_dose=False, split_log2=k)
+        base = base or r["t_total_s"]
+        out[f"split_{1 << k}"] = {"seconds": r["t_total_s"], "histories": r["histories"], "unc": r["unc"],
+                                  "histories_per_s": r["histories"] / r["t_total_s"],
+                                  "efficiency_gain": base / r["t_total_s"]}
+        log(f"splitting {1 << k}: {r['histories']} histories in {r['t_total_s']:.3f} s, unc {r['unc']:.5f}")
+    ph.close()
+    src.close()
+    ctx.close()
+    return out
+
+
 def log_accounting(what, res):
     """Report jobs whose particle accounting needed a repair, failed a check or met an anomaly
     (their signed energy balance and births - deaths gap)."""
@@ -219,7 +256,7 @@ def run_stream(G, ctx, hs, times, slots, budget, label):
         d = t - (time.perf_counter() - t0)
         if d > 0:
             time.sleep(d)
-        jobs.append(srv.submit(p, s, want_dose=False, **kw))
+        jobs.append(srv.submit(p, s, want_dose=False, **{k: v for k, v in kw.items() if k != "kind"}))
     res = []
     for k, j in enumerate(jobs):
         res.append(j.wait())
@@ -229,13 +266,17 @@ def run_stream(G, ctx, hs, times, slots, budget, label):
     lat = [r["t_total_s"] for r in res]
     hist = sum(r["histories"] for r in res)
     log_accounting(label, res)
+    kinds = [kw.get("kind", "") for _, _, kw in hs]
     log(f"{label}: p50 {pct(lat, 50):.2f} s, p99 {pct(lat, 99):.2f} s, span {wall - times[0]:.2f} s")
     return {"seconds": wall, "histories_per_s": hist / max(wall - times[0], 1e-9),
             "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(np.mean(lat)),
                           "max": float(np.max(lat))},
             "memory_high_water_bytes": info["high_water_bytes"] + info["resident_bytes"],
             "energy_balance_max": max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res),
-            "accounting_repairs": sum(r["accounting_repairs"] for r in res)}
+            "accounting_repairs": sum(r["accounting_repairs"] for r in res),
+            "latency_by_kind_s": {k: pct([l for l, kk in zip(lat, kinds) if kk == k], 50)
+                                  for k in sorted(set(kinds))},
+            "latencies_s": [round(x, 4) for x in lat]}
 
 
 def fifo_latencies(times, service):
@@ -254,9 +295,11 @@ def served_form(G, I, seconds, rate, ct, opts=None, load=0.7):
     and batches the admitted jobs.  Each request's run time alone gives the
     service demand and the capacity (jobs/s) of one GPU for this mix; the
     stream is served at the stated rate and, stretched in time, at `load` of
-    the capacity (a stable queue), by three policies: one job at a time in
-    arrival order (per-job launches), even sharing among up to 64 jobs, and up
-    to 64 jobs with the least remaining work first."""
+    the capacity (a stable queue), by five policies: one job at a time in
+    arrival order (per-job launches); up to 64 jobs sharing the device evenly,
+    least remaining work first, or earliest admitted first; and admission only
+    while the running jobs drain (a new job fills the device a running job
+    leaves at the end of its super-round), earliest admitted first."""
     reqs = I.serving_requests(duration_s=seconds, rate=rate, ct=ct)
     times = [t for t, _ in reqs]
     budget = 64 << 30
@@ -264,7 +307,9 @@ def served_form(G, I, seconds, rate, ct, opts=None, load=0.7):
                        "256x256x128 CT or IMRT-9 on 128x128x64 CT, to 1% or 2%",
            "requests": len(reqs), "hbm_budget_bytes": budget}
     ctxs = {}
-    for name, o in (("fifo", opts), ("least_work_first", '{"issue_order": 1}')):
+    for name, o in (("fifo", opts), ("least_work_first", '{"issue_order": 1}'),
+                    ("admission_order", '{"issue_order": 2}'),
+                    ("admit_draining", '{"issue_order": 2, "admit_draining": 1}')):
         ctxs[name] = G.Context(0, opts=o, materials=I.MATERIALS)
     hs = {name: [] for name in ctxs}
     for name, ctx in ctxs.items():
@@ -275,20 +320,21 @@ def served_form(G, I, seconds, rate, ct, opts=None, load=0.7):
                 phs[key] = ctx.phantom(w.phantom)
             hs[name].append((phs[key], ctx.source(w.source),
                              dict(seed=500 + k, job_id=k, n_hist=w.n_hist, target_unc=w.target_unc,
-                                  stat_min_density=0.1)))
+                                  stat_min_density=0.1, kind=w.name)))
         ctx.run(hs[name][0][0], hs[name][0][1], n_hist=10_000, want_dose=False)   # tables and queues
     # service demand: every request alone, back to back
     ctx = ctxs["fifo"]
     service, hist = [], 0
     for k, (p, s, kw) in enumerate(hs["fifo"]):
         a = time.perf_counter()
-        r = ctx.run(p, s, want_dose=False, **kw)
+        r = ctx.run(p, s, want_dose=False, **{k: v for k, v in kw.items() if k != "kind"})
         service.append(time.perf_counter() - a)
         hist += r["histories"]
         log_accounting(f"served form, request {k} alone", [r])
     mean_s = float(np.mean(service))
     out["service_s"] = {"mean": mean_s, "p50": pct(service, 50), "max": float(np.max(service)),
-                        "total": float(np.sum(service))}
+                        "total": float(np.sum(service)), "each": [round(x, 4) for x in service],
+                        "kinds": [w.name for _, w in reqs]}
     out["capacity_jobs_per_s"] = 1.0 / mean_s
     out["utilisation_at_stated_rate"] = rate * mean_s
     out["histories"] = hist
@@ -299,7 +345,7 @@ def served_form(G, I, seconds, rate, ct, opts=None, load=0.7):
     streams.append((f"load_{load:g}", rate_s, [t * rate / rate_s for t in times]))
     for sname, r_s, ts in streams:
         lat, done = fifo_latencies(ts, service)
-        res = {"rate_jobs_per_s": r_s, "utilisation": r_s * mean_s,
+        res = {"rate_jobs_per_s": r_s, "utilisation": r_s * mean_s, "arrivals_s": [round(t, 3) for t in ts],
                "one_at_a_time_replayed": {"latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99),
                                                         "mean": float(np.mean(lat)), "max": float(np.max(lat))},
                                           "histories_per_s": hist / max(done - ts[0], 1e-9)}}
@@ -309,6 +355,11 @@ def served_form(G, I, seconds, rate, ct, opts=None, load=0.7):
                                         f"served {sname}: 64 slots, even shares")
         res["shared_least_work_first"] = run_stream(G, ctxs["least_work_first"], hs["least_work_first"], ts,
                                                     64, budget, f"served {sname}: 64 slots, least work first")
+        res["shared_admission_order"] = run_stream(G, ctxs["admission_order"], hs["admission_order"], ts,
+                                                   64, budget, f"served {sname}: 64 slots, admission order first")
+        res["admit_while_draining"] = run_stream(G, ctxs["admit_draining"], hs["admit_draining"], ts, 64,
+                                                 budget, f"served {sname}: admission while the running "
+                                                         "jobs drain, admission order first")
         out[sname] = res
     for name, ctx in ctxs.items():
         done_ph = set()
@@ -329,8 +380,8 @@ def config_rates(G, I, args):
     import oracle
     threads = cpu_threads()
     cases = [("config1_water32_2MeV_parallel", I.water_cube_2mev(), 200_000, 200_000),
-             ("config2A_slab100_6MVlike_point", I.slab_photon(), 10_000_000, 200_000),
-             ("config2B_slab100_20MeV_electron_point", I.slab_electron(), 10_000_000, 20_000)]
+             ("config2A_slab100_6MVlike_point", I.slab_photon(), 10_000_000, 1_000_000),
+             ("config2B_slab100_20MeV_electron_point", I.slab_electron(), 10_000_000, 100_000)]
     ctx = G.Context(0, opts=args.opts, materials=I.MATERIALS)
     out = {}
     for name, w, n, n_cpu in cases:
@@ -421,6 +472,275 @@ def reference_copy(nbytes):
         hip.hipFree(b)
 
 
+def event_cost_workloads(I):
+    """Jobs of varied event mixes for the event-cost fit: the CT plan at two
+    sizes, configs 1, 2A and 2B, and homogeneous phantoms where one kind of
+    event dominates (pair production, photoelectric absorption, electrons of
+    several energies in water, bone and lung, fine and coarse voxels)."""
+    def homo(mat, rho, n=(40, 40, 40), d=(0.5, 0.5, 0.5)):
+        return I.homogeneous(n, d, mat, rho)
+
+    def beam(ph, particle, e, field=4.0):
+        return I.Source(particle, I.mono(e), [I.parallel_beam_z(ph, field)])
+
+    ct = I.ct_imrt()
+    small_ct = I.ct_phantom((64, 64, 32), (0.8, 0.8, 1.0))
+    out = [("ct_imrt", ct.phantom, ct.source, 1_000_000),
+           ("ct_imrt", ct.phantom, ct.source, 2_000_000)]
+    for name, w, n in (("config1_water32_2MeV", I.water_cube_2mev(), 500_000),
+                       ("config2A_slab_photon", I.slab_photon(), 500_000),
+                       ("config2B_slab_electron", I.slab_electron(), 50_000)):
+        out.append((name, w.phantom, w.source, n))
+    bone, water, lung = homo(I.ID_BONE, 1.85), homo(I.ID_WATER, 1.0), homo(I.ID_LUNG, 0.26)
+    fine = homo(I.ID_WATER, 1.0, (80, 80, 80), (0.1, 0.1, 0.1))
+    coarse = homo(I.ID_WATER, 1.0, (20, 20, 40), (1.0, 1.0, 1.0))
+    out += [("bone_20MeV_photons", bone, beam(bone, I.PHOTON, 20.0), 200_000),
+            ("bone_80keV_photons", bone, beam(bone, I.PHOTON, 0.08), 500_000),
+            ("water_300keV_photons", water, beam(water, I.PHOTON, 0.3), 500_000),
+            ("small_ct_1.25MeV_photons", small_ct, beam(small_ct, I.PHOTON, 1.25, 10.0), 500_000),
+            ("water_1MeV_electrons", water, beam(water, I.ELECTRON, 1.0), 200_000),
+            ("bone_5MeV_electrons", bone, beam(bone, I.ELECTRON, 5.0), 100_000),
+            ("lung_6MeV_electrons", lung, beam(lung, I.ELECTRON, 6.0), 100_000),
+            ("water_fine_0.5MeV_electrons", fine, beam(fine, I.ELECTRON, 0.5, 1.0), 200_000),
+            ("water_coarse_10MeV_electrons", coarse, beam(coarse, I.ELECTRON, 10.0), 100_000)]
+    return out
+
+
+def event_cost_runs(G, I):
+    """The event-cost jobs in the one-particle-per-wavefront form (every
+    wavefront executes exactly the instructions of its particle's path, so a
+    VALU instruction counter reads the straight-line cost of the events); run
+    this under a per-dispatch counter (SQ_INSTS_VALU, SQ_WAVES) and fit with
+    --event-cost-fit.  Every run of the process is listed, in order, with the
+    counts the fit needs."""
+    ctx = G.Context(0, opts='{"solo_lanes": 1, "graphs": 0}', materials=I.MATERIALS)
+    runs = []
+    for k, (name, ph, src, n) in enumerate(event_cost_workloads(I)):
+        p, s = ctx.phantom(ph), ctx.source(src)
+        r = ctx.run(p, s, n_hist=n, seed=700 + k, want_dose=False)
+        p.close()
+        s.close()
+        keep = ("histories", "passes_photon", "passes_electron", "events", "interactions", "records_loaded",
+                "records_stored", "records_requeued", "deposits", "t_photon_s", "t_electron_s")
+        runs.append(dict({k2: r[k2] for k2 in keep}, name=name))
+        log(f"event cost: {name}, {n} histories, {r['passes_photon']} + {r['passes_electron']} launches")
+    ctx.close()
+    return runs
+
+
+def event_regressors(run, kernel):
+    """The counts of EVENT_TERMS[kernel] (all but 'waves') in one run."""
+    k = 0 if kernel == "k_photon" else 1
+    vals = {"records_loaded": run["records_loaded"][k], "records_stored": run["records_stored"][k],
+            "deposits": run["deposits"][k]}
+    vals.update(run["events"])
+    vals.update(run["interactions"])
+    return [float(vals[t]) for t in EVENT_TERMS[kernel][1:]]
+
+
+def event_cost_fit(csv_path, runs_path):
+    """Instructions per history and per event of the transport kernels, from a
+    rocprofv3 counter CSV (SQ_INSTS_VALU, SQ_WAVES per dispatch) of an
+    --event-cost run and that run's output line.  Each wavefront carried one
+    particle at a time, so its instructions are exactly those of its
+    particles' paths plus the launch's fixed work.  (1) The CT plan run at two
+    sizes with the same launches: the difference of the instructions over the
+    difference of the histories is the straight-line cost of a history, free
+    of the fixed work.  (2) A non-negative least-squares fit over all runs of
+    each kernel's instructions on its wavefronts and event counts: the
+    coefficient of an event type is what its path costs.  Prints the summary."""
+    from scipy.optimize import nnls
+    disp = read_dispatch_counters(csv_path)
+    runs = bench_line(runs_path)["event_cost_runs"]
+    lines, machine = [], [f"kernel_source_sha256: {kernel_source_hash()}"]
+    per_kernel = {}
+    for kernel, passes in (("k_photon", "passes_photon"), ("k_electron", "passes_electron")):
+        ds = [disp[i] for i in sorted(disp) if kernel + "<" in disp[i]["name"]]
+        assert all("true, true" in d["name"] for d in ds), "not the one-particle-per-wavefront form"
+        assert len(ds) == sum(r[passes] for r in runs), (kernel, len(ds), sum(r[passes] for r in runs))
+        X, y, i = [], [], 0
+        for r in runs:
+            part = ds[i:i + r[passes]]
+            i += r[passes]
+            X.append([sum(d["SQ_WAVES"] for d in part)] + event_regressors(r, kernel))
+            y.append(sum(d["SQ_INSTS_VALU"] for d in part))
+        per_kernel[kernel] = (np.array(X), np.array(y), passes)
+    ct = [k for k, r in enumerate(runs) if r["name"] == "ct_imrt"]
+    a, b = ct[0], ct[-1]
+    dn = runs[b]["histories"] - runs[a]["histories"]
+    lines += ["Straight-line instructions per history of the CT plan (runs of "
+              f"{runs[a]['histories']} and {runs[b]['histories']} histories with the same launches):", "",
+              " | kernel | launches | VALU instructions (small, large run) | per history |", " |---|---:|---:|---:|"]
+    total = 0.0
+    for kernel, (X, y, passes) in per_kernel.items():
+        assert runs[a][passes] == runs[b][passes], "the two CT runs must have the same launches"
+        v = (y[b] - y[a]) / dn
+        total += v
+        lines.append(f" | {kernel} | {runs[a][passes]} | {y[a]:.4g}, {y[b]:.4g} | {v:.1f} |")
+        machine.append(f"{kernel}_valu_per_history: {v:.2f}")
+    lines += [f" | both | | | {total:.1f} |", ""]
+    for kernel, (X, y, passes) in per_kernel.items():
+        # non-negative least squares (an instruction count is not negative),
+        # on columns scaled to unit norm
+        norm = np.linalg.norm(X, axis=0)
+        keep = norm > 0
+        c = np.zeros(X.shape[1])
+        c[keep] = nnls(X[:, keep] / norm[keep], y)[0] / norm[keep]
+        fit = X @ c
+        big = y >= 0.05 * y.max()
+        lines.append(f"{kernel}: VALU instructions = sum of coefficient x count over {len(runs)} runs; "
+                     f"|residual| summed {np.abs(y - fit).sum() / y.sum() * 100:.1f}% of all instructions, "
+                     f"at most {np.abs((y - fit) / y)[big].max() * 100:.1f}% of a run's (runs with at least 5% "
+                     "of the largest run's instructions)")
+        lines += [" | term | instructions each |", " |---|---:|"]
+        for t, v in zip(EVENT_TERMS[kernel], c):
+            lines.append(f" | {t} | {v:.1f} |")
+            machine.append(f"{kernel}_cost_{t}: {v:.3f}")
+        lines += ["", " | run | histories | launches | VALU instructions | fit |", " |---|---:|---:|---:|---:|"]
+        for r, yy, ff in zip(runs, y, fit):
+            lines.append(f" | {r['name']} | {r['histories']} | {r[passes]} | {yy:.4g} | {ff:.4g} |")
+        lines.append("")
+    print("\n".join(lines + ["Machine-readable values used by bench.py (valid while the kernel source hash "
+                              "matches):", ""] + machine))
+
+
+def measured_event_costs(kernel):
+    """(straight-line instructions per CT history, {term: instructions per
+    event}) of `kernel` from the committed event-cost summary, or None."""
+    kv = profiled_values(EVENT_COST_SUMMARY)
+    if not kv or f"{kernel}_valu_per_history" not in kv:
+        return None
+    return (float(kv[f"{kernel}_valu_per_history"]),
+            {t: float(kv[f"{kernel}_cost_{t}"]) for t in EVENT_TERMS[kernel] if f"{kernel}_cost_{t}" in kv})
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def short_kernel(name):
+    """'void gdpm::k_photon<true, false>(gdpm::Ctl*, ...)' -> 'k_photon'"""
+    base = name.split("(")[0].split("<")[0].split()[-1]
+    return base.split("::")[-1]
+
+
+def read_dispatch_counters(csv_path):
+    """rocprofv3 counter CSV -> {dispatch id: {"name": kernel, counter: value}}"""
+    import csv
+    disp = {}
+    with open(csv_path) as fh:
+        for row in csv.DictReader(fh):
+            d = disp.setdefault(int(row["Dispatch_Id"]), {"name": row["Kernel_Name"]})
+            d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    return disp
+
+
+def bench_line(path):
+    return json.loads(open(path).read().strip().splitlines()[-1])
+
+
+def summarize_trace(stats_csv, bench_json):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run of the CT job."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    b = bench_line(bench_json)
+    roof = b["roofline"]
+    out = ["| kernel | calls | total ms | average us | share |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append(f"| {r['Name'].split('(')[0].replace('void ', '')} | {r['Calls']} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.2f}% |")
+    trace_avg = {short_kernel(r["Name"]): float(r["AverageNs"]) / 1e6 for r in rows}
+    k = roof["kernel"]
+    out += ["", f"The bench line of the same run (HIP events on the library stream) gives "
+                f"{roof['avg_launch_ms']:.3f} ms per {k} launch over {roof['launches']} launches; the "
+                f"trace average is {trace_avg.get(k, float('nan')):.3f} ms.",
+            f"Job: {b['config']['histories_per_job']} histories, {b['ms_per_step'] / 1e3:.3f} s, "
+            f"{b['value']:.4g} histories/s under the profiler.", "",
+            f"kernel_source_sha256: {kernel_source_hash()}"]
+    print("\n".join(out))
+
+
+def summarize_counters(bench_json, *csvs):
+    """Per-launch averages of the transport and source kernels' counters
+    (VALU busy and lane use, occupancy, L2 hit rate, atomics per second) from
+    rocprofv3 counter CSVs of the CT job, plus the active-lane instructions per
+    event that the executed-instruction roofline figure uses."""
+    per = {}
+    for c in csvs:
+        for d in read_dispatch_counters(c).values():
+            k = short_kernel(d["name"])
+            if k not in ("k_photon", "k_electron", "k_source"):
+                continue
+            acc = per.setdefault(k, {})
+            for name, v in d.items():
+                if name != "name":
+                    acc.setdefault(name, []).append(v)
+    b = bench_line(bench_json)
+    ev = b["events_per_history"]
+    hist = b["config"]["histories_per_job"]
+    kt = b["kernel_time_s"]
+    launches = b["roofline"]["launches"]
+    out = ["| kernel | VALU busy % | VALU lane use % | occupancy (waves/CU) | L2 hit % | VALU instr. per launch "
+           "| atomics per s |", "|---|---:|---:|---:|---:|---:|---:|"]
+    machine = [f"kernel_source_sha256: {kernel_source_hash()}"]
+    for k in ("k_photon", "k_electron", "k_source"):
+        a = {n: float(np.mean(v)) for n, v in per.get(k, {}).items()}
+        if not a:
+            continue
+        hit = a["TCC_HIT_sum"] / max(a["TCC_HIT_sum"] + a["TCC_MISS_sum"], 1.0) * 100
+        t = {"k_photon": kt["photon"], "k_electron": kt["electron"]}.get(k)
+        atom = a["TCC_ATOMIC_sum"] * launches / t if t else float("nan")
+        out.append(f"| {k} | {a['VALUBusy']:.1f} | {a['VALUUtilization']:.1f} | {a['MeanOccupancyPerCU']:.2f} | "
+                   f"{hit:.1f} | {a['SQ_INSTS_VALU']:.4g} | {atom:.4g} |")
+        machine += [f"{k}_valu_busy_pct: {a['VALUBusy']:.2f}", f"{k}_valu_lane_use_pct: {a['VALUUtilization']:.2f}",
+                    f"{k}_occupancy_waves_per_cu: {a['MeanOccupancyPerCU']:.3f}", f"{k}_l2_hit_pct: {hit:.2f}"]
+        if t:
+            machine.append(f"{k}_atomics_per_s: {atom:.4e}")
+            events = (ev["flights"] if k == "k_photon" else ev["esteps"]) * hist / launches
+            lane = a["SQ_INSTS_VALU"] * 64 * a["VALUUtilization"] / 100 / events
+            machine.append(f"{k}_lane_valu_per_event: {lane:.1f}")
+    print("\n".join(out + ["", "Machine-readable values used by bench.py (valid while the kernel source hash "
+                                   "matches):", ""] + machine))
+
+
+def summarize_traffic(fetch_csv, write_csv, copy_mib):
+    """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by what it reads for the plain device copy of copy_mib MiB in
+    the same run."""
+    f, w = read_dispatch_counters(fetch_csv), read_dispatch_counters(write_csv)
+    def per_kernel(disp, counter):
+        out = {}
+        for d in disp.values():
+            out.setdefault(short_kernel(d["name"]) if "gdpm" in d["name"] else d["name"], []).append(d[counter])
+        return out
+    fk, wk = per_kernel(f, "FETCH_SIZE"), per_kernel(w, "WRITE_SIZE")
+    copy = [n for n in fk if "copyBuffer" in n]
+    big_f = max(max(fk[n]) for n in copy)
+    big_w = max(max(wk[n]) for n in copy if n in wk)
+    kib = copy_mib * 1024
+    sf, sw = kib / big_f, kib / big_w
+    out = [f"Calibration: the {copy_mib} MiB device-to-device copy read {big_f:.0f} KiB by FETCH_SIZE and wrote "
+           f"{big_w:.0f} KiB by WRITE_SIZE; scale factors {sf:.4f} (fetch) and {sw:.4f} (write).", "",
+           "| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch (scaled) |",
+           "|---|---:|---:|---:|---:|"]
+    machine = [f"kernel_source_sha256: {kernel_source_hash()}"]
+    for k in ("k_photon", "k_electron", "k_source"):
+        if k not in fk or k not in wk:
+            continue
+        mf, mw = float(np.mean(fk[k])), float(np.mean(wk[k]))
+        b = (mf * sf + mw * sw) * 1024
+        out.append(f"| {k} | {len(fk[k])} | {mf:.0f} | {mw:.0f} | {b:.4g} |")
+        machine.append(f"{k}_hbm_bytes_per_launch: {b:.4e}")
+    print("\n".join(out + ["", "Machine-readable values used by bench.py (valid while the kernel source hash "
+                                   "matches):", ""] + machine))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +761,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2.0, help="requests per second")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="utilisation of the stable stream (the stated stream stretched in time)")
+    ap.add_argument("--variance-reduction", type=int, default=1,
+                    help="1: also run the CT job with primary splitting (2 and 4 copies)")
     ap.add_argument("--configs", type=int, default=1,
                     help="1: also time configs 1, 2A and 2B on the GPU and the oracle")
     ap.add_argument("--serve-only", action="store_true",
@@ -450,7 +772,30 @@ def main():
     ap.add_argument("--min-density", type=float, default=0.1,
                     help="voxels below this density (the air around the patient) are left out "
                          "of D_max and of the uncertainty statistic")
+    ap.add_argument("--event-cost", action="store_true",
+                    help="only the event-cost jobs in the one-particle-per-wavefront form (to run "
+                         "under a VALU instruction counter)")
+    ap.add_argument("--event-cost-fit", nargs=2, metavar=("COUNTER_CSV", "RUNS_JSON"),
+                    help="fit the instructions per event from a counter CSV of an --event-cost run "
+                         "and that run's output line (no GPU needed)")
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="print a profile summary (no GPU needed): 'trace STATS_CSV BENCH_JSON', "
+                         "'counters BENCH_JSON CSV...', 'traffic FETCH_CSV WRITE_CSV COPY_MIB'")
     args = ap.parse_args()
+    if args.summarize:
+        kind, rest = args.summarize[0], args.summarize[1:]
+        if kind == "trace":
+            summarize_trace(*rest)
+        elif kind == "counters":
+            summarize_counters(*rest)
+        elif kind == "traffic":
+            summarize_traffic(rest[0], rest[1], int(rest[2]))
+        else:
+            ap.error(f"unknown summary {kind}")
+        return
+    if args.event_cost_fit:
+        event_cost_fit(*args.event_cost_fit)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (histories would be "
               "sharded across GPUs by history id, with one FP64 all-reduce of the batch tallies "
@@ -460,6 +805,9 @@ def main():
     from paper_1107_3355_amd import gdpm as G
     from paper_1107_3355_amd import inputs as I
 
+    if args.event_cost:
+        print(json.dumps({"event_cost_runs": event_cost_runs(G, I)}), flush=True)
+        return
     log("building the synthetic CT workload")
     w = I.ct_imrt(target_unc=args.target)
     if args.serve_only:
@@ -520,12 +868,30 @@ def main():
     # FP32 work), not by HBM: priced as the active-lane VALU instructions one
     # transport event costs (from the committed counter profile of this kernel
     # source) times the launch's events, against the chip's lane-instruction rate.
+    # Algorithmic: the straight-line VALU instructions of the launch's
+    # histories (measured with one particle per wavefront, where every
+    # instruction serves one particle's path; the launch's fixed work left
+    # out), i.e. SURVEY-style W_h = sum over event types of count x cost.
+    # Executed: the active-lane instructions the launch really issued per event
+    # (queue work, job switches and whatever lanes ran beside the path).
     per_event = measured_lane_valu_per_event(name)
-    if per_event:
-        alu = per_event * lookups / max(launches, 1) / avg / 1e12
-        roof.update(bound="alu", achieved=alu, peak=PEAK_VALU_TLANE, unit="T lane-instructions/s",
-                    frac=alu / PEAK_VALU_TLANE, lane_valu_per_event=per_event, hbm=hbm)
+    costs = measured_event_costs(name)
+    if costs or per_event:
+        roof.update(bound="alu", peak=PEAK_VALU_TLANE, unit="T lane-instructions/s", hbm=hbm)
         roof.pop("algorithmic_bytes_per_launch")
+    if per_event:
+        executed = per_event * lookups / max(launches, 1) / avg / 1e12
+        roof["executed"] = {"achieved": executed, "frac": executed / PEAK_VALU_TLANE,
+                            "lane_valu_per_event": per_event}
+        roof.update(achieved=executed, frac=executed / PEAK_VALU_TLANE)
+    if costs:
+        per_history, per_event_type = costs
+        work = per_history * hist
+        alg = work / max(launches, 1) / avg / 1e12
+        roof.update(achieved=alg, frac=alg / PEAK_VALU_TLANE,
+                    algorithmic_lane_instructions_per_launch=work / max(launches, 1),
+                    straight_line_instructions_per_history=per_history,
+                    instructions_per_event=per_event_type)
     # the kernel's FP64 tally additions per second against the measured rate of
     # scattered FP64 atomics into an array of one CT tally slot (and a small one)
     peak = ctx.atomic_rate(8 * w.phantom.nvox)
@@ -571,6 +937,9 @@ def main():
     if args.source_modes:
         log("source modes: search and Metropolis beamlet sampling")
         out["source_modes"] = source_modes(G, I, w, args)
+    if args.variance_reduction:
+        log("variance reduction: primary splitting")
+        out["variance_reduction"] = variance_reduction(G, I, w, args)
     if args.serve_seconds > 0:
         log(f"served form: {args.serve_seconds} s of requests at {args.serve_rate}/s")
         out["served_form"] = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom, args.opts,
