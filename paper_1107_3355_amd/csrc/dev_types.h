@@ -34,9 +34,16 @@ constexpr uint32_t kMaxWaveIterations = 1u << 21;  // bound of a wavefront's loo
 enum { EV_FLIGHTS = 0, EV_REAL, EV_ESTEPS, EV_HARD_CAND, EV_HARD, EV_DEPOSITS, EV_PUSHES,
        EV_HISTORIES };
 
+// An empty queue position carries exactly this energy.  A particle's own
+// energy never does: it is >= 0, or a rounding below 0 by a few ulps that the
+// transport ends as an absorption, so such a record must still be read as a
+// particle (an empty-slot test of e < 0 would lose it: born, never ended).
+constexpr float kEmptyEnergy = -1.0f;
+__host__ __device__ inline bool record_empty(float e) { return e == kEmptyEnergy; }
+
 // A particle record: 64 bytes, four 16-byte vectors.
 struct alignas(16) Particle {
-    float x, y, z, e;        // position (cm), kinetic energy (MeV); e < 0 marks an empty slot
+    float x, y, z, e;        // position (cm), kinetic energy (MeV); kEmptyEnergy marks an empty slot
     float u, v, w, nh;       // direction; hard-event mean free paths left (< 0: unset)
     uint32_t hlo, hhi;       // history id
     uint32_t path, ctr;      // Philox stream path id and draw counter

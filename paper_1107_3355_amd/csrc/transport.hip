@@ -611,7 +611,7 @@ GDPM_DEV void release(PushState& ps, Particle* buf, uint32_t mask) {
     // run may straddle the wrap (then ps.end < ps.next as numbers)
     const uint32_t n = ps.end - ps.next;
     for (uint32_t o = lane_id(); o < n; o += 64u)
-        reinterpret_cast<float*>(buf + ((ps.next + o) & mask))[3] = -1.0f;
+        reinterpret_cast<float*>(buf + ((ps.next + o) & mask))[3] = kEmptyEnergy;
     ps.next = ps.end;
 }
 
@@ -895,7 +895,10 @@ GDPM_DEV float sample_brems(RngT<Q>& r, uint32_t k0, uint32_t k1, float tt, floa
     float kph;
     for (;;) {
         const float ua = uniform(r, k0, k1);
-        kph = wcb * hexp2(ua * lr);
+        // the hardware log2 and exp2 are within about an ulp each, so near
+        // ua = 1 their product could exceed T by a few ulps and leave the
+        // electron a negative energy: the photon takes at most T
+        kph = fminf(wcb * hexp2(ua * lr), tt);
         const float ub = uniform(r, k0, k1);
         const float yy = kph * it;
         if (ub * (4.0f / 3.0f) <= 4.0f / 3.0f - 4.0f / 3.0f * yy + yy * yy) break;
@@ -1152,7 +1155,7 @@ GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uin
     if (!active && rank < take) {
         p = staged ? load_staged(st, cs.next + rank - cs.st_lo)
                    : load(buf, mask, first + cs.next + rank);
-        got = p.e >= 0.0f;
+        got = !record_empty(p.e);
         if (got && (p.job & 0xFFFFu) != W.tag) {
             // a record of another job (or of an earlier job in this slot) in
             // this job's segment: only a broken bookkeeping puts it there; it
@@ -1241,7 +1244,7 @@ __global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg
                                        __uint_as_float(rng_ctr(rng)));
                     q[3] = make_float4(__uint_as_float(vox), 0.0f, 0.0f, __uint_as_float(jb));
                 } else {
-                    reinterpret_cast<float*>(q)[3] = -1.0f;
+                    reinterpret_cast<float*>(q)[3] = kEmptyEnergy;
                 }
             }
             if (pr.in) {
@@ -1878,7 +1881,7 @@ GDPM_DEV int record_key(const RunDev& R, const Particle* buf, uint32_t mask, uin
                         float lo, float inv, bool& live) {
     const float4 w0 = reinterpret_cast<const float4*>(buf + (slot & mask))[0];
     const float4 w3 = reinterpret_cast<const float4*>(buf + (slot & mask))[3];
-    live = w0.w >= 0.0f;
+    live = !record_empty(w0.w);
     const int j = live ? record_job(R, __float_as_uint(w3.w)) : -1;
     return j < 0 ? -1 : j * nb + energy_bin(w0.w, lo, inv, nb);
 }
@@ -1969,7 +1972,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri,
     __syncthreads();
     for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         const Particle p = load(src, R.mask[ri], r.head + i);
-        if (!(p.e >= 0.0f)) continue;
+        if (record_empty(p.e)) continue;
         const int job = record_job(R, p.job);
         if (job >= 0) {
             const int k = job * nb + energy_bin(p.e, lo, inv, nb);
@@ -1992,7 +1995,7 @@ __global__ void __launch_bounds__(256) k_count_records(const Ctl* ctl, RunDev R,
         const Particle* buf = R.buf[ri][r.cur];
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
             const float4* q = reinterpret_cast<const float4*>(buf + ((r.head + i) & R.mask[ri]));
-            const int j = q[0].w >= 0.0f ? record_job(R, __float_as_uint(q[3].w)) : -1;
+            const int j = !record_empty(q[0].w) ? record_job(R, __float_as_uint(q[3].w)) : -1;
             if (j >= 0) atomicAdd(&counts[j], 1ull);
         }
     }
