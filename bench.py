@@ -51,18 +51,17 @@ COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_ct256x256x128_imrt9.t
 EVENT_COST_SUMMARY = os.path.join(ROOT, "profiles", "event_cost_solo_lanes.txt")
 # Regressors of a transport kernel's VALU instructions in the one-particle-per-
 # wavefront form: wavefronts launched (set-up, table staging, the end of the
-# pass), records loaded and stored, tally deposits, and the kernel's events.
+# pass), records loaded, and the kernel's events.
 # A run's records loaded are the queue positions its passes read, empty ones
 # included (with one particle per wavefront most of a wavefront's push
 # reservation stays empty, and each empty position costs a refill).
 EVENT_TERMS = {
-    "k_photon": ("waves", "records_loaded", "records_stored", "deposits", "flights", "compton", "photo",
-                 "pair"),
-    "k_electron": ("waves", "records_loaded", "deposits", "esteps", "moller", "brems"),
+    "k_photon": ("waves", "records_loaded", "flights", "compton", "photo", "pair"),
+    "k_electron": ("waves", "records_loaded", "esteps", "moller", "brems"),
 }
-# (an electron pass's stores are nearly all secondaries of its hard events and
-# its hard-event candidates nearly all real ones: as regressors they would be
-# collinear with the Moller and bremsstrahlung counts, whose costs absorb them)
+# (a pass's stores and deposits follow its interactions and steps nearly in
+# proportion: as regressors they would be collinear with those counts, so the
+# cost of an interaction or a step includes its pushes and deposits)
 
 
 def log(*a):
@@ -248,18 +247,25 @@ def run_stream(G, ctx, hs, times, slots, budget, label):
     """Submit the requests at their arrival times to a server with at most
     `slots` jobs running together; returns per-request latency (submission to
     completion), histories and the span from the first arrival to the last
-    completion."""
+    completion.  A long stream logs its progress about every 30 s."""
     srv = G.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
     jobs = []
     t0 = time.perf_counter()
+    last = t0
     for t, (p, s, kw) in zip(times, hs):
         d = t - (time.perf_counter() - t0)
         if d > 0:
             time.sleep(d)
         jobs.append(srv.submit(p, s, want_dose=False, **{k: v for k, v in kw.items() if k != "kind"}))
+        if time.perf_counter() - last > 30:
+            last = time.perf_counter()
+            log(f"{label}: {len(jobs)} of {len(hs)} requests submitted at {last - t0:.0f} s")
     res = []
     for k, j in enumerate(jobs):
         res.append(j.wait())
+        if time.perf_counter() - last > 30:
+            last = time.perf_counter()
+            log(f"{label}: {k + 1} of {len(jobs)} requests done at {last - t0:.0f} s")
     wall = time.perf_counter() - t0
     info = srv.info()
     srv.close()
@@ -274,7 +280,8 @@ def run_stream(G, ctx, hs, times, slots, budget, label):
             "memory_high_water_bytes": info["high_water_bytes"] + info["resident_bytes"],
             "energy_balance_max": max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in res),
             "accounting_repairs": sum(r["accounting_repairs"] for r in res),
-            "latency_by_kind_s": {k: pct([l for l, kk in zip(lat, kinds) if kk == k], 50)
+            "latency_by_kind_s": {k: {"p50": pct([l for l, kk in zip(lat, kinds) if kk == k], 50),
+                                      "p99": pct([l for l, kk in zip(lat, kinds) if kk == k], 99)}
                                   for k in sorted(set(kinds))},
             "latencies_s": [round(x, 4) for x in lat]}
 
@@ -289,81 +296,98 @@ def fifo_latencies(times, service):
     return lat, done
 
 
-def served_form(G, I, seconds, rate, ct, opts=None, load=0.7):
+# serving policies: context options and job slots
+SERVE_POLICIES = {
+    "per_job_launches": (None, 1),
+    "shared_even": (None, 64),
+    "shared_least_work_first": ('{"issue_order": 1}', 64),
+    "shared_admission_order": ('{"issue_order": 2}', 64),
+    "admit_while_draining": ('{"issue_order": 2, "admit_draining": 1}', 64),
+}
+
+
+# the bench line's default set (least work first lost to even shares on p99 in
+# every measurement: it starves the long VMAT jobs)
+SERVE_DEFAULT = ("per_job_launches", "shared_even", "shared_admission_order", "admit_while_draining")
+
+
+def served_form(G, I, seconds, rate, ct, opts=None, load=0.7, policies=None, service_sample=0, stated=True):
     """Poisson request stream (VMAT arcs on the 256x256x128 CT and IMRT jobs on a
     128x128x64 CT, to 1% or 2%) into a server that admits by device footprint
-    and batches the admitted jobs.  Each request's run time alone gives the
-    service demand and the capacity (jobs/s) of one GPU for this mix; the
-    stream is served at the stated rate and, stretched in time, at `load` of
-    the capacity (a stable queue), by five policies: one job at a time in
-    arrival order (per-job launches); up to 64 jobs sharing the device evenly,
-    least remaining work first, or earliest admitted first; and admission only
-    while the running jobs drain (a new job fills the device a running job
-    leaves at the end of its super-round), earliest admitted first."""
+    and batches the admitted jobs.  The requests' run times alone give the
+    service demand and the capacity (jobs/s) of one GPU for this mix (all of
+    them, or the first `service_sample`); the stream is served at the stated
+    rate and (load > 0), stretched in time, at `load` of the capacity (a stable
+    queue), by the policies of SERVE_POLICIES: one job at a time in arrival
+    order (per-job launches); up to 64 jobs sharing the device evenly, least
+    remaining work first, or earliest admitted first; and admission only while
+    the running jobs drain (a new job fills the device a running job leaves at
+    the end of its super-round), earliest admitted first."""
+    policies = policies or list(SERVE_DEFAULT)
     reqs = I.serving_requests(duration_s=seconds, rate=rate, ct=ct)
     times = [t for t, _ in reqs]
     budget = 64 << 30
     out = {"workload": f"Poisson {rate} jobs/s for {seconds} s: {len(reqs)} requests, VMAT-180 on "
                        "256x256x128 CT or IMRT-9 on 128x128x64 CT, to 1% or 2%",
-           "requests": len(reqs), "hbm_budget_bytes": budget}
+           "requests": len(reqs), "hbm_budget_bytes": budget, "policies": policies}
     ctxs = {}
-    for name, o in (("fifo", opts), ("least_work_first", '{"issue_order": 1}'),
-                    ("admission_order", '{"issue_order": 2}'),
-                    ("admit_draining", '{"issue_order": 2, "admit_draining": 1}')):
-        ctxs[name] = G.Context(0, opts=o, materials=I.MATERIALS)
-    hs = {name: [] for name in ctxs}
-    for name, ctx in ctxs.items():
+    for name in policies:
+        o = SERVE_POLICIES[name][0] or opts
+        if o not in ctxs:
+            ctxs[o] = G.Context(0, opts=o, materials=I.MATERIALS)
+    hs = {o: [] for o in ctxs}
+    for o, ctx in ctxs.items():
         phs = {}
         for k, (t, w) in enumerate(reqs):
             key = id(w.phantom)
             if key not in phs:
                 phs[key] = ctx.phantom(w.phantom)
-            hs[name].append((phs[key], ctx.source(w.source),
-                             dict(seed=500 + k, job_id=k, n_hist=w.n_hist, target_unc=w.target_unc,
-                                  stat_min_density=0.1, kind=w.name)))
-        ctx.run(hs[name][0][0], hs[name][0][1], n_hist=10_000, want_dose=False)   # tables and queues
-    # service demand: every request alone, back to back
-    ctx = ctxs["fifo"]
+            hs[o].append((phs[key], ctx.source(w.source),
+                          dict(seed=500 + k, job_id=k, n_hist=w.n_hist, target_unc=w.target_unc,
+                               stat_min_density=0.1, kind=w.name)))
+        ctx.run(hs[o][0][0], hs[o][0][1], n_hist=10_000, want_dose=False)   # tables and queues
+    log(f"served form: {len(reqs)} requests prepared")
+    # service demand: the requests alone, back to back
+    o0 = next(iter(ctxs))
+    ctx = ctxs[o0]
+    n_alone = len(reqs) if service_sample <= 0 else min(service_sample, len(reqs))
     service, hist = [], 0
-    for k, (p, s, kw) in enumerate(hs["fifo"]):
+    for k, (p, s, kw) in enumerate(hs[o0][:n_alone]):
         a = time.perf_counter()
         r = ctx.run(p, s, want_dose=False, **{k: v for k, v in kw.items() if k != "kind"})
         service.append(time.perf_counter() - a)
         hist += r["histories"]
         log_accounting(f"served form, request {k} alone", [r])
     mean_s = float(np.mean(service))
-    out["service_s"] = {"mean": mean_s, "p50": pct(service, 50), "max": float(np.max(service)),
-                        "total": float(np.sum(service)), "each": [round(x, 4) for x in service],
-                        "kinds": [w.name for _, w in reqs]}
+    kinds = [w.name for _, w in reqs]
+    out["service_s"] = {"requests_measured": n_alone, "mean": mean_s, "p50": pct(service, 50),
+                        "max": float(np.max(service)), "total": float(np.sum(service)),
+                        "each": [round(x, 4) for x in service], "kinds": kinds[:n_alone],
+                        "mean_by_kind": {k: float(np.mean([x for x, kk in zip(service, kinds) if kk == k]))
+                                         for k in sorted(set(kinds[:n_alone]))}}
     out["capacity_jobs_per_s"] = 1.0 / mean_s
     out["utilisation_at_stated_rate"] = rate * mean_s
-    out["histories"] = hist
-    log(f"served form: mean service {mean_s:.3f} s, capacity {1 / mean_s:.2f} jobs/s, "
-        f"load {rate * mean_s:.2f} at {rate} jobs/s")
-    streams = [("stated_rate", rate, times)]
-    rate_s = load / mean_s
-    streams.append((f"load_{load:g}", rate_s, [t * rate / rate_s for t in times]))
+    log(f"served form: mean service {mean_s:.3f} s over {n_alone} requests, capacity {1 / mean_s:.2f} "
+        f"jobs/s, load {rate * mean_s:.2f} at {rate} jobs/s")
+    streams = [("stated_rate", rate, times)] if stated else []
+    if load > 0:
+        rate_s = load / mean_s
+        streams.append((f"load_{load:g}", rate_s, [t * rate / rate_s for t in times]))
     for sname, r_s, ts in streams:
-        lat, done = fifo_latencies(ts, service)
-        res = {"rate_jobs_per_s": r_s, "utilisation": r_s * mean_s, "arrivals_s": [round(t, 3) for t in ts],
-               "one_at_a_time_replayed": {"latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99),
-                                                        "mean": float(np.mean(lat)), "max": float(np.max(lat))},
-                                          "histories_per_s": hist / max(done - ts[0], 1e-9)}}
-        res["per_job_launches"] = run_stream(G, ctxs["fifo"], hs["fifo"], ts, 1, budget,
-                                             f"served {sname}: one job at a time")
-        res["shared_even"] = run_stream(G, ctxs["fifo"], hs["fifo"], ts, 64, budget,
-                                        f"served {sname}: 64 slots, even shares")
-        res["shared_least_work_first"] = run_stream(G, ctxs["least_work_first"], hs["least_work_first"], ts,
-                                                    64, budget, f"served {sname}: 64 slots, least work first")
-        res["shared_admission_order"] = run_stream(G, ctxs["admission_order"], hs["admission_order"], ts,
-                                                   64, budget, f"served {sname}: 64 slots, admission order first")
-        res["admit_while_draining"] = run_stream(G, ctxs["admit_draining"], hs["admit_draining"], ts, 64,
-                                                 budget, f"served {sname}: admission while the running "
-                                                         "jobs drain, admission order first")
+        res = {"rate_jobs_per_s": r_s, "utilisation": r_s * mean_s, "arrivals_s": [round(t, 3) for t in ts]}
+        if n_alone == len(reqs):
+            lat, done = fifo_latencies(ts, service)
+            res["one_at_a_time_replayed"] = {
+                "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(np.mean(lat)),
+                              "max": float(np.max(lat))},
+                "histories_per_s": hist / max(done - ts[0], 1e-9)}
+        for name in policies:
+            o, slots = SERVE_POLICIES[name][0] or opts, SERVE_POLICIES[name][1]
+            res[name] = run_stream(G, ctxs[o], hs[o], ts, slots, budget, f"served {sname}: {name}")
         out[sname] = res
-    for name, ctx in ctxs.items():
+    for o, ctx in ctxs.items():
         done_ph = set()
-        for p, s, _ in hs[name]:
+        for p, s, _ in hs[o]:
             s.close()
             if id(p) not in done_ph:
                 done_ph.add(id(p))
@@ -531,10 +555,11 @@ def event_cost_runs(G, I):
 def event_regressors(run, kernel):
     """The counts of EVENT_TERMS[kernel] (all but 'waves') in one run."""
     k = 0 if kernel == "k_photon" else 1
-    vals = {"records_loaded": run["records_loaded"][k], "records_stored": run["records_stored"][k],
-            "deposits": run["deposits"][k]}
-    vals.update(run["events"])
+    vals = dict(run["events"])
     vals.update(run["interactions"])
+    # the kernel's own records and deposits (the events' deposits are both kernels')
+    vals.update(records_loaded=run["records_loaded"][k], records_stored=run["records_stored"][k],
+                deposits=run["deposits"][k])
     return [float(vals[t]) for t in EVENT_TERMS[kernel][1:]]
 
 
@@ -767,6 +792,13 @@ def main():
                     help="1: also time configs 1, 2A and 2B on the GPU and the oracle")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the served form (a long stream's record), no CT jobs")
+    ap.add_argument("--serve-policies", default=None,
+                    help="comma-separated serving policies out of " + ",".join(SERVE_POLICIES) +
+                         " (default: " + ",".join(SERVE_DEFAULT) + ")")
+    ap.add_argument("--serve-service-sample", type=int, default=0,
+                    help="measure the service demand on the first N requests only (0: all)")
+    ap.add_argument("--serve-stated", type=int, default=1,
+                    help="1: serve the stream at the stated rate (0: only the stream at --serve-load)")
     ap.add_argument("--source-modes", type=int, default=1,
                     help="1: also run the CT job with the other source modes (section 2.3)")
     ap.add_argument("--min-density", type=float, default=0.1,
@@ -812,7 +844,9 @@ def main():
     w = I.ct_imrt(target_unc=args.target)
     if args.serve_only:
         log(f"served form only: {args.serve_seconds} s of requests at {args.serve_rate}/s")
-        res = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom, args.opts, args.serve_load)
+        pols = args.serve_policies.split(",") if args.serve_policies else None
+        res = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom, args.opts, args.serve_load,
+                          pols, args.serve_service_sample, bool(args.serve_stated))
         print(json.dumps({"served_form": res}), flush=True)
         return
     ctx = G.Context(0, opts=args.opts, materials=I.MATERIALS)
@@ -942,8 +976,10 @@ def main():
         out["variance_reduction"] = variance_reduction(G, I, w, args)
     if args.serve_seconds > 0:
         log(f"served form: {args.serve_seconds} s of requests at {args.serve_rate}/s")
+        pols = args.serve_policies.split(",") if args.serve_policies else None
         out["served_form"] = served_form(G, I, args.serve_seconds, args.serve_rate, w.phantom, args.opts,
-                                         args.serve_load)
+                                         args.serve_load, pols, args.serve_service_sample,
+                                         bool(args.serve_stated))
     if args.configs:
         log("configs 1, 2A, 2B")
         out["configs"] = config_rates(G, I, args)
