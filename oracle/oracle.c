@@ -544,21 +544,48 @@ static void make_charged(particle_t* q, int type, const particle_t* parent, cons
 /* Photon transport                                                          */
 /* ======================================================================== */
 
-/* Compton scattering of photon p (section 2.1's photon physics, read as
- * free-electron Klein-Nishina): Butcher-Messel composition and rejection for
- * eps = E'/E, an azimuth, the photon turned and left with E' = eps E; the
- * electron takes T = E - E' along E d0 - E' d (momentum conservation). */
-static void compton(particle_t* p, double* te, double de[3]) {
-    double k = p->e / MC2, e0 = 1.0 / (1.0 + 2.0 * k);
-    double a1 = log(1.0 + 2.0 * k), a2 = 0.5 * (1.0 - e0 * e0);
-    double eps, t;
-    for (;;) {
-        double ua = draw(&p->s), ub = draw(&p->s), uc = draw(&p->s);
-        if (ua * (a1 + a2) < a1) eps = exp(-a1 * ub);
-        else eps = sqrt(e0 * e0 + (1.0 - e0 * e0) * ub);
-        t = (1.0 - eps) / (k * eps);
-        if (uc <= 1.0 - eps * t * (2.0 - t) / (1.0 + eps * eps)) break;
+/* Klein-Nishina in eps = E'/E on [1/(1+2k), 1] (free electron): density
+ * proportional to 1/x + x - t(2 - t) with t = (1/x - 1)/k = 1 - cos(theta);
+ * kn_cum is its antiderivative, written out term by term:
+ * ln x + x^2/2 - (2/k)(ln x - x) + (-1/x - 2 ln x + x)/k^2 */
+static double kn_density(double x, double k) {
+    double t = (1.0 / x - 1.0) / k;
+    return 1.0 / x + x - t * (2.0 - t);
+}
+
+static double kn_cum(double x, double k) {
+    double l = log(x);
+    return l + 0.5 * x * x - 2.0 / k * (l - x) + (-1.0 / x - 2.0 * l + x) / (k * k);
+}
+
+/* eps with F(eps) = u, F the normalised Klein-Nishina distribution function:
+ * Newton steps kept inside a shrinking bracket (bisection where a step would
+ * leave it), from the log-uniform guess e0^(1 - u), to full double precision */
+static double kn_inverse(double k, double u) {
+    double e0 = 1.0 / (1.0 + 2.0 * k);
+    double g0 = kn_cum(e0, k), span = kn_cum(1.0, k) - g0;
+    double lo = e0, hi = 1.0, x = pow(e0, 1.0 - u);
+    for (int it = 0; it < 200; ++it) {
+        double f = (kn_cum(x, k) - g0) / span - u;
+        if (f > 0.0) hi = x;
+        else lo = x;
+        double xn = x - f * span / kn_density(x, k);
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (fabs(xn - x) <= 1e-15 * x || hi - lo <= 1e-15 * x) return xn;
+        x = xn;
     }
+    return x;
+}
+
+/* Compton scattering of photon p (section 2.1's photon physics, read as
+ * free-electron Klein-Nishina): eps = E'/E by inversion of the distribution
+ * function at one uniform draw, then an azimuth; the photon turned and left
+ * with E' = eps E; the electron takes T = E - E' along E d0 - E' d (momentum
+ * conservation). */
+static void compton(particle_t* p, double* te, double de[3]) {
+    double k = p->e / MC2;
+    double eps = kn_inverse(k, draw(&p->s));
+    double t = (1.0 - eps) / (k * eps);
     double phi = 2.0 * PI * draw(&p->s);
     double d0[3] = {p->d[0], p->d[1], p->d[2]};
     rotate(p->d, 1.0 - t, sqrt(fmax(0.0, t * (2.0 - t))), phi);

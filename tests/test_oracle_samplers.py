@@ -1,6 +1,6 @@
 """Pins of the oracle's sampling algorithms against their target densities
-(chi-square on histograms of many draws): Klein-Nishina (Butcher-Messel
-composition/rejection), Moller, bremsstrahlung, the modified-Wentzel deflection
+(chi-square on histograms of many draws): Klein-Nishina (inversion of its
+distribution function, also pinned draw by draw), Moller, bremsstrahlung, the modified-Wentzel deflection
 and its multiple-scattering first moment (Lewis: <cos> = exp(-sum t)),
 annihilation photon pairs (positrons: section 2.1), and the source: the
 piecewise-linear spectrum and the beamlet choice P(I) <= r < P(I+1)
@@ -41,6 +41,28 @@ def test_compton_energy_distribution(e):
     exp = np.array([quad(f, a, b, epsrel=1e-10)[0] for a, b in zip(edges[:-1], edges[1:])])
     h, _ = np.histogram(eps, edges)
     assert _chi2_p(h, exp) > 1e-4
+
+
+@pytest.mark.parametrize("e", [0.06, 0.5, 2.0, 20.0])
+def test_compton_inverts_the_distribution_function(e):
+    """The Compton sampler inverts the Klein-Nishina distribution function at
+    the sample's first draw: F(eps) = u, with F from adaptive quadrature of the
+    differential cross section (independent of the sampler's antiderivative),
+    to 1e-9; and eps grows with u (one draw, no rejection)."""
+    n = 300
+    eps, _ = oracle.sample(0, e, n=n, seed=8)
+    # sample i runs on stream (seed 8, job 0, history i, path 0) from draw 0
+    u = np.array([oracle.uniforms(8, 0, i, 0, 0, 1)[0] for i in range(n)])
+    k = e / MC2
+    e0 = 1 / (1 + 2 * k)
+    f = lambda x: oracle.phys(oracle.DSIGMA_KN, I.WATER, e, x)
+    # (epsabs 0: the cross section is of order 1e-25 cm^2, below quad's default
+    # absolute tolerance)
+    total = quad(f, e0, 1, epsabs=0, epsrel=1e-13, limit=200)[0]
+    cdf = np.array([quad(f, e0, x, epsabs=0, epsrel=1e-13, limit=200)[0] / total for x in eps])
+    assert np.max(np.abs(cdf - u)) < 1e-9
+    order = np.argsort(u)
+    assert np.all(np.diff(eps[order]) >= 0)
 
 
 @pytest.mark.parametrize("t", [0.5, 2.0, 20.0])
