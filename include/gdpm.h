@@ -450,8 +450,13 @@ gdpm_status gdpm_server_destroy(gdpm_server srv);
  * them.  which: 0 photon {muC, muPE, muPair, muTot} (cm^2/g) per material and
  * node of the photon grid; 1 electron {R (g/cm^2), muHard, muMoller,
  * 1/lambda1 (cm^2/g)} per material and node of the electron grid; 2 inverse
- * range E(w) on w = sqrt(R) per material; 3 MW screening log2 A on log2 t.
- * grid[0..3] receives (ln-grid start, spacing, node count, materials).
+ * range E(w) on w = sqrt(R) per material; 3 MW screening log2 A on log2 t;
+ * 4 Klein-Nishina inverse distribution function (section 2.1's Compton
+ * scattering, material independent): ln(eps/eps0)/ln(1/eps0) of the eps =
+ * E'/E at which the distribution function reaches u, on log2 E nodes (rows)
+ * and u = j/(columns - 1), eps0 = 1/(1 + 2E/mc^2).
+ * grid[0..3] receives (ln-grid start, spacing, node count, materials), for
+ * which 4 (log2 E start, spacing, rows, columns).
  * out: cap floats; *len receives the number needed. */
 gdpm_status gdpm_tables_host(const gdpm_material* m, int n, int n_grid, double ecut_g,
                              double ecut_e, uint32_t flags, int which, float* out, size_t cap,

@@ -111,6 +111,9 @@ struct Tables {
     float aw_lo, aw_inv;
     int aw_n;
     int n_mat;
+    const float* kn;       // [kn_ne][kn_nu] Klein-Nishina inverse: ln(eps/eps0)/ln(1/eps0)
+    float kn_lo, kn_inv;   // at log2 E = kn_lo + i / kn_inv and u = j / (kn_nu - 1)
+    int kn_ne, kn_nu;
 };
 
 // A voxel of the phantom in 4 bytes: the density's single-precision mantissa

@@ -168,7 +168,7 @@ struct TableKey {
 
 struct DevTables {
     HostTables host;
-    DevBuf phot, elec, rinv, rinv_scale, aw;
+    DevBuf phot, elec, rinv, rinv_scale, aw, kn;
     Tables view(const float* mumax) const {
         Tables t;
         t.phot = phot.as<const float4>();
@@ -188,6 +188,11 @@ struct DevTables {
         t.aw_inv = (float)(1.0 / host.aw_step);
         t.aw_n = host.aw_n;
         t.n_mat = host.n_mat;
+        t.kn = kn.as<const float>();
+        t.kn_lo = (float)host.kn_lo;
+        t.kn_inv = (float)(1.0 / host.kn_step);
+        t.kn_ne = host.kn_ne;
+        t.kn_nu = host.kn_nu;
         return t;
     }
 };
@@ -396,6 +401,7 @@ gdpm_status get_tables(gdpm_context ctx, double ecut_g, double ecut_e, uint32_t 
     HIP_TRY(upload(t->rinv, t->host.rinv));
     HIP_TRY(upload(t->rinv_scale, t->host.rinv_scale));
     HIP_TRY(upload(t->aw, t->host.aw));
+    HIP_TRY(upload(t->kn, t->host.kn));
     *out = t.get();
     ctx->tables[key] = std::move(t);
     return GDPM_OK;
@@ -2066,7 +2072,7 @@ gdpm_status gdpm_server_info_get(gdpm_server srv, gdpm_server_info* info) {
         for (int b = 0; b < 2; ++b) res += (double)ctx->rings[r][b].bytes;
     for (auto& t : ctx->tables)
         res += (double)(t.second->phot.bytes + t.second->elec.bytes + t.second->rinv.bytes +
-                        t.second->rinv_scale.bytes + t.second->aw.bytes);
+                        t.second->rinv_scale.bytes + t.second->aw.bytes + t.second->kn.bytes);
     res += ctx->resident_bytes;
     info->resident_bytes = res;
     return GDPM_OK;
@@ -2104,7 +2110,8 @@ gdpm_status gdpm_tables_host(const gdpm_material* m, int n, int n_grid, double e
     case 1: v = &T.elec; g[0] = T.eg_lo; g[1] = T.eg_step; g[2] = T.eg_n; break;
     case 2: v = &T.rinv; g[0] = 0.0; g[1] = 0.0; g[2] = T.nr; break;
     case 3: v = &T.aw; g[0] = T.aw_lo; g[1] = T.aw_step; g[2] = T.aw_n; break;
-    default: return fail(GDPM_E_INVALID, "which must be 0..3");
+    case 4: v = &T.kn; g[0] = T.kn_lo; g[1] = T.kn_step; g[2] = T.kn_ne; g[3] = T.kn_nu; break;
+    default: return fail(GDPM_E_INVALID, "which must be 0..4");
     }
     if (which == 2) {
         // the grid spacing of the inverse range differs per material: return w_max of material 0

@@ -150,6 +150,8 @@ double mw_screening(double t) {
 
 }  // namespace
 
+void build_kn_table(double log2_lo, HostTables& T);
+
 bool build_tables(const std::vector<MaterialParams>& mats, int n_grid, double ecut_g,
                   double ecut_e, uint32_t flags, HostTables* out, std::string* err) {
     if (mats.empty() || (int)mats.size() > 8) {
@@ -266,7 +268,58 @@ bool build_tables(const std::vector<MaterialParams>& mats, int n_grid, double ec
     T.aw.assign(T.aw_n, 0.0f);
     for (int i = 0; i < T.aw_n; ++i)
         T.aw[i] = (float)std::log2(mw_screening(std::exp2(T.aw_lo + i * T.aw_step)));
+
+    // Compton: the inverse of the Klein-Nishina distribution function on the
+    // photon energy range
+    build_kn_table(T.pg_lo, T);
     return true;
+}
+
+// Klein-Nishina mass of eps' in [eps, 1] (unnormalised), in terms of a = 1/eps:
+// the density 1/eps + eps - t(2 - t), t = (a - 1)/k, times |d eps| = da / a^2,
+// integrated from 1 to a:
+// [ln a - 1/(2a^2)] - (2/k)[ln a + 1/a - 1] + (1/k^2)[a - 2 ln a - 1/a]  (+ 1/2 from a = 1)
+double kn_upper_mass(double a, double k) {
+    const double la = std::log(a);
+    return (la - 0.5 / (a * a) + 0.5) - (2.0 / k) * (la + 1.0 / a - 1.0) + (a - 2.0 * la - 1.0 / a) / (k * k);
+}
+
+// eps with F(eps) = u, F the Klein-Nishina distribution function on [eps0, 1]:
+// Newton steps on F (its derivative is the density over the total) inside a
+// bracket that every evaluation narrows, bisecting where a step leaves it
+double kn_quantile(double k, double u) {
+    const double eps0 = 1.0 / (1.0 + 2.0 * k);
+    const double total = kn_upper_mass(1.0 + 2.0 * k, k);
+    double lo = eps0, hi = 1.0, x = std::pow(eps0, 1.0 - u);
+    for (int it = 0; it < 200; ++it) {
+        const double f = 1.0 - kn_upper_mass(1.0 / x, k) / total - u;
+        if (f < 0.0) lo = x;
+        else hi = x;
+        const double t = (1.0 / x - 1.0) / k;
+        const double dens = (1.0 / x + x - t * (2.0 - t)) / total;
+        double xn = x - f / dens;
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (std::fabs(xn - x) <= 1e-15 * x || hi - lo <= 1e-15 * hi) return xn;
+        x = xn;
+    }
+    return x;
+}
+
+void build_kn_table(double log2_lo, HostTables& T) {
+    T.kn_ne = 256;
+    T.kn_nu = 1025;
+    T.kn_lo = log2_lo;
+    T.kn_step = (std::log2(kEmax) - log2_lo) / (T.kn_ne - 1);
+    T.kn.assign((size_t)T.kn_ne * T.kn_nu, 0.0f);
+    for (int i = 0; i < T.kn_ne; ++i) {
+        const double k = std::exp2(T.kn_lo + i * T.kn_step) / kMec2;
+        const double l0 = std::log(1.0 + 2.0 * k);   // ln(1/eps0)
+        for (int j = 0; j < T.kn_nu; ++j) {
+            const double u = (double)j / (T.kn_nu - 1);
+            const double q = j == 0 ? 0.0 : (j == T.kn_nu - 1 ? 1.0 : std::log(kn_quantile(k, u) * (1.0 + 2.0 * k)) / l0);
+            T.kn[(size_t)i * T.kn_nu + j] = (float)q;
+        }
+    }
 }
 
 std::vector<float> build_majorant(const HostTables& t, const std::vector<double>& rho_max) {

@@ -30,6 +30,12 @@ struct HostTables {
     std::vector<float> aw;
     // photon mass attenuation (double) kept for the majorant
     std::vector<double> mu_tot;  // n_mat * pg_n
+    // Klein-Nishina inverse distribution function (material independent):
+    // kn[i * kn_nu + j] = ln(eps / eps0) / ln(1 / eps0) of the eps with F(eps) = u,
+    // at log2 E = kn_lo + i * kn_step and u = j / (kn_nu - 1); eps0 = 1/(1 + 2k)
+    double kn_lo = 0, kn_step = 0;
+    int kn_ne = 0, kn_nu = 0;
+    std::vector<float> kn;
 };
 
 // Largest kinetic energy the tables cover (MeV).

@@ -99,35 +99,28 @@ GDPM_DEV void philox(uint32_t k0, uint32_t k1, uint32_t& x0, uint32_t& x1, uint3
 
 // A lane's stream: key (k0, k1), counter (hist lo, hist hi, path, draw >> 2);
 // draw d is word d & 3 of its block.  A (block `blk`, next word `i`, 4 = used
-// up) is followed by up to Q queued blocks: C (blk + 1) and, for Q = 2, D
-// (blk + 2).  Q = 1 marks C with the flag `qc`, Q = 2 counts C and D in `nq`
-// (each form compiled best for the kernel that uses it).  Blocks are generated
-// with the wavefront converged: rng_topup once per iteration (A has a word
-// left, C is queued), rng_deep at the start of a batch of photon interactions
-// (C and D queued: at least 9 draws, enough for most interactions).  A lane
-// that still runs out takes the out-of-line path, which costs a whole
-// wavefront's Philox for the few lanes in it.  Blocks are only ever generated
-// in counter order, so the draws are the same whatever is buffered.
-template <int Q>
-struct RngT {
+// up) is followed by at most one queued block C (blk + 1, flag `qc`).  Blocks
+// are generated with the wavefront converged: rng_topup once per iteration
+// and at the start of a batch of interactions (A has a word left and C is
+// queued: at least 5 draws, enough for a flight or an electron step, and for
+// a photon interaction, which draws at most 4 with the inverse-CDF Compton
+// sampler).  A lane that still runs out (a rejection loop of an electron hard
+// event) takes the out-of-line path, which costs a whole wavefront's Philox
+// for the few lanes in it.  Blocks are only ever generated in counter order,
+// so the draws are the same whatever is buffered.
+struct Rng {
     uint32_t hlo, hhi, path;
     uint32_t blk, i, skip;
     uint32_t a0, a1, a2, a3;
     uint32_t c0, c1, c2, c3;
-    uint32_t d0, d1, d2, d3;   // Q == 2
-    uint32_t nq;               // Q == 2
-    bool qc;                   // Q == 1
+    bool qc;
 };
-using Rng = RngT<1>;       // electrons, sources, tests
-using RngDeep = RngT<2>;   // photons: an interaction draws more than a flight
 
 // counter of the next draw
-template <int Q>
-GDPM_DEV uint32_t rng_ctr(const RngT<Q>& r) { return 4u * r.blk + r.i; }
+GDPM_DEV uint32_t rng_ctr(const Rng& r) { return 4u * r.blk + r.i; }
 
 // position the stream at draw `ctr` (no block generated yet)
-template <int Q>
-GDPM_DEV void rng_start(RngT<Q>& r, uint32_t hlo, uint32_t hhi, uint32_t path, uint32_t ctr) {
+GDPM_DEV void rng_start(Rng& r, uint32_t hlo, uint32_t hhi, uint32_t path, uint32_t ctr) {
     r.hlo = hlo;
     r.hhi = hhi;
     r.path = path;
@@ -135,7 +128,6 @@ GDPM_DEV void rng_start(RngT<Q>& r, uint32_t hlo, uint32_t hhi, uint32_t path, u
     r.i = 4u;
     r.skip = ctr & 3u;
     r.qc = false;
-    r.nq = 0u;
 }
 
 __device__ __attribute__((noinline)) uint4 rng_block_slow(uint32_t k0, uint32_t k1, uint32_t hlo,
@@ -145,31 +137,18 @@ __device__ __attribute__((noinline)) uint4 rng_block_slow(uint32_t k0, uint32_t 
     return make_uint4(x0, x1, x2, x3);
 }
 
-template <int Q>
-GDPM_DEV uint4 rng_block(uint32_t k0, uint32_t k1, const RngT<Q>& r, uint32_t blk) {
+GDPM_DEV uint4 rng_block(uint32_t k0, uint32_t k1, const Rng& r, uint32_t blk) {
     uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = blk;
     philox(k0, k1, x0, x1, x2, x3);
     return make_uint4(x0, x1, x2, x3);
 }
 
-template <int Q>
-GDPM_DEV bool rng_queued(const RngT<Q>& r) {
-    if constexpr (Q == 1) return r.qc;
-    else return r.nq > 0u;
-}
-
 // A used up: the next block becomes A (from the queue, else generated here,
 // inline or out of line)
-template <int Q>
-GDPM_DEV void rng_advance(RngT<Q>& r, uint32_t k0, uint32_t k1, bool inline_block) {
-    if (rng_queued(r)) {
+GDPM_DEV void rng_advance(Rng& r, uint32_t k0, uint32_t k1, bool inline_block) {
+    if (r.qc) {
         r.a0 = r.c0; r.a1 = r.c1; r.a2 = r.c2; r.a3 = r.c3;
-        if constexpr (Q == 1) {
-            r.qc = false;
-        } else {
-            r.c0 = r.d0; r.c1 = r.d1; r.c2 = r.d2; r.c3 = r.d3;
-            r.nq -= 1u;
-        }
+        r.qc = false;
     } else {
         const uint4 b = inline_block ? rng_block(k0, k1, r, r.blk + 1u)
                                      : rng_block_slow(k0, k1, r.hlo, r.hhi, r.path, r.blk + 1u);
@@ -180,41 +159,21 @@ GDPM_DEV void rng_advance(RngT<Q>& r, uint32_t k0, uint32_t k1, bool inline_bloc
     r.skip = 0u;
 }
 
-// queue the next missing block (C, else D)
-template <int Q>
-GDPM_DEV void rng_queue(RngT<Q>& r, uint32_t k0, uint32_t k1) {
-    if constexpr (Q == 1) {
-        const uint4 b = rng_block(k0, k1, r, r.blk + 1u);
-        r.c0 = b.x; r.c1 = b.y; r.c2 = b.z; r.c3 = b.w;
-        r.qc = true;
-    } else {
-        const uint4 b = rng_block(k0, k1, r, r.blk + 1u + r.nq);
-        if (r.nq == 0u) {
-            r.c0 = b.x; r.c1 = b.y; r.c2 = b.z; r.c3 = b.w;
-        } else {
-            r.d0 = b.x; r.d1 = b.y; r.d2 = b.z; r.d3 = b.w;
-        }
-        r.nq += 1u;
-    }
+// queue the next block (C)
+GDPM_DEV void rng_queue(Rng& r, uint32_t k0, uint32_t k1) {
+    const uint4 b = rng_block(k0, k1, r, r.blk + 1u);
+    r.c0 = b.x; r.c1 = b.y; r.c2 = b.z; r.c3 = b.w;
+    r.qc = true;
 }
 
 // make sure A has a word left and C is queued
-template <int Q>
-GDPM_DEV void rng_topup(RngT<Q>& r, uint32_t k0, uint32_t k1) {
+GDPM_DEV void rng_topup(Rng& r, uint32_t k0, uint32_t k1) {
     if (r.i == 4u) rng_advance(r, k0, k1, true);
-    if (!rng_queued(r)) rng_queue(r, k0, k1);
-}
-
-// make sure A has a word left and C and D are queued (at least 9 draws)
-GDPM_DEV void rng_deep(RngDeep& r, uint32_t k0, uint32_t k1) {
-    if (r.i == 4u) rng_advance(r, k0, k1, true);
-    if (r.nq < 2u) rng_queue(r, k0, k1);
-    if (r.nq < 2u) rng_queue(r, k0, k1);
+    if (!r.qc) rng_queue(r, k0, k1);
 }
 
 // (2 (x >> 9) + 1) 2^-24: exact in single and double precision, inside (0, 1)
-template <int Q>
-GDPM_DEV float uniform(RngT<Q>& r, uint32_t k0, uint32_t k1) {
+GDPM_DEV float uniform(Rng& r, uint32_t k0, uint32_t k1) {
     if (r.i == 4u) rng_advance(r, k0, k1, false);
     const uint32_t w = r.i;
     const uint32_t x = w == 0u ? r.a0 : (w == 1u ? r.a1 : (w == 2u ? r.a2 : r.a3));
@@ -223,8 +182,7 @@ GDPM_DEV float uniform(RngT<Q>& r, uint32_t k0, uint32_t k1) {
 }
 
 // path id of the secondary created in role `word` at the parent's current counter
-template <int Q>
-GDPM_DEV uint32_t spawn_path(const RngT<Q>& r, uint32_t k0, uint32_t k1, int word) {
+GDPM_DEV uint32_t spawn_path(const Rng& r, uint32_t k0, uint32_t k1, int word) {
     uint32_t x0 = r.hlo, x1 = r.hhi, x2 = r.path, x3 = 0x80000000u | rng_ctr(r);
     philox(k0, k1, x0, x1, x2, x3);
     return word == 0 ? x0 : (word == 1 ? x1 : (word == 2 ? x2 : x3));
@@ -847,30 +805,34 @@ GDPM_DEV void pass_finish(LaneTally& t, const WaveTally& c, Ctl* ctl, int ri) {
 // samplers (the draw order is part of the contract with the reference)
 // ---------------------------------------------------------------------------
 
-// Klein-Nishina by Butcher-Messel composition and rejection: eps = E'/E and
-// t = 1 - cos(theta); then the azimuth (in turns)
-template <int Q>
-GDPM_DEV void sample_compton(RngT<Q>& r, uint32_t k0, uint32_t k1, float e, float& eps, float& t,
-                             float& turns) {
+// Klein-Nishina: eps = E'/E where the distribution function reaches one
+// uniform draw u, from the tabulated inverse (bilinear in log2 E and u, of
+// q = ln(eps/eps0)/ln(1/eps0), so that eps = eps0^(1 - q)); then
+// t = 1 - cos(theta) and the azimuth (in turns).  No rejection: every lane
+// of a wavefront runs the same instructions.
+GDPM_DEV void sample_compton(const Tables& T, Rng& r, uint32_t k0, uint32_t k1, float e, float& eps,
+                             float& t, float& turns) {
     const float k = e * (1.0f / kMec2f);
-    const float e0 = hrcp(1.0f + 2.0f * k);
-    const float a1 = kLn2f * hlog2(1.0f + 2.0f * k);
-    const float a2 = 0.5f * (1.0f - e0 * e0);
-    const float ik = hrcp(k);
-    for (;;) {
-        const float ua = uniform(r, k0, k1), ub = uniform(r, k0, k1), uc = uniform(r, k0, k1);
-        if (ua * (a1 + a2) < a1) eps = hexp2(-a1 * ub * (1.0f / kLn2f));
-        else eps = hsqrt(e0 * e0 + (1.0f - e0 * e0) * ub);
-        t = (1.0f - eps) * ik * hrcp(eps);
-        if (uc <= 1.0f - fdiv(eps * t * (2.0f - t), 1.0f + eps * eps)) break;
-    }
+    const float u = uniform(r, k0, k1);
+    float fe = (hlog2(e) - T.kn_lo) * T.kn_inv;
+    fe = fminf(fmaxf(fe, 0.0f), (float)(T.kn_ne - 1));
+    const int i = min((int)fe, T.kn_ne - 2);
+    const float a = fe - (float)i;
+    const float fu = u * (float)(T.kn_nu - 1);
+    const int j = min((int)fu, T.kn_nu - 2);
+    const float b = fu - (float)j;
+    const float* p = T.kn + (i * T.kn_nu + j);
+    const float q0 = fmaf(b, p[1] - p[0], p[0]);
+    const float q1 = fmaf(b, p[T.kn_nu + 1] - p[T.kn_nu], p[T.kn_nu]);
+    const float q = fmaf(a, q1 - q0, q0);
+    eps = fminf(hexp2(-hlog2(1.0f + 2.0f * k) * (1.0f - q)), 1.0f);
+    t = (1.0f - eps) * hrcp(k) * hrcp(eps);
     turns = uniform(r, k0, k1);
 }
 
 // Moller: eps = W/T by a 1/eps^2 proposal on [W_cc/T, 1/2] and rejection
 // eps^2 B(eps) / 2.25; then the azimuth
-template <int Q>
-GDPM_DEV void sample_moller(RngT<Q>& r, uint32_t k0, uint32_t k1, float tt, float wcc, float& eps,
+GDPM_DEV void sample_moller(Rng& r, uint32_t k0, uint32_t k1, float tt, float wcc, float& eps,
                             float& turns) {
     const float g = 1.0f + tt * (1.0f / kMec2f), e0 = fdiv(wcc, tt);
     const float ig = hrcp(g);
@@ -888,8 +850,7 @@ GDPM_DEV void sample_moller(RngT<Q>& r, uint32_t k0, uint32_t k1, float tt, floa
 
 // bremsstrahlung photon energy: 1/k proposal on [W_cb, T], rejection by the
 // complete-screening spectrum
-template <int Q>
-GDPM_DEV float sample_brems(RngT<Q>& r, uint32_t k0, uint32_t k1, float tt, float wcb) {
+GDPM_DEV float sample_brems(Rng& r, uint32_t k0, uint32_t k1, float tt, float wcb) {
     const float lr = hlog2(tt) - hlog2(wcb);
     const float it = hrcp(tt);
     float kph;
@@ -907,8 +868,7 @@ GDPM_DEV float sample_brems(RngT<Q>& r, uint32_t k0, uint32_t k1, float tt, floa
 }
 
 // isotropic direction of the first annihilation photon (cos, then azimuth)
-template <int Q>
-GDPM_DEV void sample_iso(RngT<Q>& r, uint32_t k0, uint32_t k1, float& du, float& dv, float& dw) {
+GDPM_DEV void sample_iso(Rng& r, uint32_t k0, uint32_t k1, float& du, float& dv, float& dw) {
     const float ct = 2.0f * uniform(r, k0, k1) - 1.0f;
     const float turns = uniform(r, k0, k1);
     const float st = hsqrt((1.0f - ct) * (1.0f + ct));
@@ -978,10 +938,9 @@ GDPM_DEV void write_particle(Particle* buf, uint32_t mask, uint32_t slot, float 
 }
 
 // secondaries inherit the job and the batch slot (`jb`) of their history
-template <int Q>
 GDPM_DEV void push_charged(PendCharged& q, PushState& ps, uint32_t head, Ctl* ctl, const RunDev& R,
                            const WJob& W, uint32_t jb, Particle* buf, float x, float y, float z,
-                           uint32_t vox, const RngT<Q>& rng, WaveTally& c) {
+                           uint32_t vox, const Rng& rng, WaveTally& c) {
     const uint64_t b0 = ballot(q.n >= 1), b1 = ballot(q.n >= 2);
     const uint32_t n0 = (uint32_t)__popcll(b0), n = n0 + (uint32_t)__popcll(b1);
     if (n == 0) return;
@@ -998,10 +957,9 @@ GDPM_DEV void push_charged(PendCharged& q, PushState& ps, uint32_t head, Ctl* ct
     q.n = 0;
 }
 
-template <int Q>
 GDPM_DEV void push_photons(PendPhoton& q, PushState& ps, uint32_t head, Ctl* ctl, const RunDev& R,
                            const WJob& W, uint32_t jb, Particle* buf, float x, float y, float z,
-                           const RngT<Q>& rng, WaveTally& c) {
+                           const Rng& rng, WaveTally& c) {
     const uint64_t b0 = ballot(q.n >= 1), b1 = ballot(q.n >= 2);
     const uint32_t n0 = (uint32_t)__popcll(b0), n = n0 + (uint32_t)__popcll(b1);
     if (n == 0) return;
@@ -1345,7 +1303,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
         float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
         uint32_t pb = 0u;   // batch slot of the lane's history
         int pm = -1;        // >= 0: a real interaction waits, in a voxel of this material
-        RngDeep rng;
+        Rng rng;
         rng_start(rng, 0u, 0u, 0u, 0u);
         int next = -1;
         for (;;) {
@@ -1430,14 +1388,14 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                 if (br && (cs.done || (uint32_t)__popcll(br) >= kRealBatch || br == ballot(active))) {
                     int itype = -1;   // the interaction sampled by this lane
                     if (pm >= 0) {
-                        rng_deep(rng, k0, k1);
+                        rng_topup(rng, k0, k1);
                         const int vv = voxel_of(W.G, x, y, z, ix, iy, iz);
                         const float4 mu = lerp4(ptab + pm * T.pg_n, gi, gt);
                         const float r = uniform(rng, k0, k1) * mu.w;
                         itype = r < mu.x ? 0 : (r < mu.x + mu.y ? 1 : 2);
                         if (itype == 0) {
                             float eps, t, turns;
-                            sample_compton(rng, k0, k1, e, eps, t, turns);
+                            sample_compton(T, rng, k0, k1, e, eps, t, turns);
                             const float u0 = u, v0 = v, w0 = w;
                             rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
                             // exact split of E into E' and T (the unit is built without
@@ -2108,7 +2066,7 @@ __global__ void k_test_sample(Tables T, int which, float e, float p1, float p2, 
     float a = 0.0f, b = 0.0f;
     if (which == 0) {
         float eps, t, turns;
-        sample_compton(r, k0, k1, e, eps, t, turns);
+        sample_compton(T, r, k0, k1, e, eps, t, turns);
         a = eps;
         b = 1.0f - t;
     } else if (which == 1) {
@@ -2144,7 +2102,7 @@ __global__ void k_test_sample(Tables T, int which, float e, float p1, float p2, 
     } else if (which == 7) {
         // the photon interaction's kinematics on a photon along +z
         float eps, t, turns;
-        sample_compton(r, k0, k1, e, eps, t, turns);
+        sample_compton(T, r, k0, k1, e, eps, t, turns);
         float u = 0.0f, v = 0.0f, w = 1.0f;
         rotate(u, v, w, 1.0f - t, hsqrt(fmaxf(0.0f, t * (2.0f - t))), turns);
         const float e1 = eps * e;

@@ -165,6 +165,55 @@ def test_mw_screening_table_matches_oracle():
             assert abs(2.0 ** (0.5 * (t[k] + t[k + 1])) / a_mid - 1) < 2e-4
 
 
+def test_klein_nishina_inverse_table():
+    """The Compton sampler's table: at node (E, u) it holds q with eps =
+    eps0^(1 - q) at the u-quantile of Klein-Nishina; F(eps) from adaptive
+    quadrature of the oracle's differential cross section must equal u to the
+    single-precision rounding of q, at both ends exactly, and q must increase
+    with u.  Between nodes, the bilinear value's eps is within 3e-5 of the
+    exact quantile (the device samples it)."""
+    from scipy.integrate import quad
+    t, g = G.tables_host(I.MATERIALS, 4)
+    ne, nu = int(g[2]), int(g[3])
+    q = t.reshape(ne, nu).astype(np.float64)
+    assert np.all(q[:, 0] == 0.0) and np.all(q[:, -1] == 1.0)
+    assert np.all(np.diff(q, axis=1) > 0)
+    MC2 = 0.51099895
+
+    def cdf(e, eps):
+        k = e / MC2
+        e0 = 1 / (1 + 2 * k)
+        f = lambda x: oracle.phys(oracle.DSIGMA_KN, I.WATER, e, x)
+        tot = quad(f, e0, 1, epsabs=0, epsrel=1e-12, limit=200)[0]
+        return quad(f, e0, eps, epsabs=0, epsrel=1e-12, limit=200)[0] / tot
+
+    def eps_of(e, qq):
+        return (1 + 2 * e / MC2) ** (qq - 1)
+
+    for i in (0, 37, 128, ne - 1):
+        e = 2.0 ** (g[0] + i * g[1])
+        for j in (1, 40, 128, 200, nu - 2):
+            u = j / (nu - 1)
+            # q is single precision: the quantile is off by about 1e-7 of ln(1/eps0)
+            assert abs(cdf(e, eps_of(e, q[i, j])) - u) < 2e-6
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        fi, u = rng.uniform(0, ne - 1), rng.uniform(0, 1)
+        i, fu = min(int(fi), ne - 2), u * (nu - 1)
+        j = min(int(fu), nu - 2)
+        a, b = fi - i, fu - j
+        qq = (1 - a) * ((1 - b) * q[i, j] + b * q[i, j + 1]) + a * ((1 - b) * q[i + 1, j] + b * q[i + 1, j + 1])
+        e = 2.0 ** (g[0] + fi * g[1])
+        k = e / MC2
+        eps = eps_of(e, qq)
+        # the exact quantile by bisection on the quadrature distribution function
+        lo, hi = 1 / (1 + 2 * k), 1.0
+        for _ in range(45):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if cdf(e, mid) < u else (lo, mid)
+        assert abs(eps / (0.5 * (lo + hi)) - 1) < 3e-5
+
+
 def test_phantom_sizes_checked_before_the_device():
     """The linear voxel index is a signed 32-bit integer on the device, so a
     phantom of 2^31 voxels or more is rejected; the sizes are checked before

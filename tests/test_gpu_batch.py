@@ -109,11 +109,14 @@ def test_batch_source_modes_equal_solo(gctx):
 
 def test_batch_graphs_equal_direct_launches():
     """The batched form with each iteration replayed from a recorded HIP graph
-    (the default) against direct launches: same doses, same events."""
+    (the default) against direct launches: same doses, same events.  A small
+    history budget per iteration makes many iterations of the same launch
+    configuration, so that recordings are replayed whatever the jobs' event
+    counts."""
     jobs = small_jobs(seed=4103)
     res = {}
     for graphs in (0, 1):
-        c2 = G.Context(0, opts=f'{{"graphs": {graphs}}}', materials=MATS)
+        c2 = G.Context(0, opts=f'{{"graphs": {graphs}, "pass_histories": 4000}}', materials=MATS)
         handles = [(c2.phantom(w.phantom), c2.source(w.source), kw) for w, kw in jobs]
         try:
             res[graphs] = c2.run_batch(handles)
