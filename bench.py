@@ -303,12 +303,13 @@ SERVE_POLICIES = {
     "shared_least_work_first": ('{"issue_order": 1}', 64),
     "shared_admission_order": ('{"issue_order": 2}', 64),
     "admit_while_draining": ('{"issue_order": 2, "admit_draining": 1}', 64),
+    "admit_at_final_drain": ('{"issue_order": 2, "admit_draining": 2}', 64),
 }
 
 
 # the bench line's default set (least work first lost to even shares on p99 in
 # every measurement: it starves the long VMAT jobs)
-SERVE_DEFAULT = ("per_job_launches", "shared_even", "shared_admission_order", "admit_while_draining")
+SERVE_DEFAULT = ("per_job_launches", "shared_even", "shared_admission_order", "admit_at_final_drain")
 
 
 def served_form(G, I, seconds, rate, ct, opts=None, load=0.7, policies=None, service_sample=0, stated=True):

@@ -268,10 +268,12 @@ typedef struct {
  * which runs start; positions advance with every record and wrap modulo
  * 2^32, which a value near 2^32 brings forward; default 0),
  * "admit_draining" (servers: 1 admits a job only while every running job has
- * issued all the histories of its current super-round, so that a new job
- * fills the queues a running job leaves as it drains instead of sharing the
- * device with jobs large enough to fill it alone; default 0: admission by
- * slots and device footprint only), "solo_lanes" (1: a measurement form of
+ * issued all the histories of its current super-round, 2 only while every
+ * running job drains the super-round planned as its last (the one sized by
+ * the sigma ~ N^-1/2 estimate to reach its target, or a fixed-count job's
+ * only one), so that a new job fills the queues a running job leaves as it
+ * drains instead of sharing the device with jobs large enough to fill it
+ * alone; default 0: admission by slots and device footprint only), "solo_lanes" (1: a measurement form of
  * the transport kernels in which a wavefront carries one particle at a time,
  * so that it executes exactly the instructions of that particle's path; very
  * slow; needs "lds_tables" on and "autotune" off; default 0).

@@ -21,7 +21,7 @@ constexpr uint32_t kTailMinPerLane = 4; // ... if the pass had this many per lan
 #endif
 constexpr uint32_t kHardBatch = GDPM_HARD_BATCH;  // electron hard events sampled together
 #ifndef GDPM_REAL_BATCH
-#define GDPM_REAL_BATCH 28
+#define GDPM_REAL_BATCH 22
 #endif
 constexpr uint32_t kRealBatch = GDPM_REAL_BATCH;  // photon interactions sampled together
 constexpr uint32_t kRefillMin = 12;     // empty lanes a wavefront refills at once

@@ -264,7 +264,8 @@ struct gdpm_context_s {
     int graphs = 1;              // replay each iteration's launches as a recorded HIP graph
     int check_accounting = 0;    // after every iteration, count each job's live records
     int solo_lanes = 0;          // measurement form: one particle per wavefront at a time
-    int admit_draining = 0;      // server: admit a job only while every running job drains
+    int admit_draining = 0;      // server: admit a job only while every running job drains (1: any
+                                 // super-round, 2: its last one)
     uint32_t ring_start = 0;     // queue position a run starts at (positions run modulo 2^32)
     int max_lds = 0;             // dynamic LDS bytes a workgroup may use
     bool lds_optin = false;
@@ -528,6 +529,7 @@ struct EJob {
     uint64_t hbase = 0;         // id of the job's first history
     uint64_t issued = 0;        // histories started (relative ids [0, issued))
     uint64_t sr_start = 0, sr_end = 0;  // the running super-round
+    bool sr_final = false;              // planned as the job's last super-round
     uint64_t round_size = 0;
     uint64_t max_hist = 0;
     std::vector<double> nhist;  // histories per batch slot
@@ -795,6 +797,7 @@ gdpm_status Engine::admit(EJob* j) {
     j->sr_start = 0;
     j->sr_end = plan.target ? (uint64_t)plan.nb * j->round_size
                             : std::min<uint64_t>(plan.n_hist, (uint64_t)plan.nb * j->round_size);
+    j->sr_final = !plan.target;   // a fixed-count job runs one super-round
     j->done = false;
     j->status = GDPM_OK;
     j->t_admit = now_s();
@@ -1129,6 +1132,7 @@ gdpm_status Engine::settle() {
         j->round_size = std::max<uint64_t>(1, (more + j->plan.nb - 1) / j->plan.nb);
         j->sr_start = j->issued;
         j->sr_end = j->issued + (uint64_t)j->plan.nb * j->round_size;
+        j->sr_final = true;   // sized to reach the target (or the history cap)
     }
     // nothing left anywhere but a job still waits: the bookkeeping is broken
     const Ctl* hc = ctx->host_ctl;
@@ -1360,18 +1364,21 @@ void gdpm_server_s::loop() {
     std::unique_lock<std::mutex> lk(m);
     for (;;) {
         // admission in arrival order, by slots and device footprint; with
-        // admit_draining, only while every running job has issued all the
+        // admit_draining 1, only while every running job has issued all the
         // histories of its current super-round (its particles drain from the
-        // queues, or it waits for its statistics): a new job then fills the
-        // device instead of sharing it with jobs that could fill it alone
+        // queues, or it waits for its statistics), with 2 only while every
+        // running job drains the super-round planned as its last: a new job
+        // then fills the device a finishing job leaves instead of sharing it
+        // with jobs that could fill it alone
         while (!pending.empty() && (int)running.size() < max_slots) {
             if (ctx->admit_draining && !running.empty()) {
-                bool issuing = false;
+                bool busy = false;
                 for (gdpm_job_s* r : running) {
                     const EJob* q = r->ej.get();
-                    issuing = issuing || (!q->done && q->issued < q->sr_end);
+                    const bool draining = q->issued >= q->sr_end && (ctx->admit_draining == 1 || q->sr_final);
+                    busy = busy || (!q->done && !draining);
                 }
-                if (issuing) break;
+                if (busy) break;
             }
             gdpm_job_s* job = pending.front();
             EJob* j = job->ej.get();
@@ -1490,7 +1497,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
                     "(admission order first)");
     if (ctx->share != 1)
         return fail(GDPM_E_INVALID, "share must be 1: the oldest-job-first policy (0) can overflow the queues");
-    if (ctx->admit_draining != 0 && ctx->admit_draining != 1) return fail(GDPM_E_INVALID, "admit_draining is 0 or 1");
+    if (ctx->admit_draining < 0 || ctx->admit_draining > 2) return fail(GDPM_E_INVALID, "admit_draining is 0, 1 or 2");
     if (ctx->solo_lanes != 0 && (ctx->solo_lanes != 1 || !ctx->lds_tables || ctx->autotune))
         return fail(GDPM_E_INVALID, "solo_lanes is 0 or 1 and needs lds_tables on and autotune off");
     HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device));
