@@ -186,7 +186,9 @@ typedef struct {
     double t_total_s;            /* wall time of the call */
     double t_kernel_s;           /* device time of the transport kernels (HIP events) */
     double t_photon_s, t_electron_s;  /* device time per pass type */
-    uint64_t events[8];          /* GDPM_EV_* counters */
+    uint64_t events[8];          /* GDPM_EV_* counters of the run (for a job of a batch or a
+                                    server: the engine's totals, all jobs, when it finished;
+                                    events[GDPM_EV_HISTORIES] is the job's own) */
     uint32_t passes;             /* transport kernel launches */
     uint32_t rounds;
     uint32_t passes_photon;      /* photon kernel launches (t_photon_s covers them) */
