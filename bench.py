@@ -101,7 +101,9 @@ def cpu_baseline(workload, seconds):
                    n_batches=2, n_threads=threads, want_batches=False)
         return time.perf_counter() - t0
 
-    n1, n2 = 2000, 20000
+    # probes large enough (about a second on 16 threads) that the threads' start
+    # and the first touches of the tables do not inflate the rate
+    n1, n2 = 20_000, 200_000
     d1 = timed(n1, 0)
     d2 = timed(n2, n1)
     rate = (n2 - n1) / max(d2 - d1, 1e-3)          # setup time cancels
