@@ -276,7 +276,10 @@ def run_stream(G, ctx, hs, times, slots, budget, label):
     log_accounting(label, res)
     kinds = [kw.get("kind", "") for _, _, kw in hs]
     log(f"{label}: p50 {pct(lat, 50):.2f} s, p99 {pct(lat, 99):.2f} s, span {wall - times[0]:.2f} s")
-    return {"seconds": wall, "histories_per_s": hist / max(wall - times[0], 1e-9),
+    # the engine's totals when the last job finished: device time of the
+    # transport kernels (HIP events) and launches, over the whole stream
+    engine = {k: max(r[k] for r in res) for k in ("t_kernel_s", "t_photon_s", "t_electron_s", "passes")}
+    return {"seconds": wall, "histories_per_s": hist / max(wall - times[0], 1e-9), "engine_totals": engine,
             "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(np.mean(lat)),
                           "max": float(np.max(lat))},
             "memory_high_water_bytes": info["high_water_bytes"] + info["resident_bytes"],
