@@ -278,7 +278,8 @@ def run_stream(G, ctx, hs, times, slots, budget, label):
     log(f"{label}: p50 {pct(lat, 50):.2f} s, p99 {pct(lat, 99):.2f} s, span {wall - times[0]:.2f} s")
     # the engine's totals when the last job finished: device time of the
     # transport kernels (HIP events) and launches, over the whole stream
-    engine = {k: max(r[k] for r in res) for k in ("t_kernel_s", "t_photon_s", "t_electron_s", "passes")}
+    engine = {k: max(r[k] for r in res) for k in ("t_kernel_s", "t_photon_s", "t_electron_s", "passes",
+                                                   "graph_launches", "graphs_recorded", "passes_rebinned")}
     return {"seconds": wall, "histories_per_s": hist / max(wall - times[0], 1e-9), "engine_totals": engine,
             "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(np.mean(lat)),
                           "max": float(np.max(lat))},
@@ -336,9 +337,15 @@ def served_form(G, I, seconds, rate, ct, opts=None, load=0.7, policies=None, ser
     out = {"workload": f"Poisson {rate} jobs/s for {seconds} s: {len(reqs)} requests, VMAT-180 on "
                        "256x256x128 CT or IMRT-9 on 128x128x64 CT, to 1% or 2%",
            "requests": len(reqs), "hbm_budget_bytes": budget, "policies": policies}
+    def merged(name):
+        # the policy's options, with --opts on top
+        d = json.loads(SERVE_POLICIES[name][0] or "{}")
+        d.update(json.loads(opts or "{}"))
+        return json.dumps(d, sort_keys=True)
+
     ctxs = {}
     for name in policies:
-        o = SERVE_POLICIES[name][0] or opts
+        o = merged(name)
         if o not in ctxs:
             ctxs[o] = G.Context(0, opts=o, materials=I.MATERIALS)
     hs = {o: [] for o in ctxs}
@@ -388,7 +395,7 @@ def served_form(G, I, seconds, rate, ct, opts=None, load=0.7, policies=None, ser
                               "max": float(np.max(lat))},
                 "histories_per_s": hist / max(done - ts[0], 1e-9)}
         for name in policies:
-            o, slots = SERVE_POLICIES[name][0] or opts, SERVE_POLICIES[name][1]
+            o, slots = merged(name), SERVE_POLICIES[name][1]
             res[name] = run_stream(G, ctxs[o], hs[o], ts, slots, budget, f"served {sname}: {name}")
         out[sname] = res
     for o, ctx in ctxs.items():

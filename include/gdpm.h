@@ -222,6 +222,9 @@ typedef struct {
      * particles still held by a wavefront at the tail of a large pass, or when
      * it switched jobs */
     uint64_t records_requeued[2];
+    /* transport passes whose queue was re-binned by job first (every pass in
+     * which more than one job holds particles), counted like passes */
+    uint32_t passes_rebinned;
 } gdpm_run_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -60,6 +60,8 @@ struct RingCtl {
     uint32_t begin, count;   // input of the running pass: [begin, begin + count)
     uint32_t claim;          // claim counter of the running pass
     uint32_t cur;            // which of the two buffers holds the ring
+    uint32_t permuted;       // 1: the pass reads its input through the permutation
+    uint32_t next_head;      // head after a permuted pass (the tail before it)
 };
 
 // Device-resident control block of the transport (the host reads it back
@@ -215,6 +217,23 @@ struct SrcHdr {
     uint32_t nseg, total;
     uint32_t pad0, pad1;
 };
+
+// Re-binning by job alone leaves the records where they are.  It uses the
+// queue's other buffer (idle: only the re-binning by job and energy copies
+// records into it) for two arrays of C 32-bit words, C the queue capacity:
+// each input position's job (kEmptyJob for an empty position, kOrphanJob for a
+// record of a job no longer running), then the permutation, the queue
+// positions of the pass's input in job order, which the pass reads its input
+// through.
+constexpr uint32_t kEmptyJob = 0xFFFFFFFFu, kOrphanJob = 0xFFFFFFFEu;
+__host__ __device__ inline uint32_t* bin_jobs(Particle* other) { return reinterpret_cast<uint32_t*>(other); }
+__host__ __device__ inline const uint32_t* bin_jobs(const Particle* other) {
+    return reinterpret_cast<const uint32_t*>(other);
+}
+__host__ __device__ inline uint32_t* bin_perm(Particle* other, uint32_t mask) {
+    return reinterpret_cast<uint32_t*>(other) + ((size_t)mask + 1u);
+}
+static_assert(2 * sizeof(uint32_t) <= sizeof(Particle), "job words and permutation fit in a buffer");
 
 struct RunDev {
     float ecut_g, ecut_e;      // shared by every job (the tables depend on them)

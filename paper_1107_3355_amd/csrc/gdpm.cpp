@@ -38,7 +38,7 @@ hipError_t launch_source(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, 
 hipError_t launch_finish(hipStream_t st, Ctl* ctl, int ri);
 size_t transport_lds_bytes(int ri, const Tables& T, int waves);
 hipError_t transport_lds_optin(size_t bytes);
-hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, bool solo,
+hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, bool solo, bool permuted,
                             Ctl* ctl, const Tables& T, const RunDev& R);
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
                         float lo, float inv);
@@ -496,6 +496,7 @@ struct Timers {
     double photon = 0, electron = 0;
     uint32_t passes = 0, passes_photon = 0, passes_electron = 0;
     uint32_t graph_launches = 0, graphs_recorded = 0;
+    uint32_t passes_rebinned = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -931,6 +932,7 @@ gdpm_status Engine::step() {
         // energy order gains nothing, and push order keeps some spatial
         // locality), the pass then reads the queue as it is, empty slots included
         k.rebin[ri] = !M.fixed && ((ri == 0 ? ctx->rebin_photons : ctx->rebin_electrons) || holders > 1 || lone < 0);
+        if (k.rebin[ri]) tm.passes_rebinned++;
         k.lds[ri] = ctx->lds_tables && transport_lds_bytes(ri, T, k.threads / 64) <= (size_t)ctx->max_lds;
         tm.passes++;
         (ri == 0 ? tm.passes_photon : tm.passes_electron)++;
@@ -1013,8 +1015,8 @@ gdpm_status Engine::issue(const StepGraphKey& k, bool recording) {
         // a recorded event becomes a node of the graph that records it at replay
         HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri], st, hipEventRecordExternal)
                           : hipEventRecord(ctx->events[2 * ri], st));
-        HIP_TRY(launch_transport(st, ri, k.blocks, k.threads, k.lds[ri] != 0, ctx->solo_lanes != 0, dc, k.T,
-                                 k.R));
+        HIP_TRY(launch_transport(st, ri, k.blocks, k.threads, k.lds[ri] != 0, ctx->solo_lanes != 0,
+                                 k.rebin[ri] && k.nb == 1, dc, k.T, k.R));
         HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri + 1], st, hipEventRecordExternal)
                           : hipEventRecord(ctx->events[2 * ri + 1], st));
         HIP_TRY(launch_finish(st, dc, ri));
@@ -1196,6 +1198,7 @@ void fill_stats(const Engine& E, const EJob* j, double t_start, gdpm_run_stats* 
     out->transport_anomalies = hc->anomalies;
     out->graph_launches = E.tm.graph_launches;
     out->graphs_recorded = E.tm.graphs_recorded;
+    out->passes_rebinned = E.tm.passes_rebinned;
     out->accounting_mismatches = E.mismatches;
     // the kernels count photoelectric, pair and Moller events; Compton and
     // bremsstrahlung are the rest of the real interactions and hard events

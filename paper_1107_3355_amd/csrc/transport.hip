@@ -987,7 +987,10 @@ GDPM_DEV void push_photons(PendPhoton& q, PushState& ps, uint32_t head, Ctl* ctl
 __global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri, int rebinned, int lone) {
     JobCtl* jc = R.jc;
     RingCtl& r = ctl->ring[ri];
-    const uint32_t count = ctl->overflow ? 0u : r.tail - r.head;
+    // a permuted pass reads positions [0, n_valid) of the permutation; its
+    // records stay in [head, tail), which it consumes whole
+    const bool perm = rebinned && r.permuted;
+    const uint32_t count = ctl->overflow ? 0u : (perm ? ctl->n_valid : r.tail - r.head);
     if (!rebinned)
         for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) {
             jc->seg_begin[j] = j <= lone ? 0u : count;
@@ -995,9 +998,11 @@ __global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri, int r
         }
     __syncthreads();
     if (threadIdx.x == 0) {
-        r.begin = r.head;
+        r.begin = perm ? 0u : r.head;
         r.count = count;
         r.claim = 0u;
+        r.next_head = r.tail;
+        if (!perm) r.permuted = 0u;
     }
     for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) jc->claim[j] = 0u;
     const int nw = (R.n_jobs + 63) >> 6;
@@ -1012,8 +1017,9 @@ __global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri, int r
 
 __global__ void k_finish(Ctl* ctl, int ri) {
     RingCtl& r = ctl->ring[ri];
-    r.head = r.begin + r.count;
+    r.head = r.permuted ? r.next_head : r.begin + r.count;
     r.count = 0u;
+    r.permuted = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1063,18 +1069,26 @@ GDPM_DEV Particle load_staged(const float4* st, uint32_t k) {
     return p;
 }
 
+// the queue position of input position `pos` of a pass: itself, or through the
+// permutation of a pass re-binned by job (`perm` non-null); both masked, so
+// that any value reads inside the queue
+GDPM_DEV uint32_t input_slot(const uint32_t* perm, uint32_t mask, uint32_t pos) {
+    return (perm ? perm[pos & mask] : pos) & mask;
+}
+
 // stage the records of positions [cs.next, cs.next + kStage) (every lane: 4
 // loads of 16 bytes; lane L of load c fetches piece L % 4 of record 16 c + L / 4,
 // which lands at float4 64 c + L of the slice).  Positions past the chunk are
 // loaded too (the ring index is masked) and never used.
 GDPM_DEV void stage_records(ClaimState& cs, float4* st, const Particle* buf, uint32_t mask,
-                            uint32_t first) {
+                            uint32_t first, const uint32_t* perm) {
     // the refill's reads of the slice are complete before it is overwritten
     __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
     const uint32_t l = lane_id();
     for (uint32_t c = 0; c < 4; ++c) {
         const uint32_t rec = 16u * c + (l >> 2);
-        const float4* src = reinterpret_cast<const float4*>(buf + ((first + cs.next + rec) & mask)) + (l & 3u);
+        const float4* src = reinterpret_cast<const float4*>(buf + input_slot(perm, mask, first + cs.next + rec)) +
+                            (l & 3u);
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                          (__attribute__((address_space(3))) void*)(st + 64u * c), 16, 0, 0);
     }
@@ -1091,8 +1105,8 @@ GDPM_DEV void stage_records(ClaimState& cs, float4* st, const Particle* buf, uin
 // executes exactly the instructions of that particle's path.
 template <bool kSolo>
 GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uint32_t begin,
-                     Ctl* ctl, const Particle* buf, uint32_t mask, Particle& p, WaveTally& c,
-                     float4* st) {
+                     Ctl* ctl, const Particle* buf, uint32_t mask, const uint32_t* perm, Particle& p,
+                     WaveTally& c, float4* st) {
     if (cs.done) return false;
     const uint64_t need = ballot(!active);
     if (!need) return false;
@@ -1112,7 +1126,7 @@ GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uin
     bool got = false;
     if (!active && rank < take) {
         p = staged ? load_staged(st, cs.next + rank - cs.st_lo)
-                   : load(buf, mask, first + cs.next + rank);
+                   : load(buf, mask, input_slot(perm, mask, first + cs.next + rank));
         got = !record_empty(p.e);
         if (got && (p.job & 0xFFFFu) != W.tag) {
             // a record of another job (or of an earlier job in this slot) in
@@ -1127,7 +1141,7 @@ GDPM_DEV bool refill(bool active, ClaimState& cs, JobCtl* jc, const WJob& W, uin
     if (st != nullptr && cs.next < cs.end) {
         // positions of a pass's segment do not wrap: plain comparisons
         const uint32_t left = cs.next >= cs.st_lo && cs.next < cs.st_hi ? cs.st_hi - cs.next : 0u;
-        if (left <= kStageLow) stage_records(cs, st, buf, mask, first);
+        if (left <= kStageLow) stage_records(cs, st, buf, mask, first, perm);
     }
     return got;
 }
@@ -1263,7 +1277,7 @@ GDPM_HD uint32_t stage_offset(int ri, const Tables& T, int waves) {
     return tab + (floats + 3u) / 4u;
 }
 
-template <bool kLds, bool kSolo>
+template <bool kLds, bool kSolo, bool kPerm>
 __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     const float4* ptab = T.phot;
     float* lmw = nullptr;
@@ -1279,6 +1293,10 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     }
     RingCtl* rc = &ctl->ring[0];
     const uint32_t begin = rc->begin, count = rc->count;
+    // a pass re-binned by job reads its input through the permutation (only the
+    // kPerm form has that code: single-job passes keep the plain reads)
+    const uint32_t* perm_in =
+        kPerm && __builtin_amdgcn_readfirstlane(rc->permuted) ? bin_perm(R.buf[0][rc->cur ^ 1u], R.mask[0]) : nullptr;
     const bool big = !kSolo && count >= kTailMinPerLane * gridDim.x * blockDim.x;
     Particle* bufg = R.buf[0][ctl->ring[0].cur];
     Particle* bufe = R.buf[1][ctl->ring[1].cur];
@@ -1310,7 +1328,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
             const uint32_t k0 = W.k0, k1 = W.k1;
             const bool kerma = (W.flags & 64u) != 0u;
             Particle p;
-            if (refill<kSolo>(active, cs, jc, W, begin, ctl, bufg, R.mask[0], p, wt, stage)) {
+            if (refill<kSolo>(active, cs, jc, W, begin, ctl, bufg, R.mask[0], perm_in, p, wt, stage)) {
                 x = p.x; y = p.y; z = p.z; e = p.e;
                 u = p.u; v = p.v; w = p.w;
                 pb = p.job >> 16;
@@ -1514,7 +1532,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
 // electron pass: class-II condensed history with a random hinge, one step per
 // iteration (section 2.1)
 // ---------------------------------------------------------------------------
-template <bool kLds, bool kSolo>
+template <bool kLds, bool kSolo, bool kPerm>
 __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) {
     const float4* etab = T.elec;
     const float* rtab = T.rinv;
@@ -1535,6 +1553,8 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     }
     RingCtl* rc = &ctl->ring[1];
     const uint32_t begin = rc->begin, count = rc->count;
+    const uint32_t* perm_in =
+        kPerm && __builtin_amdgcn_readfirstlane(rc->permuted) ? bin_perm(R.buf[1][rc->cur ^ 1u], R.mask[1]) : nullptr;
     const bool big = !kSolo && count >= kTailMinPerLane * gridDim.x * blockDim.x;
     Particle* bufg = R.buf[0][ctl->ring[0].cur];
     Particle* bufe = R.buf[1][ctl->ring[1].cur];
@@ -1569,7 +1589,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
             const uint32_t k0 = W.k0, k1 = W.k1;
             const bool no_ms = (W.flags & 8u) != 0u;
             Particle p;
-            if (refill<kSolo>(active, cs, jc, W, begin, ctl, bufe, R.mask[1], p, wt, stage)) {
+            if (refill<kSolo>(active, cs, jc, W, begin, ctl, bufe, R.mask[1], perm_in, p, wt, stage)) {
                 x = p.x; y = p.y; z = p.z; e = p.e;
                 u = p.u; v = p.v; w = p.w; nh = p.nh;
                 ix = (int)(p.vox & 2047u);
@@ -1854,10 +1874,14 @@ __global__ void __launch_bounds__(256) k_bin_count(Ctl* ctl, RunDev R, int ri, i
     const RingCtl& r = ctl->ring[ri];
     const uint32_t n = r.tail - r.head;
     const Particle* buf = R.buf[ri][r.cur];
+    // by job alone, each position's job is also kept (4 B in the idle buffer),
+    // so that the scatter does not read the records again
+    uint32_t* jw = nb == 1 ? bin_jobs(R.buf[ri][r.cur ^ 1u]) : nullptr;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         bool live;
         const int k = record_key(R, buf, R.mask[ri], r.head + i, nb, lo, inv, live);
         if (k >= 0) atomicAdd(&hist[k], 1u);
+        if (jw != nullptr) jw[i] = !live ? kEmptyJob : (k < 0 ? kOrphanJob : (uint32_t)k);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nk; i += blockDim.x)
@@ -1908,18 +1932,30 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri,
     uint32_t* base = cnt + nk;
     const RingCtl& r = ctl->ring[ri];
     const uint32_t n = r.tail - r.head;
+    const uint32_t mask = R.mask[ri];
     const Particle* src = R.buf[ri][r.cur];
-    Particle* dst = R.buf[ri][r.cur ^ 1u];
-    // each block moves one contiguous share of the queue: it counts its keys,
-    // takes its place in every key's run with one atomic per key, then moves
-    // its records (one global atomic per key and block, not per tile)
+    // each block takes one contiguous share of the queue: it counts its keys,
+    // takes its place in every key's run with one atomic per key, then places
+    // its records (one global atomic per key and block, not per tile).  By job
+    // alone (nb = 1) the records stay where they are: the keys come from the
+    // job words the count pass kept, and the pass reads the records in job
+    // order through the permutation written here.  With energy bins the records
+    // are copied into the other buffer in key order.
+    Particle* other = R.buf[ri][r.cur ^ 1u];
+    const uint32_t* jw = bin_jobs(other);
     const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
     const uint32_t i0 = min(n, blockIdx.x * per), i1 = min(n, i0 + per);
     for (int q = threadIdx.x; q < nk; q += blockDim.x) cnt[q] = 0u;
     __syncthreads();
     for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        bool live;
-        const int k = record_key(R, src, R.mask[ri], r.head + i, nb, lo, inv, live);
+        int k;
+        if (nb == 1) {
+            const uint32_t w = jw[i];
+            k = w >= kOrphanJob ? -1 : (int)w;
+        } else {
+            bool live;
+            k = record_key(R, src, mask, r.head + i, nb, lo, inv, live);
+        }
         if (k >= 0) atomicAdd(&cnt[k], 1u);
     }
     __syncthreads();
@@ -1928,13 +1964,28 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri,
         cnt[q] = 0u;
     }
     __syncthreads();
+    if (nb == 1) {
+        uint32_t* perm = bin_perm(other, mask);
+        for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            const uint32_t w = jw[i];
+            if (w == kEmptyJob) continue;
+            if (w != kOrphanJob) {
+                perm[(base[w] + atomicAdd(&cnt[w], 1u)) & mask] = r.head + i;
+            } else {
+                // a record of a job no longer running: only a broken bookkeeping
+                // leaves one; it is dropped (the count pass skipped it) and counted
+                atomicAdd(&ctl->anomalies, 1ull);
+            }
+        }
+        return;
+    }
     for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        const Particle p = load(src, R.mask[ri], r.head + i);
+        const Particle p = load(src, mask, r.head + i);
         if (record_empty(p.e)) continue;
         const int job = record_job(R, p.job);
         if (job >= 0) {
             const int k = job * nb + energy_bin(p.e, lo, inv, nb);
-            store(dst, R.mask[ri], base[k] + atomicAdd(&cnt[k], 1u), p);
+            store(other, mask, base[k] + atomicAdd(&cnt[k], 1u), p);
         } else {
             // a record of a job no longer running: only a broken bookkeeping
             // leaves one; it is dropped (the count pass skipped it) and counted
@@ -1959,9 +2010,16 @@ __global__ void __launch_bounds__(256) k_count_records(const Ctl* ctl, RunDev R,
     }
 }
 
-__global__ void k_bin_swap(Ctl* ctl, int ri) {
+// after the re-binning: by job alone the pass reads the queue in place through
+// the permutation; with energy bins the records were copied, and the other
+// buffer becomes the queue
+__global__ void k_bin_swap(Ctl* ctl, int ri, int nb) {
     if (ctl->overflow) return;
     RingCtl& r = ctl->ring[ri];
+    if (nb == 1) {
+        r.permuted = 1u;
+        return;
+    }
     r.cur ^= 1u;
     r.head = 0u;
     r.tail = ctl->n_valid;
@@ -2197,8 +2255,10 @@ size_t transport_lds_bytes(int ri, const Tables& T, int waves) {
 
 // allow the staged kernels to use `bytes` of dynamic LDS
 hipError_t transport_lds_optin(size_t bytes) {
-    const void* kernels[] = {(const void*)k_photon<true, false>, (const void*)k_electron<true, false>,
-                             (const void*)k_photon<true, true>, (const void*)k_electron<true, true>};
+    const void* kernels[] = {(const void*)k_photon<true, false, false>, (const void*)k_electron<true, false, false>,
+                             (const void*)k_photon<true, false, true>,  (const void*)k_electron<true, false, true>,
+                             (const void*)k_photon<true, true, false>,  (const void*)k_electron<true, true, false>,
+                             (const void*)k_photon<true, true, true>,   (const void*)k_electron<true, true, true>};
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -2206,26 +2266,39 @@ hipError_t transport_lds_optin(size_t bytes) {
     return hipSuccess;
 }
 
-// `solo`: the one-particle-per-wavefront measurement form (staged tables only)
-hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, bool solo,
+namespace {
+template <bool kPerm>
+void launch_transport_form(hipStream_t st, int ri, int blocks, int threads, bool lds, bool solo, size_t bytes,
+                           Ctl* ctl, const Tables& T, const RunDev& R) {
+    if (ri == 0) {
+        if (solo)
+            hipLaunchKernelGGL((k_photon<true, true, kPerm>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
+        else if (lds)
+            hipLaunchKernelGGL((k_photon<true, false, kPerm>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
+        else
+            hipLaunchKernelGGL((k_photon<false, false, kPerm>), dim3(blocks), dim3(threads), 0, st, ctl, T, R);
+    } else {
+        if (solo)
+            hipLaunchKernelGGL((k_electron<true, true, kPerm>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
+        else if (lds)
+            hipLaunchKernelGGL((k_electron<true, false, kPerm>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
+        else
+            hipLaunchKernelGGL((k_electron<false, false, kPerm>), dim3(blocks), dim3(threads), 0, st, ctl, T, R);
+    }
+}
+}  // namespace
+
+// `solo`: the one-particle-per-wavefront measurement form (staged tables only);
+// `permuted`: the pass follows a re-binning by job alone (its input is read
+// through the permutation)
+hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, bool solo, bool permuted,
                             Ctl* ctl, const Tables& T, const RunDev& R) {
     const size_t bytes = lds ? transport_lds_bytes(ri, T, threads / 64) : 0;
     if (solo && !lds) return hipErrorInvalidValue;
-    if (ri == 0) {
-        if (solo)
-            hipLaunchKernelGGL((k_photon<true, true>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
-        else if (lds)
-            hipLaunchKernelGGL((k_photon<true, false>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
-        else
-            hipLaunchKernelGGL((k_photon<false, false>), dim3(blocks), dim3(threads), 0, st, ctl, T, R);
-    } else {
-        if (solo)
-            hipLaunchKernelGGL((k_electron<true, true>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
-        else if (lds)
-            hipLaunchKernelGGL((k_electron<true, false>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R);
-        else
-            hipLaunchKernelGGL((k_electron<false, false>), dim3(blocks), dim3(threads), 0, st, ctl, T, R);
-    }
+    if (permuted)
+        launch_transport_form<true>(st, ri, blocks, threads, lds, solo, bytes, ctl, T, R);
+    else
+        launch_transport_form<false>(st, ri, blocks, threads, lds, solo, bytes, ctl, T, R);
     return hipGetLastError();
 }
 // nb energy bins per job; R.n_jobs * nb <= kMaxKeys
@@ -2237,7 +2310,7 @@ hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, i
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, ctl, R, nb);
     hipLaunchKernelGGL(k_bin_scatter, dim3(blocks), dim3(256), 2 * nk * sizeof(uint32_t), st, ctl, R,
                        ri, nb, lo, inv);
-    hipLaunchKernelGGL(k_bin_swap, dim3(1), dim3(1), 0, st, ctl, ri);
+    hipLaunchKernelGGL(k_bin_swap, dim3(1), dim3(1), 0, st, ctl, ri, nb);
     return hipGetLastError();
 }
 hipError_t launch_count_records(hipStream_t st, int blocks, const Ctl* ctl, const RunDev& R,

@@ -79,7 +79,7 @@ class RunStats(C.Structure):
                 ("accounting_gap", C.c_int64), ("transport_anomalies", C.c_uint64),
                 ("graph_launches", C.c_uint32), ("graphs_recorded", C.c_uint32),
                 ("accounting_mismatches", C.c_uint32), ("interactions", C.c_uint64 * 5),
-                ("records_requeued", C.c_uint64 * 2)]
+                ("records_requeued", C.c_uint64 * 2), ("passes_rebinned", C.c_uint32)]
 
 
 class JobDesc(C.Structure):
@@ -255,7 +255,8 @@ def _stats_dict(st):
             "graph_launches": int(st.graph_launches), "graphs_recorded": int(st.graphs_recorded),
             "accounting_mismatches": int(st.accounting_mismatches),
             "interactions": {k: int(st.interactions[i]) for i, k in enumerate(INTERACTION_NAMES)},
-            "records_requeued": [int(v) for v in st.records_requeued]}
+            "records_requeued": [int(v) for v in st.records_requeued],
+            "passes_rebinned": int(st.passes_rebinned)}
 
 
 class Context:

@@ -459,6 +459,10 @@ def test_determinism_and_launch_independence(gctx):
             c2.close()
         assert physics_events(c) == physics_events(a), opts
         np.testing.assert_allclose(c["dose"], a["dose"], rtol=1e-12, atol=1e-300)
+        # the forced re-binning did run (by job alone: the permuted form of the
+        # transport kernels; with energy bins: the copying form)
+        assert (c["passes_rebinned"] > 0) == ('"rebin_photons": 1' in opts), opts
+    assert a["passes_rebinned"] == 0
 
 
 def test_atomic_rate_probe(gctx):
