@@ -232,9 +232,11 @@ typedef struct {
 /* Create a context on HIP device `hip_device`.  opts_json may be NULL or a
  * flat JSON object with any of: "ring_capacity_log2" (queue records per type,
  * 2^k, default 25), "waves_per_cu" (wavefronts of the persistent workgroup
- * each CU runs, 1..12, default 12), "rebin_bins" (energy bins per job of the
- * queue re-binning, default 1: records are grouped by job only, which measured
- * faster than energy order), "rebin_photons", "rebin_electrons" (1: re-bin
+ * each CU runs, 1..12, default 12), "rebin_bins" (bins per job of the queue
+ * re-binning, 0..64, default 1: records are grouped by job only, which measured
+ * faster than energy order), "rebin_space" (0, default: the bins are intervals
+ * of log2 E; 1: they are boxes of the phantom, space^3 with space^3 the largest
+ * cube within the bins), "rebin_photons", "rebin_electrons" (1: re-bin
  * the queue of that particle type also when a single job holds all the
  * particles; default 0: then the queues are read unsorted, which measured
  * faster), "lds_tables" (1: stage interpolation tables in LDS when they fit,

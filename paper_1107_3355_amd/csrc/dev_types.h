@@ -59,7 +59,6 @@ struct RingCtl {
     uint32_t head, tail;     // records in [head, tail)
     uint32_t begin, count;   // input of the running pass: [begin, begin + count)
     uint32_t claim;          // claim counter of the running pass
-    uint32_t cur;            // which of the two buffers holds the ring
     uint32_t permuted;       // 1: the pass reads its input through the permutation
     uint32_t next_head;      // head after a permuted pass (the tail before it)
 };
@@ -218,22 +217,15 @@ struct SrcHdr {
     uint32_t pad0, pad1;
 };
 
-// Re-binning by job alone leaves the records where they are.  It uses the
-// queue's other buffer (idle: only the re-binning by job and energy copies
-// records into it) for two arrays of C 32-bit words, C the queue capacity:
-// each input position's job (kEmptyJob for an empty position, kOrphanJob for a
-// record of a job no longer running), then the permutation, the queue
-// positions of the pass's input in job order, which the pass reads its input
-// through.
-constexpr uint32_t kEmptyJob = 0xFFFFFFFFu, kOrphanJob = 0xFFFFFFFEu;
-__host__ __device__ inline uint32_t* bin_jobs(Particle* other) { return reinterpret_cast<uint32_t*>(other); }
-__host__ __device__ inline const uint32_t* bin_jobs(const Particle* other) {
-    return reinterpret_cast<const uint32_t*>(other);
-}
-__host__ __device__ inline uint32_t* bin_perm(Particle* other, uint32_t mask) {
-    return reinterpret_cast<uint32_t*>(other) + ((size_t)mask + 1u);
-}
-static_assert(2 * sizeof(uint32_t) <= sizeof(Particle), "job words and permutation fit in a buffer");
+// The re-binning leaves the records where they are.  Each queue has a
+// re-binning buffer of 2C 32-bit words, C the queue capacity: each input
+// position's key (kEmptyKey for an empty position, kOrphanKey for a record of a
+// job no longer running), then the permutation, the queue positions of the
+// pass's input in key order, which the pass reads its input through.
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu, kOrphanKey = 0xFFFFFFFEu;
+constexpr size_t kBinWordsPerSlot = 2;
+__host__ __device__ inline uint32_t* bin_keys(uint32_t* bin) { return bin; }
+__host__ __device__ inline uint32_t* bin_perm(uint32_t* bin, uint32_t mask) { return bin + ((size_t)mask + 1u); }
 
 struct RunDev {
     float ecut_g, ecut_e;      // shared by every job (the tables depend on them)
@@ -241,7 +233,8 @@ struct RunDev {
     JobCtl* jc;
     int n_jobs;                // job slots in use
     int nb;                    // energy bins per job of the re-binning
-    Particle* buf[2][2];       // [ring][buffer]
+    Particle* buf[2];          // the queues' records [ring]
+    uint32_t* bin[2];          // their re-binning buffers (2 words per queue slot), or null
     uint32_t mask[2];          // capacity - 1
     uint32_t hard[2];          // fill above which a reservation fails
 };

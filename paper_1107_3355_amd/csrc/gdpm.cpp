@@ -41,7 +41,7 @@ hipError_t transport_lds_optin(size_t bytes);
 hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, bool lds, bool solo, bool permuted,
                             Ctl* ctl, const Tables& T, const RunDev& R);
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
-                        float lo, float inv);
+                        float lo, float inv, int space);
 hipError_t launch_count_records(hipStream_t st, int blocks, const Ctl* ctl, const RunDev& R,
                                 unsigned long long* counts);
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
@@ -235,7 +235,7 @@ struct StepGraphKey {
     int src_blocks[2];
     int rebin[2], lds[2];
     int lone;            // the one job holding particles (queues not re-binned), or -1
-    int blocks, threads, nb;
+    int blocks, threads, nb, space;
     float blo, binv;
     RunDev R;
     Tables T;
@@ -252,7 +252,8 @@ struct gdpm_context_s {
     int cu_count = 0;
     int ring_log2 = 25;
     int waves_per_cu = 12;
-    int rebin_bins = 1;          // energy bins per job of the re-binning (1: by job only)
+    int rebin_bins = 1;          // bins per job of the re-binning (1: by job only)
+    int rebin_space = 0;         // 1: the bins are boxes of the phantom, not energy intervals
     int lds_tables = 1;          // stage interpolation tables in LDS when they fit
     int pass_histories = 0;      // new histories per iteration (0: half a queue less its fill)
     int autotune = 0;            // tune block size and re-binning online, queues from the work
@@ -272,7 +273,8 @@ struct gdpm_context_s {
     std::vector<MaterialParams> mats;
     int n_grid = 1024;
     std::map<TableKey, std::unique_ptr<DevTables>> tables;
-    DevBuf rings[2][2];
+    DevBuf rings[2];   // the queues' records
+    DevBuf bins[2];    // their re-binning buffers
     DevBuf ctl;
     Ctl* host_ctl = nullptr;   // pinned mirror
     DevBuf jobs_dev, jc, segs, inv_n, counts;
@@ -410,17 +412,20 @@ gdpm_status get_tables(gdpm_context ctx, double ecut_g, double ecut_e, uint32_t 
 
 gdpm_status ensure_rings(gdpm_context ctx) {
     const size_t cap = (size_t)1 << ctx->ring_log2;
-    for (int r = 0; r < 2; ++r)
-        for (int b = 0; b < 2; ++b) HIP_TRY(ctx->rings[r][b].ensure(cap * sizeof(Particle)));
+    for (int r = 0; r < 2; ++r) {
+        HIP_TRY(ctx->rings[r].ensure(cap * sizeof(Particle)));
+        HIP_TRY(ctx->bins[r].ensure(cap * kBinWordsPerSlot * sizeof(uint32_t)));
+    }
     return GDPM_OK;
 }
 
 // The device memory an engine runs in: the context's own buffers (queues
-// sized by ring_capacity_log2, two buffers per queue for the re-binning), or
-// fixed memory given to the engine (one buffer per queue: such an engine never
+// sized by ring_capacity_log2, each with its re-binning buffer), or fixed
+// memory given to the engine (no re-binning buffer: such an engine never
 // re-bins, records no graph and allocates nothing).
 struct EngineMem {
-    Particle* ring[2][2];
+    Particle* ring[2];
+    uint32_t* bin[2];
     int ring_log2;
     Ctl* ctl;
     JobDev* jobs;
@@ -436,8 +441,10 @@ gdpm_status context_mem(gdpm_context ctx, EngineMem* m) {
     gdpm_status e = ensure_rings(ctx);
     if (e) return e;
     memset(m, 0, sizeof *m);
-    for (int r = 0; r < 2; ++r)
-        for (int b = 0; b < 2; ++b) m->ring[r][b] = ctx->rings[r][b].as<Particle>();
+    for (int r = 0; r < 2; ++r) {
+        m->ring[r] = ctx->rings[r].as<Particle>();
+        m->bin[r] = ctx->bins[r].as<uint32_t>();
+    }
     m->ring_log2 = ctx->ring_log2;
     m->ctl = ctx->ctl.as<Ctl>();
     m->jobs = ctx->jobs_dev.as<JobDev>();
@@ -694,8 +701,8 @@ gdpm_status Engine::init(gdpm_context c, hipStream_t s, const RunPlan& plan, con
     R.n_jobs = 0;
     const uint32_t cap = 1u << M.ring_log2;
     for (int r = 0; r < 2; ++r) {
-        R.buf[r][0] = M.ring[r][0];
-        R.buf[r][1] = M.ring[r][1];
+        R.buf[r] = M.ring[r];
+        R.bin[r] = M.bin[r];
         R.mask[r] = cap - 1u;
         R.hard[r] = cap;
     }
@@ -881,8 +888,15 @@ gdpm_status Engine::step() {
     }
     R.n_jobs = std::max(n_slots, 1);
     for (int ri = 0; ri < 2; ++ri) ctx->h_hdr[ri] = SrcHdr{(uint32_t)nseg[ri], total[ri], 0u, 0u};
-    // energy bins per job so that jobs x bins fits the re-binning keys
-    const int nb = std::max(1, std::min(std::min(ctx->rebin_bins, kMaxBins), kMaxKeys / R.n_jobs));
+    // bins per job so that jobs x bins fits the re-binning keys; boxes of the
+    // phantom come as space^3 (the largest cube within the bins)
+    int nb = std::max(1, std::min(std::min(ctx->rebin_bins, kMaxBins), kMaxKeys / R.n_jobs));
+    int space = 0;
+    if (ctx->rebin_space) {
+        space = 1;
+        while ((space + 1) * (space + 1) * (space + 1) <= nb) ++space;
+        nb = space * space * space;
+    }
     const float blo = -5.0f, bhi = 5.0f;  // log2 E range of the bins (0.03 .. 32 MeV)
     // The jobs that hold particles in this iteration: live records after the
     // last one (births less deaths) or new histories now.  With one such job
@@ -923,11 +937,13 @@ gdpm_status Engine::step() {
     k.blocks = blocks;
     k.threads = block_threads(ctx);
     k.nb = nb;
+    k.space = space;
     k.blo = blo;
     k.binv = nb / (bhi - blo);
     for (int ri = 0; ri < 2; ++ri) {
-        // compact the queue and sort it by job (and energy, rebin_bins > 1) so
-        // that each job's records form a segment; skipped when one job holds
+        // sort the queue's positions by job (and bin, rebin_bins > 1), dropping
+        // empty ones, so that each job's records form a segment of the pass's
+        // input (read through the permutation); skipped when one job holds
         // all particles (measured faster: with lanes refilled every iteration
         // energy order gains nothing, and push order keeps some spatial
         // locality), the pass then reads the queue as it is, empty slots included
@@ -985,11 +1001,11 @@ gdpm_status Engine::check_accounting() {
         fprintf(stderr,
                 "[gdpm] accounting check: iteration %u, slot %d (job %u): births %llu deaths %llu "
                 "(offset %lld) but %llu live records; slots %d, source segments %d/%d, re-binned %d/%d, "
-                "queues [%u, %u) [%u, %u) cur %u/%u, graph %d\n",
+                "queues [%u, %u) [%u, %u), graph %d\n",
                 iter, i, j->prm.job_id, (unsigned long long)m->births[i], (unsigned long long)m->deaths[i],
                 (long long)j->death_offset, live[i], n_slots, last.seg_copy[0], last.seg_copy[1],
                 last.rebin[0], last.rebin[1], hc->ring[0].head, hc->ring[0].tail, hc->ring[1].head,
-                hc->ring[1].tail, hc->ring[0].cur, hc->ring[1].cur, ctx->graphs);
+                hc->ring[1].tail, ctx->graphs);
     }
     return GDPM_OK;
 }
@@ -1010,13 +1026,13 @@ gdpm_status Engine::issue(const StepGraphKey& k, bool recording) {
         HIP_TRY(launch_source(st, k.src_blocks[ri], dc, k.R, dseg, dh + ri, ri));
     }
     for (int ri = 0; ri < 2; ++ri) {
-        if (k.rebin[ri]) HIP_TRY(launch_rebin(st, 4 * k.blocks, dc, k.R, ri, k.nb, k.blo, k.binv));
+        if (k.rebin[ri]) HIP_TRY(launch_rebin(st, 4 * k.blocks, dc, k.R, ri, k.nb, k.blo, k.binv, k.space));
         HIP_TRY(launch_setup(st, dc, k.R, ri, k.rebin[ri], k.lone));
         // a recorded event becomes a node of the graph that records it at replay
         HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri], st, hipEventRecordExternal)
                           : hipEventRecord(ctx->events[2 * ri], st));
         HIP_TRY(launch_transport(st, ri, k.blocks, k.threads, k.lds[ri] != 0, ctx->solo_lanes != 0,
-                                 k.rebin[ri] && k.nb == 1, dc, k.T, k.R));
+                                 k.rebin[ri] != 0, dc, k.T, k.R));
         HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri + 1], st, hipEventRecordExternal)
                           : hipEventRecord(ctx->events[2 * ri + 1], st));
         HIP_TRY(launch_finish(st, dc, ri));
@@ -1248,9 +1264,10 @@ bool scratch_layout(unsigned char* base, EJob* j, EngineMem* M) {
     j->mumax_p = reinterpret_cast<float*>(take(kMaxGrid * sizeof(float)));
     j->chains_p = reinterpret_cast<uint32_t*>(take(kMetroChains * sizeof(uint32_t)));
     if (off > kScratchCtlBytes) return false;   // (a layout error; see the static sizes)
-    for (int r = 0; r < 2; ++r)
-        M->ring[r][0] = M->ring[r][1] =
-            reinterpret_cast<Particle*>(base + kScratchCtlBytes + r * kScratchRingBytes);
+    for (int r = 0; r < 2; ++r) {
+        M->ring[r] = reinterpret_cast<Particle*>(base + kScratchCtlBytes + r * kScratchRingBytes);
+        M->bin[r] = nullptr;
+    }
     M->ring_log2 = kScratchRingLog2;
     j->tally_p = reinterpret_cast<double*>(base + kScratchCtlBytes + 2 * kScratchRingBytes);
     M->fixed = true;
@@ -1474,6 +1491,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->ring_log2 = json_int(opts_json, "ring_capacity_log2", 25);
     ctx->waves_per_cu = json_int(opts_json, "waves_per_cu", 12);
     ctx->rebin_bins = json_int(opts_json, "rebin_bins", 1);
+    ctx->rebin_space = json_int(opts_json, "rebin_space", 0);
     ctx->lds_tables = json_int(opts_json, "lds_tables", 1);
     ctx->pass_histories = json_int(opts_json, "pass_histories", 0);
     ctx->autotune = json_int(opts_json, "autotune", 0);
@@ -1493,6 +1511,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     if (ctx->waves_per_cu < 1 || ctx->waves_per_cu > kMaxBlockThreads / 64)
         return fail(GDPM_E_INVALID, "waves_per_cu in [1, %d]", kMaxBlockThreads / 64);
     if (ctx->rebin_bins < 0 || ctx->rebin_bins > kMaxBins) return fail(GDPM_E_INVALID, "rebin_bins in [0, 64]");
+    if (ctx->rebin_space != 0 && ctx->rebin_space != 1) return fail(GDPM_E_INVALID, "rebin_space must be 0 or 1");
     if (ctx->pass_histories < 0) return fail(GDPM_E_INVALID, "pass_histories must be >= 0");
     if (ctx->autotune_min_events < 1) return fail(GDPM_E_INVALID, "autotune_min_events must be >= 1");
     if (ctx->issue_order < 0 || ctx->issue_order > 2)
@@ -2078,8 +2097,7 @@ gdpm_status gdpm_server_info_get(gdpm_server srv, gdpm_server_info* info) {
     info->high_water_bytes = (double)srv->high_water;
     gdpm_context ctx = srv->ctx;
     double res = (double)(ctx->ctl.bytes + ctx->jobs_dev.bytes + ctx->jc.bytes + ctx->segs.bytes);
-    for (int r = 0; r < 2; ++r)
-        for (int b = 0; b < 2; ++b) res += (double)ctx->rings[r][b].bytes;
+    for (int r = 0; r < 2; ++r) res += (double)(ctx->rings[r].bytes + ctx->bins[r].bytes);
     for (auto& t : ctx->tables)
         res += (double)(t.second->phot.bytes + t.second->elec.bytes + t.second->rinv.bytes +
                         t.second->rinv_scale.bytes + t.second->aw.bytes + t.second->kn.bytes);

@@ -1175,7 +1175,7 @@ __global__ void __launch_bounds__(256) k_source(Ctl* ctl, RunDev R, const SrcSeg
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->overflow, 1u);
         return;
     }
-    Particle* buf = R.buf[ri][r.cur];
+    Particle* buf = R.buf[ri];
     const uint32_t nthreads = gridDim.x * blockDim.x;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     for (int s = 0; s < nseg; ++s) {
@@ -1296,10 +1296,10 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     // a pass re-binned by job reads its input through the permutation (only the
     // kPerm form has that code: single-job passes keep the plain reads)
     const uint32_t* perm_in =
-        kPerm && __builtin_amdgcn_readfirstlane(rc->permuted) ? bin_perm(R.buf[0][rc->cur ^ 1u], R.mask[0]) : nullptr;
+        kPerm && __builtin_amdgcn_readfirstlane(rc->permuted) ? bin_perm(R.bin[0], R.mask[0]) : nullptr;
     const bool big = !kSolo && count >= kTailMinPerLane * gridDim.x * blockDim.x;
-    Particle* bufg = R.buf[0][ctl->ring[0].cur];
-    Particle* bufe = R.buf[1][ctl->ring[1].cur];
+    Particle* bufg = R.buf[0];
+    Particle* bufe = R.buf[1];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
     JobCtl* jc = R.jc;
     const float ecut_e = R.ecut_e, ecut_g = R.ecut_g;
@@ -1554,10 +1554,10 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     RingCtl* rc = &ctl->ring[1];
     const uint32_t begin = rc->begin, count = rc->count;
     const uint32_t* perm_in =
-        kPerm && __builtin_amdgcn_readfirstlane(rc->permuted) ? bin_perm(R.buf[1][rc->cur ^ 1u], R.mask[1]) : nullptr;
+        kPerm && __builtin_amdgcn_readfirstlane(rc->permuted) ? bin_perm(R.bin[1], R.mask[1]) : nullptr;
     const bool big = !kSolo && count >= kTailMinPerLane * gridDim.x * blockDim.x;
-    Particle* bufg = R.buf[0][ctl->ring[0].cur];
-    Particle* bufe = R.buf[1][ctl->ring[1].cur];
+    Particle* bufg = R.buf[0];
+    Particle* bufe = R.buf[1];
     const uint32_t head_g = ctl->ring[0].head, head_e = ctl->ring[1].head;
     JobCtl* jc = R.jc;
     const float ecut = R.ecut_e;
@@ -1836,13 +1836,26 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
 }
 
 // ---------------------------------------------------------------------------
-// queue compaction and re-binning: counting sort of [head, tail) by the key
-// job x log2-energy bin into the other buffer; empty slots are dropped.  The
-// jobs' records end up in contiguous segments, each ordered by energy.
+// queue re-binning: counting sort of the positions [head, tail) by the key job x
+// bin (bins: log2-energy intervals, or boxes of the phantom with `space` > 0).
+// The records stay where they are: the count pass keeps each position's key,
+// the scatter writes the permutation, in key order, of the positions that hold
+// a running job's record (empty ones are dropped), and the pass reads its input
+// through it.  Each job's records form one segment of the permutation.
 // ---------------------------------------------------------------------------
 GDPM_DEV int energy_bin(float e, float lo, float inv, int nb) {
     const int b = (int)((hlog2(e) - lo) * inv);
     return min(max(b, 0), nb - 1);
+}
+
+// the box of a position when the phantom is cut into space^3 equal boxes
+// (x fastest); positions on or past the far faces fall in the last box
+GDPM_DEV int space_bin(const Geom& G, float x, float y, float z, int space) {
+    const float sc = (float)space;
+    const int bx = min(max((int)(x * G.idx * sc / (float)G.nx), 0), space - 1);
+    const int by = min(max((int)(y * G.idy * sc / (float)G.ny), 0), space - 1);
+    const int bz = min(max((int)(z * G.idz * sc / (float)G.nz), 0), space - 1);
+    return bx + space * (by + space * bz);
 }
 
 // the slot of a record's job if that job is running in it (slot below n_jobs,
@@ -1854,18 +1867,21 @@ GDPM_DEV int record_job(const RunDev& R, uint32_t job_word) {
     return ((job_word >> 8) & 0xFFu) == gen ? slot : -1;
 }
 
-// re-binning key of the record in `slot` (-1: empty, or no running job's)
-GDPM_DEV int record_key(const RunDev& R, const Particle* buf, uint32_t mask, uint32_t slot, int nb,
-                        float lo, float inv, bool& live) {
+// re-binning key word of the record in `slot`: job x nb + bin, kEmptyKey for an
+// empty position, kOrphanKey for a record of no running job
+GDPM_DEV uint32_t record_key(const RunDev& R, const Particle* buf, uint32_t mask, uint32_t slot, int nb,
+                             float lo, float inv, int space) {
     const float4 w0 = reinterpret_cast<const float4*>(buf + (slot & mask))[0];
     const float4 w3 = reinterpret_cast<const float4*>(buf + (slot & mask))[3];
-    live = !record_empty(w0.w);
-    const int j = live ? record_job(R, __float_as_uint(w3.w)) : -1;
-    return j < 0 ? -1 : j * nb + energy_bin(w0.w, lo, inv, nb);
+    if (record_empty(w0.w)) return kEmptyKey;
+    const int j = record_job(R, __float_as_uint(w3.w));
+    if (j < 0) return kOrphanKey;
+    const int b = space > 0 ? space_bin(R.jobs[j].G, w0.x, w0.y, w0.z, space) : energy_bin(w0.w, lo, inv, nb);
+    return (uint32_t)(j * nb + b);
 }
 
 __global__ void __launch_bounds__(256) k_bin_count(Ctl* ctl, RunDev R, int ri, int nb, float lo,
-                                                   float inv) {
+                                                   float inv, int space) {
     if (ctl->overflow) return;
     extern __shared__ uint32_t hist[];
     const int nk = R.n_jobs * nb;
@@ -1873,15 +1889,14 @@ __global__ void __launch_bounds__(256) k_bin_count(Ctl* ctl, RunDev R, int ri, i
     __syncthreads();
     const RingCtl& r = ctl->ring[ri];
     const uint32_t n = r.tail - r.head;
-    const Particle* buf = R.buf[ri][r.cur];
-    // by job alone, each position's job is also kept (4 B in the idle buffer),
-    // so that the scatter does not read the records again
-    uint32_t* jw = nb == 1 ? bin_jobs(R.buf[ri][r.cur ^ 1u]) : nullptr;
+    const Particle* buf = R.buf[ri];
+    // each position's key is kept (4 B), so that the scatter does not read
+    // the records again
+    uint32_t* kw = bin_keys(R.bin[ri]);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        bool live;
-        const int k = record_key(R, buf, R.mask[ri], r.head + i, nb, lo, inv, live);
-        if (k >= 0) atomicAdd(&hist[k], 1u);
-        if (jw != nullptr) jw[i] = !live ? kEmptyJob : (k < 0 ? kOrphanJob : (uint32_t)k);
+        const uint32_t k = record_key(R, buf, R.mask[ri], r.head + i, nb, lo, inv, space);
+        if (k < kOrphanKey) atomicAdd(&hist[k], 1u);
+        kw[i] = k;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nk; i += blockDim.x)
@@ -1924,8 +1939,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan(Ctl* ctl, RunDev R, int nb) {
     if (threadIdx.x == 0) ctl->n_valid = total;
 }
 
-__global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri, int nb, float lo,
-                                                     float inv) {
+__global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri, int nb) {
     if (ctl->overflow) return;
     extern __shared__ uint32_t cnt[];   // [nk] this block's counts, then ranks; [nk] its bases
     const int nk = R.n_jobs * nb;
@@ -1933,30 +1947,18 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri,
     const RingCtl& r = ctl->ring[ri];
     const uint32_t n = r.tail - r.head;
     const uint32_t mask = R.mask[ri];
-    const Particle* src = R.buf[ri][r.cur];
-    // each block takes one contiguous share of the queue: it counts its keys,
-    // takes its place in every key's run with one atomic per key, then places
-    // its records (one global atomic per key and block, not per tile).  By job
-    // alone (nb = 1) the records stay where they are: the keys come from the
-    // job words the count pass kept, and the pass reads the records in job
-    // order through the permutation written here.  With energy bins the records
-    // are copied into the other buffer in key order.
-    Particle* other = R.buf[ri][r.cur ^ 1u];
-    const uint32_t* jw = bin_jobs(other);
+    const uint32_t* kw = bin_keys(R.bin[ri]);
+    uint32_t* perm = bin_perm(R.bin[ri], mask);
+    // each block takes one contiguous share of the positions: it counts its
+    // keys, takes its place in every key's run with one atomic per key, then
+    // writes its positions (one global atomic per key and block, not per tile)
     const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
     const uint32_t i0 = min(n, blockIdx.x * per), i1 = min(n, i0 + per);
     for (int q = threadIdx.x; q < nk; q += blockDim.x) cnt[q] = 0u;
     __syncthreads();
     for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        int k;
-        if (nb == 1) {
-            const uint32_t w = jw[i];
-            k = w >= kOrphanJob ? -1 : (int)w;
-        } else {
-            bool live;
-            k = record_key(R, src, mask, r.head + i, nb, lo, inv, live);
-        }
-        if (k >= 0) atomicAdd(&cnt[k], 1u);
+        const uint32_t k = kw[i];
+        if (k < kOrphanKey) atomicAdd(&cnt[k], 1u);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < nk; q += blockDim.x) {
@@ -1964,29 +1966,11 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Ctl* ctl, RunDev R, int ri,
         cnt[q] = 0u;
     }
     __syncthreads();
-    if (nb == 1) {
-        uint32_t* perm = bin_perm(other, mask);
-        for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-            const uint32_t w = jw[i];
-            if (w == kEmptyJob) continue;
-            if (w != kOrphanJob) {
-                perm[(base[w] + atomicAdd(&cnt[w], 1u)) & mask] = r.head + i;
-            } else {
-                // a record of a job no longer running: only a broken bookkeeping
-                // leaves one; it is dropped (the count pass skipped it) and counted
-                atomicAdd(&ctl->anomalies, 1ull);
-            }
-        }
-        return;
-    }
     for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        const Particle p = load(src, mask, r.head + i);
-        if (record_empty(p.e)) continue;
-        const int job = record_job(R, p.job);
-        if (job >= 0) {
-            const int k = job * nb + energy_bin(p.e, lo, inv, nb);
-            store(other, mask, base[k] + atomicAdd(&cnt[k], 1u), p);
-        } else {
+        const uint32_t k = kw[i];
+        if (k < kOrphanKey) {
+            perm[(base[k] + atomicAdd(&cnt[k], 1u)) & mask] = r.head + i;
+        } else if (k == kOrphanKey) {
             // a record of a job no longer running: only a broken bookkeeping
             // leaves one; it is dropped (the count pass skipped it) and counted
             atomicAdd(&ctl->anomalies, 1ull);
@@ -2001,7 +1985,7 @@ __global__ void __launch_bounds__(256) k_count_records(const Ctl* ctl, RunDev R,
     for (int ri = 0; ri < 2; ++ri) {
         const RingCtl& r = ctl->ring[ri];
         const uint32_t n = r.tail - r.head;
-        const Particle* buf = R.buf[ri][r.cur];
+        const Particle* buf = R.buf[ri];
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
             const float4* q = reinterpret_cast<const float4*>(buf + ((r.head + i) & R.mask[ri]));
             const int j = !record_empty(q[0].w) ? record_job(R, __float_as_uint(q[3].w)) : -1;
@@ -2010,19 +1994,10 @@ __global__ void __launch_bounds__(256) k_count_records(const Ctl* ctl, RunDev R,
     }
 }
 
-// after the re-binning: by job alone the pass reads the queue in place through
-// the permutation; with energy bins the records were copied, and the other
-// buffer becomes the queue
-__global__ void k_bin_swap(Ctl* ctl, int ri, int nb) {
+// after the re-binning the pass reads the queue through the permutation
+__global__ void k_bin_swap(Ctl* ctl, int ri) {
     if (ctl->overflow) return;
-    RingCtl& r = ctl->ring[ri];
-    if (nb == 1) {
-        r.permuted = 1u;
-        return;
-    }
-    r.cur ^= 1u;
-    r.head = 0u;
-    r.tail = ctl->n_valid;
+    ctl->ring[ri].permuted = 1u;
 }
 
 
@@ -2301,16 +2276,17 @@ hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, boo
         launch_transport_form<false>(st, ri, blocks, threads, lds, solo, bytes, ctl, T, R);
     return hipGetLastError();
 }
-// nb energy bins per job; R.n_jobs * nb <= kMaxKeys
+// nb bins per job (energy intervals, or space^3 boxes with space > 0);
+// R.n_jobs * nb <= kMaxKeys
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
-                        float lo, float inv) {
+                        float lo, float inv, int space) {
     const size_t nk = (size_t)R.n_jobs * nb;
     hipLaunchKernelGGL(k_bin_count, dim3(blocks), dim3(256), nk * sizeof(uint32_t), st, ctl, R, ri,
-                       nb, lo, inv);
+                       nb, lo, inv, space);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, ctl, R, nb);
     hipLaunchKernelGGL(k_bin_scatter, dim3(blocks), dim3(256), 2 * nk * sizeof(uint32_t), st, ctl, R,
-                       ri, nb, lo, inv);
-    hipLaunchKernelGGL(k_bin_swap, dim3(1), dim3(1), 0, st, ctl, ri, nb);
+                       ri, nb);
+    hipLaunchKernelGGL(k_bin_swap, dim3(1), dim3(1), 0, st, ctl, ri);
     return hipGetLastError();
 }
 hipError_t launch_count_records(hipStream_t st, int blocks, const Ctl* ctl, const RunDev& R,

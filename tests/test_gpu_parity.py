@@ -448,6 +448,8 @@ def test_determinism_and_launch_independence(gctx):
     np.testing.assert_allclose(a["dose"], b["dose"], rtol=1e-12, atol=1e-300)
     for opts in ('{"waves_per_cu": 4, "rebin_bins": 1, "rebin_photons": 1, "rebin_electrons": 1}',
                  '{"waves_per_cu": 8, "rebin_bins": 32, "rebin_photons": 1, "rebin_electrons": 1}',
+                 # boxes of the phantom as bins (4^3 per job)
+                 '{"rebin_bins": 64, "rebin_space": 1, "rebin_photons": 1, "rebin_electrons": 1}',
                  '{"ring_capacity_log2": 21, "pass_histories": 700}',
                  '{"rebin_photons": 1, "rebin_electrons": 0}',
                  # tables read through L2 and records loaded directly, no LDS staging
@@ -459,10 +461,11 @@ def test_determinism_and_launch_independence(gctx):
             c2.close()
         assert physics_events(c) == physics_events(a), opts
         np.testing.assert_allclose(c["dose"], a["dose"], rtol=1e-12, atol=1e-300)
-        # the forced re-binning did run (by job alone: the permuted form of the
-        # transport kernels; with energy bins: the copying form)
+        # the forced re-binning did run (the permuted form of the transport kernels)
         assert (c["passes_rebinned"] > 0) == ('"rebin_photons": 1' in opts), opts
     assert a["passes_rebinned"] == 0
+    with pytest.raises(G.GdpmError):
+        G.Context(0, opts='{"rebin_space": 2}', materials=MATS)
 
 
 def test_atomic_rate_probe(gctx):
