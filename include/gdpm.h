@@ -185,14 +185,16 @@ typedef struct {
     double dmax;                 /* MeV/g per history, same voxels */
     double t_total_s;            /* wall time of the call */
     double t_kernel_s;           /* device time of the transport kernels (HIP events) */
-    double t_photon_s, t_electron_s;  /* device time per pass type */
+    double t_photon_s, t_electron_s;  /* device time per pass type, when the passes are
+                                         launched apart (0 with fused_passes) */
     uint64_t events[8];          /* GDPM_EV_* counters of the run (for a job of a batch or a
                                     server: the engine's totals, all jobs, when it finished;
                                     events[GDPM_EV_HISTORIES] is the job's own) */
-    uint32_t passes;             /* transport kernel launches */
+    uint32_t passes;             /* transport passes, photon and electron (a fused launch
+                                    runs one of each) */
     uint32_t rounds;
-    uint32_t passes_photon;      /* photon kernel launches (t_photon_s covers them) */
-    uint32_t passes_electron;    /* electron kernel launches (t_electron_s covers them) */
+    uint32_t passes_photon;      /* photon passes (t_photon_s covers them when launched apart) */
+    uint32_t passes_electron;    /* electron passes (likewise t_electron_s) */
     /* per pass type (0 photon, 1 electron): 64-byte queue records the passes
      * loaded and stored (secondaries and particles handed to the next pass),
      * and FP64 tally deposits; the memory traffic the passes cannot avoid */
@@ -232,7 +234,9 @@ typedef struct {
 /* Create a context on HIP device `hip_device`.  opts_json may be NULL or a
  * flat JSON object with any of: "ring_capacity_log2" (queue records per type,
  * 2^k, default 25), "waves_per_cu" (wavefronts of the persistent workgroup
- * each CU runs, 1..12, default 12), "rebin_bins" (bins per job of the queue
+ * each CU runs, 1..12, default 12), "photon_waves_per_cu" (the same for the
+ * photon pass alone, at most waves_per_cu, 0..12, default 10; 0: waves_per_cu),
+ * "rebin_bins" (bins per job of the queue
  * re-binning, 0..64, default 1: records are grouped by job only, which measured
  * faster than energy order), "rebin_space" (0, default: the bins are intervals
  * of log2 E; 1: they are boxes of the phantom, space^3 with space^3 the largest
@@ -283,7 +287,13 @@ typedef struct {
  * alone; default 0: admission by slots and device footprint only), "solo_lanes" (1: a measurement form of
  * the transport kernels in which a wavefront carries one particle at a time,
  * so that it executes exactly the instructions of that particle's path; very
- * slow; needs "lds_tables" on and "autotune" off; default 0).
+ * slow; needs "lds_tables" on and "autotune" off; default 0), "fused_passes"
+ * (1: both transport passes of an iteration in one launch, the photon pass on
+ * "photon_waves" wavefronts of each workgroup at first (default -1: half) and
+ * the electron pass on the others, each wavefront turning to the other pass
+ * when its own has nothing left; each pass then transports what its queue held
+ * at the start of the iteration; needs the electron tables staged in LDS;
+ * 0: the photon pass, then the electron pass).
  * Results do not depend on any of these options (each particle draws from its
  * own random stream), only the speed does. */
 gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_context* out);

@@ -88,10 +88,11 @@ struct JobCtl {
     unsigned long long deaths[kMaxJobs];   // particles ended (absorbed, escaped)
     double e_in[kMaxJobs];                 // source kinetic energy (MeV)
     double e_esc[kMaxJobs];                // energy leaving the phantom (MeV)
-    uint32_t seg_begin[kMaxJobs];          // the job's records in the pass input:
-    uint32_t seg_count[kMaxJobs];          //   [seg_begin, seg_begin + seg_count)
-    uint32_t claim[kMaxJobs];              // claim counter of the job's segment
-    unsigned long long left[kMaxJobs / 64];  // jobs with unclaimed records
+    // per particle type [ri] (the two passes of an iteration may run at once):
+    uint32_t seg_begin[2][kMaxJobs];       // the job's records in the pass input:
+    uint32_t seg_count[2][kMaxJobs];       //   [seg_begin, seg_begin + seg_count)
+    uint32_t claim[2][kMaxJobs];           // claim counter of the job's segment
+    unsigned long long left[2][kMaxJobs / 64];  // jobs with unclaimed records
     uint32_t bin_count[kMaxKeys];
     uint32_t bin_cursor[kMaxKeys];
 };

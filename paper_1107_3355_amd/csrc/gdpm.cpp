@@ -42,6 +42,8 @@ hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, boo
                             Ctl* ctl, const Tables& T, const RunDev& R);
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
                         float lo, float inv, int space);
+hipError_t launch_fused(hipStream_t st, int blocks, int threads, int photon_waves, bool permuted, Ctl* ctl,
+                        const Tables& T, const RunDev& R);
 hipError_t launch_count_records(hipStream_t st, int blocks, const Ctl* ctl, const RunDev& R,
                                 unsigned long long* counts);
 hipError_t launch_stats(hipStream_t st, int blocks, Ctl* ctl, const double* slots, size_t nvox,
@@ -236,6 +238,8 @@ struct StepGraphKey {
     int rebin[2], lds[2];
     int lone;            // the one job holding particles (queues not re-binned), or -1
     int blocks, threads, nb, space;
+    int threads_photon;        // block size of the photon pass (separate launches)
+    int fused, photon_waves;   // both passes in one launch; its photon-first wavefronts
     float blo, binv;
     RunDev R;
     Tables T;
@@ -265,6 +269,10 @@ struct gdpm_context_s {
     int graphs = 1;              // replay each iteration's launches as a recorded HIP graph
     int check_accounting = 0;    // after every iteration, count each job's live records
     int solo_lanes = 0;          // measurement form: one particle per wavefront at a time
+    int fused_passes = 0;        // 1: both passes of an iteration in one launch (k_transport)
+    int photon_waves_per_cu = 10;  // wavefronts per CU of the photon pass (at most
+                                   // waves_per_cu; 0: waves_per_cu)
+    int photon_waves = -1;       // wavefronts per workgroup that start with photons (fused; -1: half)
     int admit_draining = 0;      // server: admit a job only while every running job drains (1: any
                                  // super-round, 2: its last one)
     uint32_t ring_start = 0;     // queue position a run starts at (positions run modulo 2^32)
@@ -501,6 +509,7 @@ gdpm_status validate_params(const gdpm_run_params* p, const gdpm_source_s* src, 
 
 struct Timers {
     double photon = 0, electron = 0;
+    double fused = 0;   // both passes in one launch
     uint32_t passes = 0, passes_photon = 0, passes_electron = 0;
     uint32_t graph_launches = 0, graphs_recorded = 0;
     uint32_t passes_rebinned = 0;
@@ -639,7 +648,7 @@ void Engine::tune_account() {
     if (!tune.on || tune.fixed) return;
     const Ctl* hc = ctx->host_ctl;
     const unsigned long long ev = hc->ev[GDPM_EV_FLIGHTS] + hc->ev[GDPM_EV_ESTEPS];
-    const double t = tm.photon + tm.electron;
+    const double t = tm.photon + tm.electron + tm.fused;
     const unsigned long long dev = ev - tune.last_events;
     const double dt = t - tune.last_time;
     tune.last_events = ev;
@@ -936,6 +945,9 @@ gdpm_status Engine::step() {
     }
     k.blocks = blocks;
     k.threads = block_threads(ctx);
+    // the photon pass gains nothing from more than about 10 wavefronts per CU
+    // (measured: its random voxel reads saturate the memory path first)
+    k.threads_photon = ctx->photon_waves_per_cu ? std::min(k.threads, 64 * ctx->photon_waves_per_cu) : k.threads;
     k.nb = nb;
     k.space = space;
     k.blo = blo;
@@ -949,11 +961,20 @@ gdpm_status Engine::step() {
         // locality), the pass then reads the queue as it is, empty slots included
         k.rebin[ri] = !M.fixed && ((ri == 0 ? ctx->rebin_photons : ctx->rebin_electrons) || holders > 1 || lone < 0);
         if (k.rebin[ri]) tm.passes_rebinned++;
-        k.lds[ri] = ctx->lds_tables && transport_lds_bytes(ri, T, k.threads / 64) <= (size_t)ctx->max_lds;
+        const int tpb = ri == 0 ? k.threads_photon : k.threads;
+        k.lds[ri] = ctx->lds_tables && transport_lds_bytes(ri, T, tpb / 64) <= (size_t)ctx->max_lds;
         tm.passes++;
         (ri == 0 ? tm.passes_photon : tm.passes_electron)++;
     }
     k.lone = (k.rebin[0] && k.rebin[1]) ? -1 : lone;
+    // both passes in one launch: needs the electron tables staged (the photon
+    // tables are read through the caches); not in the one-particle form
+    k.fused = ctx->fused_passes && !ctx->solo_lanes && k.lds[1];
+    if (k.fused) {
+        const int waves = k.threads / 64;
+        k.photon_waves = ctx->photon_waves < 0 ? waves / 2 : std::min(ctx->photon_waves, waves);
+        k.lds[0] = 0;
+    }
     k.R = R;
     k.T = T;
     {
@@ -961,10 +982,16 @@ gdpm_status Engine::step() {
         if (s != GDPM_OK) return s;
     }
     HIP_TRY(hipStreamSynchronize(st));
-    for (int ri = 0; ri < 2; ++ri) {
+    if (k.fused) {
         float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, ctx->events[2 * ri], ctx->events[2 * ri + 1]));
-        (ri == 0 ? tm.photon : tm.electron) += ms * 1e-3;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]));
+        tm.fused += ms * 1e-3;
+    } else {
+        for (int ri = 0; ri < 2; ++ri) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->events[2 * ri], ctx->events[2 * ri + 1]));
+            (ri == 0 ? tm.photon : tm.electron) += ms * 1e-3;
+        }
     }
     ++iter;
     last = k;
@@ -1025,14 +1052,30 @@ gdpm_status Engine::issue(const StepGraphKey& k, bool recording) {
                                hipMemcpyHostToDevice, st));
         HIP_TRY(launch_source(st, k.src_blocks[ri], dc, k.R, dseg, dh + ri, ri));
     }
+    if (k.fused) {
+        // both queues set up, then one launch runs both passes
+        for (int ri = 0; ri < 2; ++ri) {
+            if (k.rebin[ri]) HIP_TRY(launch_rebin(st, 4 * k.blocks, dc, k.R, ri, k.nb, k.blo, k.binv, k.space));
+            HIP_TRY(launch_setup(st, dc, k.R, ri, k.rebin[ri], k.lone));
+        }
+        HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[0], st, hipEventRecordExternal)
+                          : hipEventRecord(ctx->events[0], st));
+        HIP_TRY(launch_fused(st, k.blocks, k.threads, k.photon_waves, k.rebin[0] || k.rebin[1], dc, k.T, k.R));
+        HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[1], st, hipEventRecordExternal)
+                          : hipEventRecord(ctx->events[1], st));
+        for (int ri = 0; ri < 2; ++ri) HIP_TRY(launch_finish(st, dc, ri));
+        HIP_TRY(hipMemcpyAsync(ctx->host_ctl, dc, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(ctx->h_jc, M.jc, kJcMirrorBytes, hipMemcpyDeviceToHost, st));
+        return GDPM_OK;
+    }
     for (int ri = 0; ri < 2; ++ri) {
         if (k.rebin[ri]) HIP_TRY(launch_rebin(st, 4 * k.blocks, dc, k.R, ri, k.nb, k.blo, k.binv, k.space));
         HIP_TRY(launch_setup(st, dc, k.R, ri, k.rebin[ri], k.lone));
         // a recorded event becomes a node of the graph that records it at replay
         HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri], st, hipEventRecordExternal)
                           : hipEventRecord(ctx->events[2 * ri], st));
-        HIP_TRY(launch_transport(st, ri, k.blocks, k.threads, k.lds[ri] != 0, ctx->solo_lanes != 0,
-                                 k.rebin[ri] != 0, dc, k.T, k.R));
+        HIP_TRY(launch_transport(st, ri, k.blocks, ri == 0 ? k.threads_photon : k.threads, k.lds[ri] != 0,
+                                 ctx->solo_lanes != 0, k.rebin[ri] != 0, dc, k.T, k.R));
         HIP_TRY(recording ? hipEventRecordWithFlags(ctx->events[2 * ri + 1], st, hipEventRecordExternal)
                           : hipEventRecord(ctx->events[2 * ri + 1], st));
         HIP_TRY(launch_finish(st, dc, ri));
@@ -1226,7 +1269,7 @@ void fill_stats(const Engine& E, const EJob* j, double t_start, gdpm_run_stats* 
     for (int k = 0; k < 2; ++k) out->records_requeued[k] = hc->pass_ev[k][3];
     out->t_photon_s = E.tm.photon;
     out->t_electron_s = E.tm.electron;
-    out->t_kernel_s = E.tm.photon + E.tm.electron;
+    out->t_kernel_s = E.tm.photon + E.tm.electron + E.tm.fused;
     out->t_total_s = (j->t_done > 0 ? j->t_done : now_s()) - t_start;
 }
 
@@ -1503,6 +1546,9 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->graphs = json_int(opts_json, "graphs", 1);
     ctx->check_accounting = json_int(opts_json, "check_accounting", 0);
     ctx->solo_lanes = json_int(opts_json, "solo_lanes", 0);
+    ctx->fused_passes = json_int(opts_json, "fused_passes", 0);
+    ctx->photon_waves_per_cu = json_int(opts_json, "photon_waves_per_cu", 10);
+    ctx->photon_waves = json_int(opts_json, "photon_waves", -1);
     ctx->admit_draining = json_int(opts_json, "admit_draining", 0);
     const unsigned long long ring_start = json_u64(opts_json, "ring_start", 0);
     if (ring_start >= (1ull << 32)) return fail(GDPM_E_INVALID, "ring_start below 2^32");
@@ -1522,6 +1568,11 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     if (ctx->admit_draining < 0 || ctx->admit_draining > 2) return fail(GDPM_E_INVALID, "admit_draining is 0, 1 or 2");
     if (ctx->solo_lanes != 0 && (ctx->solo_lanes != 1 || !ctx->lds_tables || ctx->autotune))
         return fail(GDPM_E_INVALID, "solo_lanes is 0 or 1 and needs lds_tables on and autotune off");
+    if (ctx->fused_passes != 0 && ctx->fused_passes != 1) return fail(GDPM_E_INVALID, "fused_passes is 0 or 1");
+    if (ctx->photon_waves_per_cu < 0 || ctx->photon_waves_per_cu > kMaxBlockThreads / 64)
+        return fail(GDPM_E_INVALID, "photon_waves_per_cu in [0, %d]", kMaxBlockThreads / 64);
+    if (ctx->photon_waves != -1 && (ctx->photon_waves < 0 || ctx->photon_waves > ctx->waves_per_cu))
+        return fail(GDPM_E_INVALID, "photon_waves in [0, waves_per_cu] (or -1: half)");
     HIP_TRY(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device));
     HIP_TRY(hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device));
     if (ctx->lds_tables) {

@@ -614,6 +614,7 @@ struct WJob {
     unsigned long long hist0;
     uint32_t k0, k1, flags;
     int j;
+    int ri;                          // the particle type of the pass the wavefront works in
     uint32_t tag;                    // slot | generation << 8: low half of the records' job word
     uint32_t seg_begin, seg_count;   // the job's records in the running pass
 };
@@ -629,7 +630,7 @@ GDPM_DEV T uniform_copy(const T& v) {
     return out;
 }
 
-GDPM_DEV void load_job(WJob& w, const RunDev& R, int j) {
+GDPM_DEV void load_job(WJob& w, const RunDev& R, int j, int ri) {
     j = __builtin_amdgcn_readfirstlane(j);
     const JobDev& d = R.jobs[j];
     w.G = uniform_copy(d.G);
@@ -642,14 +643,15 @@ GDPM_DEV void load_job(WJob& w, const RunDev& R, int j) {
     w.k1 = __builtin_amdgcn_readfirstlane(d.k1);
     w.flags = __builtin_amdgcn_readfirstlane(d.flags);
     w.j = j;
+    w.ri = ri;
     w.tag = (uint32_t)j | ((__builtin_amdgcn_readfirstlane(d.gen) & 0xFFu) << 8);
-    w.seg_begin = __builtin_amdgcn_readfirstlane(R.jc->seg_begin[j]);
-    w.seg_count = __builtin_amdgcn_readfirstlane(R.jc->seg_count[j]);
+    w.seg_begin = __builtin_amdgcn_readfirstlane(R.jc->seg_begin[ri][j]);
+    w.seg_count = __builtin_amdgcn_readfirstlane(R.jc->seg_count[ri][j]);
 }
 
 // first job of a wavefront: the pass input is split over the wavefronts of the
 // grid in proportion to the jobs' record counts; -1 if the pass is empty
-GDPM_DEV int first_job(const RunDev& R, uint32_t total) {
+GDPM_DEV int first_job(const RunDev& R, uint32_t total, int ri) {
     if (total == 0) return -1;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -657,7 +659,7 @@ GDPM_DEV int first_job(const RunDev& R, uint32_t total) {
     int lo = 0, hi = R.n_jobs - 1;   // last job whose segment starts at or before pos
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (__builtin_amdgcn_readfirstlane(R.jc->seg_begin[mid]) <= pos) lo = mid;
+        if (__builtin_amdgcn_readfirstlane(R.jc->seg_begin[ri][mid]) <= pos) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -672,12 +674,12 @@ GDPM_DEV unsigned long long load_agent64(const unsigned long long* p) {
 }
 
 // the next job after j (cyclically) with unclaimed records in this pass, or -1
-GDPM_DEV int next_job(const JobCtl* jc, int j, int n_jobs) {
+GDPM_DEV int next_job(const JobCtl* jc, int j, int n_jobs, int ri) {
     if (n_jobs <= 1) return -1;
     const int nw = (n_jobs + 63) >> 6;
     for (int k = 0; k <= nw; ++k) {
         const int wi = ((j >> 6) + k) % nw;
-        unsigned long long m = load_agent64(&jc->left[wi]);
+        unsigned long long m = load_agent64(&jc->left[ri][wi]);
         if (k == 0) {
             const int b = j & 63;   // only jobs after j in j's own word
             m = b == 63 ? 0ull : m & (~0ull << (b + 1));
@@ -692,19 +694,15 @@ GDPM_DEV int next_job(const JobCtl* jc, int j, int n_jobs) {
     return -1;
 }
 
-// the job's majorant table: a copy in this wavefront's LDS slice when the
-// tables are staged, else the global array
-template <bool kLds>
+// the job's majorant table: a copy in this wavefront's LDS slice `lmw`, or the
+// global array when there is no slice
 GDPM_DEV const float* job_majorant(const WJob& W, float* lmw, int n) {
-    if constexpr (kLds) {
-        for (int i = (int)lane_id(); i < n; i += 64) lmw[i] = W.mumax[i];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        return lmw;
-    } else {
-        return W.mumax;
-    }
+    if (lmw == nullptr) return W.mumax;
+    for (int i = (int)lane_id(); i < n; i += 64) lmw[i] = W.mumax[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return lmw;
 }
 
 struct ClaimState {
@@ -993,8 +991,8 @@ __global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri, int r
     const uint32_t count = ctl->overflow ? 0u : (perm ? ctl->n_valid : r.tail - r.head);
     if (!rebinned)
         for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) {
-            jc->seg_begin[j] = j <= lone ? 0u : count;
-            jc->seg_count[j] = j == lone ? count : 0u;
+            jc->seg_begin[ri][j] = j <= lone ? 0u : count;
+            jc->seg_count[ri][j] = j == lone ? count : 0u;
         }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1004,14 +1002,14 @@ __global__ void __launch_bounds__(256) k_setup(Ctl* ctl, RunDev R, int ri, int r
         r.next_head = r.tail;
         if (!perm) r.permuted = 0u;
     }
-    for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) jc->claim[j] = 0u;
+    for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) jc->claim[ri][j] = 0u;
     const int nw = (R.n_jobs + 63) >> 6;
     for (int k = threadIdx.x; k < kMaxJobs / 64; k += blockDim.x) {
         unsigned long long m = 0ull;
         if (k < nw && !ctl->overflow)
             for (int b = 0; b < 64 && k * 64 + b < R.n_jobs; ++b)
-                if (jc->seg_count[k * 64 + b] > 0u) m |= 1ull << b;
-        jc->left[k] = m;
+                if (jc->seg_count[ri][k * 64 + b] > 0u) m |= 1ull << b;
+        jc->left[ri][k] = m;
     }
 }
 
@@ -1041,11 +1039,11 @@ GDPM_DEV void claim_refill(ClaimState& cs, JobCtl* jc, const WJob& W, const Ctl*
     }
     const uint32_t leader = first_lane(ballot(true));
     uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(&jc->claim[W.j], chunk);
+    if (lane_id() == leader) base = atomicAdd(&jc->claim[W.ri][W.j], chunk);
     base = bcast(base, leader);
     cs.seen = base + chunk;
     if (base >= count) {
-        if (lane_id() == leader) atomicAnd(&jc->left[W.j >> 6], ~(1ull << (W.j & 63)));
+        if (lane_id() == leader) atomicAnd(&jc->left[W.ri][W.j >> 6], ~(1ull << (W.j & 63)));
         cs.done = true;
         return;
     }
@@ -1277,20 +1275,12 @@ GDPM_HD uint32_t stage_offset(int ri, const Tables& T, int waves) {
     return tab + (floats + 3u) / 4u;
 }
 
-template <bool kLds, bool kSolo, bool kPerm>
-__global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
-    const float4* ptab = T.phot;
-    float* lmw = nullptr;
-    float4* stage = nullptr;
-    if constexpr (kLds) {
-        const int np = T.n_mat * T.pg_n;
-        for (int i = threadIdx.x; i < np; i += blockDim.x) lds_tables[i] = T.phot[i];
-        const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        lmw = reinterpret_cast<float*>(lds_tables + np) + wave * T.pg_n;
-        stage = lds_tables + stage_offset(0, T, blockDim.x >> 6) + wave * (4u * kStage);
-        __syncthreads();
-        ptab = lds_tables;
-    }
+// One wavefront's share of a photon pass.  ptab: the cross sections (LDS or
+// global); lmw: the wavefront's LDS slice for its job's majorant (null: the
+// global array); stage: its LDS slice for staged records (null: none).
+template <bool kSolo, bool kPerm>
+GDPM_DEV void photon_pass(Ctl* ctl, const Tables& T, const RunDev& R, const float4* ptab, float* lmw,
+                          float4* stage) {
     RingCtl* rc = &ctl->ring[0];
     const uint32_t begin = rc->begin, count = rc->count;
     // a pass re-binned by job reads its input through the permutation (only the
@@ -1304,7 +1294,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     JobCtl* jc = R.jc;
     const float ecut_e = R.ecut_e, ecut_g = R.ecut_g;
 
-    int j = first_job(R, count);
+    int j = first_job(R, count, 0);
     PushState pg{0u, 0u}, pe{0u, 0u};
     LaneTally tl;
     tally_init(tl);
@@ -1314,8 +1304,8 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
     // one job at a time: a wavefront switches jobs with all its lanes empty
     while (j >= 0) {
         WJob W;
-        load_job(W, R, j);
-        const float* mtab = job_majorant<kLds>(W, lmw, T.pg_n);
+        load_job(W, R, j, 0);
+        const float* mtab = job_majorant(W, lmw, T.pg_n);
         ClaimState cs{0u, 0u, 0u, false, 0u, 0u};
         bool active = false;
         float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0;
@@ -1499,7 +1489,7 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
                 // early; the particles still held go to the next pass
                 int nj = -1;
                 if (!last_job) {
-                    nj = next_job(jc, W.j, R.n_jobs);
+                    nj = next_job(jc, W.j, R.n_jobs, 0);
                     last_job = nj < 0;
                 }
                 if (nj >= 0 || (big && __popcll(ballot(active)) < kTailLanes)) {
@@ -1521,36 +1511,40 @@ __global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
         job_flush(tl, wt, W, jc);
         j = next;
     }
-    // no staging load may still be writing this workgroup's LDS when it ends
-    if constexpr (kLds) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    // no staging load may still be writing the slice when the wave moves on
+    if (stage != nullptr) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
     pass_finish(tl, wt, ctl, 0);
+}
+
+template <bool kLds, bool kSolo, bool kPerm>
+__global__ void __launch_bounds__(768) k_photon(Ctl* ctl, Tables T, RunDev R) {
+    const float4* ptab = T.phot;
+    float* lmw = nullptr;
+    float4* stage = nullptr;
+    if constexpr (kLds) {
+        const int np = T.n_mat * T.pg_n;
+        for (int i = threadIdx.x; i < np; i += blockDim.x) lds_tables[i] = T.phot[i];
+        const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        lmw = reinterpret_cast<float*>(lds_tables + np) + wave * T.pg_n;
+        stage = lds_tables + stage_offset(0, T, blockDim.x >> 6) + wave * (4u * kStage);
+        __syncthreads();
+        ptab = lds_tables;
+    }
+    photon_pass<kSolo, kPerm>(ctl, T, R, ptab, lmw, stage);
 }
 
 // ---------------------------------------------------------------------------
 // electron pass: class-II condensed history with a random hinge, one step per
 // iteration (section 2.1)
 // ---------------------------------------------------------------------------
-template <bool kLds, bool kSolo, bool kPerm>
-__global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) {
-    const float4* etab = T.elec;
-    const float* rtab = T.rinv;
-    const float* rscale = T.rinv_scale;
-    float4* stage = nullptr;
-    if constexpr (kLds) {
-        const int ne = T.n_mat * T.eg_n, nr = T.n_mat * T.nr;
-        stage = lds_tables + stage_offset(1, T, blockDim.x >> 6) +
-                __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * (4u * kStage);
-        for (int i = threadIdx.x; i < ne; i += blockDim.x) lds_tables[i] = T.elec[i];
-        float* lr = reinterpret_cast<float*>(lds_tables + ne);
-        for (int i = threadIdx.x; i < nr; i += blockDim.x) lr[i] = T.rinv[i];
-        for (int i = threadIdx.x; i < T.n_mat; i += blockDim.x) lr[nr + i] = T.rinv_scale[i];
-        __syncthreads();
-        etab = lds_tables;
-        rtab = lr;
-        rscale = lr + nr;
-    }
+// One wavefront's share of an electron pass.  etab, rtab, rscale: the
+// stopping and scattering data, the inverse range and its scales (LDS or
+// global); stage: the wavefront's LDS slice for staged records (null: none).
+template <bool kSolo, bool kPerm>
+GDPM_DEV void electron_pass(Ctl* ctl, const Tables& T, const RunDev& R, const float4* etab, const float* rtab,
+                            const float* rscale, float4* stage) {
     RingCtl* rc = &ctl->ring[1];
     const uint32_t begin = rc->begin, count = rc->count;
     const uint32_t* perm_in =
@@ -1562,7 +1556,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     JobCtl* jc = R.jc;
     const float ecut = R.ecut_e;
 
-    int j = first_job(R, count);
+    int j = first_job(R, count, 1);
     PushState pg{0u, 0u}, pe{0u, 0u};
     LaneTally tl;
     tally_init(tl);
@@ -1572,7 +1566,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
     // one job at a time: a wavefront switches jobs with all its lanes empty
     while (j >= 0) {
         WJob W;
-        load_job(W, R, j);
+        load_job(W, R, j, 1);
         ClaimState cs{0u, 0u, 0u, false, 0u, 0u};
         bool active = false;
         float x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, e = 0, nh = -1.0f, aa = 0.0f;
@@ -1805,7 +1799,7 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
                 // early; the particles still held go to the next pass
                 int nj = -1;
                 if (!last_job) {
-                    nj = next_job(jc, W.j, R.n_jobs);
+                    nj = next_job(jc, W.j, R.n_jobs, 1);
                     last_job = nj < 0;
                 }
                 if (nj >= 0 || (big && __popcll(ballot(active)) < kTailLanes)) {
@@ -1828,11 +1822,63 @@ __global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) 
         job_flush(tl, wt, W, jc);
         j = next;
     }
-    // no staging load may still be writing this workgroup's LDS when it ends
-    if constexpr (kLds) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    // no staging load may still be writing the slice when the wave moves on
+    if (stage != nullptr) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     release(pe, bufe, R.mask[1]);
     release(pg, bufg, R.mask[0]);
     pass_finish(tl, wt, ctl, 1);
+}
+
+template <bool kLds, bool kSolo, bool kPerm>
+__global__ void __launch_bounds__(768) k_electron(Ctl* ctl, Tables T, RunDev R) {
+    const float4* etab = T.elec;
+    const float* rtab = T.rinv;
+    const float* rscale = T.rinv_scale;
+    float4* stage = nullptr;
+    if constexpr (kLds) {
+        const int ne = T.n_mat * T.eg_n, nr = T.n_mat * T.nr;
+        stage = lds_tables + stage_offset(1, T, blockDim.x >> 6) +
+                __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * (4u * kStage);
+        for (int i = threadIdx.x; i < ne; i += blockDim.x) lds_tables[i] = T.elec[i];
+        float* lr = reinterpret_cast<float*>(lds_tables + ne);
+        for (int i = threadIdx.x; i < nr; i += blockDim.x) lr[i] = T.rinv[i];
+        for (int i = threadIdx.x; i < T.n_mat; i += blockDim.x) lr[nr + i] = T.rinv_scale[i];
+        __syncthreads();
+        etab = lds_tables;
+        rtab = lr;
+        rscale = lr + nr;
+    }
+    electron_pass<kSolo, kPerm>(ctl, T, R, etab, rtab, rscale, stage);
+}
+
+// ---------------------------------------------------------------------------
+// both passes of an iteration in one launch: the first `photon_waves`
+// wavefronts of each workgroup start with the photon pass, the others with the
+// electron pass, and a wavefront that has finished its first pass helps with
+// the other.  The photon pass mostly waits on its random voxel reads and the
+// electron pass mostly issues vector instructions, so a CU runs one while the
+// other waits.  The electron tables and the wavefronts' staging slices are in
+// LDS; the photon cross sections and majorants are read through the caches.
+// Each pass reads what its queue held at the set-up: what either pass pushes
+// is transported in the next iteration.
+// ---------------------------------------------------------------------------
+template <bool kPerm>
+__global__ void __launch_bounds__(768) k_transport(Ctl* ctl, Tables T, RunDev R, int photon_waves) {
+    const int ne = T.n_mat * T.eg_n, nr = T.n_mat * T.nr;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float4* stage = lds_tables + stage_offset(1, T, blockDim.x >> 6) + wave * (4u * kStage);
+    for (int i = threadIdx.x; i < ne; i += blockDim.x) lds_tables[i] = T.elec[i];
+    float* lr = reinterpret_cast<float*>(lds_tables + ne);
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) lr[i] = T.rinv[i];
+    for (int i = threadIdx.x; i < T.n_mat; i += blockDim.x) lr[nr + i] = T.rinv_scale[i];
+    __syncthreads();
+    for (int k = 0; k < 2; ++k) {
+        const bool photons = ((int)wave < photon_waves) == (k == 0);
+        if (photons)
+            photon_pass<false, kPerm>(ctl, T, R, T.phot, nullptr, stage);
+        else
+            electron_pass<false, kPerm>(ctl, T, R, lds_tables, lr, lr + nr, stage);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1905,7 +1951,7 @@ __global__ void __launch_bounds__(256) k_bin_count(Ctl* ctl, RunDev R, int ri, i
 
 // exclusive scan of the key counts (one block of 1024 threads, <= 4 keys each);
 // also the jobs' segments and the number of records kept
-__global__ void __launch_bounds__(1024) k_bin_scan(Ctl* ctl, RunDev R, int nb) {
+__global__ void __launch_bounds__(1024) k_bin_scan(Ctl* ctl, RunDev R, int nb, int ri) {
     if (ctl->overflow) return;
     __shared__ uint32_t part[1024];
     JobCtl* jc = R.jc;
@@ -1933,8 +1979,8 @@ __global__ void __launch_bounds__(1024) k_bin_scan(Ctl* ctl, RunDev R, int nb) {
     for (int j = threadIdx.x; j < R.n_jobs; j += blockDim.x) {
         const uint32_t b0 = jc->bin_cursor[j * nb];
         const uint32_t b1 = j + 1 < R.n_jobs ? jc->bin_cursor[(j + 1) * nb] : total;
-        jc->seg_begin[j] = b0;
-        jc->seg_count[j] = b1 - b0;
+        jc->seg_begin[ri][j] = b0;
+        jc->seg_count[ri][j] = b1 - b0;
     }
     if (threadIdx.x == 0) ctl->n_valid = total;
 }
@@ -2233,7 +2279,8 @@ hipError_t transport_lds_optin(size_t bytes) {
     const void* kernels[] = {(const void*)k_photon<true, false, false>, (const void*)k_electron<true, false, false>,
                              (const void*)k_photon<true, false, true>,  (const void*)k_electron<true, false, true>,
                              (const void*)k_photon<true, true, false>,  (const void*)k_electron<true, true, false>,
-                             (const void*)k_photon<true, true, true>,   (const void*)k_electron<true, true, true>};
+                             (const void*)k_photon<true, true, true>,   (const void*)k_electron<true, true, true>,
+                             (const void*)k_transport<false>,           (const void*)k_transport<true>};
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -2276,6 +2323,18 @@ hipError_t launch_transport(hipStream_t st, int ri, int blocks, int threads, boo
         launch_transport_form<false>(st, ri, blocks, threads, lds, solo, bytes, ctl, T, R);
     return hipGetLastError();
 }
+// both passes in one launch (k_transport); its LDS is the electron pass's
+// layout (transport_lds_bytes(1, T, threads / 64))
+hipError_t launch_fused(hipStream_t st, int blocks, int threads, int photon_waves, bool permuted, Ctl* ctl,
+                        const Tables& T, const RunDev& R) {
+    const size_t bytes = transport_lds_bytes(1, T, threads / 64);
+    if (permuted)
+        hipLaunchKernelGGL((k_transport<true>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R, photon_waves);
+    else
+        hipLaunchKernelGGL((k_transport<false>), dim3(blocks), dim3(threads), bytes, st, ctl, T, R, photon_waves);
+    return hipGetLastError();
+}
+
 // nb bins per job (energy intervals, or space^3 boxes with space > 0);
 // R.n_jobs * nb <= kMaxKeys
 hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, int ri, int nb,
@@ -2283,7 +2342,7 @@ hipError_t launch_rebin(hipStream_t st, int blocks, Ctl* ctl, const RunDev& R, i
     const size_t nk = (size_t)R.n_jobs * nb;
     hipLaunchKernelGGL(k_bin_count, dim3(blocks), dim3(256), nk * sizeof(uint32_t), st, ctl, R, ri,
                        nb, lo, inv, space);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, ctl, R, nb);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, ctl, R, nb, ri);
     hipLaunchKernelGGL(k_bin_scatter, dim3(blocks), dim3(256), 2 * nk * sizeof(uint32_t), st, ctl, R,
                        ri, nb);
     hipLaunchKernelGGL(k_bin_swap, dim3(1), dim3(1), 0, st, ctl, ri);

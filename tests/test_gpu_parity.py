@@ -450,6 +450,12 @@ def test_determinism_and_launch_independence(gctx):
                  '{"waves_per_cu": 8, "rebin_bins": 32, "rebin_photons": 1, "rebin_electrons": 1}',
                  # boxes of the phantom as bins (4^3 per job)
                  '{"rebin_bins": 64, "rebin_space": 1, "rebin_photons": 1, "rebin_electrons": 1}',
+                 # the photon pass with as many wavefronts per CU as the electron pass
+                 '{"photon_waves_per_cu": 0}',
+                 # both passes in one launch (a one-iteration lag between them)
+                 '{"fused_passes": 1}',
+                 '{"fused_passes": 1, "photon_waves": 3, "rebin_photons": 1, "rebin_electrons": 1}',
+                 '{"fused_passes": 1, "photon_waves": 0, "ring_capacity_log2": 21, "pass_histories": 700}',
                  '{"ring_capacity_log2": 21, "pass_histories": 700}',
                  '{"rebin_photons": 1, "rebin_electrons": 0}',
                  # tables read through L2 and records loaded directly, no LDS staging
@@ -464,8 +470,9 @@ def test_determinism_and_launch_independence(gctx):
         # the forced re-binning did run (the permuted form of the transport kernels)
         assert (c["passes_rebinned"] > 0) == ('"rebin_photons": 1' in opts), opts
     assert a["passes_rebinned"] == 0
-    with pytest.raises(G.GdpmError):
-        G.Context(0, opts='{"rebin_space": 2}', materials=MATS)
+    for bad in ('{"rebin_space": 2}', '{"fused_passes": 2}', '{"photon_waves": 13}', '{"photon_waves_per_cu": 13}'):
+        with pytest.raises(G.GdpmError):
+            G.Context(0, opts=bad, materials=MATS)
 
 
 def test_atomic_rate_probe(gctx):
