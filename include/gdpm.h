@@ -236,18 +236,18 @@ typedef struct {
  * 2^k, default 25), "waves_per_cu" (wavefronts of the persistent workgroup
  * each CU runs, 1..12, default 12), "photon_waves_per_cu" (the same for the
  * photon pass alone, at most waves_per_cu, 0..12, default 10; 0: waves_per_cu),
- * "rebin_bins" (bins per job of the queue
- * re-binning, 0..64, default 1: records are grouped by job only, which measured
- * faster than energy order), "rebin_space" (0, default: the bins are intervals
- * of log2 E; 1: they are boxes of the phantom, space^3 with space^3 the largest
- * cube within the bins), "rebin_photons", "rebin_electrons" (1: re-bin
- * the queue of that particle type also when a single job holds all the
- * particles; default 0: then the queues are read unsorted, which measured
- * faster), "lds_tables" (1: stage interpolation tables in LDS when they fit,
- * together with each wavefront's next claimed queue records, default; 0: read
- * the tables through the caches and load records directly), "pass_histories" (new histories
- * started per scheduler iteration, default 0 = half the queue capacity less
- * what the fuller queue holds; a larger
+ * "rebin_bins" (bins per job of the queue re-binning, 0..64, default 1:
+ * records are grouped by job only, which measured faster than energy order),
+ * "rebin_space" (0, default: the bins are intervals of log2 E; 1: they are
+ * boxes of the phantom, space^3 with space^3 the largest cube within the bins),
+ * "rebin_photons", "rebin_electrons" (1: re-bin the queue of that particle type
+ * also when a single job holds all the particles; default 0: then the queues
+ * are read unsorted, which measured faster), "lds_tables" (1: stage
+ * interpolation tables in LDS when they fit, together with each wavefront's
+ * next claimed queue records, default; 0: read the tables through the caches
+ * and load records directly), "pass_histories" (new histories started per
+ * scheduler iteration, default 0 = half the queue capacity less what the
+ * fuller queue holds; a larger
  * value can overflow the queues, which gdpm_run reports as GDPM_E_OVERFLOW).
  * Each wavefront reserves queue slots 256 at a time, so a queue needs well
  * over 256 slots per wavefront of the grid (2^21 and up on a 256-CU device
