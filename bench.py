@@ -782,7 +782,7 @@ def summarize_traffic(fetch_csv, write_csv, copy_mib):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--target", type=float, default=0.01)
     ap.add_argument("--n0", type=int, default=100_000_000, help="first history estimate per job")
@@ -891,6 +891,7 @@ def main():
     wall = time.perf_counter() - t0
     hist = sum(r["histories"] for r in runs)
     lat = np.array([r["t_total_s"] for r in runs])
+    rates = [r["histories"] / r["t_total_s"] for r in runs]
 
     # roofline of the dominant transport kernel: algorithmic bytes per launch
     # over the launch's average HIP-event duration
@@ -969,6 +970,9 @@ def main():
                    "stat_min_density": args.min_density,
                    "tally": "f64"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        # each timed job's own rate: the spread of the repeats
+        "histories_per_s_per_job": {"min": float(min(rates)), "median": float(np.median(rates)),
+                                    "max": float(max(rates))},
         "unc_reached": [r["unc"] for r in runs],
         "energy_balance_max": max(abs(r["e_dep"] + r["e_esc"] - r["e_in"]) / r["e_in"] for r in runs),
         "accounting_repairs": sum(r["accounting_repairs"] for r in runs),
