@@ -142,12 +142,17 @@ def test_batch_graphs_equal_direct_launches():
         assert balance(b) < 1e-6
 
 
-def test_accounting_check_finds_nothing():
+@pytest.mark.parametrize("extra", ["", ', "fused_passes": 1', ', "rebin_bins": 8',
+                                   ', "rebin_bins": 8, "rebin_space": 1, "fused_passes": 1, "photon_waves": 4'],
+                         ids=["default", "fused", "energy_bins", "space_bins_fused"])
+def test_accounting_check_finds_nothing(gctx, extra):
     """The diagnostic accounting check (every iteration: live queue records of
     each job against its births less deaths) on the batched form, several jobs
-    sharing the queues with re-binning, and on a multi-round target job."""
+    sharing the queues with re-binning, and on a multi-round target job; with
+    both passes in one launch and with bins within a job as well.  Each job's
+    dose equals the job run alone with the default settings."""
     jobs = small_jobs(seed=4107)
-    c2 = G.Context(0, opts='{"check_accounting": 1, "pass_histories": 3000, "ring_capacity_log2": 21}',
+    c2 = G.Context(0, opts='{"check_accounting": 1, "pass_histories": 3000, "ring_capacity_log2": 21' + extra + '}',
                    materials=MATS)
     handles = [(c2.phantom(w.phantom), c2.source(w.source), kw) for w, kw in jobs]
     try:
@@ -157,10 +162,14 @@ def test_accounting_check_finds_nothing():
             p.close()
             s.close()
         c2.close()
-    for (w, _), r in zip(jobs, res):
-        report(f"accounting check {w.name}", mismatches=r["accounting_mismatches"], passes=r["passes"])
-        assert r["accounting_mismatches"] == 0, w.name
+    for (w, kw), r in zip(jobs, res):
+        report(f"accounting check {w.name}", mismatches=r["accounting_mismatches"], passes=r["passes"],
+               rebinned=r["passes_rebinned"])
+        assert r["accounting_mismatches"] == 0 and r["transport_anomalies"] == 0, w.name
         assert balance(r) < 1e-6
+        a = solo(gctx, w, kw)
+        assert r["histories"] == a["histories"], w.name
+        same_dose(r["dose"], a["dose"], f"batch{extra} vs solo {w.name}")
 
 
 def test_batch_more_jobs_than_slots(gctx):
