@@ -1283,8 +1283,8 @@ GDPM_DEV void photon_pass(Ctl* ctl, const Tables& T, const RunDev& R, const floa
                           float4* stage) {
     RingCtl* rc = &ctl->ring[0];
     const uint32_t begin = rc->begin, count = rc->count;
-    // a pass re-binned by job reads its input through the permutation (only the
-    // kPerm form has that code: single-job passes keep the plain reads)
+    // a re-binned pass reads its input through the permutation (only the kPerm
+    // form has that code: the passes of a lone job keep the plain reads)
     const uint32_t* perm_in =
         kPerm && __builtin_amdgcn_readfirstlane(rc->permuted) ? bin_perm(R.bin[0], R.mask[0]) : nullptr;
     const bool big = !kSolo && count >= kTailMinPerLane * gridDim.x * blockDim.x;
