@@ -13,7 +13,7 @@ constexpr uint32_t kClaimMax = 256;     // wavefront claims with one atomic
 constexpr int kMaxBins = 64;            // energy bins of the queue re-binning
 constexpr int kMaxJobs = 256;           // dose jobs transported together
 constexpr int kMaxKeys = 4096;          // re-binning keys (job x energy bin)
-constexpr uint32_t kTailLanes = 32;     // a drained wavefront with fewer particles
+constexpr uint32_t kTailLanes = 16;     // a drained wavefront with fewer particles
                                         // than this hands them to the next pass ...
 constexpr uint32_t kTailMinPerLane = 4; // ... if the pass had this many per lane
 #ifndef GDPM_HARD_BATCH
