@@ -8,8 +8,11 @@ namespace gdpm {
 
 constexpr int kMaxMaterials = 8;
 constexpr uint32_t kPushChunk = 256;    // ring slots a wavefront reserves at a time
-constexpr uint32_t kClaimMin = 32;      // smallest and largest number of queue items a
-constexpr uint32_t kClaimMax = 256;     // wavefront claims with one atomic
+constexpr uint32_t kClaimMin = 32;      // smallest number of queue items a wavefront claims
+                                        // with one atomic, and the largest, per particle type:
+constexpr uint32_t kClaimMaxPhoton = 2048;   // a photon record lasts a few short iterations, so
+constexpr uint32_t kClaimMaxElectron = 256;  // photon wavefronts claim often: larger chunks keep
+                                             // them off the shared claim counter
 constexpr int kMaxBins = 64;            // energy bins of the queue re-binning
 constexpr int kMaxJobs = 256;           // dose jobs transported together
 constexpr int kMaxKeys = 4096;          // re-binning keys (job x energy bin)

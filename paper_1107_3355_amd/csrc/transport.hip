@@ -1032,7 +1032,7 @@ GDPM_DEV void claim_refill(ClaimState& cs, JobCtl* jc, const WJob& W, const Ctl*
     const uint32_t count = W.seg_count;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     const uint32_t left = count - min(cs.seen, count);
-    const uint32_t chunk = min(max(left / (2u * waves), kClaimMin), kClaimMax);
+    const uint32_t chunk = min(max(left / (2u * waves), kClaimMin), W.ri == 0 ? kClaimMaxPhoton : kClaimMaxElectron);
     if (load_agent(&ctl->overflow)) {   // a queue overflowed: the run is void
         cs.done = true;
         return;
