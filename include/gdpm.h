@@ -235,7 +235,7 @@ typedef struct {
  * flat JSON object with any of: "ring_capacity_log2" (queue records per type,
  * 2^k, default 25), "waves_per_cu" (wavefronts of the persistent workgroup
  * each CU runs, 1..12, default 12), "photon_waves_per_cu" (the same for the
- * photon pass alone, at most waves_per_cu, 0..12, default 10; 0: waves_per_cu),
+ * photon pass alone, at most waves_per_cu, 0..12, default 0: waves_per_cu),
  * "rebin_bins" (bins per job of the queue re-binning, 0..64, default 1:
  * records are grouped by job only, which measured faster than energy order),
  * "rebin_space" (0, default: the bins are intervals of log2 E; 1: they are

@@ -270,8 +270,8 @@ struct gdpm_context_s {
     int check_accounting = 0;    // after every iteration, count each job's live records
     int solo_lanes = 0;          // measurement form: one particle per wavefront at a time
     int fused_passes = 0;        // 1: both passes of an iteration in one launch (k_transport)
-    int photon_waves_per_cu = 10;  // wavefronts per CU of the photon pass (at most
-                                   // waves_per_cu; 0: waves_per_cu)
+    int photon_waves_per_cu = 0; // wavefronts per CU of the photon pass (at most
+                                 // waves_per_cu; 0: waves_per_cu)
     int photon_waves = -1;       // wavefronts per workgroup that start with photons (fused; -1: half)
     int admit_draining = 0;      // server: admit a job only while every running job drains (1: any
                                  // super-round, 2: its last one)
@@ -945,8 +945,6 @@ gdpm_status Engine::step() {
     }
     k.blocks = blocks;
     k.threads = block_threads(ctx);
-    // the photon pass gains nothing from more than about 10 wavefronts per CU
-    // (measured: its random voxel reads saturate the memory path first)
     k.threads_photon = ctx->photon_waves_per_cu ? std::min(k.threads, 64 * ctx->photon_waves_per_cu) : k.threads;
     k.nb = nb;
     k.space = space;
@@ -1547,7 +1545,7 @@ gdpm_status gdpm_context_create(int hip_device, const char* opts_json, gdpm_cont
     ctx->check_accounting = json_int(opts_json, "check_accounting", 0);
     ctx->solo_lanes = json_int(opts_json, "solo_lanes", 0);
     ctx->fused_passes = json_int(opts_json, "fused_passes", 0);
-    ctx->photon_waves_per_cu = json_int(opts_json, "photon_waves_per_cu", 10);
+    ctx->photon_waves_per_cu = json_int(opts_json, "photon_waves_per_cu", 0);
     ctx->photon_waves = json_int(opts_json, "photon_waves", -1);
     ctx->admit_draining = json_int(opts_json, "admit_draining", 0);
     const unsigned long long ring_start = json_u64(opts_json, "ring_start", 0);

@@ -450,8 +450,8 @@ def test_determinism_and_launch_independence(gctx):
                  '{"waves_per_cu": 8, "rebin_bins": 32, "rebin_photons": 1, "rebin_electrons": 1}',
                  # boxes of the phantom as bins (4^3 per job)
                  '{"rebin_bins": 64, "rebin_space": 1, "rebin_photons": 1, "rebin_electrons": 1}',
-                 # the photon pass with as many wavefronts per CU as the electron pass
-                 '{"photon_waves_per_cu": 0}',
+                 # the photon pass with fewer wavefronts per CU than the electron pass
+                 '{"photon_waves_per_cu": 10}',
                  # both passes in one launch (a one-iteration lag between them)
                  '{"fused_passes": 1}',
                  '{"fused_passes": 1, "photon_waves": 3, "rebin_photons": 1, "rebin_electrons": 1}',
